@@ -1,0 +1,398 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test checks the oracle against something other than itself: enumeration,
+closed forms, Prop. 1's invariants, LP/ILP bounds, a hand-worked example, and
+an independent torch implementation of Alg. 1 whose autograd gradient pins
+the oracle's literal Alg. 2.
+"""
+import dataclasses
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests import brute
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def tiny(seed, **kw):
+    return synth.random_tiny(seed, **kw)
+
+
+def uniform_params(p):
+    deg = p.degree()
+    return np.full(p.nnz, 0.5), 1.0 / deg[p.col]
+
+
+def learned_params(p, seed):
+    rng = np.random.default_rng(seed)
+    om = synth.sigmoid(rng.normal(size=p.nnz))
+    ah = rng.normal(0.0, 0.5, size=p.nnz)
+    return om, ah
+
+
+# ------------------------------------------------------------------------------------------
+# Min-marginals (eq. 8 / Alg. 1 min-marginal line) against enumeration and closed forms
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(12))
+def test_min_marginals_match_enumeration(orc, seed):
+    p = tiny(seed, n=10, m=6, kmax=9)
+    lam = np.random.default_rng(seed + 100).normal(size=p.nnz)
+    m0, m1 = orc.min_marginals(p, lam)
+    b0, b1 = brute.min_marginals(p, lam)
+    np.testing.assert_allclose(m0, b0, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(m1, b1, rtol=0, atol=1e-12)
+    Ej = orc.energies(p, lam)
+    np.testing.assert_allclose(Ej, brute.energies(p, lam), atol=1e-12)
+    # invariant: min(m0, m1) = E^j for every variable of row j
+    np.testing.assert_allclose(np.minimum(m0, m1), Ej[p.edge_row()], atol=1e-12)
+
+
+def test_closed_form_at_most_one(orc):
+    rng = np.random.default_rng(5)
+    L = 7
+    p = synth.generators._from_rows(L, np.zeros(L), [(np.arange(L), np.ones(L, np.int32), -1, 1)], "amo")
+    lam = rng.normal(size=L)
+    m0, m1 = orc.min_marginals(p, lam)
+    for i in range(L):
+        others = np.delete(lam, i)
+        assert m1[i] == pytest.approx(lam[i], abs=1e-14)
+        assert m0[i] == pytest.approx(min(0.0, others.min()), abs=1e-14)
+
+
+def test_closed_form_cover(orc):
+    rng = np.random.default_rng(6)
+    L = 6
+    p = synth.generators._from_rows(L, np.zeros(L), [(np.arange(L), np.ones(L, np.int32), 1, 1)], "cover")
+    lam = rng.uniform(0.1, 2.0, size=L)
+    m0, m1 = orc.min_marginals(p, lam)
+    for i in range(L):
+        assert m1[i] == pytest.approx(lam[i], abs=1e-14)
+        assert m0[i] == pytest.approx(np.delete(lam, i).min(), abs=1e-14)
+
+
+def test_argmin_is_optimal(orc):
+    p = tiny(3, n=10, m=6, kmax=8)
+    lam = np.random.default_rng(1).normal(size=p.nnz)
+    x = orc.argmin(p, lam).astype(np.int64)
+    sets = brute.row_sets(p)
+    for j, X in enumerate(sets):
+        a, b = int(p.row_ptr[j]), int(p.row_ptr[j + 1])
+        assert any((X == x[a:b]).all(1))                      # feasible
+        assert x[a:b] @ lam[a:b] == pytest.approx((X @ lam[a:b]).min(), abs=1e-12)
+
+
+# ------------------------------------------------------------------------------------------
+# Alg. 1 passes: hand-worked example, literal vs incremental, independent torch version
+# ------------------------------------------------------------------------------------------
+
+def _gold():
+    with open(os.path.join(GOLD, "two_row_iteration.json")) as f:
+        g = json.load(f)
+    q = g["problem"]
+    p = synth.Problem(q["n"], np.array(q["c"]), np.array(q["row_ptr"], np.int64), np.array(q["col"], np.int32),
+                      np.array(q["coef"], np.int32), np.array(q["sense"], np.int8), np.array(q["rhs"], np.int64))
+    return g, p
+
+
+@pytest.mark.parametrize("literal", [False, True])
+def test_golden_two_row_iteration(orc, literal):
+    g, p = _gold()
+    om, al = np.array(g["omega"]), np.array(g["alpha"])
+    lam = orc.init_lambda(p)
+    np.testing.assert_array_equal(lam, g["lambda_init"])
+    M = np.zeros(p.nnz)
+    assert orc.lower_bound(p, al, lam, M)[0] == g["lb_init"]
+    orc.run_pass(p, om, al, lam, M, 0, literal=literal)
+    np.testing.assert_array_equal(lam, g["after_forward"]["lambda"])
+    np.testing.assert_array_equal(M, g["after_forward"]["M"])
+    assert orc.lower_bound(p, al, lam, M)[0] == g["after_forward"]["lb"]
+    orc.run_pass(p, om, al, lam, M, 1, literal=literal)
+    ab = g["after_backward"]
+    np.testing.assert_array_equal(lam, ab["lambda"])
+    np.testing.assert_array_equal(M, ab["M"])
+    lb, dl, lbar = orc.lower_bound(p, al, lam, M)
+    assert lb == ab["lb"] and dl == ab["d_l"]
+    np.testing.assert_array_equal(lbar, ab["lambda_bar"])
+    m0, m1 = orc.min_marginals(p, lbar)
+    np.testing.assert_array_equal(m0, ab["m0_at_lambda_bar"])
+    np.testing.assert_array_equal(m1, ab["m1_at_lambda_bar"])
+    assert lb <= g["ilp_optimum"]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_literal_equals_incremental(orc, seed):
+    p = tiny(seed, n=12, m=8, kmax=7)
+    om, ah = learned_params(p, seed)
+    al = orc.softmax_alpha(p, ah)
+    a = orc.run(p, om, al, 6, literal=False)
+    b = orc.run(p, om, al, 6, literal=True)
+    np.testing.assert_allclose(a[0], b[0], atol=1e-12)
+    np.testing.assert_allclose(a[1], b[1], atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_trajectory_matches_torch_enumeration(orc, seed):
+    p = tiny(seed + 40, n=9, m=6, kmax=6)
+    om, ah = learned_params(p, seed)
+    al = orc.softmax_alpha(p, ah)
+    T = 3
+    _, states = brute.dmma_torch(p, torch.tensor(om), torch.tensor(al), T, record=True)
+    lam, M = orc.init_lambda(p), np.zeros(p.nnz)
+    for k in range(2 * T):
+        orc.run_pass(p, om, al, lam, M, k % 2)
+        np.testing.assert_allclose(lam, states[k + 1][0].numpy(), atol=1e-12)
+        np.testing.assert_allclose(M, states[k + 1][1].numpy(), atol=1e-12)
+
+
+def test_rows_are_independent_within_a_pass(orc):
+    """Reordering the rows gives bitwise the same per-edge result (deferred sums taken at pass start)."""
+    p = synth.workload("gm", small=True)["problem"]
+    om, ah = learned_params(p, 1)
+    al = orc.softmax_alpha(p, ah)
+    lam0, M0 = orc.run(p, om, al, 2)
+    S = np.zeros(p.n)
+    np.add.at(S, p.col.astype(np.int64), M0)
+    Se = S[p.col]
+    perm = np.random.default_rng(0).permutation(p.m)
+    q = p.subset_rows(perm)
+    eidx = np.concatenate([np.arange(p.row_ptr[r], p.row_ptr[r + 1]) for r in perm])
+    for direction in (0, 1):
+        lam, M = orc.rows_pass(p, om, al, Se, lam0, direction)
+        lq, Mq = orc.rows_pass(q, om[eidx], al[eidx], Se[eidx], lam0[eidx], direction)
+        np.testing.assert_array_equal(lq, lam[eidx])
+        np.testing.assert_array_equal(Mq, M[eidx])
+        # the full pass with S computed from M0 is the same thing
+        lf, Mf = lam0.copy(), M0.copy()
+        orc.run_pass(p, om, al, lf, Mf, direction)
+        np.testing.assert_array_equal(lf, lam)
+        np.testing.assert_array_equal(Mf, M)
+
+
+# ------------------------------------------------------------------------------------------
+# Prop. 1: feasibility and monotonicity; bound validity
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("wl", ["setcover", "indset", "gm"])
+def test_prop1_invariants(orc, wl):
+    w = synth.workload(wl, small=True)
+    p = w["problem"]
+    al = orc.softmax_alpha(p, w["alpha_hat"])
+    om = w["omega"]
+    var = p.col.astype(np.int64)
+    deg = p.degree()
+    lam, M = orc.init_lambda(p), np.zeros(p.nnz)
+    prev_dl = -np.inf
+    cov = deg > 0
+    for k in range(12):
+        orc.run_pass(p, om, al, lam, M, k % 2)
+        tot = np.zeros(p.n)
+        np.add.at(tot, var, lam + M)
+        np.testing.assert_allclose(tot[cov], p.c[cov], rtol=0, atol=1e-12 * max(1.0, np.abs(p.c).max()) * 10)
+        lb, dl, lbar = orc.lower_bound(p, al, lam, M)
+        tb = np.zeros(p.n)
+        np.add.at(tb, var, lbar)
+        np.testing.assert_allclose(tb[cov], p.c[cov], atol=1e-11)
+        assert dl >= prev_dl - 1e-9 * max(1.0, abs(dl)), (k, dl, prev_dl)
+        assert lb >= dl - 1e-9 * max(1.0, abs(dl))
+        prev_dl = dl
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_lb_below_ilp_optimum(orc, seed):
+    k = 0
+    while True:   # first jointly feasible instance from this seed on
+        p = tiny(1000 * seed + k, n=10, m=7, kmax=6, cover_all=True)
+        opt = brute.ilp_optimum(p)
+        if np.isfinite(opt):
+            break
+        k += 1
+    om, ah = learned_params(p, seed)
+    al = orc.softmax_alpha(p, ah)
+    lam, M = orc.init_lambda(p), np.zeros(p.nnz)
+    for k in range(30):
+        orc.run_pass(p, om, al, lam, M, k % 2)
+        lb, dl, _ = orc.lower_bound(p, al, lam, M)
+        assert lb <= opt + 1e-9 and dl <= lb + 1e-9
+
+
+@pytest.mark.parametrize("wl", ["setcover", "indset"])
+def test_lb_below_lp_optimum(orc, wl):
+    from scipy.optimize import linprog
+    w = synth.workload(wl, small=True)
+    p = w["problem"]
+    al = orc.softmax_alpha(p, w["alpha_hat"])
+    lam, M = orc.run(p, w["omega"], al, 50)
+    lb = orc.lower_bound(p, al, lam, M)[0]
+    # LP relaxation: rows as a_j^T x (sense) b_j, 0 <= x <= 1
+    import scipy.sparse as sp
+    A = sp.csr_matrix((p.coef.astype(float), p.col, p.row_ptr), shape=(p.m, p.n))
+    sgn = np.where(p.sense > 0, -1.0, 1.0)
+    res = linprog(p.c, A_ub=sp.diags(sgn) @ A, b_ub=sgn * p.rhs, bounds=(0, 1), method="highs")
+    assert res.status == 0
+    assert lb <= res.fun + 1e-7 * max(1.0, abs(res.fun))
+    # the rows' polytopes are integral, so the dual optimum is the LP optimum; DMMA gets close
+    assert lb >= res.fun - 0.05 * abs(res.fun)
+
+
+def test_single_row_lb_is_optimum_every_pass(orc):
+    p = tiny(77, n=8, m=1, kmin=8, kmax=8)
+    om, ah = learned_params(p, 3)
+    al = orc.softmax_alpha(p, ah)
+    np.testing.assert_allclose(al, 1.0)
+    opt = brute.ilp_optimum(p)
+    lam, M = orc.init_lambda(p), np.zeros(p.nnz)
+    for k in range(6):
+        orc.run_pass(p, om, al, lam, M, k % 2)
+        assert orc.lower_bound(p, al, lam, M)[0] == pytest.approx(opt, abs=1e-12)
+
+
+def test_disjoint_rows_lb_is_optimum(orc):
+    rows = [(np.array([0, 1, 2]), np.array([2, -1, 3]), -1, 2), (np.array([3, 4]), np.array([1, 1]), 1, 1),
+            (np.array([5, 6, 7]), np.array([1, 1, 1]), 0, 2)]
+    p = synth.generators._from_rows(9, np.random.default_rng(2).normal(size=9), rows, "disjoint")
+    om, ah = learned_params(p, 9)
+    al = orc.softmax_alpha(p, ah)
+    opt = brute.ilp_optimum(p)
+    lam, M = orc.run(p, om, al, 4)
+    assert orc.lower_bound(p, al, lam, M)[0] == pytest.approx(opt, abs=1e-12)
+
+
+def test_zero_damping_keeps_bound(orc):
+    w = synth.workload("setcover")
+    p = w["problem"]
+    al = orc.softmax_alpha(p, w["alpha_hat"])
+    lam0 = orc.init_lambda(p)
+    lam, M = orc.run(p, np.zeros(p.nnz), al, 3)
+    np.testing.assert_array_equal(lam, lam0)
+    assert not M.any()
+
+
+def test_fastdog_special_case_weights(orc):
+    p = synth.workload("gm", small=True)["problem"]
+    al = orc.softmax_alpha(p, np.zeros(p.nnz))
+    np.testing.assert_allclose(al, 1.0 / p.degree()[p.col], rtol=1e-15)
+    al2 = orc.softmax_alpha(p, np.random.default_rng(0).normal(size=p.nnz))
+    s = np.zeros(p.n)
+    np.add.at(s, p.col.astype(np.int64), al2)
+    np.testing.assert_allclose(s[p.degree() > 0], 1.0, rtol=1e-14)
+
+
+# ------------------------------------------------------------------------------------------
+# Alg. 2 and the unrolled gradient: torch autograd over enumeration, central differences
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", range(4))
+def test_pass_vjp_matches_autograd(orc, seed):
+    p = tiny(seed + 300, n=9, m=6, kmax=6)
+    om, ah = learned_params(p, seed)
+    al = orc.softmax_alpha(p, ah)
+    rng = np.random.default_rng(seed)
+    lam_in, M_in = orc.run(p, om, al, 1)
+    for direction in (0, 1):
+        dlo, dmo = rng.normal(size=p.nnz), rng.normal(size=p.nnz)
+        dli, dmi, da, dw = orc.pass_vjp(p, om, al, direction, lam_in, M_in, dlo, dmo)
+        # autograd of the same pass written with enumeration
+        L = torch.tensor(lam_in, requires_grad=True)
+        Mt = torch.tensor(M_in, requires_grad=True)
+        A = torch.tensor(al, requires_grad=True)
+        W = torch.tensor(om, requires_grad=True)
+        lo, Mo = _torch_pass(p, W, A, L, Mt, direction)
+        (lo @ torch.tensor(dlo) + Mo @ torch.tensor(dmo)).backward()
+        np.testing.assert_allclose(dli, L.grad.numpy(), atol=1e-10)
+        np.testing.assert_allclose(dmi, Mt.grad.numpy(), atol=1e-10)
+        np.testing.assert_allclose(da, A.grad.numpy(), atol=1e-10)
+        np.testing.assert_allclose(dw, W.grad.numpy(), atol=1e-10)
+
+
+def _torch_pass(p, W, A, lam, M, direction):
+    sets = [torch.tensor(X, dtype=torch.float64) for X in brute.row_sets(p)]
+    var = torch.tensor(p.col.astype(np.int64))
+    S = torch.zeros(p.n, dtype=torch.float64).index_add(0, var, M)[var]
+    lo_parts, M_parts = [], []
+    for j, X in enumerate(sets):
+        a, b = int(p.row_ptr[j]), int(p.row_ptr[j + 1])
+        lj = [lam[a + l] for l in range(b - a)]
+        Mj = [None] * (b - a)
+        for l in (range(b - a) if direction == 0 else range(b - a - 1, -1, -1)):
+            cost = X @ torch.stack(lj)
+            Mn = W[a + l] * (cost[X[:, l] == 1].min(dim=0).values - cost[X[:, l] == 0].min(dim=0).values)
+            lj[l] = lj[l] - Mn + A[a + l] * S[a + l]
+            Mj[l] = Mn
+        lo_parts += lj
+        M_parts += Mj
+    return torch.stack(lo_parts), torch.stack(M_parts)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_unrolled_grad_matches_autograd(orc, seed):
+    p = tiny(seed + 500, n=9, m=6, kmax=6)
+    om, ah = learned_params(p, seed)
+    al = orc.softmax_alpha(p, ah)
+    T = 3
+    lb, dw, da, dc = orc.unrolled_grad(p, om, al, T)
+    W = torch.tensor(om, requires_grad=True)
+    A = torch.tensor(al, requires_grad=True)
+    Cc = torch.tensor(p.c, requires_grad=True)
+    lbt, _ = brute.dmma_torch(p, W, A, T, c=Cc)
+    lbt.backward()
+    assert lb == pytest.approx(lbt.item(), abs=1e-11)
+    np.testing.assert_allclose(dw, W.grad.numpy(), atol=1e-10)
+    np.testing.assert_allclose(da, A.grad.numpy(), atol=1e-10)
+    np.testing.assert_allclose(dc, Cc.grad.numpy(), atol=1e-10)
+
+
+def test_unrolled_grad_central_differences(orc):
+    """Central differences of the oracle's own LB (f64), away from kinks."""
+    p = tiny(901, n=10, m=7, kmax=6)
+    om, ah = learned_params(p, 4)
+    al = orc.softmax_alpha(p, ah)
+    T = 4
+    lb, dw, da, dc = orc.unrolled_grad(p, om, al, T)
+    h = 1e-6
+    checked = 0
+    for k in range(p.nnz):
+        for arr, g in ((om, dw), (al, da)):
+            xp, xm = arr.copy(), arr.copy()
+            xp[k] += h
+            xm[k] -= h
+            args_p = (xp, al) if arr is om else (om, xp)
+            args_m = (xm, al) if arr is om else (om, xm)
+            fp = orc.lb_after(p, *args_p, T)
+            fm = orc.lb_after(p, *args_m, T)
+            f0 = lb
+            # skip coordinates where the LB is not differentiable (one-sided slopes differ)
+            if abs((fp - f0) - (f0 - fm)) > 1e-9:
+                continue
+            assert (fp - fm) / (2 * h) == pytest.approx(g[k], abs=1e-5)
+            checked += 1
+    for i in range(p.n):
+        cp, cm = p.c.copy(), p.c.copy()
+        cp[i] += h
+        cm[i] -= h
+        fp, fm = orc.lb_after(p, om, al, T, c=cp), orc.lb_after(p, om, al, T, c=cm)
+        if abs((fp - lb) - (lb - fm)) > 1e-9:
+            continue
+        assert (fp - fm) / (2 * h) == pytest.approx(dc[i], abs=1e-5)
+        checked += 1
+    assert checked >= p.nnz
+
+
+def test_softmax_vjp_matches_autograd(orc):
+    p = synth.workload("gm", small=True)["problem"]
+    ah = np.random.default_rng(3).normal(size=p.nnz)
+    g = np.random.default_rng(4).normal(size=p.nnz)
+    al = orc.softmax_alpha(p, ah)
+    got = orc.softmax_alpha_vjp(p, al, g)
+    A = torch.tensor(ah, requires_grad=True)
+    var = torch.tensor(p.col.astype(np.int64))
+    mx = torch.zeros(p.n, dtype=torch.float64).index_reduce(0, var, A.detach(), "amax", include_self=False)
+    z = torch.exp(A - mx[var])
+    den = torch.zeros(p.n, dtype=torch.float64).index_add(0, var, z)
+    (z / den[var] @ torch.tensor(g)).backward()
+    np.testing.assert_allclose(got, A.grad.numpy(), atol=1e-12)
