@@ -1,0 +1,191 @@
+/*
+ * dd.h -- C ABI of the MI355X Lagrange-decomposition dual solver for binary programs.
+ *
+ * The library implements the data-parallel hot path of generalized min-marginal
+ * averaging (Alg. 1 of "DOGE-Train", with its BlockUpdate backpropagation, Alg. 2):
+ * every constraint row becomes a binary decision diagram (App. B), one dual
+ * iteration is a forward and a backward pass of min-sum sweeps over all of them,
+ * and the dual lower bound (D) is reduced on the device.
+ *
+ * Conventions shared by every entry point
+ *  - Status: every function returns 0 (DD_OK) or a negative DD_E_* code; nothing
+ *    throws across the ABI.  dd_last_error() returns a thread-local message about
+ *    the last failure on the calling thread.
+ *  - Edges: a Lagrange multiplier lambda_ij (variable i, row j) is an edge.  Arrays
+ *    indexed by edge use the canonical order: rows in input order, the variables of
+ *    each row in ascending index order.  Rows given with unsorted columns are sorted
+ *    (coefficients follow); duplicate columns are rejected.
+ *  - Memory: pointers documented "device" must point to device memory of the
+ *    instance's GPU, allocated and owned by the caller, of the stated length; the
+ *    library reads or writes them in stream order on the given stream and keeps no
+ *    reference after the call.  "host" pointers are read or written before the call
+ *    returns.  All inputs are copied; the instance owns its device buffers and frees
+ *    them in dd_destroy.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Functions that return a host scalar synchronize that stream.
+ *  - Numbers: all device-side arithmetic is IEEE fp32; reported bounds are fp64 sums
+ *    of fp32 terms.
+ *  - Readings of the paper (stated once here, used throughout):
+ *      * a forward pass visits the variables of each row in ascending index order
+ *        and a backward pass in descending order (blocks B_1..B_u = hop positions);
+ *      * the deferred term alpha_ij * sum_{k in J_i} M_ik of Alg. 1 uses the M of
+ *        the previous pass for the whole pass (pass-start snapshot), as the
+ *        feasibility half of the proof of Prop. 1 requires;
+ *      * lambda starts at c_i / |J_i| and M at 0;
+ *      * the lower bound is (D) at the flushed multipliers
+ *        lambda_bar_ij = lambda_ij + alpha_ij * sum_k M_ik, plus min(0, c_i) for every
+ *        variable that appears in no row.
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DD_OK = 0,
+    DD_E_ARG = -1,         /* bad argument: null pointer, index out of range, duplicate column, bad sense */
+    DD_E_INFEASIBLE = -2,  /* a row has no feasible assignment */
+    DD_E_FORCED = -3,      /* a row fixes one of its variables (a min-marginal would be infinite) */
+    DD_E_PARAM = -4,       /* non-finite cost, omega outside [0,1], non-finite or negative alpha */
+    DD_E_HIP = -5,         /* a HIP runtime call failed (message has the HIP error string) */
+    DD_E_UNSUPPORTED = -6, /* a row's decision diagram is wider than the kernels support */
+    DD_E_OOM = -7,         /* device or host allocation failed */
+    DD_E_NONFINITE = -8,   /* a reduced bound is not finite */
+    DD_E_STATE = -9        /* call out of order (e.g. backward without a recorded forward) */
+};
+
+/* Binary program (Def. 1): min <c, x> s.t. each row  sum_p coef[p] x[col[p]]  (sense)  rhs,
+ * x in {0,1}^n; sense -1 means <=, 0 means ==, +1 means >=.  Rows in CSR form: row j
+ * holds entries row_ptr[j] .. row_ptr[j+1]-1.  All host pointers. */
+typedef struct {
+    int32_t n;              /* number of variables */
+    const double *c;        /* [n] costs */
+    int32_t m;              /* number of rows (subproblems) */
+    const int64_t *row_ptr; /* [m+1], row_ptr[0] = 0, non-decreasing */
+    const int32_t *col;     /* [nnz] variable ids in [0, n) */
+    const int32_t *coef;    /* [nnz] non-zero integer coefficients */
+    const int8_t *sense;    /* [m] */
+    const int64_t *rhs;     /* [m] */
+} dd_problem;
+
+/* Launch options; zero means "default".  Pass NULL for all defaults. */
+typedef struct {
+    int32_t nodes_per_lane; /* target decision-diagram nodes per lane per hop (team size choice), default 4 */
+    int32_t waves_per_block;/* waves (tiles) per workgroup, default 4 */
+    int32_t ckpt_every;     /* iterations between adjoint checkpoints, default 5 */
+    int32_t lds_budget;     /* max LDS bytes per workgroup, default 64 KiB */
+    int32_t reserved[4];
+} dd_options;
+
+typedef struct {
+    int64_t n, m, edges;    /* variables, rows, edges (Lagrange multipliers) */
+    int64_t nodes;          /* decision-diagram nodes (non-terminal) */
+    int64_t arcs;           /* 2 * nodes, arcs to the 0-terminal included */
+    int64_t node_slots;     /* nodes plus layout padding, as stored on the device */
+    int64_t edge_slots;     /* edges plus layout padding */
+    int64_t tiles;          /* wavefront tiles */
+    int32_t max_width;      /* widest level of any diagram */
+    int32_t max_len;        /* longest row */
+    int32_t classes;        /* kernel specialisations used */
+    int32_t uncovered;      /* variables in no row */
+    int64_t device_bytes;   /* bytes the instance holds on the device */
+} dd_stats;
+
+typedef struct dd_instance dd_instance;
+
+/* Thread-local message describing the last error on this thread ("" if none). */
+const char *dd_last_error(void);
+
+/* Compile every row to a quasi-reduced ordered decision diagram (App. B: every
+ * root-to-1 path visits one node per variable; paths are exactly X_j), lay them out
+ * for the device, upload, and reset the solver (lambda = c/|J_i|, M = 0, omega = 0.5,
+ * alpha = 1/|J_i|: the special case of the Remark after Alg. 1's description).
+ * Uses the current HIP device.  Errors: DD_E_ARG, DD_E_PARAM, DD_E_INFEASIBLE,
+ * DD_E_FORCED, DD_E_UNSUPPORTED, DD_E_OOM, DD_E_HIP.  On error *out is NULL. */
+int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_instance **out);
+
+/* Free all device and host memory of the instance (NULL is accepted). */
+int dd_destroy(dd_instance *h);
+
+/* Sizes of the instance (host struct). */
+int dd_get_stats(const dd_instance *h, dd_stats *out);
+
+/* Canonical edge e -> (variable, row); host arrays of length edges. */
+int dd_edge_map(const dd_instance *h, int32_t *var_out, int32_t *row_out);
+
+/* Set the damping factors omega_ij (in [0,1], Prop. 1) and averaging weights alpha_ij
+ * (>= 0; Prop. 1 also needs sum_{j in J_i} alpha_ij = 1, which the caller ensures,
+ * e.g. through dd_seg_softmax).  Device arrays [edges], canonical order, copied. */
+int dd_set_params(dd_instance *h, const float *omega, const float *alpha, void *stream);
+
+/* alpha_{i.} = softmax over J_i of alpha_hat_{i.} (the transform of Alg. 3 that makes
+ * alpha a convex combination).  Device arrays [edges], canonical order. */
+int dd_seg_softmax(dd_instance *h, const float *alpha_hat, float *alpha_out, void *stream);
+
+/* Back to the start state: lambda = c_i/|J_i|, M = 0, shortest-path costs recomputed. */
+int dd_reset(dd_instance *h, void *stream);
+
+/* Replace the solver state (device arrays [edges], canonical order); shortest-path
+ * costs are recomputed. */
+int dd_set_state(dd_instance *h, const float *lambda, const float *M, void *stream);
+
+/* Read the state into device arrays [edges] (canonical order).  flushed != 0 returns
+ * lambda_bar = lambda + alpha * S instead of lambda.  M_out may be NULL. */
+int dd_get_state(dd_instance *h, float *lambda_out, float *M_out, int32_t flushed, void *stream);
+
+/* T iterations of Alg. 1: each a forward pass (hops in ascending variable order)
+ * then a backward pass; every pass applies BlockUpdate to all hops of all rows. */
+int dd_run(dd_instance *h, int32_t T, void *stream);
+
+/* One pass: direction 0 = forward, 1 = backward. */
+int dd_run_pass(dd_instance *h, int32_t direction, void *stream);
+
+/* Lower bound (D) at lambda_bar plus the uncovered-variable constant (into *lb), and
+ * the lifted-representation bound of Prop. 1's proof,
+ * D_L = sum_j E^j(lambda) + sum_e min(0, M_e) + the same constant (into *dl, may be NULL).
+ * Synchronizes the stream.  DD_E_NONFINITE if a bound is not finite. */
+int dd_lower_bound(dd_instance *h, double *lb, double *dl, void *stream);
+
+/* Per-row energies E^j(lambda_bar) (eq. 1) into a device array [m]. */
+int dd_row_energies(dd_instance *h, float *E_out, void *stream);
+
+/* Min-marginals m^0, m^1 of every edge at lambda_bar (eq. 8), device arrays [edges]. */
+int dd_min_marginals(dd_instance *h, float *m0_out, float *m1_out, void *stream);
+
+/* Nodes of each row's diagram, host array [m] (0 for an empty row). */
+int dd_row_nodes(const dd_instance *h, int64_t *nodes_out);
+
+/* Per-kernel timing of the instance's own launches, for roofline reporting.
+ * dd_profile_begin starts recording a HIP event pair around every kernel launch the
+ * instance makes (pool of `max_launches` pairs, created here so recording allocates
+ * nothing); dd_profile_end synchronizes the device, stops recording and aggregates
+ * by kernel: out[k] gets the kernel's name (as the profiler shows it), launch count,
+ * summed duration and the algorithmic bytes one launch must move (the per-node and
+ * per-edge traffic of the method times the nodes and edges the launch covers).
+ * *count receives the number of kernels (at most cap are written). */
+typedef struct {
+    char name[96];
+    int64_t launches;
+    double total_ms;
+    double bytes_per_launch;
+} dd_kernel_time;
+int dd_profile_begin(dd_instance *h, int32_t max_launches);
+int dd_profile_end(dd_instance *h, dd_kernel_time *out, int32_t cap, int32_t *count);
+
+/* Host-only helper: compile row `row` of prob and return its diagram.  width[L] gets
+ * the node count per level (L = row length); arcs[nodes] gets, level by level, each
+ * node's (lo | hi << 16) child codes, where a code c < width[l+1] is a node of the
+ * next level, c == width[l+1] the 0-terminal and c == width[l+1] + 1 the 1-terminal
+ * (width[L] taken as 0).  *nodes receives the node count; arcs may be NULL to query
+ * it.  cap is the capacity of arcs.  No GPU needed. */
+int dd_compile_row(const dd_problem *prob, int32_t row, int32_t *width, uint32_t *arcs, int64_t cap,
+                   int64_t *nodes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DD_H */

@@ -587,3 +587,13 @@ done:
     free(deg);
     return st;
 }
+
+/* Threads the parallel loops above will use. */
+int orc_threads(int nthreads) {
+    set_threads(nthreads);
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

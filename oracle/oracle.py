@@ -225,3 +225,8 @@ def lb_after(prob, omega, alpha, T, c=None, threads=0):
         prob = dataclasses.replace(prob, c=np.asarray(c, dtype=np.float64))
     lam, M = run(prob, omega, alpha, T, threads=threads)
     return lower_bound(prob, alpha, lam, M, threads=threads)[0]
+
+
+def threads(n=0):
+    """Number of OpenMP threads the oracle's loops use (n > 0 sets it)."""
+    return int(_load().orc_threads(C.c_int(n)))

@@ -1,0 +1,252 @@
+"""Thin ctypes binding of libdd.so: argument marshalling only.
+
+Every step of the solver runs in the library's HIP kernels; this module passes
+pointers, sizes and the current torch stream.  It fails loudly when the built
+library is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdd.so")
+
+DD_OK, DD_E_ARG, DD_E_INFEASIBLE, DD_E_FORCED, DD_E_PARAM, DD_E_HIP, DD_E_UNSUPPORTED, DD_E_OOM, DD_E_NONFINITE, \
+    DD_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+
+_NAMES = {0: "DD_OK", -1: "DD_E_ARG", -2: "DD_E_INFEASIBLE", -3: "DD_E_FORCED", -4: "DD_E_PARAM", -5: "DD_E_HIP",
+          -6: "DD_E_UNSUPPORTED", -7: "DD_E_OOM", -8: "DD_E_NONFINITE", -9: "DD_E_STATE"}
+
+
+class DDError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class dd_problem(C.Structure):
+    _fields_ = [("n", C.c_int32), ("c", C.POINTER(C.c_double)), ("m", C.c_int32),
+                ("row_ptr", C.POINTER(C.c_int64)), ("col", C.POINTER(C.c_int32)), ("coef", C.POINTER(C.c_int32)),
+                ("sense", C.POINTER(C.c_int8)), ("rhs", C.POINTER(C.c_int64))]
+
+
+class dd_options(C.Structure):
+    _fields_ = [("nodes_per_lane", C.c_int32), ("waves_per_block", C.c_int32), ("ckpt_every", C.c_int32),
+                ("lds_budget", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+class dd_stats(C.Structure):
+    _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("edges", C.c_int64), ("nodes", C.c_int64), ("arcs", C.c_int64),
+                ("node_slots", C.c_int64), ("edge_slots", C.c_int64), ("tiles", C.c_int64),
+                ("max_width", C.c_int32), ("max_len", C.c_int32), ("classes", C.c_int32), ("uncovered", C.c_int32),
+                ("device_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class dd_kernel_time(C.Structure):
+    _fields_ = [("name", C.c_char * 96), ("launches", C.c_int64), ("total_ms", C.c_double),
+                ("bytes_per_launch", C.c_double)]
+
+
+_lib = None
+
+# (name, argtypes) of every exported entry point
+_VP = C.c_void_p
+SIGNATURES = {
+    "dd_last_error": ([], C.c_char_p),
+    "dd_create": ([C.POINTER(dd_problem), C.POINTER(dd_options), _VP, C.POINTER(_VP)], C.c_int),
+    "dd_destroy": ([_VP], C.c_int),
+    "dd_get_stats": ([_VP, C.POINTER(dd_stats)], C.c_int),
+    "dd_edge_map": ([_VP, _VP, _VP], C.c_int),
+    "dd_set_params": ([_VP, _VP, _VP, _VP], C.c_int),
+    "dd_seg_softmax": ([_VP, _VP, _VP, _VP], C.c_int),
+    "dd_reset": ([_VP, _VP], C.c_int),
+    "dd_set_state": ([_VP, _VP, _VP, _VP], C.c_int),
+    "dd_get_state": ([_VP, _VP, _VP, C.c_int32, _VP], C.c_int),
+    "dd_run": ([_VP, C.c_int32, _VP], C.c_int),
+    "dd_run_pass": ([_VP, C.c_int32, _VP], C.c_int),
+    "dd_lower_bound": ([_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), _VP], C.c_int),
+    "dd_row_energies": ([_VP, _VP, _VP], C.c_int),
+    "dd_min_marginals": ([_VP, _VP, _VP, _VP], C.c_int),
+    "dd_row_nodes": ([_VP, _VP], C.c_int),
+    "dd_profile_begin": ([_VP, C.c_int32], C.c_int),
+    "dd_profile_end": ([_VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "dd_compile_row": ([C.POINTER(dd_problem), C.c_int32, _VP, _VP, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+}
+
+
+def lib():
+    """Load libdd.so (built in-tree by paper_2205_11638_amd.build); raises if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built: run `python -m paper_2205_11638_amd.build` "
+                              "(the solver has no non-HIP path)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != DD_OK:
+        raise DDError(code, lib().dd_last_error().decode())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, dtype=None, n=None):
+    """Device pointer of a contiguous CUDA tensor (checked)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a device (cuda) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return C.c_void_p(t.data_ptr())
+
+
+class _ProblemArgs:
+    """Keeps the numpy arrays behind a dd_problem alive."""
+
+    def __init__(self, prob):
+        self.c = np.ascontiguousarray(prob.c, dtype=np.float64)
+        self.row_ptr = np.ascontiguousarray(prob.row_ptr, dtype=np.int64)
+        self.col = np.ascontiguousarray(prob.col, dtype=np.int32)
+        self.coef = np.ascontiguousarray(prob.coef, dtype=np.int32)
+        self.sense = np.ascontiguousarray(prob.sense, dtype=np.int8)
+        self.rhs = np.ascontiguousarray(prob.rhs, dtype=np.int64)
+        self.st = dd_problem(int(prob.n), self.c.ctypes.data_as(C.POINTER(C.c_double)), int(len(self.rhs)),
+                             self.row_ptr.ctypes.data_as(C.POINTER(C.c_int64)),
+                             self.col.ctypes.data_as(C.POINTER(C.c_int32)),
+                             self.coef.ctypes.data_as(C.POINTER(C.c_int32)),
+                             self.sense.ctypes.data_as(C.POINTER(C.c_int8)),
+                             self.rhs.ctypes.data_as(C.POINTER(C.c_int64)))
+
+
+def compile_row(prob, row):
+    """Host-only: (widths[L], arcs[nodes] as uint32 lo | hi << 16) of row `row`'s diagram."""
+    L_ = lib()
+    pa = _ProblemArgs(prob)
+    length = int(prob.row_ptr[row + 1] - prob.row_ptr[row])
+    nodes = C.c_int64()
+    _check(L_.dd_compile_row(C.byref(pa.st), int(row), None, None, 0, C.byref(nodes)))
+    w = np.zeros(max(length, 1), dtype=np.int32)
+    arcs = np.zeros(max(nodes.value, 1), dtype=np.uint32)
+    _check(L_.dd_compile_row(C.byref(pa.st), int(row), w.ctypes.data_as(C.c_void_p), arcs.ctypes.data_as(C.c_void_p),
+                             int(arcs.size), C.byref(nodes)))
+    return w[:length], arcs[:nodes.value]
+
+
+class Instance:
+    """A binary program resident on the current GPU (see include/dd.h for the semantics)."""
+
+    def __init__(self, prob, nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0):
+        import torch
+        L_ = lib()
+        pa = _ProblemArgs(prob)
+        opt = dd_options(int(nodes_per_lane), int(waves_per_block), int(ckpt_every), int(lds_budget))
+        h = C.c_void_p()
+        # input validation and compilation run on the host before any HIP call
+        stream = _stream() if torch.cuda.is_available() else None
+        _check(L_.dd_create(C.byref(pa.st), C.byref(opt), stream, C.byref(h)))
+        self._h = h
+        self._L = L_
+        st = dd_stats()
+        _check(L_.dd_get_stats(h, C.byref(st)))
+        self.stats = st.as_dict()
+        self.n, self.m, self.E = int(st.n), int(st.m), int(st.edges)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.dd_destroy(self._h)
+            self._h = None
+
+    __del__ = close
+
+    def _f32(self, n):
+        import torch
+        return torch.empty(n, dtype=torch.float32, device=self.device)
+
+    def edge_map(self):
+        var = np.empty(self.E, dtype=np.int32)
+        row = np.empty(self.E, dtype=np.int32)
+        _check(self._L.dd_edge_map(self._h, var.ctypes.data_as(C.c_void_p), row.ctypes.data_as(C.c_void_p)))
+        return var, row
+
+    def set_params(self, omega, alpha):
+        import torch
+        _check(self._L.dd_set_params(self._h, _dptr(omega, torch.float32, self.E), _dptr(alpha, torch.float32, self.E),
+                                     _stream()))
+
+    def seg_softmax(self, alpha_hat):
+        import torch
+        out = self._f32(self.E)
+        _check(self._L.dd_seg_softmax(self._h, _dptr(alpha_hat, torch.float32, self.E), _dptr(out), _stream()))
+        return out
+
+    def reset(self):
+        _check(self._L.dd_reset(self._h, _stream()))
+
+    def set_state(self, lam, M):
+        import torch
+        _check(self._L.dd_set_state(self._h, _dptr(lam, torch.float32, self.E), _dptr(M, torch.float32, self.E),
+                                    _stream()))
+
+    def get_state(self, flushed=False):
+        lam, M = self._f32(self.E), self._f32(self.E)
+        _check(self._L.dd_get_state(self._h, _dptr(lam), _dptr(M), int(bool(flushed)), _stream()))
+        return lam, M
+
+    def run(self, T):
+        _check(self._L.dd_run(self._h, int(T), _stream()))
+
+    def run_pass(self, direction):
+        _check(self._L.dd_run_pass(self._h, int(direction), _stream()))
+
+    def lower_bound(self):
+        lb, dl = C.c_double(), C.c_double()
+        _check(self._L.dd_lower_bound(self._h, C.byref(lb), C.byref(dl), _stream()))
+        return lb.value, dl.value
+
+    def row_energies(self):
+        out = self._f32(self.m)
+        _check(self._L.dd_row_energies(self._h, _dptr(out), _stream()))
+        return out
+
+    def min_marginals(self):
+        m0, m1 = self._f32(self.E), self._f32(self.E)
+        _check(self._L.dd_min_marginals(self._h, _dptr(m0), _dptr(m1), _stream()))
+        return m0, m1
+
+    def row_nodes(self):
+        out = np.empty(self.m, dtype=np.int64)
+        _check(self._L.dd_row_nodes(self._h, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def profile_begin(self, max_launches=4096):
+        _check(self._L.dd_profile_begin(self._h, int(max_launches)))
+
+    def profile_end(self):
+        """{kernel name: (launches, total_ms, algorithmic bytes per launch)} since profile_begin."""
+        cap = 64
+        arr = (dd_kernel_time * cap)()
+        cnt = C.c_int32()
+        _check(self._L.dd_profile_end(self._h, C.cast(arr, C.c_void_p), cap, C.byref(cnt)))
+        return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms), float(arr[i].bytes_per_launch))
+                for i in range(min(cnt.value, cap))}

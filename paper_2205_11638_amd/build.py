@@ -1,0 +1,66 @@
+"""Build the HIP shared library libdd.so in-tree for gfx950.
+
+    python -m paper_2205_11638_amd.build      (or call build())
+
+Host C++ is compiled with g++, device code with hipcc --offload-arch=gfx950; the
+objects are linked by hipcc into paper_2205_11638_amd/libdd.so.
+"""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+import tempfile
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libdd.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+HIPCC = os.path.join(ROCM, "bin", "hipcc")
+
+HOST_SRC = ["bdd.cpp", "dd_api.cpp"]
+DEVICE_SRC = ["kernels.hip"]
+# packed-fp32 instructions are disabled for all device code
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
+             "-packed-fp32-ops", "-Wall", "-Wno-unused-result"]
+HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
+        raise RuntimeError(f"build step failed: {cmd[0]} ({r.returncode})")
+    return r
+
+
+def build(verbose=False) -> str:
+    """Compile every source (always) and link libdd.so; returns the library path."""
+    with tempfile.TemporaryDirectory(prefix="ddbuild") as tmp:
+        objs = []
+        procs = []
+        for f in HOST_SRC:
+            o = os.path.join(tmp, f + ".o")
+            procs.append((["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, f), "-o", o]))
+            objs.append(o)
+        for f in DEVICE_SRC:
+            o = os.path.join(tmp, f + ".o")
+            procs.append(([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, f), "-o", o]))
+            objs.append(o)
+        running = [(c, subprocess.Popen(c, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True))
+                   for c in procs]
+        for c, p in running:
+            out, _ = p.communicate()
+            if verbose and out:
+                sys.stderr.write(out)
+            if p.returncode != 0:
+                sys.stderr.write(" ".join(c) + "\n" + (out or ""))
+                raise RuntimeError("compile failed: " + c[-3])
+        tmp_lib = LIB + ".tmp%d" % os.getpid()
+        _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_lib, *objs, "-lpthread"])
+        os.replace(tmp_lib, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

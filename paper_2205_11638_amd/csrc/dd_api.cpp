@@ -1,0 +1,782 @@
+// dd_api.cpp -- C ABI: problem validation, parallel diagram compilation, tile packing,
+// device memory and the launch sequences of the hot path.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/dd.h"
+#include "bdd.hpp"
+#include "kernels.hpp"
+
+using namespace dd;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(x)                                                                                  \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess) return fail(DD_E_HIP, "%s: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+int worker_count() {
+    const char *env = getenv("DD_THREADS");
+    int n = env ? atoi(env) : (int)std::thread::hardware_concurrency();
+    return std::max(1, std::min(n, 64));
+}
+
+template <class F>
+void parallel_for(int64_t n, int64_t chunk, F f) {
+    int nw = (int)std::min<int64_t>(worker_count(), (n + chunk - 1) / std::max<int64_t>(chunk, 1));
+    if (nw <= 1) {
+        for (int64_t i = 0; i < n; ++i) f(i, 0);
+        return;
+    }
+    std::atomic<int64_t> next(0);
+    std::vector<std::thread> th;
+    for (int w = 0; w < nw; ++w)
+        th.emplace_back([&, w] {
+            for (;;) {
+                int64_t a = next.fetch_add(chunk);
+                if (a >= n) break;
+                int64_t b = std::min(n, a + chunk);
+                for (int64_t i = a; i < b; ++i) f(i, w);
+            }
+        });
+    for (auto &t : th) t.join();
+}
+
+int next_pow2(int v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// Sorted copy of the problem's rows (canonical order: variables ascending in each row).
+struct SortedRows {
+    std::vector<int64_t> ptr;
+    std::vector<int32_t> col, coef;
+};
+
+int validate_and_sort(const dd_problem *p, SortedRows &sr) {
+    if (!p) return fail(DD_E_ARG, "problem is NULL");
+    if (p->n < 0 || p->m < 0) return fail(DD_E_ARG, "negative n or m");
+    if (p->n > 0 && !p->c) return fail(DD_E_ARG, "c is NULL");
+    if (!p->row_ptr) return fail(DD_E_ARG, "row_ptr is NULL");
+    if (p->row_ptr[0] != 0) return fail(DD_E_ARG, "row_ptr[0] must be 0");
+    for (int j = 0; j < p->m; ++j)
+        if (p->row_ptr[j + 1] < p->row_ptr[j]) return fail(DD_E_ARG, "row_ptr decreases at row %d", j);
+    const int64_t nnz = p->row_ptr[p->m];
+    if (nnz > 0 && (!p->col || !p->coef)) return fail(DD_E_ARG, "col or coef is NULL");
+    if (p->m > 0 && (!p->sense || !p->rhs)) return fail(DD_E_ARG, "sense or rhs is NULL");
+    if (nnz >= ((int64_t)1 << 31) - 1) return fail(DD_E_UNSUPPORTED, "more than 2^31 edges");
+    for (int i = 0; i < p->n; ++i)
+        if (!std::isfinite(p->c[i])) return fail(DD_E_PARAM, "c[%d] is not finite", i);
+    sr.ptr.assign(p->row_ptr, p->row_ptr + p->m + 1);
+    sr.col.resize(nnz);
+    sr.coef.resize(nnz);
+    std::atomic<int> status(DD_OK);
+    std::atomic<int> bad_row(-1);
+    parallel_for(p->m, 256, [&](int64_t j, int) {
+        const int64_t a = p->row_ptr[j], b = p->row_ptr[j + 1];
+        if (p->sense[j] < -1 || p->sense[j] > 1) {
+            status = DD_E_ARG;
+            bad_row = (int)j;
+            return;
+        }
+        std::vector<std::pair<int32_t, int32_t>> v;
+        v.reserve(b - a);
+        for (int64_t q = a; q < b; ++q) {
+            if (p->col[q] < 0 || p->col[q] >= p->n || p->coef[q] == 0) {
+                status = DD_E_ARG;
+                bad_row = (int)j;
+                return;
+            }
+            v.emplace_back(p->col[q], p->coef[q]);
+        }
+        std::sort(v.begin(), v.end());
+        for (size_t t = 0; t < v.size(); ++t) {
+            if (t && v[t].first == v[t - 1].first) {
+                status = DD_E_ARG;
+                bad_row = (int)j;
+                return;
+            }
+            sr.col[a + t] = v[t].first;
+            sr.coef[a + t] = v[t].second;
+        }
+    });
+    if (status != DD_OK)
+        return fail(DD_E_ARG, "row %d: bad sense, variable out of range, zero coefficient or duplicate variable",
+                    (int)bad_row);
+    return DD_OK;
+}
+
+struct HostPlan {
+    std::vector<ClassLaunch> classes;
+    // tiles
+    std::vector<int64_t> node_base;
+    std::vector<int32_t> edge_base, nlev, lev_base, w_base, bdd;
+    std::vector<int32_t> lev_off, lev_rows;
+    std::vector<uint16_t> widths;
+    std::vector<int32_t> tile_P;
+    int64_t node_slots = 0, edge_slots = 0;
+    // edges
+    std::vector<int32_t> canon2slot, slot2canon, evar;
+    std::vector<int32_t> var_ptr, var_slots, var_canon;
+};
+
+}  // namespace
+
+struct dd_instance {
+    int device = 0;
+    int64_t n = 0, m = 0, E = 0, nodes = 0;
+    int max_width = 0, max_len = 0, uncovered = 0;
+    double unc_const = 0.0;
+    std::vector<ClassLaunch> classes;
+    int64_t ntiles = 0, node_slots = 0, edge_slots = 0, device_bytes = 0;
+    std::vector<int32_t> edge_var, edge_row;  // canonical edge map (host)
+    std::vector<int64_t> row_nodes;
+    // profiling: event pairs recorded around launches while enabled
+    struct Rec {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    std::vector<Rec> recs;
+    std::vector<std::string> kname;
+    std::vector<double> kbytes;
+    int kernel_id(const std::string &name, double bytes) {
+        for (size_t q = 0; q < kname.size(); ++q)
+            if (kname[q] == name) return (int)q;
+        kname.push_back(name);
+        kbytes.push_back(bytes);
+        return (int)kname.size() - 1;
+    }
+    // device buffers
+    std::vector<void *> allocs;
+    DevTables T{};
+    int32_t *var_ptr = nullptr, *var_slots = nullptr, *var_canon = nullptr, *canon2slot = nullptr;
+    float *cdev = nullptr, *S = nullptr, *omega = nullptr, *alpha = nullptr, *tmp = nullptr;
+    double *red = nullptr;   // device reduction output [4]
+    double *red_host = nullptr;  // pinned
+    int32_t *flags = nullptr;
+
+    ~dd_instance() {
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        for (void *p : allocs) (void)hipFree(p);
+        if (red_host) (void)hipHostFree(red_host);
+    }
+    template <class T_>
+    int alloc(T_ **p, size_t count) {
+        void *q = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T_);
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return fail(DD_E_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+        allocs.push_back(q);
+        device_bytes += (int64_t)bytes;
+        *p = (T_ *)q;
+        return DD_OK;
+    }
+};
+
+namespace {
+
+template <class T_>
+int upload(dd_instance *h, T_ **dst, const std::vector<T_> &src, hipStream_t s) {
+    int st = h->alloc(dst, src.size());
+    if (st) return st;
+    if (!src.empty()) HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T_), hipMemcpyHostToDevice, s));
+    return DD_OK;
+}
+
+int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowBdd> &bdds, int npl, int wpb,
+               int lds_budget, HostPlan &hp, std::vector<uint32_t> &topo) {
+    const int m = p->m;
+    // class of every row
+    std::vector<int> rP(m, 0), rR(m, 0);
+    for (int j = 0; j < m; ++j) {
+        const RowBdd &b = bdds[j];
+        if (b.L == 0) continue;
+        int P = std::min(64, next_pow2((b.max_width + npl - 1) / npl));
+        int R = (b.max_width + P - 1) / P;
+        int RMAX = P < 64 ? 4 : std::max(4, next_pow2(R));
+        if (!class_supported(P, RMAX))
+            return fail(DD_E_UNSUPPORTED, "row %d: diagram width %d is wider than the kernels support (2048)", j,
+                        b.max_width);
+        rP[j] = P;
+        rR[j] = RMAX;
+    }
+    std::vector<int> order;
+    for (int j = 0; j < m; ++j)
+        if (bdds[j].L > 0) order.push_back(j);
+    std::sort(order.begin(), order.end(), [&](int x, int y) {
+        if (rP[x] != rP[y]) return rP[x] < rP[y];
+        if (rR[x] != rR[y]) return rR[x] < rR[y];
+        if (bdds[x].L != bdds[y].L) return bdds[x].L > bdds[y].L;
+        if (bdds[x].max_width != bdds[y].max_width) return bdds[x].max_width > bdds[y].max_width;
+        return x < y;
+    });
+    // tiles
+    size_t i = 0;
+    int64_t node_slots = 0, edge_slots = 0;
+    while (i < order.size()) {
+        const int P = rP[order[i]], RMAX = rR[order[i]], G = 64 / P;
+        ClassLaunch cl{};
+        cl.P = P;
+        cl.RMAX = RMAX;
+        cl.WL = 1;
+        cl.tile0 = (int64_t)hp.nlev.size();
+        size_t j = i;
+        while (j < order.size() && rP[order[j]] == P && rR[order[j]] == RMAX) ++j;
+        for (size_t t0 = i; t0 < j; t0 += G) {
+            const size_t t1 = std::min(j, t0 + G);
+            int nl = 0;
+            for (size_t q = t0; q < t1; ++q) {
+                nl = std::max(nl, bdds[order[q]].L);
+                cl.WL = std::max(cl.WL, bdds[order[q]].max_width);
+                cl.nodes += (int64_t)bdds[order[q]].arcs.size();
+                cl.edges += bdds[order[q]].L;
+                cl.rows += 1;
+            }
+            hp.node_base.push_back(node_slots);
+            if (edge_slots + (int64_t)nl * G >= ((int64_t)1 << 31)) return fail(DD_E_UNSUPPORTED, "too many edge slots");
+            hp.edge_base.push_back((int32_t)edge_slots);
+            hp.nlev.push_back(nl);
+            hp.lev_base.push_back((int32_t)hp.lev_off.size());
+            hp.w_base.push_back((int32_t)hp.widths.size());
+            hp.tile_P.push_back(P);
+            for (int g = 0; g < 64; ++g) hp.bdd.push_back(g < G && t0 + g < t1 ? order[t0 + g] : -1);
+            int64_t off = 0;
+            for (int l = 0; l < nl; ++l) {
+                int R = 0;
+                for (int g = 0; g < G; ++g) {
+                    int w = 0;
+                    if (t0 + g < t1 && l < bdds[order[t0 + g]].L) w = bdds[order[t0 + g]].width[l];
+                    hp.widths.push_back((uint16_t)w);
+                    R = std::max(R, (w + P - 1) / P);
+                }
+                if (off >= ((int64_t)1 << 31)) return fail(DD_E_UNSUPPORTED, "tile too large");
+                if (R > RMAX) return fail(DD_E_UNSUPPORTED, "internal: level needs %d rows > %d", R, RMAX);
+                hp.lev_off.push_back((int32_t)off);
+                hp.lev_rows.push_back(R);
+                off += (int64_t)R * 64;
+            }
+            node_slots += off;
+            edge_slots += (int64_t)nl * G;
+        }
+        cl.ntiles = (int64_t)hp.nlev.size() - cl.tile0;
+        // waves per workgroup limited by the LDS budget: 2 buffers * WL * G * 4 bytes per wave
+        const int64_t per_wave = 2LL * cl.WL * G * 4;
+        if (per_wave > 160 * 1024) return fail(DD_E_UNSUPPORTED, "LDS need %lld bytes per wave", (long long)per_wave);
+        cl.wpb = std::max(1, (int)std::min<int64_t>(wpb, std::max<int64_t>(1, lds_budget / per_wave)));
+        hp.classes.push_back(cl);
+        i = j;
+    }
+    hp.node_slots = node_slots;
+    hp.edge_slots = edge_slots;
+    // nodes
+    topo.assign((size_t)node_slots, 0u);
+    const int64_t ntiles = (int64_t)hp.nlev.size();
+    parallel_for(ntiles, 64, [&](int64_t t, int) {
+        const int P = hp.tile_P[t], G = 64 / P;
+        for (int g = 0; g < G; ++g) {
+            const int row = hp.bdd[t * 64 + g];
+            if (row < 0) continue;
+            const RowBdd &b = bdds[row];
+            size_t src = 0;
+            for (int l = 0; l < b.L; ++l) {
+                const int64_t base = hp.node_base[t] + hp.lev_off[hp.lev_base[t] + l];
+                for (int k = 0; k < b.width[l]; ++k)
+                    topo[(size_t)(base + (int64_t)(k / P) * 64 + g * P + (k % P))] = b.arcs[src++];
+            }
+        }
+    });
+    // edges
+    const int64_t E = sr.ptr[m];
+    hp.canon2slot.assign((size_t)E, -1);
+    hp.slot2canon.assign((size_t)edge_slots, -1);
+    hp.evar.assign((size_t)edge_slots, -1);
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int P = hp.tile_P[t], G = 64 / P;
+        for (int g = 0; g < G; ++g) {
+            const int row = hp.bdd[t * 64 + g];
+            if (row < 0) continue;
+            for (int l = 0; l < bdds[row].L; ++l) {
+                const int64_t slot = hp.edge_base[t] + (int64_t)l * G + g;
+                const int64_t ce = sr.ptr[row] + l;
+                hp.canon2slot[ce] = (int32_t)slot;
+                hp.slot2canon[slot] = (int32_t)ce;
+                hp.evar[slot] = sr.col[ce];
+            }
+        }
+    }
+    // variable -> edges (canonical order within a variable: rows ascending)
+    hp.var_ptr.assign((size_t)p->n + 1, 0);
+    for (int64_t e = 0; e < E; ++e) hp.var_ptr[sr.col[e] + 1]++;
+    for (int v = 0; v < p->n; ++v) hp.var_ptr[v + 1] += hp.var_ptr[v];
+    hp.var_slots.assign((size_t)E, 0);
+    hp.var_canon.assign((size_t)E, 0);
+    std::vector<int32_t> fill(hp.var_ptr.begin(), hp.var_ptr.end() - 1);
+    for (int64_t e = 0; e < E; ++e) {
+        const int v = sr.col[e];
+        hp.var_canon[fill[v]] = (int32_t)e;
+        hp.var_slots[fill[v]++] = hp.canon2slot[e];
+    }
+    return DD_OK;
+}
+
+// Bytes one launch must move by the method's own accounting (per node / per edge / per row).
+double algorithmic_bytes(bool fwd, int mode, const ClassLaunch &c) {
+    const double N = (double)c.nodes, E = (double)c.edges, R = (double)c.rows;
+    if (fwd) return mode == FWD_UPDATE ? 12 * N + 28 * E : 8 * N + 16 * E;
+    switch (mode) {
+        case BWD_UPDATE: return 12 * N + 28 * E + 4 * R;
+        case BWD_STORE: return 8 * N + 8 * E + 4 * R;
+        case BWD_EN_LAM: return 4 * N + 4 * E + 4 * R;
+        case BWD_EN_BAR: return 4 * N + 16 * E + 4 * R;
+        default: return 8 * N + 24 * E;
+    }
+}
+
+template <class F>
+int recorded(dd_instance *h, const char *name, double bytes, hipStream_t s, F launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool rec = h->prof && h->pool_used + 2 <= h->pool.size();
+    if (rec) {
+        a = h->pool[h->pool_used++];
+        b = h->pool[h->pool_used++];
+        HIP_TRY(hipEventRecord(a, s));
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return fail(DD_E_HIP, "%s launch: %s", name, hipGetErrorString(e));
+    if (rec) {
+        HIP_TRY(hipEventRecord(b, s));
+        h->recs.push_back({h->kernel_id(name, bytes), a, b});
+    }
+    return DD_OK;
+}
+
+int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
+    for (const ClassLaunch &c : h->classes) {
+        char name[96];
+        snprintf(name, sizeof name, "%s<%d, %d, %d>", fwd ? "k_fwd" : "k_bwd", c.P, c.RMAX, mode);
+        int st = recorded(h, name, algorithmic_bytes(fwd, mode, c), s, [&] {
+            return fwd ? launch_fwd(h->T, c, mode, s) : launch_bwd(h->T, c, mode, s);
+        });
+        if (st) return st;
+    }
+    return DD_OK;
+}
+
+int deferred(dd_instance *h, hipStream_t s) {
+    return recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 8.0 * (double)h->n, s, [&] {
+        return launch_deferred_sum(h->var_ptr, h->var_slots, h->T.M, h->S, (int)h->n, s);
+    });
+}
+
+int recompute_B(dd_instance *h, hipStream_t s) { return all_classes(h, false, BWD_STORE, s); }
+
+}  // namespace
+
+extern "C" {
+
+const char *dd_last_error(void) { return g_err.c_str(); }
+
+int dd_compile_row(const dd_problem *prob, int32_t row, int32_t *width, uint32_t *arcs, int64_t cap, int64_t *nodes) {
+    if (!prob || !nodes) return fail(DD_E_ARG, "NULL argument");
+    if (row < 0 || row >= prob->m) return fail(DD_E_ARG, "row %d out of range", row);
+    SortedRows sr;
+    int st = validate_and_sort(prob, sr);
+    if (st) return st;
+    const int64_t a = sr.ptr[row];
+    const int L = (int)(sr.ptr[row + 1] - a);
+    RowBdd b;
+    CompileScratch scr;
+    if (L == 0) {
+        *nodes = 0;
+        return DD_OK;
+    }
+    st = compile_row(L, sr.coef.data() + a, prob->sense[row], prob->rhs[row], b, scr);
+    if (st) return fail(st, "row %d: %s", row,
+                        st == E_INFEASIBLE ? "infeasible" : st == E_FORCED ? "fixes a variable" : "unsupported");
+    *nodes = (int64_t)b.arcs.size();
+    if (width) std::copy(b.width.begin(), b.width.end(), width);
+    if (arcs) {
+        if (cap < (int64_t)b.arcs.size()) return fail(DD_E_ARG, "arcs capacity %lld < %zu", (long long)cap, b.arcs.size());
+        std::copy(b.arcs.begin(), b.arcs.end(), arcs);
+    }
+    return DD_OK;
+}
+
+int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_instance **out) {
+    if (!out) return fail(DD_E_ARG, "out is NULL");
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    dd_options o{};
+    if (opt) o = *opt;
+    const int npl = o.nodes_per_lane > 0 ? o.nodes_per_lane : 4;
+    if (npl != 1 && npl != 2 && npl != 4) return fail(DD_E_ARG, "nodes_per_lane must be 1, 2 or 4");
+    const int wpb = o.waves_per_block > 0 ? std::min(o.waves_per_block, 16) : 4;
+    const int lds_budget = o.lds_budget > 0 ? o.lds_budget : 64 * 1024;
+    SortedRows sr;
+    int st = validate_and_sort(prob, sr);
+    if (st) return st;
+    const int m = prob->m;
+    // compile every row
+    std::vector<RowBdd> bdds((size_t)m);
+    std::atomic<int> status(DD_OK), bad(-1);
+    {
+        int nw = worker_count();
+        std::vector<CompileScratch> scr((size_t)nw);
+        parallel_for(m, 32, [&](int64_t j, int w) {
+            if (status != DD_OK) return;
+            const int64_t a = sr.ptr[j];
+            const int L = (int)(sr.ptr[j + 1] - a);
+            if (L == 0) {
+                const int64_t r = prob->rhs[j];
+                const bool okk = prob->sense[j] < 0 ? 0 <= r : prob->sense[j] > 0 ? 0 >= r : r == 0;
+                if (!okk) {
+                    status = E_INFEASIBLE;
+                    bad = (int)j;
+                }
+                return;
+            }
+            int r = compile_row(L, sr.coef.data() + a, prob->sense[j], prob->rhs[j], bdds[j], scr[w]);
+            if (r != OK) {
+                status = r;
+                bad = (int)j;
+            }
+        });
+    }
+    if (status != DD_OK) {
+        int c = status;
+        return fail(c, "row %d: %s", (int)bad,
+                    c == E_INFEASIBLE ? "no feasible assignment"
+                    : c == E_FORCED   ? "fixes one of its variables (a min-marginal would be infinite)"
+                                      : "diagram too wide");
+    }
+    HostPlan hp;
+    std::vector<uint32_t> topo;
+    st = build_plan(prob, sr, bdds, npl, wpb, lds_budget, hp, topo);
+    if (st) return st;
+
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    dd_instance *h = new dd_instance();
+    h->device = device;
+    h->n = prob->n;
+    h->m = m;
+    h->E = sr.ptr[m];
+    h->classes = hp.classes;
+    h->ntiles = (int64_t)hp.nlev.size();
+    h->node_slots = hp.node_slots;
+    h->edge_slots = hp.edge_slots;
+    h->row_nodes.resize((size_t)m);
+    for (int j = 0; j < m; ++j) h->row_nodes[j] = (int64_t)bdds[j].arcs.size();
+    for (const RowBdd &b : bdds) {
+        h->nodes += (int64_t)b.arcs.size();
+        h->max_width = std::max(h->max_width, b.max_width);
+        h->max_len = std::max(h->max_len, b.L);
+    }
+    bdds.clear();
+    bdds.shrink_to_fit();
+    h->edge_var.assign(sr.col.begin(), sr.col.end());
+    h->edge_row.resize((size_t)h->E);
+    for (int j = 0; j < m; ++j)
+        for (int64_t e = sr.ptr[j]; e < sr.ptr[j + 1]; ++e) h->edge_row[e] = j;
+    std::vector<float> c32((size_t)prob->n), om((size_t)h->E), al((size_t)h->E);
+    for (int i = 0; i < prob->n; ++i) {
+        c32[i] = (float)prob->c[i];
+        if (hp.var_ptr[i + 1] == hp.var_ptr[i]) {
+            h->uncovered++;
+            if (prob->c[i] < 0) h->unc_const += prob->c[i];
+        }
+    }
+    for (int64_t e = 0; e < h->E; ++e) {
+        const int v = sr.col[e];
+        om[e] = 0.5f;
+        al[e] = 1.0f / (float)(hp.var_ptr[v + 1] - hp.var_ptr[v]);
+    }
+
+    auto cleanup = [&](int code) {
+        delete h;
+        return code;
+    };
+#define TRY(x)              \
+    do {                    \
+        int r_ = (x);       \
+        if (r_) return cleanup(r_); \
+    } while (0)
+    DevTables &T = h->T;
+    TRY(upload(h, (int64_t **)&T.node_base, hp.node_base, s));
+    TRY(upload(h, (int32_t **)&T.edge_base, hp.edge_base, s));
+    TRY(upload(h, (int32_t **)&T.nlev, hp.nlev, s));
+    TRY(upload(h, (int32_t **)&T.lev_base, hp.lev_base, s));
+    TRY(upload(h, (int32_t **)&T.w_base, hp.w_base, s));
+    TRY(upload(h, (int32_t **)&T.bdd, hp.bdd, s));
+    TRY(upload(h, (int32_t **)&T.lev_off, hp.lev_off, s));
+    TRY(upload(h, (int32_t **)&T.lev_rows, hp.lev_rows, s));
+    TRY(upload(h, (uint16_t **)&T.widths, hp.widths, s));
+    TRY(upload(h, (uint32_t **)&T.topo, topo, s));
+    TRY(h->alloc(&T.F, (size_t)hp.node_slots));
+    TRY(h->alloc(&T.B, (size_t)hp.node_slots));
+    TRY(h->alloc(&T.lam, (size_t)hp.edge_slots));
+    TRY(h->alloc(&T.M, (size_t)hp.edge_slots));
+    TRY(h->alloc(&h->omega, (size_t)hp.edge_slots));
+    TRY(h->alloc(&h->alpha, (size_t)hp.edge_slots));
+    T.omega = h->omega;
+    T.alpha = h->alpha;
+    TRY(upload(h, (int32_t **)&T.evar, hp.evar, s));
+    TRY(upload(h, (int32_t **)&T.slot2canon, hp.slot2canon, s));
+    TRY(upload(h, &h->canon2slot, hp.canon2slot, s));
+    TRY(upload(h, &h->var_ptr, hp.var_ptr, s));
+    TRY(upload(h, &h->var_slots, hp.var_slots, s));
+    TRY(upload(h, &h->var_canon, hp.var_canon, s));
+    TRY(upload(h, &h->cdev, c32, s));
+    TRY(h->alloc(&h->S, (size_t)prob->n));
+    T.S = h->S;
+    TRY(h->alloc(&T.energies, (size_t)m));
+    TRY(h->alloc(&h->tmp, (size_t)std::max<int64_t>(h->E, 1) * 2));
+    TRY(h->alloc(&h->red, 4));
+    TRY(h->alloc(&h->flags, 2));
+    {
+        hipError_t e = hipHostMalloc((void **)&h->red_host, 4 * sizeof(double), hipHostMallocDefault);
+        if (e != hipSuccess) return cleanup(fail(DD_E_OOM, "hipHostMalloc: %s", hipGetErrorString(e)));
+    }
+    auto hip_ok = [&](hipError_t e) { return e == hipSuccess ? DD_OK : fail(DD_E_HIP, "%s", hipGetErrorString(e)); };
+    TRY(hip_ok(hipMemsetAsync(T.lam, 0, sizeof(float) * hp.edge_slots, s)));
+    TRY(hip_ok(hipMemsetAsync(T.M, 0, sizeof(float) * hp.edge_slots, s)));
+    TRY(hip_ok(hipMemsetAsync(h->omega, 0, sizeof(float) * hp.edge_slots, s)));
+    TRY(hip_ok(hipMemsetAsync(h->alpha, 0, sizeof(float) * hp.edge_slots, s)));
+    TRY(hip_ok(hipMemsetAsync(T.energies, 0, sizeof(float) * std::max(m, 1), s)));
+    TRY(hip_ok(hipMemsetAsync(h->S, 0, sizeof(float) * std::max<int64_t>(prob->n, 1), s)));
+    // default parameters (FastDOG special case), staged through tmp
+    {
+        float *d_om = h->tmp, *d_al = h->tmp + std::max<int64_t>(h->E, 1);
+        if (h->E) {
+            TRY(hip_ok(hipMemcpyAsync(d_om, om.data(), sizeof(float) * h->E, hipMemcpyHostToDevice, s)));
+            TRY(hip_ok(hipMemcpyAsync(d_al, al.data(), sizeof(float) * h->E, hipMemcpyHostToDevice, s)));
+            TRY(hip_ok(launch_scatter(h->canon2slot, d_om, h->omega, h->E, s)));
+            TRY(hip_ok(launch_scatter(h->canon2slot, d_al, h->alpha, h->E, s)));
+        }
+    }
+    // the host staging vectors must outlive the async copies
+    TRY(hip_ok(hipStreamSynchronize(s)));
+    TRY(dd_reset(h, stream));
+    TRY(hip_ok(hipStreamSynchronize(s)));
+#undef TRY
+    *out = h;
+    return DD_OK;
+}
+
+int dd_destroy(dd_instance *h) {
+    delete h;
+    return DD_OK;
+}
+
+int dd_get_stats(const dd_instance *h, dd_stats *o) {
+    if (!h || !o) return fail(DD_E_ARG, "NULL argument");
+    o->n = h->n;
+    o->m = h->m;
+    o->edges = h->E;
+    o->nodes = h->nodes;
+    o->arcs = 2 * h->nodes;
+    o->node_slots = h->node_slots;
+    o->edge_slots = h->edge_slots;
+    o->tiles = h->ntiles;
+    o->max_width = h->max_width;
+    o->max_len = h->max_len;
+    o->classes = (int32_t)h->classes.size();
+    o->uncovered = h->uncovered;
+    o->device_bytes = h->device_bytes;
+    return DD_OK;
+}
+
+int dd_edge_map(const dd_instance *h, int32_t *var_out, int32_t *row_out) {
+    if (!h) return fail(DD_E_ARG, "NULL instance");
+    if (var_out) std::copy(h->edge_var.begin(), h->edge_var.end(), var_out);
+    if (row_out) std::copy(h->edge_row.begin(), h->edge_row.end(), row_out);
+    return DD_OK;
+}
+
+int dd_set_params(dd_instance *h, const float *omega, const float *alpha, void *stream) {
+    if (!h || (h->E && (!omega || !alpha))) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemsetAsync(h->flags, 0, 2 * sizeof(int32_t), s));
+    HIP_TRY(launch_check_params(omega, alpha, h->E, h->flags, s));
+    int32_t f[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(f, h->flags, sizeof f, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (f[0]) return fail(DD_E_PARAM, "omega must lie in [0, 1]");
+    if (f[1]) return fail(DD_E_PARAM, "alpha must be finite and non-negative");
+    HIP_TRY(launch_scatter(h->canon2slot, omega, h->omega, h->E, s));
+    HIP_TRY(launch_scatter(h->canon2slot, alpha, h->alpha, h->E, s));
+    return DD_OK;
+}
+
+int dd_seg_softmax(dd_instance *h, const float *alpha_hat, float *alpha_out, void *stream) {
+    if (!h || (h->E && (!alpha_hat || !alpha_out))) return fail(DD_E_ARG, "NULL argument");
+    HIP_TRY(launch_seg_softmax(h->var_ptr, h->var_canon, alpha_hat, alpha_out, (int)h->n, (hipStream_t)stream));
+    return DD_OK;
+}
+
+int dd_reset(dd_instance *h, void *stream) {
+    if (!h) return fail(DD_E_ARG, "NULL instance");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_init_lambda(h->canon2slot, h->T.evar, h->var_ptr, h->cdev, h->T.lam, h->T.M, h->E, s));
+    return recompute_B(h, s);
+}
+
+int dd_set_state(dd_instance *h, const float *lambda, const float *M, void *stream) {
+    if (!h || (h->E && (!lambda || !M))) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_scatter(h->canon2slot, lambda, h->T.lam, h->E, s));
+    HIP_TRY(launch_scatter(h->canon2slot, M, h->T.M, h->E, s));
+    return recompute_B(h, s);
+}
+
+int dd_get_state(dd_instance *h, float *lambda_out, float *M_out, int32_t flushed, void *stream) {
+    if (!h || (h->E && !lambda_out)) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (flushed) {
+        int st = deferred(h, s);
+        if (st) return st;
+    }
+    HIP_TRY(launch_gather(h->canon2slot, h->T.lam, lambda_out, h->E, h->alpha, h->S, h->T.evar, flushed ? 1 : 0, s));
+    if (M_out) HIP_TRY(launch_gather(h->canon2slot, h->T.M, M_out, h->E, nullptr, nullptr, nullptr, 0, s));
+    return DD_OK;
+}
+
+int dd_run_pass(dd_instance *h, int32_t direction, void *stream) {
+    if (!h || (direction != 0 && direction != 1)) return fail(DD_E_ARG, "bad instance or direction");
+    hipStream_t s = (hipStream_t)stream;
+    int st = deferred(h, s);
+    if (st) return st;
+    return all_classes(h, direction == 0, direction == 0 ? (int)FWD_UPDATE : (int)BWD_UPDATE, s);
+}
+
+int dd_run(dd_instance *h, int32_t T, void *stream) {
+    if (!h || T < 0) return fail(DD_E_ARG, "bad instance or T");
+    for (int t = 0; t < T; ++t)
+        for (int d = 0; d < 2; ++d) {
+            int st = dd_run_pass(h, d, stream);
+            if (st) return st;
+        }
+    return DD_OK;
+}
+
+int dd_lower_bound(dd_instance *h, double *lb, double *dl, void *stream) {
+    if (!h || !lb) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int st = deferred(h, s);
+    if (st) return st;
+    if ((st = all_classes(h, false, BWD_EN_BAR, s))) return st;
+    HIP_TRY(launch_bound_reduce(h->T.energies, h->m, h->T.M, h->edge_slots, h->red, s));
+    if (dl) {
+        if ((st = all_classes(h, false, BWD_EN_LAM, s))) return st;
+        HIP_TRY(launch_bound_reduce(h->T.energies, h->m, h->T.M, h->edge_slots, h->red + 2, s));
+    }
+    HIP_TRY(hipMemcpyAsync(h->red_host, h->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *lb = h->red_host[0] + h->unc_const;
+    if (dl) *dl = h->red_host[2] + h->red_host[3] + h->unc_const;
+    if (!std::isfinite(*lb) || (dl && !std::isfinite(*dl))) return fail(DD_E_NONFINITE, "lower bound is not finite");
+    return DD_OK;
+}
+
+int dd_row_energies(dd_instance *h, float *E_out, void *stream) {
+    if (!h || (h->m && !E_out)) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int st = deferred(h, s);
+    if (st) return st;
+    if ((st = all_classes(h, false, BWD_EN_BAR, s))) return st;
+    if (h->m) HIP_TRY(hipMemcpyAsync(E_out, h->T.energies, sizeof(float) * h->m, hipMemcpyDeviceToDevice, s));
+    return DD_OK;
+}
+
+int dd_min_marginals(dd_instance *h, float *m0_out, float *m1_out, void *stream) {
+    if (!h || (h->E && (!m0_out || !m1_out))) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int st = deferred(h, s);
+    if (st) return st;
+    // F at lambda_bar into the F buffer (free between passes), then m0/m1 during a B sweep at lambda_bar
+    if ((st = all_classes(h, true, FWD_SWEEP_BAR, s))) return st;
+    h->T.out0 = m0_out;
+    h->T.out1 = m1_out;
+    st = all_classes(h, false, BWD_MM, s);
+    h->T.out0 = h->T.out1 = nullptr;
+    return st;
+}
+
+int dd_row_nodes(const dd_instance *h, int64_t *nodes_out) {
+    if (!h || (h->m && !nodes_out)) return fail(DD_E_ARG, "NULL argument");
+    std::copy(h->row_nodes.begin(), h->row_nodes.end(), nodes_out);
+    return DD_OK;
+}
+
+int dd_profile_begin(dd_instance *h, int32_t max_launches) {
+    if (!h || max_launches <= 0) return fail(DD_E_ARG, "bad instance or max_launches");
+    while (h->pool.size() < 2 * (size_t)max_launches) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreate(&e));
+        h->pool.push_back(e);
+    }
+    h->pool_used = 0;
+    h->recs.clear();
+    h->prof = true;
+    return DD_OK;
+}
+
+int dd_profile_end(dd_instance *h, dd_kernel_time *out, int32_t cap, int32_t *count) {
+    if (!h || !count) return fail(DD_E_ARG, "NULL argument");
+    h->prof = false;
+    HIP_TRY(hipDeviceSynchronize());
+    std::vector<double> ms(h->kname.size(), 0.0);
+    std::vector<int64_t> cnt(h->kname.size(), 0);
+    for (const auto &r : h->recs) {
+        float t = 0.f;
+        HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+        ms[r.kernel] += t;
+        cnt[r.kernel] += 1;
+    }
+    int k = 0;
+    for (size_t q = 0; q < h->kname.size(); ++q) {
+        if (!cnt[q]) continue;
+        if (out && k < cap) {
+            snprintf(out[k].name, sizeof out[k].name, "%s", h->kname[q].c_str());
+            out[k].launches = cnt[q];
+            out[k].total_ms = ms[q];
+            out[k].bytes_per_launch = h->kbytes[q];
+        }
+        ++k;
+    }
+    *count = k;
+    h->recs.clear();
+    h->pool_used = 0;
+    return DD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,81 @@
+// kernels.hpp -- device data layout and kernel launchers (host-visible declarations).
+//
+// Layout ("tiles"): one wavefront processes one tile; its 64 lanes form G = 64/P teams of
+// P lanes and each team owns one decision diagram (one constraint row).  For level l of a
+// tile, node k of team g is stored at slot
+//     node_base[tile] + lev_off[l] + (k / P) * 64 + g * P + (k % P)
+// so the lanes of a wave read 64 consecutive slots per row of the level: every hop of
+// every diagram in the tile is one coalesced sweep.  lev_rows[l] = max over teams of
+// ceil(width / P) rows.  Per-edge data (lambda, M, omega, alpha, variable) of level l of
+// team g is at edge slot edge_base[tile] + l * G + g.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+
+namespace dd {
+
+enum FwdMode { FWD_UPDATE = 0, FWD_SWEEP_BAR = 1 };
+enum BwdMode { BWD_UPDATE = 0, BWD_STORE = 1, BWD_EN_LAM = 2, BWD_EN_BAR = 3, BWD_MM = 4 };
+
+struct DevTables {
+    // tile tables
+    const int64_t *node_base;
+    const int32_t *edge_base;
+    const int32_t *nlev;
+    const int32_t *lev_base;  // index of the tile's first level in lev_off / lev_rows
+    const int32_t *w_base;    // index of the tile's first width entry (level-major, G per level)
+    const int32_t *bdd;       // [tiles * 64] row id per team (-1: empty team)
+    const int32_t *lev_off;   // node offset of each level relative to node_base
+    const int32_t *lev_rows;
+    const uint16_t *widths;
+    // nodes
+    const uint32_t *topo;     // lo | hi << 16 child codes
+    float *F;                 // shortest path root -> node (forward pass output)
+    float *B;                 // shortest path node -> 1-terminal (backward pass output)
+    // edges (slot indexed)
+    float *lam;
+    float *M;
+    const float *omega;
+    const float *alpha;
+    const int32_t *evar;      // variable of each edge slot (-1: padding)
+    const int32_t *slot2canon;
+    const float *S;           // [n] deferred sums
+    float *energies;          // [m] per-row E^j
+    float *out0, *out1;       // [edges] canonical min-marginal outputs
+};
+
+struct ClassLaunch {
+    int P;         // team size (lanes per diagram)
+    int RMAX;      // max rows (of 64 slots) per level for this class
+    int WL;        // LDS floats per team per buffer (max width in the class)
+    int wpb;       // waves per workgroup
+    int64_t tile0, ntiles;
+    int64_t nodes, edges, rows;  // real (unpadded) counts covered by one launch, for byte accounting
+};
+
+hipError_t launch_fwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
+hipError_t launch_bwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
+bool class_supported(int P, int RMAX);
+
+// S_i = sum over the CSR list of edge slots of variable i of M[slot], in list order.
+hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots, const float *M, float *S, int n,
+                               hipStream_t s);
+// lambda[slot] = c_i / |J_i|, M[slot] = 0 for every canonical edge.
+hipError_t launch_init_lambda(const int32_t *canon2slot, const int32_t *evar, const int32_t *var_ptr, const float *c,
+                              float *lam, float *M, int64_t E, hipStream_t s);
+// dst[canon2slot[e]] = src[e]
+hipError_t launch_scatter(const int32_t *canon2slot, const float *src, float *dst, int64_t E, hipStream_t s);
+// dst[e] = src[canon2slot[e]] (+ alpha[slot] * S[var] when flush)
+hipError_t launch_gather(const int32_t *canon2slot, const float *src, float *dst, int64_t E, const float *alpha,
+                         const float *S, const int32_t *evar, int flush, hipStream_t s);
+// softmax over each variable's edges; inputs/outputs canonical, var_canon is the CSR of canonical edge ids
+hipError_t launch_seg_softmax(const int32_t *var_ptr, const int32_t *var_canon, const float *x, float *y, int n,
+                              hipStream_t s);
+// out[0] = sum_j energies[j] (fp64, fixed order), out[1] = sum_slots min(0, M[slot])
+hipError_t launch_bound_reduce(const float *energies, int64_t m, const float *M, int64_t slots, double *out,
+                               hipStream_t s);
+// validity check of parameters: flags[0] |= omega outside [0,1] or non-finite, flags[1] |= alpha < 0 or non-finite
+hipError_t launch_check_params(const float *omega, const float *alpha, int64_t E, int32_t *flags, hipStream_t s);
+
+}  // namespace dd

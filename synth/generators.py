@@ -100,18 +100,22 @@ def _csr_from_sorted_blocks(cols_flat, coefs_flat, lens):
 
 
 def _distinct_rows(rng, n, lens):
-    """Per row, len distinct variables drawn uniformly from [0, n) (without replacement)."""
+    """Per row, len distinct variables drawn uniformly from [0, n) (without replacement).
+
+    Draws iid, then redraws only the repeated entries until none is left; the
+    procedure is symmetric in the labels, so every subset is equally likely.
+    """
     rid = np.repeat(np.arange(len(lens)), lens)
     cols = rng.integers(0, n, size=int(lens.sum()))
     while True:
         o = np.lexsort((cols, rid))
         cs, rs = cols[o], rid[o]
-        dup = (cs[1:] == cs[:-1]) & (rs[1:] == rs[:-1])
+        dup = np.zeros(cs.size, dtype=bool)
+        dup[1:] = (cs[1:] == cs[:-1]) & (rs[1:] == rs[:-1])
         if not dup.any():
             return cs, rs
-        bad = np.unique(rs[1:][dup])
-        mask = np.isin(rid, bad)
-        cols[mask] = rng.integers(0, n, size=int(mask.sum()))
+        cols, rid = cs, rs
+        cols[dup] = rng.integers(0, n, size=int(dup.sum()))
 
 
 # ----------------------------------------------------------------------------------------------

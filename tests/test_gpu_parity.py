@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the same seeded inputs.
+
+Tolerances (stated by the task for this solver): lower bound within 1e-5
+relative; multipliers, deferred min-marginal differences and min-marginals
+within 1e-4 relative to the larger of |reference| and the row's path-cost
+scale sum_{i in I_j} |lambda_ij|.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import assert_close_scaled, host, make_instance, row_scale, say
+
+pytestmark = pytest.mark.gpu
+
+LB_RTOL = 1e-5
+RTOL = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def check_passes(orc, prob, omega, alpha_hat, npass, what, literal=False):
+    """Each pass on the GPU against one oracle pass started from the GPU's own pass-start state."""
+    inst, om, al = make_instance(prob, f32(omega), f32(alpha_hat))
+    om64, al64 = host(om), host(al)
+    np.testing.assert_allclose(al64, orc.softmax_alpha(prob, f32(alpha_hat)), rtol=2e-6, atol=1e-7)
+    for k in range(npass):
+        lam_in, M_in = (host(t) for t in inst.get_state())
+        inst.run_pass(k % 2)
+        lam_g, M_g = (host(t) for t in inst.get_state())
+        lam_o, M_o = lam_in.copy(), M_in.copy()
+        orc.run_pass(prob, om64, al64, lam_o, M_o, k % 2, literal=literal)
+        sc = row_scale(prob, lam_o)
+        assert_close_scaled(lam_g, lam_o, sc, RTOL, f"{what} pass {k} lambda")
+        assert_close_scaled(M_g, M_o, sc, RTOL, f"{what} pass {k} M")
+    return inst
+
+
+def test_golden_two_row_iteration():
+    from tests.test_oracle_pins import _gold
+    g, p = _gold()
+    say("golden two-row")
+    inst, om, al = make_instance(p)
+    import torch
+    inst.set_params(torch.tensor(g["omega"], dtype=torch.float32, device="cuda"),
+                    torch.tensor(g["alpha"], dtype=torch.float32, device="cuda"))
+    inst.reset()
+    lam, M = inst.get_state()
+    np.testing.assert_array_equal(host(lam), g["lambda_init"])
+    assert inst.lower_bound()[0] == g["lb_init"]
+    inst.run_pass(0)
+    lam, M = inst.get_state()
+    np.testing.assert_array_equal(host(lam), g["after_forward"]["lambda"])
+    np.testing.assert_array_equal(host(M), g["after_forward"]["M"])
+    assert inst.lower_bound()[0] == g["after_forward"]["lb"]
+    inst.run_pass(1)
+    ab = g["after_backward"]
+    lam, M = inst.get_state()
+    np.testing.assert_array_equal(host(lam), ab["lambda"])
+    np.testing.assert_array_equal(host(M), ab["M"])
+    lb, dl = inst.lower_bound()
+    assert lb == ab["lb"] and dl == ab["d_l"]
+    lbar, _ = inst.get_state(flushed=True)
+    np.testing.assert_array_equal(host(lbar), ab["lambda_bar"])
+    m0, m1 = inst.min_marginals()
+    np.testing.assert_array_equal(host(m0), ab["m0_at_lambda_bar"])
+    np.testing.assert_array_equal(host(m1), ab["m1_at_lambda_bar"])
+
+
+@pytest.mark.parametrize("wl", ["setcover", "indset", "gm"])
+def test_single_pass_parity_workloads(orc, wl):
+    w = synth.workload(wl, small=(wl != "setcover"))
+    say(f"single-pass parity {wl} E={w['problem'].nnz}")
+    check_passes(orc, w["problem"], w["omega"], w["alpha_hat"], 6, wl)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_single_pass_parity_mixed_rows(orc, seed):
+    """Random rows: every sense, mixed-sign coefficients, ragged lengths; several tile classes."""
+    p = synth.random_tiny(seed, n=40, m=60, kmin=1, kmax=14, amin=-7, amax=7)
+    rng = np.random.default_rng(seed)
+    say(f"mixed rows seed {seed}")
+    check_passes(orc, p, synth.sigmoid(rng.normal(size=p.nnz)), rng.normal(0, 0.3, size=p.nnz), 6, f"mixed{seed}")
+
+
+def test_single_pass_parity_wide_and_narrow(orc):
+    """Knapsack rows of several widths (up to the 2048-wide class) next to 2-variable rows."""
+    k = synth.knapsack(n=3000, m=12, kmin=20, kmax=200, amax=20, frac=0.5, seed=7)
+    s = synth.independent_set(n=3000, M=200, seed=8)
+    rows = [k.row(j) for j in range(k.m)] + [s.row(j) for j in range(s.m)]
+    p = synth.generators._from_rows(3000, k.c, rows, "wide-narrow")
+    rng = np.random.default_rng(4)
+    say(f"wide and narrow rows E={p.nnz}")
+    inst = check_passes(orc, p, synth.sigmoid(rng.normal(size=p.nnz)), rng.normal(0, 0.1, size=p.nnz), 4, "wide")
+    assert inst.stats["max_width"] > 1024
+    assert inst.stats["classes"] >= 3
+
+
+def test_empty_and_single_variable_rows(orc):
+    rows = [(np.array([0]), np.array([1]), -1, 1),          # x0 <= 1: vacuous single-variable row
+            (np.array([], dtype=np.int64), np.array([], dtype=np.int64), -1, 0),   # empty row, feasible
+            (np.array([0, 1, 2]), np.array([1, 2, -1]), 0, 1),  # equality with a negative coefficient
+            (np.array([1, 3]), np.array([1, 1]), 1, 1)]
+    p = synth.generators._from_rows(5, np.array([0.3, -0.7, 0.2, 0.5, -0.4]), rows, "edge")
+    say("empty and single-variable rows")
+    inst = check_passes(orc, p, np.full(p.nnz, 0.5), np.zeros(p.nnz), 6, "edge")
+    lam, M = inst.get_state()
+    lb, dl = inst.lower_bound()
+    lbo, dlo, _ = orc.lower_bound(p, orc.softmax_alpha(p, np.zeros(p.nnz)), host(lam), host(M))
+    assert lb == pytest.approx(lbo, rel=LB_RTOL, abs=1e-6)
+    assert dl == pytest.approx(dlo, rel=LB_RTOL, abs=1e-6)
+
+
+def _trajectory(orc, wl, T, every, small=False):
+    w = synth.workload(wl, small=small)
+    p = w["problem"]
+    say(f"LB trajectory {wl} T={T}")
+    inst, om, al = make_instance(p, f32(w["omega"]), f32(w["alpha_hat"]))
+    om64 = f32(w["omega"])
+    al_o = orc.softmax_alpha(p, f32(w["alpha_hat"]))
+    lam_o, M_o = orc.init_lambda(p), np.zeros(p.nnz)
+    lb0 = inst.lower_bound()[0]
+    assert lb0 == pytest.approx(orc.lower_bound(p, al_o, lam_o, M_o)[0], rel=LB_RTOL)
+    out = []
+    for t in range(0, T, every):
+        inst.run(every)
+        lam_o, M_o = orc.run(p, om64, al_o, every, lam=lam_o, M=M_o)
+        lb_g, dl_g = inst.lower_bound()
+        lb_o, dl_o, _ = orc.lower_bound(p, al_o, lam_o, M_o)
+        out.append((t + every, lb_g, lb_o))
+        assert lb_g == pytest.approx(lb_o, rel=LB_RTOL), (t + every, lb_g, lb_o)
+        assert dl_g <= lb_g + 1e-6 * abs(lb_g)
+    return inst, p, lam_o, M_o, out
+
+
+def test_lb_trajectory_setcover(orc):
+    inst, p, lam_o, M_o, tr = _trajectory(orc, "setcover", 200, 20)
+    assert tr[-1][1] > tr[0][1]
+    lam_g, M_g = (host(t) for t in inst.get_state())
+    # entrywise over a short horizon is checked per pass elsewhere; here only the bound
+
+
+def test_lb_trajectory_indset_full(orc):
+    inst, p, lam_o, M_o, tr = _trajectory(orc, "indset", 1000, 10)
+    say("indset LB", tr[0], tr[-1])
+
+
+def test_gm_full_short_horizon(orc):
+    w = synth.workload("gm")
+    p = w["problem"]
+    say(f"gm full E={p.nnz}")
+    inst = check_passes(orc, p, w["omega"], w["alpha_hat"], 2, "gm-full")
+    inst.reset()
+    om64 = f32(w["omega"])
+    al_o = orc.softmax_alpha(p, f32(w["alpha_hat"]))
+    inst.run(20)
+    lam_o, M_o = orc.run(p, om64, al_o, 20)
+    lb_g = inst.lower_bound()[0]
+    lb_o = orc.lower_bound(p, al_o, lam_o, M_o)[0]
+    assert lb_g == pytest.approx(lb_o, rel=LB_RTOL)
+
+
+@pytest.mark.parametrize("wl", ["setcover", "gm"])
+def test_min_marginals_at_flushed(orc, wl):
+    w = synth.workload(wl, small=True)
+    p = w["problem"]
+    inst, om, al = make_instance(p, f32(w["omega"]), f32(w["alpha_hat"]))
+    inst.run(5)
+    lbar = host(inst.get_state(flushed=True)[0])
+    m0g, m1g = (host(t) for t in inst.min_marginals())
+    m0o, m1o = orc.min_marginals(p, lbar)
+    sc = row_scale(p, lbar)
+    assert_close_scaled(m0g, m0o, sc, RTOL, "m0")
+    assert_close_scaled(m1g, m1o, sc, RTOL, "m1")
+    Eg = host(inst.row_energies())
+    np.testing.assert_allclose(Eg, orc.energies(p, lbar), rtol=1e-5, atol=1e-5 * np.abs(lbar).max())
+
+
+def test_prop1_on_gpu(orc):
+    w = synth.workload("gm", small=True)
+    p = w["problem"]
+    inst, om, al = make_instance(p, f32(w["omega"]), f32(w["alpha_hat"]))
+    var = p.col.astype(np.int64)
+    cov = p.degree() > 0
+    prev = -np.inf
+    for k in range(16):
+        inst.run_pass(k % 2)
+        lam, M = (host(t) for t in inst.get_state())
+        tot = np.zeros(p.n)
+        np.add.at(tot, var, lam + M)
+        scale = np.zeros(p.n)
+        np.add.at(scale, var, np.abs(lam) + np.abs(M))
+        assert np.all(np.abs(tot - p.c)[cov] <= 1e-5 * np.maximum(scale[cov], 1.0))
+        lb, dl = inst.lower_bound()
+        assert dl >= prev - 1e-5 * abs(dl)
+        prev = dl
+
+
+def test_knapsack_full_sampled_rows(orc):
+    """The full 2,000,000-variable knapsack program in the benchmark's launch configuration;
+    400 seeded rows are recomputed by the oracle from the GPU's pass-start state."""
+    import torch
+    w = synth.workload("knapsack")
+    p = w["problem"]
+    say(f"knapsack full E={p.nnz}: compiling")
+    inst, om, al = make_instance(p, f32(w["omega"]), f32(w["alpha_hat"]))
+    say("knapsack stats", json.dumps(inst.stats))
+    om64, al64 = host(om), host(al)
+    rows = np.sort(np.random.default_rng(4004).choice(p.m, size=400, replace=False))
+    sub = p.subset_rows(rows)
+    eidx = np.concatenate([np.arange(p.row_ptr[r], p.row_ptr[r + 1]) for r in rows])
+    inst.run(2)
+    for direction in (0, 1):
+        lam_in, M_in = (host(t) for t in inst.get_state())
+        S = np.zeros(p.n)
+        np.add.at(S, p.col.astype(np.int64), M_in)
+        inst.run_pass(direction)
+        lam_g, M_g = (host(t) for t in inst.get_state())
+        lo, Mo = orc.rows_pass(sub, om64[eidx], al64[eidx], S[p.col[eidx]], lam_in[eidx], direction)
+        sc = row_scale(sub, lo)
+        assert_close_scaled(lam_g[eidx], lo, sc, RTOL, f"knapsack dir {direction} lambda")
+        assert_close_scaled(M_g[eidx], Mo, sc, RTOL, f"knapsack dir {direction} M")
+    lbar = host(inst.get_state(flushed=True)[0])
+    Eg = host(inst.row_energies())[rows]
+    Eo = orc.energies(sub, lbar[eidx])
+    np.testing.assert_allclose(Eg, Eo, rtol=1e-5, atol=1e-5 * np.abs(Eo).max())
+    m0g, m1g = (host(t) for t in inst.min_marginals())
+    m0o, m1o = orc.min_marginals(sub, lbar[eidx])
+    sc = row_scale(sub, lbar[eidx])
+    assert_close_scaled(m0g[eidx], m0o, sc, RTOL, "knapsack m0")
+    assert_close_scaled(m1g[eidx], m1o, sc, RTOL, "knapsack m1")
+    lb, dl = inst.lower_bound()
+    assert np.isfinite(lb) and dl <= lb + 1e-5 * abs(lb)
+    del inst
+    torch.cuda.synchronize()
+
+
+def test_bad_parameters_rejected():
+    import torch
+
+    import paper_2205_11638_amd as dd
+    p = synth.set_cover(n=50, m=20, seed=1)
+    inst, _, _ = make_instance(p)
+    om = torch.full((p.nnz,), 1.5, device="cuda")
+    al = torch.full((p.nnz,), 0.5, device="cuda")
+    with pytest.raises(dd.DDError) as e:
+        inst.set_params(om, al)
+    assert e.value.code == dd.binding.DD_E_PARAM
+    with pytest.raises(dd.DDError):
+        inst.set_params(torch.full((p.nnz,), 0.5, device="cuda"), torch.full((p.nnz,), -1.0, device="cuda"))

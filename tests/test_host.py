@@ -1,0 +1,146 @@
+"""Host-side checks of the library (no GPU): exports, decision-diagram compiler, input validation."""
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+from tests import brute
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_2205_11638_amd as pkg
+    pkg.lib()
+    return pkg
+
+
+def test_every_declared_symbol_is_exported(dd):
+    import ctypes
+    decl = set()
+    for name in os.listdir(os.path.join(ROOT, "include")):
+        if name.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", name)).read()
+            decl |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(dd_\w+)\s*\(", txt, re.M))
+    assert len(decl) >= 15
+    L = ctypes.CDLL(dd.binding.LIB_PATH)
+    for s in sorted(decl):
+        assert hasattr(L, s), s
+    assert decl <= set(dd.binding.SIGNATURES), decl - set(dd.binding.SIGNATURES)
+
+
+def _paths(width, arcs):
+    """All root-to-1 assignments of a compiled diagram."""
+    L = len(width)
+    starts = np.concatenate([[0], np.cumsum(width)])
+    out = []
+
+    def walk(l, k, x):
+        code = int(arcs[starts[l] + k])
+        Wn = int(width[l + 1]) if l + 1 < L else 0
+        for beta, c in ((0, code & 0xFFFF), (1, code >> 16)):
+            if c == Wn:
+                continue                    # 0-terminal
+            if c == Wn + 1:
+                assert l == L - 1           # 1-terminal only below the last level
+                out.append(tuple(x + [beta]))
+                continue
+            assert c < Wn
+            walk(l + 1, c, x + [beta])
+
+    walk(0, 0, [])
+    return sorted(out)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_compiled_paths_are_exactly_the_feasible_set(dd, seed):
+    p = synth.random_tiny(seed, n=10, m=3, kmin=1, kmax=9, amin=-6, amax=6)
+    for j in range(p.m):
+        width, arcs = dd.compile_row(p, j)
+        cols, coefs, sense, rhs = p.row(j)
+        X = brute.feasible_set(coefs, sense, rhs)
+        assert _paths(width, arcs) == sorted(map(tuple, X.tolist()))
+        # quasi-reduced: one root, no two nodes of a level with the same children, no dead node
+        assert width[0] == 1
+        start = 0
+        for l, w in enumerate(width):
+            lvl = arcs[start:start + w]
+            assert len(set(lvl.tolist())) == w
+            Wn = width[l + 1] if l + 1 < len(width) else 0
+            assert not np.any(((lvl & 0xFFFF) == Wn) & ((lvl >> 16) == Wn))
+            start += w
+
+
+def test_known_shapes(dd):
+    p = synth.set_cover(n=30, m=5, seed=3)
+    for j in range(p.m):
+        w, a = dd.compile_row(p, j)
+        L = len(w)
+        assert list(w) == [1] + [2] * (L - 1)        # "no 1 yet" / "covered"
+    q = synth.independent_set(n=20, M=10, seed=1)
+    for j in range(q.m):
+        w, a = dd.compile_row(q, j)
+        assert list(w) == [1, 2]
+    k = synth.knapsack(n=1000, m=3, seed=5)
+    for j in range(k.m):
+        w, a = dd.compile_row(k, j)
+        cols, coefs, sense, rhs = k.row(j)
+        assert max(w) <= rhs + 2                      # states are partial sums 0..b plus "always feasible"
+
+
+def _one_row(coefs, sense, rhs, n=None):
+    n = n or len(coefs)
+    return synth.generators._from_rows(n, np.zeros(n), [(np.arange(len(coefs)), np.array(coefs), sense, rhs)], "r")
+
+
+def test_errors(dd):
+    with pytest.raises(dd.DDError) as e:
+        dd.compile_row(_one_row([1, 1], -1, -1), 0)
+    assert e.value.code == dd.binding.DD_E_INFEASIBLE
+    with pytest.raises(dd.DDError) as e:
+        dd.compile_row(_one_row([1, 1], 1, 2), 0)          # x0 + x1 >= 2 fixes both
+    assert e.value.code == dd.binding.DD_E_FORCED
+    with pytest.raises(dd.DDError) as e:
+        dd.compile_row(_one_row([1, 1, 1], 0, 3), 0)
+    assert e.value.code == dd.binding.DD_E_FORCED
+    bad = _one_row([1, 1], -1, 1)
+    bad.col[1] = 0                                         # duplicate variable
+    with pytest.raises(dd.DDError) as e:
+        dd.compile_row(bad, 0)
+    assert e.value.code == dd.binding.DD_E_ARG
+    oob = _one_row([1, 1], -1, 1)
+    oob.col[1] = 7
+    with pytest.raises(dd.DDError) as e:
+        dd.compile_row(oob, 0)
+    assert e.value.code == dd.binding.DD_E_ARG
+
+
+def test_create_rejects_bad_input_before_touching_the_gpu(dd):
+    p = _one_row([1, 1], -1, 1)
+    p.c[0] = np.nan
+    with pytest.raises(dd.DDError) as e:
+        dd.Instance(p)
+    assert e.value.code == dd.binding.DD_E_PARAM
+    q = _one_row([1, 1], 1, 2)
+    with pytest.raises(dd.DDError) as e:
+        dd.Instance(q)
+    assert e.value.code == dd.binding.DD_E_FORCED
+    r = _one_row([1, 1], -1, 1)
+    r.sense[0] = 3
+    with pytest.raises(dd.DDError) as e:
+        dd.Instance(r)
+    assert e.value.code == dd.binding.DD_E_ARG
+
+
+def test_unsorted_columns_are_sorted(dd):
+    p = synth.generators._from_rows(4, np.zeros(4), [(np.array([0, 2, 3]), np.array([3, -2, 1]), -1, 1)], "u")
+    w1, a1 = dd.compile_row(p, 0)
+    p.col[:] = p.col[::-1].copy()
+    p.coef[:] = p.coef[::-1].copy()
+    w2, a2 = dd.compile_row(p, 0)
+    np.testing.assert_array_equal(w1, w2)
+    np.testing.assert_array_equal(a1, a2)
