@@ -57,6 +57,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="knapsack", choices=["knapsack", "indset", "gm", "setcover"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
+                    help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this solver has no multi-GPU path "
@@ -65,10 +67,20 @@ def main():
 
     import torch
 
+    torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        n = int(args.copy_probe * (1 << 30)) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: {4 * n} bytes read and {4 * n} bytes written by one copy kernel")
+        return
+
     import paper_2205_11638_amd as dd
     import synth
 
-    torch.cuda.set_device(0)
     t0 = time.time()
     w = synth.workload(args.workload)
     prob = w["problem"]
@@ -93,7 +105,7 @@ def main():
         log(f"[bench] warmup {k}: lb={lb[0]:.6f}")
     stream = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    inst.profile_begin(max_launches=args.steps * (4 * T + 16) * max(1, st["classes"]) + 64)
+    inst.profile_begin(max_launches=args.steps * (8 * T + 32) * max(1, st["classes"]) + 256)
     torch.cuda.synchronize()
     e0.record(stream)
     for k in range(args.steps):

@@ -132,6 +132,8 @@ int validate_and_sort(const dd_problem *p, SortedRows &sr) {
     return DD_OK;
 }
 
+constexpr int64_t kLdsPerCU = 160 * 1024;
+
 struct HostPlan {
     std::vector<ClassLaunch> classes;
     // tiles
@@ -179,12 +181,20 @@ struct dd_instance {
     std::vector<void *> allocs;
     DevTables T{};
     int32_t *var_ptr = nullptr, *var_slots = nullptr, *var_canon = nullptr, *canon2slot = nullptr;
-    float *cdev = nullptr, *S = nullptr, *omega = nullptr, *alpha = nullptr, *tmp = nullptr;
+    float *cdev = nullptr, *S = nullptr, *aS = nullptr, *omega = nullptr, *alpha = nullptr, *tmp = nullptr;
     double *red = nullptr;   // device reduction output [4]
     double *red_host = nullptr;  // pinned
     int32_t *flags = nullptr;
 
+    // side streams (default priority) and fork/join events for concurrent class launches
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+
     ~dd_instance() {
+        for (hipEvent_t e : join) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        for (hipStream_t q : side) (void)hipStreamDestroy(q);
         for (hipEvent_t e : pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
         if (red_host) (void)hipHostFree(red_host);
@@ -222,13 +232,26 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
         if (b.L == 0) continue;
         int P = std::min(64, next_pow2((b.max_width + npl - 1) / npl));
         int R = (b.max_width + P - 1) / P;
-        int RMAX = P < 64 ? 4 : std::max(4, next_pow2(R));
+        int RMAX = 4;
+        if (P == 64)
+            for (int cand : {4, 8, 12, 16, 24, 32, 1 << 30})
+                if (cand >= R) {
+                    RMAX = cand;
+                    break;
+                }
         if (!class_supported(P, RMAX))
             return fail(DD_E_UNSUPPORTED, "row %d: diagram width %d is wider than the kernels support (2048)", j,
                         b.max_width);
         rP[j] = P;
         rR[j] = RMAX;
     }
+    // All one-wave diagrams share one launch (register tiles sized for the widest): a single
+    // kernel per pass instead of one per width class, so no launch waits on another's tail.
+    int wide = 0;
+    for (int j = 0; j < m; ++j)
+        if (rP[j] == 64) wide = std::max(wide, rR[j]);
+    for (int j = 0; j < m; ++j)
+        if (rP[j] == 64) rR[j] = wide;
     std::vector<int> order;
     for (int j = 0; j < m; ++j)
         if (bdds[j].L > 0) order.push_back(j);
@@ -255,6 +278,7 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
             const size_t t1 = std::min(j, t0 + G);
             int nl = 0;
             for (size_t q = t0; q < t1; ++q) {
+                cl.NL = std::max(cl.NL, bdds[order[q]].L);
                 nl = std::max(nl, bdds[order[q]].L);
                 cl.WL = std::max(cl.WL, bdds[order[q]].max_width);
                 cl.nodes += (int64_t)bdds[order[q]].arcs.size();
@@ -288,10 +312,26 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
             edge_slots += (int64_t)nl * G;
         }
         cl.ntiles = (int64_t)hp.nlev.size() - cl.tile0;
-        // waves per workgroup limited by the LDS budget: 2 buffers * WL * G * 4 bytes per wave
-        const int64_t per_wave = 2LL * cl.WL * G * 4;
-        if (per_wave > 160 * 1024) return fail(DD_E_UNSUPPORTED, "LDS need %lld bytes per wave", (long long)per_wave);
-        cl.wpb = std::max(1, (int)std::min<int64_t>(wpb, std::max<int64_t>(1, lds_budget / per_wave)));
+        cl.WB = (cl.WL + 2 + P - 1) / P * P;
+        // waves per workgroup: most resident waves per CU under the LDS budget per workgroup
+        auto pick = [&](int64_t words) {
+            const int64_t per_wave = words * 4;
+            int best = 0, best_waves = -1;
+            for (int w = 1; w <= 16; w *= 2) {
+                if (w > wpb || w * per_wave > lds_budget) break;
+                const int waves = (int)(kLdsPerCU / (w * per_wave)) * w;
+                if (waves >= best_waves) {
+                    best_waves = waves;
+                    best = w;
+                }
+            }
+            return best;
+        };
+        cl.wpb_f = pick(lds_words_fwd(P, cl.WB, cl.NL));
+        cl.wpb_b = pick(lds_words_bwd(P, cl.WB, cl.NL));
+        if (!cl.wpb_f || !cl.wpb_b)
+            return fail(DD_E_UNSUPPORTED, "LDS need %lld bytes per wave exceeds the budget",
+                        (long long)lds_words_fwd(P, cl.WB, cl.NL) * 4);
         hp.classes.push_back(cl);
         i = j;
     }
@@ -301,16 +341,22 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
     topo.assign((size_t)node_slots, 0u);
     const int64_t ntiles = (int64_t)hp.nlev.size();
     parallel_for(ntiles, 64, [&](int64_t t, int) {
-        const int P = hp.tile_P[t], G = 64 / P;
+        const int P = hp.tile_P[t], G = 64 / P, nl = hp.nlev[t];
         for (int g = 0; g < G; ++g) {
             const int row = hp.bdd[t * 64 + g];
-            if (row < 0) continue;
-            const RowBdd &b = bdds[row];
+            const RowBdd *b = row >= 0 ? &bdds[row] : nullptr;
+            const int L = b ? b->L : 0;
             size_t src = 0;
-            for (int l = 0; l < b.L; ++l) {
+            for (int l = 0; l < nl; ++l) {
                 const int64_t base = hp.node_base[t] + hp.lev_off[hp.lev_base[t] + l];
-                for (int k = 0; k < b.width[l]; ++k)
-                    topo[(size_t)(base + (int64_t)(k / P) * 64 + g * P + (k % P))] = b.arcs[src++];
+                const int W = l < L ? b->width[l] : 0;
+                const int Wn = l + 1 < L ? b->width[l + 1] : 0;
+                const int slots = hp.lev_rows[hp.lev_base[t] + l] * P;
+                // real nodes, then padding whose two arcs lead to the 0-terminal
+                for (int k = 0; k < W; ++k)
+                    topo[(size_t)(base + (int64_t)(k / P) * 64 + g * P + (k % P))] = b->arcs[src++];
+                for (int k = W; k < slots; ++k)
+                    topo[(size_t)(base + (int64_t)(k / P) * 64 + g * P + (k % P))] = (uint32_t)Wn | ((uint32_t)Wn << 16);
             }
         }
     });
@@ -379,21 +425,38 @@ int recorded(dd_instance *h, const char *name, double bytes, hipStream_t s, F la
     return DD_OK;
 }
 
+// The classes of one pass are independent launches; all but the first run on side streams
+// forked from (and joined back into) the caller's stream, so their tails overlap.
 int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
-    for (const ClassLaunch &c : h->classes) {
+    const size_t nc = h->classes.size();
+    if (nc > 1) {
+        HIP_TRY(hipEventRecord(h->fork, s));
+        for (size_t c = 1; c < nc; ++c) HIP_TRY(hipStreamWaitEvent(h->side[c - 1], h->fork, 0));
+    }
+    for (size_t c = 0; c < nc; ++c) {
+        const ClassLaunch &cl = h->classes[c];
+        hipStream_t cs = c == 0 ? s : h->side[c - 1];
         char name[96];
-        snprintf(name, sizeof name, "%s<%d, %d, %d>", fwd ? "k_fwd" : "k_bwd", c.P, c.RMAX, mode);
-        int st = recorded(h, name, algorithmic_bytes(fwd, mode, c), s, [&] {
-            return fwd ? launch_fwd(h->T, c, mode, s) : launch_bwd(h->T, c, mode, s);
+        snprintf(name, sizeof name, "%s<%d, %d, %d>", fwd ? "k_fwd" : "k_bwd", cl.P, cl.RMAX, mode);
+        int st = recorded(h, name, algorithmic_bytes(fwd, mode, cl), cs, [&] {
+            return fwd ? launch_fwd(h->T, cl, mode, cs) : launch_bwd(h->T, cl, mode, cs);
         });
         if (st) return st;
+    }
+    for (size_t c = 1; c < nc; ++c) {
+        HIP_TRY(hipEventRecord(h->join[c - 1], h->side[c - 1]));
+        HIP_TRY(hipStreamWaitEvent(s, h->join[c - 1], 0));
     }
     return DD_OK;
 }
 
 int deferred(dd_instance *h, hipStream_t s) {
-    return recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 8.0 * (double)h->n, s, [&] {
+    int st = recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 12.0 * (double)h->n, s, [&] {
         return launch_deferred_sum(h->var_ptr, h->var_slots, h->T.M, h->S, (int)h->n, s);
+    });
+    if (st) return st;
+    return recorded(h, "k_edge_alpha_s", 16.0 * (double)h->edge_slots, s, [&] {
+        return launch_edge_alpha_s(h->T.evar, h->alpha, h->S, h->aS, h->edge_slots, s);
     });
 }
 
@@ -491,6 +554,8 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     h->m = m;
     h->E = sr.ptr[m];
     h->classes = hp.classes;
+    std::stable_sort(h->classes.begin(), h->classes.end(),
+                     [](const ClassLaunch &x, const ClassLaunch &y) { return x.nodes > y.nodes; });
     h->ntiles = (int64_t)hp.nlev.size();
     h->node_slots = hp.node_slots;
     h->edge_slots = hp.edge_slots;
@@ -547,6 +612,8 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     TRY(h->alloc(&T.M, (size_t)hp.edge_slots));
     TRY(h->alloc(&h->omega, (size_t)hp.edge_slots));
     TRY(h->alloc(&h->alpha, (size_t)hp.edge_slots));
+    TRY(h->alloc(&h->aS, (size_t)hp.edge_slots));
+    T.aS = h->aS;
     T.omega = h->omega;
     T.alpha = h->alpha;
     TRY(upload(h, (int32_t **)&T.evar, hp.evar, s));
@@ -562,15 +629,27 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     TRY(h->alloc(&h->tmp, (size_t)std::max<int64_t>(h->E, 1) * 2));
     TRY(h->alloc(&h->red, 4));
     TRY(h->alloc(&h->flags, 2));
+    auto hip_ok = [&](hipError_t e) { return e == hipSuccess ? DD_OK : fail(DD_E_HIP, "%s", hipGetErrorString(e)); };
+    for (size_t c = 1; c < h->classes.size(); ++c) {
+        hipStream_t q;
+        hipEvent_t ev;
+        TRY(hip_ok(hipStreamCreateWithFlags(&q, hipStreamNonBlocking)));
+        h->side.push_back(q);
+        TRY(hip_ok(hipEventCreateWithFlags(&ev, hipEventDisableTiming)));
+        h->join.push_back(ev);
+    }
+    TRY(hip_ok(hipEventCreateWithFlags(&h->fork, hipEventDisableTiming)));
     {
         hipError_t e = hipHostMalloc((void **)&h->red_host, 4 * sizeof(double), hipHostMallocDefault);
         if (e != hipSuccess) return cleanup(fail(DD_E_OOM, "hipHostMalloc: %s", hipGetErrorString(e)));
     }
-    auto hip_ok = [&](hipError_t e) { return e == hipSuccess ? DD_OK : fail(DD_E_HIP, "%s", hipGetErrorString(e)); };
     TRY(hip_ok(hipMemsetAsync(T.lam, 0, sizeof(float) * hp.edge_slots, s)));
     TRY(hip_ok(hipMemsetAsync(T.M, 0, sizeof(float) * hp.edge_slots, s)));
     TRY(hip_ok(hipMemsetAsync(h->omega, 0, sizeof(float) * hp.edge_slots, s)));
     TRY(hip_ok(hipMemsetAsync(h->alpha, 0, sizeof(float) * hp.edge_slots, s)));
+    TRY(hip_ok(hipMemsetAsync(h->aS, 0, sizeof(float) * hp.edge_slots, s)));
+    TRY(hip_ok(hipMemsetAsync(T.F, 0, sizeof(float) * hp.node_slots, s)));
+    TRY(hip_ok(hipMemsetAsync(T.B, 0, sizeof(float) * hp.node_slots, s)));
     TRY(hip_ok(hipMemsetAsync(T.energies, 0, sizeof(float) * std::max(m, 1), s)));
     TRY(hip_ok(hipMemsetAsync(h->S, 0, sizeof(float) * std::max<int64_t>(prob->n, 1), s)));
     // default parameters (FastDOG special case), staged through tmp
@@ -665,8 +744,8 @@ int dd_get_state(dd_instance *h, float *lambda_out, float *M_out, int32_t flushe
         int st = deferred(h, s);
         if (st) return st;
     }
-    HIP_TRY(launch_gather(h->canon2slot, h->T.lam, lambda_out, h->E, h->alpha, h->S, h->T.evar, flushed ? 1 : 0, s));
-    if (M_out) HIP_TRY(launch_gather(h->canon2slot, h->T.M, M_out, h->E, nullptr, nullptr, nullptr, 0, s));
+    HIP_TRY(launch_gather(h->canon2slot, h->T.lam, lambda_out, h->E, flushed ? h->aS : nullptr, s));
+    if (M_out) HIP_TRY(launch_gather(h->canon2slot, h->T.M, M_out, h->E, nullptr, s));
     return DD_OK;
 }
 

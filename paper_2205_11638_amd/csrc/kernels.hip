@@ -33,6 +33,9 @@ __device__ __forceinline__ int f2k(float f) {
 }
 __device__ __forceinline__ float k2f(int k) { return __int_as_float(k >= 0 ? k : k ^ 0x7FFFFFFF); }
 
+// Values known to be equal on every lane of the wavefront, made scalar for the compiler.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 template <int P>
 __device__ __forceinline__ float team_min(float v) {
 #pragma unroll
@@ -55,164 +58,258 @@ __device__ __forceinline__ TileCtx tile_ctx(const DevTables &T, int64_t tile) {
     return c;
 }
 
+// Per-wave LDS layout shared by the pass kernels (all entries 4 bytes):
+//   [X: WB*G floats] [Y: WB*G floats] [meta: NL*G ints] [off: NL ints]
+// meta[l*G + g] = width of team g at level l | rows of level l << 16; off[l] = level offset.
+// Node buffers are interleaved over teams (index k*G + g) and hold WB >= width + 2 entries
+// per team: the two past the level's width are the terminals (0-terminal = +inf, 1-terminal
+// = 0), so a child code indexes the buffer directly, with no branch.  Slots past a team's
+// width inside a level's rows are padding whose child codes both point at the 0-terminal,
+// so every global access of a level is unconditional and in bounds.
+template <int G>
+__device__ __forceinline__ void preload_meta(const DevTables &T, const TileCtx &tc, int lane, int *meta, int *off) {
+    const int n = tc.nlev * G;
+    for (int i = lane; i < n; i += 64) meta[i] = T.widths[tc.wbase + i] | (T.lev_rows[tc.lbase + i / G] << 16);
+    for (int l = lane; l < tc.nlev; l += 64) off[l] = T.lev_off[tc.lbase + l];
+    wave_sync();
+}
+
+__device__ __forceinline__ void lds_fmin(float *a, float v) {
+    __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
 // ------------------------------------------------------------------------------------------
-// Forward pass.  LDS per team: two int buffers of WL entries (F of level l, partial F of
-// level l+1), interleaved over teams: index (buf * WL + k) * G + g.
+// Forward pass.  X = F of the current level (min-accumulated for the next one), Y = B of the
+// next level staged from global memory.
 // ------------------------------------------------------------------------------------------
 template <int P, int RMAX, int MODE>
-__global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t ntiles, int WL) {
+__global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
-    extern __shared__ int lds_i[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr bool UPD = MODE == FWD_UPDATE;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int g = lane / P, p = lane % P;
     const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;  // uniform per wave
-    int *my = lds_i + (size_t)wave * 2 * WL * G;
+    float *Fb = lds_f + (size_t)wave * (2 * WB * G + NL * (G + 1));
+    float *Bst = Fb + WB * G;
+    int *meta = (int *)(Bst + WB * G);
+    int *off = meta + NL * G;
     const TileCtx tc = tile_ctx(T, tile);
-    int cur = 0;
-    if (p == 0) my[(0 * WL + 0) * G + g] = f2k(0.f);  // F(root) = 0
-    float lam_prev = 0.f;
-    wave_sync();
-    for (int l = 0; l < tc.nlev; ++l) {
-        const int W = T.widths[tc.wbase + l * G + g];
-        const bool has_next = l + 1 < tc.nlev;
-        const int Wn = has_next ? (int)T.widths[tc.wbase + (l + 1) * G + g] : 0;
-        const int R = T.lev_rows[tc.lbase + l];
-        const int64_t off = tc.nbase + T.lev_off[tc.lbase + l];
-        const int64_t offn = has_next ? tc.nbase + T.lev_off[tc.lbase + l + 1] : 0;
-        const int e = tc.ebase + l * G + g;
-        float lam = 0.f, om = 0.f, al = 0.f, S = 0.f;
-        if (W > 0) {
-            lam = T.lam[e];
-            al = T.alpha[e];
-            S = T.S[T.evar[e]];
-            if (MODE == FWD_UPDATE) om = T.omega[e];
-        }
-        int *nxt = my + (size_t)(cur ^ 1) * WL * G;
-        const int *cb = my + (size_t)cur * WL * G;
-        for (int k = p; k < Wn; k += P) nxt[k * G + g] = f2k(kInf);
-        wave_sync();
-        float m0 = kInf, m1 = kInf;
-        uint32_t tp[RMAX];
-        float fv[RMAX];
+    preload_meta<G>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto Wof = [&](int l) {
+        const int w = l < nlev ? (meta[l * G + g] & 0xFFFF) : 0;
+        return G == 1 ? uni(w) : w;
+    };
+    auto Rof = [&](int l) { return uni(l < nlev ? (meta[l * G] >> 16) : 0); };
+    auto lev = [&](int l) { return tc.nbase + (int64_t)uni(off[l]); };
+    const int mine = p * G + g;  // this lane's buffer index for k = p; row r adds r * P * G
+
+    uint32_t tpn[RMAX];
+    float bvn[RMAX];
+    float lamn = 0.f, omn = 0.f, aSn = 0.f;
+    {
+        const int R0 = Rof(0), R1 = Rof(1);
+        const uint32_t *tg = T.topo + lev(0);
+        const float *bg = T.B + (R1 ? lev(1) : 0);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            tp[r] = 0u;
-            fv[r] = kInf;
-            const int k = r * P + p;
-            if (r < R && k < W) {
-                const int64_t slot = off + (int64_t)r * 64 + lane;
-                const float f = k2f(cb[k * G + g]);
-                const uint32_t t = T.topo[slot];
-                T.F[slot] = f;
-                if (MODE == FWD_UPDATE) {
-                    const int lo = (int)(t & 0xFFFFu), hi = (int)(t >> 16);
-                    float b0 = lo == Wn ? kInf : 0.f, b1 = hi == Wn ? kInf : 0.f;
-                    if (lo < Wn) b0 = T.B[offn + (int64_t)(lo / P) * 64 + g * P + (lo % P)];
-                    if (hi < Wn) b1 = T.B[offn + (int64_t)(hi / P) * 64 + g * P + (hi % P)];
-                    m0 = fminf(m0, f + b0);
-                    m1 = fminf(m1, f + b1);
+            if (r < R0) tpn[r] = tg[r * 64 + lane];
+            if (UPD && r < R1) bvn[r] = bg[r * 64 + lane];
+        }
+        const int e = tc.ebase + g;
+        lamn = T.lam[e];
+        aSn = T.aS[e];
+        if (UPD) omn = T.omega[e];
+    }
+    if (p == 0) Fb[g] = 0.f;  // F(root) = 0
+    wave_sync();
+    for (int l = 0; l < nlev; ++l) {
+        const int W = Wof(l), R = Rof(l), Wn = Wof(l + 1), Rn = Rof(l + 1);
+        const float lam = lamn, om = omn, aS = aSn;
+        uint32_t tp[RMAX];
+        float fv[RMAX];
+        // read F of this level, clear the slots of the next level, stage B of the next level
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            tp[r] = tpn[r];
+            const int k = r * P + p, x = mine + r * P * G;
+            if (r < R) fv[r] = k < W ? Fb[x] : kInf;
+            if (r < Rn) {
+                Fb[x] = kInf;
+                if (UPD) Bst[x] = bvn[r];
+            }
+        }
+        if (UPD && p == 0) {
+            Bst[Wn * G + g] = kInf;       // 0-terminal
+            Bst[(Wn + 1) * G + g] = 0.f;  // 1-terminal
+        }
+        wave_sync();
+        // prefetch: topology of level l+1, B of level l+2, edge data of level l+1
+        if (l + 1 < nlev) {
+            const int R2 = Rof(l + 2);
+            const uint32_t *tg = T.topo + lev(l + 1);
+            const float *bg = T.B + (R2 ? lev(l + 2) : 0);
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                if (r < Rn) tpn[r] = tg[r * 64 + lane];
+                if (UPD && r < R2) bvn[r] = bg[r * 64 + lane];
+            }
+            const int e = tc.ebase + (l + 1) * G + g;
+            lamn = T.lam[e];
+            aSn = T.aS[e];
+            if (UPD) omn = T.omega[e];
+        }
+        float m0 = kInf, m1 = kInf;
+        float *fg = T.F + lev(l);
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < R) {
+                fg[r * 64 + lane] = fv[r];
+                if (UPD) {
+                    const float b0 = Bst[(int)(tp[r] & 0xFFFFu) * G + g];
+                    const float b1 = Bst[(int)(tp[r] >> 16) * G + g];
+                    m0 = fminf(m0, fv[r] + b0);
+                    m1 = fminf(m1, fv[r] + b1);
                 }
-                tp[r] = t;
-                fv[r] = f;
             }
         }
         float lam_new;
-        if (MODE == FWD_UPDATE) {
+        if (UPD) {
             m0 = team_min<P>(m0);
             m1 = team_min<P>(m1);
             lam_new = lam;
             if (W > 0) {
                 m1 += lam;
                 const float Mn = om * (m1 - m0);
-                lam_new = lam - Mn + al * S;
+                lam_new = lam - Mn + aS;
                 if (p == 0) {
+                    const int e = tc.ebase + l * G + g;
                     T.lam[e] = lam_new;
                     T.M[e] = Mn;
                 }
             }
         } else {
-            lam_new = lam + al * S;  // flushed multipliers, no update
+            lam_new = lam + aS;  // flushed multipliers, no update
         }
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            const int k = r * P + p;
-            if (r < R && k < W) {
+            if (r < R) {
                 const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
-                if (lo < Wn) atomicMin(&nxt[lo * G + g], f2k(fv[r]));
-                if (hi < Wn) atomicMin(&nxt[hi * G + g], f2k(fv[r] + lam_new));
+                if (lo < Wn) lds_fmin(&Fb[lo * G + g], fv[r]);
+                if (hi < Wn) lds_fmin(&Fb[hi * G + g], fv[r] + lam_new);
             }
         }
         wave_sync();
-        cur ^= 1;
-        (void)lam_prev;
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// Backward pass and sweeps.  LDS per team: two float buffers (B of level l+1, B of level l).
+// Backward pass and sweeps.  X / Y alternate as B of level l+1 (read) and B of level l (written).
 // ------------------------------------------------------------------------------------------
 template <int P, int RMAX, int MODE>
-__global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t ntiles, int WL) {
+__global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
+    constexpr bool UPD = MODE == BWD_UPDATE, MM = MODE == BWD_MM;
+    constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM;
     extern __shared__ float lds_f[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int g = lane / P, p = lane % P;
     const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;
-    float *my = lds_f + (size_t)wave * 2 * WL * G;
+    float *buf0 = lds_f + (size_t)wave * (2 * WB * G + NL * (G + 1));
+    int *meta = (int *)(buf0 + 2 * WB * G);
+    int *off = meta + NL * G;
     const TileCtx tc = tile_ctx(T, tile);
     const int row = T.bdd[tile * 64 + g];
-    int cur = 0;  // buffer holding B of level l+1
-    for (int l = tc.nlev - 1; l >= 0; --l) {
-        const int W = T.widths[tc.wbase + l * G + g];
-        const int Wn = l + 1 < tc.nlev ? (int)T.widths[tc.wbase + (l + 1) * G + g] : 0;
-        const int R = T.lev_rows[tc.lbase + l];
-        const int64_t off = tc.nbase + T.lev_off[tc.lbase + l];
-        const int e = tc.ebase + l * G + g;
-        float lam = 0.f, om = 0.f, al = 0.f, S = 0.f;
-        if (W > 0) {
-            lam = T.lam[e];
-            if (MODE == BWD_UPDATE || MODE == BWD_EN_BAR || MODE == BWD_MM) {
-                al = T.alpha[e];
-                S = T.S[T.evar[e]];
+    preload_meta<G>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto Wof = [&](int l) {
+        const int w = l < nlev ? (meta[l * G + g] & 0xFFFF) : 0;
+        return G == 1 ? uni(w) : w;
+    };
+    auto Rof = [&](int l) { return uni(l < nlev ? (meta[l * G] >> 16) : 0); };
+    auto lev = [&](int l) { return tc.nbase + (int64_t)uni(off[l]); };
+    const int mine = p * G + g;
+
+    uint32_t tpn[RMAX];
+    float fn[RMAX];
+    float lamn, omn = 0.f, aSn = 0.f;
+    {
+        const int lt = nlev - 1, Rt = Rof(lt);
+        const uint32_t *tg = T.topo + lev(lt);
+        const float *fg = T.F + lev(lt);
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < Rt) {
+                tpn[r] = tg[r * 64 + lane];
+                if (NEEDF) fn[r] = fg[r * 64 + lane];
             }
-            if (MODE == BWD_UPDATE) om = T.omega[e];
         }
-        const float lam_use = (MODE == BWD_EN_BAR || MODE == BWD_MM) ? lam + al * S : lam;
-        const float *bn = my + (size_t)cur * WL * G;
-        float *bc = my + (size_t)(cur ^ 1) * WL * G;
+        const int e = tc.ebase + lt * G + g;
+        lamn = T.lam[e];
+        if (UPD || BAR) aSn = T.aS[e];
+        if (UPD) omn = T.omega[e];
+    }
+    int cur = 0;  // buffer holding B of level l+1 (terminals only, below the last level)
+    if (p == 0) {
+        buf0[g] = kInf;
+        buf0[G + g] = 0.f;
+    }
+    wave_sync();
+    for (int l = nlev - 1; l >= 0; --l) {
+        const int W = Wof(l), R = Rof(l);
+        const float lam = lamn, om = omn, aS = aSn;
+        uint32_t tp[RMAX];
+        float fv[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            tp[r] = tpn[r];
+            if (NEEDF) fv[r] = fn[r];
+        }
+        if (l > 0) {  // prefetch level l-1
+            const int Rp = Rof(l - 1);
+            const uint32_t *tg = T.topo + lev(l - 1);
+            const float *fg = T.F + lev(l - 1);
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                if (r < Rp) {
+                    tpn[r] = tg[r * 64 + lane];
+                    if (NEEDF) fn[r] = fg[r * 64 + lane];
+                }
+            }
+            const int e = tc.ebase + (l - 1) * G + g;
+            lamn = T.lam[e];
+            if (UPD || BAR) aSn = T.aS[e];
+            if (UPD) omn = T.omega[e];
+        }
+        const float *bn = buf0 + cur * WB * G;
+        float *bc = buf0 + (cur ^ 1) * WB * G;
         float m0 = kInf, m1 = kInf;
         float b0r[RMAX], b1r[RMAX];
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            b0r[r] = kInf;
-            b1r[r] = kInf;
-            const int k = r * P + p;
-            if (r < R && k < W) {
-                const int64_t slot = off + (int64_t)r * 64 + lane;
-                const uint32_t t = T.topo[slot];
-                const int lo = (int)(t & 0xFFFFu), hi = (int)(t >> 16);
-                const float b0 = lo < Wn ? bn[lo * G + g] : (lo == Wn ? kInf : 0.f);
-                const float b1 = hi < Wn ? bn[hi * G + g] : (hi == Wn ? kInf : 0.f);
-                if (MODE == BWD_UPDATE || MODE == BWD_MM) {
-                    const float f = T.F[slot];
-                    m0 = fminf(m0, f + b0);
-                    m1 = fminf(m1, f + b1);
+            if (r < R) {
+                b0r[r] = bn[(int)(tp[r] & 0xFFFFu) * G + g];
+                b1r[r] = bn[(int)(tp[r] >> 16) * G + g];
+                if (NEEDF) {
+                    m0 = fminf(m0, fv[r] + b0r[r]);
+                    m1 = fminf(m1, fv[r] + b1r[r]);
                 }
-                b0r[r] = b0;
-                b1r[r] = b1;
             }
         }
+        const float lam_use = BAR ? lam + aS : lam;
         float lam_new = lam_use;
-        if (MODE == BWD_UPDATE || MODE == BWD_MM) {
+        if (NEEDF) {
             m0 = team_min<P>(m0);
             m1 = team_min<P>(m1);
             if (W > 0) {
                 m1 += lam_use;
-                if (MODE == BWD_UPDATE) {
+                const int e = tc.ebase + l * G + g;
+                if (UPD) {
                     const float Mn = om * (m1 - m0);
-                    lam_new = lam - Mn + al * S;
+                    lam_new = lam - Mn + aS;
                     if (p == 0) {
                         T.lam[e] = lam_new;
                         T.M[e] = Mn;
@@ -224,45 +321,52 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                 }
             }
         }
+        float *bg = T.B + lev(l);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            const int k = r * P + p;
-            if (r < R && k < W) {
+            if (r < R) {
                 const float b = fminf(b0r[r], lam_new + b1r[r]);
-                bc[k * G + g] = b;
-                if (MODE == BWD_UPDATE || MODE == BWD_STORE) T.B[off + (int64_t)r * 64 + lane] = b;
+                bc[mine + r * P * G] = b;
+                if (UPD || MODE == BWD_STORE) bg[r * 64 + lane] = b;
             }
+        }
+        if (p == 0) {
+            bc[W * G + g] = kInf;
+            bc[(W + 1) * G + g] = 0.f;
         }
         wave_sync();
         cur ^= 1;
     }
-    if (MODE != BWD_MM && p == 0 && row >= 0) T.energies[row] = my[(size_t)cur * WL * G + g];
+    if (!MM && p == 0 && row >= 0) T.energies[row] = buf0[cur * WB * G + g];
 }
 
 template <int P, int RMAX>
 hipError_t fwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
-    dim3 grid((unsigned)((c.ntiles + c.wpb - 1) / c.wpb)), block(64 * c.wpb);
-    size_t lds = (size_t)c.wpb * 2 * c.WL * (64 / P) * sizeof(int);
-    if (mode == FWD_UPDATE) hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WL);
-    else hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_SWEEP_BAR>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WL);
+    dim3 grid((unsigned)((c.ntiles + c.wpb_f - 1) / c.wpb_f)), block(64 * c.wpb_f);
+    size_t lds = (size_t)c.wpb_f * lds_words_fwd(P, c.WB, c.NL) * 4;
+    if (mode == FWD_UPDATE)
+        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL);
+    else
+        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_SWEEP_BAR>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL);
     return hipGetLastError();
 }
 
 template <int P, int RMAX>
 hipError_t bwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
-    dim3 grid((unsigned)((c.ntiles + c.wpb - 1) / c.wpb)), block(64 * c.wpb);
-    size_t lds = (size_t)c.wpb * 2 * c.WL * (64 / P) * sizeof(float);
+    dim3 grid((unsigned)((c.ntiles + c.wpb_b - 1) / c.wpb_b)), block(64 * c.wpb_b);
+    size_t lds = (size_t)c.wpb_b * lds_words_bwd(P, c.WB, c.NL) * 4;
     switch (mode) {
-        case BWD_UPDATE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WL); break;
-        case BWD_STORE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_STORE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WL); break;
-        case BWD_EN_LAM: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_LAM>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WL); break;
-        case BWD_EN_BAR: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_BAR>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WL); break;
-        default: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_MM>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WL); break;
+        case BWD_UPDATE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        case BWD_STORE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_STORE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        case BWD_EN_LAM: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_LAM>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        case BWD_EN_BAR: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_BAR>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        default: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_MM>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
     }
     return hipGetLastError();
 }
 
-#define DD_CLASSES(X) X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(64, 8) X(64, 16) X(64, 32)
+#define DD_CLASSES(X) \
+    X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(64, 8) X(64, 12) X(64, 16) X(64, 24) X(64, 32)
 
 __global__ void k_deferred_sum(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_slots,
                                const float *__restrict__ M, float *__restrict__ S, int n) {
@@ -271,6 +375,15 @@ __global__ void k_deferred_sum(const int32_t *__restrict__ var_ptr, const int32_
     float s = 0.f;
     for (int q = var_ptr[i]; q < var_ptr[i + 1]; ++q) s += M[var_slots[q]];
     S[i] = s;
+}
+
+// aS[slot] = alpha[slot] * S[var(slot)] over all edge slots (padding slots have var -1).
+__global__ void k_edge_alpha_s(const int32_t *__restrict__ evar, const float *__restrict__ alpha,
+                               const float *__restrict__ S, float *__restrict__ aS, int64_t slots) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= slots) return;
+    const int v = evar[e];
+    aS[e] = v >= 0 ? alpha[e] * S[v] : 0.f;
 }
 
 __global__ void k_init_lambda(const int32_t *__restrict__ canon2slot, const int32_t *__restrict__ evar,
@@ -291,13 +404,12 @@ __global__ void k_scatter(const int32_t *__restrict__ canon2slot, const float *_
 }
 
 __global__ void k_gather(const int32_t *__restrict__ canon2slot, const float *__restrict__ src, float *dst, int64_t E,
-                         const float *__restrict__ alpha, const float *__restrict__ S, const int32_t *__restrict__ evar,
-                         int flush) {
+                         const float *__restrict__ add) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
     const int s = canon2slot[e];
     float v = src[s];
-    if (flush) v = v + alpha[s] * S[evar[s]];
+    if (add) v = v + add[s];
     dst[e] = v;
 }
 
@@ -341,9 +453,12 @@ __global__ __launch_bounds__(1024) void k_bound_reduce(const float *__restrict__
 __global__ void k_check_params(const float *__restrict__ om, const float *__restrict__ al, int64_t E, int32_t *flags) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= E) return;
-    const float w = om[e], a = al[e];
-    if (!(w >= 0.f && w <= 1.f)) atomicOr(&flags[0], 1);
-    if (!(a >= 0.f && a <= 3.0e38f)) atomicOr(&flags[1], 1);
+    // bit tests, so the check holds under -fno-honor-nans: an all-ones exponent is inf or NaN
+    const uint32_t w = __float_as_uint(om[e]), a = __float_as_uint(al[e]);
+    const bool w_nonfinite = (w & 0x7F800000u) == 0x7F800000u, a_nonfinite = (a & 0x7F800000u) == 0x7F800000u;
+    const bool w_neg = (w >> 31) && (w & 0x7FFFFFFFu), a_neg = (a >> 31) && (a & 0x7FFFFFFFu);
+    if (w_nonfinite || w_neg || __uint_as_float(w) > 1.f) atomicOr(&flags[0], 1);
+    if (a_nonfinite || a_neg) atomicOr(&flags[1], 1);
 }
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -380,6 +495,13 @@ hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots,
     return hipGetLastError();
 }
 
+hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, int64_t slots,
+                               hipStream_t s) {
+    if (slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge_alpha_s, dim3(blocks_for(slots, 256)), dim3(256), 0, s, evar, alpha, S, aS, slots);
+    return hipGetLastError();
+}
+
 hipError_t launch_init_lambda(const int32_t *canon2slot, const int32_t *evar, const int32_t *var_ptr, const float *c,
                               float *lam, float *M, int64_t E, hipStream_t s) {
     if (E <= 0) return hipSuccess;
@@ -393,11 +515,10 @@ hipError_t launch_scatter(const int32_t *canon2slot, const float *src, float *ds
     return hipGetLastError();
 }
 
-hipError_t launch_gather(const int32_t *canon2slot, const float *src, float *dst, int64_t E, const float *alpha,
-                         const float *S, const int32_t *evar, int flush, hipStream_t s) {
+hipError_t launch_gather(const int32_t *canon2slot, const float *src, float *dst, int64_t E, const float *add,
+                         hipStream_t s) {
     if (E <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gather, dim3(blocks_for(E, 256)), dim3(256), 0, s, canon2slot, src, dst, E, alpha, S, evar,
-                       flush);
+    hipLaunchKernelGGL(k_gather, dim3(blocks_for(E, 256)), dim3(256), 0, s, canon2slot, src, dst, E, add);
     return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct DevTables {
     const int32_t *evar;      // variable of each edge slot (-1: padding)
     const int32_t *slot2canon;
     const float *S;           // [n] deferred sums
+    const float *aS;          // [edge slots] alpha * S of the edge's variable
     float *energies;          // [m] per-row E^j
     float *out0, *out1;       // [edges] canonical min-marginal outputs
 };
@@ -48,11 +49,17 @@ struct DevTables {
 struct ClassLaunch {
     int P;         // team size (lanes per diagram)
     int RMAX;      // max rows (of 64 slots) per level for this class
-    int WL;        // LDS floats per team per buffer (max width in the class)
-    int wpb;       // waves per workgroup
+    int WL;        // max level width in the class
+    int WB;        // LDS floats per team per node buffer: WL + 2 terminals, rounded up to P
+    int NL;        // max levels of a tile in the class
+    int wpb_f, wpb_b;  // waves per workgroup of the forward / backward kernels
     int64_t tile0, ntiles;
     int64_t nodes, edges, rows;  // real (unpadded) counts covered by one launch, for byte accounting
 };
+
+// LDS words (4 bytes) one wavefront of the forward / backward pass kernels uses.
+inline int64_t lds_words_fwd(int P, int WB, int NL) { return 2LL * WB * (64 / P) + (int64_t)NL * ((64 / P) + 1); }
+inline int64_t lds_words_bwd(int P, int WB, int NL) { return 2LL * WB * (64 / P) + (int64_t)NL * ((64 / P) + 1); }
 
 hipError_t launch_fwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
 hipError_t launch_bwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
@@ -61,14 +68,17 @@ bool class_supported(int P, int RMAX);
 // S_i = sum over the CSR list of edge slots of variable i of M[slot], in list order.
 hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots, const float *M, float *S, int n,
                                hipStream_t s);
+// aS[slot] = alpha[slot] * S[evar[slot]] for every edge slot (0 on padding).
+hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, int64_t slots,
+                               hipStream_t s);
 // lambda[slot] = c_i / |J_i|, M[slot] = 0 for every canonical edge.
 hipError_t launch_init_lambda(const int32_t *canon2slot, const int32_t *evar, const int32_t *var_ptr, const float *c,
                               float *lam, float *M, int64_t E, hipStream_t s);
 // dst[canon2slot[e]] = src[e]
 hipError_t launch_scatter(const int32_t *canon2slot, const float *src, float *dst, int64_t E, hipStream_t s);
-// dst[e] = src[canon2slot[e]] (+ alpha[slot] * S[var] when flush)
-hipError_t launch_gather(const int32_t *canon2slot, const float *src, float *dst, int64_t E, const float *alpha,
-                         const float *S, const int32_t *evar, int flush, hipStream_t s);
+// dst[e] = src[canon2slot[e]] (+ add[canon2slot[e]] when add is not NULL)
+hipError_t launch_gather(const int32_t *canon2slot, const float *src, float *dst, int64_t E, const float *add,
+                         hipStream_t s);
 // softmax over each variable's edges; inputs/outputs canonical, var_canon is the CSR of canonical edge ids
 hipError_t launch_seg_softmax(const int32_t *var_ptr, const int32_t *var_canon, const float *x, float *y, int n,
                               hipStream_t s);
