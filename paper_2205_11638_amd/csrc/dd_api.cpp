@@ -142,7 +142,7 @@ struct HostPlan {
     std::vector<int32_t> lev_off, lev_rows;
     std::vector<uint16_t> widths;
     std::vector<int32_t> tile_P;
-    int64_t node_slots = 0, edge_slots = 0;
+    int64_t node_slots = 0, edge_slots = 0, node_alloc = 0;
     // edges
     std::vector<int32_t> canon2slot, slot2canon, evar;
     std::vector<int32_t> var_ptr, var_slots, var_canon;
@@ -183,6 +183,8 @@ struct dd_instance {
     int32_t *var_ptr = nullptr, *var_slots = nullptr, *var_canon = nullptr, *canon2slot = nullptr;
     float *cdev = nullptr, *S = nullptr, *aS = nullptr, *omega = nullptr, *alpha = nullptr, *tmp = nullptr;
     double *red = nullptr;   // device reduction output [4]
+    double *partial = nullptr;  // [kSumBlocks] reduction scratch
+    bool en_lam_valid = false;  // T.en_lam holds E^j at the current multipliers
     double *red_host = nullptr;  // pinned
     int32_t *flags = nullptr;
 
@@ -295,18 +297,21 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
             for (int g = 0; g < 64; ++g) hp.bdd.push_back(g < G && t0 + g < t1 ? order[t0 + g] : -1);
             int64_t off = 0;
             for (int l = 0; l < nl; ++l) {
-                int R = 0;
+                int R = 0, wmax = 0;
                 for (int g = 0; g < G; ++g) {
                     int w = 0;
                     if (t0 + g < t1 && l < bdds[order[t0 + g]].L) w = bdds[order[t0 + g]].width[l];
                     hp.widths.push_back((uint16_t)w);
                     R = std::max(R, (w + P - 1) / P);
+                    wmax = std::max(wmax, w);
                 }
                 if (off >= ((int64_t)1 << 31)) return fail(DD_E_UNSUPPORTED, "tile too large");
                 if (R > RMAX) return fail(DD_E_UNSUPPORTED, "internal: level needs %d rows > %d", R, RMAX);
                 hp.lev_off.push_back((int32_t)off);
                 hp.lev_rows.push_back(R);
-                off += (int64_t)R * 64;
+                // one-wave diagrams are stored compactly (levels back to back); teams of a
+                // narrower tile interleave, so their levels are padded to whole rows
+                off += P == 64 ? (int64_t)wmax : (int64_t)R * 64;
             }
             node_slots += off;
             edge_slots += (int64_t)nl * G;
@@ -336,9 +341,10 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
         i = j;
     }
     hp.node_slots = node_slots;
+    hp.node_alloc = node_slots + 64;  // the last row of a compact level may read up to 63 slots past it
     hp.edge_slots = edge_slots;
     // nodes
-    topo.assign((size_t)node_slots, 0u);
+    topo.assign((size_t)hp.node_alloc, 0u);
     const int64_t ntiles = (int64_t)hp.nlev.size();
     parallel_for(ntiles, 64, [&](int64_t t, int) {
         const int P = hp.tile_P[t], G = 64 / P, nl = hp.nlev[t];
@@ -355,8 +361,10 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
                 // real nodes, then padding whose two arcs lead to the 0-terminal
                 for (int k = 0; k < W; ++k)
                     topo[(size_t)(base + (int64_t)(k / P) * 64 + g * P + (k % P))] = b->arcs[src++];
-                for (int k = W; k < slots; ++k)
-                    topo[(size_t)(base + (int64_t)(k / P) * 64 + g * P + (k % P))] = (uint32_t)Wn | ((uint32_t)Wn << 16);
+                if (P < 64)
+                    for (int k = W; k < slots; ++k)
+                        topo[(size_t)(base + (int64_t)(k / P) * 64 + g * P + (k % P))] =
+                            (uint32_t)Wn | ((uint32_t)Wn << 16);
             }
         }
     });
@@ -460,7 +468,11 @@ int deferred(dd_instance *h, hipStream_t s) {
     });
 }
 
-int recompute_B(dd_instance *h, hipStream_t s) { return all_classes(h, false, BWD_STORE, s); }
+int recompute_B(dd_instance *h, hipStream_t s) {
+    int st = all_classes(h, false, BWD_STORE, s);
+    h->en_lam_valid = st == DD_OK;
+    return st;
+}
 
 }  // namespace
 
@@ -606,8 +618,8 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     TRY(upload(h, (int32_t **)&T.lev_rows, hp.lev_rows, s));
     TRY(upload(h, (uint16_t **)&T.widths, hp.widths, s));
     TRY(upload(h, (uint32_t **)&T.topo, topo, s));
-    TRY(h->alloc(&T.F, (size_t)hp.node_slots));
-    TRY(h->alloc(&T.B, (size_t)hp.node_slots));
+    TRY(h->alloc(&T.F, (size_t)hp.node_alloc));
+    TRY(h->alloc(&T.B, (size_t)hp.node_alloc));
     TRY(h->alloc(&T.lam, (size_t)hp.edge_slots));
     TRY(h->alloc(&T.M, (size_t)hp.edge_slots));
     TRY(h->alloc(&h->omega, (size_t)hp.edge_slots));
@@ -626,6 +638,8 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     TRY(h->alloc(&h->S, (size_t)prob->n));
     T.S = h->S;
     TRY(h->alloc(&T.energies, (size_t)m));
+    TRY(h->alloc(&T.en_lam, (size_t)m));
+    TRY(h->alloc(&h->partial, (size_t)kSumBlocks));
     TRY(h->alloc(&h->tmp, (size_t)std::max<int64_t>(h->E, 1) * 2));
     TRY(h->alloc(&h->red, 4));
     TRY(h->alloc(&h->flags, 2));
@@ -648,9 +662,10 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     TRY(hip_ok(hipMemsetAsync(h->omega, 0, sizeof(float) * hp.edge_slots, s)));
     TRY(hip_ok(hipMemsetAsync(h->alpha, 0, sizeof(float) * hp.edge_slots, s)));
     TRY(hip_ok(hipMemsetAsync(h->aS, 0, sizeof(float) * hp.edge_slots, s)));
-    TRY(hip_ok(hipMemsetAsync(T.F, 0, sizeof(float) * hp.node_slots, s)));
-    TRY(hip_ok(hipMemsetAsync(T.B, 0, sizeof(float) * hp.node_slots, s)));
+    TRY(hip_ok(hipMemsetAsync(T.F, 0, sizeof(float) * hp.node_alloc, s)));
+    TRY(hip_ok(hipMemsetAsync(T.B, 0, sizeof(float) * hp.node_alloc, s)));
     TRY(hip_ok(hipMemsetAsync(T.energies, 0, sizeof(float) * std::max(m, 1), s)));
+    TRY(hip_ok(hipMemsetAsync(T.en_lam, 0, sizeof(float) * std::max(m, 1), s)));
     TRY(hip_ok(hipMemsetAsync(h->S, 0, sizeof(float) * std::max<int64_t>(prob->n, 1), s)));
     // default parameters (FastDOG special case), staged through tmp
     {
@@ -754,7 +769,12 @@ int dd_run_pass(dd_instance *h, int32_t direction, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     int st = deferred(h, s);
     if (st) return st;
-    return all_classes(h, direction == 0, direction == 0 ? (int)FWD_UPDATE : (int)BWD_UPDATE, s);
+    // a backward pass ends with B(root) = E^j at the updated multipliers; a forward pass
+    // changes the multipliers without computing it
+    h->en_lam_valid = false;
+    st = all_classes(h, direction == 0, direction == 0 ? (int)FWD_UPDATE : (int)BWD_UPDATE, s);
+    h->en_lam_valid = st == DD_OK && direction == 1;
+    return st;
 }
 
 int dd_run(dd_instance *h, int32_t T, void *stream) {
@@ -773,10 +793,17 @@ int dd_lower_bound(dd_instance *h, double *lb, double *dl, void *stream) {
     int st = deferred(h, s);
     if (st) return st;
     if ((st = all_classes(h, false, BWD_EN_BAR, s))) return st;
-    HIP_TRY(launch_bound_reduce(h->T.energies, h->m, h->T.M, h->edge_slots, h->red, s));
+    auto sum = [&](const float *x, int64_t n, int neg, double *out) {
+        return recorded(h, "k_sum", 4.0 * (double)n, s, [&] { return launch_sum(x, n, neg, h->partial, out, s); });
+    };
+    if ((st = sum(h->T.energies, h->m, 0, h->red))) return st;
     if (dl) {
-        if ((st = all_classes(h, false, BWD_EN_LAM, s))) return st;
-        HIP_TRY(launch_bound_reduce(h->T.energies, h->m, h->T.M, h->edge_slots, h->red + 2, s));
+        if (!h->en_lam_valid) {
+            if ((st = all_classes(h, false, BWD_EN_LAM, s))) return st;
+            h->en_lam_valid = true;
+        }
+        if ((st = sum(h->T.en_lam, h->m, 0, h->red + 2))) return st;
+        if ((st = sum(h->T.M, h->edge_slots, 1, h->red + 3))) return st;
     }
     HIP_TRY(hipMemcpyAsync(h->red_host, h->red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));

@@ -11,6 +11,7 @@
 // level's costs live in LDS, so hops need only wavefront-local synchronisation.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 
 #include "kernels.hpp"
@@ -36,10 +37,28 @@ __device__ __forceinline__ float k2f(int k) { return __int_as_float(k >= 0 ? k :
 // Values known to be equal on every lane of the wavefront, made scalar for the compiler.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// min over the P lanes of a team (P a power of two, teams aligned to P lanes), result in
+// every lane of the team.  Within 16-lane rows: DPP quad permutes and row mirrors; across
+// rows: lane reads (P = 64) or one cross-row shuffle (P = 32).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
 template <int P>
 __device__ __forceinline__ float team_min(float v) {
-#pragma unroll
-    for (int o = P / 2; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    if (P >= 2) v = fminf(v, dpp<0xB1>(v));    // quad_perm [1,0,3,2]: lanes i, i^1
+    if (P >= 4) v = fminf(v, dpp<0x4E>(v));    // quad_perm [2,3,0,1]: lanes i, i^2
+    if (P >= 8) v = fminf(v, dpp<0x141>(v));   // row_half_mirror: the two quads of 8 lanes
+    if (P >= 16) v = fminf(v, dpp<0x140>(v));  // row_mirror: the two halves of 16 lanes
+    if (P == 32) v = fminf(v, __shfl_xor(v, 16));
+    if (P == 64) {
+        const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+        const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+        const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+        const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+        v = fminf(fminf(r0, r1), fminf(r2, r3));
+    }
     return v;
 }
 
@@ -82,6 +101,16 @@ __device__ __forceinline__ void lds_fmin(float *a, float v) {
 // Forward pass.  X = F of the current level (min-accumulated for the next one), Y = B of the
 // next level staged from global memory.
 // ------------------------------------------------------------------------------------------
+// One-wave diagrams (P = 64) are stored compactly: level l+1 starts right after the last
+// node of level l, so the last row of a level also reads a few slots of the next level (or
+// of the slack after the array).  Those lanes are masked on that row only: their topology is
+// replaced by two 0-terminal arcs and their stores are skipped.  Narrower teams use levels
+// padded to whole rows, whose padding slots already hold 0-terminal arcs.
+template <int P>
+__device__ __forceinline__ bool in_level(int r, int R, int lane, int W) {
+    return P < 64 || r < R - 1 || lane < W - r * 64;
+}
+
 template <int P, int RMAX, int MODE>
 __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
@@ -163,10 +192,13 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
         }
         float m0 = kInf, m1 = kInf;
         float *fg = T.F + lev(l);
+        const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             if (r < R) {
-                fg[r * 64 + lane] = fv[r];
+                const bool ok = in_level<P>(r, R, lane, W);
+                if (!ok) tp[r] = dead;
+                if (ok) fg[r * 64 + lane] = fv[r];
                 if (UPD) {
                     const float b0 = Bst[(int)(tp[r] & 0xFFFFu) * G + g];
                     const float b1 = Bst[(int)(tp[r] >> 16) * G + g];
@@ -287,15 +319,18 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         const float *bn = buf0 + cur * WB * G;
         float *bc = buf0 + (cur ^ 1) * WB * G;
         float m0 = kInf, m1 = kInf;
-        float b0r[RMAX], b1r[RMAX];
+        const int Wn = Wof(l + 1);
+        const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             if (r < R) {
-                b0r[r] = bn[(int)(tp[r] & 0xFFFFu) * G + g];
-                b1r[r] = bn[(int)(tp[r] >> 16) * G + g];
+                if (!in_level<P>(r, R, lane, W)) tp[r] = dead;
                 if (NEEDF) {
-                    m0 = fminf(m0, fv[r] + b0r[r]);
-                    m1 = fminf(m1, fv[r] + b1r[r]);
+                    // a lane past the level's end has two 0-terminal children: its cost is +inf
+                    const float b0 = bn[(int)(tp[r] & 0xFFFFu) * G + g];
+                    const float b1 = bn[(int)(tp[r] >> 16) * G + g];
+                    m0 = fminf(m0, fv[r] + b0);
+                    m1 = fminf(m1, fv[r] + b1);
                 }
             }
         }
@@ -325,9 +360,10 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             if (r < R) {
-                const float b = fminf(b0r[r], lam_new + b1r[r]);
+                // child costs read again from LDS: cheaper than keeping 2 * RMAX registers live
+                const float b = fminf(bn[(int)(tp[r] & 0xFFFFu) * G + g], lam_new + bn[(int)(tp[r] >> 16) * G + g]);
                 bc[mine + r * P * G] = b;
-                if (UPD || MODE == BWD_STORE) bg[r * 64 + lane] = b;
+                if ((UPD || MODE == BWD_STORE) && in_level<P>(r, R, lane, W)) bg[r * 64 + lane] = b;
             }
         }
         if (p == 0) {
@@ -337,7 +373,11 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         wave_sync();
         cur ^= 1;
     }
-    if (!MM && p == 0 && row >= 0) T.energies[row] = buf0[cur * WB * G + g];
+    if (!MM && p == 0 && row >= 0) {
+        const float e0 = buf0[cur * WB * G + g];  // B(root) = E^j at the multipliers swept
+        if (MODE == BWD_EN_BAR) T.energies[row] = e0;
+        else T.en_lam[row] = e0;
+    }
 }
 
 template <int P, int RMAX>
@@ -425,29 +465,40 @@ __global__ void k_seg_softmax(const int32_t *__restrict__ var_ptr, const int32_t
     for (int q = a; q < b; ++q) y[var_canon[q]] = expf(x[var_canon[q]] - mx) / den;
 }
 
-// One workgroup of 1024 threads: per-thread fp64 partial sums in a fixed stride order,
-// then a fixed-shape tree in LDS, so the result does not depend on scheduling.
-__global__ __launch_bounds__(1024) void k_bound_reduce(const float *__restrict__ En, int64_t m,
-                                                       const float *__restrict__ M, int64_t slots, double *out) {
-    __shared__ double sa[1024], sb[1024];
+// Deterministic two-stage sum in fp64: block b sums a fixed contiguous chunk (thread-strided,
+// then a fixed-shape tree), one block then sums the per-block partials in index order.
+// neg_part != 0 sums min(0, x) instead of x.
+__global__ __launch_bounds__(256) void k_sum_partial(const float *__restrict__ x, int64_t n, int64_t chunk,
+                                                     int neg_part, double *partial) {
+    __shared__ double sh[256];
     const int t = threadIdx.x;
-    double a = 0.0, b = 0.0;
-    for (int64_t j = t; j < m; j += 1024) a += (double)En[j];
-    for (int64_t j = t; j < slots; j += 1024) b += (double)fminf(M[j], 0.f);
-    sa[t] = a;
-    sb[t] = b;
+    const int64_t a = (int64_t)blockIdx.x * chunk, b = a + chunk < n ? a + chunk : n;
+    double acc = 0.0;
+    for (int64_t j = a + t; j < b; j += 256) {
+        const float v = x[j];
+        acc += (double)(neg_part ? fminf(v, 0.f) : v);
+    }
+    sh[t] = acc;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-        if (t < w) {
-            sa[t] += sa[t + w];
-            sb[t] += sb[t + w];
-        }
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
         __syncthreads();
     }
-    if (t == 0) {
-        out[0] = sa[0];
-        out[1] = sb[0];
+    if (t == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ partial, int nb, double *out) {
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    double acc = 0.0;
+    for (int j = t; j < nb; j += 256) acc += partial[j];
+    sh[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
     }
+    if (t == 0) *out = sh[0];
 }
 
 __global__ void k_check_params(const float *__restrict__ om, const float *__restrict__ al, int64_t E, int32_t *flags) {
@@ -529,9 +580,11 @@ hipError_t launch_seg_softmax(const int32_t *var_ptr, const int32_t *var_canon, 
     return hipGetLastError();
 }
 
-hipError_t launch_bound_reduce(const float *energies, int64_t m, const float *M, int64_t slots, double *out,
-                               hipStream_t s) {
-    hipLaunchKernelGGL(k_bound_reduce, dim3(1), dim3(1024), 0, s, energies, m, M, slots, out);
+hipError_t launch_sum(const float *x, int64_t n, int neg_part, double *partial, double *out, hipStream_t s) {
+    const int nb = (int)std::min<int64_t>(kSumBlocks, std::max<int64_t>(1, (n + 4095) / 4096));
+    const int64_t chunk = (std::max<int64_t>(n, 1) + nb - 1) / nb;
+    hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(256), 0, s, x, n, chunk, neg_part, partial);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, out);
     return hipGetLastError();
 }
 

@@ -42,7 +42,8 @@ struct DevTables {
     const int32_t *slot2canon;
     const float *S;           // [n] deferred sums
     const float *aS;          // [edge slots] alpha * S of the edge's variable
-    float *energies;          // [m] per-row E^j
+    float *energies;          // [m] per-row E^j at the flushed multipliers
+    float *en_lam;            // [m] per-row E^j at the current multipliers (from backward passes)
     float *out0, *out1;       // [edges] canonical min-marginal outputs
 };
 
@@ -82,9 +83,10 @@ hipError_t launch_gather(const int32_t *canon2slot, const float *src, float *dst
 // softmax over each variable's edges; inputs/outputs canonical, var_canon is the CSR of canonical edge ids
 hipError_t launch_seg_softmax(const int32_t *var_ptr, const int32_t *var_canon, const float *x, float *y, int n,
                               hipStream_t s);
-// out[0] = sum_j energies[j] (fp64, fixed order), out[1] = sum_slots min(0, M[slot])
-hipError_t launch_bound_reduce(const float *energies, int64_t m, const float *M, int64_t slots, double *out,
-                               hipStream_t s);
+// *out = sum of x[0..n) (or of min(0, x) when neg_part), fp64, fixed order; partial holds
+// kSumBlocks doubles of scratch.
+constexpr int kSumBlocks = 1024;
+hipError_t launch_sum(const float *x, int64_t n, int neg_part, double *partial, double *out, hipStream_t s);
 // validity check of parameters: flags[0] |= omega outside [0,1] or non-finite, flags[1] |= alpha < 0 or non-finite
 hipError_t launch_check_params(const float *omega, const float *alpha, int64_t E, int32_t *flags, hipStream_t s);
 

@@ -116,6 +116,23 @@ def test_single_pass_parity_wide_and_narrow(orc):
     assert inst.stats["classes"] >= 2          # one-wave diagrams share a launch; 2-variable rows use another
 
 
+def test_single_pass_parity_every_team_size(orc):
+    """Rows whose diagram widths span every team size (1, 2, 4, ... 64 lanes per diagram)."""
+    rows = []
+    rng = np.random.default_rng(12)
+    n = 4000
+    for width_target in (2, 6, 12, 24, 48, 100, 200, 400, 900):
+        for _ in range(5):
+            k = int(rng.integers(8, 60))
+            cols = rng.choice(n, size=k, replace=False)
+            a = rng.integers(1, 4 * max(1, width_target // k) + 2, size=k)
+            rows.append((cols, a, -1, int(max(a.max(), min(width_target, a.sum() // 2)))))
+    p = synth.generators._from_rows(n, -rng.uniform(0, 1, size=n), rows, "team-sizes")
+    say(f"every team size E={p.nnz}")
+    inst = check_passes(orc, p, synth.sigmoid(rng.normal(size=p.nnz)), rng.normal(0, 0.2, size=p.nnz), 4, "teams")
+    assert inst.stats["classes"] >= 6
+
+
 def test_empty_and_single_variable_rows(orc):
     rows = [(np.array([0]), np.array([1]), -1, 1),          # x0 <= 1: vacuous single-variable row
             (np.array([], dtype=np.int64), np.array([], dtype=np.int64), -1, 0),   # empty row, feasible
