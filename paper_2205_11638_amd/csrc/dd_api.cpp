@@ -332,11 +332,11 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
             }
             return best;
         };
-        cl.wpb_f = pick(lds_words_fwd(P, cl.WB, cl.NL));
-        cl.wpb_b = pick(lds_words_bwd(P, cl.WB, cl.NL));
+        cl.wpb_f = pick(lds_words_pass(P, cl.WB, cl.NL));
+        cl.wpb_b = pick(lds_words_pass(P, cl.WB, cl.NL));
         if (!cl.wpb_f || !cl.wpb_b)
             return fail(DD_E_UNSUPPORTED, "LDS need %lld bytes per wave exceeds the budget",
-                        (long long)lds_words_fwd(P, cl.WB, cl.NL) * 4);
+                        (long long)lds_words_pass(P, cl.WB, cl.NL) * 4);
         hp.classes.push_back(cl);
         i = j;
     }

@@ -111,6 +111,12 @@ __device__ __forceinline__ bool in_level(int r, int R, int lane, int W) {
     return P < 64 || r < R - 1 || lane < W - r * 64;
 }
 
+// Per-level scalars of a tile: this team's width, the level's rows and first slot.
+struct Lev {
+    int W, R;
+    int64_t base;
+};
+
 template <int P, int RMAX, int MODE>
 __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
@@ -120,85 +126,82 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
     const int g = lane / P, p = lane % P;
     const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;  // uniform per wave
-    float *Fb = lds_f + (size_t)wave * (2 * WB * G + NL * (G + 1));
+    float *Fb = lds_f + (size_t)wave * lds_words_pass(P, WB, NL);
     float *Bst = Fb + WB * G;
     int *meta = (int *)(Bst + WB * G);
     int *off = meta + NL * G;
+    float *lamo = (float *)(off + NL);  // updated multipliers and M, flushed once per tile
+    float *Mo = lamo + NL * G;
     const TileCtx tc = tile_ctx(T, tile);
     preload_meta<G>(T, tc, lane, meta, off);
     const int nlev = tc.nlev;
-    auto Wof = [&](int l) {
-        const int w = l < nlev ? (meta[l * G + g] & 0xFFFF) : 0;
-        return G == 1 ? uni(w) : w;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l < nlev) {
+            const int w = meta[l * G + g] & 0xFFFF;
+            v.W = G == 1 ? uni(w) : w;
+            v.R = uni(meta[l * G] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
     };
-    auto Rof = [&](int l) { return uni(l < nlev ? (meta[l * G] >> 16) : 0); };
-    auto lev = [&](int l) { return tc.nbase + (int64_t)uni(off[l]); };
     const int mine = p * G + g;  // this lane's buffer index for k = p; row r adds r * P * G
 
+    Lev c0 = level(0), c1 = level(1), c2 = level(2);
     uint32_t tpn[RMAX];
     float bvn[RMAX];
-    float lamn = 0.f, omn = 0.f, aSn = 0.f;
-    {
-        const int R0 = Rof(0), R1 = Rof(1);
-        const uint32_t *tg = T.topo + lev(0);
-        const float *bg = T.B + (R1 ? lev(1) : 0);
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-            if (r < R0) tpn[r] = tg[r * 64 + lane];
-            if (UPD && r < R1) bvn[r] = bg[r * 64 + lane];
-        }
-        const int e = tc.ebase + g;
-        lamn = T.lam[e];
-        aSn = T.aS[e];
-        if (UPD) omn = T.omega[e];
+    for (int r = 0; r < RMAX; ++r) {
+        tpn[r] = r < c0.R ? T.topo[c0.base + r * 64 + lane] : 0u;
+        bvn[r] = (UPD && r < c1.R) ? T.B[c1.base + r * 64 + lane] : 0.f;
     }
+    float lamn = T.lam[tc.ebase + g], aSn = T.aS[tc.ebase + g], omn = UPD ? T.omega[tc.ebase + g] : 0.f;
     if (p == 0) Fb[g] = 0.f;  // F(root) = 0
     wave_sync();
     for (int l = 0; l < nlev; ++l) {
-        const int W = Wof(l), R = Rof(l), Wn = Wof(l + 1), Rn = Rof(l + 1);
         const float lam = lamn, om = omn, aS = aSn;
         uint32_t tp[RMAX];
         float fv[RMAX];
-        // read F of this level, clear the slots of the next level, stage B of the next level
+        // B of level l+1 (prefetched last hop) into LDS, with the terminals after it
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             tp[r] = tpn[r];
-            const int k = r * P + p, x = mine + r * P * G;
-            if (r < R) fv[r] = k < W ? Fb[x] : kInf;
-            if (r < Rn) {
-                Fb[x] = kInf;
-                if (UPD) Bst[x] = bvn[r];
-            }
+            if (UPD && r < c1.R) Bst[mine + r * P * G] = bvn[r];
         }
         if (UPD && p == 0) {
-            Bst[Wn * G + g] = kInf;       // 0-terminal
-            Bst[(Wn + 1) * G + g] = 0.f;  // 1-terminal
+            Bst[c1.W * G + g] = kInf;       // 0-terminal
+            Bst[(c1.W + 1) * G + g] = 0.f;  // 1-terminal
+        }
+        // F of this level: read, store for the backward pass, clear the slots of level l+1
+        float *fg = T.F + c0.base;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            const int k = r * P + p, x = mine + r * P * G;
+            if (r < c0.R) {
+                fv[r] = k < c0.W ? Fb[x] : kInf;
+                if (in_level<P>(r, c0.R, lane, c0.W)) fg[r * 64 + lane] = fv[r];
+            }
+            if (r < c1.R) Fb[x] = kInf;
         }
         wave_sync();
-        // prefetch: topology of level l+1, B of level l+2, edge data of level l+1
-        if (l + 1 < nlev) {
-            const int R2 = Rof(l + 2);
-            const uint32_t *tg = T.topo + lev(l + 1);
-            const float *bg = T.B + (R2 ? lev(l + 2) : 0);
+        // prefetch (issued after this hop's stores): topology of l+1, B of l+2, edge data of l+1
 #pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                if (r < Rn) tpn[r] = tg[r * 64 + lane];
-                if (UPD && r < R2) bvn[r] = bg[r * 64 + lane];
-            }
+        for (int r = 0; r < RMAX; ++r) {
+            tpn[r] = r < c1.R ? T.topo[c1.base + r * 64 + lane] : 0u;
+            bvn[r] = (UPD && r < c2.R) ? T.B[c2.base + r * 64 + lane] : 0.f;
+        }
+        if (l + 1 < nlev) {
             const int e = tc.ebase + (l + 1) * G + g;
             lamn = T.lam[e];
             aSn = T.aS[e];
             if (UPD) omn = T.omega[e];
         }
         float m0 = kInf, m1 = kInf;
-        float *fg = T.F + lev(l);
-        const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
+        const uint32_t dead = (uint32_t)c1.W | ((uint32_t)c1.W << 16);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            if (r < R) {
-                const bool ok = in_level<P>(r, R, lane, W);
-                if (!ok) tp[r] = dead;
-                if (ok) fg[r * 64 + lane] = fv[r];
+            if (r < c0.R) {
+                if (!in_level<P>(r, c0.R, lane, c0.W)) tp[r] = dead;
                 if (UPD) {
                     const float b0 = Bst[(int)(tp[r] & 0xFFFFu) * G + g];
                     const float b1 = Bst[(int)(tp[r] >> 16) * G + g];
@@ -212,14 +215,13 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
             m0 = team_min<P>(m0);
             m1 = team_min<P>(m1);
             lam_new = lam;
-            if (W > 0) {
+            if (c0.W > 0) {
                 m1 += lam;
                 const float Mn = om * (m1 - m0);
                 lam_new = lam - Mn + aS;
                 if (p == 0) {
-                    const int e = tc.ebase + l * G + g;
-                    T.lam[e] = lam_new;
-                    T.M[e] = Mn;
+                    lamo[l * G + g] = lam_new;
+                    Mo[l * G + g] = Mn;
                 }
             }
         } else {
@@ -227,63 +229,73 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
         }
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            if (r < R) {
+            if (r < c0.R) {
                 const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
-                if (lo < Wn) lds_fmin(&Fb[lo * G + g], fv[r]);
-                if (hi < Wn) lds_fmin(&Fb[hi * G + g], fv[r] + lam_new);
+                if (lo < c1.W) lds_fmin(&Fb[lo * G + g], fv[r]);
+                if (hi < c1.W) lds_fmin(&Fb[hi * G + g], fv[r] + lam_new);
             }
         }
         wave_sync();
+        c0 = c1;
+        c1 = c2;
+        c2 = level(l + 3);
+    }
+    if (UPD) {
+        for (int i = lane; i < nlev * G; i += 64) {
+            if (meta[i] & 0xFFFF) {
+                T.lam[tc.ebase + i] = lamo[i];
+                T.M[tc.ebase + i] = Mo[i];
+            }
+        }
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// Backward pass and sweeps.  X / Y alternate as B of level l+1 (read) and B of level l (written).
+// Backward pass and sweeps.  The two node buffers alternate as B of level l+1 (read) and B of
+// level l (written); B of a level goes to global memory at the start of the next hop, before
+// that hop's prefetch, so waiting for prefetched data never waits for a fresh store.
 // ------------------------------------------------------------------------------------------
 template <int P, int RMAX, int MODE>
 __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
     constexpr bool UPD = MODE == BWD_UPDATE, MM = MODE == BWD_MM;
-    constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM;
+    constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM, STOREB = UPD || MODE == BWD_STORE;
     extern __shared__ float lds_f[];
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int g = lane / P, p = lane % P;
     const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;
-    float *buf0 = lds_f + (size_t)wave * (2 * WB * G + NL * (G + 1));
+    float *buf0 = lds_f + (size_t)wave * lds_words_pass(P, WB, NL);
     int *meta = (int *)(buf0 + 2 * WB * G);
     int *off = meta + NL * G;
+    float *lamo = (float *)(off + NL);
+    float *Mo = lamo + NL * G;
     const TileCtx tc = tile_ctx(T, tile);
     const int row = T.bdd[tile * 64 + g];
     preload_meta<G>(T, tc, lane, meta, off);
     const int nlev = tc.nlev;
-    auto Wof = [&](int l) {
-        const int w = l < nlev ? (meta[l * G + g] & 0xFFFF) : 0;
-        return G == 1 ? uni(w) : w;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l >= 0 && l < nlev) {
+            const int w = meta[l * G + g] & 0xFFFF;
+            v.W = G == 1 ? uni(w) : w;
+            v.R = uni(meta[l * G] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
     };
-    auto Rof = [&](int l) { return uni(l < nlev ? (meta[l * G] >> 16) : 0); };
-    auto lev = [&](int l) { return tc.nbase + (int64_t)uni(off[l]); };
     const int mine = p * G + g;
 
+    Lev cn{0, 0, 0}, c0 = level(nlev - 1), cp = level(nlev - 2);  // levels l+1, l, l-1
     uint32_t tpn[RMAX];
     float fn[RMAX];
-    float lamn, omn = 0.f, aSn = 0.f;
-    {
-        const int lt = nlev - 1, Rt = Rof(lt);
-        const uint32_t *tg = T.topo + lev(lt);
-        const float *fg = T.F + lev(lt);
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-            if (r < Rt) {
-                tpn[r] = tg[r * 64 + lane];
-                if (NEEDF) fn[r] = fg[r * 64 + lane];
-            }
-        }
-        const int e = tc.ebase + lt * G + g;
-        lamn = T.lam[e];
-        if (UPD || BAR) aSn = T.aS[e];
-        if (UPD) omn = T.omega[e];
+    for (int r = 0; r < RMAX; ++r) {
+        tpn[r] = r < c0.R ? T.topo[c0.base + r * 64 + lane] : 0u;
+        fn[r] = (NEEDF && r < c0.R) ? T.F[c0.base + r * 64 + lane] : 0.f;
     }
+    const int et = tc.ebase + (nlev - 1) * G + g;
+    float lamn = T.lam[et], aSn = (UPD || BAR) ? T.aS[et] : 0.f, omn = UPD ? T.omega[et] : 0.f;
     int cur = 0;  // buffer holding B of level l+1 (terminals only, below the last level)
     if (p == 0) {
         buf0[g] = kInf;
@@ -291,40 +303,41 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
     }
     wave_sync();
     for (int l = nlev - 1; l >= 0; --l) {
-        const int W = Wof(l), R = Rof(l);
         const float lam = lamn, om = omn, aS = aSn;
         uint32_t tp[RMAX];
         float fv[RMAX];
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             tp[r] = tpn[r];
-            if (NEEDF) fv[r] = fn[r];
+            fv[r] = fn[r];
         }
-        if (l > 0) {  // prefetch level l-1
-            const int Rp = Rof(l - 1);
-            const uint32_t *tg = T.topo + lev(l - 1);
-            const float *fg = T.F + lev(l - 1);
+        const float *bn = buf0 + cur * WB * G;
+        float *bc = buf0 + (cur ^ 1) * WB * G;
+        // B of level l+1, computed last hop, to global memory
+        if (STOREB) {
+            float *bg = T.B + cn.base;
 #pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                if (r < Rp) {
-                    tpn[r] = tg[r * 64 + lane];
-                    if (NEEDF) fn[r] = fg[r * 64 + lane];
-                }
-            }
+            for (int r = 0; r < RMAX; ++r)
+                if (r < cn.R && in_level<P>(r, cn.R, lane, cn.W)) bg[r * 64 + lane] = bn[mine + r * P * G];
+        }
+        // prefetch level l-1
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            tpn[r] = r < cp.R ? T.topo[cp.base + r * 64 + lane] : 0u;
+            fn[r] = (NEEDF && r < cp.R) ? T.F[cp.base + r * 64 + lane] : 0.f;
+        }
+        if (l > 0) {
             const int e = tc.ebase + (l - 1) * G + g;
             lamn = T.lam[e];
             if (UPD || BAR) aSn = T.aS[e];
             if (UPD) omn = T.omega[e];
         }
-        const float *bn = buf0 + cur * WB * G;
-        float *bc = buf0 + (cur ^ 1) * WB * G;
         float m0 = kInf, m1 = kInf;
-        const int Wn = Wof(l + 1);
-        const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
+        const uint32_t dead = (uint32_t)cn.W | ((uint32_t)cn.W << 16);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            if (r < R) {
-                if (!in_level<P>(r, R, lane, W)) tp[r] = dead;
+            if (r < c0.R) {
+                if (!in_level<P>(r, c0.R, lane, c0.W)) tp[r] = dead;
                 if (NEEDF) {
                     // a lane past the level's end has two 0-terminal children: its cost is +inf
                     const float b0 = bn[(int)(tp[r] & 0xFFFFu) * G + g];
@@ -339,51 +352,66 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         if (NEEDF) {
             m0 = team_min<P>(m0);
             m1 = team_min<P>(m1);
-            if (W > 0) {
+            if (c0.W > 0) {
                 m1 += lam_use;
-                const int e = tc.ebase + l * G + g;
                 if (UPD) {
                     const float Mn = om * (m1 - m0);
                     lam_new = lam - Mn + aS;
                     if (p == 0) {
-                        T.lam[e] = lam_new;
-                        T.M[e] = Mn;
+                        lamo[l * G + g] = lam_new;
+                        Mo[l * G + g] = Mn;
                     }
                 } else if (p == 0) {
-                    const int ce = T.slot2canon[e];
+                    const int ce = T.slot2canon[tc.ebase + l * G + g];
                     T.out0[ce] = m0;
                     T.out1[ce] = m1;
                 }
             }
         }
-        float *bg = T.B + lev(l);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            if (r < R) {
+            if (r < c0.R) {
                 // child costs read again from LDS: cheaper than keeping 2 * RMAX registers live
-                const float b = fminf(bn[(int)(tp[r] & 0xFFFFu) * G + g], lam_new + bn[(int)(tp[r] >> 16) * G + g]);
-                bc[mine + r * P * G] = b;
-                if ((UPD || MODE == BWD_STORE) && in_level<P>(r, R, lane, W)) bg[r * 64 + lane] = b;
+                bc[mine + r * P * G] =
+                    fminf(bn[(int)(tp[r] & 0xFFFFu) * G + g], lam_new + bn[(int)(tp[r] >> 16) * G + g]);
             }
         }
         if (p == 0) {
-            bc[W * G + g] = kInf;
-            bc[(W + 1) * G + g] = 0.f;
+            bc[c0.W * G + g] = kInf;
+            bc[(c0.W + 1) * G + g] = 0.f;
         }
         wave_sync();
         cur ^= 1;
+        cn = c0;
+        c0 = cp;
+        cp = level(l - 2);
+    }
+    const float *bn = buf0 + cur * WB * G;  // B of level 0
+    if (STOREB) {
+        float *bg = T.B + cn.base;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+            if (r < cn.R && in_level<P>(r, cn.R, lane, cn.W)) bg[r * 64 + lane] = bn[mine + r * P * G];
     }
     if (!MM && p == 0 && row >= 0) {
-        const float e0 = buf0[cur * WB * G + g];  // B(root) = E^j at the multipliers swept
+        const float e0 = bn[g];  // B(root) = E^j at the multipliers swept
         if (MODE == BWD_EN_BAR) T.energies[row] = e0;
         else T.en_lam[row] = e0;
+    }
+    if (UPD) {
+        for (int i = lane; i < nlev * G; i += 64) {
+            if (meta[i] & 0xFFFF) {
+                T.lam[tc.ebase + i] = lamo[i];
+                T.M[tc.ebase + i] = Mo[i];
+            }
+        }
     }
 }
 
 template <int P, int RMAX>
 hipError_t fwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
     dim3 grid((unsigned)((c.ntiles + c.wpb_f - 1) / c.wpb_f)), block(64 * c.wpb_f);
-    size_t lds = (size_t)c.wpb_f * lds_words_fwd(P, c.WB, c.NL) * 4;
+    size_t lds = (size_t)c.wpb_f * lds_words_pass(P, c.WB, c.NL) * 4;
     if (mode == FWD_UPDATE)
         hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL);
     else
@@ -394,7 +422,7 @@ hipError_t fwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipS
 template <int P, int RMAX>
 hipError_t bwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
     dim3 grid((unsigned)((c.ntiles + c.wpb_b - 1) / c.wpb_b)), block(64 * c.wpb_b);
-    size_t lds = (size_t)c.wpb_b * lds_words_bwd(P, c.WB, c.NL) * 4;
+    size_t lds = (size_t)c.wpb_b * lds_words_pass(P, c.WB, c.NL) * 4;
     switch (mode) {
         case BWD_UPDATE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
         case BWD_STORE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_STORE>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;

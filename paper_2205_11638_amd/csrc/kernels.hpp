@@ -59,8 +59,10 @@ struct ClassLaunch {
 };
 
 // LDS words (4 bytes) one wavefront of the forward / backward pass kernels uses.
-inline int64_t lds_words_fwd(int P, int WB, int NL) { return 2LL * WB * (64 / P) + (int64_t)NL * ((64 / P) + 1); }
-inline int64_t lds_words_bwd(int P, int WB, int NL) { return 2LL * WB * (64 / P) + (int64_t)NL * ((64 / P) + 1); }
+// per wave: two node buffers (2 * WB * G), level table (NL * G + NL), staged lambda and M (2 * NL * G)
+constexpr int lds_words_pass(int P, int WB, int NL) {  // constexpr: usable in device code too
+    return 2 * WB * (64 / P) + NL * (3 * (64 / P) + 1);
+}
 
 hipError_t launch_fwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
 hipError_t launch_bwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
