@@ -18,6 +18,22 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def counted_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
+    against a plain copy), or None when the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "traffic_knapsack_2M_vars.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(HERE, "paper_2205_11638_amd", "csrc", "kernels.hip")
+    if rec.get("workload") != workload or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get(
+            "kernels_hip_sha256"):
+        return None
+    return rec["per_launch_bytes"].get(kernel)
 
 
 def log(*a):
@@ -143,7 +159,8 @@ def main():
         "config": {"workload": prob.name, "n": prob.n, "m": prob.m, "edges": prob.nnz, "nodes": int(st["nodes"]),
                    "arcs": arcs, "iterations_per_step": T, "step": "T dual iterations + lower bound"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(dom, prob.name),
+                     "algorithmic_bytes_per_launch": b_dom, "avg_launch_ms": tot_dom / n_dom},
         "hbm_frac_step": (sum(b * n for n, _, b in prof.values()) / args.steps) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "lower_bound": lb[0],
         "cpu_baseline": cpu,
