@@ -156,6 +156,38 @@ int dd_row_energies(dd_instance *h, float *E_out, void *stream);
 /* Min-marginals m^0, m^1 of every edge at lambda_bar (eq. 8), device arrays [edges]. */
 int dd_min_marginals(dd_instance *h, float *m0_out, float *m1_out, void *stream);
 
+/* Replace the costs c (device array [n], f32) and reset the solver (lambda = c/|J_i|, M = 0). */
+int dd_set_costs(dd_instance *h, const float *c, void *stream);
+
+/* ---- Reverse mode (Alg. 2, Prop. 2; loss = the dual objective, Sec. "Loss") ---------------- */
+
+/* Reset, then run T iterations of Alg. 1 keeping the state (lambda, M) every ckpt_every
+ * iterations (0: the instance default), and return the lower bound of the final state.
+ * Records what dd_backward needs; any later call that changes the state (a pass, reset,
+ * set_state, set_params, set_costs) invalidates the record. */
+int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream);
+
+/* Gradient of dlb * LB(after the recorded T iterations) with respect to omega, alpha and c:
+ * the seed dLB/dlambda_bar is the argmin assignment of every row (Sec. "Loss"), the flush
+ * lambda_bar = lambda + alpha*S is differentiated, then every pass in reverse with Alg. 2
+ * (each segment between checkpoints is recomputed; every pass is replayed bit for bit to
+ * recover its node costs), and finally lambda_0 = c/|J_i|; a variable in no row contributes
+ * dlb * [c_i < 0].  Subgradients at ties: lo arcs before hi arcs, lower node indices first.
+ * Outputs are device arrays (may be NULL): d_omega, d_alpha [edges] canonical, d_c [n].
+ * Leaves the solver at the final state.  DD_E_STATE without a valid record. */
+int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream);
+
+/* Alg. 2 applied to one whole pass (direction 0 forward, 1 backward): given the pass input
+ * (lam_in, M_in) and the adjoints of its outputs (dlam_out, dM_out), write the adjoints of the
+ * inputs (dlam_in, dM_in) and of alpha and omega (d_alpha, d_omega, not accumulated).  All
+ * device arrays [edges], canonical order.  The state is left at the pass output. */
+int dd_pass_vjp(dd_instance *h, int32_t direction, const float *lam_in, const float *M_in, const float *dlam_out,
+                const float *dM_out, float *dlam_in, float *dM_in, float *d_alpha, float *d_omega, void *stream);
+
+/* d_alpha_hat = VJP of alpha = softmax over J_i (dd_seg_softmax): alpha_e (d_alpha_e - sum_k alpha_k d_alpha_k).
+ * Device arrays [edges], canonical order. */
+int dd_seg_softmax_vjp(dd_instance *h, const float *alpha, const float *d_alpha, float *d_alpha_hat, void *stream);
+
 /* Nodes of each row's diagram, host array [m] (0 for an empty row). */
 int dd_row_nodes(const dd_instance *h, int64_t *nodes_out);
 

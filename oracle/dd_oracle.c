@@ -142,36 +142,49 @@ static double energy(const row_t *r, const double *lam, double *Q) {
     return Q[-r->smin];
 }
 
+/* Smallest relative gap between the two options of any decision taken so far (a diagnostic:
+ * where it is tiny the minimizer is not unique up to rounding, so any subgradient is valid). */
+static void note_gap(double *gap, double a, double b) {
+    if (!gap || a == INF || b == INF) return;
+    double d = fabs(a - b), s = fmax(fmax(fabs(a), fabs(b)), 1e-300);
+    if (d / s < *gap) *gap = d / s;
+}
+
 /* Minimizer of <lam, x> over X_j with x_l = beta (l = -1: unconstrained), written to x[0..L).
- * Ties: lowest partial sum, then x_p = 0 before x_p = 1. */
+ * Ties: lowest partial sum, then x_p = 0 before x_p = 1.  gap (may be NULL): see note_gap. */
 static void minimizer(const row_t *r, const double *lam, const double *P, const double *Q, int l, int beta,
-                      int8_t *x) {
+                      int8_t *x, double *gap) {
     int64_t s;
     if (l < 0) {
         s = 0;
         for (int p = 0; p < r->L; ++p) {
             double x0 = at(r, Q, p + 1, s), x1 = lam[p] + at(r, Q, p + 1, s + r->a[p]);
+            note_gap(gap, x0, x1);
             x[p] = x0 <= x1 ? 0 : 1;
             if (x[p]) s += r->a[p];
         }
         return;
     }
-    double best = INF; int64_t sb = 0;
+    double best = INF, second = INF; int64_t sb = 0;
     for (int k = 0; k < r->W; ++k) {
         int64_t ss = r->smin + k;
         double v = at(r, P, l, ss) + (beta ? lam[l] : 0.0) + at(r, Q, l + 1, ss + (beta ? r->a[l] : 0));
-        if (v < best) { best = v; sb = ss; }
+        if (v < best) { second = best; best = v; sb = ss; }
+        else if (v < second) second = v;
     }
+    note_gap(gap, best, second);
     x[l] = (int8_t)beta;
     s = sb;
     for (int p = l - 1; p >= 0; --p) {           /* back through the prefix table */
         double x0 = at(r, P, p, s), x1 = at(r, P, p, s - r->a[p]) + lam[p];
+        note_gap(gap, x0, x1);
         x[p] = x0 <= x1 ? 0 : 1;
         if (x[p]) s -= r->a[p];
     }
     s = sb + (beta ? r->a[l] : 0);
     for (int p = l + 1; p < r->L; ++p) {         /* forward through the suffix table */
         double x0 = at(r, Q, p + 1, s), x1 = lam[p] + at(r, Q, p + 1, s + r->a[p]);
+        note_gap(gap, x0, x1);
         x[p] = x0 <= x1 ? 0 : 1;
         if (x[p]) s += r->a[p];
     }
@@ -397,7 +410,7 @@ int orc_min_marginals(int m, const int64_t *row_ptr, const int32_t *col, const i
 
 /* Minimizing assignment of every row at lam (the supergradient of (D), Sec. "Loss"). */
 int orc_argmin(int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
-               const int64_t *rhs, const double *lam, int8_t *x, int nthreads) {
+               const int64_t *rhs, const double *lam, int8_t *x, double *gap, int nthreads) {
     size_t tab;
     max_table(m, row_ptr, coef, &tab);
     set_threads(nthreads);
@@ -412,7 +425,7 @@ int orc_argmin(int m, const int64_t *row_ptr, const int32_t *col, const int32_t 
             int st = row_init(&r, (int)(row_ptr[j + 1] - b), col + b, coef + b, sense[j], rhs[j]);
             if (st == ORC_OK) {
                 suffix_table(&r, lam + b, Q);
-                minimizer(&r, lam + b, NULL, Q, -1, 0, x + b);
+                minimizer(&r, lam + b, NULL, Q, -1, 0, x + b, gap ? gap + j : NULL);
             } else {
 #pragma omp critical
                 status = st;
@@ -433,7 +446,7 @@ int orc_argmin(int m, const int64_t *row_ptr, const int32_t *col, const int32_t 
 static int row_pass_vjp(const row_t *r, int dir, const double *omega, const double *alpha, const double *S,
                         const double *lam_in, const double *lam_out, const double *dlam_out, const double *dM_out,
                         double *dlam_in, double *gS, double *d_alpha, double *d_omega, double *P, double *Q,
-                        double *lam_h, double *ad_new, int8_t *x0, int8_t *x1) {
+                        double *lam_h, double *ad_new, int8_t *x0, int8_t *x1, double *gap) {
     const int L = r->L;
     for (int p = 0; p < L; ++p) { ad_new[p] = dlam_out[p]; dlam_in[p] = 0.0; }
     for (int h = L - 1; h >= 0; --h) {
@@ -454,8 +467,8 @@ static int row_pass_vjp(const row_t *r, int dir, const double *omega, const doub
         marginals(r, P, Q, lam_h, l, &m0, &m1);
         if (m0 == INF || m1 == INF) return ORC_E_FORCED;
         d_omega[l] += Mt * (m1 - m0);  /* dM_new * M_new / omega, written without the division */
-        minimizer(r, lam_h, P, Q, l, 0, x0);
-        minimizer(r, lam_h, P, Q, l, 1, x1);
+        minimizer(r, lam_h, P, Q, l, 0, x0, gap);
+        minimizer(r, lam_h, P, Q, l, 1, x1, gap);
         double k = omega[l] * Mt;
         for (int p = 0; p < L; ++p) {
             double d = k * (double)(x1[p] - x0[p]);
@@ -469,11 +482,12 @@ static int row_pass_vjp(const row_t *r, int dir, const double *omega, const doub
 }
 
 /* VJP of one full pass.  lam_in/M_in: pass input; the pass is re-run here to get lam_out.
- * Outputs dlam_in[E], dM_in[E]; d_alpha[E], d_omega[E] are accumulated (+=). */
+ * Outputs dlam_in[E], dM_in[E]; d_alpha[E], d_omega[E] are accumulated (+=).
+ * row_gap (may be NULL): per row, the smallest relative gap of its minimizer decisions. */
 int orc_pass_vjp(int n, int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
                  const int64_t *rhs, const double *omega, const double *alpha, int dir, const double *lam_in,
                  const double *M_in, const double *dlam_out, const double *dM_out, double *dlam_in, double *dM_in,
-                 double *d_alpha, double *d_omega, int nthreads) {
+                 double *d_alpha, double *d_omega, double *row_gap, int nthreads) {
     int64_t E = row_ptr[m];
     size_t nE = (size_t)(E > 0 ? E : 1);
     double *Sv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
@@ -503,10 +517,11 @@ int orc_pass_vjp(int n, int m, const int64_t *row_ptr, const int32_t *col, const
             row_t r;
             int64_t b = row_ptr[j];
             int st = row_init(&r, (int)(row_ptr[j + 1] - b), col + b, coef + b, sense[j], rhs[j]);
+            if (row_gap) row_gap[j] = INF;
             if (st == ORC_OK)
                 st = row_pass_vjp(&r, dir, omega + b, alpha + b, Se + b, lam_in + b, lam_out + b, dlam_out + b,
                                   dM_out + b, dlam_in + b, gS + b, d_alpha + b, d_omega + b, P, Q, lam_h, ad_new, x0,
-                                  x1);
+                                  x1, row_gap ? row_gap + j : NULL);
             if (st) {
 #pragma omp critical
                 status = st;
@@ -532,7 +547,7 @@ done:
 int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef,
                       const int8_t *sense, const int64_t *rhs, const double *c, const double *omega,
                       const double *alpha, int T, double *lb_out, double *d_omega, double *d_alpha, double *d_c,
-                      int nthreads) {
+                      double *min_gap, int nthreads) {
     int64_t E = row_ptr[m];
     size_t nE = (size_t)(E > 0 ? E : 1);
     int npass = 2 * T;
@@ -547,6 +562,8 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
     double *Se = (double *)malloc(sizeof(double) * nE);
     int8_t *x = (int8_t *)malloc(nE);
     int64_t *deg = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    double *gaps = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
+    if (min_gap) *min_gap = INF;
     int st = orc_init_lambda(n, c, E, col, lam);
     for (int p = 0; p < npass && st == ORC_OK; ++p) {
         memcpy(lam + nE * (p + 1), lam + nE * p, sizeof(double) * (size_t)E);
@@ -559,8 +576,10 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
     st = orc_lower_bound(n, m, row_ptr, col, coef, sense, rhs, c, alpha, lam + nE * npass, M + nE * npass, lb_out,
                          &dlv, lam_bar, nthreads);
     if (st) goto done;
-    st = orc_argmin(m, row_ptr, col, coef, sense, rhs, lam_bar, x, nthreads);
+    for (int j = 0; j < m; ++j) gaps[j] = INF;
+    st = orc_argmin(m, row_ptr, col, coef, sense, rhs, lam_bar, x, gaps, nthreads);
     if (st) goto done;
+    for (int j = 0; j < m && min_gap; ++j) *min_gap = fmin(*min_gap, gaps[j]);
     for (int64_t e = 0; e < E; ++e) { d_alpha[e] = 0.0; d_omega[e] = 0.0; }
     /* flush adjoint: lambda_bar_e = lambda_e + alpha_e S_i */
     deferred_sums(n, E, col, M + nE * npass, Sv, Se);
@@ -573,7 +592,8 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
     for (int64_t e = 0; e < E; ++e) dM[e] = Sv[col[e]];
     for (int p = npass - 1; p >= 0 && st == ORC_OK; --p) {
         st = orc_pass_vjp(n, m, row_ptr, col, coef, sense, rhs, omega, alpha, p % 2, lam + nE * p, M + nE * p, dl, dM,
-                          dl2, dM2, d_alpha, d_omega, nthreads);
+                          dl2, dM2, d_alpha, d_omega, gaps, nthreads);
+        for (int j = 0; j < m && min_gap; ++j) *min_gap = fmin(*min_gap, gaps[j]);
         double *t;
         t = dl; dl = dl2; dl2 = t;
         t = dM; dM = dM2; dM2 = t;
@@ -584,7 +604,7 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
     for (int64_t e = 0; e < E; ++e) d_c[col[e]] += dl[e] / (double)deg[col[e]];
 done:
     free(lam); free(M); free(lam_bar); free(dl); free(dM); free(dl2); free(dM2); free(Sv); free(Se); free(x);
-    free(deg);
+    free(deg); free(gaps);
     return st;
 }
 

@@ -179,32 +179,38 @@ def min_marginals(prob, lam, threads=0):
     return m0, m1
 
 
-def argmin(prob, lam, threads=0):
+def argmin(prob, lam, threads=0, with_gap=False):
+    """Minimizing assignment of every row; with_gap also returns each row's smallest relative
+    gap between the two options of a decision (tiny gap: the minimizer is not unique up to rounding)."""
     lib = _load()
     keep, pa = _prob_args(prob)
     lam = _f64(lam, prob.nnz)
     x = np.empty(prob.nnz, dtype=np.int8)
-    _check(lib.orc_argmin(C.c_int(prob.m), *pa, _p(lam, C.c_double), _p(x, C.c_int8), C.c_int(threads)), "argmin")
-    return x
+    gap = np.full(max(prob.m, 1), np.inf)
+    _check(lib.orc_argmin(C.c_int(prob.m), *pa, _p(lam, C.c_double), _p(x, C.c_int8), _p(gap, C.c_double),
+                          C.c_int(threads)), "argmin")
+    return (x, gap[:prob.m]) if with_gap else x
 
 
-def pass_vjp(prob, omega, alpha, direction, lam_in, M_in, dlam_out, dM_out, threads=0):
-    """Alg. 2 over one pass. Returns (dlam_in, dM_in, d_alpha, d_omega)."""
+def pass_vjp(prob, omega, alpha, direction, lam_in, M_in, dlam_out, dM_out, threads=0, with_gap=False):
+    """Alg. 2 over one pass. Returns (dlam_in, dM_in, d_alpha, d_omega) [+ per-row minimizer gap]."""
     lib = _load()
     keep, pa = _prob_args(prob)
     E = prob.nnz
     om, al = _f64(omega, E), _f64(alpha, E)
     li, mi, dlo, dmo = _f64(lam_in, E), _f64(M_in, E), _f64(dlam_out, E), _f64(dM_out, E)
     dli, dmi, da, dw = np.empty(E), np.empty(E), np.zeros(E), np.zeros(E)
+    gap = np.full(max(prob.m, 1), np.inf)
     _check(lib.orc_pass_vjp(C.c_int(prob.n), C.c_int(prob.m), *pa, _p(om, C.c_double), _p(al, C.c_double),
                             C.c_int(direction), _p(li, C.c_double), _p(mi, C.c_double), _p(dlo, C.c_double),
                             _p(dmo, C.c_double), _p(dli, C.c_double), _p(dmi, C.c_double), _p(da, C.c_double),
-                            _p(dw, C.c_double), C.c_int(threads)), "pass_vjp")
-    return dli, dmi, da, dw
+                            _p(dw, C.c_double), _p(gap, C.c_double), C.c_int(threads)), "pass_vjp")
+    return (dli, dmi, da, dw, gap[:prob.m]) if with_gap else (dli, dmi, da, dw)
 
 
-def unrolled_grad(prob, omega, alpha, T, threads=0):
-    """LB after T iterations from the default start and its gradient w.r.t. (omega, alpha, c)."""
+def unrolled_grad(prob, omega, alpha, T, threads=0, with_gap=False):
+    """LB after T iterations from the default start and its gradient w.r.t. (omega, alpha, c)
+    [+ the smallest relative gap of any minimizer decision taken on the way]."""
     lib = _load()
     keep, pa = _prob_args(prob)
     E = prob.nnz
@@ -212,10 +218,11 @@ def unrolled_grad(prob, omega, alpha, T, threads=0):
     om, al = _f64(omega, E), _f64(alpha, E)
     lb = C.c_double()
     dw, da, dc = np.empty(E), np.empty(E), np.empty(prob.n)
+    gap = C.c_double()
     _check(lib.orc_unrolled_grad(C.c_int(prob.n), C.c_int(prob.m), *pa, _p(c, C.c_double), _p(om, C.c_double),
                                  _p(al, C.c_double), C.c_int(T), C.byref(lb), _p(dw, C.c_double), _p(da, C.c_double),
-                                 _p(dc, C.c_double), C.c_int(threads)), "unrolled_grad")
-    return lb.value, dw, da, dc
+                                 _p(dc, C.c_double), C.byref(gap), C.c_int(threads)), "unrolled_grad")
+    return (lb.value, dw, da, dc, gap.value) if with_gap else (lb.value, dw, da, dc)
 
 
 def lb_after(prob, omega, alpha, T, c=None, threads=0):

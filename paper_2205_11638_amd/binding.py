@@ -74,6 +74,11 @@ SIGNATURES = {
     "dd_row_energies": ([_VP, _VP, _VP], C.c_int),
     "dd_min_marginals": ([_VP, _VP, _VP, _VP], C.c_int),
     "dd_row_nodes": ([_VP, _VP], C.c_int),
+    "dd_set_costs": ([_VP, _VP, _VP], C.c_int),
+    "dd_forward_unrolled": ([_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), _VP], C.c_int),
+    "dd_backward": ([_VP, C.c_double, _VP, _VP, _VP, _VP], C.c_int),
+    "dd_pass_vjp": ([_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
+    "dd_seg_softmax_vjp": ([_VP, _VP, _VP, _VP, _VP], C.c_int),
     "dd_profile_begin": ([_VP, C.c_int32], C.c_int),
     "dd_profile_end": ([_VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "dd_compile_row": ([C.POINTER(dd_problem), C.c_int32, _VP, _VP, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
@@ -250,3 +255,32 @@ class Instance:
         _check(self._L.dd_profile_end(self._h, C.cast(arr, C.c_void_p), cap, C.byref(cnt)))
         return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms), float(arr[i].bytes_per_launch))
                 for i in range(min(cnt.value, cap))}
+
+    def set_costs(self, c):
+        import torch
+        _check(self._L.dd_set_costs(self._h, _dptr(c, torch.float32, self.n), _stream()))
+
+    def forward_unrolled(self, T, ckpt_every=0):
+        lb = C.c_double()
+        _check(self._L.dd_forward_unrolled(self._h, int(T), int(ckpt_every), C.byref(lb), _stream()))
+        return lb.value
+
+    def backward(self, dlb=1.0):
+        """(d_omega [E], d_alpha [E], d_c [n]) of dlb * LB of the recorded unrolled forward."""
+        dw, da, dc = self._f32(self.E), self._f32(self.E), self._f32(self.n)
+        _check(self._L.dd_backward(self._h, float(dlb), _dptr(dw), _dptr(da), _dptr(dc), _stream()))
+        return dw, da, dc
+
+    def pass_vjp(self, direction, lam_in, M_in, dlam_out, dM_out):
+        import torch
+        outs = [self._f32(self.E) for _ in range(4)]
+        args = [_dptr(t, torch.float32, self.E) for t in (lam_in, M_in, dlam_out, dM_out)]
+        _check(self._L.dd_pass_vjp(self._h, int(direction), *args, *[_dptr(o) for o in outs], _stream()))
+        return tuple(outs)  # dlam_in, dM_in, d_alpha, d_omega
+
+    def seg_softmax_vjp(self, alpha, d_alpha):
+        import torch
+        out = self._f32(self.E)
+        _check(self._L.dd_seg_softmax_vjp(self._h, _dptr(alpha, torch.float32, self.E),
+                                          _dptr(d_alpha, torch.float32, self.E), _dptr(out), _stream()))
+        return out

@@ -1,0 +1,537 @@
+// adjoint.hip -- reverse mode of the dual iteration (Alg. 2, Prop. 2) on CDNA4 (gfx950).
+//
+// One pass of Alg. 1 on a diagram, seen as a computation graph (forward pass shown; the
+// backward pass is its mirror image): B_{l+1} from the pass-input multipliers, then per hop l
+//     m^beta_l = min_v F_l(v) + beta*lambda_l + B_{l+1}(child_beta v)           (eq. 8)
+//     M_l = omega_l (m^1_l - m^0_l),  lambda'_l = lambda_l - M_l + alpha_l S_i    (Alg. 1)
+//     F_{l+1}(w) = min over arcs (v, beta) -> w of F_l(v) + beta*lambda'_l.
+// Reverse mode replaces every min by its argmin (App. B, backpropagation paragraph):
+//   * the "update side" (F for a forward pass) is swept against the pass order and carries
+//     the BlockUpdate adjoint of Alg. 2 at each hop: lambda'-dot collects the adjoint of the
+//     hi arcs that won a min of the next level, dM = dM_out - dlambda', d_omega += dM (m1 - m0),
+//     d_alpha += dlambda' S, dm^1 = omega dM = -dm^0 routed to the argmin node of each
+//     min-marginal and to its child on the other side;
+//   * the "fixed side" (B for a forward pass, computed from the pass-input multipliers) is swept
+//     afterwards and routes what reached it to the pass-input multipliers.
+// Minimum propagation comes in two forms: pull (B_l(v) = min over its two children: each node
+// picks its argmin child, lo on ties) and push (F_{l+1}(w) = min over its parents: every
+// parent arc whose value equals F_{l+1}(w) bids with (node index, lo before hi) in LDS and the
+// lowest bid wins, so each minimum has exactly one argmin).  Argmin tests are exact float
+// equalities: the stored costs and the recomputed candidates come from the same expressions.
+// Contributions from one sweep to the other side travel as per-edge records
+// (two node indices, two values), not as a dense per-node array.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace dd {
+namespace {
+
+using namespace dev;
+
+struct AdjEdge {
+    float lam_use;   // multiplier on the hi arcs of the swept side
+    float lam_old;   // pass-input multiplier (update sweeps)
+    float dlo, dMo;  // adjoints of the pass outputs (update sweeps)
+    float om, al, S;
+};
+
+template <bool UPD>
+__device__ __forceinline__ AdjEdge adj_edge(const DevTables &T, const AdjTables &A, int e, bool valid, bool bar) {
+    AdjEdge x{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (!valid) return x;
+    if (UPD) {
+        x.lam_use = T.lam[e];  // after the replayed pass: the updated multipliers
+        x.lam_old = A.lam_in[e];
+        x.dlo = A.dlam_out[e];
+        x.dMo = A.dM_out[e];
+        x.om = T.omega[e];
+        x.al = T.alpha[e];
+        x.S = T.S[T.evar[e]];
+    } else {
+        x.lam_use = A.lam_src[e];
+        if (bar) x.lam_use = x.lam_use + T.aS[e];
+    }
+    return x;
+}
+
+// ------------------------------------------------------------------------------------------
+// Push-form sweep (F side), against the level order: l = L-1 .. 0.
+// LDS per wave: Fv[2], Fa[2] (cost and adjoint of levels l+1 / l), bid (ints), Bst (B of the
+// level below, update sweeps), then the level table.
+// ------------------------------------------------------------------------------------------
+template <int P, int RMAX, bool UPD>
+__global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int WB,
+                                               int NL) {
+    constexpr int G = 64 / P;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int g = lane / P, p = lane % P;
+    const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;
+    float *Fv = lds_f + (size_t)wave * lds_words_adj_F(P, WB, NL);
+    float *Fa = Fv + 2 * WB * G;
+    int *bid = (int *)(Fa + 2 * WB * G);
+    float *Bst = (float *)(bid + WB * G);
+    int *meta = (int *)(Bst + WB * G);
+    int *off = meta + NL * G;
+    const TileCtx tc = tile_ctx(T, tile);
+    preload_meta<G>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l < nlev) {
+            const int w = meta[l * G + g] & 0xFFFF;
+            v.W = G == 1 ? uni(w) : w;
+            v.R = uni(meta[l * G] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
+    };
+    const int mine = p * G + g;
+    int cur = 0;     // Fv/Fa[cur]: level l+1
+    Lev c1{0, 0, 0};  // level l+1 (terminals only below the last level)
+    for (int l = nlev - 1; l >= 0; --l) {
+        const Lev c0 = level(l);
+        const int Wn = c1.W;
+        const int e = tc.ebase + l * G + g;
+        const AdjEdge x = adj_edge<UPD>(T, A, e, c0.W > 0, false);
+        const float *fv1 = Fv + cur * WB * G, *fa1 = Fa + cur * WB * G;
+        float *fv0 = Fv + (cur ^ 1) * WB * G, *fa0 = Fa + (cur ^ 1) * WB * G;
+        uint32_t tp[RMAX];
+        float fv[RMAX];
+        const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
+        const uint32_t *tg = T.topo + c0.base;
+        const float *fg = T.F + c0.base;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < c0.R) {
+                const bool ok = in_level<P>(r, c0.R, lane, c0.W);
+                tp[r] = ok ? tg[r * 64 + lane] : dead;
+                fv[r] = ok ? fg[r * 64 + lane] : kInf;
+            }
+        }
+        if (UPD) {  // B of level l+1 with the terminals after it
+            const float *bg = T.B + c1.base;
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r)
+                if (r < c1.R) Bst[mine + r * P * G] = bg[r * 64 + lane];
+            if (p == 0) {
+                Bst[Wn * G + g] = kInf;
+                Bst[(Wn + 1) * G + g] = 0.f;
+            }
+        }
+        wave_sync();
+        // bids for the argmin parent arc of every node of level l+1
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < c0.R) {
+                const int k = r * P + p, lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
+                if (lo < Wn && fv[r] == fv1[lo * G + g]) lds_imin(&bid[lo * G + g], 2 * k);
+                if (hi < Wn && fv[r] + x.lam_use == fv1[hi * G + g]) lds_imin(&bid[hi * G + g], 2 * k + 1);
+            }
+        }
+        wave_sync();
+        float acc[RMAX];
+        float hisum = 0.f;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            acc[r] = 0.f;
+            if (r < c0.R) {
+                const int k = r * P + p, lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
+                if (lo < Wn && bid[lo * G + g] == 2 * k) acc[r] += fa1[lo * G + g];
+                if (hi < Wn && bid[hi * G + g] == 2 * k + 1) {
+                    const float c = fa1[hi * G + g];
+                    acc[r] += c;
+                    hisum += c;
+                }
+            }
+        }
+        hisum = team_sum<P>(hisum);
+        if (UPD) {
+            // min-marginals of this hop again (same expressions as the pass), then their argmins
+            float m0 = kInf, m1 = kInf;
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                if (r < c0.R) {
+                    m0 = fminf(m0, fv[r] + Bst[(int)(tp[r] & 0xFFFFu) * G + g]);
+                    m1 = fminf(m1, fv[r] + Bst[(int)(tp[r] >> 16) * G + g]);
+                }
+            }
+            m0 = team_min<P>(m0);
+            m1 = team_min<P>(m1);
+            int k0 = INT_MAX, k1 = INT_MAX;
+#pragma unroll
+            for (int r = RMAX - 1; r >= 0; --r) {
+                if (r < c0.R) {
+                    const int k = r * P + p;
+                    if (fv[r] + Bst[(int)(tp[r] & 0xFFFFu) * G + g] == m0) k0 = k;
+                    if (fv[r] + Bst[(int)(tp[r] >> 16) * G + g] == m1) k1 = k;
+                }
+            }
+            k0 = team_min_i<P>(k0);
+            k1 = team_min_i<P>(k1);
+            // children of the two argmin nodes (for the record of the fixed-side sweep)
+            int ch0 = INT_MAX, ch1 = INT_MAX;
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                if (r < c0.R) {
+                    const int k = r * P + p;
+                    if (k == k0) ch0 = (int)(tp[r] & 0xFFFFu);
+                    if (k == k1) ch1 = (int)(tp[r] >> 16);
+                }
+            }
+            ch0 = team_min_i<P>(ch0);
+            ch1 = team_min_i<P>(ch1);
+            if (c0.W > 0) {
+                const float dlam_new = x.dlo + hisum;
+                const float dM = x.dMo - dlam_new;
+                const float diff = (m1 + x.lam_old) - m0;  // m^1 - m^0 as the pass formed it
+                const float dm1 = x.om * dM, dm0 = -dm1;
+                if (p == 0) {
+                    A.dlam_in[e] = dlam_new + dm1;  // identity path + the hi arc of m^1 itself
+                    A.g[e] = dlam_new * x.al;
+                    A.dalpha[e] += dlam_new * x.S;
+                    A.domega[e] += dM * diff;
+                    A.rec_idx[2 * e] = ch0 < Wn ? ch0 : -1;
+                    A.rec_idx[2 * e + 1] = ch1 < Wn ? ch1 : -1;
+                    A.rec_val[2 * e] = dm0;
+                    A.rec_val[2 * e + 1] = dm1;
+                }
+#pragma unroll
+                for (int r = 0; r < RMAX; ++r) {
+                    const int k = r * P + p;
+                    if (k == k0) acc[r] += dm0;
+                    if (k == k1) acc[r] += dm1;
+                }
+            }
+        } else if (c0.W > 0) {
+            if (p == 0) A.dlam_in[e] += hisum;
+            // argmin contributions of the update sweep to F_l (record of edge l)
+            const int i0 = A.rec_idx[2 * e], i1 = A.rec_idx[2 * e + 1];
+            const float v0 = A.rec_val[2 * e], v1 = A.rec_val[2 * e + 1];
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                const int k = r * P + p;
+                if (k == i0) acc[r] += v0;
+                if (k == i1) acc[r] += v1;
+            }
+        }
+        wave_sync();  // every bid has been read before the buffer is reset for level l
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < c0.R) {
+                const int xi = mine + r * P * G;
+                fa0[xi] = acc[r];
+                fv0[xi] = fv[r];
+                bid[xi] = INT_MAX;
+            }
+        }
+        wave_sync();
+        cur ^= 1;
+        c1 = c0;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Pull-form sweep (B side), along the level order: l = 0 .. L-1.
+// LDS per wave: Bst (B of level l+1), Ba[2] (adjoints of levels l / l+1), level table.
+// seed != 0: the adjoint of B(root) is `seed` (the lower bound's own gradient).
+// ------------------------------------------------------------------------------------------
+template <int P, int RMAX, bool UPD>
+__global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int WB,
+                                               int NL, int bar, int recs, float seed) {
+    constexpr int G = 64 / P;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int g = lane / P, p = lane % P;
+    const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;
+    float *Bst = lds_f + (size_t)wave * lds_words_adj_B(P, WB, NL);
+    float *Ba = Bst + WB * G;
+    int *meta = (int *)(Ba + 2 * WB * G);
+    int *off = meta + NL * G;
+    const TileCtx tc = tile_ctx(T, tile);
+    preload_meta<G>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l < nlev) {
+            const int w = meta[l * G + g] & 0xFFFF;
+            v.W = G == 1 ? uni(w) : w;
+            v.R = uni(meta[l * G] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
+    };
+    const int mine = p * G + g;
+    int cur = 0;  // Ba[cur]: level l
+    {
+        const int R0 = uni(meta[0] >> 16);
+        for (int r = 0; r < R0; ++r) Ba[mine + r * P * G] = 0.f;
+        if (p == 0) Ba[g] = seed;  // the root is node 0 of level 0
+    }
+    Lev c0 = level(0);
+    for (int l = 0; l < nlev; ++l) {
+        const Lev c1 = level(l + 1);
+        const int Wn = c1.W;
+        const int e = tc.ebase + l * G + g;
+        const AdjEdge x = adj_edge<UPD>(T, A, e, c0.W > 0, bar != 0);
+        float *ba0 = Ba + cur * WB * G, *ba1 = Ba + (cur ^ 1) * WB * G;
+        // fixed side: argmin contributions of the update sweep to B_l (record of edge l-1)
+        if (!UPD && recs && l > 0 && p == 0) {
+            const int ep = e - G;
+            if (level(l - 1).W > 0) {
+                const int i0 = A.rec_idx[2 * ep], i1 = A.rec_idx[2 * ep + 1];
+                if (i0 >= 0) ba0[i0 * G + g] += A.rec_val[2 * ep];
+                if (i1 >= 0) ba0[i1 * G + g] += A.rec_val[2 * ep + 1];
+            }
+        }
+        const float *bg = T.B + c1.base;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < c1.R) {
+                Bst[mine + r * P * G] = bg[r * 64 + lane];
+                ba1[mine + r * P * G] = 0.f;
+            }
+        }
+        if (p == 0) {
+            Bst[Wn * G + g] = kInf;
+            Bst[(Wn + 1) * G + g] = 0.f;
+        }
+        uint32_t tp[RMAX];
+        float fv[RMAX];
+        const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
+        const uint32_t *tg = T.topo + c0.base;
+        const float *fg = T.F + c0.base;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < c0.R) {
+                const bool ok = in_level<P>(r, c0.R, lane, c0.W);
+                tp[r] = ok ? tg[r * 64 + lane] : dead;
+                if (UPD) fv[r] = ok ? fg[r * 64 + lane] : kInf;
+            }
+        }
+        wave_sync();
+        float hisum = 0.f;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < c0.R) {
+                const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
+                const float b0 = Bst[lo * G + g], b1 = x.lam_use + Bst[hi * G + g];
+                const float d = ba0[mine + r * P * G];
+                const bool take_hi = b1 < b0;  // the pass formed min(b0, b1): lo on ties
+                const int ch = take_hi ? hi : lo;
+                if (ch < Wn) lds_fadd(&ba1[ch * G + g], d);
+                if (take_hi) hisum += d;
+            }
+        }
+        hisum = team_sum<P>(hisum);
+        if (UPD) {
+            float m0 = kInf, m1 = kInf;
+#pragma unroll
+            for (int r = 0; r < RMAX; ++r) {
+                if (r < c0.R) {
+                    m0 = fminf(m0, fv[r] + Bst[(int)(tp[r] & 0xFFFFu) * G + g]);
+                    m1 = fminf(m1, fv[r] + Bst[(int)(tp[r] >> 16) * G + g]);
+                }
+            }
+            m0 = team_min<P>(m0);
+            m1 = team_min<P>(m1);
+            int k0 = INT_MAX, k1 = INT_MAX;
+#pragma unroll
+            for (int r = RMAX - 1; r >= 0; --r) {
+                if (r < c0.R) {
+                    const int k = r * P + p;
+                    if (fv[r] + Bst[(int)(tp[r] & 0xFFFFu) * G + g] == m0) k0 = k;
+                    if (fv[r] + Bst[(int)(tp[r] >> 16) * G + g] == m1) k1 = k;
+                }
+            }
+            k0 = team_min_i<P>(k0);
+            k1 = team_min_i<P>(k1);
+            if (c0.W > 0) {
+                const float dlam_new = x.dlo + hisum;
+                const float dM = x.dMo - dlam_new;
+                const float diff = (m1 + x.lam_old) - m0;
+                const float dm1 = x.om * dM, dm0 = -dm1;
+#pragma unroll
+                for (int r = 0; r < RMAX; ++r) {
+                    if (r < c0.R) {
+                        const int k = r * P + p;
+                        const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
+                        if (k == k0 && lo < Wn) lds_fadd(&ba1[lo * G + g], dm0);
+                        if (k == k1 && hi < Wn) lds_fadd(&ba1[hi * G + g], dm1);
+                    }
+                }
+                if (p == 0) {
+                    A.dlam_in[e] = dlam_new + dm1;
+                    A.g[e] = dlam_new * x.al;
+                    A.dalpha[e] += dlam_new * x.S;
+                    A.domega[e] += dM * diff;
+                    A.rec_idx[2 * e] = k0;  // argmin nodes of level l: F_l side contributions
+                    A.rec_idx[2 * e + 1] = k1;
+                    A.rec_val[2 * e] = dm0;
+                    A.rec_val[2 * e + 1] = dm1;
+                }
+            }
+        } else if (c0.W > 0 && p == 0) {
+            A.dlam_in[e] += hisum;
+        }
+        wave_sync();
+        cur ^= 1;
+        c0 = c1;
+    }
+}
+
+// dS_i = sum over the edges of variable i of g (= dlambda' alpha), then dM_in[slot] = dS_i
+// (first line of Alg. 2, with alpha_ik per the derivative of the lambda update).
+__global__ void k_adj_deferred(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_slots,
+                               const float *__restrict__ g, float *__restrict__ dM, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = var_ptr[i], b = var_ptr[i + 1];
+    float s = 0.f;
+    for (int q = a; q < b; ++q) s += g[var_slots[q]];
+    for (int q = a; q < b; ++q) dM[var_slots[q]] = s;
+}
+
+// Adjoint of lambda_bar = lambda + alpha * S: dlambda stays, d_alpha += dlambda_bar * S_i,
+// g = dlambda_bar * alpha (dS then dM as in k_adj_deferred).
+__global__ void k_flush_adj(const int32_t *__restrict__ evar, const float *__restrict__ S,
+                            const float *__restrict__ alpha, const float *__restrict__ dlam, float *__restrict__ dalpha,
+                            float *__restrict__ g, int64_t slots) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= slots) return;
+    const int v = evar[e];
+    const float d = v >= 0 ? dlam[e] : 0.f;
+    if (v >= 0) dalpha[e] += d * S[v];
+    g[e] = d * alpha[e];
+}
+
+// d c_i = sum_{e of i} dlambda_e / |J_i|  (lambda_0 = c / |J|); variables in no row: seed * [c_i < 0].
+__global__ void k_dc(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_slots,
+                     const float *__restrict__ dlam, const float *__restrict__ c, float seed, float *__restrict__ dc,
+                     int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = var_ptr[i], b = var_ptr[i + 1];
+    if (a == b) {
+        dc[i] = c[i] < 0.f ? seed : 0.f;
+        return;
+    }
+    float s = 0.f;
+    for (int q = a; q < b; ++q) s += dlam[var_slots[q]];
+    dc[i] = s / (float)(b - a);
+}
+
+// d alpha_hat_e = alpha_e (d alpha_e - sum_{k in J_i} alpha_k d alpha_k), canonical arrays.
+__global__ void k_softmax_vjp(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_canon,
+                              const float *__restrict__ alpha, const float *__restrict__ dalpha, float *__restrict__ out,
+                              int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = var_ptr[i], b = var_ptr[i + 1];
+    float s = 0.f;
+    for (int q = a; q < b; ++q) s += alpha[var_canon[q]] * dalpha[var_canon[q]];
+    for (int q = a; q < b; ++q) {
+        const int e = var_canon[q];
+        out[e] = alpha[e] * (dalpha[e] - s);
+    }
+}
+
+// sum over variables with no row of min(0, c_i)
+__global__ void k_fill(float *__restrict__ x, float v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+__global__ void k_uncovered(const int32_t *__restrict__ var_ptr, const float *__restrict__ c, float *__restrict__ out,
+                            int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = var_ptr[i + 1] == var_ptr[i] ? fminf(c[i], 0.f) : 0.f;
+}
+
+inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int P, int RMAX>
+hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
+                        float seed, hipStream_t s) {
+    if (which == ADJ_F_UPDATE || which == ADJ_F_FIXED) {
+        dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
+        const size_t lds = (size_t)c.wpb_af * lds_words_adj_F(P, c.WB, c.NL) * 4;
+        if (which == ADJ_F_UPDATE)
+            hipLaunchKernelGGL((k_adj_F<P, RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.WB, c.NL);
+        else
+            hipLaunchKernelGGL((k_adj_F<P, RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.WB, c.NL);
+    } else {
+        dim3 grid((unsigned)((c.ntiles + c.wpb_ab - 1) / c.wpb_ab)), block(64 * c.wpb_ab);
+        const size_t lds = (size_t)c.wpb_ab * lds_words_adj_B(P, c.WB, c.NL) * 4;
+        if (which == ADJ_B_UPDATE)
+            hipLaunchKernelGGL((k_adj_B<P, RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.WB, c.NL, bar,
+                               recs, seed);
+        else
+            hipLaunchKernelGGL((k_adj_B<P, RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.WB, c.NL, bar,
+                               recs, seed);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
+                      float seed, hipStream_t s) {
+    if (c.ntiles <= 0) return hipSuccess;
+#define DD_ADJ(PP, RR) \
+    if (c.P == PP && c.RMAX == RR) return adj_dispatch<PP, RR>(t, a, c, which, bar, recs, seed, s);
+    DD_CLASSES(DD_ADJ)
+#undef DD_ADJ
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots, const float *g, float *dM, int n,
+                               hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_deferred, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_slots, g, dM, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_flush_adj(const int32_t *evar, const float *S, const float *alpha, const float *dlam, float *dalpha,
+                            float *g, int64_t slots, hipStream_t s) {
+    if (slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_flush_adj, dim3(blocks_for(slots, 256)), dim3(256), 0, s, evar, S, alpha, dlam, dalpha, g,
+                       slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_dc(const int32_t *var_ptr, const int32_t *var_slots, const float *dlam, const float *c, float seed,
+                     float *dc, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_dc, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_slots, dlam, c, seed, dc, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_softmax_vjp(const int32_t *var_ptr, const int32_t *var_canon, const float *alpha,
+                              const float *dalpha, float *out, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_softmax_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, alpha, dalpha, out,
+                       n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(float *x, float v, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, x, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_uncovered(const int32_t *var_ptr, const float *c, float *out, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_uncovered, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, c, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace dd

@@ -155,6 +155,7 @@ struct dd_instance {
     int64_t n = 0, m = 0, E = 0, nodes = 0;
     int max_width = 0, max_len = 0, uncovered = 0;
     double unc_const = 0.0;
+    int ckpt_default = 5;
     std::vector<ClassLaunch> classes;
     int64_t ntiles = 0, node_slots = 0, edge_slots = 0, device_bytes = 0;
     std::vector<int32_t> edge_var, edge_row;  // canonical edge map (host)
@@ -185,6 +186,15 @@ struct dd_instance {
     double *red = nullptr;   // device reduction output [4]
     double *partial = nullptr;  // [kSumBlocks] reduction scratch
     bool en_lam_valid = false;  // T.en_lam holds E^j at the current multipliers
+    // reverse mode (buffers allocated on first use)
+    bool adj_ready = false;
+    float *lam_in = nullptr, *dlamA = nullptr, *dlamB = nullptr, *dMA = nullptr, *dMB = nullptr, *g = nullptr;
+    float *dalpha = nullptr, *domega = nullptr, *rec_val = nullptr, *scratch_n = nullptr;
+    int32_t *rec_idx = nullptr;
+    std::vector<float *> ck_lam, ck_M;    // checkpoints of the unrolled forward (state at iterations 0, K, 2K, ..., T)
+    std::vector<float *> seg_lam, seg_M;  // pass-input states inside one checkpoint segment
+    int fwd_T = -1, fwd_K = 0;
+    int64_t version = 0, fwd_version = -1;  // the recorded forward is valid while the state is unchanged
     double *red_host = nullptr;  // pinned
     int32_t *flags = nullptr;
 
@@ -334,9 +344,11 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
         };
         cl.wpb_f = pick(lds_words_pass(P, cl.WB, cl.NL));
         cl.wpb_b = pick(lds_words_pass(P, cl.WB, cl.NL));
-        if (!cl.wpb_f || !cl.wpb_b)
+        cl.wpb_af = pick(lds_words_adj_F(P, cl.WB, cl.NL));
+        cl.wpb_ab = pick(lds_words_adj_B(P, cl.WB, cl.NL));
+        if (!cl.wpb_f || !cl.wpb_b || !cl.wpb_af || !cl.wpb_ab)
             return fail(DD_E_UNSUPPORTED, "LDS need %lld bytes per wave exceeds the budget",
-                        (long long)lds_words_pass(P, cl.WB, cl.NL) * 4);
+                        (long long)lds_words_adj_F(P, cl.WB, cl.NL) * 4);
         hp.classes.push_back(cl);
         i = j;
     }
@@ -433,9 +445,11 @@ int recorded(dd_instance *h, const char *name, double bytes, hipStream_t s, F la
     return DD_OK;
 }
 
-// The classes of one pass are independent launches; all but the first run on side streams
+// The classes of one sweep are independent launches; all but the first run on side streams
 // forked from (and joined back into) the caller's stream, so their tails overlap.
-int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
+// launch(class, stream) returns hipError_t; name(class) and bytes(class) label it for profiling.
+template <class L, class N, class B>
+int per_class(dd_instance *h, hipStream_t s, L launch, N name, B bytes) {
     const size_t nc = h->classes.size();
     if (nc > 1) {
         HIP_TRY(hipEventRecord(h->fork, s));
@@ -444,11 +458,7 @@ int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
     for (size_t c = 0; c < nc; ++c) {
         const ClassLaunch &cl = h->classes[c];
         hipStream_t cs = c == 0 ? s : h->side[c - 1];
-        char name[96];
-        snprintf(name, sizeof name, "%s<%d, %d, %d>", fwd ? "k_fwd" : "k_bwd", cl.P, cl.RMAX, mode);
-        int st = recorded(h, name, algorithmic_bytes(fwd, mode, cl), cs, [&] {
-            return fwd ? launch_fwd(h->T, cl, mode, cs) : launch_bwd(h->T, cl, mode, cs);
-        });
+        int st = recorded(h, name(cl).c_str(), bytes(cl), cs, [&] { return launch(cl, cs); });
         if (st) return st;
     }
     for (size_t c = 1; c < nc; ++c) {
@@ -456,6 +466,35 @@ int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
         HIP_TRY(hipStreamWaitEvent(s, h->join[c - 1], 0));
     }
     return DD_OK;
+}
+
+std::string kname(const char *k, const ClassLaunch &cl, int mode) {
+    char name[96];
+    snprintf(name, sizeof name, "%s<%d, %d, %d>", k, cl.P, cl.RMAX, mode);
+    return name;
+}
+
+int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
+    return per_class(
+        h, s,
+        [&](const ClassLaunch &cl, hipStream_t cs) {
+            return fwd ? launch_fwd(h->T, cl, mode, cs) : launch_bwd(h->T, cl, mode, cs);
+        },
+        [&](const ClassLaunch &cl) { return kname(fwd ? "k_fwd" : "k_bwd", cl, mode); },
+        [&](const ClassLaunch &cl) { return algorithmic_bytes(fwd, mode, cl); });
+}
+
+// Reverse sweeps.  Bytes: update sweeps read topology, the swept side's cost and the staged
+// other side (12 B/node) and ~68 B of edge data; fixed sweeps 8 B/node and ~28 B/edge.
+int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs, float seed, hipStream_t s) {
+    const bool upd = which == ADJ_F_UPDATE || which == ADJ_B_UPDATE;
+    const char *nm = which == ADJ_F_UPDATE || which == ADJ_F_FIXED ? "k_adj_F" : "k_adj_B";
+    return per_class(
+        h, s, [&](const ClassLaunch &cl, hipStream_t cs) { return launch_adj(h->T, A, cl, which, bar, recs, seed, cs); },
+        [&](const ClassLaunch &cl) { return kname(nm, cl, upd ? 1 : 0); },
+        [&](const ClassLaunch &cl) {
+            return upd ? 12.0 * cl.nodes + 68.0 * cl.edges : 8.0 * cl.nodes + 28.0 * cl.edges;
+        });
 }
 
 int deferred(dd_instance *h, hipStream_t s) {
@@ -516,6 +555,7 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     if (npl != 1 && npl != 2 && npl != 4) return fail(DD_E_ARG, "nodes_per_lane must be 1, 2 or 4");
     const int wpb = o.waves_per_block > 0 ? std::min(o.waves_per_block, 16) : 4;
     const int lds_budget = o.lds_budget > 0 ? o.lds_budget : 64 * 1024;
+    if (o.ckpt_every < 0) return fail(DD_E_ARG, "ckpt_every must be >= 0");
     SortedRows sr;
     int st = validate_and_sort(prob, sr);
     if (st) return st;
@@ -562,6 +602,7 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     HIP_TRY(hipGetDevice(&device));
     dd_instance *h = new dd_instance();
     h->device = device;
+    if (o.ckpt_every > 0) h->ckpt_default = o.ckpt_every;
     h->n = prob->n;
     h->m = m;
     h->E = sr.ptr[m];
@@ -728,6 +769,7 @@ int dd_set_params(dd_instance *h, const float *omega, const float *alpha, void *
     if (f[1]) return fail(DD_E_PARAM, "alpha must be finite and non-negative");
     HIP_TRY(launch_scatter(h->canon2slot, omega, h->omega, h->E, s));
     HIP_TRY(launch_scatter(h->canon2slot, alpha, h->alpha, h->E, s));
+    h->version++;
     return DD_OK;
 }
 
@@ -741,6 +783,7 @@ int dd_reset(dd_instance *h, void *stream) {
     if (!h) return fail(DD_E_ARG, "NULL instance");
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_init_lambda(h->canon2slot, h->T.evar, h->var_ptr, h->cdev, h->T.lam, h->T.M, h->E, s));
+    h->version++;
     return recompute_B(h, s);
 }
 
@@ -749,6 +792,7 @@ int dd_set_state(dd_instance *h, const float *lambda, const float *M, void *stre
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_scatter(h->canon2slot, lambda, h->T.lam, h->E, s));
     HIP_TRY(launch_scatter(h->canon2slot, M, h->T.M, h->E, s));
+    h->version++;
     return recompute_B(h, s);
 }
 
@@ -772,6 +816,7 @@ int dd_run_pass(dd_instance *h, int32_t direction, void *stream) {
     // a backward pass ends with B(root) = E^j at the updated multipliers; a forward pass
     // changes the multipliers without computing it
     h->en_lam_valid = false;
+    h->version++;
     st = all_classes(h, direction == 0, direction == 0 ? (int)FWD_UPDATE : (int)BWD_UPDATE, s);
     h->en_lam_valid = st == DD_OK && direction == 1;
     return st;
@@ -835,6 +880,210 @@ int dd_min_marginals(dd_instance *h, float *m0_out, float *m1_out, void *stream)
     st = all_classes(h, false, BWD_MM, s);
     h->T.out0 = h->T.out1 = nullptr;
     return st;
+}
+
+}  // extern "C"
+
+namespace {
+
+int adj_alloc(dd_instance *h) {
+    if (h->adj_ready) return DD_OK;
+    const size_t S = (size_t)h->edge_slots;
+    int st;
+    for (float **b : {&h->lam_in, &h->dlamA, &h->dlamB, &h->dMA, &h->dMB, &h->g, &h->dalpha, &h->domega})
+        if ((st = h->alloc(b, S))) return st;
+    if ((st = h->alloc(&h->rec_val, 2 * S))) return st;
+    if ((st = h->alloc(&h->rec_idx, 2 * S))) return st;
+    if ((st = h->alloc(&h->scratch_n, (size_t)std::max<int64_t>(h->n, 1)))) return st;
+    for (float *b : {h->lam_in, h->dlamA, h->dlamB, h->dMA, h->dMB, h->g, h->dalpha, h->domega})
+        HIP_TRY(hipMemset(b, 0, sizeof(float) * S));
+    HIP_TRY(hipMemset(h->rec_val, 0, sizeof(float) * 2 * S));
+    HIP_TRY(hipMemset(h->rec_idx, 0xFF, sizeof(int32_t) * 2 * S));
+    h->adj_ready = true;
+    return DD_OK;
+}
+
+int copy_slots(dd_instance *h, float *dst, const float *src, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(dst, src, sizeof(float) * h->edge_slots, hipMemcpyDeviceToDevice, s));
+    return DD_OK;
+}
+
+// Reverse mode of one pass.  On entry the instance state (lambda, M) is the pass input; on exit
+// it is the pass output.  dlam_out/dM_out: adjoints of the outputs; dlam_in/dM_in receive the
+// adjoints of the inputs; d_alpha and d_omega accumulate.
+int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out, float *dlam_in, float *dM_in,
+             hipStream_t s) {
+    int st = deferred(h, s);  // S and alpha*S of the pass-input M
+    if (st) return st;
+    if ((st = copy_slots(h, h->lam_in, h->T.lam, s))) return st;
+    AdjTables A{};
+    A.lam_in = h->lam_in;
+    A.lam_src = h->lam_in;
+    A.dlam_out = dlam_out;
+    A.dM_out = dM_out;
+    A.dlam_in = dlam_in;
+    A.g = h->g;
+    A.dalpha = h->dalpha;
+    A.domega = h->domega;
+    A.rec_idx = h->rec_idx;
+    A.rec_val = h->rec_val;
+    h->en_lam_valid = false;
+    if (dir == 0) {
+        // fixed side B at the input multipliers, the pass replayed (F), then the two reverse sweeps
+        if ((st = all_classes(h, false, BWD_STORE, s))) return st;
+        if ((st = all_classes(h, true, FWD_UPDATE, s))) return st;
+        if ((st = adj_classes(h, A, ADJ_F_UPDATE, 0, 0, 0.f, s))) return st;
+        if ((st = adj_classes(h, A, ADJ_B_FIXED, 0, 1, 0.f, s))) return st;
+    } else {
+        if ((st = all_classes(h, true, FWD_SWEEP_LAM, s))) return st;
+        if ((st = all_classes(h, false, BWD_UPDATE, s))) return st;
+        if ((st = adj_classes(h, A, ADJ_B_UPDATE, 0, 0, 0.f, s))) return st;
+        if ((st = adj_classes(h, A, ADJ_F_FIXED, 0, 1, 0.f, s))) return st;
+    }
+    return recorded(h, "k_adj_deferred", 12.0 * (double)h->E + 8.0 * (double)h->n, s, [&] {
+        return launch_adj_deferred(h->var_ptr, h->var_slots, h->g, dM_in, (int)h->n, s);
+    });
+}
+
+int save_state(dd_instance *h, std::vector<float *> &L, std::vector<float *> &Mv, size_t i, hipStream_t s) {
+    while (L.size() <= i) {
+        float *a = nullptr, *b = nullptr;
+        int st = h->alloc(&a, (size_t)h->edge_slots);
+        if (st) return st;
+        if ((st = h->alloc(&b, (size_t)h->edge_slots))) return st;
+        L.push_back(a);
+        Mv.push_back(b);
+    }
+    int st = copy_slots(h, L[i], h->T.lam, s);
+    if (st) return st;
+    return copy_slots(h, Mv[i], h->T.M, s);
+}
+
+int load_state(dd_instance *h, const std::vector<float *> &L, const std::vector<float *> &Mv, size_t i,
+               hipStream_t s) {
+    int st = copy_slots(h, h->T.lam, L[i], s);
+    if (st) return st;
+    return copy_slots(h, h->T.M, Mv[i], s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int dd_pass_vjp(dd_instance *h, int32_t direction, const float *lam_in, const float *M_in, const float *dlam_out,
+                const float *dM_out, float *dlam_in, float *dM_in, float *d_alpha, float *d_omega, void *stream) {
+    if (!h || (direction != 0 && direction != 1)) return fail(DD_E_ARG, "bad instance or direction");
+    if (h->E && (!lam_in || !M_in || !dlam_out || !dM_out || !dlam_in || !dM_in || !d_alpha || !d_omega))
+        return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int st = adj_alloc(h);
+    if (st) return st;
+    HIP_TRY(launch_scatter(h->canon2slot, lam_in, h->T.lam, h->E, s));
+    HIP_TRY(launch_scatter(h->canon2slot, M_in, h->T.M, h->E, s));
+    HIP_TRY(launch_scatter(h->canon2slot, dlam_out, h->dlamA, h->E, s));
+    HIP_TRY(launch_scatter(h->canon2slot, dM_out, h->dMA, h->E, s));
+    HIP_TRY(launch_fill(h->dalpha, 0.f, h->edge_slots, s));
+    HIP_TRY(launch_fill(h->domega, 0.f, h->edge_slots, s));
+    h->version++;
+    if ((st = pass_vjp(h, direction, h->dlamA, h->dMA, h->dlamB, h->dMB, s))) return st;
+    HIP_TRY(launch_gather(h->canon2slot, h->dlamB, dlam_in, h->E, nullptr, s));
+    HIP_TRY(launch_gather(h->canon2slot, h->dMB, dM_in, h->E, nullptr, s));
+    HIP_TRY(launch_gather(h->canon2slot, h->dalpha, d_alpha, h->E, nullptr, s));
+    HIP_TRY(launch_gather(h->canon2slot, h->domega, d_omega, h->E, nullptr, s));
+    return recompute_B(h, s);
+}
+
+int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream) {
+    if (!h || T < 0 || !lb) return fail(DD_E_ARG, "bad instance, T or lb");
+    hipStream_t s = (hipStream_t)stream;
+    int st = adj_alloc(h);
+    if (st) return st;
+    const int K = ckpt_every > 0 ? ckpt_every : (h->ckpt_default > 0 ? h->ckpt_default : 5);
+    if ((st = dd_reset(h, stream))) return st;
+    for (int t = 0; t < T; ++t) {
+        if (t % K == 0 && (st = save_state(h, h->ck_lam, h->ck_M, (size_t)(t / K), s))) return st;
+        if ((st = dd_run(h, 1, stream))) return st;
+    }
+    const int nseg = (T + K - 1) / K;
+    if ((st = save_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;  // the final state
+    if ((st = dd_lower_bound(h, lb, nullptr, stream))) return st;
+    h->fwd_T = T;
+    h->fwd_K = K;
+    h->fwd_version = h->version;
+    return DD_OK;
+}
+
+int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream) {
+    if (!h) return fail(DD_E_ARG, "NULL instance");
+    if (h->fwd_T < 0 || h->fwd_version != h->version)
+        return fail(DD_E_STATE, "dd_backward needs the state left by dd_forward_unrolled");
+    hipStream_t s = (hipStream_t)stream;
+    const int T = h->fwd_T, K = h->fwd_K, nseg = (T + K - 1) / K;
+    const float seed = (float)dlb;
+    int st;
+    // adjoint of the lower bound at the final state: dLB / dlambda_bar_j = argmin assignment of row j
+    if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;
+    if ((st = deferred(h, s))) return st;
+    if ((st = all_classes(h, false, BWD_STORE_BAR, s))) return st;
+    HIP_TRY(launch_fill(h->dalpha, 0.f, h->edge_slots, s));
+    HIP_TRY(launch_fill(h->domega, 0.f, h->edge_slots, s));
+    HIP_TRY(launch_fill(h->dlamA, 0.f, h->edge_slots, s));
+    {
+        AdjTables A{};
+        A.lam_src = h->T.lam;
+        A.dlam_in = h->dlamA;
+        if ((st = adj_classes(h, A, ADJ_B_FIXED, 1, 0, seed, s))) return st;
+    }
+    // lambda_bar = lambda + alpha S(M): dlambda = dlambda_bar, d_alpha += dlambda_bar S, dM = dS
+    HIP_TRY(launch_flush_adj(h->T.evar, h->S, h->alpha, h->dlamA, h->dalpha, h->g, h->edge_slots, s));
+    HIP_TRY(launch_adj_deferred(h->var_ptr, h->var_slots, h->g, h->dMA, (int)h->n, s));
+    float *dl = h->dlamA, *dm = h->dMA, *dl2 = h->dlamB, *dm2 = h->dMB;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int t0 = seg * K, t1 = std::min(T, t0 + K), np = 2 * (t1 - t0);
+        if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)seg, s))) return st;
+        // a forward pass reads B at its input multipliers: the backward pass before it left
+        // exactly that, so rebuild it from the checkpoint (same expression, same bits)
+        if ((st = recompute_B(h, s))) return st;
+        for (int q = 0; q < np; ++q) {  // recompute the pass inputs of the segment
+            if ((st = save_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
+            if ((st = dd_run_pass(h, q % 2, stream))) return st;
+        }
+        for (int q = np - 1; q >= 0; --q) {
+            if ((st = load_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
+            if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s))) return st;
+            std::swap(dl, dl2);
+            std::swap(dm, dm2);
+        }
+    }
+    // lambda_0 = c / |J_i|
+    if (d_c) HIP_TRY(launch_dc(h->var_ptr, h->var_slots, dl, h->cdev, seed, d_c, (int)h->n, s));
+    if (d_omega) HIP_TRY(launch_gather(h->canon2slot, h->domega, d_omega, h->E, nullptr, s));
+    if (d_alpha) HIP_TRY(launch_gather(h->canon2slot, h->dalpha, d_alpha, h->E, nullptr, s));
+    // leave the solver at the final state of the recorded forward
+    if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;
+    if ((st = recompute_B(h, s))) return st;
+    h->fwd_version = h->version;
+    return DD_OK;
+}
+
+int dd_seg_softmax_vjp(dd_instance *h, const float *alpha, const float *d_alpha, float *d_alpha_hat, void *stream) {
+    if (!h || (h->E && (!alpha || !d_alpha || !d_alpha_hat))) return fail(DD_E_ARG, "NULL argument");
+    HIP_TRY(launch_softmax_vjp(h->var_ptr, h->var_canon, alpha, d_alpha, d_alpha_hat, (int)h->n, (hipStream_t)stream));
+    return DD_OK;
+}
+
+int dd_set_costs(dd_instance *h, const float *c, void *stream) {
+    if (!h || (h->n && !c)) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int st = adj_alloc(h);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(h->cdev, c, sizeof(float) * h->n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_uncovered(h->var_ptr, h->cdev, h->scratch_n, (int)h->n, s));
+    HIP_TRY(launch_sum(h->scratch_n, h->n, 0, h->partial, h->red, s));
+    HIP_TRY(hipMemcpyAsync(h->red_host, h->red, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    h->unc_const = h->red_host[0];
+    return dd_reset(h, stream);
 }
 
 int dd_row_nodes(const dd_instance *h, int64_t *nodes_out) {

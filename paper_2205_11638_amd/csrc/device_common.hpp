@@ -1,0 +1,148 @@
+// device_common.hpp -- device helpers shared by the pass kernels and the adjoint kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace dd {
+namespace dev {
+
+constexpr float kInf = __builtin_huge_valf();
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Values known to be equal on every lane of the wavefront, made scalar for the compiler.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// min over the P lanes of a team (P a power of two, teams aligned to P lanes), result in
+// every lane of the team.  Within 16-lane rows: DPP quad permutes and row mirrors; across
+// rows: lane reads (P = 64) or one cross-row shuffle (P = 32).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int P>
+__device__ __forceinline__ float team_min(float v) {
+    if (P >= 2) v = fminf(v, dpp<0xB1>(v));    // quad_perm [1,0,3,2]: lanes i, i^1
+    if (P >= 4) v = fminf(v, dpp<0x4E>(v));    // quad_perm [2,3,0,1]: lanes i, i^2
+    if (P >= 8) v = fminf(v, dpp<0x141>(v));   // row_half_mirror: the two quads of 8 lanes
+    if (P >= 16) v = fminf(v, dpp<0x140>(v));  // row_mirror: the two halves of 16 lanes
+    if (P == 32) v = fminf(v, __shfl_xor(v, 16));
+    if (P == 64) {
+        const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+        const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+        const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+        const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+        v = fminf(fminf(r0, r1), fminf(r2, r3));
+    }
+    return v;
+}
+
+struct TileCtx {
+    int64_t nbase;
+    int ebase, lbase, wbase, nlev;
+};
+
+__device__ __forceinline__ TileCtx tile_ctx(const DevTables &T, int64_t tile) {
+    TileCtx c;
+    c.nbase = T.node_base[tile];
+    c.ebase = T.edge_base[tile];
+    c.lbase = T.lev_base[tile];
+    c.wbase = T.w_base[tile];
+    c.nlev = T.nlev[tile];
+    return c;
+}
+
+// Per-wave LDS layout shared by the pass kernels (all entries 4 bytes):
+//   [X: WB*G floats] [Y: WB*G floats] [meta: NL*G ints] [off: NL ints]
+// meta[l*G + g] = width of team g at level l | rows of level l << 16; off[l] = level offset.
+// Node buffers are interleaved over teams (index k*G + g) and hold WB >= width + 2 entries
+// per team: the two past the level's width are the terminals (0-terminal = +inf, 1-terminal
+// = 0), so a child code indexes the buffer directly, with no branch.  Slots past a team's
+// width inside a level's rows are padding whose child codes both point at the 0-terminal,
+// so every global access of a level is unconditional and in bounds.
+template <int G>
+__device__ __forceinline__ void preload_meta(const DevTables &T, const TileCtx &tc, int lane, int *meta, int *off) {
+    const int n = tc.nlev * G;
+    for (int i = lane; i < n; i += 64) meta[i] = T.widths[tc.wbase + i] | (T.lev_rows[tc.lbase + i / G] << 16);
+    for (int l = lane; l < tc.nlev; l += 64) off[l] = T.lev_off[tc.lbase + l];
+    wave_sync();
+}
+
+__device__ __forceinline__ void lds_fmin(float *a, float v) {
+    __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// ------------------------------------------------------------------------------------------
+// Forward pass.  X = F of the current level (min-accumulated for the next one), Y = B of the
+// next level staged from global memory.
+// ------------------------------------------------------------------------------------------
+// One-wave diagrams (P = 64) are stored compactly: level l+1 starts right after the last
+// node of level l, so the last row of a level also reads a few slots of the next level (or
+// of the slack after the array).  Those lanes are masked on that row only: their topology is
+// replaced by two 0-terminal arcs and their stores are skipped.  Narrower teams use levels
+// padded to whole rows, whose padding slots already hold 0-terminal arcs.
+template <int P>
+__device__ __forceinline__ bool in_level(int r, int R, int lane, int W) {
+    return P < 64 || r < R - 1 || lane < W - r * 64;
+}
+
+// Per-level scalars of a tile: this team's width, the level's rows and first slot.
+struct Lev {
+    int W, R;
+    int64_t base;
+};
+
+// sum / integer min over the P lanes of a team, same lane pattern as team_min
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+
+template <int P>
+__device__ __forceinline__ float team_sum(float v) {
+    if (P >= 2) v += dpp<0xB1>(v);
+    if (P >= 4) v += dpp<0x4E>(v);
+    if (P >= 8) v += dpp<0x141>(v);
+    if (P >= 16) v += dpp<0x140>(v);
+    if (P == 32) v += __shfl_xor(v, 16);
+    if (P == 64) {
+        const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+        const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+        const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+        const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+        v = (r0 + r1) + (r2 + r3);
+    }
+    return v;
+}
+
+template <int P>
+__device__ __forceinline__ int team_min_i(int v) {
+    if (P >= 2) v = min(v, dpp_i<0xB1>(v));
+    if (P >= 4) v = min(v, dpp_i<0x4E>(v));
+    if (P >= 8) v = min(v, dpp_i<0x141>(v));
+    if (P >= 16) v = min(v, dpp_i<0x140>(v));
+    if (P == 32) v = min(v, __shfl_xor(v, 16));
+    if (P == 64) {
+        const int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+        const int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+        v = min(min(r0, r1), min(r2, r3));
+    }
+    return v;
+}
+
+__device__ __forceinline__ void lds_fadd(float *a, float v) {
+    __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+__device__ __forceinline__ void lds_imin(int *a, int v) {
+    __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+}  // namespace dev
+}  // namespace dd

@@ -15,8 +15,11 @@
 
 namespace dd {
 
-enum FwdMode { FWD_UPDATE = 0, FWD_SWEEP_BAR = 1 };
-enum BwdMode { BWD_UPDATE = 0, BWD_STORE = 1, BWD_EN_LAM = 2, BWD_EN_BAR = 3, BWD_MM = 4 };
+// forward: update pass; F sweep at lambda_bar (no update); F sweep at lambda (no update)
+enum FwdMode { FWD_UPDATE = 0, FWD_SWEEP_BAR = 1, FWD_SWEEP_LAM = 2 };
+// backward: update pass; B sweep at lambda stored; energies at lambda; energies at lambda_bar;
+// min-marginals at lambda_bar; B sweep at lambda_bar stored
+enum BwdMode { BWD_UPDATE = 0, BWD_STORE = 1, BWD_EN_LAM = 2, BWD_EN_BAR = 3, BWD_MM = 4, BWD_STORE_BAR = 5 };
 
 struct DevTables {
     // tile tables
@@ -54,6 +57,7 @@ struct ClassLaunch {
     int WB;        // LDS floats per team per node buffer: WL + 2 terminals, rounded up to P
     int NL;        // max levels of a tile in the class
     int wpb_f, wpb_b;  // waves per workgroup of the forward / backward kernels
+    int wpb_af, wpb_ab;  // waves per workgroup of the push-form / pull-form adjoint sweeps
     int64_t tile0, ntiles;
     int64_t nodes, edges, rows;  // real (unpadded) counts covered by one launch, for byte accounting
 };
@@ -63,6 +67,44 @@ struct ClassLaunch {
 constexpr int lds_words_pass(int P, int WB, int NL) {  // constexpr: usable in device code too
     return 2 * WB * (64 / P) + NL * (3 * (64 / P) + 1);
 }
+
+#define DD_CLASSES(X) \
+    X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(64, 8) X(64, 12) X(64, 16) X(64, 24) X(64, 32)
+
+// per wave of the adjoint sweeps: push form = cost and adjoint of two levels, bids, staged B;
+// pull form = staged B and the adjoints of two levels; both + the level table
+constexpr int lds_words_adj_F(int P, int WB, int NL) { return 6 * WB * (64 / P) + NL * ((64 / P) + 1); }
+constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) + NL * ((64 / P) + 1); }
+
+// Arrays of the reverse sweeps (edge-slot indexed unless noted).
+struct AdjTables {
+    const float *lam_in;    // pass-input multipliers
+    const float *lam_src;   // multipliers of a fixed-side sweep (plus alpha*S when flushed)
+    const float *dlam_out;  // adjoint of the pass-output multipliers
+    const float *dM_out;    // adjoint of the pass-output M
+    float *dlam_in;         // adjoint of the pass-input multipliers (set by the update sweep, added to by the fixed one)
+    float *g;               // dlambda' * alpha, summed per variable into dS
+    float *dalpha, *domega; // accumulated over passes
+    int32_t *rec_idx;       // [2 * slots] argmin node indices handed from one sweep to the other (-1: none)
+    float *rec_val;         // [2 * slots] the adjoint values that go with them
+};
+
+enum AdjSweep { ADJ_F_UPDATE = 0, ADJ_F_FIXED = 1, ADJ_B_UPDATE = 2, ADJ_B_FIXED = 3 };
+
+// One reverse sweep over the tiles of a class.  bar: fixed pull sweeps use lam_src + alpha*S;
+// recs: fixed sweeps add the records of the update sweep; seed: adjoint of B(root) (pull form).
+hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
+                      float seed, hipStream_t s);
+hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots, const float *g, float *dM, int n,
+                               hipStream_t s);
+hipError_t launch_flush_adj(const int32_t *evar, const float *S, const float *alpha, const float *dlam, float *dalpha,
+                            float *g, int64_t slots, hipStream_t s);
+hipError_t launch_dc(const int32_t *var_ptr, const int32_t *var_slots, const float *dlam, const float *c, float seed,
+                     float *dc, int n, hipStream_t s);
+hipError_t launch_softmax_vjp(const int32_t *var_ptr, const int32_t *var_canon, const float *alpha,
+                              const float *dalpha, float *out, int n, hipStream_t s);
+hipError_t launch_fill(float *x, float v, int64_t n, hipStream_t s);
+hipError_t launch_uncovered(const int32_t *var_ptr, const float *c, float *out, int n, hipStream_t s);
 
 hipError_t launch_fwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
 hipError_t launch_bwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);

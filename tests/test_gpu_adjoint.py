@@ -1,0 +1,207 @@
+"""GPU reverse mode (Alg. 2 through unrolled passes) against the FP64 oracle's literal Alg. 2.
+
+The oracle traces the minimizers s^j(i, beta) of every block explicitly on the partial-sum
+diagram; the GPU routes adjoints through argmins of its BDD sweeps.  Where a minimizer is
+unique the two must agree: gradients to 1e-4 relative, norm-wise per parameter vector and
+entry-wise with a floor of 1e-4 * max |reference|.  Where two options of a decision are within
+GAP_MIN (relative) of each other, fp32 and fp64 may legitimately take different sides, and
+both results are valid subgradients.  There the tests compare what is unique (the rows, and
+the variables, that no near-tie touches) and check the rest through Euler's identity for
+positively homogeneous maps, which every linear piece meeting at the point satisfies.
+"""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import host, make_instance, say
+
+pytestmark = pytest.mark.gpu
+GRAD_RTOL = 1e-4
+GAP_MIN = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+@pytest.fixture(scope="module")
+def orc():
+    from oracle import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def f32(x):
+    return np.asarray(x, dtype=np.float32).astype(np.float64)
+
+
+def close_grad(got, ref, what):
+    ref = np.asarray(ref, dtype=np.float64)
+    got = np.asarray(got, dtype=np.float64)
+    nr = np.linalg.norm(ref)
+    assert np.linalg.norm(got - ref) <= GRAD_RTOL * max(nr, 1e-6), (what, np.linalg.norm(got - ref), nr)
+    floor = GRAD_RTOL * max(np.abs(ref).max(), 1e-6)
+    bad = np.abs(got - ref) > np.maximum(GRAD_RTOL * np.abs(ref), floor)
+    assert not bad.any(), (what, int(bad.sum()), int(np.argmax(np.abs(got - ref))))
+
+
+def euler_close(lhs, rhs, scale, what):
+    assert abs(lhs - rhs) <= GRAD_RTOL * max(scale, 1e-6), (what, lhs, rhs, scale)
+
+
+def mixed_problem(seed):
+    return synth.random_tiny(seed, n=40, m=60, kmin=1, kmax=14, amin=-7, amax=7)
+
+
+def team_size_problem():
+    rows, rng, n = [], np.random.default_rng(12), 4000
+    for width_target in (2, 6, 12, 24, 48, 100, 200, 400, 900):
+        for _ in range(3):
+            k = int(rng.integers(8, 60))
+            cols = rng.choice(n, size=k, replace=False)
+            a = rng.integers(1, 4 * max(1, width_target // k) + 2, size=k)
+            rows.append((cols, a, -1, int(max(a.max(), min(width_target, a.sum() // 2)))))
+    return synth.generators._from_rows(n, -rng.uniform(0, 1, size=n), rows, "team-sizes")
+
+
+CASES = {
+    "mixed0": lambda: mixed_problem(0),
+    "mixed3": lambda: mixed_problem(3),
+    "setcover": lambda: synth.workload("setcover")["problem"],
+    "gm-small": lambda: synth.workload("gm", small=True)["problem"],
+    "team-sizes": team_size_problem,
+    "knapsack-small": lambda: synth.knapsack(n=3000, m=30, seed=9),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("direction", [0, 1])
+def test_pass_vjp_matches_oracle(orc, case, direction):
+    import torch
+    p = CASES[case]()
+    rng = np.random.default_rng(len(case) + direction)
+    om = f32(synth.sigmoid(rng.normal(size=p.nnz)))
+    ah = f32(rng.normal(0, 0.3, size=p.nnz))
+    say(f"pass vjp {case} dir {direction} E={p.nnz}")
+    inst, omt, alt = make_instance(p, om, ah)
+    al = host(alt)
+    inst.run(2)
+    if direction == 1:
+        inst.run_pass(0)
+    lam_in, M_in = inst.get_state()
+    dlo = rng.normal(size=p.nnz)
+    dmo = rng.normal(size=p.nnz)
+    dev = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda")
+    dli, dmi, da, dw = (host(t) for t in inst.pass_vjp(direction, lam_in, M_in, dev(dlo), dev(dmo)))
+    # the state is left at the pass output
+    lam_o, M_o = (host(t) for t in inst.get_state())
+    li, mi = host(lam_in), host(M_in)
+    *r, gap = orc.pass_vjp(p, om, al, direction, li, mi, f32(dlo), f32(dmo), with_gap=True)
+    rowid = np.repeat(np.arange(p.m), np.diff(p.row_ptr))
+    tie_row = gap < GAP_MIN
+    ok_e = ~tie_row[rowid]
+    tie_var = np.zeros(p.n, bool)
+    tie_var[p.col[~ok_e]] = True
+    ok_v = ~tie_var[p.col]  # dM_in gathers over every edge of the variable
+    say(f"  near-tie rows {int(tie_row.sum())}/{p.m}; edges compared {int(ok_e.sum())}/{p.nnz}")
+    assert ok_e.sum() >= min(p.nnz, 100)
+    close_grad(dli[ok_e], r[0][ok_e], "dlam_in")
+    close_grad(dmi[ok_v], r[1][ok_v], "dM_in")
+    close_grad(da[ok_e], r[2][ok_e], "d_alpha")
+    close_grad(dw[ok_e], r[3][ok_e], "d_omega")
+    for a in (dli, dmi, da, dw):
+        assert np.isfinite(a).all()
+    lo, Mo = li.copy(), mi.copy()
+    orc.run_pass(p, om, al, lo, Mo, direction)
+    np.testing.assert_allclose(lam_o, lo, atol=1e-4 * np.abs(lo).max())
+    # Euler's identity over all rows, then for each near-tie row on its own (seed on that row only)
+    terms = np.concatenate([dli * li, dmi * mi])
+    euler_close(terms.sum(), f32(dlo) @ lam_o + f32(dmo) @ M_o, np.abs(terms).sum(), "all rows")
+    for j in np.flatnonzero(tie_row)[:6]:
+        on = (rowid == j).astype(np.float64)
+        dl, dm, _, _ = (host(t) for t in inst.pass_vjp(direction, lam_in, M_in, dev(dlo * on), dev(dmo * on)))
+        terms = np.concatenate([dl * li, dm * mi])
+        euler_close(terms.sum(), f32(dlo * on) @ lam_o + f32(dmo * on) @ M_o, np.abs(terms).sum(), f"row {j}")
+
+
+# seeds picked so that the first three trajectories take no near-tie decision (the oracle
+# reports it); the wide diagrams of the last two always do, and are checked through Euler
+@pytest.mark.parametrize("case,T,K,seed", [("mixed0", 3, 2, 23), ("setcover", 4, 3, 3), ("gm-small", 5, 2, 1),
+                                           ("team-sizes", 3, 1, 0), ("knapsack-small", 3, 5, 0)])
+def test_unrolled_gradient_matches_oracle(orc, case, T, K, seed):
+    p = CASES[case]()
+    rng = np.random.default_rng(seed)
+    om = f32(synth.sigmoid(rng.normal(size=p.nnz)))
+    ah = f32(rng.normal(0, 0.3, size=p.nnz))
+    say(f"unrolled grad {case} T={T} K={K}")
+    inst, omt, alt = make_instance(p, om, ah)
+    al = host(alt)
+    lb = inst.forward_unrolled(T, K)
+    dw, da, dc = (host(t) for t in inst.backward(1.0))
+    pc = synth.Problem(p.n, f32(p.c), p.row_ptr, p.col, p.coef, p.sense, p.rhs)
+    lb_o, dw_o, da_o, dc_o, gap = orc.unrolled_grad(pc, om, al, T, with_gap=True)
+    assert lb == pytest.approx(lb_o, rel=1e-5, abs=1e-6)
+    euler_close(dc @ pc.c, lb, np.abs(dc * pc.c).sum(), "<d_c, c> = LB")
+    for a in (dw, da, dc):
+        assert np.isfinite(a).all()
+    say(f"  smallest decision gap on the trajectory {gap:.3g}")
+    if gap >= GAP_MIN:  # every decision unique: the gradient is unique
+        close_grad(dw, dw_o, "d_omega")
+        close_grad(da, da_o, "d_alpha")
+        close_grad(dc, dc_o, "d_c")
+    # the state is the final one again: the bound is unchanged
+    assert inst.lower_bound()[0] == pytest.approx(lb, rel=1e-6, abs=1e-7)
+
+
+def test_backward_is_linear_in_the_seed_and_checkpoint_free():
+    p = CASES["gm-small"]()
+    rng = np.random.default_rng(5)
+    inst, _, _ = make_instance(p, synth.sigmoid(rng.normal(size=p.nnz)), rng.normal(0, 0.3, size=p.nnz))
+    inst.forward_unrolled(6, 2)
+    g1 = [host(t) for t in inst.backward(1.0)]
+    g2 = [host(t) for t in inst.backward(-2.5)]
+    for a, b in zip(g1, g2):
+        np.testing.assert_allclose(b, -2.5 * a, rtol=1e-6, atol=1e-6 * max(1.0, np.abs(a).max()))
+    inst.forward_unrolled(6, 6)  # one segment: same numbers (replays are bit-exact)
+    g3 = [host(t) for t in inst.backward(1.0)]
+    for a, b in zip(g1, g3):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_backward_needs_a_recorded_forward():
+    import paper_2205_11638_amd as dd
+    p = CASES["mixed0"]()
+    inst, _, _ = make_instance(p)
+    with pytest.raises(dd.DDError) as e:
+        inst.backward(1.0)
+    assert e.value.code == dd.binding.DD_E_STATE
+    inst.forward_unrolled(2)
+    inst.run_pass(0)  # the state moved on: the record is stale
+    with pytest.raises(dd.DDError):
+        inst.backward(1.0)
+
+
+def test_autograd_function(orc):
+    import torch
+
+    from paper_2205_11638_amd.autograd import dual_lower_bound
+    p = CASES["gm-small"]()
+    rng = np.random.default_rng(1)
+    inst, _, _ = make_instance(p)
+    c = torch.tensor(p.c, dtype=torch.float32, device="cuda", requires_grad=True)
+    om = torch.tensor(synth.sigmoid(rng.normal(size=p.nnz)), dtype=torch.float32, device="cuda", requires_grad=True)
+    ah = torch.tensor(rng.normal(0, 0.3, size=p.nnz), dtype=torch.float32, device="cuda", requires_grad=True)
+    lb = dual_lower_bound(inst, c, om, ah, 4, 2)
+    (-lb).backward()
+    pc = synth.Problem(p.n, f32(p.c), p.row_ptr, p.col, p.coef, p.sense, p.rhs)
+    al = orc.softmax_alpha(pc, f32(host(ah)))
+    lb_o, dw_o, da_o, dc_o, gap = orc.unrolled_grad(pc, f32(host(om)), al, 4, with_gap=True)
+    assert lb.item() == pytest.approx(lb_o, rel=1e-5)
+    assert gap >= GAP_MIN
+    close_grad(-host(c.grad), dc_o, "d_c")
+    close_grad(-host(om.grad), dw_o, "d_omega")
+    close_grad(-host(ah.grad), orc.softmax_alpha_vjp(pc, al, da_o), "d_alpha_hat")

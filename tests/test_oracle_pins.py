@@ -396,3 +396,54 @@ def test_softmax_vjp_matches_autograd(orc):
     den = torch.zeros(p.n, dtype=torch.float64).index_add(0, var, z)
     (z / den[var] @ torch.tensor(g)).backward()
     np.testing.assert_allclose(got, A.grad.numpy(), atol=1e-12)
+
+
+# ------------------------------------------------------------------------------------------
+# Positive homogeneity (every min-marginal, update and bound is a min over path sums, so
+# scaling (lambda, M, c) by t > 0 scales every output by t).  Euler's identity then holds for
+# the Jacobian of every linear piece that touches the point, so it pins any subgradient the
+# reverse mode may pick, ties included.
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("wl", ["gm", "setcover"])
+def test_pass_vjp_euler_identity(orc, wl):
+    p = synth.workload(wl, small=True)["problem"]
+    om, ah = learned_params(p, 11)
+    al = orc.softmax_alpha(p, ah)
+    lam, M = orc.run(p, om, al, 2)
+    rng = np.random.default_rng(12)
+    for direction in (0, 1):
+        dlo, dmo = rng.normal(size=p.nnz), rng.normal(size=p.nnz)
+        dli, dmi, _, _ = orc.pass_vjp(p, om, al, direction, lam, M, dlo, dmo)
+        lo, Mo = lam.copy(), M.copy()
+        orc.run_pass(p, om, al, lo, Mo, direction)
+        lhs = dli @ lam + dmi @ M
+        rhs = dlo @ lo + dmo @ Mo
+        scale = np.abs(dli * lam).sum() + np.abs(dmi * M).sum()
+        assert lhs == pytest.approx(rhs, abs=1e-10 * scale)
+
+
+@pytest.mark.parametrize("wl", ["gm", "setcover"])
+def test_unrolled_grad_euler_identity(orc, wl):
+    p = synth.workload(wl, small=True)["problem"]
+    om, ah = learned_params(p, 13)
+    al = orc.softmax_alpha(p, ah)
+    lb, _, _, dc = orc.unrolled_grad(p, om, al, 5)
+    assert dc @ p.c == pytest.approx(lb, abs=1e-10 * np.abs(dc * p.c).sum())
+
+
+def test_argmin_gap_reports_ties(orc):
+    p = tiny(77, n=12, m=8, kmax=6)
+    x, gap = orc.argmin(p, np.zeros(p.nnz), with_gap=True)
+    assert (gap[np.diff(p.row_ptr) > 0] == 0.0).all()  # all-zero costs: every decision is a tie
+    lam = np.random.default_rng(5).normal(size=p.nnz)
+    x2, gap2 = orc.argmin(p, lam, with_gap=True)
+    assert (gap2 > 0).all()  # continuous random costs: unique minimizers
+    np.testing.assert_array_equal(x2, orc.argmin(p, lam))
+    # a tie made on purpose: two equal-cost optima of a one-row at-most-one constraint
+    q = synth.random_tiny(3, n=3, m=1, kmin=3, kmax=3, amin=1, amax=1, senses=(-1,))
+    q = dataclasses.replace(q, rhs=np.array([1]))
+    _, g = orc.argmin(q, np.array([-1.0, -1.0, 0.5]), with_gap=True)
+    assert g[0] == 0.0
+    _, g = orc.argmin(q, np.array([-1.0, -1.25, 0.5]), with_gap=True)
+    assert g[0] > 0.1
