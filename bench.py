@@ -66,6 +66,47 @@ def cpu_baseline(prob, w, row_nodes, target_s=15.0):
                       f"{iters} dual iterations in {dt:.1f} s (fp64, OpenMP over rows)"}
 
 
+def adjoint_leg(inst, T, K, reps, stream):
+    """Time T unrolled iterations with checkpoints every K plus the reverse sweep back to
+    (omega, alpha, c), against the plain forward (reset, T iterations, lower bound) on the
+    same instance and stream."""
+    import torch
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def plain():
+        inst.reset()
+        inst.run(T)
+        inst.lower_bound()
+
+    def unrolled():
+        inst.forward_unrolled(T, K)
+        inst.backward(1.0)
+
+    unrolled()  # warm-up: allocates checkpoints and adjoint buffers
+    plain()
+    fwd_ms = timed(plain)
+    inst.profile_begin(max_launches=reps * (64 * T + 64) * max(1, inst.stats["classes"]) + 256)
+    both_ms = timed(unrolled)
+    prof = inst.profile_end()
+    kernels = {}
+    for name, (n, tot, b) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
+        log(f"[bench] adj  {name:28s} launches={n:6d} avg={tot / n * 1e3:9.1f} us  "
+            f"{b / (tot / n) / 1e6:8.1f} GB/s algorithmic")
+        kernels[name] = {"launches": n // reps, "avg_ms": tot / n, "gbs_algorithmic": b / (tot / n) / 1e6}
+    log(f"[bench] unrolled T={T} K={K}: fwd {fwd_ms:.2f} ms, fwd+bwd {both_ms:.2f} ms, ratio {both_ms / fwd_ms:.2f}")
+    return {"T": T, "ckpt_every": K, "plain_fwd_ms": fwd_ms, "fwd_bwd_ms": both_ms, "ratio": both_ms / fwd_ms,
+            "kernels": kernels}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +114,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="knapsack", choices=["knapsack", "indset", "gm", "setcover"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the unrolled forward + backward leg")
+    ap.add_argument("--adjoint-reps", type=int, default=2)
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -138,6 +181,7 @@ def main():
     achieved = b_dom / (tot_dom / n_dom) / 1e6   # bytes / ms -> GB/s
     arcs = int(st["arcs"])
     value = arcs * T / (ms / 1e3)
+    adj = None if args.no_adjoint else adjoint_leg(inst, T, int(w.get("ckpt") or 5), args.adjoint_reps, stream)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -163,6 +207,7 @@ def main():
                      "algorithmic_bytes_per_launch": b_dom, "avg_launch_ms": tot_dom / n_dom},
         "hbm_frac_step": (sum(b * n for n, _, b in prof.values()) / args.steps) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "lower_bound": lb[0],
+        "adjoint": adj,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
