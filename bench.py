@@ -107,6 +107,56 @@ def adjoint_leg(inst, T, K, reps, stream):
             "kernels": kernels}
 
 
+def batch_leg(T, stream):
+    """64 uneven set-cover / independent-set programs: T iterations of all of them packed into
+    one instance (one launch per kernel class per pass, graph replays) against the same T
+    iterations run program by program (each with its own graph replays), same stream."""
+    import torch
+
+    import paper_2205_11638_amd as dd
+    import synth
+
+    t0 = time.time()
+    w = synth.workload("batch")
+    ps = w["problems"]
+    bt = dd.Batch(ps)
+    singles = [dd.Instance(p) for p in ps]
+    arcs = int(bt.instance.stats["arcs"])
+    log(f"[bench] batch: {len(ps)} programs, n={sum(p.n for p in ps)}, edges={bt.instance.E}, arcs={arcs} "
+        f"({time.time() - t0:.1f}s)")
+
+    def timed(fn):
+        fn(10)  # warm-up (captures the graphs)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        fn(T)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    def packed(iters):
+        bt.run(iters)
+
+    def one_by_one(iters):
+        for inst in singles:
+            inst.run(iters)
+
+    ms_packed = timed(packed)
+    ms_seq = timed(one_by_one)
+    lbs, _ = bt.lower_bounds()
+    out = {"programs": len(ps), "iterations": T, "arcs": arcs, "packed_ms": ms_packed, "sequential_ms": ms_seq,
+           "packed_instances_per_s": len(ps) / (ms_packed / 1e3),
+           "sequential_instances_per_s": len(ps) / (ms_seq / 1e3),
+           "packed_arcs_per_s": arcs * T / (ms_packed / 1e3), "sequential_arcs_per_s": arcs * T / (ms_seq / 1e3),
+           "speedup": ms_seq / ms_packed, "lb_sum": float(np.sum(lbs))}
+    log(f"[bench] batch T={T}: packed {ms_packed:.1f} ms, one by one {ms_seq:.1f} ms ({ms_seq / ms_packed:.2f}x)")
+    for x in singles:
+        x.close()
+    bt.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +166,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the unrolled forward + backward leg")
     ap.add_argument("--adjoint-reps", type=int, default=2)
+    ap.add_argument("--no-batch", action="store_true", help="skip the packed-batch leg")
+    ap.add_argument("--batch-iters", type=int, default=500)
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -182,6 +234,7 @@ def main():
     arcs = int(st["arcs"])
     value = arcs * T / (ms / 1e3)
     adj = None if args.no_adjoint else adjoint_leg(inst, T, int(w.get("ckpt") or 5), args.adjoint_reps, stream)
+    bat = None if args.no_batch else batch_leg(args.batch_iters, stream)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -208,6 +261,7 @@ def main():
         "hbm_frac_step": (sum(b * n for n, _, b in prof.values()) / args.steps) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "lower_bound": lb[0],
         "adjoint": adj,
+        "batch": bat,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -78,7 +78,8 @@ typedef struct {
     int32_t waves_per_block;/* waves (tiles) per workgroup, default 4 */
     int32_t ckpt_every;     /* iterations between adjoint checkpoints, default 5 */
     int32_t lds_budget;     /* max LDS bytes per workgroup, default 64 KiB */
-    int32_t reserved[4];
+    int32_t no_graphs;      /* nonzero: dd_run launches every kernel itself instead of replaying graphs */
+    int32_t reserved[3];
 } dd_options;
 
 typedef struct {
@@ -138,7 +139,10 @@ int dd_set_state(dd_instance *h, const float *lambda, const float *M, void *stre
 int dd_get_state(dd_instance *h, float *lambda_out, float *M_out, int32_t flushed, void *stream);
 
 /* T iterations of Alg. 1: each a forward pass (hops in ascending variable order)
- * then a backward pass; every pass applies BlockUpdate to all hops of all rows. */
+ * then a backward pass; every pass applies BlockUpdate to all hops of all rows.
+ * For T >= 2 the iterations are replayed from HIP graphs captured on first use (one
+ * of 1 iteration, one of 8), unless the instance was created with no_graphs or is
+ * profiling; the launches, and so the results, are the same either way. */
 int dd_run(dd_instance *h, int32_t T, void *stream);
 
 /* One pass: direction 0 = forward, 1 = backward. */
@@ -207,6 +211,48 @@ typedef struct {
 } dd_kernel_time;
 int dd_profile_begin(dd_instance *h, int32_t max_launches);
 int dd_profile_end(dd_instance *h, dd_kernel_time *out, int32_t cap, int32_t *count);
+
+/* ---- Launch shapes -------------------------------------------------------------------------- */
+
+/* Kernel specialisation classes of the instance and their launch shapes.  Class c's entry is
+ * out[6c .. 6c+5] = {team size P, register rows RMAX, waves per workgroup of the forward and
+ * backward pass kernels, workgroups of the forward and backward pass kernels (0: one wave
+ * per tile; otherwise that many resident workgroups whose waves walk the tile list)}.
+ * *count receives the number of classes; at most cap entries are written. */
+int dd_get_launch(const dd_instance *h, int32_t *out, int32_t cap, int32_t *count);
+
+/* Set class c's pass-kernel launch shape (waves per workgroup 1..16 within the LDS budget;
+ * grid 0 or a positive workgroup count).  The arithmetic, and so every result, does not
+ * depend on the shape.  DD_E_ARG on an out-of-range class or an infeasible shape. */
+int dd_set_launch(dd_instance *h, int32_t c, int32_t wpb_f, int32_t wpb_b, int32_t grid_f, int32_t grid_b);
+
+/* Autotuner: time the forward and backward update kernels of every class over a small set
+ * of launch shapes (waves per workgroup x {one wave per tile, a resident grid of the size the
+ * CUs hold at once}) and keep the fastest.  cache_path (may be NULL) names a text file: a
+ * line "signature<TAB>shapes" per tuned instance shape, signature = device architecture and
+ * every class's (P, RMAX, tiles, nodes); a hit is applied without timing (*from_cache = 1).
+ * New results are appended.  The solver state is restored afterwards. */
+int dd_autotune(dd_instance *h, const char *cache_path, int32_t *from_cache, void *stream);
+
+/* ---- Batches: many programs packed into one instance ---------------------------------------- */
+
+/* A batch is the disjoint union of k programs (variables and rows of program q follow those
+ * of q-1): every pass over the batch is one launch per kernel class over all programs, and
+ * rows of different programs share tiles.  Since the programs share no variable, each one's
+ * iterates are those it would have alone.  dd_batch_instance returns the packed instance
+ * (owned by the batch) for every per-instance call; its edge, variable and row arrays are the
+ * programs' canonical arrays concatenated in batch order. */
+typedef struct dd_batch dd_batch;
+int dd_batch_create(const dd_problem *probs, int32_t k, const dd_options *opt, void *stream, dd_batch **out);
+int dd_batch_destroy(dd_batch *b);
+dd_instance *dd_batch_instance(dd_batch *b);
+/* Offsets of program q's variables, rows and edges: host arrays [k+1] each (may be NULL). */
+int dd_batch_offsets(const dd_batch *b, int64_t *var_off, int64_t *row_off, int64_t *edge_off);
+/* T iterations over every program (graph replays as in dd_run). */
+int dd_batch_run(dd_batch *b, int32_t T, void *stream);
+/* Per-program lower bounds (as dd_lower_bound, each with its own uncovered-variable
+ * constant): lbs[k] and, if not NULL, dls[k] (D_L).  Host arrays; synchronizes the stream. */
+int dd_batch_lower_bounds(dd_batch *b, double *lbs, double *dls, void *stream);
 
 /* Host-only helper: compile row `row` of prob and return its diagram.  width[L] gets
  * the node count per level (L = row length); arcs[nodes] gets, level by level, each

@@ -35,7 +35,7 @@ class dd_problem(C.Structure):
 
 class dd_options(C.Structure):
     _fields_ = [("nodes_per_lane", C.c_int32), ("waves_per_block", C.c_int32), ("ckpt_every", C.c_int32),
-                ("lds_budget", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("lds_budget", C.c_int32), ("no_graphs", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class dd_stats(C.Structure):
@@ -82,6 +82,15 @@ SIGNATURES = {
     "dd_profile_begin": ([_VP, C.c_int32], C.c_int),
     "dd_profile_end": ([_VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "dd_compile_row": ([C.POINTER(dd_problem), C.c_int32, _VP, _VP, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+    "dd_get_launch": ([_VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
+    "dd_set_launch": ([_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32], C.c_int),
+    "dd_autotune": ([_VP, C.c_char_p, C.POINTER(C.c_int32), _VP], C.c_int),
+    "dd_batch_create": ([C.POINTER(dd_problem), C.c_int32, C.POINTER(dd_options), _VP, C.POINTER(_VP)], C.c_int),
+    "dd_batch_destroy": ([_VP], C.c_int),
+    "dd_batch_instance": ([_VP], _VP),
+    "dd_batch_offsets": ([_VP, _VP, _VP, _VP], C.c_int),
+    "dd_batch_run": ([_VP, C.c_int32, _VP], C.c_int),
+    "dd_batch_lower_bounds": ([_VP, _VP, _VP, _VP], C.c_int),
 }
 
 
@@ -157,29 +166,47 @@ def compile_row(prob, row):
     return w[:length], arcs[:nodes.value]
 
 
+def _options(nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0, graphs=True):
+    return dd_options(int(nodes_per_lane), int(waves_per_block), int(ckpt_every), int(lds_budget),
+                      0 if graphs else 1)
+
+
 class Instance:
     """A binary program resident on the current GPU (see include/dd.h for the semantics)."""
 
-    def __init__(self, prob, nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0):
+    def __init__(self, prob, nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0, graphs=True):
         import torch
         L_ = lib()
         pa = _ProblemArgs(prob)
-        opt = dd_options(int(nodes_per_lane), int(waves_per_block), int(ckpt_every), int(lds_budget))
+        opt = _options(nodes_per_lane, waves_per_block, lds_budget, ckpt_every, graphs)
         h = C.c_void_p()
         # input validation and compilation run on the host before any HIP call
         stream = _stream() if torch.cuda.is_available() else None
         _check(L_.dd_create(C.byref(pa.st), C.byref(opt), stream, C.byref(h)))
+        self._attach(L_, h, owned=True)
+
+    def _attach(self, L_, h, owned):
+        import torch
         self._h = h
         self._L = L_
+        self._owned = owned
         st = dd_stats()
         _check(L_.dd_get_stats(h, C.byref(st)))
         self.stats = st.as_dict()
         self.n, self.m, self.E = int(st.n), int(st.m), int(st.edges)
         self.device = torch.device("cuda", torch.cuda.current_device())
 
+    @classmethod
+    def _borrowed(cls, L_, h):
+        """View of an instance owned by someone else (a batch)."""
+        self = cls.__new__(cls)
+        self._attach(L_, h, owned=False)
+        return self
+
     def close(self):
         if getattr(self, "_h", None):
-            self._L.dd_destroy(self._h)
+            if self._owned:
+                self._L.dd_destroy(self._h)
             self._h = None
 
     __del__ = close
@@ -278,9 +305,70 @@ class Instance:
         _check(self._L.dd_pass_vjp(self._h, int(direction), *args, *[_dptr(o) for o in outs], _stream()))
         return tuple(outs)  # dlam_in, dM_in, d_alpha, d_omega
 
+    def launch_shapes(self):
+        """[{P, RMAX, wpb_f, wpb_b, grid_f, grid_b}] per kernel class."""
+        cnt = C.c_int32()
+        _check(self._L.dd_get_launch(self._h, None, 0, C.byref(cnt)))
+        out = np.zeros(6 * max(cnt.value, 1), dtype=np.int32)
+        _check(self._L.dd_get_launch(self._h, out.ctypes.data_as(C.c_void_p), cnt.value, C.byref(cnt)))
+        keys = ("P", "RMAX", "wpb_f", "wpb_b", "grid_f", "grid_b")
+        return [dict(zip(keys, map(int, out[6 * i:6 * i + 6]))) for i in range(cnt.value)]
+
+    def set_launch(self, c, wpb_f, wpb_b, grid_f=0, grid_b=0):
+        _check(self._L.dd_set_launch(self._h, int(c), int(wpb_f), int(wpb_b), int(grid_f), int(grid_b)))
+
+    def autotune(self, cache_path=None):
+        """Time launch shapes of the pass kernels and keep the fastest; True if read from the cache."""
+        hit = C.c_int32()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(self._L.dd_autotune(self._h, path, C.byref(hit), _stream()))
+        return bool(hit.value)
+
     def seg_softmax_vjp(self, alpha, d_alpha):
         import torch
         out = self._f32(self.E)
         _check(self._L.dd_seg_softmax_vjp(self._h, _dptr(alpha, torch.float32, self.E),
                                           _dptr(d_alpha, torch.float32, self.E), _dptr(out), _stream()))
         return out
+
+
+class Batch:
+    """Several programs packed into one device instance (include/dd.h, dd_batch_*).
+
+    `instance` is the packed instance: per-edge / per-variable arrays are the programs'
+    canonical arrays concatenated; `var_off`, `row_off`, `edge_off` give each program's slice."""
+
+    def __init__(self, probs, **opts):
+        import torch
+        L_ = lib()
+        pas = [_ProblemArgs(p) for p in probs]
+        k = len(pas)
+        arr = (dd_problem * k)(*[pa.st for pa in pas])
+        opt = _options(**opts)
+        b = C.c_void_p()
+        stream = _stream() if torch.cuda.is_available() else None
+        _check(L_.dd_batch_create(arr, k, C.byref(opt), stream, C.byref(b)))
+        self._b, self._L, self.k = b, L_, k
+        self.instance = Instance._borrowed(L_, C.c_void_p(L_.dd_batch_instance(b)))
+        offs = [np.zeros(k + 1, dtype=np.int64) for _ in range(3)]
+        _check(L_.dd_batch_offsets(b, *[o.ctypes.data_as(C.c_void_p) for o in offs]))
+        self.var_off, self.row_off, self.edge_off = offs
+
+    def close(self):
+        if getattr(self, "_b", None):
+            self.instance.close()
+            self._L.dd_batch_destroy(self._b)
+            self._b = None
+
+    __del__ = close
+
+    def run(self, T):
+        _check(self._L.dd_batch_run(self._b, int(T), _stream()))
+
+    def lower_bounds(self):
+        """(lbs [k], dls [k]) as numpy float64 arrays."""
+        lbs = np.zeros(self.k)
+        dls = np.zeros(self.k)
+        _check(self._L.dd_batch_lower_bounds(self._b, lbs.ctypes.data_as(C.c_void_p), dls.ctypes.data_as(C.c_void_p),
+                                             _stream()))
+        return lbs, dls

@@ -16,11 +16,13 @@
 
 #include "../../include/dd.h"
 #include "bdd.hpp"
+#include "instance.hpp"
 #include "kernels.hpp"
 
 using namespace dd;
+using namespace ddi;
 
-namespace {
+namespace ddi {
 
 thread_local std::string g_err;
 
@@ -34,11 +36,9 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(x)                                                                                  \
-    do {                                                                                            \
-        hipError_t e_ = (x);                                                                        \
-        if (e_ != hipSuccess) return fail(DD_E_HIP, "%s: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__); \
-    } while (0)
+}  // namespace ddi
+
+namespace {
 
 int worker_count() {
     const char *env = getenv("DD_THREADS");
@@ -150,81 +150,8 @@ struct HostPlan {
 
 }  // namespace
 
-struct dd_instance {
-    int device = 0;
-    int64_t n = 0, m = 0, E = 0, nodes = 0;
-    int max_width = 0, max_len = 0, uncovered = 0;
-    double unc_const = 0.0;
-    int ckpt_default = 5;
-    std::vector<ClassLaunch> classes;
-    int64_t ntiles = 0, node_slots = 0, edge_slots = 0, device_bytes = 0;
-    std::vector<int32_t> edge_var, edge_row;  // canonical edge map (host)
-    std::vector<int64_t> row_nodes;
-    // profiling: event pairs recorded around launches while enabled
-    struct Rec {
-        int kernel;
-        hipEvent_t a, b;
-    };
-    bool prof = false;
-    std::vector<hipEvent_t> pool;
-    size_t pool_used = 0;
-    std::vector<Rec> recs;
-    std::vector<std::string> kname;
-    std::vector<double> kbytes;
-    int kernel_id(const std::string &name, double bytes) {
-        for (size_t q = 0; q < kname.size(); ++q)
-            if (kname[q] == name) return (int)q;
-        kname.push_back(name);
-        kbytes.push_back(bytes);
-        return (int)kname.size() - 1;
-    }
-    // device buffers
-    std::vector<void *> allocs;
-    DevTables T{};
-    int32_t *var_ptr = nullptr, *var_slots = nullptr, *var_canon = nullptr, *canon2slot = nullptr;
-    float *cdev = nullptr, *S = nullptr, *aS = nullptr, *omega = nullptr, *alpha = nullptr, *tmp = nullptr;
-    double *red = nullptr;   // device reduction output [4]
-    double *partial = nullptr;  // [kSumBlocks] reduction scratch
-    bool en_lam_valid = false;  // T.en_lam holds E^j at the current multipliers
-    // reverse mode (buffers allocated on first use)
-    bool adj_ready = false;
-    float *lam_in = nullptr, *dlamA = nullptr, *dlamB = nullptr, *dMA = nullptr, *dMB = nullptr, *g = nullptr;
-    float *dalpha = nullptr, *domega = nullptr, *rec_val = nullptr, *scratch_n = nullptr;
-    int32_t *rec_idx = nullptr;
-    std::vector<float *> ck_lam, ck_M;    // checkpoints of the unrolled forward (state at iterations 0, K, 2K, ..., T)
-    std::vector<float *> seg_lam, seg_M;  // pass-input states inside one checkpoint segment
-    int fwd_T = -1, fwd_K = 0;
-    int64_t version = 0, fwd_version = -1;  // the recorded forward is valid while the state is unchanged
-    double *red_host = nullptr;  // pinned
-    int32_t *flags = nullptr;
 
-    // side streams (default priority) and fork/join events for concurrent class launches
-    std::vector<hipStream_t> side;
-    std::vector<hipEvent_t> join;
-    hipEvent_t fork = nullptr;
-
-    ~dd_instance() {
-        for (hipEvent_t e : join) (void)hipEventDestroy(e);
-        if (fork) (void)hipEventDestroy(fork);
-        for (hipStream_t q : side) (void)hipStreamDestroy(q);
-        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
-        for (void *p : allocs) (void)hipFree(p);
-        if (red_host) (void)hipHostFree(red_host);
-    }
-    template <class T_>
-    int alloc(T_ **p, size_t count) {
-        void *q = nullptr;
-        size_t bytes = std::max<size_t>(count, 1) * sizeof(T_);
-        hipError_t e = hipMalloc(&q, bytes);
-        if (e != hipSuccess) return fail(DD_E_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
-        allocs.push_back(q);
-        device_bytes += (int64_t)bytes;
-        *p = (T_ *)q;
-        return DD_OK;
-    }
-};
-
-namespace {
+namespace ddi {
 
 template <class T_>
 int upload(dd_instance *h, T_ **dst, const std::vector<T_> &src, hipStream_t s) {
@@ -427,23 +354,6 @@ double algorithmic_bytes(bool fwd, int mode, const ClassLaunch &c) {
     }
 }
 
-template <class F>
-int recorded(dd_instance *h, const char *name, double bytes, hipStream_t s, F launch) {
-    hipEvent_t a = nullptr, b = nullptr;
-    const bool rec = h->prof && h->pool_used + 2 <= h->pool.size();
-    if (rec) {
-        a = h->pool[h->pool_used++];
-        b = h->pool[h->pool_used++];
-        HIP_TRY(hipEventRecord(a, s));
-    }
-    hipError_t e = launch();
-    if (e != hipSuccess) return fail(DD_E_HIP, "%s launch: %s", name, hipGetErrorString(e));
-    if (rec) {
-        HIP_TRY(hipEventRecord(b, s));
-        h->recs.push_back({h->kernel_id(name, bytes), a, b});
-    }
-    return DD_OK;
-}
 
 // The classes of one sweep are independent launches; all but the first run on side streams
 // forked from (and joined back into) the caller's stream, so their tails overlap.
@@ -480,7 +390,17 @@ int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
         [&](const ClassLaunch &cl, hipStream_t cs) {
             return fwd ? launch_fwd(h->T, cl, mode, cs) : launch_bwd(h->T, cl, mode, cs);
         },
-        [&](const ClassLaunch &cl) { return kname(fwd ? "k_fwd" : "k_bwd", cl, mode); },
+        [&](const ClassLaunch &cl) {
+            // the template arguments as the profiler prints them; the last says whether the
+            // waves of a resident grid walk the tile list
+            const int wpb = fwd ? cl.wpb_f : cl.wpb_b, grid = fwd ? cl.grid_f : cl.grid_b;
+            const bool loop = mode == (fwd ? (int)FWD_UPDATE : (int)BWD_UPDATE) && grid > 0 &&
+                              (int64_t)grid < (cl.ntiles + wpb - 1) / wpb;
+            char name[96];
+            snprintf(name, sizeof name, "%s<%d, %d, %d, %s>", fwd ? "k_fwd" : "k_bwd", cl.P, cl.RMAX, mode,
+                     loop ? "true" : "false");
+            return std::string(name);
+        },
         [&](const ClassLaunch &cl) { return algorithmic_bytes(fwd, mode, cl); });
 }
 
@@ -513,7 +433,13 @@ int recompute_B(dd_instance *h, hipStream_t s) {
     return st;
 }
 
-}  // namespace
+int pass_launches(dd_instance *h, int dir, hipStream_t s) {
+    int st = deferred(h, s);
+    if (st) return st;
+    return all_classes(h, dir == 0, dir == 0 ? (int)FWD_UPDATE : (int)BWD_UPDATE, s);
+}
+
+}  // namespace ddi
 
 extern "C" {
 
@@ -603,6 +529,8 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     dd_instance *h = new dd_instance();
     h->device = device;
     if (o.ckpt_every > 0) h->ckpt_default = o.ckpt_every;
+    h->use_graphs = o.no_graphs == 0;
+    h->lds_budget = lds_budget;
     h->n = prob->n;
     h->m = m;
     h->E = sr.ptr[m];
@@ -810,25 +738,78 @@ int dd_get_state(dd_instance *h, float *lambda_out, float *M_out, int32_t flushe
 
 int dd_run_pass(dd_instance *h, int32_t direction, void *stream) {
     if (!h || (direction != 0 && direction != 1)) return fail(DD_E_ARG, "bad instance or direction");
-    hipStream_t s = (hipStream_t)stream;
-    int st = deferred(h, s);
-    if (st) return st;
     // a backward pass ends with B(root) = E^j at the updated multipliers; a forward pass
     // changes the multipliers without computing it
     h->en_lam_valid = false;
     h->version++;
-    st = all_classes(h, direction == 0, direction == 0 ? (int)FWD_UPDATE : (int)BWD_UPDATE, s);
+    int st = pass_launches(h, direction, (hipStream_t)stream);
     h->en_lam_valid = st == DD_OK && direction == 1;
     return st;
 }
 
+}  // extern "C"
+
+namespace {
+
+constexpr int kGraphChunk = 8;  // iterations per replay of the large graph
+
+// Capture `iters` dual iterations (2 passes each) into an executable graph.  Capture runs on
+// the instance's own stream (the caller's may be the legacy default stream, which cannot be
+// captured); the executable graph is then launched on any stream.
+int capture_iterations(dd_instance *h, int iters, hipGraphExec_t *out) {
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int st = DD_OK;
+    for (int t = 0; t < iters && st == DD_OK; ++t)
+        for (int d = 0; d < 2 && st == DD_OK; ++d) st = pass_launches(h, d, h->cap_stream);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (st != DD_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != DD_OK ? st : fail(DD_E_HIP, "graph capture: %s", hipGetErrorString(e));
+    }
+    const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(DD_E_HIP, "graph instantiate: %s", hipGetErrorString(ei));
+    return DD_OK;
+}
+
+}  // namespace
+
+namespace ddi {
+
+void drop_graphs(dd_instance *h) {
+    if (h->graph_one) (void)hipGraphExecDestroy(h->graph_one);
+    if (h->graph_chunk) (void)hipGraphExecDestroy(h->graph_chunk);
+    h->graph_one = h->graph_chunk = nullptr;
+}
+
+}  // namespace ddi
+
+extern "C" {
+
 int dd_run(dd_instance *h, int32_t T, void *stream) {
     if (!h || T < 0) return fail(DD_E_ARG, "bad instance or T");
-    for (int t = 0; t < T; ++t)
-        for (int d = 0; d < 2; ++d) {
-            int st = dd_run_pass(h, d, stream);
-            if (st) return st;
-        }
+    if (T == 0) return DD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    if (h->prof || !h->use_graphs || T == 1) {  // eager launches (profiling brackets each one)
+        for (int t = 0; t < T; ++t)
+            for (int d = 0; d < 2; ++d) {
+                int st = dd_run_pass(h, d, stream);
+                if (st) return st;
+            }
+        return DD_OK;
+    }
+    int st;
+    if (!h->graph_one && (st = capture_iterations(h, 1, &h->graph_one))) return st;
+    if (T >= kGraphChunk && !h->graph_chunk && (st = capture_iterations(h, kGraphChunk, &h->graph_chunk)))
+        return st;
+    h->en_lam_valid = false;
+    int t = 0;
+    for (; t + kGraphChunk <= T; t += kGraphChunk) HIP_TRY(hipGraphLaunch(h->graph_chunk, s));
+    for (; t < T; ++t) HIP_TRY(hipGraphLaunch(h->graph_one, s));
+    h->version += 2 * (int64_t)T;
+    h->en_lam_valid = true;
     return DD_OK;
 }
 

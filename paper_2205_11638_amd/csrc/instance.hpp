@@ -1,0 +1,144 @@
+// instance.hpp -- host-side state of a device instance and the launch helpers shared by the
+// C ABI's translation units.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/dd.h"
+#include "kernels.hpp"
+
+namespace ddi {
+// Record a thread-local error message and return code.
+int fail(int code, const char *fmt, ...);
+}  // namespace ddi
+
+#define HIP_TRY(x)                                                                                            \
+    do {                                                                                                      \
+        hipError_t e_ = (x);                                                                                  \
+        if (e_ != hipSuccess)                                                                                 \
+            return ddi::fail(DD_E_HIP, "%s: %s (%s:%d)", #x, hipGetErrorString(e_), __FILE__, __LINE__);      \
+    } while (0)
+
+using dd::ClassLaunch;
+using dd::DevTables;
+
+struct dd_instance {
+    int device = 0;
+    int64_t n = 0, m = 0, E = 0, nodes = 0;
+    int max_width = 0, max_len = 0, uncovered = 0;
+    double unc_const = 0.0;
+    int ckpt_default = 5;
+    int lds_budget = 64 * 1024;  // max LDS bytes per workgroup
+    std::vector<ClassLaunch> classes;
+    int64_t ntiles = 0, node_slots = 0, edge_slots = 0, device_bytes = 0;
+    std::vector<int32_t> edge_var, edge_row;  // canonical edge map (host)
+    std::vector<int64_t> row_nodes;
+    // profiling: event pairs recorded around launches while enabled
+    struct Rec {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    bool prof = false;
+    std::vector<hipEvent_t> pool;
+    size_t pool_used = 0;
+    std::vector<Rec> recs;
+    std::vector<std::string> kname;
+    std::vector<double> kbytes;
+    int kernel_id(const std::string &name, double bytes) {
+        for (size_t q = 0; q < kname.size(); ++q)
+            if (kname[q] == name) return (int)q;
+        kname.push_back(name);
+        kbytes.push_back(bytes);
+        return (int)kname.size() - 1;
+    }
+    // device buffers
+    std::vector<void *> allocs;
+    DevTables T{};
+    int32_t *var_ptr = nullptr, *var_slots = nullptr, *var_canon = nullptr, *canon2slot = nullptr;
+    float *cdev = nullptr, *S = nullptr, *aS = nullptr, *omega = nullptr, *alpha = nullptr, *tmp = nullptr;
+    double *red = nullptr;   // device reduction output [4]
+    double *partial = nullptr;  // [kSumBlocks] reduction scratch
+    bool en_lam_valid = false;  // T.en_lam holds E^j at the current multipliers
+    // reverse mode (buffers allocated on first use)
+    bool adj_ready = false;
+    float *lam_in = nullptr, *dlamA = nullptr, *dlamB = nullptr, *dMA = nullptr, *dMB = nullptr, *g = nullptr;
+    float *dalpha = nullptr, *domega = nullptr, *rec_val = nullptr, *scratch_n = nullptr;
+    int32_t *rec_idx = nullptr;
+    std::vector<float *> ck_lam, ck_M;    // checkpoints of the unrolled forward (state at iterations 0, K, 2K, ..., T)
+    std::vector<float *> seg_lam, seg_M;  // pass-input states inside one checkpoint segment
+    int fwd_T = -1, fwd_K = 0;
+    int64_t version = 0, fwd_version = -1;  // the recorded forward is valid while the state is unchanged
+    double *red_host = nullptr;  // pinned
+    int32_t *flags = nullptr;
+
+    // side streams (default priority) and fork/join events for concurrent class launches
+    std::vector<hipStream_t> side;
+    std::vector<hipEvent_t> join;
+    hipEvent_t fork = nullptr;
+
+    // iterations replayed from captured graphs (capture happens on cap_stream; launches go
+    // to the caller's stream)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t graph_one = nullptr, graph_chunk = nullptr;
+    bool use_graphs = true;
+
+    ~dd_instance() {
+        if (graph_one) (void)hipGraphExecDestroy(graph_one);
+        if (graph_chunk) (void)hipGraphExecDestroy(graph_chunk);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (hipEvent_t e : join) (void)hipEventDestroy(e);
+        if (fork) (void)hipEventDestroy(fork);
+        for (hipStream_t q : side) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+        for (void *p : allocs) (void)hipFree(p);
+        if (red_host) (void)hipHostFree(red_host);
+    }
+    template <class T_>
+    int alloc(T_ **p, size_t count) {
+        void *q = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T_);
+        hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) return ddi::fail(DD_E_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
+        allocs.push_back(q);
+        device_bytes += (int64_t)bytes;
+        *p = (T_ *)q;
+        return DD_OK;
+    }
+};
+
+namespace ddi {
+
+// Launch through `launch` (returns hipError_t); while profiling, bracket it with events on s.
+template <class F>
+inline int recorded(dd_instance *h, const char *name, double bytes, hipStream_t s, F launch) {
+    hipEvent_t a = nullptr, b = nullptr;
+    const bool rec = h->prof && h->pool_used + 2 <= h->pool.size();
+    if (rec) {
+        a = h->pool[h->pool_used++];
+        b = h->pool[h->pool_used++];
+        HIP_TRY(hipEventRecord(a, s));
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return fail(DD_E_HIP, "%s launch: %s", name, hipGetErrorString(e));
+    if (rec) {
+        HIP_TRY(hipEventRecord(b, s));
+        h->recs.push_back({h->kernel_id(name, bytes), a, b});
+    }
+    return DD_OK;
+}
+
+// S and alpha*S of the current M (start of a pass).
+int deferred(dd_instance *h, hipStream_t s);
+// One sweep (pass-kernel mode) over every class, classes concurrently on side streams.
+int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s);
+// B at the current multipliers, stored (what a forward pass reads).
+int recompute_B(dd_instance *h, hipStream_t s);
+// The launches of one pass (deferred sums, then the update sweep of every class); host flags untouched.
+int pass_launches(dd_instance *h, int dir, hipStream_t s);
+// Forget captured iteration graphs (after a change of launch shapes).
+void drop_graphs(dd_instance *h);
+
+}  // namespace ddi

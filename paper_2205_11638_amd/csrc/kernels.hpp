@@ -58,6 +58,7 @@ struct ClassLaunch {
     int NL;        // max levels of a tile in the class
     int wpb_f, wpb_b;  // waves per workgroup of the forward / backward kernels
     int wpb_af, wpb_ab;  // waves per workgroup of the push-form / pull-form adjoint sweeps
+    int grid_f, grid_b;  // workgroups of the pass kernels (0: one wave per tile; else resident waves walk the tiles)
     int64_t tile0, ntiles;
     int64_t nodes, edges, rows;  // real (unpadded) counts covered by one launch, for byte accounting
 };
@@ -107,6 +108,10 @@ hipError_t launch_fill(float *x, float v, int64_t n, hipStream_t s);
 hipError_t launch_uncovered(const int32_t *var_ptr, const float *c, float *out, int n, hipStream_t s);
 
 hipError_t launch_fwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
+// Workgroups of the update-pass kernel of class c (at its waves per workgroup) one CU holds at once.
+int pass_blocks_per_cu(const ClassLaunch &c, bool fwd);
+// out[q] = fp64 sum over x[seg[q] .. seg[q+1]) (of min(0, x) when neg_part), fixed order, q < k.
+hipError_t launch_seg_sum(const float *x, const int64_t *seg, int k, int neg_part, double *out, hipStream_t s);
 hipError_t launch_bwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
 bool class_supported(int P, int RMAX);
 

@@ -144,3 +144,9 @@ def test_unsorted_columns_are_sorted(dd):
     w2, a2 = dd.compile_row(p, 0)
     np.testing.assert_array_equal(w1, w2)
     np.testing.assert_array_equal(a1, a2)
+
+
+def test_batch_needs_programs(dd):
+    with pytest.raises(dd.DDError) as e:
+        dd.Batch([])
+    assert e.value.code == dd.binding.DD_E_ARG
