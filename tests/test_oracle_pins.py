@@ -447,3 +447,76 @@ def test_argmin_gap_reports_ties(orc):
     assert g[0] == 0.0
     _, g = orc.argmin(q, np.array([-1.0, -1.25, 0.5]), with_gap=True)
     assert g[0] > 0.1
+
+
+# ------------------------------------------------------------------------------------------
+# Finite differences on the graph-matching shape: every coordinate of a 50-assignment-variable
+# instance, and random directions on a 50-variable slice of the full-size instance (T = 20).
+# ------------------------------------------------------------------------------------------
+
+def _fd_check(f, f0, g_dot, h, tol, kink=1e-3):
+    fp, fm = f(h), f(-h)
+    if abs((fp - f0) - (f0 - fm)) > kink * abs(fp - fm) + 1e-12:  # a kink between the two sides
+        return None
+    return abs((fp - fm) / (2 * h) - g_dot) <= tol * max(1.0, abs(g_dot))
+
+
+def test_unrolled_grad_fd_gm_mini(orc):
+    p = synth.graph_matching(n_left=5, n_right=10, cand=10, n_pairs=60, seed=35)
+    assert p.n == 110
+    om, ah = learned_params(p, 34)
+    al = orc.softmax_alpha(p, ah)
+    T = 20
+    lb, dw, da, dc = orc.unrolled_grad(p, om, al, T)
+    checked = skipped = 0
+    for k in range(p.nnz):
+        for which, g in (("w", dw), ("a", da)):
+            def f(h, k=k, which=which):
+                x = (om if which == "w" else al).copy()
+                x[k] += h
+                return orc.lb_after(p, x, al, T) if which == "w" else orc.lb_after(p, om, x, T)
+            r = _fd_check(f, lb, g[k], 1e-6, 1e-5)
+            if r is None:
+                skipped += 1
+                continue
+            assert r, (which, k)
+            checked += 1
+    for i in range(p.n):
+        def f(h, i=i):
+            c = p.c.copy()
+            c[i] += h
+            return orc.lb_after(p, om, al, T, c=c)
+        r = _fd_check(f, lb, dc[i], 1e-6, 1e-5)
+        if r is None:
+            skipped += 1
+            continue
+        assert r, ("c", i)
+        checked += 1
+    assert checked >= 0.9 * (2 * p.nnz + p.n), (checked, skipped)
+
+
+@pytest.mark.slow
+def test_unrolled_grad_directional_fd_gm_full(orc):
+    w = synth.workload("gm")
+    p = w["problem"]
+    om, ah = w["omega"], w["alpha_hat"]
+    al = orc.softmax_alpha(p, ah)
+    T = 20
+    lb, dw, da, dc = orc.unrolled_grad(p, om, al, T)
+    on_e = np.isin(p.col, np.arange(50)).astype(np.float64)  # edges of assignment variables 0..49
+    on_v = (np.arange(p.n) < 50).astype(np.float64)
+    rng = np.random.default_rng(40)
+    checked = 0
+    for k in range(8):
+        d_w, d_a, d_c = (rng.normal(size=p.nnz) * on_e, rng.normal(size=p.nnz) * on_e * 0.1,
+                         rng.normal(size=p.n) * on_v)
+        g_dot = dw @ d_w + da @ d_a + dc @ d_c
+        # h balances fp64 rounding of a bound of size ~5e4 against the decisions that flip
+        # somewhere among 600k rows within +-h (each bends the slope a little)
+        r = _fd_check(lambda h: orc.lb_after(p, om + h * d_w, al + h * d_a, T, c=p.c + h * d_c), lb, g_dot, 1e-5,
+                      1e-4, kink=1e-2)
+        if r is None:
+            continue
+        assert r, k
+        checked += 1
+    assert checked >= 6
