@@ -32,36 +32,50 @@ namespace {
 
 using namespace dev;
 
+// Per-edge inputs of one hop, loaded one hop ahead.  Update sweeps: the multipliers after
+// (lam_use) and before (lam_old) the replayed pass, the output adjoints, omega, alpha, S of
+// the variable, and the d_alpha / d_omega accumulated so far.  Fixed sweeps: the multiplier
+// the side was computed with, the dlambda_in accumulated by the update sweep, and the record
+// (two node indices and adjoints) handed over by the update sweep.
 struct AdjEdge {
-    float lam_use;   // multiplier on the hi arcs of the swept side
-    float lam_old;   // pass-input multiplier (update sweeps)
-    float dlo, dMo;  // adjoints of the pass outputs (update sweeps)
-    float om, al, S;
+    float lam_use, lam_old, dlo, dMo, om, al, S, da, dw;
+    float dl;
+    int i0, i1;
+    float v0, v1;
 };
 
 template <bool UPD>
-__device__ __forceinline__ AdjEdge adj_edge(const DevTables &T, const AdjTables &A, int e, bool valid, bool bar) {
-    AdjEdge x{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    if (!valid) return x;
+__device__ __forceinline__ AdjEdge adj_edge(const DevTables &T, const AdjTables &A, int e, bool bar, bool rec) {
+    AdjEdge x{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, -1, 0.f, 0.f};
     if (UPD) {
-        x.lam_use = T.lam[e];  // after the replayed pass: the updated multipliers
+        x.lam_use = T.lam[e];
         x.lam_old = A.lam_in[e];
         x.dlo = A.dlam_out[e];
         x.dMo = A.dM_out[e];
         x.om = T.omega[e];
         x.al = T.alpha[e];
-        x.S = T.S[T.evar[e]];
+        x.S = A.Se[e];
+        x.da = A.dalpha[e];
+        x.dw = A.domega[e];
     } else {
         x.lam_use = A.lam_src[e];
         if (bar) x.lam_use = x.lam_use + T.aS[e];
+        x.dl = A.dlam_in[e];
+        if (rec) {
+            x.i0 = A.rec_idx[2 * e];
+            x.i1 = A.rec_idx[2 * e + 1];
+            x.v0 = A.rec_val[2 * e];
+            x.v1 = A.rec_val[2 * e + 1];
+        }
     }
     return x;
 }
 
 // ------------------------------------------------------------------------------------------
-// Push-form sweep (F side), against the level order: l = L-1 .. 0.
-// LDS per wave: Fv[2], Fa[2] (cost and adjoint of levels l+1 / l), bid (ints), Bst (B of the
-// level below, update sweeps), then the level table.
+// Push-form sweep (F side), against the level order: l = L-1 .. 0.  Every global operand of
+// hop l-1 (topology, F, B of level l, edge data) is loaded during hop l.
+// LDS per wave: Fv, Fa (cost and adjoint of level l+1, overwritten by level l at the end of
+// the hop), bid (ints), Bst (B of level l+1, update sweeps), then the level table.
 // ------------------------------------------------------------------------------------------
 template <int P, int RMAX, bool UPD>
 __global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int WB,
@@ -73,8 +87,8 @@ __global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t
     const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;
     float *Fv = lds_f + (size_t)wave * lds_words_adj_F(P, WB, NL);
-    float *Fa = Fv + 2 * WB * G;
-    int *bid = (int *)(Fa + 2 * WB * G);
+    float *Fa = Fv + WB * G;
+    int *bid = (int *)(Fa + WB * G);
     float *Bst = (float *)(bid + WB * G);
     int *meta = (int *)(Bst + WB * G);
     int *off = meta + NL * G;
@@ -83,7 +97,7 @@ __global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t
     const int nlev = tc.nlev;
     auto level = [&](int l) {
         Lev v{0, 0, 0};
-        if (l < nlev) {
+        if (l >= 0 && l < nlev) {
             const int w = meta[l * G + g] & 0xFFFF;
             v.W = G == 1 ? uni(w) : w;
             v.R = uni(meta[l * G] >> 16);
@@ -92,46 +106,54 @@ __global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t
         return v;
     };
     const int mine = p * G + g;
-    int cur = 0;     // Fv/Fa[cur]: level l+1
-    Lev c1{0, 0, 0};  // level l+1 (terminals only below the last level)
+    Lev c0 = level(nlev - 1), c1{0, 0, 0};  // levels l and l+1 (terminals only below the last level)
+    uint32_t tpn[RMAX];
+    float fvn[RMAX], bvn[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        tpn[r] = r < c0.R ? T.topo[c0.base + r * 64 + lane] : 0u;
+        fvn[r] = r < c0.R ? T.F[c0.base + r * 64 + lane] : kInf;
+        bvn[r] = 0.f;
+    }
+    AdjEdge xn = adj_edge<UPD>(T, A, tc.ebase + (nlev - 1) * G + g, false, true);
     for (int l = nlev - 1; l >= 0; --l) {
-        const Lev c0 = level(l);
         const int Wn = c1.W;
         const int e = tc.ebase + l * G + g;
-        const AdjEdge x = adj_edge<UPD>(T, A, e, c0.W > 0, false);
-        const float *fv1 = Fv + cur * WB * G, *fa1 = Fa + cur * WB * G;
-        float *fv0 = Fv + (cur ^ 1) * WB * G, *fa0 = Fa + (cur ^ 1) * WB * G;
+        const AdjEdge x = xn;
         uint32_t tp[RMAX];
         float fv[RMAX];
         const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
-        const uint32_t *tg = T.topo + c0.base;
-        const float *fg = T.F + c0.base;
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            if (r < c0.R) {
-                const bool ok = in_level<P>(r, c0.R, lane, c0.W);
-                tp[r] = ok ? tg[r * 64 + lane] : dead;
-                fv[r] = ok ? fg[r * 64 + lane] : kInf;
+            tp[r] = tpn[r];
+            fv[r] = fvn[r];
+            if (r < c0.R && !in_level<P>(r, c0.R, lane, c0.W)) {
+                tp[r] = dead;
+                fv[r] = kInf;
             }
+            if (UPD && r < c1.R) Bst[mine + r * P * G] = bvn[r];  // B of level l+1
         }
-        if (UPD) {  // B of level l+1 with the terminals after it
-            const float *bg = T.B + c1.base;
+        if (UPD && p == 0) {
+            Bst[Wn * G + g] = kInf;
+            Bst[(Wn + 1) * G + g] = 0.f;
+        }
+        // prefetch hop l-1: topology and F of level l-1, B of level l, edge data of level l-1
+        const Lev cp = level(l - 1);
 #pragma unroll
-            for (int r = 0; r < RMAX; ++r)
-                if (r < c1.R) Bst[mine + r * P * G] = bg[r * 64 + lane];
-            if (p == 0) {
-                Bst[Wn * G + g] = kInf;
-                Bst[(Wn + 1) * G + g] = 0.f;
-            }
+        for (int r = 0; r < RMAX; ++r) {
+            tpn[r] = r < cp.R ? T.topo[cp.base + r * 64 + lane] : 0u;
+            fvn[r] = r < cp.R ? T.F[cp.base + r * 64 + lane] : kInf;
+            if (UPD) bvn[r] = r < c0.R ? T.B[c0.base + r * 64 + lane] : 0.f;
         }
+        if (l > 0) xn = adj_edge<UPD>(T, A, e - G, false, true);
         wave_sync();
         // bids for the argmin parent arc of every node of level l+1
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             if (r < c0.R) {
                 const int k = r * P + p, lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
-                if (lo < Wn && fv[r] == fv1[lo * G + g]) lds_imin(&bid[lo * G + g], 2 * k);
-                if (hi < Wn && fv[r] + x.lam_use == fv1[hi * G + g]) lds_imin(&bid[hi * G + g], 2 * k + 1);
+                if (lo < Wn && fv[r] == Fv[lo * G + g]) lds_imin(&bid[lo * G + g], 2 * k);
+                if (hi < Wn && fv[r] + x.lam_use == Fv[hi * G + g]) lds_imin(&bid[hi * G + g], 2 * k + 1);
             }
         }
         wave_sync();
@@ -142,9 +164,9 @@ __global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t
             acc[r] = 0.f;
             if (r < c0.R) {
                 const int k = r * P + p, lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
-                if (lo < Wn && bid[lo * G + g] == 2 * k) acc[r] += fa1[lo * G + g];
+                if (lo < Wn && bid[lo * G + g] == 2 * k) acc[r] += Fa[lo * G + g];
                 if (hi < Wn && bid[hi * G + g] == 2 * k + 1) {
-                    const float c = fa1[hi * G + g];
+                    const float c = Fa[hi * G + g];
                     acc[r] += c;
                     hisum += c;
                 }
@@ -163,30 +185,20 @@ __global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t
             }
             m0 = team_min<P>(m0);
             m1 = team_min<P>(m1);
-            int k0 = INT_MAX, k1 = INT_MAX;
-#pragma unroll
-            for (int r = RMAX - 1; r >= 0; --r) {
-                if (r < c0.R) {
-                    const int k = r * P + p;
-                    if (fv[r] + Bst[(int)(tp[r] & 0xFFFFu) * G + g] == m0) k0 = k;
-                    if (fv[r] + Bst[(int)(tp[r] >> 16) * G + g] == m1) k1 = k;
-                }
-            }
-            k0 = team_min_i<P>(k0);
-            k1 = team_min_i<P>(k1);
-            // children of the two argmin nodes (for the record of the fixed-side sweep)
-            int ch0 = INT_MAX, ch1 = INT_MAX;
+            // lowest argmin node and its child in one key: node << 12 | child code
+            int key0 = INT_MAX, key1 = INT_MAX;
 #pragma unroll
             for (int r = 0; r < RMAX; ++r) {
                 if (r < c0.R) {
-                    const int k = r * P + p;
-                    if (k == k0) ch0 = (int)(tp[r] & 0xFFFFu);
-                    if (k == k1) ch1 = (int)(tp[r] >> 16);
+                    const int k = r * P + p, lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
+                    if (fv[r] + Bst[lo * G + g] == m0) key0 = min(key0, (k << 12) | lo);
+                    if (fv[r] + Bst[hi * G + g] == m1) key1 = min(key1, (k << 12) | hi);
                 }
             }
-            ch0 = team_min_i<P>(ch0);
-            ch1 = team_min_i<P>(ch1);
+            key0 = team_min_i<P>(key0);
+            key1 = team_min_i<P>(key1);
             if (c0.W > 0) {
+                const int k0 = key0 >> 12, k1 = key1 >> 12, ch0 = key0 & 0xFFF, ch1 = key1 & 0xFFF;
                 const float dlam_new = x.dlo + hisum;
                 const float dM = x.dMo - dlam_new;
                 const float diff = (m1 + x.lam_old) - m0;  // m^1 - m^0 as the pass formed it
@@ -194,8 +206,8 @@ __global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t
                 if (p == 0) {
                     A.dlam_in[e] = dlam_new + dm1;  // identity path + the hi arc of m^1 itself
                     A.g[e] = dlam_new * x.al;
-                    A.dalpha[e] += dlam_new * x.S;
-                    A.domega[e] += dM * diff;
+                    A.dalpha[e] = x.da + dlam_new * x.S;
+                    A.domega[e] = x.dw + dM * diff;
                     A.rec_idx[2 * e] = ch0 < Wn ? ch0 : -1;
                     A.rec_idx[2 * e + 1] = ch1 < Wn ? ch1 : -1;
                     A.rec_val[2 * e] = dm0;
@@ -209,35 +221,34 @@ __global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t
                 }
             }
         } else if (c0.W > 0) {
-            if (p == 0) A.dlam_in[e] += hisum;
+            if (p == 0) A.dlam_in[e] = x.dl + hisum;
             // argmin contributions of the update sweep to F_l (record of edge l)
-            const int i0 = A.rec_idx[2 * e], i1 = A.rec_idx[2 * e + 1];
-            const float v0 = A.rec_val[2 * e], v1 = A.rec_val[2 * e + 1];
 #pragma unroll
             for (int r = 0; r < RMAX; ++r) {
                 const int k = r * P + p;
-                if (k == i0) acc[r] += v0;
-                if (k == i1) acc[r] += v1;
+                if (k == x.i0) acc[r] += x.v0;
+                if (k == x.i1) acc[r] += x.v1;
             }
         }
-        wave_sync();  // every bid has been read before the buffer is reset for level l
+        wave_sync();  // level l+1 is fully read before level l replaces it
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             if (r < c0.R) {
                 const int xi = mine + r * P * G;
-                fa0[xi] = acc[r];
-                fv0[xi] = fv[r];
+                Fa[xi] = acc[r];
+                Fv[xi] = fv[r];
                 bid[xi] = INT_MAX;
             }
         }
         wave_sync();
-        cur ^= 1;
         c1 = c0;
+        c0 = cp;
     }
 }
 
 // ------------------------------------------------------------------------------------------
-// Pull-form sweep (B side), along the level order: l = 0 .. L-1.
+// Pull-form sweep (B side), along the level order: l = 0 .. L-1, with the operands of hop l+1
+// (topology and F of level l+1, B of level l+2, edge data) loaded during hop l.
 // LDS per wave: Bst (B of level l+1), Ba[2] (adjoints of levels l / l+1), level table.
 // seed != 0: the adjoint of B(root) is `seed` (the lower bound's own gradient).
 // ------------------------------------------------------------------------------------------
@@ -259,7 +270,7 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
     const int nlev = tc.nlev;
     auto level = [&](int l) {
         Lev v{0, 0, 0};
-        if (l < nlev) {
+        if (l >= 0 && l < nlev) {
             const int w = meta[l * G + g] & 0xFFFF;
             v.W = G == 1 ? uni(w) : w;
             v.R = uni(meta[l * G] >> 16);
@@ -274,27 +285,41 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
         for (int r = 0; r < R0; ++r) Ba[mine + r * P * G] = 0.f;
         if (p == 0) Ba[g] = seed;  // the root is node 0 of level 0
     }
-    Lev c0 = level(0);
+    Lev c0 = level(0), c1 = level(1);
+    uint32_t tpn[RMAX];
+    float fvn[RMAX], bvn[RMAX];
+#pragma unroll
+    for (int r = 0; r < RMAX; ++r) {
+        tpn[r] = r < c0.R ? T.topo[c0.base + r * 64 + lane] : 0u;
+        fvn[r] = (UPD && r < c0.R) ? T.F[c0.base + r * 64 + lane] : 0.f;
+        bvn[r] = r < c1.R ? T.B[c1.base + r * 64 + lane] : 0.f;
+    }
+    AdjEdge xn = adj_edge<UPD>(T, A, tc.ebase + g, bar != 0, false);
+    int pi0 = -1, pi1 = -1;  // record of the previous hop's edge (fixed sweeps)
+    float pv0 = 0.f, pv1 = 0.f;
     for (int l = 0; l < nlev; ++l) {
-        const Lev c1 = level(l + 1);
         const int Wn = c1.W;
         const int e = tc.ebase + l * G + g;
-        const AdjEdge x = adj_edge<UPD>(T, A, e, c0.W > 0, bar != 0);
+        const AdjEdge x = xn;
         float *ba0 = Ba + cur * WB * G, *ba1 = Ba + (cur ^ 1) * WB * G;
         // fixed side: argmin contributions of the update sweep to B_l (record of edge l-1)
-        if (!UPD && recs && l > 0 && p == 0) {
-            const int ep = e - G;
-            if (level(l - 1).W > 0) {
-                const int i0 = A.rec_idx[2 * ep], i1 = A.rec_idx[2 * ep + 1];
-                if (i0 >= 0) ba0[i0 * G + g] += A.rec_val[2 * ep];
-                if (i1 >= 0) ba0[i1 * G + g] += A.rec_val[2 * ep + 1];
-            }
+        if (!UPD && p == 0) {
+            if (pi0 >= 0) ba0[pi0 * G + g] += pv0;
+            if (pi1 >= 0) ba0[pi1 * G + g] += pv1;
         }
-        const float *bg = T.B + c1.base;
+        uint32_t tp[RMAX];
+        float fv[RMAX];
+        const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
+            tp[r] = tpn[r];
+            fv[r] = fvn[r];
+            if (r < c0.R && !in_level<P>(r, c0.R, lane, c0.W)) {
+                tp[r] = dead;
+                fv[r] = kInf;
+            }
             if (r < c1.R) {
-                Bst[mine + r * P * G] = bg[r * 64 + lane];
+                Bst[mine + r * P * G] = bvn[r];
                 ba1[mine + r * P * G] = 0.f;
             }
         }
@@ -302,17 +327,22 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
             Bst[Wn * G + g] = kInf;
             Bst[(Wn + 1) * G + g] = 0.f;
         }
-        uint32_t tp[RMAX];
-        float fv[RMAX];
-        const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
-        const uint32_t *tg = T.topo + c0.base;
-        const float *fg = T.F + c0.base;
+        // prefetch hop l+1: topology and F of level l+1, B of level l+2, edge data of level l+1
+        const Lev c2 = level(l + 2);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
-            if (r < c0.R) {
-                const bool ok = in_level<P>(r, c0.R, lane, c0.W);
-                tp[r] = ok ? tg[r * 64 + lane] : dead;
-                if (UPD) fv[r] = ok ? fg[r * 64 + lane] : kInf;
+            tpn[r] = r < c1.R ? T.topo[c1.base + r * 64 + lane] : 0u;
+            if (UPD) fvn[r] = r < c1.R ? T.F[c1.base + r * 64 + lane] : 0.f;
+            bvn[r] = r < c2.R ? T.B[c2.base + r * 64 + lane] : 0.f;
+        }
+        if (l + 1 < nlev) xn = adj_edge<UPD>(T, A, e + G, bar != 0, false);
+        if (!UPD) {
+            pi0 = pi1 = -1;
+            if (recs && c0.W > 0) {
+                pi0 = A.rec_idx[2 * e];
+                pi1 = A.rec_idx[2 * e + 1];
+                pv0 = A.rec_val[2 * e];
+                pv1 = A.rec_val[2 * e + 1];
             }
         }
         wave_sync();
@@ -369,8 +399,8 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
                 if (p == 0) {
                     A.dlam_in[e] = dlam_new + dm1;
                     A.g[e] = dlam_new * x.al;
-                    A.dalpha[e] += dlam_new * x.S;
-                    A.domega[e] += dM * diff;
+                    A.dalpha[e] = x.da + dlam_new * x.S;
+                    A.domega[e] = x.dw + dM * diff;
                     A.rec_idx[2 * e] = k0;  // argmin nodes of level l: F_l side contributions
                     A.rec_idx[2 * e + 1] = k1;
                     A.rec_val[2 * e] = dm0;
@@ -378,11 +408,12 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
                 }
             }
         } else if (c0.W > 0 && p == 0) {
-            A.dlam_in[e] += hisum;
+            A.dlam_in[e] = x.dl + hisum;
         }
         wave_sync();
         cur ^= 1;
         c0 = c1;
+        c1 = c2;
     }
 }
 
@@ -396,6 +427,14 @@ __global__ void k_adj_deferred(const int32_t *__restrict__ var_ptr, const int32_
     float s = 0.f;
     for (int q = a; q < b; ++q) s += g[var_slots[q]];
     for (int q = a; q < b; ++q) dM[var_slots[q]] = s;
+}
+
+__global__ void k_edge_S(const int32_t *__restrict__ evar, const float *__restrict__ S, float *__restrict__ Se,
+                         int64_t slots) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= slots) return;
+    const int v = evar[e];
+    Se[e] = v >= 0 ? S[v] : 0.f;
 }
 
 // Adjoint of lambda_bar = lambda + alpha * S: dlambda stays, d_alpha += dlambda_bar * S_i,
@@ -496,6 +535,12 @@ hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots,
                                hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_adj_deferred, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_slots, g, dM, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_edge_S(const int32_t *evar, const float *S, float *Se, int64_t slots, hipStream_t s) {
+    if (slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_edge_S, dim3(blocks_for(slots, 256)), dim3(256), 0, s, evar, S, Se, slots);
     return hipGetLastError();
 }
 

@@ -871,12 +871,12 @@ int adj_alloc(dd_instance *h) {
     if (h->adj_ready) return DD_OK;
     const size_t S = (size_t)h->edge_slots;
     int st;
-    for (float **b : {&h->lam_in, &h->dlamA, &h->dlamB, &h->dMA, &h->dMB, &h->g, &h->dalpha, &h->domega})
+    for (float **b : {&h->lam_in, &h->dlamA, &h->dlamB, &h->dMA, &h->dMB, &h->g, &h->dalpha, &h->domega, &h->Se})
         if ((st = h->alloc(b, S))) return st;
     if ((st = h->alloc(&h->rec_val, 2 * S))) return st;
     if ((st = h->alloc(&h->rec_idx, 2 * S))) return st;
     if ((st = h->alloc(&h->scratch_n, (size_t)std::max<int64_t>(h->n, 1)))) return st;
-    for (float *b : {h->lam_in, h->dlamA, h->dlamB, h->dMA, h->dMB, h->g, h->dalpha, h->domega})
+    for (float *b : {h->lam_in, h->dlamA, h->dlamB, h->dMA, h->dMB, h->g, h->dalpha, h->domega, h->Se})
         HIP_TRY(hipMemset(b, 0, sizeof(float) * S));
     HIP_TRY(hipMemset(h->rec_val, 0, sizeof(float) * 2 * S));
     HIP_TRY(hipMemset(h->rec_idx, 0xFF, sizeof(int32_t) * 2 * S));
@@ -896,12 +896,16 @@ int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out
              hipStream_t s) {
     int st = deferred(h, s);  // S and alpha*S of the pass-input M
     if (st) return st;
+    st = recorded(h, "k_edge_S", 12.0 * (double)h->edge_slots, s,
+                  [&] { return launch_edge_S(h->T.evar, h->S, h->Se, h->edge_slots, s); });
+    if (st) return st;
     if ((st = copy_slots(h, h->lam_in, h->T.lam, s))) return st;
     AdjTables A{};
     A.lam_in = h->lam_in;
     A.lam_src = h->lam_in;
     A.dlam_out = dlam_out;
     A.dM_out = dM_out;
+    A.Se = h->Se;
     A.dlam_in = dlam_in;
     A.g = h->g;
     A.dalpha = h->dalpha;

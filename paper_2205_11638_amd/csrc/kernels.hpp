@@ -72,9 +72,9 @@ constexpr int lds_words_pass(int P, int WB, int NL) {  // constexpr: usable in d
 #define DD_CLASSES(X) \
     X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(64, 8) X(64, 12) X(64, 16) X(64, 24) X(64, 32)
 
-// per wave of the adjoint sweeps: push form = cost and adjoint of two levels, bids, staged B;
+// per wave of the adjoint sweeps: push form = cost and adjoint of one level, bids, staged B;
 // pull form = staged B and the adjoints of two levels; both + the level table
-constexpr int lds_words_adj_F(int P, int WB, int NL) { return 6 * WB * (64 / P) + NL * ((64 / P) + 1); }
+constexpr int lds_words_adj_F(int P, int WB, int NL) { return 4 * WB * (64 / P) + NL * ((64 / P) + 1); }
 constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) + NL * ((64 / P) + 1); }
 
 // Arrays of the reverse sweeps (edge-slot indexed unless noted).
@@ -83,6 +83,7 @@ struct AdjTables {
     const float *lam_src;   // multipliers of a fixed-side sweep (plus alpha*S when flushed)
     const float *dlam_out;  // adjoint of the pass-output multipliers
     const float *dM_out;    // adjoint of the pass-output M
+    const float *Se;        // S of each edge's variable (update sweeps)
     float *dlam_in;         // adjoint of the pass-input multipliers (set by the update sweep, added to by the fixed one)
     float *g;               // dlambda' * alpha, summed per variable into dS
     float *dalpha, *domega; // accumulated over passes
@@ -96,6 +97,8 @@ enum AdjSweep { ADJ_F_UPDATE = 0, ADJ_F_FIXED = 1, ADJ_B_UPDATE = 2, ADJ_B_FIXED
 // recs: fixed sweeps add the records of the update sweep; seed: adjoint of B(root) (pull form).
 hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
                       float seed, hipStream_t s);
+// Se[slot] = S[evar[slot]] (0 on padding)
+hipError_t launch_edge_S(const int32_t *evar, const float *S, float *Se, int64_t slots, hipStream_t s);
 hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots, const float *g, float *dM, int n,
                                hipStream_t s);
 hipError_t launch_flush_adj(const int32_t *evar, const float *S, const float *alpha, const float *dlam, float *dalpha,
