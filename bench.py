@@ -23,15 +23,16 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def counted_traffic(kernel, workload):
     """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
-    against a plain copy), or None when the kernel source changed since the counters were taken."""
+    against a plain copy), or None when a kernel source changed since the counters were taken."""
     import hashlib
     path = os.path.join(HERE, "profiles", "traffic_knapsack_2M_vars.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(HERE, "paper_2205_11638_amd", "csrc", "kernels.hip")
-    if rec.get("workload") != workload or hashlib.sha256(open(src, "rb").read()).hexdigest() != rec.get(
-            "kernels_hip_sha256"):
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "adjoint.hip"):
+        h.update(open(os.path.join(HERE, "paper_2205_11638_amd", "csrc", f), "rb").read())
+    if rec.get("workload") != workload or h.hexdigest() != rec.get("sources_sha256"):
         return None
     return rec["per_launch_bytes"].get(kernel)
 
