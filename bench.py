@@ -168,6 +168,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the unrolled forward + backward leg")
     ap.add_argument("--adjoint-reps", type=int, default=2)
     ap.add_argument("--no-batch", action="store_true", help="skip the packed-batch leg")
+    ap.add_argument("--autotune", default=None, metavar="CACHE",
+                    help="tune the pass kernels' launch shapes before timing ('-' for no cache file)")
     ap.add_argument("--batch-iters", type=int, default=500)
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
@@ -207,6 +209,10 @@ def main():
     al = inst.seg_softmax(ah)
     inst.set_params(om, al)
     inst.reset()
+    if args.autotune:
+        t0 = time.time()
+        hit = inst.autotune(None if args.autotune == "-" else args.autotune)
+        log(f"[bench] autotune ({'cache' if hit else 'timed'}, {time.time() - t0:.1f}s): {inst.launch_shapes()}")
 
     def step():
         inst.run(T)
@@ -255,7 +261,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": prob.name, "n": prob.n, "m": prob.m, "edges": prob.nnz, "nodes": int(st["nodes"]),
-                   "arcs": arcs, "iterations_per_step": T, "step": "T dual iterations + lower bound"},
+                   "arcs": arcs, "iterations_per_step": T, "step": "T dual iterations + lower bound",
+                   "launch_shapes": inst.launch_shapes()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(dom, prob.name),
                      "algorithmic_bytes_per_launch": b_dom, "avg_launch_ms": tot_dom / n_dom},
