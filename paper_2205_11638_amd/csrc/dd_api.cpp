@@ -417,9 +417,11 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
         });
 }
 
-int deferred(dd_instance *h, hipStream_t s) {
+int deferred(dd_instance *h, hipStream_t s) { return deferred_from(h, h->T.M, s); }
+
+int deferred_from(dd_instance *h, const float *M, hipStream_t s) {
     int st = recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 12.0 * (double)h->n, s, [&] {
-        return launch_deferred_sum(h->var_ptr, h->var_slots, h->T.M, h->S, (int)h->n, s);
+        return launch_deferred_sum(h->var_ptr, h->var_slots, M, h->S, (int)h->n, s);
     });
     if (st) return st;
     return recorded(h, "k_edge_alpha_s", 16.0 * (double)h->edge_slots, s, [&] {
@@ -892,14 +894,19 @@ int copy_slots(dd_instance *h, float *dst, const float *src, hipStream_t s) {
 // Reverse mode of one pass.  On entry the instance state (lambda, M) is the pass input; on exit
 // it is the pass output.  dlam_out/dM_out: adjoints of the outputs; dlam_in/dM_in receive the
 // adjoints of the inputs; d_alpha and d_omega accumulate.
+// With lam_src/M_src (slot order): the instance already holds this pass's outputs -- its
+// multipliers, M and both node sides exactly as the pass left them (the side it read, computed
+// from the input multipliers, and the side it rebuilt) -- and lam_src/M_src are its inputs;
+// the fixed-side sweep and the replay are then skipped.
 int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out, float *dlam_in, float *dM_in,
-             hipStream_t s) {
-    int st = deferred(h, s);  // S and alpha*S of the pass-input M
+             hipStream_t s, const float *lam_src = nullptr, const float *M_src = nullptr) {
+    const bool fresh = lam_src != nullptr;
+    int st = deferred_from(h, fresh ? M_src : h->T.M, s);  // S and alpha*S of the pass-input M
     if (st) return st;
     st = recorded(h, "k_edge_S", 12.0 * (double)h->edge_slots, s,
                   [&] { return launch_edge_S(h->T.evar, h->S, h->Se, h->edge_slots, s); });
     if (st) return st;
-    if ((st = copy_slots(h, h->lam_in, h->T.lam, s))) return st;
+    if ((st = copy_slots(h, h->lam_in, fresh ? lam_src : h->T.lam, s))) return st;
     AdjTables A{};
     A.lam_in = h->lam_in;
     A.lam_src = h->lam_in;
@@ -915,13 +922,13 @@ int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out
     h->en_lam_valid = false;
     if (dir == 0) {
         // fixed side B at the input multipliers, the pass replayed (F), then the two reverse sweeps
-        if ((st = all_classes(h, false, BWD_STORE, s))) return st;
-        if ((st = all_classes(h, true, FWD_UPDATE, s))) return st;
+        if (!fresh && (st = all_classes(h, false, BWD_STORE, s))) return st;
+        if (!fresh && (st = all_classes(h, true, FWD_UPDATE, s))) return st;
         if ((st = adj_classes(h, A, ADJ_F_UPDATE, 0, 0, 0.f, s))) return st;
         if ((st = adj_classes(h, A, ADJ_B_FIXED, 0, 1, 0.f, s))) return st;
     } else {
-        if ((st = all_classes(h, true, FWD_SWEEP_LAM, s))) return st;
-        if ((st = all_classes(h, false, BWD_UPDATE, s))) return st;
+        if (!fresh && (st = all_classes(h, true, FWD_SWEEP_LAM, s))) return st;
+        if (!fresh && (st = all_classes(h, false, BWD_UPDATE, s))) return st;
         if ((st = adj_classes(h, A, ADJ_B_UPDATE, 0, 0, 0.f, s))) return st;
         if ((st = adj_classes(h, A, ADJ_F_FIXED, 0, 1, 0.f, s))) return st;
     }
@@ -1034,8 +1041,14 @@ int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, floa
             if ((st = dd_run_pass(h, q % 2, stream))) return st;
         }
         for (int q = np - 1; q >= 0; --q) {
-            if ((st = load_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
-            if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s))) return st;
+            if (q == np - 1) {
+                // the recomputation just ran this pass: its outputs and both node sides are in place
+                // (a segment ends with a backward pass, whose fixed side is the F its forward pass left)
+                if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s, h->seg_lam[q], h->seg_M[q]))) return st;
+            } else {
+                if ((st = load_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
+                if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s))) return st;
+            }
             std::swap(dl, dl2);
             std::swap(dm, dm2);
         }

@@ -130,8 +130,9 @@ inline int recorded(dd_instance *h, const char *name, double bytes, hipStream_t 
     return DD_OK;
 }
 
-// S and alpha*S of the current M (start of a pass).
+// S and alpha*S of the current M (start of a pass), or of a given M (slot order).
 int deferred(dd_instance *h, hipStream_t s);
+int deferred_from(dd_instance *h, const float *M, hipStream_t s);
 // One sweep (pass-kernel mode) over every class, classes concurrently on side streams.
 int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s);
 // B at the current multipliers, stored (what a forward pass reads).
