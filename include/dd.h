@@ -75,7 +75,7 @@ typedef struct {
 /* Launch options; zero means "default".  Pass NULL for all defaults. */
 typedef struct {
     int32_t nodes_per_lane; /* target decision-diagram nodes per lane per hop (team size choice), default 4 */
-    int32_t waves_per_block;/* waves (tiles) per workgroup, default 4 */
+    int32_t waves_per_block;/* max waves (tiles) per workgroup, 1..4, default 4 (DD_E_ARG otherwise) */
     int32_t ckpt_every;     /* iterations between adjoint checkpoints, default 5 */
     int32_t lds_budget;     /* max LDS bytes per workgroup, default 64 KiB */
     int32_t no_graphs;      /* nonzero: dd_run launches every kernel itself instead of replaying graphs */
@@ -221,13 +221,13 @@ int dd_profile_end(dd_instance *h, dd_kernel_time *out, int32_t cap, int32_t *co
  * *count receives the number of classes; at most cap entries are written. */
 int dd_get_launch(const dd_instance *h, int32_t *out, int32_t cap, int32_t *count);
 
-/* Set class c's pass-kernel launch shape (waves per workgroup 1..16 within the LDS budget;
+/* Set class c's pass-kernel launch shape (waves per workgroup 1..4 within the LDS budget;
  * grid 0 or a positive workgroup count).  The arithmetic, and so every result, does not
  * depend on the shape.  DD_E_ARG on an out-of-range class or an infeasible shape. */
 int dd_set_launch(dd_instance *h, int32_t c, int32_t wpb_f, int32_t wpb_b, int32_t grid_f, int32_t grid_b);
 
 /* Autotuner: time the forward and backward update kernels of every class over a small set
- * of launch shapes (waves per workgroup x {one wave per tile, a resident grid of the size the
+ * of launch shapes (waves per workgroup 1, 2, 4 x {one wave per tile, a resident grid of the size the
  * CUs hold at once}) and keep the fastest.  cache_path (may be NULL) names a text file: a
  * line "signature<TAB>shapes" per tuned instance shape, signature = device architecture and
  * every class's (P, RMAX, tiles, nodes); a hit is applied without timing (*from_cache = 1).

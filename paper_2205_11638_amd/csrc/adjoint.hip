@@ -499,6 +499,8 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 template <int P, int RMAX>
 hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
                         float seed, hipStream_t s) {
+    if (c.wpb_af < 1 || c.wpb_af > kMaxWavesPerBlock || c.wpb_ab < 1 || c.wpb_ab > kMaxWavesPerBlock)
+        return hipErrorInvalidConfiguration;
     if (which == ADJ_F_UPDATE || which == ADJ_F_FIXED) {
         dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
         const size_t lds = (size_t)c.wpb_af * lds_words_adj_F(P, c.WB, c.NL) * 4;

@@ -2,7 +2,7 @@
 // text cache.
 //
 // A pass kernel's arithmetic does not depend on its launch shape (each wave owns whole tiles),
-// so shapes trade only speed: waves per workgroup set how many tiles share a CU's LDS
+// so shapes trade only speed: waves per workgroup (at most 4: the kernels are compiled for 256 threads) set how many tiles share a CU's LDS
 // allocation granule, and a resident grid (as many workgroups as the CUs hold at once, whose
 // waves walk the tile list) replaces one wave per tile.
 #include <hip/hip_runtime_api.h>
@@ -24,7 +24,7 @@ using namespace ddi;
 namespace {
 
 bool shape_ok(const dd_instance *h, const ClassLaunch &c, int wpb) {
-    if (wpb < 1 || wpb > 16) return false;
+    if (wpb < 1 || wpb > dd::kMaxWavesPerBlock) return false;
     return (int64_t)wpb * dd::lds_words_pass(c.P, c.WB, c.NL) * 4 <= h->lds_budget;
 }
 
@@ -101,7 +101,8 @@ int dd_set_launch(dd_instance *h, int32_t c, int32_t wpb_f, int32_t wpb_b, int32
     if (!h || c < 0 || c >= (int)h->classes.size()) return fail(DD_E_ARG, "bad instance or class index");
     ClassLaunch &cl = h->classes[c];
     if (!shape_ok(h, cl, wpb_f) || !shape_ok(h, cl, wpb_b) || grid_f < 0 || grid_b < 0)
-        return fail(DD_E_ARG, "class %d: waves per workgroup must be 1..16 within the LDS budget, grids >= 0", c);
+        return fail(DD_E_ARG, "class %d: waves per workgroup must be 1..%d within the LDS budget, grids >= 0", c,
+                    dd::kMaxWavesPerBlock);
     cl.wpb_f = wpb_f;
     cl.wpb_b = wpb_b;
     cl.grid_f = grid_f;
@@ -155,7 +156,7 @@ int dd_autotune(dd_instance *h, const char *cache_path, int32_t *from_cache, voi
                 int best_w = fwd ? c.wpb_f : c.wpb_b, best_g = fwd ? c.grid_f : c.grid_b;
                 float best = INFINITY;
                 int reps = 0;
-                for (int w = 1; w <= 16; w *= 2) {
+                for (int w = 1; w <= dd::kMaxWavesPerBlock; w *= 2) {
                     if (!shape_ok(h, c, w)) break;
                     ClassLaunch t = c;
                     t.wpb_f = t.wpb_b = w;

@@ -259,7 +259,7 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
         auto pick = [&](int64_t words) {
             const int64_t per_wave = words * 4;
             int best = 0, best_waves = -1;
-            for (int w = 1; w <= 16; w *= 2) {
+            for (int w = 1; w <= kMaxWavesPerBlock; w *= 2) {
                 if (w > wpb || w * per_wave > lds_budget) break;
                 const int waves = (int)(kLdsPerCU / (w * per_wave)) * w;
                 if (waves >= best_waves) {
@@ -481,7 +481,9 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     if (opt) o = *opt;
     const int npl = o.nodes_per_lane > 0 ? o.nodes_per_lane : 4;
     if (npl != 1 && npl != 2 && npl != 4) return fail(DD_E_ARG, "nodes_per_lane must be 1, 2 or 4");
-    const int wpb = o.waves_per_block > 0 ? std::min(o.waves_per_block, 16) : 4;
+    if (o.waves_per_block < 0 || o.waves_per_block > kMaxWavesPerBlock)
+        return fail(DD_E_ARG, "waves_per_block must be 0 (default) or 1..%d", kMaxWavesPerBlock);
+    const int wpb = o.waves_per_block > 0 ? o.waves_per_block : kMaxWavesPerBlock;
     const int lds_budget = o.lds_budget > 0 ? o.lds_budget : 64 * 1024;
     if (o.ckpt_every < 0) return fail(DD_E_ARG, "ckpt_every must be >= 0");
     SortedRows sr;

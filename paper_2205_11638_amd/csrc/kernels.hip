@@ -39,8 +39,6 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
         float *Bst = Fb + WB * G;
         int *meta = (int *)(Bst + WB * G);
         int *off = meta + NL * G;
-        float *lamo = (float *)(off + NL);  // updated multipliers and M, flushed once per tile
-        float *Mo = lamo + NL * G;
         const TileCtx tc = tile_ctx(T, tile);
         preload_meta<G>(T, tc, lane, meta, off);
         const int nlev = tc.nlev;
@@ -129,8 +127,9 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
                     const float Mn = om * (m1 - m0);
                     lam_new = lam - Mn + aS;
                     if (p == 0) {
-                        lamo[l * G + g] = lam_new;
-                        Mo[l * G + g] = Mn;
+                        const int e = tc.ebase + l * G + g;
+                        T.lam[e] = lam_new;
+                        T.M[e] = Mn;
                     }
                 }
             } else {
@@ -148,14 +147,6 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
             c0 = c1;
             c1 = c2;
             c2 = level(l + 3);
-        }
-        if (UPD) {
-            for (int i = lane; i < nlev * G; i += 64) {
-                if (meta[i] & 0xFFFF) {
-                    T.lam[tc.ebase + i] = lamo[i];
-                    T.M[tc.ebase + i] = Mo[i];
-                }
-            }
         }
         if (!LOOP) break;
         tile += (int64_t)gridDim.x * (blockDim.x >> 6);
@@ -184,8 +175,6 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         float *buf0 = lds_f + (size_t)wave * lds_words_pass(P, WB, NL);
         int *meta = (int *)(buf0 + 2 * WB * G);
         int *off = meta + NL * G;
-        float *lamo = (float *)(off + NL);
-        float *Mo = lamo + NL * G;
         const TileCtx tc = tile_ctx(T, tile);
         const int row = T.bdd[tile * 64 + g];
         preload_meta<G>(T, tc, lane, meta, off);
@@ -274,8 +263,9 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                         const float Mn = om * (m1 - m0);
                         lam_new = lam - Mn + aS;
                         if (p == 0) {
-                            lamo[l * G + g] = lam_new;
-                            Mo[l * G + g] = Mn;
+                            const int e = tc.ebase + l * G + g;
+                            T.lam[e] = lam_new;
+                            T.M[e] = Mn;
                         }
                     } else if (p == 0) {
                         const int ce = T.slot2canon[tc.ebase + l * G + g];
@@ -314,14 +304,6 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
             if (BAR) T.energies[row] = e0;
             else T.en_lam[row] = e0;
         }
-        if (UPD) {
-            for (int i = lane; i < nlev * G; i += 64) {
-                if (meta[i] & 0xFFFF) {
-                    T.lam[tc.ebase + i] = lamo[i];
-                    T.M[tc.ebase + i] = Mo[i];
-                }
-            }
-        }
         if (!LOOP) break;
         tile += (int64_t)gridDim.x * (blockDim.x >> 6);
         if (tile >= tile0 + ntiles) break;
@@ -333,6 +315,7 @@ inline unsigned full_grid(int64_t ntiles, int wpb) { return (unsigned)((ntiles +
 
 template <int P, int RMAX>
 hipError_t fwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
+    if (c.wpb_f < 1 || c.wpb_f > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
     const unsigned full = full_grid(c.ntiles, c.wpb_f);
     dim3 grid(full), block(64 * c.wpb_f);
     size_t lds = (size_t)c.wpb_f * lds_words_pass(P, c.WB, c.NL) * 4;
@@ -352,6 +335,7 @@ hipError_t fwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipS
 
 template <int P, int RMAX>
 hipError_t bwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
+    if (c.wpb_b < 1 || c.wpb_b > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
     const unsigned full = full_grid(c.ntiles, c.wpb_b);
     dim3 grid(full), block(64 * c.wpb_b);
     size_t lds = (size_t)c.wpb_b * lds_words_pass(P, c.WB, c.NL) * 4;

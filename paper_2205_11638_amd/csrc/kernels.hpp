@@ -64,9 +64,12 @@ struct ClassLaunch {
 };
 
 // LDS words (4 bytes) one wavefront of the forward / backward pass kernels uses.
-// per wave: two node buffers (2 * WB * G), level table (NL * G + NL), staged lambda and M (2 * NL * G)
+// per wave: two node buffers (2 * WB * G) and the level table (NL * G + NL)
+// Every kernel of the solver is compiled for workgroups of at most 256 threads (4 waves).
+constexpr int kMaxWavesPerBlock = 4;
+
 constexpr int lds_words_pass(int P, int WB, int NL) {  // constexpr: usable in device code too
-    return 2 * WB * (64 / P) + NL * (3 * (64 / P) + 1);
+    return 2 * WB * (64 / P) + NL * ((64 / P) + 1);
 }
 
 #define DD_CLASSES(X) \

@@ -88,7 +88,7 @@ def test_set_launch_rejects_bad_shapes():
     import paper_2205_11638_amd as dd
     inst, _, _ = make_instance(mixed())
     n = len(inst.launch_shapes())
-    for args in ((n, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, 17), (0, 1, 1, -1, 0)):
+    for args in ((n, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, 8), (0, 8, 1), (0, 1, 17), (0, 1, 1, -1, 0)):
         with pytest.raises(dd.DDError):
             inst.set_launch(*args)
 

@@ -150,3 +150,11 @@ def test_batch_needs_programs(dd):
     with pytest.raises(dd.DDError) as e:
         dd.Batch([])
     assert e.value.code == dd.binding.DD_E_ARG
+
+
+def test_waves_per_block_limited_to_the_compiled_workgroup_size(dd):
+    # the kernels are compiled for workgroups of at most 256 threads (4 waves)
+    p = synth.random_tiny(2, n=10, m=5)
+    with pytest.raises(dd.DDError) as e:
+        dd.Instance(p, waves_per_block=8)
+    assert e.value.code == dd.binding.DD_E_ARG
