@@ -108,6 +108,41 @@ def adjoint_leg(inst, T, K, reps, stream):
             "kernels": kernels}
 
 
+def other_workloads(stream):
+    """The smaller configurations at their own iteration counts (graph replays), timed like the
+    main step: T iterations + the lower bound, inputs resident."""
+    import torch
+
+    import paper_2205_11638_amd as dd
+    import synth
+
+    out = {}
+    for name in ("setcover", "indset", "gm"):
+        w = synth.workload(name)
+        p, T = w["problem"], int(w["T"])
+        inst = dd.Instance(p)
+        inst.set_params(torch.tensor(np.asarray(w["omega"], np.float32), device="cuda"),
+                        inst.seg_softmax(torch.tensor(np.asarray(w["alpha_hat"], np.float32), device="cuda")))
+        inst.reset()
+        inst.run(2)
+        inst.reset()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        inst.run(T)
+        lb = inst.lower_bound()[0]
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        arcs = int(inst.stats["arcs"])
+        out[p.name] = {"iterations": T, "ms": ms, "us_per_iteration": ms * 1e3 / T, "arcs": arcs,
+                       "arcs_per_s": arcs * T / (ms / 1e3), "lower_bound": lb}
+        log(f"[bench] {p.name}: T={T} in {ms:.2f} ms ({ms * 1e3 / T:.1f} us/iteration, "
+            f"{arcs * T / (ms / 1e3):.3e} arcs/s)")
+        inst.close()
+    return out
+
+
 def batch_leg(T, stream):
     """64 uneven set-cover / independent-set programs: T iterations of all of them packed into
     one instance (one launch per kernel class per pass, graph replays) against the same T
@@ -171,6 +206,7 @@ def main():
     ap.add_argument("--autotune", default=None, metavar="CACHE",
                     help="tune the pass kernels' launch shapes before timing ('-' for no cache file)")
     ap.add_argument("--batch-iters", type=int, default=500)
+    ap.add_argument("--no-others", action="store_true", help="skip the set-cover / independent-set / GM rates")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -248,6 +284,7 @@ def main():
         adj["ckpt_every_5"] = {k: v for k, v in adjoint_leg(inst, T, 5, args.adjoint_reps, stream).items()
                                if k != "kernels"}
     bat = None if args.no_batch else batch_leg(args.batch_iters, stream)
+    others = None if args.no_others else other_workloads(stream)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -276,6 +313,7 @@ def main():
         "lower_bound": lb[0],
         "adjoint": adj,
         "batch": bat,
+        "other_workloads": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
