@@ -544,9 +544,14 @@ done:
  * dLB/dlambda_bar = argmin assignment (Sec. "Loss"), the flush lambda_bar = lambda + alpha S,
  * then orc_pass_vjp on every pass in reverse, then lambda_0 = c / |J_i|.
  * Variables in no row contribute min(0, c_i) to LB, so dLB/dc_i = [c_i < 0] for them. */
+/* T iterations from (lam0, M0) -- or, when lam0 is NULL, from lambda = c/|J_i|, M = 0 -- then the
+ * lower bound and its gradient by Alg. 2 pass by pass in reverse.  d_c is the gradient through
+ * lambda_0 = c/|J_i| and the uncovered-variable constant (reset start only; may be NULL);
+ * d_lam0 / d_M0 (may be NULL) are the adjoints of the start state. */
 int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef,
                       const int8_t *sense, const int64_t *rhs, const double *c, const double *omega,
-                      const double *alpha, int T, double *lb_out, double *d_omega, double *d_alpha, double *d_c,
+                      const double *alpha, int T, const double *lam0, const double *M0, double *lb_out,
+                      double *d_omega, double *d_alpha, double *d_c, double *d_lam0, double *d_M0,
                       double *min_gap, int nthreads) {
     int64_t E = row_ptr[m];
     size_t nE = (size_t)(E > 0 ? E : 1);
@@ -564,7 +569,13 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
     int64_t *deg = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
     double *gaps = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
     if (min_gap) *min_gap = INF;
-    int st = orc_init_lambda(n, c, E, col, lam);
+    int st = ORC_OK;
+    if (lam0) {
+        memcpy(lam, lam0, sizeof(double) * (size_t)E);
+        memcpy(M, M0, sizeof(double) * (size_t)E);
+    } else {
+        st = orc_init_lambda(n, c, E, col, lam);
+    }
     for (int p = 0; p < npass && st == ORC_OK; ++p) {
         memcpy(lam + nE * (p + 1), lam + nE * p, sizeof(double) * (size_t)E);
         memcpy(M + nE * (p + 1), M + nE * p, sizeof(double) * (size_t)E);
@@ -599,9 +610,13 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
         t = dM; dM = dM2; dM2 = t;
     }
     if (st) goto done;
-    for (int64_t e = 0; e < E; ++e) deg[col[e]]++;
-    for (int i = 0; i < n; ++i) d_c[i] = deg[i] == 0 ? (c[i] < 0.0 ? 1.0 : 0.0) : 0.0;
-    for (int64_t e = 0; e < E; ++e) d_c[col[e]] += dl[e] / (double)deg[col[e]];
+    if (d_lam0) memcpy(d_lam0, dl, sizeof(double) * (size_t)E);
+    if (d_M0) memcpy(d_M0, dM, sizeof(double) * (size_t)E);
+    if (d_c) {
+        for (int64_t e = 0; e < E; ++e) deg[col[e]]++;
+        for (int i = 0; i < n; ++i) d_c[i] = deg[i] == 0 ? (c[i] < 0.0 ? 1.0 : 0.0) : 0.0;
+        for (int64_t e = 0; e < E; ++e) d_c[col[e]] += dl[e] / (double)deg[col[e]];
+    }
 done:
     free(lam); free(M); free(lam_bar); free(dl); free(dM); free(dl2); free(dM2); free(Sv); free(Se); free(x);
     free(deg); free(gaps);

@@ -208,9 +208,10 @@ def pass_vjp(prob, omega, alpha, direction, lam_in, M_in, dlam_out, dM_out, thre
     return (dli, dmi, da, dw, gap[:prob.m]) if with_gap else (dli, dmi, da, dw)
 
 
-def unrolled_grad(prob, omega, alpha, T, threads=0, with_gap=False):
-    """LB after T iterations from the default start and its gradient w.r.t. (omega, alpha, c)
-    [+ the smallest relative gap of any minimizer decision taken on the way]."""
+def unrolled_grad(prob, omega, alpha, T, threads=0, with_gap=False, lam0=None, M0=None):
+    """LB after T iterations and its gradient w.r.t. (omega, alpha, c) [+ the smallest relative gap
+    of any minimizer decision taken on the way].  With lam0/M0 the iterations start from that state
+    instead of lambda = c/|J_i|, M = 0, and the third gradient is (d_lam0, d_M0) instead of d_c."""
     lib = _load()
     keep, pa = _prob_args(prob)
     E = prob.nnz
@@ -219,10 +220,54 @@ def unrolled_grad(prob, omega, alpha, T, threads=0, with_gap=False):
     lb = C.c_double()
     dw, da, dc = np.empty(E), np.empty(E), np.empty(prob.n)
     gap = C.c_double()
-    _check(lib.orc_unrolled_grad(C.c_int(prob.n), C.c_int(prob.m), *pa, _p(c, C.c_double), _p(om, C.c_double),
-                                 _p(al, C.c_double), C.c_int(T), C.byref(lb), _p(dw, C.c_double), _p(da, C.c_double),
-                                 _p(dc, C.c_double), C.byref(gap), C.c_int(threads)), "unrolled_grad")
-    return (lb.value, dw, da, dc, gap.value) if with_gap else (lb.value, dw, da, dc)
+    if lam0 is None:
+        _check(lib.orc_unrolled_grad(C.c_int(prob.n), C.c_int(prob.m), *pa, _p(c, C.c_double), _p(om, C.c_double),
+                                     _p(al, C.c_double), C.c_int(T), None, None, C.byref(lb), _p(dw, C.c_double),
+                                     _p(da, C.c_double), _p(dc, C.c_double), None, None, C.byref(gap),
+                                     C.c_int(threads)), "unrolled_grad")
+        out = (lb.value, dw, da, dc)
+    else:
+        l0, m0 = _f64(lam0, E), _f64(M0, E)
+        dl0, dm0 = np.empty(E), np.empty(E)
+        _check(lib.orc_unrolled_grad(C.c_int(prob.n), C.c_int(prob.m), *pa, _p(c, C.c_double), _p(om, C.c_double),
+                                     _p(al, C.c_double), C.c_int(T), _p(l0, C.c_double), _p(m0, C.c_double),
+                                     C.byref(lb), _p(dw, C.c_double), _p(da, C.c_double), None,
+                                     _p(dl0, C.c_double), _p(dm0, C.c_double), C.byref(gap), C.c_int(threads)),
+               "unrolled_grad")
+        out = (lb.value, dw, da, (dl0, dm0))
+    return out + (gap.value,) if with_gap else out
+
+
+def center(prob, x):
+    """x_e minus the mean of x over the edges of e's variable (the feasibility projection of the
+    non-parametric update, eq. 2, and of the theta transform of Alg. 3)."""
+    x = _f64(x, prob.nnz)
+    var = prob.col.astype(np.int64)
+    s = np.zeros(prob.n)
+    np.add.at(s, var, x)
+    deg = np.bincount(var, minlength=prob.n).astype(np.float64)
+    return x - s[var] / deg[var]
+
+
+def nonparam_update(prob, lam, theta_hat):
+    """Eq. 2: lambda_ij + theta_hat_ij - (1/|J_i|) sum_{k in J_i} theta_hat_ik."""
+    return _f64(lam, prob.nnz) + center(prob, theta_hat)
+
+
+def sigmoid(x):
+    x = np.asarray(x, dtype=np.float64)
+    return 1.0 / (1.0 + np.exp(-x))
+
+
+def param_transform(prob, omega_hat, alpha_hat, theta_hat):
+    """Alg. 3's output transforms: omega = sigmoid, alpha = softmax over J_i, theta centred over J_i."""
+    return sigmoid(omega_hat), softmax_alpha(prob, alpha_hat), center(prob, theta_hat)
+
+
+def param_transform_vjp(prob, omega, alpha, d_omega, d_alpha, d_theta):
+    """Adjoints of param_transform's inputs (the centring is symmetric and idempotent)."""
+    return (_f64(d_omega) * omega * (1.0 - omega), softmax_alpha_vjp(prob, alpha, _f64(d_alpha)),
+            center(prob, d_theta))
 
 
 def lb_after(prob, omega, alpha, T, c=None, threads=0):

@@ -55,21 +55,24 @@ def ilp_optimum(prob):
     return float((xs[ok] @ prob.c).min()) if ok.any() else float("inf")
 
 
-def dmma_torch(prob, omega, alpha, T, c=None, record=False):
+def dmma_torch(prob, omega, alpha, T, c=None, record=False, lam0=None, M0=None):
     """Alg. 1 with enumerated min-marginals, in torch float64 (differentiable).
 
-    omega, alpha, c may be tensors requiring grad.  Deferred sums are taken at
-    the start of each pass; lambda starts at c_i/|J_i|, M at 0; forward passes
-    visit the variables of each row in ascending order, backward passes in
-    descending order.  Returns (LB at the flushed multipliers, list of states).
+    omega, alpha, c (and lam0, M0) may be tensors requiring grad.  Deferred sums are taken at
+    the start of each pass; lambda starts at c_i/|J_i|, M at 0 unless a start state (lam0, M0)
+    is given; forward passes visit the variables of each row in ascending order, backward
+    passes in descending order.  Returns (LB at the flushed multipliers, list of states).
     """
     sets = [torch.tensor(X, dtype=torch.float64) for X in row_sets(prob)]
     E = prob.nnz
     var = torch.tensor(prob.col.astype(np.int64))
     deg = torch.bincount(var, minlength=prob.n).to(torch.float64)
     c = torch.as_tensor(prob.c, dtype=torch.float64) if c is None else c
-    lam = c[var] / deg[var]
-    M = torch.zeros(E, dtype=torch.float64)
+    if lam0 is None:
+        lam = c[var] / deg[var]
+        M = torch.zeros(E, dtype=torch.float64)
+    else:
+        lam, M = lam0, M0
     states = [(lam.detach().clone(), M.detach().clone())]
     ptr = [int(v) for v in prob.row_ptr]
     for t in range(T):

@@ -520,3 +520,93 @@ def test_unrolled_grad_directional_fd_gm_full(orc):
         assert r, k
         checked += 1
     assert checked >= 6
+
+
+# ------------------------------------------------------------------------------------------
+# Non-parametric update (eq. 2), the output transforms of Alg. 3, and the unrolled gradient
+# from an arbitrary start state (a training round starts from the previous round's state)
+# ------------------------------------------------------------------------------------------
+
+def test_center_is_the_feasibility_projection(orc):
+    p = synth.workload("gm", small=True)["problem"]
+    rng = np.random.default_rng(50)
+    x, y = rng.normal(size=p.nnz), rng.normal(size=p.nnz)
+    cx = orc.center(p, x)
+    sums = np.zeros(p.n)
+    np.add.at(sums, p.col.astype(np.int64), cx)
+    np.testing.assert_allclose(sums, 0.0, atol=1e-12)                   # sums over J_i vanish
+    np.testing.assert_allclose(orc.center(p, cx), cx, atol=1e-12)        # idempotent
+    assert cx @ y == pytest.approx(x @ orc.center(p, y), abs=1e-10)      # symmetric
+    # a variable in one row: its theta is removed entirely
+    one = np.bincount(p.col, minlength=p.n)[p.col] == 1
+    np.testing.assert_allclose(cx[one], 0.0, atol=1e-15)
+
+
+def test_nonparam_update_keeps_the_dual_feasible(orc):
+    p = synth.workload("gm", small=True)["problem"]
+    om, ah = learned_params(p, 51)
+    al = orc.softmax_alpha(p, ah)
+    lam, M = orc.run(p, om, al, 3)
+    th = np.random.default_rng(52).normal(size=p.nnz)
+    lam2 = orc.nonparam_update(p, lam, th)
+    var = p.col.astype(np.int64)
+    tot1, tot2 = np.zeros(p.n), np.zeros(p.n)
+    np.add.at(tot1, var, lam + M)
+    np.add.at(tot2, var, lam2 + M)
+    np.testing.assert_allclose(tot2, tot1, atol=1e-12)   # sum_j (lambda_ij + M_ij) = c_i still holds
+    np.testing.assert_allclose(tot1[np.bincount(var, minlength=p.n) > 0],
+                               p.c[np.bincount(var, minlength=p.n) > 0], atol=1e-10)
+
+
+def test_param_transform_vjp_matches_autograd(orc):
+    p = synth.workload("gm", small=True)["problem"]
+    rng = np.random.default_rng(53)
+    wh, ah, th = (rng.normal(size=p.nnz) for _ in range(3))
+    g = [rng.normal(size=p.nnz) for _ in range(3)]
+    om, al, tt = orc.param_transform(p, wh, ah, th)
+    got = orc.param_transform_vjp(p, om, al, *g)
+    W, A, Th = (torch.tensor(x, requires_grad=True) for x in (wh, ah, th))
+    var = torch.tensor(p.col.astype(np.int64))
+    deg = torch.bincount(var, minlength=p.n).to(torch.float64)
+    mx = torch.zeros(p.n, dtype=torch.float64).index_reduce(0, var, A.detach(), "amax", include_self=False)
+    z = torch.exp(A - mx[var])
+    alpha = z / torch.zeros(p.n, dtype=torch.float64).index_add(0, var, z)[var]
+    theta = Th - torch.zeros(p.n, dtype=torch.float64).index_add(0, var, Th)[var] / deg[var]
+    np.testing.assert_allclose(torch.sigmoid(W).detach().numpy(), om, atol=1e-14)
+    np.testing.assert_allclose(alpha.detach().numpy(), al, atol=1e-14)
+    np.testing.assert_allclose(theta.detach().numpy(), tt, atol=1e-14)
+    (torch.sigmoid(W) @ torch.tensor(g[0]) + alpha @ torch.tensor(g[1]) + theta @ torch.tensor(g[2])).backward()
+    for x, t in zip(got, (W, A, Th)):
+        np.testing.assert_allclose(x, t.grad.numpy(), atol=1e-12)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_unrolled_grad_from_state_matches_autograd(orc, seed):
+    p = tiny(seed + 700, n=9, m=6, kmax=6)
+    om, ah = learned_params(p, seed + 1)
+    al = orc.softmax_alpha(p, ah)
+    lam0, M0 = orc.run(p, om, al, 2)
+    lam0 = orc.nonparam_update(p, lam0, np.random.default_rng(seed).normal(size=p.nnz))
+    T = 2
+    lb, dw, da, (dl0, dm0) = orc.unrolled_grad(p, om, al, T, lam0=lam0, M0=M0)
+    W = torch.tensor(om, requires_grad=True)
+    A = torch.tensor(al, requires_grad=True)
+    L0 = torch.tensor(lam0, requires_grad=True)
+    M0t = torch.tensor(M0, requires_grad=True)
+    lbt, _ = brute.dmma_torch(p, W, A, T, lam0=L0, M0=M0t)
+    lbt.backward()
+    assert lb == pytest.approx(lbt.item(), abs=1e-11)
+    for x, t in ((dw, W), (da, A), (dl0, L0), (dm0, M0t)):
+        np.testing.assert_allclose(x, t.grad.numpy(), atol=1e-10)
+
+
+def test_unrolled_grad_from_state_euler_identity(orc):
+    p = synth.workload("gm", small=True)["problem"]
+    om, ah = learned_params(p, 54)
+    al = orc.softmax_alpha(p, ah)
+    lam0, M0 = orc.run(p, om, al, 3)
+    lb, _, _, (dl0, dm0) = orc.unrolled_grad(p, om, al, 4, lam0=lam0, M0=M0)
+    unc = np.bincount(p.col, minlength=p.n) == 0
+    const = np.minimum(p.c[unc], 0.0).sum()
+    terms = np.concatenate([dl0 * lam0, dm0 * M0])
+    assert terms.sum() == pytest.approx(lb - const, abs=1e-10 * np.abs(terms).sum())
