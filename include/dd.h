@@ -188,6 +188,39 @@ int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, floa
 int dd_pass_vjp(dd_instance *h, int32_t direction, const float *lam_in, const float *M_in, const float *dlam_out,
                 const float *dM_out, float *dlam_in, float *dM_in, float *d_alpha, float *d_omega, void *stream);
 
+/* As dd_forward_unrolled, but the T iterations start from the instance's current state (lambda, M)
+ * instead of the reset state: one round of the paper's pipeline (Sec. "Overall pipeline") starts
+ * where the previous round stopped, after the non-parametric update. */
+int dd_forward_unrolled_from_state(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream);
+
+/* As dd_backward, but also returning the adjoints of the state the recorded forward started from:
+ * d_lam0, d_M0 (device arrays [edges], canonical order; any output may be NULL).  After a forward
+ * from the reset state d_lam0 is the adjoint of lambda_0 = c/|J_i|; dd_backward's d_c needs such a
+ * forward (DD_E_ARG after dd_forward_unrolled_from_state). */
+int dd_backward_state(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_lam0, float *d_M0,
+                      void *stream);
+
+/* Output transforms of the parameter predictor (Alg. 3, last lines): omega = sigmoid(omega_hat),
+ * alpha = softmax over J_i of alpha_hat (as dd_seg_softmax), theta = theta_hat minus its mean over
+ * J_i (dual feasibility).  Device arrays [edges], canonical order; theta_hat and theta may both be
+ * NULL. */
+int dd_param_transform(dd_instance *h, const float *omega_hat, const float *alpha_hat, const float *theta_hat,
+                       float *omega, float *alpha, float *theta, void *stream);
+
+/* Adjoint of dd_param_transform: given its outputs omega, alpha and the adjoints d_omega, d_alpha,
+ * d_theta, writes d_omega_hat = d_omega * omega (1 - omega), d_alpha_hat (softmax VJP) and
+ * d_theta_hat = d_theta minus its mean over J_i (the centring is symmetric and idempotent).
+ * d_theta and d_theta_hat may both be NULL. */
+int dd_param_transform_vjp(dd_instance *h, const float *omega, const float *alpha, const float *d_omega,
+                           const float *d_alpha, const float *d_theta, float *d_omega_hat, float *d_alpha_hat,
+                           float *d_theta_hat, void *stream);
+
+/* Non-parametric update (eq. 2): lambda_ij += theta_hat_ij - (1/|J_i|) sum_{k in J_i} theta_hat_ik on
+ * the current state (M unchanged; sum_j (lambda_ij + M_ij) is preserved).  theta_hat: device array
+ * [edges], canonical order.  Its adjoint is the same centring of d_lambda (dd_param_transform_vjp's
+ * theta part). */
+int dd_nonparam_update(dd_instance *h, const float *theta_hat, void *stream);
+
 /* d_alpha_hat = VJP of alpha = softmax over J_i (dd_seg_softmax): alpha_e (d_alpha_e - sum_k alpha_k d_alpha_k).
  * Device arrays [edges], canonical order. */
 int dd_seg_softmax_vjp(dd_instance *h, const float *alpha, const float *d_alpha, float *d_alpha_hat, void *stream);

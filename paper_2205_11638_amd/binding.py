@@ -82,6 +82,11 @@ SIGNATURES = {
     "dd_profile_begin": ([_VP, C.c_int32], C.c_int),
     "dd_profile_end": ([_VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "dd_compile_row": ([C.POINTER(dd_problem), C.c_int32, _VP, _VP, C.c_int64, C.POINTER(C.c_int64)], C.c_int),
+    "dd_forward_unrolled_from_state": ([_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), _VP], C.c_int),
+    "dd_backward_state": ([_VP, C.c_double, _VP, _VP, _VP, _VP, _VP], C.c_int),
+    "dd_param_transform": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
+    "dd_param_transform_vjp": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
+    "dd_nonparam_update": ([_VP, _VP, _VP], C.c_int),
     "dd_get_launch": ([_VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "dd_set_launch": ([_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "dd_autotune": ([_VP, C.c_char_p, C.POINTER(C.c_int32), _VP], C.c_int),
@@ -297,6 +302,42 @@ class Instance:
         dw, da, dc = self._f32(self.E), self._f32(self.E), self._f32(self.n)
         _check(self._L.dd_backward(self._h, float(dlb), _dptr(dw), _dptr(da), _dptr(dc), _stream()))
         return dw, da, dc
+
+    def forward_unrolled_from_state(self, T, ckpt_every=0):
+        lb = C.c_double()
+        _check(self._L.dd_forward_unrolled_from_state(self._h, int(T), int(ckpt_every), C.byref(lb), _stream()))
+        return lb.value
+
+    def backward_state(self, dlb=1.0):
+        """(d_omega, d_alpha, d_lam0, d_M0) of dlb * LB of the recorded unrolled forward ([E] each)."""
+        outs = [self._f32(self.E) for _ in range(4)]
+        _check(self._L.dd_backward_state(self._h, float(dlb), *[_dptr(o) for o in outs], _stream()))
+        return tuple(outs)
+
+    def param_transform(self, omega_hat, alpha_hat, theta_hat=None):
+        """(omega, alpha, theta) = (sigmoid, softmax over J_i, centring over J_i) of the raw predictions."""
+        import torch
+        w, a = self._f32(self.E), self._f32(self.E)
+        t = self._f32(self.E) if theta_hat is not None else None
+        th = _dptr(theta_hat, torch.float32, self.E) if theta_hat is not None else None
+        _check(self._L.dd_param_transform(self._h, _dptr(omega_hat, torch.float32, self.E),
+                                          _dptr(alpha_hat, torch.float32, self.E), th, _dptr(w), _dptr(a),
+                                          _dptr(t) if t is not None else None, _stream()))
+        return w, a, t
+
+    def param_transform_vjp(self, omega, alpha, d_omega, d_alpha, d_theta=None):
+        import torch
+        dw, da = self._f32(self.E), self._f32(self.E)
+        dt = self._f32(self.E) if d_theta is not None else None
+        args = [_dptr(x, torch.float32, self.E) for x in (omega, alpha, d_omega, d_alpha)]
+        _check(self._L.dd_param_transform_vjp(
+            self._h, *args, _dptr(d_theta, torch.float32, self.E) if d_theta is not None else None, _dptr(dw),
+            _dptr(da), _dptr(dt) if dt is not None else None, _stream()))
+        return dw, da, dt
+
+    def nonparam_update(self, theta_hat):
+        import torch
+        _check(self._L.dd_nonparam_update(self._h, _dptr(theta_hat, torch.float32, self.E), _stream()))
 
     def pass_vjp(self, direction, lam_in, M_in, dlam_out, dM_out):
         import torch

@@ -481,6 +481,75 @@ __global__ void k_softmax_vjp(const int32_t *__restrict__ var_ptr, const int32_t
     }
 }
 
+// Output transforms of the parameter predictor (Alg. 3): omega = sigmoid(omega_hat) per edge,
+// alpha = softmax over J_i of alpha_hat, theta = theta_hat minus its mean over J_i.  One thread per
+// variable; canonical edge arrays, var_canon = CSR of each variable's canonical edges.
+__global__ void k_param_transform(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_canon,
+                                  const float *__restrict__ wh, const float *__restrict__ ah,
+                                  const float *__restrict__ th, float *__restrict__ w, float *__restrict__ al,
+                                  float *__restrict__ t, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = var_ptr[i], b = var_ptr[i + 1];
+    float mx = -kInf, tsum = 0.f;
+    for (int q = a; q < b; ++q) {
+        const int e = var_canon[q];
+        mx = fmaxf(mx, ah[e]);
+        if (th) tsum += th[e];
+    }
+    float den = 0.f;
+    for (int q = a; q < b; ++q) den += expf(ah[var_canon[q]] - mx);
+    const float tmean = tsum / (float)(b > a ? b - a : 1);
+    for (int q = a; q < b; ++q) {
+        const int e = var_canon[q];
+        w[e] = 1.f / (1.f + expf(-wh[e]));
+        al[e] = expf(ah[e] - mx) / den;
+        if (th) t[e] = th[e] - tmean;
+    }
+}
+
+// Adjoints of k_param_transform's inputs: d_omega_hat = d_omega * omega (1 - omega),
+// d_alpha_hat = alpha (d_alpha - sum_k alpha_k d_alpha_k), d_theta_hat = d_theta minus its mean.
+__global__ void k_param_transform_vjp(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_canon,
+                                      const float *__restrict__ w, const float *__restrict__ al,
+                                      const float *__restrict__ dw, const float *__restrict__ da,
+                                      const float *__restrict__ dt, float *__restrict__ dwh,
+                                      float *__restrict__ dah, float *__restrict__ dth, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = var_ptr[i], b = var_ptr[i + 1];
+    float s = 0.f, tsum = 0.f;
+    for (int q = a; q < b; ++q) {
+        const int e = var_canon[q];
+        s += al[e] * da[e];
+        if (dt) tsum += dt[e];
+    }
+    const float tmean = tsum / (float)(b > a ? b - a : 1);
+    for (int q = a; q < b; ++q) {
+        const int e = var_canon[q];
+        dwh[e] = dw[e] * w[e] * (1.f - w[e]);
+        dah[e] = al[e] * (da[e] - s);
+        if (dt) dth[e] = dt[e] - tmean;
+    }
+}
+
+// Non-parametric update (eq. 2): lambda[slot of e] += theta_hat[e] - mean over J_i of theta_hat.
+__global__ void k_nonparam_update(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_canon,
+                                  const int32_t *__restrict__ canon2slot, const float *__restrict__ th,
+                                  float *__restrict__ lam, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int a = var_ptr[i], b = var_ptr[i + 1];
+    float tsum = 0.f;
+    for (int q = a; q < b; ++q) tsum += th[var_canon[q]];
+    const float tmean = tsum / (float)(b > a ? b - a : 1);
+    for (int q = a; q < b; ++q) {
+        const int e = var_canon[q];
+        const int sl = canon2slot[e];
+        lam[sl] = lam[sl] + (th[e] - tmean);
+    }
+}
+
 // sum over variables with no row of min(0, c_i)
 __global__ void k_fill(float *__restrict__ x, float v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -566,6 +635,31 @@ hipError_t launch_softmax_vjp(const int32_t *var_ptr, const int32_t *var_canon, 
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_softmax_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, alpha, dalpha, out,
                        n);
+    return hipGetLastError();
+}
+
+hipError_t launch_param_transform(const int32_t *var_ptr, const int32_t *var_canon, const float *wh, const float *ah,
+                                  const float *th, float *w, float *al, float *t, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_param_transform, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, wh, ah, th, w,
+                       al, t, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_param_transform_vjp(const int32_t *var_ptr, const int32_t *var_canon, const float *w,
+                                      const float *al, const float *dw, const float *da, const float *dt, float *dwh,
+                                      float *dah, float *dth, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_param_transform_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, w, al, dw,
+                       da, dt, dwh, dah, dth, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonparam_update(const int32_t *var_ptr, const int32_t *var_canon, const int32_t *canon2slot,
+                                  const float *th, float *lam, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_nonparam_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, canon2slot,
+                       th, lam, n);
     return hipGetLastError();
 }
 

@@ -987,13 +987,24 @@ int dd_pass_vjp(dd_instance *h, int32_t direction, const float *lam_in, const fl
     return recompute_B(h, s);
 }
 
-int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream) {
+}  // extern "C"
+
+namespace {
+
+int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, bool from_state, void *stream) {
     if (!h || T < 0 || !lb) return fail(DD_E_ARG, "bad instance, T or lb");
+    if (ckpt_every < 0) return fail(DD_E_ARG, "ckpt_every must be >= 0");
     hipStream_t s = (hipStream_t)stream;
     int st = adj_alloc(h);
     if (st) return st;
     const int K = ckpt_every > 0 ? ckpt_every : (h->ckpt_default > 0 ? h->ckpt_default : 5);
-    if ((st = dd_reset(h, stream))) return st;
+    if (from_state) {
+        // a forward pass reads B at its input multipliers
+        if ((st = recompute_B(h, s))) return st;
+        h->version++;
+    } else if ((st = dd_reset(h, stream))) {
+        return st;
+    }
     for (int t = 0; t < T; ++t) {
         if (t % K == 0 && (st = save_state(h, h->ck_lam, h->ck_M, (size_t)(t / K), s))) return st;
         if ((st = dd_run(h, 1, stream))) return st;
@@ -1003,14 +1014,18 @@ int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *l
     if ((st = dd_lower_bound(h, lb, nullptr, stream))) return st;
     h->fwd_T = T;
     h->fwd_K = K;
+    h->fwd_from_state = from_state;
     h->fwd_version = h->version;
     return DD_OK;
 }
 
-int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream) {
+int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, float *d_lam0, float *d_M0,
+             void *stream) {
     if (!h) return fail(DD_E_ARG, "NULL instance");
     if (h->fwd_T < 0 || h->fwd_version != h->version)
-        return fail(DD_E_STATE, "dd_backward needs the state left by dd_forward_unrolled");
+        return fail(DD_E_STATE, "the backward sweep needs the state left by an unrolled forward");
+    if (d_c && h->fwd_from_state)
+        return fail(DD_E_ARG, "d_c needs an unrolled forward from the reset state (lambda = c/|J_i|)");
     hipStream_t s = (hipStream_t)stream;
     const int T = h->fwd_T, K = h->fwd_K, nseg = (T + K - 1) / K;
     const float seed = (float)dlb;
@@ -1057,6 +1072,8 @@ int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, floa
     }
     // lambda_0 = c / |J_i|
     if (d_c) HIP_TRY(launch_dc(h->var_ptr, h->var_slots, dl, h->cdev, seed, d_c, (int)h->n, s));
+    if (d_lam0) HIP_TRY(launch_gather(h->canon2slot, dl, d_lam0, h->E, nullptr, s));
+    if (d_M0) HIP_TRY(launch_gather(h->canon2slot, dm, d_M0, h->E, nullptr, s));
     if (d_omega) HIP_TRY(launch_gather(h->canon2slot, h->domega, d_omega, h->E, nullptr, s));
     if (d_alpha) HIP_TRY(launch_gather(h->canon2slot, h->dalpha, d_alpha, h->E, nullptr, s));
     // leave the solver at the final state of the recorded forward
@@ -1064,6 +1081,55 @@ int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, floa
     if ((st = recompute_B(h, s))) return st;
     h->fwd_version = h->version;
     return DD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream) {
+    return forward_unrolled(h, T, ckpt_every, lb, false, stream);
+}
+
+int dd_forward_unrolled_from_state(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream) {
+    return forward_unrolled(h, T, ckpt_every, lb, true, stream);
+}
+
+int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream) {
+    return backward(h, dlb, d_omega, d_alpha, d_c, nullptr, nullptr, stream);
+}
+
+int dd_backward_state(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_lam0, float *d_M0,
+                      void *stream) {
+    return backward(h, dlb, d_omega, d_alpha, nullptr, d_lam0, d_M0, stream);
+}
+
+int dd_param_transform(dd_instance *h, const float *omega_hat, const float *alpha_hat, const float *theta_hat,
+                       float *omega, float *alpha, float *theta, void *stream) {
+    if (!h || (h->E && (!omega_hat || !alpha_hat || !omega || !alpha || (!theta_hat != !theta))))
+        return fail(DD_E_ARG, "NULL argument");
+    HIP_TRY(launch_param_transform(h->var_ptr, h->var_canon, omega_hat, alpha_hat, theta_hat, omega, alpha, theta,
+                                   (int)h->n, (hipStream_t)stream));
+    return DD_OK;
+}
+
+int dd_param_transform_vjp(dd_instance *h, const float *omega, const float *alpha, const float *d_omega,
+                           const float *d_alpha, const float *d_theta, float *d_omega_hat, float *d_alpha_hat,
+                           float *d_theta_hat, void *stream) {
+    if (!h || (h->E && (!omega || !alpha || !d_omega || !d_alpha || !d_omega_hat || !d_alpha_hat ||
+                        (!d_theta != !d_theta_hat))))
+        return fail(DD_E_ARG, "NULL argument");
+    HIP_TRY(launch_param_transform_vjp(h->var_ptr, h->var_canon, omega, alpha, d_omega, d_alpha, d_theta, d_omega_hat,
+                                       d_alpha_hat, d_theta_hat, (int)h->n, (hipStream_t)stream));
+    return DD_OK;
+}
+
+int dd_nonparam_update(dd_instance *h, const float *theta_hat, void *stream) {
+    if (!h || (h->E && !theta_hat)) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(launch_nonparam_update(h->var_ptr, h->var_canon, h->canon2slot, theta_hat, h->T.lam, (int)h->n, s));
+    h->version++;
+    return recompute_B(h, s);
 }
 
 int dd_seg_softmax_vjp(dd_instance *h, const float *alpha, const float *d_alpha, float *d_alpha_hat, void *stream) {

@@ -70,6 +70,7 @@ struct dd_instance {
     std::vector<float *> ck_lam, ck_M;    // checkpoints of the unrolled forward (state at iterations 0, K, 2K, ..., T)
     std::vector<float *> seg_lam, seg_M;  // pass-input states inside one checkpoint segment
     int fwd_T = -1, fwd_K = 0;
+    bool fwd_from_state = false;  // the recorded forward started from a given state (no reset)
     int64_t version = 0, fwd_version = -1;  // the recorded forward is valid while the state is unchanged
     double *red_host = nullptr;  // pinned
     int32_t *flags = nullptr;

@@ -111,6 +111,15 @@ hipError_t launch_dc(const int32_t *var_ptr, const int32_t *var_slots, const flo
 hipError_t launch_softmax_vjp(const int32_t *var_ptr, const int32_t *var_canon, const float *alpha,
                               const float *dalpha, float *out, int n, hipStream_t s);
 hipError_t launch_fill(float *x, float v, int64_t n, hipStream_t s);
+// Alg. 3's output transforms and their adjoint (canonical arrays; th/t and dt/dth may be NULL).
+hipError_t launch_param_transform(const int32_t *var_ptr, const int32_t *var_canon, const float *wh, const float *ah,
+                                  const float *th, float *w, float *al, float *t, int n, hipStream_t s);
+hipError_t launch_param_transform_vjp(const int32_t *var_ptr, const int32_t *var_canon, const float *w,
+                                      const float *al, const float *dw, const float *da, const float *dt, float *dwh,
+                                      float *dah, float *dth, int n, hipStream_t s);
+// eq. 2 on the slot-ordered multipliers; th canonical
+hipError_t launch_nonparam_update(const int32_t *var_ptr, const int32_t *var_canon, const int32_t *canon2slot,
+                                  const float *th, float *lam, int n, hipStream_t s);
 hipError_t launch_uncovered(const int32_t *var_ptr, const float *c, float *out, int n, hipStream_t s);
 
 hipError_t launch_fwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
