@@ -143,6 +143,59 @@ def other_workloads(stream):
     return out
 
 
+def round_leg(stream, reps=3):
+    """One training round of the pipeline on the graph-matching configuration (1.44M edges,
+    T = 20, checkpoints every 5): output transforms, non-parametric update, T unrolled iterations,
+    the bound, and the reverse mode back to the three raw predictions -- against the plain
+    forward (T iterations + bound) from the same state."""
+    import torch
+
+    import paper_2205_11638_amd as dd
+    import synth
+    from paper_2205_11638_amd.autograd import dual_round
+
+    w = synth.workload("gm")
+    p, T, K = w["problem"], int(w["T"]), int(w["ckpt"])
+    inst = dd.Instance(p)
+    rng = np.random.default_rng(5)
+    # raw predictions: omega logits, the configuration's alpha logits, theta
+    raw = [torch.tensor(np.asarray(x, np.float32), device="cuda", requires_grad=True)
+           for x in (rng.normal(size=p.nnz), w["alpha_hat"], rng.normal(0, 0.1, size=p.nnz))]
+    om, al, _ = inst.param_transform(raw[0].detach(), raw[1].detach())
+    inst.set_params(om, al)
+    inst.run(5)  # an earlier round
+    lam, M = inst.get_state()
+
+    def one_round():
+        inst.set_state(lam, M)
+        for x in raw:
+            x.grad = None
+        (-dual_round(inst, *raw, T, K)).backward()
+
+    def plain():
+        inst.set_state(lam, M)
+        inst.run(T)
+        inst.lower_bound()
+
+    one_round()
+    plain()
+    out = {"workload": p.name, "T": T, "ckpt_every": K}
+    for name, fn in (("round_fwd_bwd_ms", one_round), ("plain_fwd_ms", plain)):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out[name] = e0.elapsed_time(e1) / reps
+    out["ratio"] = out["round_fwd_bwd_ms"] / out["plain_fwd_ms"]
+    log(f"[bench] GM round (T={T}, K={K}): fwd+bwd {out['round_fwd_bwd_ms']:.2f} ms, plain forward "
+        f"{out['plain_fwd_ms']:.2f} ms, ratio {out['ratio']:.2f}")
+    inst.close()
+    return out
+
+
 def batch_leg(T, stream):
     """64 uneven set-cover / independent-set programs: T iterations of all of them packed into
     one instance (one launch per kernel class per pass, graph replays) against the same T
@@ -207,6 +260,7 @@ def main():
                     help="tune the pass kernels' launch shapes before timing ('-' for no cache file)")
     ap.add_argument("--batch-iters", type=int, default=500)
     ap.add_argument("--no-others", action="store_true", help="skip the set-cover / independent-set / GM rates")
+    ap.add_argument("--no-round", action="store_true", help="skip the graph-matching training-round leg")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -285,6 +339,7 @@ def main():
                                if k != "kernels"}
     bat = None if args.no_batch else batch_leg(args.batch_iters, stream)
     others = None if args.no_others else other_workloads(stream)
+    rnd = None if args.no_round else round_leg(stream)
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -314,6 +369,7 @@ def main():
         "adjoint": adj,
         "batch": bat,
         "other_workloads": others,
+        "gm_round": rnd,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
