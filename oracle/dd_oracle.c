@@ -346,6 +346,77 @@ int orc_energies(int m, const int64_t *row_ptr, const int32_t *col, const int32_
     return status;
 }
 
+/* Smoothed subproblem (the smoothing of the feature table of the appendix, read as a soft-min):
+ * E_tau^j(lambda) = -tau log sum_{x in X_j} exp(-<lambda, x> / tau), which tends to E^j as tau -> 0.
+ * Its gradient is the Gibbs marginal p_l = P(x_l = 1) under exp(-<lambda, x>/tau) on X_j.  Computed
+ * with the prefix/suffix tables of the partial-sum diagram in the (soft-min, +) semiring (every x
+ * is one path of that diagram). */
+static double softmin2(double a, double b, double tau) {
+    if (a == INF) return b;
+    if (b == INF) return a;
+    double m = a < b ? a : b, d = fabs(a - b);
+    return m - tau * log1p(exp(-d / tau));
+}
+
+static void smoothed_row(const row_t *r, const double *lam, double tau, double *P, double *Q, double *E, double *p) {
+    for (int k = 0; k < r->W; ++k) P[k] = INF;
+    P[-r->smin] = 0.0;
+    for (int l = 0; l < r->L; ++l)
+        for (int k = 0; k < r->W; ++k) {
+            int64_t s = r->smin + k;
+            P[(size_t)(l + 1) * r->W + k] = softmin2(at(r, P, l, s), at(r, P, l, s - r->a[l]) + lam[l], tau);
+        }
+    suffix_init(r, Q);
+    for (int l = r->L - 1; l >= 0; --l)
+        for (int k = 0; k < r->W; ++k) {
+            int64_t s = r->smin + k;
+            Q[(size_t)l * r->W + k] = softmin2(at(r, Q, l + 1, s), lam[l] + at(r, Q, l + 1, s + r->a[l]), tau);
+        }
+    double e = Q[-r->smin];
+    *E = e;
+    for (int l = 0; l < r->L; ++l) {
+        double acc = 0.0;
+        for (int k = 0; k < r->W; ++k) {
+            double pl = P[(size_t)l * r->W + k];
+            if (pl == INF) continue;
+            double c1 = pl + lam[l] + at(r, Q, l + 1, r->smin + k + r->a[l]);
+            if (c1 != INF) acc += exp(-(c1 - e) / tau);
+        }
+        p[l] = acc;
+    }
+}
+
+int orc_smoothed(int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
+                 const int64_t *rhs, const double *lam, double tau, double *E_out, double *p_out, int nthreads) {
+    if (!(tau > 0.0)) return ORC_E_ARG;
+    size_t tab;
+    max_table(m, row_ptr, coef, &tab);
+    set_threads(nthreads);
+    int status = ORC_OK;
+#pragma omp parallel
+    {
+        double *P = (double *)malloc(sizeof(double) * tab);
+        double *Q = (double *)malloc(sizeof(double) * tab);
+#pragma omp for schedule(dynamic, 16)
+        for (int j = 0; j < m; ++j) {
+            row_t r;
+            int64_t b = row_ptr[j];
+            int st = row_init(&r, (int)(row_ptr[j + 1] - b), col + b, coef + b, sense[j], rhs[j]);
+            if (st) {
+#pragma omp critical
+                status = st;
+                continue;
+            }
+            double E;
+            smoothed_row(&r, lam + b, tau, P, Q, &E, p_out + b);
+            if (E_out) E_out[j] = E;
+        }
+        free(P);
+        free(Q);
+    }
+    return status;
+}
+
 /* Lower bound: lambda_bar = lambda + alpha * S(M), LB = sum_j E^j(lambda_bar) + sum_{|J_i|=0} min(0, c_i).
  * Also D_L = sum_j E^j(lambda) + sum_e min(0, M_e), the lifted-representation bound of Prop. 1's proof.
  * lam_bar_out (optional) receives lambda_bar. */

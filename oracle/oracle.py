@@ -179,6 +179,19 @@ def min_marginals(prob, lam, threads=0):
     return m0, m1
 
 
+def smoothed(prob, lam, tau, threads=0):
+    """(E_tau^j [m], p [E]): smoothed energies -tau log sum_{x in X_j} exp(-<lambda, x>/tau) and their
+    gradient, the marginals P(x_l = 1) of the Gibbs distribution on each X_j."""
+    lib = _load()
+    keep, pa = _prob_args(prob)
+    lam = _f64(lam, prob.nnz)
+    E = np.empty(max(prob.m, 1))
+    pm = np.empty(max(prob.nnz, 1))
+    _check(lib.orc_smoothed(C.c_int(prob.m), *pa, _p(lam, C.c_double), C.c_double(tau), _p(E, C.c_double),
+                            _p(pm, C.c_double), C.c_int(threads)), "smoothed")
+    return E[:prob.m], pm[:prob.nnz]
+
+
 def argmin(prob, lam, threads=0, with_gap=False):
     """Minimizing assignment of every row; with_gap also returns each row's smallest relative
     gap between the two options of a decision (tiny gap: the minimizer is not unique up to rounding)."""

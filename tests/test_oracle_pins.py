@@ -610,3 +610,42 @@ def test_unrolled_grad_from_state_euler_identity(orc):
     const = np.minimum(p.c[unc], 0.0).sum()
     terms = np.concatenate([dl0 * lam0, dm0 * M0])
     assert terms.sum() == pytest.approx(lb - const, abs=1e-10 * np.abs(terms).sum())
+
+
+# ------------------------------------------------------------------------------------------
+# Smoothed subproblems (feature table of the appendix), read as a soft-min: Gibbs marginals
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("tau", [0.3, 1.0, 10.0])
+def test_smoothed_matches_enumeration(orc, tau):
+    p = tiny(81, n=12, m=8, kmax=7)
+    lam = np.random.default_rng(82).normal(size=p.nnz)
+    E, pm = orc.smoothed(p, lam, tau)
+    for j, X in enumerate(brute.row_sets(p)):
+        a, b = int(p.row_ptr[j]), int(p.row_ptr[j + 1])
+        cost = X @ lam[a:b]
+        w = np.exp(-(cost - cost.min()) / tau)
+        assert E[j] == pytest.approx(cost.min() - tau * np.log(w.sum()), abs=1e-12)
+        np.testing.assert_allclose(pm[a:b], (w[:, None] * X).sum(0) / w.sum(), atol=1e-12)
+
+
+def test_smoothed_limits_and_gradient(orc):
+    p = tiny(83, n=12, m=8, kmax=7)
+    lam = np.random.default_rng(84).normal(size=p.nnz)
+    Ej = orc.energies(p, lam)
+    x = orc.argmin(p, lam)
+    E, pm = orc.smoothed(p, lam, 1e-4)
+    np.testing.assert_allclose(E, Ej, atol=1e-3)           # tau -> 0: the subproblem minimum
+    np.testing.assert_allclose(pm, x, atol=1e-6)            # and the minimizing assignment
+    for tau in (0.5, 5.0):
+        E, pm = orc.smoothed(p, lam, tau)
+        sizes = np.array([len(X) for X in brute.row_sets(p)])
+        assert (E <= Ej + 1e-12).all() and (E >= Ej - tau * np.log(sizes) - 1e-12).all()
+        h = 1e-6
+        for e in range(0, p.nnz, 3):   # central differences of E_tau
+            lp, lm = lam.copy(), lam.copy()
+            lp[e] += h
+            lm[e] -= h
+            j = int(np.searchsorted(p.row_ptr, e, side="right") - 1)
+            d = (orc.smoothed(p, lp, tau)[0][j] - orc.smoothed(p, lm, tau)[0][j]) / (2 * h)
+            assert d == pytest.approx(pm[e], abs=1e-6)
