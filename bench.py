@@ -108,6 +108,31 @@ def adjoint_leg(inst, T, K, reps, stream):
             "kernels": kernels}
 
 
+def features_leg(inst, stream):
+    """The solver features of the appendix's feature table on the main instance: smoothed energies
+    and Gibbs marginals at tau = 1, 10, 100 (at lambda_bar) and the minimizing assignment."""
+    import torch
+
+    inst.smoothed(1.0, flushed=True)  # allocates the scratch node array
+    inst.profile_begin(max_launches=256)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for tau in (1.0, 10.0, 100.0):
+        inst.smoothed(tau, flushed=True)
+    inst.argmin_assignment(flushed=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    prof = inst.profile_end()
+    out = {"total_ms": e0.elapsed_time(e1), "kernels": {}}
+    for name, (n, tot, b) in prof.items():
+        out["kernels"][name] = {"launches": n, "avg_ms": tot / n, "gbs_algorithmic": b / (tot / n) / 1e6}
+    sm = [v for k, v in out["kernels"].items() if k.startswith("k_smooth")]
+    log(f"[bench] features: 3 smoothed sweeps + assignment in {out['total_ms']:.1f} ms"
+        + (f" (k_smooth {sm[0]['avg_ms']:.2f} ms, {sm[0]['gbs_algorithmic']:.0f} GB/s)" if sm else ""))
+    return out
+
+
 def other_workloads(stream):
     """The smaller configurations at their own iteration counts (graph replays), timed like the
     main step: T iterations + the lower bound, inputs resident."""
@@ -261,6 +286,7 @@ def main():
     ap.add_argument("--batch-iters", type=int, default=500)
     ap.add_argument("--no-others", action="store_true", help="skip the set-cover / independent-set / GM rates")
     ap.add_argument("--no-round", action="store_true", help="skip the graph-matching training-round leg")
+    ap.add_argument("--no-features", action="store_true", help="skip the solver-feature leg")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -330,6 +356,7 @@ def main():
     achieved = b_dom / (tot_dom / n_dom) / 1e6   # bytes / ms -> GB/s
     arcs = int(st["arcs"])
     value = arcs * T / (ms / 1e3)
+    feats = None if args.no_features else features_leg(inst, stream)
     adj = None
     if not args.no_adjoint:
         # checkpoints every iteration (a checkpoint is lambda and M: 2 x 4 bytes per edge), and every
@@ -367,6 +394,7 @@ def main():
         "hbm_frac_step": (sum(b * n for n, _, b in prof.values()) / args.steps) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "lower_bound": lb[0],
         "adjoint": adj,
+        "features": feats,
         "batch": bat,
         "other_workloads": others,
         "gm_round": rnd,

@@ -225,6 +225,19 @@ int dd_nonparam_update(dd_instance *h, const float *theta_hat, void *stream);
  * Device arrays [edges], canonical order. */
 int dd_seg_softmax_vjp(dd_instance *h, const float *alpha, const float *d_alpha, float *d_alpha_hat, void *stream);
 
+/* ---- Solver features (the appendix's feature table) ----------------------------------------- */
+
+/* Smoothed subproblems at temperature tau > 0 (the smoothing of the feature table, read as a
+ * soft-min): E_tau^j = -tau log sum_{x in X_j} exp(-<lambda_.j, x>/tau) into E_out [m] (may be NULL),
+ * and its gradient, the Gibbs marginals P(x_i = 1) on X_j, into p_out [edges] (canonical order),
+ * at lambda (flushed = 0) or at lambda_bar (flushed != 0).  Device arrays.  The first call
+ * allocates a node-sized scratch array kept until dd_destroy. */
+int dd_smoothed(dd_instance *h, float tau, int32_t flushed, float *E_out, float *p_out, void *stream);
+
+/* Minimizing assignment of every row (a subgradient of the dual objective, Sec. "Loss"), 0/1 per
+ * edge into x_out [edges] (f32, canonical order), at lambda or lambda_bar; ties: lo arcs first. */
+int dd_argmin_assignment(dd_instance *h, int32_t flushed, float *x_out, void *stream);
+
 /* Nodes of each row's diagram, host array [m] (0 for an empty row). */
 int dd_row_nodes(const dd_instance *h, int64_t *nodes_out);
 

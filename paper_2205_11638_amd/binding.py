@@ -87,6 +87,8 @@ SIGNATURES = {
     "dd_param_transform": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
     "dd_param_transform_vjp": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
     "dd_nonparam_update": ([_VP, _VP, _VP], C.c_int),
+    "dd_smoothed": ([_VP, C.c_float, C.c_int32, _VP, _VP, _VP], C.c_int),
+    "dd_argmin_assignment": ([_VP, C.c_int32, _VP, _VP], C.c_int),
     "dd_get_launch": ([_VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "dd_set_launch": ([_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "dd_autotune": ([_VP, C.c_char_p, C.POINTER(C.c_int32), _VP], C.c_int),
@@ -334,6 +336,17 @@ class Instance:
             self._h, *args, _dptr(d_theta, torch.float32, self.E) if d_theta is not None else None, _dptr(dw),
             _dptr(da), _dptr(dt) if dt is not None else None, _stream()))
         return dw, da, dt
+
+    def smoothed(self, tau, flushed=False):
+        """(E_tau [m], Gibbs marginals P(x_i = 1) [E]) of the smoothed subproblems."""
+        E, pm = self._f32(self.m), self._f32(self.E)
+        _check(self._L.dd_smoothed(self._h, float(tau), int(bool(flushed)), _dptr(E), _dptr(pm), _stream()))
+        return E, pm
+
+    def argmin_assignment(self, flushed=False):
+        x = self._f32(self.E)
+        _check(self._L.dd_argmin_assignment(self._h, int(bool(flushed)), _dptr(x), _stream()))
+        return x
 
     def nonparam_update(self, theta_hat):
         import torch

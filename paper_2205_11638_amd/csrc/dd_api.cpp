@@ -1132,6 +1132,41 @@ int dd_nonparam_update(dd_instance *h, const float *theta_hat, void *stream) {
     return recompute_B(h, s);
 }
 
+int dd_smoothed(dd_instance *h, float tau, int32_t flushed, float *E_out, float *p_out, void *stream) {
+    if (!h || !(tau > 0.f) || !std::isfinite(tau) || (h->E && !p_out)) return fail(DD_E_ARG, "bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    int st;
+    if (!h->Bs && (st = h->alloc(&h->Bs, (size_t)(h->node_slots + 64)))) return st;
+    if (flushed && (st = deferred(h, s))) return st;
+    if (E_out) HIP_TRY(launch_fill(E_out, 0.f, h->m, s));  // rows with no variable: E = 0
+    return per_class(
+        h, s, [&](const ClassLaunch &cl, hipStream_t cs) {
+            return launch_smooth(h->T, cl, h->Bs, tau, flushed ? 1 : 0, E_out, p_out, cs);
+        },
+        [&](const ClassLaunch &cl) { return kname("k_smooth", cl, 0); },
+        // per node: topology twice, the soft-min cost written, read back and gathered for two
+        // children (24 B); per edge: multipliers (and alpha*S) twice, the marginal and its index
+        [&](const ClassLaunch &cl) { return 24.0 * cl.nodes + 24.0 * cl.edges; });
+}
+
+int dd_argmin_assignment(dd_instance *h, int32_t flushed, float *x_out, void *stream) {
+    if (!h || (h->E && !x_out)) return fail(DD_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int st = adj_alloc(h);
+    if (st) return st;
+    // a pull sweep with a unit adjoint at every root routes it along each row's minimizing path:
+    // the adjoint that crosses hi arcs is x*
+    if (flushed && (st = deferred(h, s))) return st;
+    if ((st = all_classes(h, false, flushed ? BWD_STORE_BAR : BWD_STORE, s))) return st;
+    HIP_TRY(launch_fill(h->dlamA, 0.f, h->edge_slots, s));
+    AdjTables A{};
+    A.lam_src = h->T.lam;
+    A.dlam_in = h->dlamA;
+    if ((st = adj_classes(h, A, ADJ_B_FIXED, flushed ? 1 : 0, 0, 1.f, s))) return st;
+    HIP_TRY(launch_gather(h->canon2slot, h->dlamA, x_out, h->E, nullptr, s));
+    return flushed ? recompute_B(h, s) : DD_OK;  // B at the multipliers again
+}
+
 int dd_seg_softmax_vjp(dd_instance *h, const float *alpha, const float *d_alpha, float *d_alpha_hat, void *stream) {
     if (!h || (h->E && (!alpha || !d_alpha || !d_alpha_hat))) return fail(DD_E_ARG, "NULL argument");
     HIP_TRY(launch_softmax_vjp(h->var_ptr, h->var_canon, alpha, d_alpha, d_alpha_hat, (int)h->n, (hipStream_t)stream));

@@ -1,0 +1,170 @@
+// features.hip -- per-row solver features of the appendix's feature table on CDNA4 (gfx950):
+// the smoothed subproblems E_tau^j(lambda) = -tau log sum_{x in X_j} exp(-<lambda, x>/tau) and their
+// gradients, the marginals P(x_l = 1) of the Gibbs distribution exp(-<lambda, x>/tau) on X_j.
+//
+// One wavefront per tile, as in the pass kernels.  Phase 1 sweeps the levels bottom-up in the
+// (soft-min, +) semiring: Bs(v) = softmin(Bs(lo v), lambda_l + Bs(hi v)) is the smoothed cost from
+// v to the 1-terminal, stored to a node array, and Bs(root) = E_tau^j.  Phase 2 sweeps top-down
+// pushing probability mass: the root holds 1, and node v passes p(v) exp(-(beta lambda_l +
+// Bs(child_beta v) - Bs(v)) / tau) along its beta arc (the two shares sum to 1); the mass that
+// takes hi arcs at level l is P(x_l = 1).  Mass is accumulated in LDS with native float adds.
+#include <hip/hip_runtime.h>
+
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace dd {
+namespace {
+
+using namespace dev;
+
+__device__ __forceinline__ float softmin2(float a, float b, float tau) {
+    if (a == kInf) return b;
+    if (b == kInf) return a;
+    const float m = fminf(a, b), d = fabsf(a - b);
+    return m - tau * log1pf(expf(-d / tau));
+}
+
+template <int P, int RMAX>
+__global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__ Bs, float tau, int bar,
+                                                float *__restrict__ E_out, float *__restrict__ p_out, int64_t tile0,
+                                                int64_t ntiles, int WB, int NL) {
+    constexpr int G = 64 / P;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int g = lane / P, p = lane % P;
+    const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;
+    float *buf = lds_f + (size_t)wave * lds_words_features(P, WB, NL);  // two node buffers
+    int *meta = (int *)(buf + 2 * WB * G);
+    int *off = meta + NL * G;
+    const TileCtx tc = tile_ctx(T, tile);
+    const int row = T.bdd[tile * 64 + g];
+    preload_meta<G>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l >= 0 && l < nlev) {
+            const int w = meta[l * G + g] & 0xFFFF;
+            v.W = G == 1 ? uni(w) : w;
+            v.R = uni(meta[l * G] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
+    };
+    auto lam_at = [&](int l) {
+        const int e = tc.ebase + l * G + g;
+        float x = T.lam[e];
+        if (bar) x = x + T.aS[e];
+        return x;
+    };
+    const int mine = p * G + g;
+    // ---- phase 1: bottom-up soft-min costs, stored to Bs
+    int cur = 0;  // buffer holding level l+1
+    if (p == 0) {
+        buf[g] = kInf;
+        buf[G + g] = 0.f;
+    }
+    wave_sync();
+    Lev cn{0, 0, 0};
+    for (int l = nlev - 1; l >= 0; --l) {
+        const Lev c0 = level(l);
+        const float lam = lam_at(l);
+        const float *bn = buf + cur * WB * G;
+        float *bc = buf + (cur ^ 1) * WB * G;
+        const uint32_t dead = (uint32_t)cn.W | ((uint32_t)cn.W << 16);
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < c0.R) {
+                const bool ok = in_level<P>(r, c0.R, lane, c0.W);
+                const uint32_t tp = ok ? T.topo[c0.base + r * 64 + lane] : dead;
+                const float v = softmin2(bn[(int)(tp & 0xFFFFu) * G + g], lam + bn[(int)(tp >> 16) * G + g], tau);
+                bc[mine + r * P * G] = v;
+                if (ok) Bs[c0.base + r * 64 + lane] = v;
+            }
+        }
+        if (p == 0) {
+            bc[c0.W * G + g] = kInf;
+            bc[(c0.W + 1) * G + g] = 0.f;
+        }
+        wave_sync();
+        cur ^= 1;
+        cn = c0;
+    }
+    if (p == 0 && row >= 0 && E_out) E_out[row] = buf[cur * WB * G + g];  // Bs(root)
+    // phase 2 reads back what phase 1 stored: make the stores visible to this wave's loads
+    __threadfence();
+    wave_sync();
+    // ---- phase 2: top-down probability mass; buffers: mass of level l (pa) and of level l+1 (pb)
+    float *pa = buf, *pb = buf + WB * G;
+    {
+        const int R0 = uni(meta[0] >> 16);
+        for (int r = 0; r < R0; ++r) pa[mine + r * P * G] = 0.f;
+        if (p == 0) pa[g] = 1.f;
+    }
+    wave_sync();
+    for (int l = 0; l < nlev; ++l) {
+        const Lev c0 = level(l), c1 = level(l + 1);
+        const int Wn = c1.W;
+        const float lam = lam_at(l);
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r)
+            if (r < c1.R) pb[mine + r * P * G] = 0.f;
+        wave_sync();
+        float hi_mass = 0.f;
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) {
+            if (r < c0.R) {
+                const bool ok = in_level<P>(r, c0.R, lane, c0.W);
+                const float m = ok ? pa[mine + r * P * G] : 0.f;
+                if (m > 0.f) {
+                    const uint32_t tp = T.topo[c0.base + r * 64 + lane];
+                    const int lo = (int)(tp & 0xFFFFu), hi = (int)(tp >> 16);
+                    const float bv = Bs[c0.base + r * 64 + lane];
+                    // children's costs: a node of level l+1 from Bs, a terminal by its code
+                    const float b0 = lo < Wn ? Bs[c1.base + (int64_t)((lo / P) * 64 + g * P + lo % P)]
+                                             : (lo == Wn ? kInf : 0.f);
+                    const float b1 = hi < Wn ? Bs[c1.base + (int64_t)((hi / P) * 64 + g * P + hi % P)]
+                                             : (hi == Wn ? kInf : 0.f);
+                    const float q0 = b0 < kInf ? expf(-(b0 - bv) / tau) : 0.f;
+                    const float q1 = b1 < kInf ? expf(-(lam + b1 - bv) / tau) : 0.f;
+                    if (lo < Wn) lds_fadd(&pb[lo * G + g], m * q0);
+                    if (hi < Wn) lds_fadd(&pb[hi * G + g], m * q1);
+                    hi_mass += m * q1;
+                }
+            }
+        }
+        hi_mass = team_sum<P>(hi_mass);
+        if (p == 0 && c0.W > 0) p_out[T.slot2canon[tc.ebase + l * G + g]] = hi_mass;
+        wave_sync();
+        float *t = pa;
+        pa = pb;
+        pb = t;
+    }
+}
+
+template <int P, int RMAX>
+hipError_t smooth_dispatch(const DevTables &t, const ClassLaunch &c, float *Bs, float tau, int bar, float *E_out,
+                           float *p_out, hipStream_t s) {
+    const int wpb = c.wpb_b;
+    if (wpb < 1 || wpb > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
+    dim3 grid((unsigned)((c.ntiles + wpb - 1) / wpb)), block(64 * wpb);
+    const size_t lds = (size_t)wpb * lds_words_features(P, c.WB, c.NL) * 4;
+    hipLaunchKernelGGL((k_smooth<P, RMAX>), grid, block, lds, s, t, Bs, tau, bar, E_out, p_out, c.tile0, c.ntiles,
+                       c.WB, c.NL);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_smooth(const DevTables &t, const ClassLaunch &c, float *Bs, float tau, int bar, float *E_out,
+                         float *p_out, hipStream_t s) {
+    if (c.ntiles <= 0) return hipSuccess;
+#define DD_SMOOTH(PP, RR) \
+    if (c.P == PP && c.RMAX == RR) return smooth_dispatch<PP, RR>(t, c, Bs, tau, bar, E_out, p_out, s);
+    DD_CLASSES(DD_SMOOTH)
+#undef DD_SMOOTH
+    return hipErrorInvalidValue;
+}
+
+}  // namespace dd

@@ -66,6 +66,7 @@ struct dd_instance {
     bool adj_ready = false;
     float *lam_in = nullptr, *dlamA = nullptr, *dlamB = nullptr, *dMA = nullptr, *dMB = nullptr, *g = nullptr;
     float *dalpha = nullptr, *domega = nullptr, *rec_val = nullptr, *scratch_n = nullptr, *Se = nullptr;
+    float *Bs = nullptr;  // smoothed node costs (allocated on first use)
     int32_t *rec_idx = nullptr;
     std::vector<float *> ck_lam, ck_M;    // checkpoints of the unrolled forward (state at iterations 0, K, 2K, ..., T)
     std::vector<float *> seg_lam, seg_M;  // pass-input states inside one checkpoint segment
