@@ -168,6 +168,47 @@ def other_workloads(stream):
     return out
 
 
+def lp_optimum(prob):
+    """LP relaxation optimum with scipy's HiGHS (host).  For set cover and independent set every row
+    is an integral polytope, so this is the optimum d* of the Lagrange dual."""
+    import scipy.sparse as sp
+    from scipy.optimize import linprog
+    A = sp.csr_matrix((prob.coef.astype(float), prob.col, prob.row_ptr), shape=(prob.m, prob.n))
+    sgn = np.where(prob.sense > 0, -1.0, 1.0)
+    res = linprog(prob.c, A_ub=sp.diags(sgn) @ A, b_ub=sgn * prob.rhs, bounds=(0, 1), method="highs")
+    return float(res.fun) if res.status == 0 else None
+
+
+def driver_leg():
+    """Test-time driver (rounds of T iterations, stop at a relative improvement below 1e-6) on the
+    set-cover and independent-set configurations, with the relative dual gap g(t) and its integral
+    g_I (Sec. "Evaluation") against d* = the LP optimum computed on the host."""
+    import paper_2205_11638_amd as dd
+    import synth
+
+    out = {}
+    for name, T, rounds in (("setcover", 20, 50), ("indset", 50, 20)):
+        w = synth.workload(name)
+        p = w["problem"]
+        inst = dd.Instance(p)  # default parameters: omega = 0.5, alpha = 1/|J_i|
+        inst.solve(T, 1)       # warm-up (captures the graphs)
+        inst.reset()
+        lbs, ms = inst.solve(T, rounds, 1e-6)
+        t0 = time.time()
+        d_star = lp_optimum(p)
+        lp_s = time.time() - t0
+        rec = {"T_round": T, "rounds": len(lbs) - 1, "ms": float(ms[-1]), "lb_init": float(lbs[0]),
+               "lb_final": float(lbs[-1]), "d_star_lp": d_star, "lp_host_s": lp_s}
+        if d_star is not None:
+            g, gi = dd.gap_integral(lbs, ms, d_star)
+            rec.update({"g_final": float(g[-1]), "g_integral_s": gi})
+        out[p.name] = rec
+        log(f"[bench] driver {p.name}: {rec['rounds']} rounds of {T} in {rec['ms']:.1f} ms, bound "
+            f"{rec['lb_final']:.4f}, d* {d_star}, g {rec.get('g_final')}, g_I {rec.get('g_integral_s')} s")
+        inst.close()
+    return out
+
+
 def round_leg(stream, reps=3):
     """One training round of the pipeline on the graph-matching configuration (1.44M edges,
     T = 20, checkpoints every 5): output transforms, non-parametric update, T unrolled iterations,
@@ -287,6 +328,7 @@ def main():
     ap.add_argument("--no-others", action="store_true", help="skip the set-cover / independent-set / GM rates")
     ap.add_argument("--no-round", action="store_true", help="skip the graph-matching training-round leg")
     ap.add_argument("--no-features", action="store_true", help="skip the solver-feature leg")
+    ap.add_argument("--no-driver", action="store_true", help="skip the test-time driver / relative-gap leg")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
     args = ap.parse_args()
@@ -367,6 +409,7 @@ def main():
     bat = None if args.no_batch else batch_leg(args.batch_iters, stream)
     others = None if args.no_others else other_workloads(stream)
     rnd = None if args.no_round else round_leg(stream)
+    drv = None if args.no_driver else driver_leg()
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -398,6 +441,7 @@ def main():
         "batch": bat,
         "other_workloads": others,
         "gm_round": rnd,
+        "driver": drv,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

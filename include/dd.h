@@ -238,6 +238,22 @@ int dd_smoothed(dd_instance *h, float tau, int32_t flushed, float *E_out, float 
  * edge into x_out [edges] (f32, canonical order), at lambda or lambda_bar; ties: lo arcs first. */
 int dd_argmin_assignment(dd_instance *h, int32_t flushed, float *x_out, void *stream);
 
+/* ---- Test-time driver (Sec. "Overall pipeline", Sec. "Evaluation") -------------------------- */
+
+/* Rounds of T iterations of Alg. 1 (as dd_run) with the lower bound after each: stops after
+ * max_rounds rounds or after the first round whose bound improves on the previous one by less than
+ * rel_tol times its magnitude (the paper switches networks at a relative improvement of 1e-6).
+ * lb_trace, ms_trace: host arrays [max_rounds + 1] receiving the bound before the first round and
+ * after each round, with the milliseconds elapsed since the call began (host clock, taken after the
+ * bound's synchronization); *rounds receives the number of rounds run. */
+int dd_solve(dd_instance *h, int32_t T, int32_t max_rounds, double rel_tol, double *lb_trace, double *ms_trace,
+             int32_t *rounds, void *stream);
+
+/* Relative dual gap of a trace (Sec. "Evaluation"): g_i = min((d_star - lb_i) / (d_star - lb_0), 1)
+ * into g_out [k] (may be NULL; 0 when d_star <= lb_0), and its integral over time in seconds with each
+ * value held until the next, g_I = sum_i g_i (ms_{i+1} - ms_i) / 1000.  Host-only. */
+int dd_gap_integral(const double *lb, const double *ms, int32_t k, double d_star, double *g_out, double *g_integral);
+
 /* Nodes of each row's diagram, host array [m] (0 for an empty row). */
 int dd_row_nodes(const dd_instance *h, int64_t *nodes_out);
 

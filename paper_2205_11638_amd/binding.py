@@ -89,6 +89,8 @@ SIGNATURES = {
     "dd_nonparam_update": ([_VP, _VP, _VP], C.c_int),
     "dd_smoothed": ([_VP, C.c_float, C.c_int32, _VP, _VP, _VP], C.c_int),
     "dd_argmin_assignment": ([_VP, C.c_int32, _VP, _VP], C.c_int),
+    "dd_solve": ([_VP, C.c_int32, C.c_int32, C.c_double, _VP, _VP, C.POINTER(C.c_int32), _VP], C.c_int),
+    "dd_gap_integral": ([_VP, _VP, C.c_int32, C.c_double, _VP, C.POINTER(C.c_double)], C.c_int),
     "dd_get_launch": ([_VP, _VP, C.c_int32, C.POINTER(C.c_int32)], C.c_int),
     "dd_set_launch": ([_VP, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32], C.c_int),
     "dd_autotune": ([_VP, C.c_char_p, C.POINTER(C.c_int32), _VP], C.c_int),
@@ -157,6 +159,17 @@ class _ProblemArgs:
                              self.coef.ctypes.data_as(C.POINTER(C.c_int32)),
                              self.sense.ctypes.data_as(C.POINTER(C.c_int8)),
                              self.rhs.ctypes.data_as(C.POINTER(C.c_int64)))
+
+
+def gap_integral(lb, ms, d_star):
+    """(g [k], g_I): the relative dual gap of a trace and its time integral (seconds)."""
+    lb = np.ascontiguousarray(lb, dtype=np.float64)
+    ms = np.ascontiguousarray(ms, dtype=np.float64)
+    g = np.zeros(len(lb))
+    gi = C.c_double()
+    _check(lib().dd_gap_integral(lb.ctypes.data_as(C.c_void_p), ms.ctypes.data_as(C.c_void_p), len(lb),
+                                 float(d_star), g.ctypes.data_as(C.c_void_p), C.byref(gi)))
+    return g, gi.value
 
 
 def compile_row(prob, row):
@@ -336,6 +349,15 @@ class Instance:
             self._h, *args, _dptr(d_theta, torch.float32, self.E) if d_theta is not None else None, _dptr(dw),
             _dptr(da), _dptr(dt) if dt is not None else None, _stream()))
         return dw, da, dt
+
+    def solve(self, T, max_rounds, rel_tol=1e-6):
+        """Test-time driver: (lower bounds, elapsed ms) before the first round and after each round."""
+        lb = np.zeros(int(max_rounds) + 1)
+        ms = np.zeros(int(max_rounds) + 1)
+        r = C.c_int32()
+        _check(self._L.dd_solve(self._h, int(T), int(max_rounds), float(rel_tol), lb.ctypes.data_as(C.c_void_p),
+                                ms.ctypes.data_as(C.c_void_p), C.byref(r), _stream()))
+        return lb[:r.value + 1], ms[:r.value + 1]
 
     def smoothed(self, tau, flushed=False):
         """(E_tau [m], Gibbs marginals P(x_i = 1) [E]) of the smoothed subproblems."""

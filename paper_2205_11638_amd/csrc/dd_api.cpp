@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1165,6 +1166,43 @@ int dd_argmin_assignment(dd_instance *h, int32_t flushed, float *x_out, void *st
     if ((st = adj_classes(h, A, ADJ_B_FIXED, flushed ? 1 : 0, 0, 1.f, s))) return st;
     HIP_TRY(launch_gather(h->canon2slot, h->dlamA, x_out, h->E, nullptr, s));
     return flushed ? recompute_B(h, s) : DD_OK;  // B at the multipliers again
+}
+
+int dd_solve(dd_instance *h, int32_t T, int32_t max_rounds, double rel_tol, double *lb_trace, double *ms_trace,
+             int32_t *rounds, void *stream) {
+    if (!h || T < 1 || max_rounds < 0 || !(rel_tol >= 0.0) || !lb_trace || !ms_trace || !rounds)
+        return fail(DD_E_ARG, "bad argument");
+    const auto t0 = std::chrono::steady_clock::now();
+    auto elapsed_ms = [&] {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    int st = dd_lower_bound(h, &lb_trace[0], nullptr, stream);
+    if (st) return st;
+    ms_trace[0] = elapsed_ms();
+    *rounds = 0;
+    for (int r = 1; r <= max_rounds; ++r) {
+        if ((st = dd_run(h, T, stream))) return st;
+        if ((st = dd_lower_bound(h, &lb_trace[r], nullptr, stream))) return st;  // synchronizes
+        ms_trace[r] = elapsed_ms();
+        *rounds = r;
+        const double prev = lb_trace[r - 1];
+        if ((lb_trace[r] - prev) < rel_tol * std::max(std::fabs(prev), 1e-300)) break;
+    }
+    return DD_OK;
+}
+
+int dd_gap_integral(const double *lb, const double *ms, int32_t k, double d_star, double *g_out,
+                    double *g_integral) {
+    if (!lb || !ms || k < 1 || !g_integral) return fail(DD_E_ARG, "bad argument");
+    const double span = d_star - lb[0];
+    double gi = 0.0;
+    for (int i = 0; i < k; ++i) {
+        const double g = span > 0.0 ? std::min((d_star - lb[i]) / span, 1.0) : 0.0;
+        if (g_out) g_out[i] = g;
+        if (i + 1 < k) gi += g * (ms[i + 1] - ms[i]) * 1e-3;  // each value holds until the next
+    }
+    *g_integral = gi;
+    return DD_OK;
 }
 
 int dd_seg_softmax_vjp(dd_instance *h, const float *alpha, const float *d_alpha, float *d_alpha_hat, void *stream) {

@@ -104,3 +104,19 @@ def dmma_torch(prob, omega, alpha, T, c=None, record=False, lam0=None, M0=None):
     unc = deg == 0
     lb = lb + torch.clamp(c[unc], max=0.0).sum()
     return lb, states
+
+
+def lp_optimum(prob):
+    """Optimum of the LP relaxation (rows as written, 0 <= x <= 1) with scipy's HiGHS.  For programs
+    whose single rows are integral polytopes (set cover, independent set) this is the optimum of the
+    Lagrange dual (D)."""
+    import scipy.sparse as sp
+    from scipy.optimize import linprog
+    A = sp.csr_matrix((prob.coef.astype(float), prob.col, prob.row_ptr), shape=(prob.m, prob.n))
+    le, ge, eq = prob.sense < 0, prob.sense > 0, prob.sense == 0
+    A_ub = sp.vstack([A[le], -A[ge]]).tocsr()
+    b_ub = np.concatenate([prob.rhs[le], -prob.rhs[ge]]).astype(float)
+    kw = {"A_eq": A[eq], "b_eq": prob.rhs[eq].astype(float)} if eq.any() else {}
+    res = linprog(prob.c, A_ub=A_ub, b_ub=b_ub, bounds=(0, 1), method="highs", **kw)
+    assert res.status == 0, res.message
+    return float(res.fun)

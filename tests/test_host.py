@@ -158,3 +158,16 @@ def test_waves_per_block_limited_to_the_compiled_workgroup_size(dd):
     with pytest.raises(dd.DDError) as e:
         dd.Instance(p, waves_per_block=8)
     assert e.value.code == dd.binding.DD_E_ARG
+
+
+def test_gap_integral(dd):
+    # hand-worked: d_init = 0, d* = 10; bounds 0, 5, 8, 10 at 0, 1000, 3000, 4000 ms
+    g, gi = dd.gap_integral([0.0, 5.0, 8.0, 10.0], [0.0, 1000.0, 3000.0, 4000.0], 10.0)
+    np.testing.assert_allclose(g, [1.0, 0.5, 0.2, 0.0])
+    assert gi == pytest.approx(1.0 * 1 + 0.5 * 2 + 0.2 * 1)
+    # a bound below the start is clipped to 1; d* not above the start gives 0
+    g, _ = dd.gap_integral([1.0, -1.0], [0.0, 10.0], 3.0)
+    np.testing.assert_allclose(g, [1.0, 1.0])
+    g, gi = dd.gap_integral([1.0, 2.0], [0.0, 10.0], 1.0)
+    np.testing.assert_allclose(g, [0.0, 0.0])
+    assert gi == 0.0
