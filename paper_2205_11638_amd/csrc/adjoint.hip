@@ -78,8 +78,9 @@ __device__ __forceinline__ AdjEdge adj_edge(const DevTables &T, const AdjTables 
 // the hop), bid (ints), Bst (B of level l+1, update sweeps), then the level table.
 // ------------------------------------------------------------------------------------------
 template <int P, int RMAX, bool UPD>
-__global__ __launch_bounds__(256) void k_adj_F(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int WB,
-                                               int NL) {
+// (the fixed-side variant is asked for 3 waves per SIMD: measured faster; the update variant would spill)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!UPD && RMAX <= 16 ? 3 : 1))) void k_adj_F(
+    DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
     extern __shared__ float lds_f[];
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
