@@ -25,7 +25,7 @@ namespace {
 
 bool shape_ok(const dd_instance *h, const ClassLaunch &c, int wpb) {
     if (wpb < 1 || wpb > dd::kMaxWavesPerBlock) return false;
-    return (int64_t)wpb * dd::lds_words_pass(c.P, c.WB, c.NL) * 4 <= h->lds_budget;
+    return (int64_t)wpb * dd::lds_words_pass_c(c.P, c.RMAX, c.WB, c.NL) * 4 <= h->lds_budget;
 }
 
 std::string signature(const dd_instance *h) {

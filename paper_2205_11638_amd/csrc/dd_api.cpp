@@ -247,9 +247,10 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
                 if (R > RMAX) return fail(DD_E_UNSUPPORTED, "internal: level needs %d rows > %d", R, RMAX);
                 hp.lev_off.push_back((int32_t)off);
                 hp.lev_rows.push_back(R);
-                // one-wave diagrams are stored compactly (levels back to back); teams of a
-                // narrower tile interleave, so their levels are padded to whole rows
-                off += P == 64 ? (int64_t)wmax : (int64_t)R * 64;
+                // one-wave diagrams are stored nearly compactly (each level starts at a multiple
+                // of 4 nodes, for 16-byte row accesses); teams of a narrower tile interleave, so
+                // their levels are padded to whole rows
+                off += P == 64 ? (int64_t)((wmax + 3) & ~3) : (int64_t)R * 64;
             }
             node_slots += off;
             edge_slots += (int64_t)nl * G;
@@ -270,8 +271,8 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
             }
             return best;
         };
-        cl.wpb_f = pick(lds_words_pass(P, cl.WB, cl.NL));
-        cl.wpb_b = pick(lds_words_pass(P, cl.WB, cl.NL));
+        cl.wpb_f = pick(lds_words_pass_c(P, RMAX, cl.WB, cl.NL));
+        cl.wpb_b = pick(lds_words_pass_c(P, RMAX, cl.WB, cl.NL));
         cl.wpb_af = pick(lds_words_adj_F(P, cl.WB, cl.NL));
         cl.wpb_ab = pick(lds_words_adj_B(P, cl.WB, cl.NL));
         if (!cl.wpb_f || !cl.wpb_b || !cl.wpb_af || !cl.wpb_ab)

@@ -82,11 +82,12 @@ __device__ __forceinline__ void lds_fmin(float *a, float v) {
 // Forward pass.  X = F of the current level (min-accumulated for the next one), Y = B of the
 // next level staged from global memory.
 // ------------------------------------------------------------------------------------------
-// One-wave diagrams (P = 64) are stored compactly: level l+1 starts right after the last
-// node of level l, so the last row of a level also reads a few slots of the next level (or
-// of the slack after the array).  Those lanes are masked on that row only: their topology is
-// replaced by two 0-terminal arcs and their stores are skipped.  Narrower teams use levels
-// padded to whole rows, whose padding slots already hold 0-terminal arcs.
+// One-wave diagrams (P = 64) are stored nearly compactly: level l+1 starts at the first
+// multiple of 4 nodes after the last node of level l, so the last row of a level also reads a
+// few slots of the next level (or of the slack after the array).  Those lanes are masked on
+// that row only: their topology is replaced by two 0-terminal arcs and their stores are
+// skipped.  Narrower teams use levels padded to whole rows, whose padding slots already hold
+// 0-terminal arcs.
 template <int P>
 __device__ __forceinline__ bool in_level(int r, int R, int lane, int W) {
     return P < 64 || r < R - 1 || lane < W - r * 64;

@@ -311,11 +311,442 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
     }  // tiles
 }
 
+// ------------------------------------------------------------------------------------------
+// One-wave diagrams (P = 64): the same passes, laid out for wide memory operations.
+// ------------------------------------------------------------------------------------------
+// Each lane owns 4 consecutive nodes of a group of 256 (node k = 256 q + 4 lane + j), so
+// every row of topology, F or B moves with one 16-byte access per lane: a quarter of the
+// memory instructions of one node per lane, whose address processing, not HBM, would
+// otherwise bound the pass.  Levels of these tiles start at multiples of 4 nodes.
+// A hop branches once on its level's group count Q (a binary tree of scalar compares) into a
+// body unrolled over exactly Q groups, so no group carries a predicate of its own.  Node
+// buffers hold RMAX rows of 64 and 64 more slots: clears and staged groups cover all RMAX
+// rows without a test (slots past a level are never read), the terminal sentinels of a full
+// last group fit, and arcs into a terminal send their min-update to the lane's own sink slot
+// past the rows (a terminal needs no forward cost; one slot per lane keeps the atomics
+// conflict free).  Global rows go through buffer resources sized to the level: an access
+// past them loads 0 without touching memory or is dropped, so every load and store is issued
+// unconditionally (no branch, no merge of a prefetched register with its old value, which
+// would force a wait right after the load), and every path of a hop issues the same memory
+// operations after its prefetch, so the next hop waits for the prefetched rows alone.  The
+// multiplier and M of a hop are stored by lane 0 alone: the other lanes' offsets fall outside
+// the tile.  Every level of a built diagram holds at least one node, so the update needs no
+// empty-level case.  The arithmetic is that of the general kernels above; the min over a
+// level's arcs is exact, so the order in which a lane visits its nodes does not matter.
+template <int N>
+struct Count {
+    static constexpr int value = N;
+};
+
+template <int LO, int HI, typename Fn>
+__device__ __forceinline__ void with_count(int n, Fn &&fn) {
+    if constexpr (LO == HI) {
+        fn(Count<LO>{});
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (n <= MID) with_count<LO, MID>(n, fn);
+        else with_count<MID + 1, HI>(n, fn);
+    }
+}
+
+// gfx9-family buffer resource word 3: 32-bit data format, raw (byte) addressing, range checked
+constexpr int kBufWord3 = 0x00020000;
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ rsrc_t buf(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, kBufWord3);
+}
+__device__ __forceinline__ u32x4 ld4(rsrc_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0); }
+__device__ __forceinline__ f32x4 ld4f(rsrc_t r, int off) { return __builtin_bit_cast(f32x4, ld4(r, off)); }
+__device__ __forceinline__ void st4(rsrc_t r, int off, f32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void st1(rsrc_t r, int off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+__device__ __forceinline__ f32x4 &lds4(float *base, int byte_off) { return *(f32x4 *)((char *)base + byte_off); }
+
+// 16 * lane, made anew in each hop body: an offset shared by the bodies (or loop invariant)
+// would be computed once per group ahead of them and held in one register per group, instead
+// of folding the group into the instruction's offset field
+__device__ __forceinline__ int lane16(int lane) {
+    int v = lane * 16;
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
+
+// bytes of a level's node rows (loads) and of its nodes rounded up to whole lane chunks (stores)
+__device__ __forceinline__ int row_bytes(const Lev &c) { return c.R * 256; }
+__device__ __forceinline__ int node_bytes(const Lev &c) { return ((c.W + 3) & ~3) * 4; }
+__device__ __forceinline__ int groups(const Lev &c) { return (c.R + 3) >> 2; }
+
+template <int Q, int RMAX, int MODE, typename Prefetch>
+__device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, float *Fb, const float *Bst,
+                                          const u32x4 (&tp)[RMAX / 4], int lane, int out, const Lev &c0,
+                                          const Lev &c1, float lam, float om, float aS, Prefetch &&prefetch) {
+    constexpr bool UPD = MODE == FWD_UPDATE;
+    constexpr int QM = RMAX / 4, SINK = RMAX * 64;
+    const int l16 = lane16(lane);
+    f32x4 fv[Q];
+    u32x4 t[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        fv[q] = lds4(Fb, l16 + q * 1024);  // slots past the level's width hold +inf
+        t[q] = tp[q];
+    }
+    // last group: this lane's slots past the level's width get two 0-terminal arcs
+    const int rem = c0.W - (Q - 1) * 256 - lane * 4;
+    const uint32_t dead = (uint32_t)c1.W | ((uint32_t)c1.W << 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j >= rem) t[Q - 1][j] = dead;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) st4(Fr, l16 + q * 1024, fv[q]);  // F for the backward pass
+    prefetch(l16);  // after the stores: waiting for the prefetched rows then waits for no fresh store
+    const f32x4 inf4 = {kInf, kInf, kInf, kInf};
+#pragma unroll
+    for (int q = 0; q < QM; ++q) lds4(Fb, l16 + q * 1024) = inf4;  // F of level l+1 accumulates here
+    wave_sync();
+    float lam_new;
+    if (UPD) {
+        float m0 = kInf, m1 = kInf;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float b0 = Bst[(int)(t[q][j] & 0xFFFFu)];
+                const float b1 = Bst[(int)(t[q][j] >> 16)];
+                m0 = fminf(m0, fv[q][j] + b0);
+                m1 = fminf(m1, fv[q][j] + b1);
+            }
+        m0 = team_min<64>(m0);
+        m1 = team_min<64>(m1);
+        m1 += lam;
+        const float Mn = om * (m1 - m0);
+        lam_new = lam - Mn + aS;
+        st1(lam_r, out, lam_new);
+        st1(M_r, out, Mn);
+    } else {
+        lam_new = MODE == FWD_SWEEP_BAR ? lam + aS : lam;
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
+            lds_fmin(&Fb[lo < c1.W ? lo : SINK + lane], fv[q][j]);
+            lds_fmin(&Fb[hi < c1.W ? hi : SINK + lane], fv[q][j] + lam_new);
+        }
+    wave_sync();
+}
+
+template <int RMAX, int MODE, bool LOOP>
+__global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64_t ntiles, int NL) {
+    constexpr bool UPD = MODE == FWD_UPDATE;
+    constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;  // uniform per wave
+    float *Fb = lds_f + (size_t)wave * lds_words_pass_w(RMAX, NL);
+    float *Bst = Fb + NB;
+    int *meta = (int *)(Bst + NB);
+    int *off = meta + NL;
+    const f32x4 inf4 = {kInf, kInf, kInf, kInf};
+    for (;;) {
+        const TileCtx tc = tile_ctx(T, tile);
+        preload_meta<1>(T, tc, lane, meta, off);
+        const int nlev = tc.nlev;
+        auto level = [&](int l) {
+            Lev v{0, 0, 0};
+            if (l < nlev) {
+                v.W = uni(meta[l] & 0xFFFF);
+                v.R = uni(meta[l] >> 16);
+                v.base = tc.nbase + (int64_t)uni(off[l]);
+            }
+            return v;
+        };
+        const rsrc_t lam_r = buf(T.lam + tc.ebase, nlev * 4), M_r = buf(T.M + tc.ebase, nlev * 4);
+        const int out0 = lane * nlev * 4;  // hop l stores at out0 + 4 l: in range for lane 0 only
+        Lev c0 = level(0), c1 = level(1), c2 = level(2);
+        u32x4 tpn[QM];
+        f32x4 bvn[QM];
+        {
+            const int l16 = lane16(lane);
+            const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), br = buf(T.B + c1.base, row_bytes(c1));
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                tpn[q] = ld4(tr, l16 + q * 1024);
+                bvn[q] = UPD ? ld4f(br, l16 + q * 1024) : inf4;
+            }
+        }
+        float lamn = T.lam[tc.ebase], aSn = T.aS[tc.ebase], omn = UPD ? T.omega[tc.ebase] : 0.f;
+        {
+            const int l16 = lane16(lane);
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                f32x4 v = inf4;
+                if (q == 0 && lane == 0) v[0] = 0.f;  // F(root) = 0
+                lds4(Fb, l16 + q * 1024) = v;
+            }
+        }
+        wave_sync();
+        for (int l = 0; l < nlev; ++l) {
+            const float lam = lamn, om = omn, aS = aSn;
+            u32x4 tp[QM];
+#pragma unroll
+            for (int q = 0; q < QM; ++q) tp[q] = tpn[q];
+            if (UPD) {
+                // B of level l+1, then its terminals
+                const int l16 = lane16(lane);
+#pragma unroll
+                for (int q = 0; q < QM; ++q) lds4(Bst, l16 + q * 1024) = bvn[q];
+                if (lane == 0) {
+                    Bst[c1.W] = kInf;
+                    Bst[c1.W + 1] = 0.f;
+                }
+            }
+            // prefetch: topology of l+1, B of l+2, edge data of l+1 (the last hop reloads its own)
+            auto prefetch = [&](int l16) {
+                const rsrc_t tr = buf(T.topo + c1.base, row_bytes(c1)), br = buf(T.B + c2.base, row_bytes(c2));
+#pragma unroll
+                for (int q = 0; q < QM; ++q) {
+                    tpn[q] = ld4(tr, l16 + q * 1024);
+                    if (UPD) bvn[q] = ld4f(br, l16 + q * 1024);
+                }
+                const int e = tc.ebase + min(l + 1, nlev - 1);
+                lamn = T.lam[e];
+                aSn = T.aS[e];
+                if (UPD) omn = T.omega[e];
+            };
+            const rsrc_t Fr = buf(T.F + c0.base, node_bytes(c0));
+            with_count<1, QM>(groups(c0), [&](auto qc) {
+                fwd_hop_w<decltype(qc)::value, RMAX, MODE>(Fr, lam_r, M_r, Fb, Bst, tp, lane, out0 + 4 * l, c0, c1,
+                                                           lam, om, aS, prefetch);
+            });
+            c0 = c1;
+            c1 = c2;
+            c2 = level(l + 3);
+        }
+        if (!LOOP) break;
+        tile += (int64_t)gridDim.x * (blockDim.x >> 6);
+        if (tile >= tile0 + ntiles) break;
+        wave_sync();
+    }  // tiles
+}
+
+// Backward hop of level l: bn = B of level l+1 (Wn its width: terminals at Wn, Wn+1), bc
+// receives B of level l, which also goes to global memory here, from registers.
+template <int Q, int RMAX, int MODE>
+__device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t lam_r, rsrc_t M_r, const float *bn,
+                                          float *bc, const u32x4 (&tp)[RMAX / 4], const f32x4 (&fn)[RMAX / 4],
+                                          int lane, int out, const Lev &c0, int Wn, float lam, float om, float aS,
+                                          int e) {
+    constexpr bool UPD = MODE == BWD_UPDATE, MM = MODE == BWD_MM;
+    constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM || MODE == BWD_STORE_BAR;
+    constexpr bool STOREB = UPD || MODE == BWD_STORE || MODE == BWD_STORE_BAR;
+    constexpr int QM = RMAX / 4;
+    const int l16 = lane16(lane);
+    u32x4 t[Q];
+    f32x4 b0[Q], b1[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) t[q] = tp[q];
+    const int rem = c0.W - (Q - 1) * 256 - lane * 4;
+    const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j >= rem) t[Q - 1][j] = dead;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            b0[q][j] = bn[(int)(t[q][j] & 0xFFFFu)];
+            b1[q][j] = bn[(int)(t[q][j] >> 16)];
+        }
+    const float lam_use = BAR ? lam + aS : lam;
+    float lam_new = lam_use;
+    if (NEEDF) {
+        float m0 = kInf, m1 = kInf;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                m0 = fminf(m0, fn[q][j] + b0[q][j]);
+                m1 = fminf(m1, fn[q][j] + b1[q][j]);
+            }
+        m0 = team_min<64>(m0);
+        m1 = team_min<64>(m1);
+        m1 += lam_use;
+        if (UPD) {
+            const float Mn = om * (m1 - m0);
+            lam_new = lam - Mn + aS;
+            st1(lam_r, out, lam_new);
+            st1(M_r, out, Mn);
+        } else if (lane == 0) {
+            const int ce = T.slot2canon[e];
+            T.out0[ce] = m0;
+            T.out1[ce] = m1;
+        }
+    }
+    f32x4 bv[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[q][j] = fminf(b0[q][j], lam_new + b1[q][j]);
+        lds4(bc, l16 + q * 1024) = bv[q];
+    }
+    if (lane == 0) {
+        bc[c0.W] = kInf;
+        bc[c0.W + 1] = 0.f;
+    }
+    if (STOREB) {
+        // groups past the level fall outside Br and are dropped: the same stores on every path
+        const f32x4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < QM; ++q) st4(Br, l16 + q * 1024, q < Q ? bv[q < Q ? q : 0] : z);
+    }
+}
+
+template <int RMAX, int MODE, bool LOOP>
+__global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64_t ntiles, int NL) {
+    constexpr bool UPD = MODE == BWD_UPDATE, MM = MODE == BWD_MM;
+    constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM || MODE == BWD_STORE_BAR;
+    constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;
+    float *buf0 = lds_f + (size_t)wave * lds_words_pass_w(RMAX, NL);
+    int *meta = (int *)(buf0 + 2 * NB);
+    int *off = meta + NL;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    for (;;) {
+        const TileCtx tc = tile_ctx(T, tile);
+        const int row = T.bdd[tile * 64];
+        preload_meta<1>(T, tc, lane, meta, off);
+        const int nlev = tc.nlev;
+        auto level = [&](int l) {
+            Lev v{0, 0, 0};
+            if (l >= 0 && l < nlev) {
+                v.W = uni(meta[l] & 0xFFFF);
+                v.R = uni(meta[l] >> 16);
+                v.base = tc.nbase + (int64_t)uni(off[l]);
+            }
+            return v;
+        };
+        const rsrc_t lam_r = buf(T.lam + tc.ebase, nlev * 4), M_r = buf(T.M + tc.ebase, nlev * 4);
+        const int out0 = lane * nlev * 4;  // hop l stores at out0 + 4 l: in range for lane 0 only
+        Lev c0 = level(nlev - 1), cp = level(nlev - 2);  // levels l, l-1
+        int Wn = 0;                                       // width of level l+1 (none below the last)
+        u32x4 tpn[QM];
+        f32x4 fn[QM];
+        {
+            const int l16 = lane16(lane);
+            const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), fr = buf(T.F + c0.base, row_bytes(c0));
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                tpn[q] = ld4(tr, l16 + q * 1024);
+                fn[q] = NEEDF ? ld4f(fr, l16 + q * 1024) : zero4;
+            }
+        }
+        const int et = tc.ebase + nlev - 1;
+        float lamn = T.lam[et], aSn = (UPD || BAR) ? T.aS[et] : 0.f, omn = UPD ? T.omega[et] : 0.f;
+        int cur = 0;  // buffer holding B of level l+1 (terminals only, below the last level)
+        if (lane == 0) {
+            buf0[0] = kInf;
+            buf0[1] = 0.f;
+        }
+        wave_sync();
+        for (int l = nlev - 1; l >= 0; --l) {
+            const float lam = lamn, om = omn, aS = aSn;
+            u32x4 tp[QM];
+            f32x4 fv[QM];
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                tp[q] = tpn[q];
+                fv[q] = fn[q];
+            }
+            const float *bn = buf0 + cur * NB;
+            float *bc = buf0 + (cur ^ 1) * NB;
+            // prefetch level l-1 (the first level reloads its own edge data)
+            {
+                const int l16 = lane16(lane);
+                const rsrc_t tr = buf(T.topo + cp.base, row_bytes(cp)), fr = buf(T.F + cp.base, row_bytes(cp));
+#pragma unroll
+                for (int q = 0; q < QM; ++q) {
+                    tpn[q] = ld4(tr, l16 + q * 1024);
+                    if (NEEDF) fn[q] = ld4f(fr, l16 + q * 1024);
+                }
+                const int e = tc.ebase + max(l - 1, 0);
+                lamn = T.lam[e];
+                if (UPD || BAR) aSn = T.aS[e];
+                if (UPD) omn = T.omega[e];
+            }
+            const rsrc_t Br = buf(T.B + c0.base, node_bytes(c0));
+            with_count<1, QM>(groups(c0), [&](auto qc) {
+                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, lam_r, M_r, bn, bc, tp, fv, lane, out0 + 4 * l, c0,
+                                                           Wn, lam, om, aS, tc.ebase + l);
+            });
+            wave_sync();
+            cur ^= 1;
+            Wn = c0.W;
+            c0 = cp;
+            cp = level(l - 2);
+        }
+        if (!MM && lane == 0 && row >= 0) {
+            const float e0 = buf0[cur * NB];  // B(root) = E^j at the multipliers swept
+            if (BAR) T.energies[row] = e0;
+            else T.en_lam[row] = e0;
+        }
+        if (!LOOP) break;
+        tile += (int64_t)gridDim.x * (blockDim.x >> 6);
+        if (tile >= tile0 + ntiles) break;
+        wave_sync();
+    }  // tiles
+}
+
 inline unsigned full_grid(int64_t ntiles, int wpb) { return (unsigned)((ntiles + wpb - 1) / wpb); }
 
+template <int RMAX>
+hipError_t fwd_dispatch_w(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
+    const unsigned full = full_grid(c.ntiles, c.wpb_f);
+    dim3 grid(full), block(64 * c.wpb_f);
+    size_t lds = (size_t)c.wpb_f * lds_words_pass_w(RMAX, c.NL) * 4;
+    if (mode == FWD_UPDATE && c.grid_f > 0 && (unsigned)c.grid_f < full)
+        hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_UPDATE, true>), dim3(c.grid_f), block, lds, s, t, c.tile0, c.ntiles, c.NL);
+    else if (mode == FWD_UPDATE)
+        hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_UPDATE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL);
+    else if (mode == FWD_SWEEP_BAR)
+        hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_SWEEP_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL);
+    else
+        hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_SWEEP_LAM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL);
+    return hipGetLastError();
+}
+
+template <int RMAX>
+hipError_t bwd_dispatch_w(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
+    const unsigned full = full_grid(c.ntiles, c.wpb_b);
+    dim3 grid(full), block(64 * c.wpb_b);
+    size_t lds = (size_t)c.wpb_b * lds_words_pass_w(RMAX, c.NL) * 4;
+    if (mode == BWD_UPDATE && c.grid_b > 0 && (unsigned)c.grid_b < full) {
+        hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_UPDATE, true>), dim3(c.grid_b), block, lds, s, t, c.tile0, c.ntiles, c.NL);
+        return hipGetLastError();
+    }
+    switch (mode) {
+        case BWD_UPDATE: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_UPDATE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
+        case BWD_STORE: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_STORE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
+        case BWD_EN_LAM: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_EN_LAM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
+        case BWD_EN_BAR: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_EN_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
+        case BWD_STORE_BAR: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_STORE_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
+        default: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_MM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
+    }
+    return hipGetLastError();
+}
+
 template <int P, int RMAX>
-hipError_t fwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
-    if (c.wpb_f < 1 || c.wpb_f > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
+hipError_t fwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
     const unsigned full = full_grid(c.ntiles, c.wpb_f);
     dim3 grid(full), block(64 * c.wpb_f);
     size_t lds = (size_t)c.wpb_f * lds_words_pass(P, c.WB, c.NL) * 4;
@@ -334,8 +765,7 @@ hipError_t fwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipS
 }
 
 template <int P, int RMAX>
-hipError_t bwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
-    if (c.wpb_b < 1 || c.wpb_b > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
+hipError_t bwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
     const unsigned full = full_grid(c.ntiles, c.wpb_b);
     dim3 grid(full), block(64 * c.wpb_b);
     size_t lds = (size_t)c.wpb_b * lds_words_pass(P, c.WB, c.NL) * 4;
@@ -353,6 +783,21 @@ hipError_t bwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipS
         default: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_MM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
     }
     return hipGetLastError();
+}
+
+
+template <int P, int RMAX>
+hipError_t fwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
+    if (c.wpb_f < 1 || c.wpb_f > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
+    if constexpr (P == 64) return fwd_dispatch_w<RMAX>(t, c, mode, s);
+    else return fwd_dispatch_g<P, RMAX>(t, c, mode, s);
+}
+
+template <int P, int RMAX>
+hipError_t bwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
+    if (c.wpb_b < 1 || c.wpb_b > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
+    if constexpr (P == 64) return bwd_dispatch_w<RMAX>(t, c, mode, s);
+    else return bwd_dispatch_g<P, RMAX>(t, c, mode, s);
 }
 
 
@@ -487,12 +932,22 @@ template <int P, int RMAX>
 int pass_blocks_per_cu_t(const ClassLaunch &c, bool fwd) {
     int nb = 0;
     const int wpb = fwd ? c.wpb_f : c.wpb_b;
-    const size_t lds = (size_t)wpb * lds_words_pass(P, c.WB, c.NL) * 4;
-    hipError_t e = fwd ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, reinterpret_cast<const void *>(&k_fwd<P, RMAX, FWD_UPDATE, true>), 64 * wpb, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                             &nb, reinterpret_cast<const void *>(&k_bwd<P, RMAX, BWD_UPDATE, true>), 64 * wpb, lds);
-    return e == hipSuccess ? nb : 0;
+    const size_t lds = (size_t)wpb * lds_words_pass_c(P, RMAX, c.WB, c.NL) * 4;
+    if constexpr (P == 64) {
+        const hipError_t e =
+            fwd ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, reinterpret_cast<const void *>(&k_fwd_w<RMAX, FWD_UPDATE, true>), 64 * wpb, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, reinterpret_cast<const void *>(&k_bwd_w<RMAX, BWD_UPDATE, true>), 64 * wpb, lds);
+        return e == hipSuccess ? nb : 0;
+    } else {
+        const hipError_t e =
+            fwd ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, reinterpret_cast<const void *>(&k_fwd<P, RMAX, FWD_UPDATE, true>), 64 * wpb, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &nb, reinterpret_cast<const void *>(&k_bwd<P, RMAX, BWD_UPDATE, true>), 64 * wpb, lds);
+        return e == hipSuccess ? nb : 0;
+    }
 }
 
 }  // namespace

@@ -78,6 +78,15 @@ constexpr int kMaxWavesPerBlock = 4;
 constexpr int lds_words_pass(int P, int WB, int NL) {  // constexpr: usable in device code too
     return 2 * WB * (64 / P) + NL * ((64 / P) + 1);
 }
+// One-wave diagrams (P = 64) use pass kernels whose node buffers always hold RMAX whole rows
+// plus 64 slots (terminal sentinels; one sink slot per lane for arcs into a terminal); a
+// wave's share is a multiple of 4 words, so 16-byte LDS accesses stay aligned.
+constexpr int node_buf_w(int RMAX) { return RMAX * 64 + 64; }
+constexpr int lds_words_pass_w(int RMAX, int NL) { return 2 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+// LDS words per wave of the pass kernels of a class
+constexpr int lds_words_pass_c(int P, int RMAX, int WB, int NL) {
+    return P == 64 ? lds_words_pass_w(RMAX, NL) : lds_words_pass(P, WB, NL);
+}
 
 #define DD_CLASSES(X) \
     X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(64, 8) X(64, 12) X(64, 16) X(64, 24) X(64, 32)
