@@ -108,6 +108,27 @@ def adjoint_leg(inst, T, K, reps, stream):
             "kernels": kernels}
 
 
+def stream_reference(reps=10):
+    """HBM rate of a plain elementwise stream on this GPU (torch.add: two 1 GiB reads, one 1 GiB
+    write), for reading the roofline fraction against what streaming code reaches here."""
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.empty_like(a)
+    torch.add(a, b, out=c)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        torch.add(a, b, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b, c
+    return 3 * 4 * n / ms / 1e6  # GB/s
+
+
 def features_leg(inst, stream):
     """The solver features of the appendix's feature table on the main instance: smoothed energies
     and Gibbs marginals at tau = 1, 10, 100 (at lambda_bar) and the minimizing assignment."""
@@ -398,6 +419,8 @@ def main():
     achieved = b_dom / (tot_dom / n_dom) / 1e6   # bytes / ms -> GB/s
     arcs = int(st["arcs"])
     value = arcs * T / (ms / 1e3)
+    stream_gbs = stream_reference()
+    log(f"[bench] stream reference (torch.add, 3 x 1 GiB): {stream_gbs:.1f} GB/s")
     feats = None if args.no_features else features_leg(inst, stream)
     adj = None
     if not args.no_adjoint:
@@ -433,7 +456,8 @@ def main():
                    "launch_shapes": inst.launch_shapes()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(dom, prob.name),
-                     "algorithmic_bytes_per_launch": b_dom, "avg_launch_ms": tot_dom / n_dom},
+                     "algorithmic_bytes_per_launch": b_dom, "avg_launch_ms": tot_dom / n_dom,
+                     "stream_reference_gbs": stream_gbs, "frac_of_stream_reference": achieved / stream_gbs},
         "hbm_frac_step": (sum(b * n for n, _, b in prof.values()) / args.steps) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "lower_bound": lb[0],
         "adjoint": adj,

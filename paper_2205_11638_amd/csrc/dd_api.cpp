@@ -399,8 +399,12 @@ int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
             const bool loop = mode == (fwd ? (int)FWD_UPDATE : (int)BWD_UPDATE) && grid > 0 &&
                               (int64_t)grid < (cl.ntiles + wpb - 1) / wpb;
             char name[96];
-            snprintf(name, sizeof name, "%s<%d, %d, %d, %s>", fwd ? "k_fwd" : "k_bwd", cl.P, cl.RMAX, mode,
-                     loop ? "true" : "false");
+            if (cl.P == 64)  // one-wave tiles run the wide-row kernels
+                snprintf(name, sizeof name, "%s<%d, %d, %s>", fwd ? "k_fwd_w" : "k_bwd_w", cl.RMAX, mode,
+                         loop ? "true" : "false");
+            else
+                snprintf(name, sizeof name, "%s<%d, %d, %d, %s>", fwd ? "k_fwd" : "k_bwd", cl.P, cl.RMAX, mode,
+                         loop ? "true" : "false");
             return std::string(name);
         },
         [&](const ClassLaunch &cl) { return algorithmic_bytes(fwd, mode, cl); });
