@@ -380,9 +380,10 @@ int per_class(dd_instance *h, hipStream_t s, L launch, N name, B bytes) {
     return DD_OK;
 }
 
-std::string kname(const char *k, const ClassLaunch &cl, int mode) {
+// a kernel templated on the class, named as the profiler prints it
+std::string kname(const char *k, const ClassLaunch &cl) {
     char name[96];
-    snprintf(name, sizeof name, "%s<%d, %d, %d>", k, cl.P, cl.RMAX, mode);
+    snprintf(name, sizeof name, "%s<%d, %d>", k, cl.P, cl.RMAX);
     return name;
 }
 
@@ -417,7 +418,12 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
     const char *nm = which == ADJ_F_UPDATE || which == ADJ_F_FIXED ? "k_adj_F" : "k_adj_B";
     return per_class(
         h, s, [&](const ClassLaunch &cl, hipStream_t cs) { return launch_adj(h->T, A, cl, which, bar, recs, seed, cs); },
-        [&](const ClassLaunch &cl) { return kname(nm, cl, upd ? 1 : 0); },
+        [&](const ClassLaunch &cl) {
+            // the kernel and template arguments as the profiler prints them
+            char name[96];
+            snprintf(name, sizeof name, "%s<%d, %d, %s>", nm, cl.P, cl.RMAX, upd ? "true" : "false");
+            return std::string(name);
+        },
         [&](const ClassLaunch &cl) {
             return upd ? 12.0 * cl.nodes + 68.0 * cl.edges : 8.0 * cl.nodes + 28.0 * cl.edges;
         });
@@ -1149,7 +1155,7 @@ int dd_smoothed(dd_instance *h, float tau, int32_t flushed, float *E_out, float 
         h, s, [&](const ClassLaunch &cl, hipStream_t cs) {
             return launch_smooth(h->T, cl, h->Bs, tau, flushed ? 1 : 0, E_out, p_out, cs);
         },
-        [&](const ClassLaunch &cl) { return kname("k_smooth", cl, 0); },
+        [&](const ClassLaunch &cl) { return kname("k_smooth", cl); },
         // per node: topology twice, the soft-min cost written, read back and gathered for two
         // children (24 B); per edge: multipliers (and alpha*S) twice, the marginal and its index
         [&](const ClassLaunch &cl) { return 24.0 * cl.nodes + 24.0 * cl.edges; });
