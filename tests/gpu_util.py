@@ -47,3 +47,36 @@ def assert_close_scaled(got, ref, scale, rtol, what=""):
         k = int(np.argmax(err / bound))
         raise AssertionError(f"{what}: {int(bad.sum())}/{bad.size} entries off; worst at {k}: got {got[k]!r} "
                              f"ref {ref[k]!r} scale {scale[k]!r} (bound {bound[k]:.3g})")
+
+
+def _row_of_width(rng, n, lo, hi, k, amax):
+    """A knapsack row (k variables, a ~ U{1..amax}) whose diagram width lies in (lo, hi]: capacities are
+    tried on one-row programs until the library reports such a width."""
+    import synth
+    import paper_2205_11638_amd as dd
+    cols = rng.choice(n, size=k, replace=False)
+    a = rng.integers(1, amax + 1, size=k)
+    for frac in np.linspace(0.05, 0.5, 46):
+        rhs = int(frac * a.sum())
+        one = synth.generators._from_rows(n, -np.ones(n), [(cols, a, -1, rhs)], "probe")
+        w = dd.Instance(one).stats["max_width"]
+        if lo < w <= hi:
+            return (cols, a, -1, rhs), w
+    raise AssertionError(f"no capacity gives a width in ({lo}, {hi}]")
+
+
+def wide_class_problem(rmax):
+    """A program whose one-wave diagrams fall in the register-tile class RMAX (the widest row sets the
+    class of all of them): one row of width in that class's range, narrower knapsack rows, and
+    2-variable rows (another tile class).  Returns (problem, width of the widest row)."""
+    import synth
+    lo = {4: 128, 8: 256, 12: 512, 16: 768, 24: 1024, 32: 1536}[rmax]
+    rng = np.random.default_rng(100 + rmax)
+    n = 3000
+    wide, w = _row_of_width(rng, n, lo, rmax * 64, *((200, 40) if rmax > 16 else (140, 24)))
+    rows = [wide]
+    k = synth.knapsack(n=n, m=6, kmin=20, kmax=60, amax=10, frac=0.3, seed=200 + rmax)
+    rows += [k.row(j) for j in range(k.m)]
+    s = synth.independent_set(n=n, M=50, seed=300 + rmax)
+    rows += [s.row(j) for j in range(s.m)]
+    return synth.generators._from_rows(n, -rng.uniform(0, 1, size=n), rows, f"class-{rmax}"), w

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import host, make_instance, say
+from tests.gpu_util import host, make_instance, say, wide_class_problem
 
 pytestmark = pytest.mark.gpu
 GRAD_RTOL = 1e-4
@@ -76,6 +76,8 @@ CASES = {
     "team-sizes": team_size_problem,
     "knapsack-small": lambda: synth.knapsack(n=3000, m=30, seed=9),
     "gm-full": lambda: synth.workload("gm")["problem"],
+    "wide-24": lambda: wide_class_problem(24)[0],
+    "wide-32": lambda: wide_class_problem(32)[0],
 }
 
 

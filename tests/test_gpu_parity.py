@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import assert_close_scaled, host, make_instance, row_scale, say
+from tests.gpu_util import assert_close_scaled, host, make_instance, row_scale, say, wide_class_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -114,6 +114,29 @@ def test_single_pass_parity_wide_and_narrow(orc):
     inst = check_passes(orc, p, synth.sigmoid(rng.normal(size=p.nnz)), rng.normal(0, 0.1, size=p.nnz), 4, "wide")
     assert 1024 < inst.stats["max_width"] <= 2048
     assert inst.stats["classes"] >= 2          # one-wave diagrams share a launch; 2-variable rows use another
+
+
+@pytest.mark.parametrize("rmax", [4, 8, 12, 16, 24, 32])
+def test_single_pass_parity_every_wide_class(orc, rmax):
+    """One-wave diagrams in each register-tile class (the widest row sets the class of all of them):
+    partial last groups and levels whose widths are not multiples of 4 occur along every row."""
+    p, w = wide_class_problem(rmax)
+    rng = np.random.default_rng(400 + rmax)
+    say(f"wide class RMAX {rmax}: widest row {w}, E={p.nnz}")
+    ah = rng.normal(0, 0.2, size=p.nnz)
+    inst = check_passes(orc, p, synth.sigmoid(rng.normal(size=p.nnz)), ah, 4, f"class{rmax}")
+    assert {c["RMAX"] for c in inst.launch_shapes() if c["P"] == 64} == {rmax}
+    # the bound sweep and the min-marginal query of the same kernels at the state reached
+    lam, M = (host(t) for t in inst.get_state())
+    lb_g, dl_g = inst.lower_bound()
+    assert lb_g == pytest.approx(orc.lower_bound(p, orc.softmax_alpha(p, f32(ah)), lam, M)[0], rel=LB_RTOL)
+    assert dl_g <= lb_g + 1e-6 * abs(lb_g)
+    lbar = host(inst.get_state(flushed=True)[0])
+    m0g, m1g = (host(t) for t in inst.min_marginals())
+    m0o, m1o = orc.min_marginals(p, lbar)
+    sc = row_scale(p, lbar)
+    assert_close_scaled(m0g, m0o, sc, RTOL, f"class{rmax} m0")
+    assert_close_scaled(m1g, m1o, sc, RTOL, f"class{rmax} m1")
 
 
 def test_single_pass_parity_every_team_size(orc):
