@@ -429,6 +429,13 @@ def main():
         adj = adjoint_leg(inst, T, 1, args.adjoint_reps, stream)
         adj["ckpt_every_5"] = {k: v for k, v in adjoint_leg(inst, T, 5, args.adjoint_reps, stream).items()
                                if k != "kernels"}
+        # the whole trajectory kept on the device (2T + 1 node-cost arrays): no pass recomputed
+        try:
+            adj["stored_trajectory"] = {k: v for k, v in adjoint_leg(inst, T, -1, args.adjoint_reps, stream).items()
+                                        if k != "kernels"}
+        except RuntimeError as e:
+            adj["stored_trajectory"] = {"error": str(e)}
+            log(f"[bench] stored trajectory: {e}")
     bat = None if args.no_batch else batch_leg(args.batch_iters, stream)
     others = None if args.no_others else other_workloads(stream)
     rnd = None if args.no_round else round_leg(stream)

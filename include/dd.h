@@ -167,6 +167,10 @@ int dd_set_costs(dd_instance *h, const float *c, void *stream);
 
 /* Reset, then run T iterations of Alg. 1 keeping the state (lambda, M) every ckpt_every
  * iterations (0: the instance default), and return the lower bound of the final state.
+ * ckpt_every = -1 keeps the whole trajectory on the device instead: the node costs F or B that
+ * every pass wrote (2T + 1 arrays of the diagrams' node count, f32) and the state before every
+ * pass, so dd_backward recomputes no pass (DD_E_OOM, with nothing run, when the free device
+ * memory is short; the arrays stay allocated with the instance for later calls).
  * Records what dd_backward needs; any later call that changes the state (a pass, reset,
  * set_state, set_params, set_costs) invalidates the record. */
 int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream);

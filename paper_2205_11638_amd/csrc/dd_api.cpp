@@ -1003,12 +1003,79 @@ int dd_pass_vjp(dd_instance *h, int32_t direction, const float *lam_in, const fl
 
 namespace {
 
+// The unrolled forward with its whole trajectory kept on the device: every forward pass writes F
+// into an array of its own and every backward pass B (the tables are pointed at them), and the
+// state before every pass is kept.  Afterwards the instance is back on its own arrays, with B as
+// the last pass left it, so any later call finds it as after an ordinary run.
+int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const size_t nodes = (size_t)h->node_slots + 64, bytes = nodes * sizeof(float);
+    size_t need = 0;
+    if ((int)h->trF.size() < T) need += (size_t)T - h->trF.size();
+    if ((int)h->trB.size() < T + 1) need += (size_t)T + 1 - h->trB.size();
+    if (need) {
+        size_t free_b = 0, total_b = 0;
+        HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+        const size_t margin = (size_t)2 << 30;
+        if (need * bytes + margin > free_b)
+            return fail(DD_E_OOM,
+                        "a stored trajectory of %d iterations needs %.1f GB more device memory (%.1f GB free): "
+                        "use checkpoints (ckpt_every >= 1)",
+                        T, (double)(need * bytes) / 1e9, (double)free_b / 1e9);
+    }
+    int st;
+    while ((int)h->trF.size() < T) {
+        float *p = nullptr;
+        if ((st = h->alloc(&p, nodes))) return st;
+        h->trF.push_back(p);
+    }
+    while ((int)h->trB.size() < T + 1) {
+        float *p = nullptr;
+        if ((st = h->alloc(&p, nodes))) return st;
+        h->trB.push_back(p);
+    }
+    h->F0 = h->T.F;
+    h->B0 = h->T.B;
+    h->fwd_stored = false;
+    h->T.B = h->trB[0];  // B at the start state goes to the first stored array
+    if (from_state) {
+        if ((st = recompute_B(h, s))) return st;
+        h->version++;
+    } else if ((st = dd_reset(h, stream))) {
+        h->T.B = h->B0;
+        return st;
+    }
+    st = save_state(h, h->tr_lam, h->tr_M, 0, s);
+    for (int t = 0; t < T && st == DD_OK; ++t) {
+        h->T.F = h->trF[t];
+        h->T.B = h->trB[t];
+        if ((st = dd_run_pass(h, 0, stream)) || (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s))) break;
+        h->T.B = h->trB[t + 1];
+        if ((st = dd_run_pass(h, 1, stream))) break;
+        st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s);
+    }
+    if (st == DD_OK) st = dd_lower_bound(h, lb, nullptr, stream);
+    const hipError_t e = hipMemcpyAsync(h->B0, h->trB[T], bytes, hipMemcpyDeviceToDevice, s);
+    h->T.F = h->F0;
+    h->T.B = h->B0;
+    if (st) return st;
+    if (e != hipSuccess) return fail(DD_E_HIP, "copy of the final B: %s", hipGetErrorString(e));
+    h->fwd_T = T;
+    h->fwd_K = -1;
+    h->fwd_stored = true;
+    h->fwd_from_state = from_state;
+    h->fwd_version = h->version;
+    return DD_OK;
+}
+
 int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, bool from_state, void *stream) {
     if (!h || T < 0 || !lb) return fail(DD_E_ARG, "bad instance, T or lb");
-    if (ckpt_every < 0) return fail(DD_E_ARG, "ckpt_every must be >= 0");
+    if (ckpt_every < -1) return fail(DD_E_ARG, "ckpt_every must be >= -1");
     hipStream_t s = (hipStream_t)stream;
     int st = adj_alloc(h);
     if (st) return st;
+    if (ckpt_every == -1) return forward_stored(h, T, lb, from_state, stream);
+    h->fwd_stored = false;
     const int K = ckpt_every > 0 ? ckpt_every : (h->ckpt_default > 0 ? h->ckpt_default : 5);
     if (from_state) {
         // a forward pass reads B at its input multipliers
@@ -1039,13 +1106,21 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     if (d_c && h->fwd_from_state)
         return fail(DD_E_ARG, "d_c needs an unrolled forward from the reset state (lambda = c/|J_i|)");
     hipStream_t s = (hipStream_t)stream;
-    const int T = h->fwd_T, K = h->fwd_K, nseg = (T + K - 1) / K;
+    const bool stored = h->fwd_stored;
+    const int T = h->fwd_T, K = stored ? 1 : h->fwd_K, nseg = (T + K - 1) / K;
     const float seed = (float)dlb;
     int st;
     // adjoint of the lower bound at the final state: dLB / dlambda_bar_j = argmin assignment of row j
-    if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;
+    if (stored) st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)T, s);
+    else st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s);
+    if (st) return st;
     if ((st = deferred(h, s))) return st;
-    if ((st = all_classes(h, false, BWD_STORE_BAR, s))) return st;
+    if (stored) h->T.B = h->F0;  // a stored trajectory keeps the final B in B0: the bound's B goes to the spare array
+    st = all_classes(h, false, BWD_STORE_BAR, s);
+    if (st) {
+        h->T.B = h->B0;
+        return st;
+    }
     HIP_TRY(launch_fill(h->dalpha, 0.f, h->edge_slots, s));
     HIP_TRY(launch_fill(h->domega, 0.f, h->edge_slots, s));
     HIP_TRY(launch_fill(h->dlamA, 0.f, h->edge_slots, s));
@@ -1059,7 +1134,28 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     HIP_TRY(launch_flush_adj(h->T.evar, h->S, h->alpha, h->dlamA, h->dalpha, h->g, h->edge_slots, s));
     HIP_TRY(launch_adj_deferred(h->var_ptr, h->var_slots, h->g, h->dMA, (int)h->n, s));
     float *dl = h->dlamA, *dm = h->dMA, *dl2 = h->dlamB, *dm2 = h->dMB;
-    for (int seg = nseg - 1; seg >= 0; --seg) {
+    if (stored) {
+        // every pass from its stored output state and node costs: no recomputation, no replay
+        for (int t = T - 1; t >= 0 && st == DD_OK; --t) {
+            h->T.F = h->trF[t];
+            h->T.B = h->trB[t + 1];  // the backward pass of iteration t
+            if ((st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s)) ||
+                (st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1])))
+                break;
+            std::swap(dl, dl2);
+            std::swap(dm, dm2);
+            h->T.B = h->trB[t];  // its forward pass
+            if ((st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)) ||
+                (st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t])))
+                break;
+            std::swap(dl, dl2);
+            std::swap(dm, dm2);
+        }
+        h->T.F = h->F0;
+        h->T.B = h->B0;
+        if (st) return st;
+    }
+    for (int seg = stored ? -1 : nseg - 1; seg >= 0; --seg) {
         const int t0 = seg * K, t1 = std::min(T, t0 + K), np = 2 * (t1 - t0);
         if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)seg, s))) return st;
         // a forward pass reads B at its input multipliers: the backward pass before it left
@@ -1088,9 +1184,14 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     if (d_M0) HIP_TRY(launch_gather(h->canon2slot, dm, d_M0, h->E, nullptr, s));
     if (d_omega) HIP_TRY(launch_gather(h->canon2slot, h->domega, d_omega, h->E, nullptr, s));
     if (d_alpha) HIP_TRY(launch_gather(h->canon2slot, h->dalpha, d_alpha, h->E, nullptr, s));
-    // leave the solver at the final state of the recorded forward
-    if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;
-    if ((st = recompute_B(h, s))) return st;
+    // leave the solver at the final state of the recorded forward (a stored trajectory left the
+    // final B in B0, which the backward sweep did not touch)
+    if (stored) {
+        if ((st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)T, s))) return st;
+    } else {
+        if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;
+        if ((st = recompute_B(h, s))) return st;
+    }
     h->fwd_version = h->version;
     return DD_OK;
 }
