@@ -253,11 +253,11 @@ def round_leg(stream, reps=3):
     inst.run(5)  # an earlier round
     lam, M = inst.get_state()
 
-    def one_round():
+    def one_round(k=K):
         inst.set_state(lam, M)
         for x in raw:
             x.grad = None
-        (-dual_round(inst, *raw, T, K)).backward()
+        (-dual_round(inst, *raw, T, k)).backward()
 
     def plain():
         inst.set_state(lam, M)
@@ -265,9 +265,12 @@ def round_leg(stream, reps=3):
         inst.lower_bound()
 
     one_round()
+    one_round(-1)
     plain()
     out = {"workload": p.name, "T": T, "ckpt_every": K}
-    for name, fn in (("round_fwd_bwd_ms", one_round), ("plain_fwd_ms", plain)):
+    # checkpoints every K as in the configuration, and the whole trajectory kept (ckpt_every = -1)
+    for name, fn in (("round_fwd_bwd_ms", one_round), ("round_stored_fwd_bwd_ms", lambda: one_round(-1)),
+                     ("plain_fwd_ms", plain)):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record(stream)
@@ -277,8 +280,10 @@ def round_leg(stream, reps=3):
         torch.cuda.synchronize()
         out[name] = e0.elapsed_time(e1) / reps
     out["ratio"] = out["round_fwd_bwd_ms"] / out["plain_fwd_ms"]
+    out["ratio_stored"] = out["round_stored_fwd_bwd_ms"] / out["plain_fwd_ms"]
     log(f"[bench] GM round (T={T}, K={K}): fwd+bwd {out['round_fwd_bwd_ms']:.2f} ms, plain forward "
-        f"{out['plain_fwd_ms']:.2f} ms, ratio {out['ratio']:.2f}")
+        f"{out['plain_fwd_ms']:.2f} ms, ratio {out['ratio']:.2f}; stored trajectory "
+        f"{out['round_stored_fwd_bwd_ms']:.2f} ms, ratio {out['ratio_stored']:.2f}")
     inst.close()
     return out
 
