@@ -420,14 +420,18 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
 
 // dS_i = sum over the edges of variable i of g (= dlambda' alpha), then dM_in[slot] = dS_i
 // (first line of Alg. 2, with alpha_ik per the derivative of the lambda update).
+// TS lanes per variable, summed as S is in the forward direction (strided partial sums, then a fixed
+// butterfly), the total written to every edge of the variable.
+template <int TS>
 __global__ void k_adj_deferred(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_slots,
                                const float *__restrict__ g, float *__restrict__ dM, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a = var_ptr[i], b = var_ptr[i + 1];
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / TS), u = (int)(t % TS);
+    const int a = i < n ? var_ptr[i] : 0, b = i < n ? var_ptr[i + 1] : 0;
     float s = 0.f;
-    for (int q = a; q < b; ++q) s += g[var_slots[q]];
-    for (int q = a; q < b; ++q) dM[var_slots[q]] = s;
+    for (int q = a + u; q < b; q += TS) s += g[var_slots[q]];
+    for (int w = TS / 2; w > 0; w >>= 1) s += __shfl_xor(s, w, TS);  // every lane takes part
+    for (int q = a + u; q < b; q += TS) dM[var_slots[q]] = s;
 }
 
 __global__ void k_edge_S(const int32_t *__restrict__ evar, const float *__restrict__ S, float *__restrict__ Se,
@@ -604,9 +608,17 @@ hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch 
 }
 
 hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots, const float *g, float *dM, int n,
-                               hipStream_t s) {
+                               int team, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_adj_deferred, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_slots, g, dM, n);
+    const unsigned nb = blocks_for((int64_t)n * team, 256);
+    switch (team) {
+        case 1: hipLaunchKernelGGL(k_adj_deferred<1>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
+        case 2: hipLaunchKernelGGL(k_adj_deferred<2>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
+        case 4: hipLaunchKernelGGL(k_adj_deferred<4>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
+        case 8: hipLaunchKernelGGL(k_adj_deferred<8>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
+        case 16: hipLaunchKernelGGL(k_adj_deferred<16>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -433,7 +433,7 @@ int deferred(dd_instance *h, hipStream_t s) { return deferred_from(h, h->T.M, s)
 
 int deferred_from(dd_instance *h, const float *M, hipStream_t s) {
     int st = recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 12.0 * (double)h->n, s, [&] {
-        return launch_deferred_sum(h->var_ptr, h->var_slots, M, h->S, (int)h->n, s);
+        return launch_deferred_sum(h->var_ptr, h->var_slots, M, h->S, (int)h->n, h->var_team, s);
     });
     if (st) return st;
     return recorded(h, "k_edge_alpha_s", 16.0 * (double)h->edge_slots, s, [&] {
@@ -617,6 +617,9 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     TRY(upload(h, (int32_t **)&T.slot2canon, hp.slot2canon, s));
     TRY(upload(h, &h->canon2slot, hp.canon2slot, s));
     TRY(upload(h, &h->var_ptr, hp.var_ptr, s));
+    // lanes per variable in the per-variable sums: one constant, so that a program gets the same bits
+    // alone and packed into a batch with programs of other degrees
+    h->var_team = dd_instance::kVarTeam;
     TRY(upload(h, &h->var_slots, hp.var_slots, s));
     TRY(upload(h, &h->var_canon, hp.var_canon, s));
     TRY(upload(h, &h->cdev, c32, s));
@@ -947,7 +950,7 @@ int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out
         if ((st = adj_classes(h, A, ADJ_F_FIXED, 0, 1, 0.f, s))) return st;
     }
     return recorded(h, "k_adj_deferred", 12.0 * (double)h->E + 8.0 * (double)h->n, s, [&] {
-        return launch_adj_deferred(h->var_ptr, h->var_slots, h->g, dM_in, (int)h->n, s);
+        return launch_adj_deferred(h->var_ptr, h->var_slots, h->g, dM_in, (int)h->n, h->var_team, s);
     });
 }
 
@@ -1132,7 +1135,7 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     }
     // lambda_bar = lambda + alpha S(M): dlambda = dlambda_bar, d_alpha += dlambda_bar S, dM = dS
     HIP_TRY(launch_flush_adj(h->T.evar, h->S, h->alpha, h->dlamA, h->dalpha, h->g, h->edge_slots, s));
-    HIP_TRY(launch_adj_deferred(h->var_ptr, h->var_slots, h->g, h->dMA, (int)h->n, s));
+    HIP_TRY(launch_adj_deferred(h->var_ptr, h->var_slots, h->g, h->dMA, (int)h->n, h->var_team, s));
     float *dl = h->dlamA, *dm = h->dMA, *dl2 = h->dlamB, *dm2 = h->dMB;
     if (stored) {
         // every pass from its stored output state and node costs: no recomputation, no replay

@@ -31,6 +31,8 @@ struct dd_instance {
     int max_width = 0, max_len = 0, uncovered = 0;
     double unc_const = 0.0;
     int ckpt_default = 5;
+    int var_team = 1;  // lanes per variable in the per-variable sums (deferred S and its adjoint)
+    static constexpr int kVarTeam = 4;
     int lds_budget = 64 * 1024;  // max LDS bytes per workgroup
     std::vector<ClassLaunch> classes;
     int64_t ntiles = 0, node_slots = 0, edge_slots = 0, device_bytes = 0;

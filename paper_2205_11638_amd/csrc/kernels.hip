@@ -801,13 +801,20 @@ hipError_t bwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipS
 }
 
 
+// S_i = sum of M over the edges of variable i.  TS lanes per variable (a power of two, fixed for an
+// instance): lane u adds edges u, u + TS, ... of the variable in CSR order, then a fixed butterfly
+// adds the TS partial sums, so S has the same bits on every call (TS = 1: one serial sum).  Teams
+// keep the chain of dependent loads short for variables in many rows.
+template <int TS>
 __global__ void k_deferred_sum(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_slots,
                                const float *__restrict__ M, float *__restrict__ S, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / TS), u = (int)(t % TS);
     float s = 0.f;
-    for (int q = var_ptr[i]; q < var_ptr[i + 1]; ++q) s += M[var_slots[q]];
-    S[i] = s;
+    if (i < n)
+        for (int q = var_ptr[i] + u; q < var_ptr[i + 1]; q += TS) s += M[var_slots[q]];
+    for (int w = TS / 2; w > 0; w >>= 1) s += __shfl_xor(s, w, TS);  // every lane takes part
+    if (i < n && u == 0) S[i] = s;
 }
 
 // aS[slot] = alpha[slot] * S[var(slot)] over all edge slots (padding slots have var -1).
@@ -989,9 +996,17 @@ hipError_t launch_bwd(const DevTables &t, const ClassLaunch &c, int mode, hipStr
 }
 
 hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots, const float *M, float *S, int n,
-                               hipStream_t s) {
+                               int team, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_deferred_sum, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_slots, M, S, n);
+    const unsigned nb = blocks_for((int64_t)n * team, 256);
+    switch (team) {
+        case 1: hipLaunchKernelGGL(k_deferred_sum<1>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, M, S, n); break;
+        case 2: hipLaunchKernelGGL(k_deferred_sum<2>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, M, S, n); break;
+        case 4: hipLaunchKernelGGL(k_deferred_sum<4>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, M, S, n); break;
+        case 8: hipLaunchKernelGGL(k_deferred_sum<8>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, M, S, n); break;
+        case 16: hipLaunchKernelGGL(k_deferred_sum<16>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, M, S, n); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

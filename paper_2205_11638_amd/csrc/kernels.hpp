@@ -119,7 +119,7 @@ hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch 
 // Se[slot] = S[evar[slot]] (0 on padding)
 hipError_t launch_edge_S(const int32_t *evar, const float *S, float *Se, int64_t slots, hipStream_t s);
 hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots, const float *g, float *dM, int n,
-                               hipStream_t s);
+                               int team, hipStream_t s);
 hipError_t launch_flush_adj(const int32_t *evar, const float *S, const float *alpha, const float *dlam, float *dalpha,
                             float *g, int64_t slots, hipStream_t s);
 hipError_t launch_dc(const int32_t *var_ptr, const int32_t *var_slots, const float *dlam, const float *c, float seed,
@@ -146,9 +146,10 @@ hipError_t launch_seg_sum(const float *x, const int64_t *seg, int k, int neg_par
 hipError_t launch_bwd(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s);
 bool class_supported(int P, int RMAX);
 
-// S_i = sum over the CSR list of edge slots of variable i of M[slot], in list order.
+// S_i = sum over the CSR list of edge slots of variable i of M[slot]: `team` lanes per variable (1, 2,
+// 4, 8 or 16), strided partial sums in list order, then a fixed butterfly (same bits on every call).
 hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots, const float *M, float *S, int n,
-                               hipStream_t s);
+                               int team, hipStream_t s);
 // aS[slot] = alpha[slot] * S[evar[slot]] for every edge slot (0 on padding).
 hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, int64_t slots,
                                hipStream_t s);
