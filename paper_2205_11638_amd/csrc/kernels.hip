@@ -22,6 +22,60 @@ namespace {
 
 using namespace dev;
 
+// Helpers of the kernels below: dispatch on a uniform count into bodies unrolled for exactly that
+// count, and range-checked buffer resources (an access past a resource's size loads 0 without
+// touching memory, or is dropped), so prefetches and stores can be issued unconditionally.
+template <int N>
+struct Count {
+    static constexpr int value = N;
+};
+
+template <int LO, int HI, typename Fn>
+__device__ __forceinline__ void with_count(int n, Fn &&fn) {
+    if constexpr (LO == HI) {
+        fn(Count<LO>{});
+    } else {
+        constexpr int MID = (LO + HI) / 2;
+        if (n <= MID) with_count<LO, MID>(n, fn);
+        else with_count<MID + 1, HI>(n, fn);
+    }
+}
+
+// gfx9-family buffer resource word 3: 32-bit data format, raw (byte) addressing, range checked
+constexpr int kBufWord3 = 0x00020000;
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ rsrc_t buf(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, kBufWord3);
+}
+__device__ __forceinline__ u32x4 ld4(rsrc_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0); }
+__device__ __forceinline__ f32x4 ld4f(rsrc_t r, int off) { return __builtin_bit_cast(f32x4, ld4(r, off)); }
+__device__ __forceinline__ void st4(rsrc_t r, int off, f32x4 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+}
+__device__ __forceinline__ uint32_t ld1(rsrc_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0); }
+__device__ __forceinline__ float ld1f(rsrc_t r, int off) { return __uint_as_float(ld1(r, off)); }
+__device__ __forceinline__ void st1(rsrc_t r, int off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
+}
+__device__ __forceinline__ f32x4 &lds4(float *base, int byte_off) { return *(f32x4 *)((char *)base + byte_off); }
+
+// 16 * lane, made anew in each hop body: an offset shared by the bodies (or loop invariant)
+// would be computed once per group ahead of them and held in one register per group, instead
+// of folding the group into the instruction's offset field
+__device__ __forceinline__ int lane16(int lane) {
+    int v = lane * 16;
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
+
+// bytes of a level's node rows (loads) and of its nodes rounded up to whole lane chunks (stores)
+__device__ __forceinline__ int row_bytes(const Lev &c) { return c.R * 256; }
+__device__ __forceinline__ int node_bytes(const Lev &c) { return ((c.W + 3) & ~3) * 4; }
+__device__ __forceinline__ int groups(const Lev &c) { return (c.R + 3) >> 2; }
+
 // LOOP = false: one wave per tile.  LOOP = true (update passes on a resident grid): each wave
 // takes tiles w, w + stride, ... (stride = waves in the grid); tiles are sorted by decreasing
 // length within a class, so striding mixes long and short ones.
@@ -91,14 +145,18 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
                 if (r < c1.R) Fb[x] = kInf;
             }
             wave_sync();
-            // prefetch (issued after this hop's stores): topology of l+1, B of l+2, edge data of l+1
+            // prefetch (issued after this hop's stores): topology of l+1, B of l+2, edge data of l+1.
+            // Rows past a level load 0 without a memory access, and the last hop reloads its own
+            // edge data: no branch, so no prefetched register is merged with its old value (a merge
+            // would wait for the load right after issuing it).
+            {
+                const rsrc_t tr = buf(T.topo + c1.base, c1.R * 256), br = buf(T.B + c2.base, c2.R * 256);
     #pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                tpn[r] = r < c1.R ? T.topo[c1.base + r * 64 + lane] : 0u;
-                bvn[r] = (UPD && r < c2.R) ? T.B[c2.base + r * 64 + lane] : 0.f;
-            }
-            if (l + 1 < nlev) {
-                const int e = tc.ebase + (l + 1) * G + g;
+                for (int r = 0; r < RMAX; ++r) {
+                    tpn[r] = ld1(tr, (r * 64 + lane) * 4);
+                    if (UPD) bvn[r] = ld1f(br, (r * 64 + lane) * 4);
+                }
+                const int e = tc.ebase + min(l + 1, nlev - 1) * G + g;
                 lamn = T.lam[e];
                 aSn = T.aS[e];
                 if (UPD) omn = T.omega[e];
@@ -121,17 +179,15 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
             if (UPD) {
                 m0 = team_min<P>(m0);
                 m1 = team_min<P>(m1);
-                lam_new = lam;
-                if (c0.W > 0) {
-                    m1 += lam;
-                    const float Mn = om * (m1 - m0);
-                    lam_new = lam - Mn + aS;
-                    if (p == 0) {
-                        const int e = tc.ebase + l * G + g;
-                        T.lam[e] = lam_new;
-                        T.M[e] = Mn;
-                    }
-                }
+                m1 += lam;
+                const float Mn = om * (m1 - m0);
+                const bool live = c0.W > 0;  // this team's diagram has a node at level l
+                lam_new = live ? lam - Mn + aS : lam;
+                // stored by the team's first lane through a resource over the tile's edges: the
+                // offsets of the other lanes, and of teams with no node here, fall outside it
+                const int ne = nlev * G * 4, off = p == 0 && live ? (l * G + g) * 4 : ne;
+                st1(buf(T.lam + tc.ebase, ne), off, lam_new);
+                st1(buf(T.M + tc.ebase, ne), off, Mn);
             } else {
                 lam_new = MODE == FWD_SWEEP_BAR ? lam + aS : lam;  // sweep, no update
             }
@@ -225,14 +281,16 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                 for (int r = 0; r < RMAX; ++r)
                     if (r < cn.R && in_level<P>(r, cn.R, lane, cn.W)) bg[r * 64 + lane] = bn[mine + r * P * G];
             }
-            // prefetch level l-1
+            // prefetch level l-1 (unconditional, as in the forward pass; the first level reloads its own
+            // edge data)
+            {
+                const rsrc_t tr = buf(T.topo + cp.base, cp.R * 256), fr = buf(T.F + cp.base, cp.R * 256);
     #pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                tpn[r] = r < cp.R ? T.topo[cp.base + r * 64 + lane] : 0u;
-                fn[r] = (NEEDF && r < cp.R) ? T.F[cp.base + r * 64 + lane] : 0.f;
-            }
-            if (l > 0) {
-                const int e = tc.ebase + (l - 1) * G + g;
+                for (int r = 0; r < RMAX; ++r) {
+                    tpn[r] = ld1(tr, (r * 64 + lane) * 4);
+                    if (NEEDF) fn[r] = ld1f(fr, (r * 64 + lane) * 4);
+                }
+                const int e = tc.ebase + max(l - 1, 0) * G + g;
                 lamn = T.lam[e];
                 if (UPD || BAR) aSn = T.aS[e];
                 if (UPD) omn = T.omega[e];
@@ -257,21 +315,19 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
             if (NEEDF) {
                 m0 = team_min<P>(m0);
                 m1 = team_min<P>(m1);
-                if (c0.W > 0) {
-                    m1 += lam_use;
-                    if (UPD) {
-                        const float Mn = om * (m1 - m0);
-                        lam_new = lam - Mn + aS;
-                        if (p == 0) {
-                            const int e = tc.ebase + l * G + g;
-                            T.lam[e] = lam_new;
-                            T.M[e] = Mn;
-                        }
-                    } else if (p == 0) {
-                        const int ce = T.slot2canon[tc.ebase + l * G + g];
-                        T.out0[ce] = m0;
-                        T.out1[ce] = m1;
-                    }
+                m1 += lam_use;
+                const bool live = c0.W > 0;  // this team's diagram has a node at level l
+                if (UPD) {
+                    const float Mn = om * (m1 - m0);
+                    lam_new = live ? lam - Mn + aS : lam_new;
+                    // the team's first lane stores; other offsets fall outside the tile's edges
+                    const int ne = nlev * G * 4, off = p == 0 && live ? (l * G + g) * 4 : ne;
+                    st1(buf(T.lam + tc.ebase, ne), off, lam_new);
+                    st1(buf(T.M + tc.ebase, ne), off, Mn);
+                } else if (p == 0 && live) {
+                    const int ce = T.slot2canon[tc.ebase + l * G + g];
+                    T.out0[ce] = m0;
+                    T.out1[ce] = m1;
                 }
             }
     #pragma unroll
@@ -333,55 +389,6 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
 // the tile.  Every level of a built diagram holds at least one node, so the update needs no
 // empty-level case.  The arithmetic is that of the general kernels above; the min over a
 // level's arcs is exact, so the order in which a lane visits its nodes does not matter.
-template <int N>
-struct Count {
-    static constexpr int value = N;
-};
-
-template <int LO, int HI, typename Fn>
-__device__ __forceinline__ void with_count(int n, Fn &&fn) {
-    if constexpr (LO == HI) {
-        fn(Count<LO>{});
-    } else {
-        constexpr int MID = (LO + HI) / 2;
-        if (n <= MID) with_count<LO, MID>(n, fn);
-        else with_count<MID + 1, HI>(n, fn);
-    }
-}
-
-// gfx9-family buffer resource word 3: 32-bit data format, raw (byte) addressing, range checked
-constexpr int kBufWord3 = 0x00020000;
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ rsrc_t buf(const void *base, int bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, kBufWord3);
-}
-__device__ __forceinline__ u32x4 ld4(rsrc_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0); }
-__device__ __forceinline__ f32x4 ld4f(rsrc_t r, int off) { return __builtin_bit_cast(f32x4, ld4(r, off)); }
-__device__ __forceinline__ void st4(rsrc_t r, int off, f32x4 v) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
-}
-__device__ __forceinline__ void st1(rsrc_t r, int off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
-}
-__device__ __forceinline__ f32x4 &lds4(float *base, int byte_off) { return *(f32x4 *)((char *)base + byte_off); }
-
-// 16 * lane, made anew in each hop body: an offset shared by the bodies (or loop invariant)
-// would be computed once per group ahead of them and held in one register per group, instead
-// of folding the group into the instruction's offset field
-__device__ __forceinline__ int lane16(int lane) {
-    int v = lane * 16;
-    __asm__ volatile("" : "+v"(v));
-    return v;
-}
-
-// bytes of a level's node rows (loads) and of its nodes rounded up to whole lane chunks (stores)
-__device__ __forceinline__ int row_bytes(const Lev &c) { return c.R * 256; }
-__device__ __forceinline__ int node_bytes(const Lev &c) { return ((c.W + 3) & ~3) * 4; }
-__device__ __forceinline__ int groups(const Lev &c) { return (c.R + 3) >> 2; }
-
 template <int Q, int RMAX, int MODE, typename Prefetch>
 __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, float *Fb, const float *Bst,
                                           const u32x4 (&tp)[RMAX / 4], int lane, int out, const Lev &c0,
