@@ -132,6 +132,31 @@ def test_dual_round_autograd(orc):
     close_grad(-host(Th.grad), dth, "d_theta_hat")
 
 
+def test_dual_round_stored_trajectory_matches_checkpoints():
+    """A round with the whole trajectory kept (ckpt_every = -1) gives the bound and the gradients of the
+    three raw predictions of checkpoints every iteration, bit for bit."""
+    import torch
+
+    from paper_2205_11638_amd.autograd import dual_round
+    p = synth.workload("gm", small=True)["problem"]
+    inst, _, _ = make_instance(p)
+    wh, ah, th = raw(p, 11)
+    inst.set_params(*inst.param_transform(dev(wh), dev(ah))[:2])
+    inst.run(2)
+    lam, M = inst.get_state()
+    lam, M = lam.clone(), M.clone()
+    out = []
+    for K in (1, -1):
+        inst.set_state(lam, M)
+        W, A, Th = (torch.tensor(np.asarray(x, np.float32), device="cuda", requires_grad=True) for x in (wh, ah, th))
+        lb = dual_round(inst, W, A, Th, 4, K)
+        (-lb).backward()
+        out.append((lb.item(), host(W.grad), host(A.grad), host(Th.grad)))
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1:], out[1][1:]):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_d_c_needs_a_reset_start():
     import paper_2205_11638_amd as dd
     p = synth.workload("setcover")["problem"]
