@@ -418,6 +418,314 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Pull-form sweep of one-wave diagrams (P = 64), laid out like the wide pass kernels: a lane
+// owns nodes k = 256 q + 4 lane + j of level l (the node indices of the general sweep, so the
+// argmin keys and the records are the same), rows move with one 16-byte access per lane through
+// level-sized buffer resources, every prefetch is issued unconditionally, and each hop branches
+// once on its group count.
+// The adjoint of B lives on minimizing paths only: a node hands its whole adjoint to one child,
+// and the update sweep adds two per level, so a level holds a handful of nonzero adjoints
+// whatever its width.  A hop therefore first lists them (children and adjoint of each nonzero
+// node, in wave order, written over the level's own adjoint buffer once it has been read) and
+// routes the list with one lane per entry, instead of a routing step for every node.  A level
+// whose nonzero adjoints overflow the list is routed node by node by the owning lanes.  The
+// argmin nodes of the two min-marginals come out of the same pass over the nodes as the minima:
+// each lane visits its nodes in increasing index and keeps the first one that attains its
+// running minimum.  Float sums (LDS adds, the hi-arc sum) may be added in another order than in
+// the general sweep; the mins and the argmin tests are exact.
+// ------------------------------------------------------------------------------------------
+template <bool UPD>
+struct AdjIn;
+template <>
+struct AdjIn<true> {  // multipliers after and before the replayed pass, output adjoints, omega, alpha, S, sums
+    float lam, lam_in, dlo, dMo, om, al, S, da, dw;
+};
+template <>
+struct AdjIn<false> {  // multiplier of the fixed side, alpha*S and dlambda_in so far
+    float lam_src, aS, dl;
+};
+
+template <bool UPD>
+__device__ __forceinline__ AdjIn<UPD> adj_in(const DevTables &T, const AdjTables &A, int e) {
+    AdjIn<UPD> x;
+    if constexpr (UPD) {
+        x.lam = T.lam[e];
+        x.lam_in = A.lam_in[e];
+        x.dlo = A.dlam_out[e];
+        x.dMo = A.dM_out[e];
+        x.om = T.omega[e];
+        x.al = T.alpha[e];
+        x.S = A.Se[e];
+        x.da = A.dalpha[e];
+        x.dw = A.domega[e];
+    } else {
+        x.lam_src = A.lam_src[e];
+        x.aS = T.aS[e];
+        x.dl = A.dlam_in[e];
+    }
+    return x;
+}
+
+// Outputs of a hop, stored by lane 0 through resources over the tile's edges: hop l stores at
+// o4 + 4 l (o8 + 8 l for the two-word records), past the resource for every other lane.
+struct AdjOut {
+    rsrc_t dlam_in, g, dalpha, domega, rec_idx, rec_val;
+    int o4, o8;
+};
+
+template <bool UPD>
+__device__ __forceinline__ AdjOut adj_out(const AdjTables &A, const TileCtx &tc, int nlev, int lane) {
+    AdjOut o{};
+    o.dlam_in = buf(A.dlam_in + tc.ebase, nlev * 4);
+    if constexpr (UPD) {
+        o.g = buf(A.g + tc.ebase, nlev * 4);
+        o.dalpha = buf(A.dalpha + tc.ebase, nlev * 4);
+        o.domega = buf(A.domega + tc.ebase, nlev * 4);
+        o.rec_idx = buf(A.rec_idx + 2 * (int64_t)tc.ebase, nlev * 8);
+        o.rec_val = buf(A.rec_val + 2 * (int64_t)tc.ebase, nlev * 8);
+    }
+    o.o4 = lane * nlev * 4;
+    o.o8 = lane * nlev * 8;
+    return o;
+}
+
+__device__ __forceinline__ void st2(rsrc_t r, int off, uint32_t a, uint32_t b) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = {a, b};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
+
+// lanes below this one whose bit is set in a wave mask
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <int Q, int RMAX, bool UPD>
+__device__ __forceinline__ void adjB_hop_w(const float *Bst, float *ba0, float *ba1, const u32x4 (&tp)[RMAX / 4],
+                                           const f32x4 (&fvi)[RMAX / 4], int lane, const Lev &c0, int Wn,
+                                           float lam_use, const AdjIn<UPD> &x, const AdjOut &o, int l) {
+    constexpr int CAP = node_buf_w(RMAX) / 2;  // list entries that fit in a node buffer
+    const int l16 = lane16(lane);
+    u32x4 t[Q];
+    f32x4 d[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        t[q] = tp[q];
+        d[q] = lds4(ba0, l16 + q * 1024);  // slots past the level's width hold 0
+    }
+    // last group: this lane's slots past the level's width get two 0-terminal arcs
+    const int rem = c0.W - (Q - 1) * 256 - lane * 4;
+    const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j >= rem) t[Q - 1][j] = dead;
+    // the level's nonzero adjoints: children at [0, CAP) and adjoint at [CAP, 2 CAP) of ba0
+    uint32_t *lt = (uint32_t *)ba0;
+    float *lv = ba0 + CAP;
+    int n = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const bool nz = d[q][j] != 0.f;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
+            const int pos = n + lanes_below(m);
+            if (nz && pos < CAP) {
+                lt[pos] = t[q][j];
+                lv[pos] = d[q][j];
+            }
+            n += (int)__builtin_popcountll(m);
+        }
+    wave_sync();
+    float hisum = 0.f;
+    auto route = [&](uint32_t tt, float dv) {
+        const int lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
+        const float b0 = Bst[lo], b1 = lam_use + Bst[hi];
+        const bool take_hi = b1 < b0;  // the pass formed min(b0, b1): lo on ties
+        const int ch = take_hi ? hi : lo;
+        if (ch < Wn) lds_fadd(&ba1[ch], dv);
+        if (take_hi) hisum += dv;
+    };
+    if (n <= CAP) {
+        for (int c = 0; c < n; c += 64)
+            if (c + lane < n) route(lt[c + lane], lv[c + lane]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (d[q][j] != 0.f) route(t[q][j], d[q][j]);
+    }
+    hisum = team_sum<64>(hisum);
+    if constexpr (UPD) {
+        f32x4 f[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) f[q] = fvi[q];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (j >= rem) f[Q - 1][j] = kInf;
+        // min-marginals again (same expressions as the pass) with the first node attaining each
+        float m0 = kInf, m1 = kInf;
+        int k0 = INT_MAX, k1 = INT_MAX, ch0 = 0, ch1 = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = q * 256 + (l16 >> 2) + j;
+                const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
+                const float v0 = f[q][j] + Bst[lo], v1 = f[q][j] + Bst[hi];
+                if (v0 < m0 || (v0 == m0 && k0 == INT_MAX)) {
+                    m0 = v0;
+                    k0 = k;
+                    ch0 = lo;
+                }
+                if (v1 < m1 || (v1 == m1 && k1 == INT_MAX)) {
+                    m1 = v1;
+                    k1 = k;
+                    ch1 = hi;
+                }
+            }
+        const float M0 = team_min<64>(m0), M1 = team_min<64>(m1);
+        const int K0 = team_min_i<64>(m0 == M0 ? k0 : INT_MAX);  // lowest argmin node of each
+        const int K1 = team_min_i<64>(m1 == M1 ? k1 : INT_MAX);
+        const float dlam_new = x.dlo + hisum;
+        const float dM = x.dMo - dlam_new;
+        const float diff = (M1 + x.lam_in) - M0;  // m^1 - m^0 as the pass formed it
+        const float dm1 = x.om * dM, dm0 = -dm1;
+        if (k0 == K0 && ch0 < Wn) lds_fadd(&ba1[ch0], dm0);
+        if (k1 == K1 && ch1 < Wn) lds_fadd(&ba1[ch1], dm1);
+        st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
+        st1(o.g, o.o4 + 4 * l, dlam_new * x.al);
+        st1(o.dalpha, o.o4 + 4 * l, x.da + dlam_new * x.S);
+        st1(o.domega, o.o4 + 4 * l, x.dw + dM * diff);
+        st2(o.rec_idx, o.o8 + 8 * l, (uint32_t)K0, (uint32_t)K1);  // argmin nodes of level l: F_l side
+        st2(o.rec_val, o.o8 + 8 * l, __float_as_uint(dm0), __float_as_uint(dm1));
+    } else {
+        st1(o.dlam_in, o.o4 + 4 * l, x.dl + hisum);
+    }
+}
+
+template <int RMAX, bool UPD>
+__global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int NL,
+                                                 int bar, int recs, float seed) {
+    constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;  // uniform per wave
+    float *Bst = lds_f + (size_t)wave * lds_words_adj_B_w(RMAX, NL);
+    float *Ba = Bst + NB;
+    int *meta = (int *)(Ba + 2 * NB);
+    int *off = meta + NL;
+    const TileCtx tc = tile_ctx(T, tile);
+    preload_meta<1>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l < nlev) {
+            v.W = uni(meta[l] & 0xFFFF);
+            v.R = uni(meta[l] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
+    };
+    const AdjOut o = adj_out<UPD>(A, tc, nlev, lane);
+    // records of the update sweep (fixed sweeps with recs): a resource of no size otherwise
+    const bool use_rec = !UPD && recs;
+    const rsrc_t ri = buf(use_rec ? (const void *)(A.rec_idx + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
+                          use_rec ? nlev * 8 : 0);
+    const rsrc_t rv = buf(use_rec ? (const void *)(A.rec_val + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
+                          use_rec ? nlev * 8 : 0);
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    int cur = 0;  // Ba + cur * NB: adjoints of level l
+    {
+        const int l16 = lane16(lane);
+#pragma unroll
+        for (int q = 0; q < QM; ++q) lds4(Ba, l16 + q * 1024) = zero4;
+        if (lane == 0) Ba[0] = seed;  // the root is node 0 of level 0
+    }
+    Lev c0 = level(0), c1 = level(1);
+    u32x4 tpn[QM];
+    f32x4 fvn[QM], bvn[QM];
+    {
+        const int l16 = lane16(lane);
+        const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), fr = buf(T.F + c0.base, row_bytes(c0));
+        const rsrc_t br = buf(T.B + c1.base, row_bytes(c1));
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            tpn[q] = ld4(tr, l16 + q * 1024);
+            fvn[q] = UPD ? ld4f(fr, l16 + q * 1024) : zero4;
+            bvn[q] = ld4f(br, l16 + q * 1024);
+        }
+    }
+    AdjIn<UPD> xn = adj_in<UPD>(T, A, tc.ebase);
+    int pi0 = -1, pi1 = -1;  // record of the previous hop's edge (children at this level, or -1)
+    float pv0 = 0.f, pv1 = 0.f;
+    for (int l = 0; l < nlev; ++l) {
+        const int Wn = c1.W;
+        const AdjIn<UPD> x = xn;
+        float *ba0 = Ba + cur * NB, *ba1 = Ba + (cur ^ 1) * NB;
+        // fixed side: argmin contributions of the update sweep to B_l (record of edge l-1)
+        if (use_rec && l > 0 && lane == 0) {
+            if (pi0 >= 0) ba0[pi0] += pv0;
+            if (pi1 >= 0) ba0[pi1] += pv1;
+        }
+        u32x4 tp[QM];
+        f32x4 fv[QM];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            tp[q] = tpn[q];
+            fv[q] = fvn[q];
+        }
+        {
+            // B of level l+1 with its terminals; the adjoints of level l+1 start at 0
+            const int l16 = lane16(lane);
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                lds4(Bst, l16 + q * 1024) = bvn[q];
+                lds4(ba1, l16 + q * 1024) = zero4;
+            }
+        }
+        if (lane == 0) {
+            Bst[Wn] = kInf;
+            Bst[Wn + 1] = 0.f;
+        }
+        // prefetch hop l+1: topology and F of level l+1, B of level l+2, edge data of level l+1
+        // (the last hop reloads its own), the record of edge l
+        const Lev c2 = level(l + 2);
+        {
+            const int l16 = lane16(lane);
+            const rsrc_t tr = buf(T.topo + c1.base, row_bytes(c1)), fr = buf(T.F + c1.base, row_bytes(c1));
+            const rsrc_t br = buf(T.B + c2.base, row_bytes(c2));
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                tpn[q] = ld4(tr, l16 + q * 1024);
+                if (UPD) fvn[q] = ld4f(fr, l16 + q * 1024);
+                bvn[q] = ld4f(br, l16 + q * 1024);
+            }
+            xn = adj_in<UPD>(T, A, tc.ebase + min(l + 1, nlev - 1));
+            if (!UPD) {
+                pi0 = (int)ld1(ri, 8 * l);
+                pi1 = (int)ld1(ri, 8 * l + 4);
+                pv0 = ld1f(rv, 8 * l);
+                pv1 = ld1f(rv, 8 * l + 4);
+            }
+        }
+        wave_sync();
+        float lam_use;
+        if constexpr (UPD) lam_use = x.lam;
+        else lam_use = bar ? x.lam_src + x.aS : x.lam_src;
+        with_count<1, QM>(groups(c0), [&](auto qc) {
+            adjB_hop_w<decltype(qc)::value, RMAX, UPD>(Bst, ba0, ba1, tp, fv, lane, c0, Wn, lam_use, x, o, l);
+        });
+        wave_sync();
+        cur ^= 1;
+        c0 = c1;
+        c1 = c2;
+    }
+}
+
 // dS_i = sum over the edges of variable i of g (= dlambda' alpha), then dM_in[slot] = dS_i
 // (first line of Alg. 2, with alpha_ik per the derivative of the lambda update).
 // TS lanes per variable, summed as S is in the forward direction (strided partial sums, then a fixed
@@ -582,6 +890,15 @@ hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunc
             hipLaunchKernelGGL((k_adj_F<P, RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.WB, c.NL);
         else
             hipLaunchKernelGGL((k_adj_F<P, RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.WB, c.NL);
+    } else if constexpr (P == 64) {
+        dim3 grid((unsigned)((c.ntiles + c.wpb_ab - 1) / c.wpb_ab)), block(64 * c.wpb_ab);
+        const size_t lds = (size_t)c.wpb_ab * lds_words_adj_B_w(RMAX, c.NL) * 4;
+        if (which == ADJ_B_UPDATE)
+            hipLaunchKernelGGL((k_adj_B_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, bar, recs,
+                               seed);
+        else
+            hipLaunchKernelGGL((k_adj_B_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, bar, recs,
+                               seed);
     } else {
         dim3 grid((unsigned)((c.ntiles + c.wpb_ab - 1) / c.wpb_ab)), block(64 * c.wpb_ab);
         const size_t lds = (size_t)c.wpb_ab * lds_words_adj_B(P, c.WB, c.NL) * 4;

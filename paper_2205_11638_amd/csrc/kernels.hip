@@ -22,60 +22,6 @@ namespace {
 
 using namespace dev;
 
-// Helpers of the kernels below: dispatch on a uniform count into bodies unrolled for exactly that
-// count, and range-checked buffer resources (an access past a resource's size loads 0 without
-// touching memory, or is dropped), so prefetches and stores can be issued unconditionally.
-template <int N>
-struct Count {
-    static constexpr int value = N;
-};
-
-template <int LO, int HI, typename Fn>
-__device__ __forceinline__ void with_count(int n, Fn &&fn) {
-    if constexpr (LO == HI) {
-        fn(Count<LO>{});
-    } else {
-        constexpr int MID = (LO + HI) / 2;
-        if (n <= MID) with_count<LO, MID>(n, fn);
-        else with_count<MID + 1, HI>(n, fn);
-    }
-}
-
-// gfx9-family buffer resource word 3: 32-bit data format, raw (byte) addressing, range checked
-constexpr int kBufWord3 = 0x00020000;
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ rsrc_t buf(const void *base, int bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, kBufWord3);
-}
-__device__ __forceinline__ u32x4 ld4(rsrc_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0); }
-__device__ __forceinline__ f32x4 ld4f(rsrc_t r, int off) { return __builtin_bit_cast(f32x4, ld4(r, off)); }
-__device__ __forceinline__ void st4(rsrc_t r, int off, f32x4 v) {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
-}
-__device__ __forceinline__ uint32_t ld1(rsrc_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0); }
-__device__ __forceinline__ float ld1f(rsrc_t r, int off) { return __uint_as_float(ld1(r, off)); }
-__device__ __forceinline__ void st1(rsrc_t r, int off, float v) {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, off, 0, 0);
-}
-__device__ __forceinline__ f32x4 &lds4(float *base, int byte_off) { return *(f32x4 *)((char *)base + byte_off); }
-
-// 16 * lane, made anew in each hop body: an offset shared by the bodies (or loop invariant)
-// would be computed once per group ahead of them and held in one register per group, instead
-// of folding the group into the instruction's offset field
-__device__ __forceinline__ int lane16(int lane) {
-    int v = lane * 16;
-    __asm__ volatile("" : "+v"(v));
-    return v;
-}
-
-// bytes of a level's node rows (loads) and of its nodes rounded up to whole lane chunks (stores)
-__device__ __forceinline__ int row_bytes(const Lev &c) { return c.R * 256; }
-__device__ __forceinline__ int node_bytes(const Lev &c) { return ((c.W + 3) & ~3) * 4; }
-__device__ __forceinline__ int groups(const Lev &c) { return (c.R + 3) >> 2; }
-
 // LOOP = false: one wave per tile.  LOOP = true (update passes on a resident grid): each wave
 // takes tiles w, w + stride, ... (stride = waves in the grid); tiles are sorted by decreasing
 // length within a class, so striding mixes long and short ones.

@@ -95,6 +95,12 @@ constexpr int lds_words_pass_c(int P, int RMAX, int WB, int NL) {
 // pull form = staged B and the adjoints of two levels; both + the level table
 constexpr int lds_words_adj_F(int P, int WB, int NL) { return 4 * WB * (64 / P) + NL * ((64 / P) + 1); }
 constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) + NL * ((64 / P) + 1); }
+// one-wave diagrams (P = 64), pull form: staged B and the adjoints of two levels in node buffers
+// of RMAX rows + 64 slots, then the level table
+constexpr int lds_words_adj_B_w(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+constexpr int lds_words_adj_B_c(int P, int RMAX, int WB, int NL) {
+    return P == 64 ? lds_words_adj_B_w(RMAX, NL) : lds_words_adj_B(P, WB, NL);
+}
 
 // Arrays of the reverse sweeps (edge-slot indexed unless noted).
 struct AdjTables {
