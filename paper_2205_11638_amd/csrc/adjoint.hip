@@ -726,6 +726,315 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
     }
 }
 
+// ------------------------------------------------------------------------------------------
+// Push-form sweep of one-wave diagrams (P = 64), levels l = L-1 .. 0, in the wide layout.  The
+// adjoint of F also lives on minimizing paths only (a node hands its adjoint to its argmin
+// parent arc), but a node's parents are known only to the level above, so every arc of level l
+// still looks up its child's adjoint; the few arcs into a nonzero one are listed (key 2k + beta,
+// child, arc value, child adjoint) and bid for their child with one lane per entry, and the
+// winners add into the level's adjoint buffer.  Overflowing lists are bid and collected by the
+// owning lanes.  F and its adjoint share one buffer per level: level l overwrites level l+1
+// once every value of level l+1 that the hop needs has been read.
+// LDS per wave: Fv, Fa (cost and adjoint), bid (ints), Bst (B of level l+1, update sweeps),
+// the list, then the level table.
+// ------------------------------------------------------------------------------------------
+template <bool UPD>
+struct AdjInF;
+template <>
+struct AdjInF<true> {
+    AdjIn<true> a;
+};
+template <>
+struct AdjInF<false> {  // fixed side: the multiplier swept, dlambda_in so far, the update sweep's record
+    float lam_src, dl;
+    int i0, i1;
+    float v0, v1;
+};
+
+template <int Q, int RMAX, bool UPD>
+__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, const float *Bst, uint32_t *lkw,
+                                           float *lval, float *lfa, const u32x4 (&tp)[RMAX / 4],
+                                           const f32x4 (&fvi)[RMAX / 4], int lane, const Lev &c0, int Wn,
+                                           float lam_use, const AdjInF<UPD> &x, const AdjOut &o, int l) {
+    constexpr int CAP = kAdjListW;
+    const int l16 = lane16(lane);
+    u32x4 t[Q];
+    f32x4 f[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        t[q] = tp[q];
+        f[q] = fvi[q];
+    }
+    const int rem = c0.W - (Q - 1) * 256 - lane * 4;
+    const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        if (j >= rem) {
+            t[Q - 1][j] = dead;
+            f[Q - 1][j] = kInf;
+        }
+    // arcs into a child with a nonzero adjoint (terminal slots of Fa hold 0)
+    int n = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int beta = 0; beta < 2; ++beta) {
+                const int w = beta ? (int)(t[q][j] >> 16) : (int)(t[q][j] & 0xFFFFu);
+                const float a = Fa[w];
+                const bool nz = a != 0.f;
+                const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
+                const int pos = n + lanes_below(m);
+                if (nz && pos < CAP) {
+                    const int key = 2 * (q * 256 + (l16 >> 2) + j) + beta;
+                    lkw[pos] = (uint32_t)key | ((uint32_t)w << 16);
+                    lval[pos] = beta ? f[q][j] + lam_use : f[q][j];
+                    lfa[pos] = a;
+                }
+                n += (int)__builtin_popcountll(m);
+            }
+    wave_sync();
+    float hisum = 0.f;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    if (n <= CAP) {
+        // bids of the listed arcs whose value equals the child's cost
+        const bool mine = lane < n;
+        const uint32_t kw = mine ? lkw[lane] : 0u;
+        const float v = mine ? lval[lane] : 0.f, a = mine ? lfa[lane] : 0.f;
+        const int key = (int)(kw & 0xFFFFu), w = (int)(kw >> 16);
+        const bool tight = mine && v == Fv[w];
+        if (tight) lds_imin(&bid[w], key);
+        wave_sync();
+        // level l replaces level l+1 (everything read from it is in registers now)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            lds4(Fv, l16 + q * 1024) = f[q];
+            lds4(Fa, l16 + q * 1024) = zero4;
+        }
+        const bool won = tight && bid[w] == key;
+        if (tight) bid[w] = INT_MAX;
+        if (won) {
+            lds_fadd(&Fa[key >> 1], a);
+            if (key & 1) hisum = a;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = q * 256 + (l16 >> 2) + j, lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
+                if (Fa[lo] != 0.f && f[q][j] == Fv[lo]) lds_imin(&bid[lo], 2 * k);
+                if (Fa[hi] != 0.f && f[q][j] + lam_use == Fv[hi]) lds_imin(&bid[hi], 2 * k + 1);
+            }
+        wave_sync();
+        f32x4 acc[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = q * 256 + (l16 >> 2) + j, lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
+                acc[q][j] = 0.f;
+                const float alo = Fa[lo], ahi = Fa[hi];
+                if (alo != 0.f && bid[lo] == 2 * k) acc[q][j] += alo;
+                if (ahi != 0.f && bid[hi] == 2 * k + 1) {
+                    acc[q][j] += ahi;
+                    hisum += ahi;
+                }
+            }
+        wave_sync();  // every bid and every value of level l+1 is read
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            lds4(Fv, l16 + q * 1024) = f[q];
+            lds4(Fa, l16 + q * 1024) = acc[q];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                bid[(int)(t[q][j] & 0xFFFFu)] = INT_MAX;
+                bid[(int)(t[q][j] >> 16)] = INT_MAX;
+            }
+        }
+    }
+    hisum = team_sum<64>(hisum);
+    if constexpr (UPD) {
+        // min-marginals again (same expressions as the pass) with the first node attaining each
+        float m0 = kInf, m1 = kInf;
+        int k0 = INT_MAX, k1 = INT_MAX, ch0 = 0, ch1 = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int k = q * 256 + (l16 >> 2) + j;
+                const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
+                const float v0 = f[q][j] + Bst[lo], v1 = f[q][j] + Bst[hi];
+                if (v0 < m0 || (v0 == m0 && k0 == INT_MAX)) {
+                    m0 = v0;
+                    k0 = k;
+                    ch0 = lo;
+                }
+                if (v1 < m1 || (v1 == m1 && k1 == INT_MAX)) {
+                    m1 = v1;
+                    k1 = k;
+                    ch1 = hi;
+                }
+            }
+        const float M0 = team_min<64>(m0), M1 = team_min<64>(m1);
+        const int K0 = team_min_i<64>(m0 == M0 ? k0 : INT_MAX);
+        const int K1 = team_min_i<64>(m1 == M1 ? k1 : INT_MAX);
+        const AdjIn<true> &y = x.a;
+        const float dlam_new = y.dlo + hisum;
+        const float dM = y.dMo - dlam_new;
+        const float diff = (M1 + y.lam_in) - M0;  // m^1 - m^0 as the pass formed it
+        const float dm1 = y.om * dM, dm0 = -dm1;
+        if (k0 == K0) lds_fadd(&Fa[K0], dm0);
+        if (k1 == K1) lds_fadd(&Fa[K1], dm1);
+        const int r0 = __builtin_amdgcn_readlane(k0 == K0 ? ch0 : 0, __builtin_ctzll(__builtin_amdgcn_ballot_w64(k0 == K0)));
+        const int r1 = __builtin_amdgcn_readlane(k1 == K1 ? ch1 : 0, __builtin_ctzll(__builtin_amdgcn_ballot_w64(k1 == K1)));
+        st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
+        st1(o.g, o.o4 + 4 * l, dlam_new * y.al);
+        st1(o.dalpha, o.o4 + 4 * l, y.da + dlam_new * y.S);
+        st1(o.domega, o.o4 + 4 * l, y.dw + dM * diff);
+        // children of the argmin nodes: B_{l+1} side contributions (-1 for a terminal)
+        st2(o.rec_idx, o.o8 + 8 * l, (uint32_t)(r0 < Wn ? r0 : -1), (uint32_t)(r1 < Wn ? r1 : -1));
+        st2(o.rec_val, o.o8 + 8 * l, __float_as_uint(dm0), __float_as_uint(dm1));
+    } else {
+        // argmin contributions of the update sweep to F_l (record of edge l)
+        if (lane == 0) {
+            if (x.i0 >= 0 && x.i0 < c0.W) Fa[x.i0] += x.v0;
+            if (x.i1 >= 0 && x.i1 < c0.W) Fa[x.i1] += x.v1;
+        }
+        st1(o.dlam_in, o.o4 + 4 * l, x.dl + hisum);
+    }
+}
+
+template <int RMAX, bool UPD>
+__global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int NL,
+                                                 int recs) {
+    constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;  // uniform per wave
+    float *Fv = lds_f + (size_t)wave * lds_words_adj_F_w(RMAX, NL);
+    float *Fa = Fv + NB;
+    int *bid = (int *)(Fa + NB);
+    float *Bst = (float *)(bid + NB);
+    uint32_t *lkw = (uint32_t *)(Bst + NB);
+    float *lval = (float *)(lkw + kAdjListW), *lfa = lval + kAdjListW;
+    int *meta = (int *)(lfa + kAdjListW);
+    int *off = meta + NL;
+    const TileCtx tc = tile_ctx(T, tile);
+    preload_meta<1>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l >= 0 && l < nlev) {
+            v.W = uni(meta[l] & 0xFFFF);
+            v.R = uni(meta[l] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
+    };
+    const AdjOut o = adj_out<UPD>(A, tc, nlev, lane);
+    const bool use_rec = !UPD && recs;
+    const rsrc_t ri = buf(use_rec ? (const void *)(A.rec_idx + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
+                          use_rec ? nlev * 8 : 0);
+    const rsrc_t rv = buf(use_rec ? (const void *)(A.rec_val + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
+                          use_rec ? nlev * 8 : 0);
+    auto edge = [&](int l) {
+        AdjInF<UPD> x;
+        const int e = tc.ebase + l;
+        if constexpr (UPD) {
+            x.a = adj_in<true>(T, A, e);
+        } else {
+            x.lam_src = A.lam_src[e];
+            x.dl = A.dlam_in[e];
+            x.i0 = (int)ld1(ri, 8 * l);  // no record: 0 bytes loaded, and use_rec is checked at use
+            x.i1 = (int)ld1(ri, 8 * l + 4);
+            x.v0 = ld1f(rv, 8 * l);
+            x.v1 = ld1f(rv, 8 * l + 4);
+        }
+        return x;
+    };
+    {
+        // level L: terminals only, no adjoint; no bids
+        const int l16 = lane16(lane);
+        const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+        typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+        const i32x4 none = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+#pragma unroll
+        for (int q = 0; q <= QM; ++q) {
+            if (q < QM || lane < 16) {
+                lds4(Fa, l16 + q * 1024) = zero4;
+                *(i32x4 *)((char *)bid + l16 + q * 1024) = none;
+            }
+        }
+    }
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    Lev c0 = level(nlev - 1), c1{0, 0, 0};
+    u32x4 tpn[QM];
+    f32x4 fvn[QM], bvn[QM];
+    {
+        const int l16 = lane16(lane);
+        const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), fr = buf(T.F + c0.base, row_bytes(c0));
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            tpn[q] = ld4(tr, l16 + q * 1024);
+            fvn[q] = ld4f(fr, l16 + q * 1024);
+            bvn[q] = zero4;  // B of level L: only its terminals are read
+        }
+    }
+    AdjInF<UPD> xn = edge(nlev - 1);
+    for (int l = nlev - 1; l >= 0; --l) {
+        const int Wn = c1.W;
+        const AdjInF<UPD> x = xn;
+        u32x4 tp[QM];
+        f32x4 fv[QM];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            tp[q] = tpn[q];
+            fv[q] = fvn[q];
+        }
+        if (UPD) {
+            const int l16 = lane16(lane);
+#pragma unroll
+            for (int q = 0; q < QM; ++q) lds4(Bst, l16 + q * 1024) = bvn[q];  // B of level l+1
+            if (lane == 0) {
+                Bst[Wn] = kInf;
+                Bst[Wn + 1] = 0.f;
+            }
+        }
+        // prefetch hop l-1: topology and F of level l-1, B of level l, edge data of level l-1
+        // (the last hop reloads its own)
+        const Lev cp = level(l - 1);
+        {
+            const int l16 = lane16(lane);
+            const rsrc_t tr = buf(T.topo + cp.base, row_bytes(cp)), fr = buf(T.F + cp.base, row_bytes(cp));
+            const rsrc_t br = buf(T.B + c0.base, row_bytes(c0));
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                tpn[q] = ld4(tr, l16 + q * 1024);
+                fvn[q] = ld4f(fr, l16 + q * 1024);
+                if (UPD) bvn[q] = ld4f(br, l16 + q * 1024);
+            }
+            xn = edge(max(l - 1, 0));
+        }
+        wave_sync();
+        float lam_use;
+        if constexpr (UPD) lam_use = x.a.lam;
+        else lam_use = x.lam_src;
+        AdjInF<UPD> xu = x;
+        if constexpr (!UPD)
+            if (!use_rec) xu.i0 = xu.i1 = -1;
+        with_count<1, QM>(groups(c0), [&](auto qc) {
+            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, bid, Bst, lkw, lval, lfa, tp, fv, lane, c0, Wn,
+                                                       lam_use, xu, o, l);
+        });
+        wave_sync();
+        c1 = c0;
+        c0 = cp;
+    }
+}
+
 // dS_i = sum over the edges of variable i of g (= dlambda' alpha), then dM_in[slot] = dS_i
 // (first line of Alg. 2, with alpha_ik per the derivative of the lambda update).
 // TS lanes per variable, summed as S is in the forward direction (strided partial sums, then a fixed
@@ -883,7 +1192,14 @@ hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunc
                         float seed, hipStream_t s) {
     if (c.wpb_af < 1 || c.wpb_af > kMaxWavesPerBlock || c.wpb_ab < 1 || c.wpb_ab > kMaxWavesPerBlock)
         return hipErrorInvalidConfiguration;
-    if (which == ADJ_F_UPDATE || which == ADJ_F_FIXED) {
+    if ((which == ADJ_F_UPDATE || which == ADJ_F_FIXED) && P == 64) {
+        dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
+        const size_t lds = (size_t)c.wpb_af * lds_words_adj_F_w(RMAX, c.NL) * 4;
+        if (which == ADJ_F_UPDATE)
+            hipLaunchKernelGGL((k_adj_F_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs);
+        else
+            hipLaunchKernelGGL((k_adj_F_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs);
+    } else if (which == ADJ_F_UPDATE || which == ADJ_F_FIXED) {
         dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
         const size_t lds = (size_t)c.wpb_af * lds_words_adj_F(P, c.WB, c.NL) * 4;
         if (which == ADJ_F_UPDATE)

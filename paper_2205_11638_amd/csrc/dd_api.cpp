@@ -273,11 +273,11 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
         };
         cl.wpb_f = pick(lds_words_pass_c(P, RMAX, cl.WB, cl.NL));
         cl.wpb_b = pick(lds_words_pass_c(P, RMAX, cl.WB, cl.NL));
-        cl.wpb_af = pick(lds_words_adj_F(P, cl.WB, cl.NL));
+        cl.wpb_af = pick(lds_words_adj_F_c(P, RMAX, cl.WB, cl.NL));
         cl.wpb_ab = pick(lds_words_adj_B_c(P, RMAX, cl.WB, cl.NL));
         if (!cl.wpb_f || !cl.wpb_b || !cl.wpb_af || !cl.wpb_ab)
             return fail(DD_E_UNSUPPORTED, "LDS need %lld bytes per wave exceeds the budget",
-                        (long long)lds_words_adj_F(P, cl.WB, cl.NL) * 4);
+                        (long long)lds_words_adj_F_c(P, RMAX, cl.WB, cl.NL) * 4);
         hp.classes.push_back(cl);
         i = j;
     }
@@ -421,7 +421,7 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
         [&](const ClassLaunch &cl) {
             // the kernel and template arguments as the profiler prints them
             char name[96];
-            if (cl.P == 64 && (which == ADJ_B_UPDATE || which == ADJ_B_FIXED))
+            if (cl.P == 64)
                 snprintf(name, sizeof name, "%s_w<%d, %s>", nm, cl.RMAX, upd ? "true" : "false");
             else
                 snprintf(name, sizeof name, "%s<%d, %d, %s>", nm, cl.P, cl.RMAX, upd ? "true" : "false");

@@ -98,6 +98,15 @@ constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) 
 // one-wave diagrams (P = 64), pull form: staged B and the adjoints of two levels in node buffers
 // of RMAX rows + 64 slots, then the level table
 constexpr int lds_words_adj_B_w(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+// one-wave diagrams, push form: cost, adjoint, bids and staged B of a level, the list of arcs
+// into nonzero adjoints (key and child, arc value, child adjoint), then the level table
+constexpr int kAdjListW = 64;
+constexpr int lds_words_adj_F_w(int RMAX, int NL) {
+    return 4 * node_buf_w(RMAX) + 3 * kAdjListW + ((2 * NL + 3) & ~3);
+}
+constexpr int lds_words_adj_F_c(int P, int RMAX, int WB, int NL) {
+    return P == 64 ? lds_words_adj_F_w(RMAX, NL) : lds_words_adj_F(P, WB, NL);
+}
 constexpr int lds_words_adj_B_c(int P, int RMAX, int WB, int NL) {
     return P == 64 ? lds_words_adj_B_w(RMAX, NL) : lds_words_adj_B(P, WB, NL);
 }
