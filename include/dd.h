@@ -79,7 +79,10 @@ typedef struct {
     int32_t ckpt_every;     /* iterations between adjoint checkpoints, default 5 */
     int32_t lds_budget;     /* max LDS bytes per workgroup, default 64 KiB */
     int32_t no_graphs;      /* nonzero: dd_run launches every kernel itself instead of replaying graphs */
-    int32_t reserved[3];
+    int32_t adj_route_dense;/* nonzero: the reverse sweeps of one-wave diagrams route every level node by
+                               node instead of through their per-level lists of nonzero adjoints (the
+                               path taken by levels whose lists overflow); for checking that path */
+    int32_t reserved[2];
 } dd_options;
 
 typedef struct {

@@ -490,6 +490,8 @@ __device__ __forceinline__ AdjOut adj_out(const AdjTables &A, const TileCtx &tc,
     return o;
 }
 
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ void st2(rsrc_t r, int off, uint32_t a, uint32_t b) {
     typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     const u32x2 v = {a, b};
@@ -504,7 +506,7 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 template <int Q, int RMAX, bool UPD>
 __device__ __forceinline__ void adjB_hop_w(const float *Bst, float *ba0, float *ba1, const u32x4 (&tp)[RMAX / 4],
                                            const f32x4 (&fvi)[RMAX / 4], int lane, const Lev &c0, int Wn,
-                                           float lam_use, const AdjIn<UPD> &x, const AdjOut &o, int l) {
+                                           float lam_use, const AdjIn<UPD> &x, const AdjOut &o, int l, int cap) {
     constexpr int CAP = node_buf_w(RMAX) / 2;  // list entries that fit in a node buffer
     const int l16 = lane16(lane);
     u32x4 t[Q];
@@ -520,6 +522,7 @@ __device__ __forceinline__ void adjB_hop_w(const float *Bst, float *ba0, float *
 #pragma unroll
     for (int j = 0; j < 4; ++j)
         if (j >= rem) t[Q - 1][j] = dead;
+    wave_sync();  // every lane has read ba0: the list overwrites it
     // the level's nonzero adjoints: children at [0, CAP) and adjoint at [CAP, 2 CAP) of ba0
     uint32_t *lt = (uint32_t *)ba0;
     float *lv = ba0 + CAP;
@@ -547,7 +550,7 @@ __device__ __forceinline__ void adjB_hop_w(const float *Bst, float *ba0, float *
         if (ch < Wn) lds_fadd(&ba1[ch], dv);
         if (take_hi) hisum += dv;
     };
-    if (n <= CAP) {
+    if (n <= min(cap, CAP)) {
         for (int c = 0; c < n; c += 64)
             if (c + lane < n) route(lt[c + lane], lv[c + lane]);
     } else {
@@ -593,6 +596,7 @@ __device__ __forceinline__ void adjB_hop_w(const float *Bst, float *ba0, float *
         const float dM = x.dMo - dlam_new;
         const float diff = (M1 + x.lam_in) - M0;  // m^1 - m^0 as the pass formed it
         const float dm1 = x.om * dM, dm0 = -dm1;
+        wave_sync();  // after the routed adjoints (a fixed order of the float adds)
         if (k0 == K0 && ch0 < Wn) lds_fadd(&ba1[ch0], dm0);
         if (k1 == K1 && ch1 < Wn) lds_fadd(&ba1[ch1], dm1);
         st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
@@ -608,7 +612,7 @@ __device__ __forceinline__ void adjB_hop_w(const float *Bst, float *ba0, float *
 
 template <int RMAX, bool UPD>
 __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int NL,
-                                                 int bar, int recs, float seed) {
+                                                 int bar, int recs, float seed, int cap) {
     constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
     extern __shared__ float lds_f[];
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -687,6 +691,7 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
                 lds4(ba1, l16 + q * 1024) = zero4;
             }
         }
+        wave_sync();  // the terminals' slots may have been staged by another lane
         if (lane == 0) {
             Bst[Wn] = kInf;
             Bst[Wn + 1] = 0.f;
@@ -717,7 +722,7 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
         if constexpr (UPD) lam_use = x.lam;
         else lam_use = bar ? x.lam_src + x.aS : x.lam_src;
         with_count<1, QM>(groups(c0), [&](auto qc) {
-            adjB_hop_w<decltype(qc)::value, RMAX, UPD>(Bst, ba0, ba1, tp, fv, lane, c0, Wn, lam_use, x, o, l);
+            adjB_hop_w<decltype(qc)::value, RMAX, UPD>(Bst, ba0, ba1, tp, fv, lane, c0, Wn, lam_use, x, o, l, cap);
         });
         wave_sync();
         cur ^= 1;
@@ -731,12 +736,13 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
 // adjoint of F also lives on minimizing paths only (a node hands its adjoint to its argmin
 // parent arc), but a node's parents are known only to the level above, so every arc of level l
 // still looks up its child's adjoint; the few arcs into a nonzero one are listed (key 2k + beta,
-// child, arc value, child adjoint) and bid for their child with one lane per entry, and the
-// winners add into the level's adjoint buffer.  Overflowing lists are bid and collected by the
-// owning lanes.  F and its adjoint share one buffer per level: level l overwrites level l+1
-// once every value of level l+1 that the hop needs has been read.
-// LDS per wave: Fv, Fa (cost and adjoint), bid (ints), Bst (B of level l+1, update sweeps),
-// the list, then the level table.
+// child, arc value, child adjoint) and bid for their child with one lane per entry, in the
+// child's adjoint slot (its value is in the list by then), and the winners add into the level's
+// adjoint.  A list that overflows is bid and collected by the owning lanes instead.  F and its
+// adjoint have one buffer each: level l overwrites level l+1 once every value of level l+1 that
+// the hop needs has been read.  The update sweep forms the min-marginals first, which frees the
+// staged B for the overflow case's bids.
+// LDS per wave: Fv, Fa (cost and adjoint), Bst (B of level l+1), the list, the level table.
 // ------------------------------------------------------------------------------------------
 template <bool UPD>
 struct AdjInF;
@@ -752,10 +758,10 @@ struct AdjInF<false> {  // fixed side: the multiplier swept, dlambda_in so far, 
 };
 
 template <int Q, int RMAX, bool UPD>
-__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, const float *Bst, uint32_t *lkw,
-                                           float *lval, float *lfa, const u32x4 (&tp)[RMAX / 4],
-                                           const f32x4 (&fvi)[RMAX / 4], int lane, const Lev &c0, int Wn,
-                                           float lam_use, const AdjInF<UPD> &x, const AdjOut &o, int l) {
+__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *Bst, uint32_t *lkw, float *lval, float *lfa,
+                                           const u32x4 (&tp)[RMAX / 4], const f32x4 (&fvi)[RMAX / 4], int lane,
+                                           const Lev &c0, int Wn, float lam_use, const AdjInF<UPD> &x,
+                                           const AdjOut &o, int l, int cap) {
     constexpr int CAP = kAdjListW;
     const int l16 = lane16(lane);
     u32x4 t[Q];
@@ -773,90 +779,12 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, const
             t[Q - 1][j] = dead;
             f[Q - 1][j] = kInf;
         }
-    // arcs into a child with a nonzero adjoint (terminal slots of Fa hold 0)
-    int n = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int beta = 0; beta < 2; ++beta) {
-                const int w = beta ? (int)(t[q][j] >> 16) : (int)(t[q][j] & 0xFFFFu);
-                const float a = Fa[w];
-                const bool nz = a != 0.f;
-                const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
-                const int pos = n + lanes_below(m);
-                if (nz && pos < CAP) {
-                    const int key = 2 * (q * 256 + (l16 >> 2) + j) + beta;
-                    lkw[pos] = (uint32_t)key | ((uint32_t)w << 16);
-                    lval[pos] = beta ? f[q][j] + lam_use : f[q][j];
-                    lfa[pos] = a;
-                }
-                n += (int)__builtin_popcountll(m);
-            }
-    wave_sync();
-    float hisum = 0.f;
-    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
-    if (n <= CAP) {
-        // bids of the listed arcs whose value equals the child's cost
-        const bool mine = lane < n;
-        const uint32_t kw = mine ? lkw[lane] : 0u;
-        const float v = mine ? lval[lane] : 0.f, a = mine ? lfa[lane] : 0.f;
-        const int key = (int)(kw & 0xFFFFu), w = (int)(kw >> 16);
-        const bool tight = mine && v == Fv[w];
-        if (tight) lds_imin(&bid[w], key);
-        wave_sync();
-        // level l replaces level l+1 (everything read from it is in registers now)
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            lds4(Fv, l16 + q * 1024) = f[q];
-            lds4(Fa, l16 + q * 1024) = zero4;
-        }
-        const bool won = tight && bid[w] == key;
-        if (tight) bid[w] = INT_MAX;
-        if (won) {
-            lds_fadd(&Fa[key >> 1], a);
-            if (key & 1) hisum = a;
-        }
-    } else {
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = q * 256 + (l16 >> 2) + j, lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
-                if (Fa[lo] != 0.f && f[q][j] == Fv[lo]) lds_imin(&bid[lo], 2 * k);
-                if (Fa[hi] != 0.f && f[q][j] + lam_use == Fv[hi]) lds_imin(&bid[hi], 2 * k + 1);
-            }
-        wave_sync();
-        f32x4 acc[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = q * 256 + (l16 >> 2) + j, lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
-                acc[q][j] = 0.f;
-                const float alo = Fa[lo], ahi = Fa[hi];
-                if (alo != 0.f && bid[lo] == 2 * k) acc[q][j] += alo;
-                if (ahi != 0.f && bid[hi] == 2 * k + 1) {
-                    acc[q][j] += ahi;
-                    hisum += ahi;
-                }
-            }
-        wave_sync();  // every bid and every value of level l+1 is read
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            lds4(Fv, l16 + q * 1024) = f[q];
-            lds4(Fa, l16 + q * 1024) = acc[q];
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                bid[(int)(t[q][j] & 0xFFFFu)] = INT_MAX;
-                bid[(int)(t[q][j] >> 16)] = INT_MAX;
-            }
-        }
-    }
-    hisum = team_sum<64>(hisum);
+    // update sweeps: min-marginals again (same expressions as the pass) with the first node
+    // attaining each; the staged B is free afterwards
+    float M0 = 0.f, M1 = 0.f;
+    int K0 = 0, K1 = 0, r0 = 0, r1 = 0;
+    bool own0 = false, own1 = false;
     if constexpr (UPD) {
-        // min-marginals again (same expressions as the pass) with the first node attaining each
         float m0 = kInf, m1 = kInf;
         int k0 = INT_MAX, k1 = INT_MAX, ch0 = 0, ch1 = 0;
 #pragma unroll
@@ -864,8 +792,11 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, const
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int k = q * 256 + (l16 >> 2) + j;
-                const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
-                const float v0 = f[q][j] + Bst[lo], v1 = f[q][j] + Bst[hi];
+                uint32_t tt = t[q][j];
+                float ff = f[q][j];
+                if (j == 0) __asm__ volatile("" : "+v"(tt), "+v"(ff));  // loads stay with their group
+                const int lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
+                const float v0 = ff + Bst[lo], v1 = ff + Bst[hi];
                 if (v0 < m0 || (v0 == m0 && k0 == INT_MAX)) {
                     m0 = v0;
                     k0 = k;
@@ -877,18 +808,137 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, const
                     ch1 = hi;
                 }
             }
-        const float M0 = team_min<64>(m0), M1 = team_min<64>(m1);
-        const int K0 = team_min_i<64>(m0 == M0 ? k0 : INT_MAX);
-        const int K1 = team_min_i<64>(m1 == M1 ? k1 : INT_MAX);
+        M0 = team_min<64>(m0);
+        M1 = team_min<64>(m1);
+        K0 = team_min_i<64>(m0 == M0 ? k0 : INT_MAX);
+        K1 = team_min_i<64>(m1 == M1 ? k1 : INT_MAX);
+        own0 = k0 == K0;
+        own1 = k1 == K1;
+        // children of the argmin nodes (one lane owns each)
+        r0 = __builtin_amdgcn_readlane(ch0, __builtin_ctzll(__builtin_amdgcn_ballot_w64(own0)));
+        r1 = __builtin_amdgcn_readlane(ch1, __builtin_ctzll(__builtin_amdgcn_ballot_w64(own1)));
+    }
+    // arcs into a child with a nonzero adjoint (terminal slots of Fa hold 0), in wave order;
+    // the first CAP go to the list; returns the number of such arcs
+    // (the node values are taken afresh, so nothing derived from them is computed ahead and
+    // held in registers)
+    auto detect = [&]() {
+        int n = 0;
+        const int k4 = lane16(lane) >> 2;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                uint32_t tt = t[q][j];
+                float ff = f[q][j];
+                __asm__ volatile("" : "+v"(tt), "+v"(ff));
+#pragma unroll
+                for (int beta = 0; beta < 2; ++beta) {
+                    const int w = beta ? (int)(tt >> 16) : (int)(tt & 0xFFFFu);
+                    const float a = Fa[w];
+                    const bool nz = a != 0.f;
+                    const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
+                    const int pos = n + lanes_below(m);
+                    if (nz && pos < CAP) {
+                        const int key = 2 * (q * 256 + k4 + j) + beta;
+                        lkw[pos] = (uint32_t)key | ((uint32_t)w << 16);
+                        lval[pos] = beta ? ff + lam_use : ff;
+                        lfa[pos] = a;
+                    }
+                    n += (int)__builtin_popcountll(m);
+                }
+            }
+        return n;
+    };
+    const int n = detect();
+    wave_sync();
+    float hisum = 0.f;
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    int *Fai = (int *)Fa;
+    if (n <= min(cap, CAP)) {
+        // the listed arcs whose value equals the child's cost bid for it, in the child's own
+        // adjoint slot (its value is in the list now)
+        const bool mine = lane < n;
+        const uint32_t kw = mine ? lkw[lane] : 0u;
+        const float v = mine ? lval[lane] : 0.f, a = mine ? lfa[lane] : 0.f;
+        const int key = (int)(kw & 0xFFFFu), w = (int)(kw >> 16);
+        const bool tight = mine && v == Fv[w];
+        if (tight) Fai[w] = INT_MAX;
+        wave_sync();
+        if (tight) lds_imin(&Fai[w], key);
+        wave_sync();
+        const bool won = tight && Fai[w] == key;
+        wave_sync();  // a lane's node of level l may share a slot with another lane's child
+        // level l replaces level l+1 (everything read from it is in registers now)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            lds4(Fv, l16 + q * 1024) = f[q];
+            lds4(Fa, l16 + q * 1024) = zero4;
+        }
+        wave_sync();
+        if (won) {
+            lds_fadd(&Fa[key >> 1], a);
+            if (key & 1) hisum = a;
+        }
+    } else {
+        // more arcs than the list holds: every lane bids for its own arcs (bids in the staged-B
+        // buffer, free by now) and collects its nodes' adjoints
+        int *obid = (int *)Bst;
+        const i32x4 none = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
+#pragma unroll
+        for (int q = 0; q < RMAX / 4; ++q) *(i32x4 *)((char *)obid + l16 + q * 1024) = none;
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                uint32_t tt = t[q][j];
+                float ff = f[q][j];
+                __asm__ volatile("" : "+v"(tt), "+v"(ff));
+                const int k = q * 256 + (l16 >> 2) + j, lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
+                if (Fa[lo] != 0.f && ff == Fv[lo]) lds_imin(&obid[lo], 2 * k);
+                if (Fa[hi] != 0.f && ff + lam_use == Fv[hi]) lds_imin(&obid[hi], 2 * k + 1);
+            }
+        wave_sync();  // the bids are in: F of level l+1 is not read again, its buffer collects
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                uint32_t tt = t[q][j];
+                __asm__ volatile("" : "+v"(tt));
+                const int k = q * 256 + (l16 >> 2) + j, lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
+                const float alo = Fa[lo], ahi = Fa[hi];
+                float acc = 0.f;
+                if (alo != 0.f && obid[lo] == 2 * k) acc += alo;
+                if (ahi != 0.f && obid[hi] == 2 * k + 1) {
+                    acc += ahi;
+                    hisum += ahi;
+                }
+                Fv[k] = acc;
+            }
+        wave_sync();  // every adjoint of level l+1 is read
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            lds4(Fa, l16 + q * 1024) = lds4(Fv, l16 + q * 1024);
+            lds4(Fv, l16 + q * 1024) = f[q];
+        }
+    }
+    wave_sync();
+    // the terminals of level l (children codes W, W + 1 of the next hop) carry no adjoint
+    if (lane == 0) {
+        Fa[c0.W] = 0.f;
+        Fa[c0.W + 1] = 0.f;
+    }
+    hisum = team_sum<64>(hisum);
+    if constexpr (UPD) {
         const AdjIn<true> &y = x.a;
         const float dlam_new = y.dlo + hisum;
         const float dM = y.dMo - dlam_new;
         const float diff = (M1 + y.lam_in) - M0;  // m^1 - m^0 as the pass formed it
         const float dm1 = y.om * dM, dm0 = -dm1;
-        if (k0 == K0) lds_fadd(&Fa[K0], dm0);
-        if (k1 == K1) lds_fadd(&Fa[K1], dm1);
-        const int r0 = __builtin_amdgcn_readlane(k0 == K0 ? ch0 : 0, __builtin_ctzll(__builtin_amdgcn_ballot_w64(k0 == K0)));
-        const int r1 = __builtin_amdgcn_readlane(k1 == K1 ? ch1 : 0, __builtin_ctzll(__builtin_amdgcn_ballot_w64(k1 == K1)));
+        wave_sync();  // after the winners' adds (a fixed order of the float adds)
+        if (own0) lds_fadd(&Fa[K0], dm0);
+        if (own1) lds_fadd(&Fa[K1], dm1);
         st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
         st1(o.g, o.o4 + 4 * l, dlam_new * y.al);
         st1(o.dalpha, o.o4 + 4 * l, y.da + dlam_new * y.S);
@@ -908,7 +958,7 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, const
 
 template <int RMAX, bool UPD>
 __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int NL,
-                                                 int recs) {
+                                                 int recs, int cap) {
     constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
     extern __shared__ float lds_f[];
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -916,8 +966,7 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
     if (tile >= tile0 + ntiles) return;  // uniform per wave
     float *Fv = lds_f + (size_t)wave * lds_words_adj_F_w(RMAX, NL);
     float *Fa = Fv + NB;
-    int *bid = (int *)(Fa + NB);
-    float *Bst = (float *)(bid + NB);
+    float *Bst = Fa + NB;
     uint32_t *lkw = (uint32_t *)(Bst + NB);
     float *lval = (float *)(lkw + kAdjListW), *lfa = lval + kAdjListW;
     int *meta = (int *)(lfa + kAdjListW);
@@ -956,18 +1005,12 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         return x;
     };
     {
-        // level L: terminals only, no adjoint; no bids
+        // level L: terminals only, no adjoint
         const int l16 = lane16(lane);
         const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
-        typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-        const i32x4 none = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
 #pragma unroll
-        for (int q = 0; q <= QM; ++q) {
-            if (q < QM || lane < 16) {
-                lds4(Fa, l16 + q * 1024) = zero4;
-                *(i32x4 *)((char *)bid + l16 + q * 1024) = none;
-            }
-        }
+        for (int q = 0; q <= QM; ++q)
+            if (q < QM || lane < 16) lds4(Fa, l16 + q * 1024) = zero4;
     }
     const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
     Lev c0 = level(nlev - 1), c1{0, 0, 0};
@@ -998,6 +1041,7 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
             const int l16 = lane16(lane);
 #pragma unroll
             for (int q = 0; q < QM; ++q) lds4(Bst, l16 + q * 1024) = bvn[q];  // B of level l+1
+            wave_sync();  // the terminals' slots may have been staged by another lane
             if (lane == 0) {
                 Bst[Wn] = kInf;
                 Bst[Wn + 1] = 0.f;
@@ -1026,8 +1070,8 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         if constexpr (!UPD)
             if (!use_rec) xu.i0 = xu.i1 = -1;
         with_count<1, QM>(groups(c0), [&](auto qc) {
-            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, bid, Bst, lkw, lval, lfa, tp, fv, lane, c0, Wn,
-                                                       lam_use, xu, o, l);
+            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, Bst, lkw, lval, lfa, tp, fv, lane, c0, Wn, lam_use,
+                                                       xu, o, l, cap);
         });
         wave_sync();
         c1 = c0;
@@ -1189,16 +1233,19 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 
 template <int P, int RMAX>
 hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
-                        float seed, hipStream_t s) {
+                        float seed, int dense, hipStream_t s) {
+    const int cap = dense ? 0 : INT_MAX;  // list entries the one-wave sweeps may use
     if (c.wpb_af < 1 || c.wpb_af > kMaxWavesPerBlock || c.wpb_ab < 1 || c.wpb_ab > kMaxWavesPerBlock)
         return hipErrorInvalidConfiguration;
     if ((which == ADJ_F_UPDATE || which == ADJ_F_FIXED) && P == 64) {
         dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
         const size_t lds = (size_t)c.wpb_af * lds_words_adj_F_w(RMAX, c.NL) * 4;
         if (which == ADJ_F_UPDATE)
-            hipLaunchKernelGGL((k_adj_F_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs);
+            hipLaunchKernelGGL((k_adj_F_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs,
+                               cap);
         else
-            hipLaunchKernelGGL((k_adj_F_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs);
+            hipLaunchKernelGGL((k_adj_F_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs,
+                               cap);
     } else if (which == ADJ_F_UPDATE || which == ADJ_F_FIXED) {
         dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
         const size_t lds = (size_t)c.wpb_af * lds_words_adj_F(P, c.WB, c.NL) * 4;
@@ -1211,10 +1258,10 @@ hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunc
         const size_t lds = (size_t)c.wpb_ab * lds_words_adj_B_w(RMAX, c.NL) * 4;
         if (which == ADJ_B_UPDATE)
             hipLaunchKernelGGL((k_adj_B_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, bar, recs,
-                               seed);
+                               seed, cap);
         else
             hipLaunchKernelGGL((k_adj_B_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, bar, recs,
-                               seed);
+                               seed, cap);
     } else {
         dim3 grid((unsigned)((c.ntiles + c.wpb_ab - 1) / c.wpb_ab)), block(64 * c.wpb_ab);
         const size_t lds = (size_t)c.wpb_ab * lds_words_adj_B(P, c.WB, c.NL) * 4;
@@ -1231,10 +1278,10 @@ hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunc
 }  // namespace
 
 hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
-                      float seed, hipStream_t s) {
+                      float seed, int dense, hipStream_t s) {
     if (c.ntiles <= 0) return hipSuccess;
 #define DD_ADJ(PP, RR) \
-    if (c.P == PP && c.RMAX == RR) return adj_dispatch<PP, RR>(t, a, c, which, bar, recs, seed, s);
+    if (c.P == PP && c.RMAX == RR) return adj_dispatch<PP, RR>(t, a, c, which, bar, recs, seed, dense, s);
     DD_CLASSES(DD_ADJ)
 #undef DD_ADJ
     return hipErrorInvalidValue;

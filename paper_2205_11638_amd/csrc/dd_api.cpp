@@ -417,7 +417,7 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
     const bool upd = which == ADJ_F_UPDATE || which == ADJ_B_UPDATE;
     const char *nm = which == ADJ_F_UPDATE || which == ADJ_F_FIXED ? "k_adj_F" : "k_adj_B";
     return per_class(
-        h, s, [&](const ClassLaunch &cl, hipStream_t cs) { return launch_adj(h->T, A, cl, which, bar, recs, seed, cs); },
+        h, s, [&](const ClassLaunch &cl, hipStream_t cs) { return launch_adj(h->T, A, cl, which, bar, recs, seed, h->adj_dense, cs); },
         [&](const ClassLaunch &cl) {
             // the kernel and template arguments as the profiler prints them
             char name[96];
@@ -549,6 +549,7 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     h->device = device;
     if (o.ckpt_every > 0) h->ckpt_default = o.ckpt_every;
     h->use_graphs = o.no_graphs == 0;
+    h->adj_dense = o.adj_route_dense != 0;
     h->lds_budget = lds_budget;
     h->n = prob->n;
     h->m = m;

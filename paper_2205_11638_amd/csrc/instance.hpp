@@ -94,6 +94,7 @@ struct dd_instance {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_one = nullptr, graph_chunk = nullptr;
     bool use_graphs = true;
+    int adj_dense = 0;  // reverse sweeps of one-wave diagrams route node by node (check of that path)
 
     ~dd_instance() {
         if (graph_one) (void)hipGraphExecDestroy(graph_one);

@@ -98,11 +98,11 @@ constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) 
 // one-wave diagrams (P = 64), pull form: staged B and the adjoints of two levels in node buffers
 // of RMAX rows + 64 slots, then the level table
 constexpr int lds_words_adj_B_w(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
-// one-wave diagrams, push form: cost, adjoint, bids and staged B of a level, the list of arcs
-// into nonzero adjoints (key and child, arc value, child adjoint), then the level table
+// one-wave diagrams, push form: cost, adjoint and staged B of a level, the list of arcs into
+// nonzero adjoints (key and child, arc value, child adjoint), then the level table
 constexpr int kAdjListW = 64;
 constexpr int lds_words_adj_F_w(int RMAX, int NL) {
-    return 4 * node_buf_w(RMAX) + 3 * kAdjListW + ((2 * NL + 3) & ~3);
+    return 3 * node_buf_w(RMAX) + 3 * kAdjListW + ((2 * NL + 3) & ~3);
 }
 constexpr int lds_words_adj_F_c(int P, int RMAX, int WB, int NL) {
     return P == 64 ? lds_words_adj_F_w(RMAX, NL) : lds_words_adj_F(P, WB, NL);
@@ -129,8 +129,9 @@ enum AdjSweep { ADJ_F_UPDATE = 0, ADJ_F_FIXED = 1, ADJ_B_UPDATE = 2, ADJ_B_FIXED
 
 // One reverse sweep over the tiles of a class.  bar: fixed pull sweeps use lam_src + alpha*S;
 // recs: fixed sweeps add the records of the update sweep; seed: adjoint of B(root) (pull form).
+// dense != 0: one-wave sweeps route every level node by node (the path of overflowing lists).
 hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
-                      float seed, hipStream_t s);
+                      float seed, int dense, hipStream_t s);
 // Se[slot] = S[evar[slot]] (0 on padding)
 hipError_t launch_edge_S(const int32_t *evar, const float *S, float *Se, int64_t slots, hipStream_t s);
 hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots, const float *g, float *dM, int n,

@@ -200,6 +200,53 @@ def test_stored_trajectory_too_large_is_rejected():
     assert inst.lower_bound()[0] == lb  # nothing ran
 
 
+@pytest.mark.parametrize("case", ["knapsack-small", "team-sizes", "wide-24", "wide-32"])
+def test_dense_routing_matches_listed_routing(case):
+    """The reverse sweeps of one-wave diagrams route a level's nonzero adjoints through a per-level
+    list, and a level whose list would overflow node by node from the owning lanes; the option
+    adj_route_dense takes the second path on every level.  Both follow the same argmins, so pass
+    VJPs and unrolled gradients agree up to the order of float sums (a node reached from several
+    parents or children, the hi-arc sums): 1e-5 relative, norm-wise and entry-wise with a floor."""
+    import torch
+    p = CASES[case]()
+    rng = np.random.default_rng(5)
+    om = f32(synth.sigmoid(rng.normal(size=p.nnz)))
+    ah = f32(rng.normal(0, 0.3, size=p.nnz))
+    say(f"dense routing {case}")
+    a, _, _ = make_instance(p, om, ah)
+    b, _, _ = make_instance(p, om, ah, adj_route_dense=True)
+    assert any(s["P"] == 64 for s in a.launch_shapes())
+    dev = lambda x: torch.tensor(np.asarray(x, np.float32), device="cuda")
+
+    def close(x, y, what):
+        x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)
+        assert np.linalg.norm(x - y) <= 1e-5 * max(np.linalg.norm(y), 1e-6), (what, np.linalg.norm(x - y))
+        bad = np.abs(x - y) > np.maximum(1e-5 * np.abs(y), 1e-5 * max(np.abs(y).max(), 1e-6))
+        assert not bad.any(), (what, int(bad.sum()))
+
+    for direction in (0, 1):
+        for inst in (a, b):
+            inst.reset()
+            inst.run(2)
+            if direction == 1:
+                inst.run_pass(0)
+        (la, Ma), (lb, Mb) = a.get_state(), b.get_state()
+        np.testing.assert_array_equal(host(la), host(lb))
+        dlo, dmo = rng.normal(size=p.nnz), rng.normal(size=p.nnz)
+        ra = [host(t) for t in a.pass_vjp(direction, la, Ma, dev(dlo), dev(dmo))]
+        rb = [host(t) for t in b.pass_vjp(direction, lb, Mb, dev(dlo), dev(dmo))]
+        for x, y, name in zip(rb, ra, ("dlam_in", "dM_in", "d_alpha", "d_omega")):
+            close(x, y, f"dir {direction} {name}")
+    for inst in (a, b):
+        inst.reset()
+    lba, lbb = a.forward_unrolled(3, 1), b.forward_unrolled(3, 1)
+    assert lba == lbb
+    ga = [host(t) for t in a.backward(1.0)]
+    gb = [host(t) for t in b.backward(1.0)]
+    for x, y, name in zip(gb, ga, ("d_omega", "d_alpha", "d_c")):
+        close(x, y, name)
+
+
 def test_gm_mini_unrolled_gradient(orc):
     """The 50-assignment-variable graph-matching instance whose oracle gradient is pinned by
     central differences on every coordinate; T = 20, checkpoints every 5."""
