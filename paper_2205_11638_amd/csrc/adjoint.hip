@@ -430,16 +430,18 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
 // node, in wave order, written over the level's own adjoint buffer once it has been read) and
 // routes the list with one lane per entry, instead of a routing step for every node.  A level
 // whose nonzero adjoints overflow the list is routed node by node by the owning lanes.  The
-// argmin nodes of the two min-marginals come out of the same pass over the nodes as the minima:
-// each lane visits its nodes in increasing index and keeps the first one that attains its
-// running minimum.  Float sums (LDS adds, the hi-arc sum) may be added in another order than in
-// the general sweep; the mins and the argmin tests are exact.
+// update sweep takes the hop's argmin nodes of the two min-marginals, their children and
+// m^1 - m^0 from the records of the replayed (or stored) pass, so it reads no F at all.  Float
+// sums (LDS adds, the hi-arc sum) may be added in another order than in the general sweep; the
+// mins and the argmin tests are exact.
 // ------------------------------------------------------------------------------------------
 template <bool UPD>
 struct AdjIn;
 template <>
-struct AdjIn<true> {  // multipliers after and before the replayed pass, output adjoints, omega, alpha, S, sums
-    float lam, lam_in, dlo, dMo, om, al, S, da, dw;
+struct AdjIn<true> {  // multiplier after the pass, output adjoints, omega, alpha, S, sums, the pass's records
+    float lam, dlo, dMo, om, al, S, da, dw;
+    uint32_t kc0, kc1;  // argmin node of m^0 | its lo child << 16; the same for m^1 and the hi child
+    float d;            // m^1 - m^0 as the pass formed it
 };
 template <>
 struct AdjIn<false> {  // multiplier of the fixed side, alpha*S and dlambda_in so far
@@ -451,7 +453,6 @@ __device__ __forceinline__ AdjIn<UPD> adj_in(const DevTables &T, const AdjTables
     AdjIn<UPD> x;
     if constexpr (UPD) {
         x.lam = T.lam[e];
-        x.lam_in = A.lam_in[e];
         x.dlo = A.dlam_out[e];
         x.dMo = A.dM_out[e];
         x.om = T.omega[e];
@@ -459,6 +460,9 @@ __device__ __forceinline__ AdjIn<UPD> adj_in(const DevTables &T, const AdjTables
         x.S = A.Se[e];
         x.da = A.dalpha[e];
         x.dw = A.domega[e];
+        x.kc0 = (uint32_t)A.mrec[2 * e];
+        x.kc1 = (uint32_t)A.mrec[2 * e + 1];
+        x.d = A.mdiff[e];
     } else {
         x.lam_src = A.lam_src[e];
         x.aS = T.aS[e];
@@ -492,12 +496,6 @@ __device__ __forceinline__ AdjOut adj_out(const AdjTables &A, const TileCtx &tc,
 
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ void st2(rsrc_t r, int off, uint32_t a, uint32_t b) {
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
-    const u32x2 v = {a, b};
-    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
-}
-
 // lanes below this one whose bit is set in a wave mask
 __device__ __forceinline__ int lanes_below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -505,8 +503,8 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 
 template <int Q, int RMAX, bool UPD>
 __device__ __forceinline__ void adjB_hop_w(const float *Bst, float *ba0, float *ba1, const u32x4 (&tp)[RMAX / 4],
-                                           const f32x4 (&fvi)[RMAX / 4], int lane, const Lev &c0, int Wn,
-                                           float lam_use, const AdjIn<UPD> &x, const AdjOut &o, int l, int cap) {
+                                           int lane, const Lev &c0, int Wn, float lam_use, const AdjIn<UPD> &x,
+                                           const AdjOut &o, int l, int cap) {
     constexpr int CAP = node_buf_w(RMAX) / 2;  // list entries that fit in a node buffer
     const int l16 = lane16(lane);
     u32x4 t[Q];
@@ -562,47 +560,19 @@ __device__ __forceinline__ void adjB_hop_w(const float *Bst, float *ba0, float *
     }
     hisum = team_sum<64>(hisum);
     if constexpr (UPD) {
-        f32x4 f[Q];
-#pragma unroll
-        for (int q = 0; q < Q; ++q) f[q] = fvi[q];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            if (j >= rem) f[Q - 1][j] = kInf;
-        // min-marginals again (same expressions as the pass) with the first node attaining each
-        float m0 = kInf, m1 = kInf;
-        int k0 = INT_MAX, k1 = INT_MAX, ch0 = 0, ch1 = 0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = q * 256 + (l16 >> 2) + j;
-                const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
-                const float v0 = f[q][j] + Bst[lo], v1 = f[q][j] + Bst[hi];
-                if (v0 < m0 || (v0 == m0 && k0 == INT_MAX)) {
-                    m0 = v0;
-                    k0 = k;
-                    ch0 = lo;
-                }
-                if (v1 < m1 || (v1 == m1 && k1 == INT_MAX)) {
-                    m1 = v1;
-                    k1 = k;
-                    ch1 = hi;
-                }
-            }
-        const float M0 = team_min<64>(m0), M1 = team_min<64>(m1);
-        const int K0 = team_min_i<64>(m0 == M0 ? k0 : INT_MAX);  // lowest argmin node of each
-        const int K1 = team_min_i<64>(m1 == M1 ? k1 : INT_MAX);
+        // the pass's argmin nodes of the two min-marginals and their children (recorded)
+        const int K0 = (int)(x.kc0 & 0xFFFFu), K1 = (int)(x.kc1 & 0xFFFFu);
+        const int r0 = (int)(x.kc0 >> 16), r1 = (int)(x.kc1 >> 16);
         const float dlam_new = x.dlo + hisum;
         const float dM = x.dMo - dlam_new;
-        const float diff = (M1 + x.lam_in) - M0;  // m^1 - m^0 as the pass formed it
         const float dm1 = x.om * dM, dm0 = -dm1;
         wave_sync();  // after the routed adjoints (a fixed order of the float adds)
-        if (k0 == K0 && ch0 < Wn) lds_fadd(&ba1[ch0], dm0);
-        if (k1 == K1 && ch1 < Wn) lds_fadd(&ba1[ch1], dm1);
+        if (lane == 0 && r0 < Wn) lds_fadd(&ba1[r0], dm0);
+        if (lane == 0 && r1 < Wn) lds_fadd(&ba1[r1], dm1);
         st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
         st1(o.g, o.o4 + 4 * l, dlam_new * x.al);
         st1(o.dalpha, o.o4 + 4 * l, x.da + dlam_new * x.S);
-        st1(o.domega, o.o4 + 4 * l, x.dw + dM * diff);
+        st1(o.domega, o.o4 + 4 * l, x.dw + dM * x.d);
         st2(o.rec_idx, o.o8 + 8 * l, (uint32_t)K0, (uint32_t)K1);  // argmin nodes of level l: F_l side
         st2(o.rec_val, o.o8 + 8 * l, __float_as_uint(dm0), __float_as_uint(dm1));
     } else {
@@ -651,15 +621,13 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
     }
     Lev c0 = level(0), c1 = level(1);
     u32x4 tpn[QM];
-    f32x4 fvn[QM], bvn[QM];
+    f32x4 bvn[QM];
     {
         const int l16 = lane16(lane);
-        const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), fr = buf(T.F + c0.base, row_bytes(c0));
-        const rsrc_t br = buf(T.B + c1.base, row_bytes(c1));
+        const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), br = buf(T.B + c1.base, row_bytes(c1));
 #pragma unroll
         for (int q = 0; q < QM; ++q) {
             tpn[q] = ld4(tr, l16 + q * 1024);
-            fvn[q] = UPD ? ld4f(fr, l16 + q * 1024) : zero4;
             bvn[q] = ld4f(br, l16 + q * 1024);
         }
     }
@@ -676,12 +644,8 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
             if (pi1 >= 0) ba0[pi1] += pv1;
         }
         u32x4 tp[QM];
-        f32x4 fv[QM];
 #pragma unroll
-        for (int q = 0; q < QM; ++q) {
-            tp[q] = tpn[q];
-            fv[q] = fvn[q];
-        }
+        for (int q = 0; q < QM; ++q) tp[q] = tpn[q];
         {
             // B of level l+1 with its terminals; the adjoints of level l+1 start at 0
             const int l16 = lane16(lane);
@@ -696,17 +660,15 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
             Bst[Wn] = kInf;
             Bst[Wn + 1] = 0.f;
         }
-        // prefetch hop l+1: topology and F of level l+1, B of level l+2, edge data of level l+1
-        // (the last hop reloads its own), the record of edge l
+        // prefetch hop l+1: topology of level l+1, B of level l+2, edge data of level l+1 (the
+        // last hop reloads its own), the record of edge l
         const Lev c2 = level(l + 2);
         {
             const int l16 = lane16(lane);
-            const rsrc_t tr = buf(T.topo + c1.base, row_bytes(c1)), fr = buf(T.F + c1.base, row_bytes(c1));
-            const rsrc_t br = buf(T.B + c2.base, row_bytes(c2));
+            const rsrc_t tr = buf(T.topo + c1.base, row_bytes(c1)), br = buf(T.B + c2.base, row_bytes(c2));
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
                 tpn[q] = ld4(tr, l16 + q * 1024);
-                if (UPD) fvn[q] = ld4f(fr, l16 + q * 1024);
                 bvn[q] = ld4f(br, l16 + q * 1024);
             }
             xn = adj_in<UPD>(T, A, tc.ebase + min(l + 1, nlev - 1));
@@ -722,7 +684,7 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
         if constexpr (UPD) lam_use = x.lam;
         else lam_use = bar ? x.lam_src + x.aS : x.lam_src;
         with_count<1, QM>(groups(c0), [&](auto qc) {
-            adjB_hop_w<decltype(qc)::value, RMAX, UPD>(Bst, ba0, ba1, tp, fv, lane, c0, Wn, lam_use, x, o, l, cap);
+            adjB_hop_w<decltype(qc)::value, RMAX, UPD>(Bst, ba0, ba1, tp, lane, c0, Wn, lam_use, x, o, l, cap);
         });
         wave_sync();
         cur ^= 1;
@@ -740,9 +702,10 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
 // child's adjoint slot (its value is in the list by then), and the winners add into the level's
 // adjoint.  A list that overflows is bid and collected by the owning lanes instead.  F and its
 // adjoint have one buffer each: level l overwrites level l+1 once every value of level l+1 that
-// the hop needs has been read.  The update sweep forms the min-marginals first, which frees the
-// staged B for the overflow case's bids.
-// LDS per wave: Fv, Fa (cost and adjoint), Bst (B of level l+1), the list, the level table.
+// the hop needs has been read.  The update sweep takes the hop's argmin nodes, their children and
+// m^1 - m^0 from the records of the replayed (or stored) pass, so it reads no B at all.
+// LDS per wave: Fv, Fa (cost and adjoint), a spare node buffer (the bids of an overflowing list),
+// the list, the level table.
 // ------------------------------------------------------------------------------------------
 template <bool UPD>
 struct AdjInF;
@@ -758,7 +721,7 @@ struct AdjInF<false> {  // fixed side: the multiplier swept, dlambda_in so far, 
 };
 
 template <int Q, int RMAX, bool UPD>
-__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *Bst, uint32_t *lkw, float *lval, float *lfa,
+__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, uint32_t *lkw, float *lval, float *lfa,
                                            const u32x4 (&tp)[RMAX / 4], const f32x4 (&fvi)[RMAX / 4], int lane,
                                            const Lev &c0, int Wn, float lam_use, const AdjInF<UPD> &x,
                                            const AdjOut &o, int l, int cap) {
@@ -779,45 +742,6 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *Bst, uin
             t[Q - 1][j] = dead;
             f[Q - 1][j] = kInf;
         }
-    // update sweeps: min-marginals again (same expressions as the pass) with the first node
-    // attaining each; the staged B is free afterwards
-    float M0 = 0.f, M1 = 0.f;
-    int K0 = 0, K1 = 0, r0 = 0, r1 = 0;
-    bool own0 = false, own1 = false;
-    if constexpr (UPD) {
-        float m0 = kInf, m1 = kInf;
-        int k0 = INT_MAX, k1 = INT_MAX, ch0 = 0, ch1 = 0;
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int k = q * 256 + (l16 >> 2) + j;
-                uint32_t tt = t[q][j];
-                float ff = f[q][j];
-                if (j == 0) __asm__ volatile("" : "+v"(tt), "+v"(ff));  // loads stay with their group
-                const int lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
-                const float v0 = ff + Bst[lo], v1 = ff + Bst[hi];
-                if (v0 < m0 || (v0 == m0 && k0 == INT_MAX)) {
-                    m0 = v0;
-                    k0 = k;
-                    ch0 = lo;
-                }
-                if (v1 < m1 || (v1 == m1 && k1 == INT_MAX)) {
-                    m1 = v1;
-                    k1 = k;
-                    ch1 = hi;
-                }
-            }
-        M0 = team_min<64>(m0);
-        M1 = team_min<64>(m1);
-        K0 = team_min_i<64>(m0 == M0 ? k0 : INT_MAX);
-        K1 = team_min_i<64>(m1 == M1 ? k1 : INT_MAX);
-        own0 = k0 == K0;
-        own1 = k1 == K1;
-        // children of the argmin nodes (one lane owns each)
-        r0 = __builtin_amdgcn_readlane(ch0, __builtin_ctzll(__builtin_amdgcn_ballot_w64(own0)));
-        r1 = __builtin_amdgcn_readlane(ch1, __builtin_ctzll(__builtin_amdgcn_ballot_w64(own1)));
-    }
     // arcs into a child with a nonzero adjoint (terminal slots of Fa hold 0), in wave order;
     // the first CAP go to the list; returns the number of such arcs
     // (the node values are taken afresh, so nothing derived from them is computed ahead and
@@ -881,9 +805,9 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *Bst, uin
             if (key & 1) hisum = a;
         }
     } else {
-        // more arcs than the list holds: every lane bids for its own arcs (bids in the staged-B
-        // buffer, free by now) and collects its nodes' adjoints
-        int *obid = (int *)Bst;
+        // more arcs than the list holds: every lane bids for its own arcs (bids in the spare
+        // buffer) and collects its nodes' adjoints
+        int *obid = (int *)spare;
         const i32x4 none = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
 #pragma unroll
         for (int q = 0; q < RMAX / 4; ++q) *(i32x4 *)((char *)obid + l16 + q * 1024) = none;
@@ -931,14 +855,17 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *Bst, uin
     }
     hisum = team_sum<64>(hisum);
     if constexpr (UPD) {
+        // the pass's argmin nodes of the two min-marginals and their children (recorded)
         const AdjIn<true> &y = x.a;
+        const int K0 = (int)(y.kc0 & 0xFFFFu), K1 = (int)(y.kc1 & 0xFFFFu);
+        const int r0 = (int)(y.kc0 >> 16), r1 = (int)(y.kc1 >> 16);
         const float dlam_new = y.dlo + hisum;
         const float dM = y.dMo - dlam_new;
-        const float diff = (M1 + y.lam_in) - M0;  // m^1 - m^0 as the pass formed it
+        const float diff = y.d;
         const float dm1 = y.om * dM, dm0 = -dm1;
         wave_sync();  // after the winners' adds (a fixed order of the float adds)
-        if (own0) lds_fadd(&Fa[K0], dm0);
-        if (own1) lds_fadd(&Fa[K1], dm1);
+        if (lane == 0) lds_fadd(&Fa[K0], dm0);
+        if (lane == 0) lds_fadd(&Fa[K1], dm1);
         st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
         st1(o.g, o.o4 + 4 * l, dlam_new * y.al);
         st1(o.dalpha, o.o4 + 4 * l, y.da + dlam_new * y.S);
@@ -966,8 +893,8 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
     if (tile >= tile0 + ntiles) return;  // uniform per wave
     float *Fv = lds_f + (size_t)wave * lds_words_adj_F_w(RMAX, NL);
     float *Fa = Fv + NB;
-    float *Bst = Fa + NB;
-    uint32_t *lkw = (uint32_t *)(Bst + NB);
+    float *spare = Fa + NB;
+    uint32_t *lkw = (uint32_t *)(spare + NB);
     float *lval = (float *)(lkw + kAdjListW), *lfa = lval + kAdjListW;
     int *meta = (int *)(lfa + kAdjListW);
     int *off = meta + NL;
@@ -1012,10 +939,9 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         for (int q = 0; q <= QM; ++q)
             if (q < QM || lane < 16) lds4(Fa, l16 + q * 1024) = zero4;
     }
-    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
     Lev c0 = level(nlev - 1), c1{0, 0, 0};
     u32x4 tpn[QM];
-    f32x4 fvn[QM], bvn[QM];
+    f32x4 fvn[QM];
     {
         const int l16 = lane16(lane);
         const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), fr = buf(T.F + c0.base, row_bytes(c0));
@@ -1023,7 +949,6 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         for (int q = 0; q < QM; ++q) {
             tpn[q] = ld4(tr, l16 + q * 1024);
             fvn[q] = ld4f(fr, l16 + q * 1024);
-            bvn[q] = zero4;  // B of level L: only its terminals are read
         }
     }
     AdjInF<UPD> xn = edge(nlev - 1);
@@ -1037,28 +962,16 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
             tp[q] = tpn[q];
             fv[q] = fvn[q];
         }
-        if (UPD) {
-            const int l16 = lane16(lane);
-#pragma unroll
-            for (int q = 0; q < QM; ++q) lds4(Bst, l16 + q * 1024) = bvn[q];  // B of level l+1
-            wave_sync();  // the terminals' slots may have been staged by another lane
-            if (lane == 0) {
-                Bst[Wn] = kInf;
-                Bst[Wn + 1] = 0.f;
-            }
-        }
-        // prefetch hop l-1: topology and F of level l-1, B of level l, edge data of level l-1
-        // (the last hop reloads its own)
+        // prefetch hop l-1: topology and F of level l-1, edge data of level l-1 (the last hop
+        // reloads its own)
         const Lev cp = level(l - 1);
         {
             const int l16 = lane16(lane);
             const rsrc_t tr = buf(T.topo + cp.base, row_bytes(cp)), fr = buf(T.F + cp.base, row_bytes(cp));
-            const rsrc_t br = buf(T.B + c0.base, row_bytes(c0));
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
                 tpn[q] = ld4(tr, l16 + q * 1024);
                 fvn[q] = ld4f(fr, l16 + q * 1024);
-                if (UPD) bvn[q] = ld4f(br, l16 + q * 1024);
             }
             xn = edge(max(l - 1, 0));
         }
@@ -1070,7 +983,7 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         if constexpr (!UPD)
             if (!use_rec) xu.i0 = xu.i1 = -1;
         with_count<1, QM>(groups(c0), [&](auto qc) {
-            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, Bst, lkw, lval, lfa, tp, fv, lane, c0, Wn, lam_use,
+            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, spare, lkw, lval, lfa, tp, fv, lane, c0, Wn, lam_use,
                                                        xu, o, l, cap);
         });
         wave_sync();

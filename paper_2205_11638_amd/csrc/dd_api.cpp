@@ -346,9 +346,10 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
 // Bytes one launch must move by the method's own accounting (per node / per edge / per row).
 double algorithmic_bytes(bool fwd, int mode, const ClassLaunch &c) {
     const double N = (double)c.nodes, E = (double)c.edges, R = (double)c.rows;
-    if (fwd) return mode == FWD_UPDATE ? 12 * N + 28 * E : 8 * N + 16 * E;
+    if (fwd) return mode == FWD_UPDATE ? 12 * N + 28 * E : mode == FWD_UPDATE_REC ? 12 * N + 40 * E : 8 * N + 16 * E;
     switch (mode) {
         case BWD_UPDATE: return 12 * N + 28 * E + 4 * R;
+        case BWD_UPDATE_REC: return 12 * N + 40 * E + 4 * R;
         case BWD_STORE: return 8 * N + 8 * E + 4 * R;
         case BWD_EN_LAM: return 4 * N + 4 * E + 4 * R;
         case BWD_EN_BAR: return 4 * N + 16 * E + 4 * R;
@@ -412,7 +413,8 @@ int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
 }
 
 // Reverse sweeps.  Bytes: update sweeps read topology, the swept side's cost and the staged
-// other side (12 B/node) and ~68 B of edge data; fixed sweeps 8 B/node and ~28 B/edge.
+// other side (12 B/node) and ~68 B of edge data, or, for one-wave diagrams, topology and the swept
+// side (8 B/node) and ~76 B of edge data with the pass's records; fixed sweeps 8 B/node, ~28 B/edge.
 int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs, float seed, hipStream_t s) {
     const bool upd = which == ADJ_F_UPDATE || which == ADJ_B_UPDATE;
     const char *nm = which == ADJ_F_UPDATE || which == ADJ_F_FIXED ? "k_adj_F" : "k_adj_B";
@@ -428,6 +430,8 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
             return std::string(name);
         },
         [&](const ClassLaunch &cl) {
+            // one-wave update sweeps take the argmins from the pass's records instead of the other side
+            if (upd && cl.P == 64) return 8.0 * cl.nodes + 76.0 * cl.edges;
             return upd ? 12.0 * cl.nodes + 68.0 * cl.edges : 8.0 * cl.nodes + 28.0 * cl.edges;
         });
 }
@@ -898,6 +902,10 @@ int adj_alloc(dd_instance *h) {
         if ((st = h->alloc(b, S))) return st;
     if ((st = h->alloc(&h->rec_val, 2 * S))) return st;
     if ((st = h->alloc(&h->rec_idx, 2 * S))) return st;
+    if ((st = h->alloc(&h->mrec, 2 * S))) return st;
+    if ((st = h->alloc(&h->mdiff, S))) return st;
+    HIP_TRY(hipMemset(h->mrec, 0, sizeof(int32_t) * 2 * S));
+    HIP_TRY(hipMemset(h->mdiff, 0, sizeof(float) * S));
     if ((st = h->alloc(&h->scratch_n, (size_t)std::max<int64_t>(h->n, 1)))) return st;
     for (float *b : {h->lam_in, h->dlamA, h->dlamB, h->dMA, h->dMB, h->g, h->dalpha, h->domega, h->Se})
         HIP_TRY(hipMemset(b, 0, sizeof(float) * S));
@@ -912,25 +920,55 @@ int copy_slots(dd_instance *h, float *dst, const float *src, hipStream_t s) {
     return DD_OK;
 }
 
+// Launches fn with the tables pointed at the record arrays (the instance's own unless given), so its
+// recording update passes write them; the tables never keep those pointers.
+template <typename Fn>
+int recording(dd_instance *h, Fn &&fn, int32_t *mrec = nullptr, float *mdiff = nullptr) {
+    h->T.mrec = mrec ? mrec : h->mrec;
+    h->T.mdiff = mdiff ? mdiff : h->mdiff;
+    const int st = fn();
+    h->T.mrec = nullptr;
+    h->T.mdiff = nullptr;
+    return st;
+}
+
+// An update pass that records its argmins (as dd_run_pass otherwise).
+int run_pass_rec(dd_instance *h, int dir, hipStream_t s, int32_t *mrec = nullptr, float *mdiff = nullptr) {
+    h->en_lam_valid = false;
+    h->version++;
+    int st = deferred(h, s);
+    if (st == DD_OK)
+        st = recording(h, [&] { return all_classes(h, dir == 0, dir == 0 ? (int)FWD_UPDATE_REC : (int)BWD_UPDATE_REC, s); },
+                       mrec, mdiff);
+    h->en_lam_valid = st == DD_OK && dir == 1;
+    return st;
+}
+
 // Reverse mode of one pass.  On entry the instance state (lambda, M) is the pass input; on exit
 // it is the pass output.  dlam_out/dM_out: adjoints of the outputs; dlam_in/dM_in receive the
 // adjoints of the inputs; d_alpha and d_omega accumulate.
 // With lam_src/M_src (slot order): the instance already holds this pass's outputs -- its
 // multipliers, M and both node sides exactly as the pass left them (the side it read, computed
-// from the input multipliers, and the side it rebuilt) -- and lam_src/M_src are its inputs;
-// the fixed-side sweep and the replay are then skipped.
+// from the input multipliers, and the side it rebuilt) -- and lam_src/M_src are its inputs and
+// mrec_src/mdiff_src its argmin records; the fixed-side sweep and the replay are then skipped.
+// Otherwise the replay records them.
 int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out, float *dlam_in, float *dM_in,
-             hipStream_t s, const float *lam_src = nullptr, const float *M_src = nullptr) {
+             hipStream_t s, const float *lam_src = nullptr, const float *M_src = nullptr,
+             const int32_t *mrec_src = nullptr, const float *mdiff_src = nullptr) {
     const bool fresh = lam_src != nullptr;
+    if (fresh && (!mrec_src || !mdiff_src)) return fail(DD_E_ARG, "internal: a pass adjoint needs the pass's records");
     int st = deferred_from(h, fresh ? M_src : h->T.M, s);  // S and alpha*S of the pass-input M
     if (st) return st;
     st = recorded(h, "k_edge_S", 12.0 * (double)h->edge_slots, s,
                   [&] { return launch_edge_S(h->T.evar, h->S, h->Se, h->edge_slots, s); });
     if (st) return st;
-    if ((st = copy_slots(h, h->lam_in, fresh ? lam_src : h->T.lam, s))) return st;
+    // the pass-input multipliers: kept by the caller, or copied before the replay overwrites them
+    if (!fresh && (st = copy_slots(h, h->lam_in, h->T.lam, s))) return st;
     AdjTables A{};
-    A.lam_in = h->lam_in;
-    A.lam_src = h->lam_in;
+    A.lam_in = fresh ? lam_src : h->lam_in;
+    A.lam_src = A.lam_in;
+    A.mrec = fresh ? mrec_src : h->mrec;
+    A.mdiff = fresh ? mdiff_src : h->mdiff;
     A.dlam_out = dlam_out;
     A.dM_out = dM_out;
     A.Se = h->Se;
@@ -944,12 +982,12 @@ int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out
     if (dir == 0) {
         // fixed side B at the input multipliers, the pass replayed (F), then the two reverse sweeps
         if (!fresh && (st = all_classes(h, false, BWD_STORE, s))) return st;
-        if (!fresh && (st = all_classes(h, true, FWD_UPDATE, s))) return st;
+        if (!fresh && (st = recording(h, [&] { return all_classes(h, true, FWD_UPDATE_REC, s); }))) return st;
         if ((st = adj_classes(h, A, ADJ_F_UPDATE, 0, 0, 0.f, s))) return st;
         if ((st = adj_classes(h, A, ADJ_B_FIXED, 0, 1, 0.f, s))) return st;
     } else {
         if (!fresh && (st = all_classes(h, true, FWD_SWEEP_LAM, s))) return st;
-        if (!fresh && (st = all_classes(h, false, BWD_UPDATE, s))) return st;
+        if (!fresh && (st = recording(h, [&] { return all_classes(h, false, BWD_UPDATE_REC, s); }))) return st;
         if ((st = adj_classes(h, A, ADJ_B_UPDATE, 0, 0, 0.f, s))) return st;
         if ((st = adj_classes(h, A, ADJ_F_FIXED, 0, 1, 0.f, s))) return st;
     }
@@ -1017,18 +1055,20 @@ namespace {
 int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     const size_t nodes = (size_t)h->node_slots + 64, bytes = nodes * sizeof(float);
+    const size_t rec_bytes = (size_t)h->edge_slots * 12;  // argmin records of one pass
     size_t need = 0;
-    if ((int)h->trF.size() < T) need += (size_t)T - h->trF.size();
-    if ((int)h->trB.size() < T + 1) need += (size_t)T + 1 - h->trB.size();
+    if ((int)h->trF.size() < T) need += ((size_t)T - h->trF.size()) * bytes;
+    if ((int)h->trB.size() < T + 1) need += ((size_t)T + 1 - h->trB.size()) * bytes;
+    if ((int)h->tr_mrec.size() < 2 * T) need += ((size_t)2 * T - h->tr_mrec.size()) * rec_bytes;
     if (need) {
         size_t free_b = 0, total_b = 0;
         HIP_TRY(hipMemGetInfo(&free_b, &total_b));
         const size_t margin = (size_t)2 << 30;
-        if (need * bytes + margin > free_b)
+        if (need + margin > free_b)
             return fail(DD_E_OOM,
                         "a stored trajectory of %d iterations needs %.1f GB more device memory (%.1f GB free): "
                         "use checkpoints (ckpt_every >= 1)",
-                        T, (double)(need * bytes) / 1e9, (double)free_b / 1e9);
+                        T, (double)need / 1e9, (double)free_b / 1e9);
     }
     int st;
     while ((int)h->trF.size() < T) {
@@ -1040,6 +1080,13 @@ int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void 
         float *p = nullptr;
         if ((st = h->alloc(&p, nodes))) return st;
         h->trB.push_back(p);
+    }
+    while ((int)h->tr_mrec.size() < 2 * T) {
+        int32_t *p = nullptr;
+        float *q = nullptr;
+        if ((st = h->alloc(&p, 2 * (size_t)h->edge_slots)) || (st = h->alloc(&q, (size_t)h->edge_slots))) return st;
+        h->tr_mrec.push_back(p);
+        h->tr_mdiff.push_back(q);
     }
     h->F0 = h->T.F;
     h->B0 = h->T.B;
@@ -1056,9 +1103,11 @@ int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void 
     for (int t = 0; t < T && st == DD_OK; ++t) {
         h->T.F = h->trF[t];
         h->T.B = h->trB[t];
-        if ((st = dd_run_pass(h, 0, stream)) || (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s))) break;
+        if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t])) ||
+            (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)))
+            break;
         h->T.B = h->trB[t + 1];
-        if ((st = dd_run_pass(h, 1, stream))) break;
+        if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1]))) break;
         st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s);
     }
     if (st == DD_OK) st = dd_lower_bound(h, lb, nullptr, stream);
@@ -1147,13 +1196,15 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
             h->T.F = h->trF[t];
             h->T.B = h->trB[t + 1];  // the backward pass of iteration t
             if ((st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s)) ||
-                (st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1])))
+                (st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1],
+                               h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1])))
                 break;
             std::swap(dl, dl2);
             std::swap(dm, dm2);
             h->T.B = h->trB[t];  // its forward pass
             if ((st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)) ||
-                (st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t])))
+                (st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t], h->tr_mrec[2 * t],
+                               h->tr_mdiff[2 * t])))
                 break;
             std::swap(dl, dl2);
             std::swap(dm, dm2);
@@ -1168,15 +1219,16 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
         // a forward pass reads B at its input multipliers: the backward pass before it left
         // exactly that, so rebuild it from the checkpoint (same expression, same bits)
         if ((st = recompute_B(h, s))) return st;
-        for (int q = 0; q < np; ++q) {  // recompute the pass inputs of the segment
+        for (int q = 0; q < np; ++q) {  // recompute the pass inputs of the segment (the last records)
             if ((st = save_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
-            if ((st = dd_run_pass(h, q % 2, stream))) return st;
+            if ((st = q == np - 1 ? run_pass_rec(h, q % 2, s) : dd_run_pass(h, q % 2, stream))) return st;
         }
         for (int q = np - 1; q >= 0; --q) {
             if (q == np - 1) {
                 // the recomputation just ran this pass: its outputs and both node sides are in place
                 // (a segment ends with a backward pass, whose fixed side is the F its forward pass left)
-                if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s, h->seg_lam[q], h->seg_M[q]))) return st;
+                if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s, h->seg_lam[q], h->seg_M[q], h->mrec, h->mdiff)))
+                    return st;
             } else {
                 if ((st = load_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
                 if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s))) return st;

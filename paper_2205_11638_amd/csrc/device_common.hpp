@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "kernels.hpp"
 
 namespace dd {
@@ -198,6 +200,48 @@ __device__ __forceinline__ int lane16(int lane) {
 __device__ __forceinline__ int row_bytes(const Lev &c) { return c.R * 256; }
 __device__ __forceinline__ int node_bytes(const Lev &c) { return ((c.W + 3) & ~3) * 4; }
 __device__ __forceinline__ int groups(const Lev &c) { return (c.R + 3) >> 2; }
+
+
+__device__ __forceinline__ void st2(rsrc_t r, int off, uint32_t a, uint32_t b) {
+    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 v = {a, b};
+    __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
+
+// Recording update passes (one-wave diagrams): each lane visits its nodes in increasing index and
+// keeps the first one attaining its running minimum m of a min-marginal (call before m takes v),
+// with the child code the minimum went through.
+__device__ __forceinline__ void argmin_step(float v, float m, int k, int child, int &kk, int &hh) {
+    if (v < m || (v == m && kk == INT_MAX)) {
+        kk = k;
+        hh = child;
+    }
+}
+
+// The lowest node attaining each min-marginal of the hop (lm: the lane's minima, M: the wave's,
+// k / h: the lane's first attaining node and its child) with its child code, and m^1 - m^0 as the
+// pass formed it; lane 0 stores them (record offset 2 out, difference offset out).
+__device__ __forceinline__ void record_argmins(rsrc_t rec_r, rsrc_t md_r, int out, float lm0, float M0, int k0,
+                                               int h0, float lm1, float M1, int k1, int h1, float d) {
+    const int K0 = team_min_i<64>(lm0 == M0 ? k0 : INT_MAX);
+    const int K1 = team_min_i<64>(lm1 == M1 ? k1 : INT_MAX);
+    const int c0 = __builtin_amdgcn_readlane(h0, __builtin_ctzll(__builtin_amdgcn_ballot_w64(k0 == K0)));
+    const int c1 = __builtin_amdgcn_readlane(h1, __builtin_ctzll(__builtin_amdgcn_ballot_w64(k1 == K1)));
+    st2(rec_r, 2 * out, (uint32_t)K0 | ((uint32_t)c0 << 16), (uint32_t)K1 | ((uint32_t)c1 << 16));
+    st1(md_r, out, d);
+}
+
+// the records' resources over a tile's edges (no size when not recording)
+template <bool REC>
+__device__ __forceinline__ rsrc_t rec_buf(const DevTables &T, const TileCtx &tc, int nlev) {
+    if constexpr (REC) return buf(T.mrec + 2 * (int64_t)tc.ebase, nlev * 8);
+    else return buf(T.lam, 0);
+}
+template <bool REC>
+__device__ __forceinline__ rsrc_t mdiff_buf(const DevTables &T, const TileCtx &tc, int nlev) {
+    if constexpr (REC) return buf(T.mdiff + tc.ebase, nlev * 4);
+    else return buf(T.lam, 0);
+}
 
 }  // namespace dev
 }  // namespace dd

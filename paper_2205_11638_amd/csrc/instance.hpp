@@ -70,12 +70,16 @@ struct dd_instance {
     float *dalpha = nullptr, *domega = nullptr, *rec_val = nullptr, *scratch_n = nullptr, *Se = nullptr;
     float *Bs = nullptr;  // smoothed node costs (allocated on first use)
     int32_t *rec_idx = nullptr;
+    int32_t *mrec = nullptr;  // argmin records of the last recording update pass (one-wave diagrams)
+    float *mdiff = nullptr;
     std::vector<float *> ck_lam, ck_M;    // checkpoints of the unrolled forward (state at iterations 0, K, 2K, ..., T)
     std::vector<float *> seg_lam, seg_M;  // pass-input states inside one checkpoint segment
     // stored trajectory of the unrolled forward (ckpt_every = -1): the node costs every pass read or
     // wrote and the state before every pass, so the backward sweep recomputes nothing
     std::vector<float *> trF, trB;      // trF[t]: F left by forward pass t; trB[t]: B forward pass t read (t <= T)
     std::vector<float *> tr_lam, tr_M;  // state before pass q = 0 .. 2T (the last one: the final state)
+    std::vector<int32_t *> tr_mrec;     // argmin records of pass q = 0 .. 2T-1
+    std::vector<float *> tr_mdiff;
     float *F0 = nullptr, *B0 = nullptr; // the instance's own node-cost arrays
     bool fwd_stored = false;
     int fwd_T = -1, fwd_K = 0;

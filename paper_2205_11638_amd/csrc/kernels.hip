@@ -336,10 +336,11 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
 // empty-level case.  The arithmetic is that of the general kernels above; the min over a
 // level's arcs is exact, so the order in which a lane visits its nodes does not matter.
 template <int Q, int RMAX, int MODE, typename Prefetch>
-__device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, float *Fb, const float *Bst,
-                                          const u32x4 (&tp)[RMAX / 4], int lane, int out, const Lev &c0,
-                                          const Lev &c1, float lam, float om, float aS, Prefetch &&prefetch) {
-    constexpr bool UPD = MODE == FWD_UPDATE;
+__device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, rsrc_t rec_r, rsrc_t md_r, float *Fb,
+                                          const float *Bst, const u32x4 (&tp)[RMAX / 4], int lane, int out,
+                                          const Lev &c0, const Lev &c1, float lam, float om, float aS,
+                                          Prefetch &&prefetch) {
+    constexpr bool REC = MODE == FWD_UPDATE_REC, UPD = MODE == FWD_UPDATE || REC;
     constexpr int QM = RMAX / 4, SINK = RMAX * 64;
     const int l16 = lane16(lane);
     f32x4 fv[Q];
@@ -365,22 +366,25 @@ __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, f
     float lam_new;
     if (UPD) {
         float m0 = kInf, m1 = kInf;
+        int k0 = INT_MAX, k1 = INT_MAX, h0 = 0, h1 = 0;  // recording: first node attaining the lane's min
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float b0 = Bst[(int)(t[q][j] & 0xFFFFu)];
-                const float b1 = Bst[(int)(t[q][j] >> 16)];
-                m0 = fminf(m0, fv[q][j] + b0);
-                m1 = fminf(m1, fv[q][j] + b1);
+                const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
+                const float v0 = fv[q][j] + Bst[lo], v1 = fv[q][j] + Bst[hi];
+                if (REC) argmin_step(v0, m0, q * 256 + (l16 >> 2) + j, lo, k0, h0);
+                if (REC) argmin_step(v1, m1, q * 256 + (l16 >> 2) + j, hi, k1, h1);
+                m0 = fminf(m0, v0);
+                m1 = fminf(m1, v1);
             }
-        m0 = team_min<64>(m0);
-        m1 = team_min<64>(m1);
-        m1 += lam;
-        const float Mn = om * (m1 - m0);
+        const float M0 = team_min<64>(m0), M1 = team_min<64>(m1);
+        const float d = (M1 + lam) - M0;
+        const float Mn = om * d;
         lam_new = lam - Mn + aS;
         st1(lam_r, out, lam_new);
         st1(M_r, out, Mn);
+        if (REC) record_argmins(rec_r, md_r, out, m0, M0, k0, h0, m1, M1, k1, h1, d);
     } else {
         lam_new = MODE == FWD_SWEEP_BAR ? lam + aS : lam;
     }
@@ -397,7 +401,7 @@ __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, f
 
 template <int RMAX, int MODE, bool LOOP>
 __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64_t ntiles, int NL) {
-    constexpr bool UPD = MODE == FWD_UPDATE;
+    constexpr bool REC = MODE == FWD_UPDATE_REC, UPD = MODE == FWD_UPDATE || REC;
     constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
     extern __shared__ float lds_f[];
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -422,6 +426,7 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
             return v;
         };
         const rsrc_t lam_r = buf(T.lam + tc.ebase, nlev * 4), M_r = buf(T.M + tc.ebase, nlev * 4);
+        const rsrc_t rec_r = rec_buf<REC>(T, tc, nlev), md_r = mdiff_buf<REC>(T, tc, nlev);
         const int out0 = lane * nlev * 4;  // hop l stores at out0 + 4 l: in range for lane 0 only
         Lev c0 = level(0), c1 = level(1), c2 = level(2);
         u32x4 tpn[QM];
@@ -476,8 +481,8 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
             };
             const rsrc_t Fr = buf(T.F + c0.base, node_bytes(c0));
             with_count<1, QM>(groups(c0), [&](auto qc) {
-                fwd_hop_w<decltype(qc)::value, RMAX, MODE>(Fr, lam_r, M_r, Fb, Bst, tp, lane, out0 + 4 * l, c0, c1,
-                                                           lam, om, aS, prefetch);
+                fwd_hop_w<decltype(qc)::value, RMAX, MODE>(Fr, lam_r, M_r, rec_r, md_r, Fb, Bst, tp, lane,
+                                                           out0 + 4 * l, c0, c1, lam, om, aS, prefetch);
             });
             c0 = c1;
             c1 = c2;
@@ -493,11 +498,11 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
 // Backward hop of level l: bn = B of level l+1 (Wn its width: terminals at Wn, Wn+1), bc
 // receives B of level l, which also goes to global memory here, from registers.
 template <int Q, int RMAX, int MODE>
-__device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t lam_r, rsrc_t M_r, const float *bn,
-                                          float *bc, const u32x4 (&tp)[RMAX / 4], const f32x4 (&fn)[RMAX / 4],
-                                          int lane, int out, const Lev &c0, int Wn, float lam, float om, float aS,
-                                          int e) {
-    constexpr bool UPD = MODE == BWD_UPDATE, MM = MODE == BWD_MM;
+__device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t lam_r, rsrc_t M_r, rsrc_t rec_r,
+                                          rsrc_t md_r, const float *bn, float *bc, const u32x4 (&tp)[RMAX / 4],
+                                          const f32x4 (&fn)[RMAX / 4], int lane, int out, const Lev &c0, int Wn,
+                                          float lam, float om, float aS, int e) {
+    constexpr bool REC = MODE == BWD_UPDATE_REC, UPD = MODE == BWD_UPDATE || REC, MM = MODE == BWD_MM;
     constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM || MODE == BWD_STORE_BAR;
     constexpr bool STOREB = UPD || MODE == BWD_STORE || MODE == BWD_STORE_BAR;
     constexpr int QM = RMAX / 4;
@@ -522,21 +527,29 @@ __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t 
     float lam_new = lam_use;
     if (NEEDF) {
         float m0 = kInf, m1 = kInf;
+        int k0 = INT_MAX, k1 = INT_MAX, h0 = 0, h1 = 0;  // recording: first node attaining the lane's min
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                m0 = fminf(m0, fn[q][j] + b0[q][j]);
-                m1 = fminf(m1, fn[q][j] + b1[q][j]);
+                const float v0 = fn[q][j] + b0[q][j], v1 = fn[q][j] + b1[q][j];
+                if (REC) argmin_step(v0, m0, q * 256 + (l16 >> 2) + j, (int)(t[q][j] & 0xFFFFu), k0, h0);
+                if (REC) argmin_step(v1, m1, q * 256 + (l16 >> 2) + j, (int)(t[q][j] >> 16), k1, h1);
+                m0 = fminf(m0, v0);
+                m1 = fminf(m1, v1);
             }
+        const float lm0 = m0, lm1 = m1;
         m0 = team_min<64>(m0);
         m1 = team_min<64>(m1);
+        const float M1 = m1;
         m1 += lam_use;
         if (UPD) {
-            const float Mn = om * (m1 - m0);
+            const float d = m1 - m0;
+            const float Mn = om * d;
             lam_new = lam - Mn + aS;
             st1(lam_r, out, lam_new);
             st1(M_r, out, Mn);
+            if (REC) record_argmins(rec_r, md_r, out, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
         } else if (lane == 0) {
             const int ce = T.slot2canon[e];
             T.out0[ce] = m0;
@@ -564,7 +577,7 @@ __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t 
 
 template <int RMAX, int MODE, bool LOOP>
 __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64_t ntiles, int NL) {
-    constexpr bool UPD = MODE == BWD_UPDATE, MM = MODE == BWD_MM;
+    constexpr bool REC = MODE == BWD_UPDATE_REC, UPD = MODE == BWD_UPDATE || REC, MM = MODE == BWD_MM;
     constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM || MODE == BWD_STORE_BAR;
     constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
     extern __shared__ float lds_f[];
@@ -590,6 +603,7 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
             return v;
         };
         const rsrc_t lam_r = buf(T.lam + tc.ebase, nlev * 4), M_r = buf(T.M + tc.ebase, nlev * 4);
+        const rsrc_t rec_r = rec_buf<REC>(T, tc, nlev), md_r = mdiff_buf<REC>(T, tc, nlev);
         const int out0 = lane * nlev * 4;  // hop l stores at out0 + 4 l: in range for lane 0 only
         Lev c0 = level(nlev - 1), cp = level(nlev - 2);  // levels l, l-1
         int Wn = 0;                                       // width of level l+1 (none below the last)
@@ -639,8 +653,8 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
             }
             const rsrc_t Br = buf(T.B + c0.base, node_bytes(c0));
             with_count<1, QM>(groups(c0), [&](auto qc) {
-                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, lam_r, M_r, bn, bc, tp, fv, lane, out0 + 4 * l, c0,
-                                                           Wn, lam, om, aS, tc.ebase + l);
+                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, lam_r, M_r, rec_r, md_r, bn, bc, tp, fv, lane,
+                                                           out0 + 4 * l, c0, Wn, lam, om, aS, tc.ebase + l);
             });
             wave_sync();
             cur ^= 1;
@@ -671,6 +685,8 @@ hipError_t fwd_dispatch_w(const DevTables &t, const ClassLaunch &c, int mode, hi
         hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_UPDATE, true>), dim3(c.grid_f), block, lds, s, t, c.tile0, c.ntiles, c.NL);
     else if (mode == FWD_UPDATE)
         hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_UPDATE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL);
+    else if (mode == FWD_UPDATE_REC)
+        hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_UPDATE_REC, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL);
     else if (mode == FWD_SWEEP_BAR)
         hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_SWEEP_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL);
     else
@@ -689,6 +705,7 @@ hipError_t bwd_dispatch_w(const DevTables &t, const ClassLaunch &c, int mode, hi
     }
     switch (mode) {
         case BWD_UPDATE: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_UPDATE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
+        case BWD_UPDATE_REC: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_UPDATE_REC, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
         case BWD_STORE: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_STORE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
         case BWD_EN_LAM: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_EN_LAM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
         case BWD_EN_BAR: hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_EN_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.NL); break;
@@ -700,6 +717,7 @@ hipError_t bwd_dispatch_w(const DevTables &t, const ClassLaunch &c, int mode, hi
 
 template <int P, int RMAX>
 hipError_t fwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
+    if (mode == FWD_UPDATE_REC) mode = FWD_UPDATE;  // narrow reverse sweeps form their argmins themselves
     const unsigned full = full_grid(c.ntiles, c.wpb_f);
     dim3 grid(full), block(64 * c.wpb_f);
     size_t lds = (size_t)c.wpb_f * lds_words_pass(P, c.WB, c.NL) * 4;
@@ -719,6 +737,7 @@ hipError_t fwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hi
 
 template <int P, int RMAX>
 hipError_t bwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
+    if (mode == BWD_UPDATE_REC) mode = BWD_UPDATE;  // narrow reverse sweeps form their argmins themselves
     const unsigned full = full_grid(c.ntiles, c.wpb_b);
     dim3 grid(full), block(64 * c.wpb_b);
     size_t lds = (size_t)c.wpb_b * lds_words_pass(P, c.WB, c.NL) * 4;

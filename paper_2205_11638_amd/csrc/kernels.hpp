@@ -15,11 +15,20 @@
 
 namespace dd {
 
-// forward: update pass; F sweep at lambda_bar (no update); F sweep at lambda (no update)
-enum FwdMode { FWD_UPDATE = 0, FWD_SWEEP_BAR = 1, FWD_SWEEP_LAM = 2 };
+// forward: update pass; F sweep at lambda_bar (no update); F sweep at lambda (no update); update
+// pass that also records each hop's min-marginal argmins (DevTables::mrec / mdiff)
+enum FwdMode { FWD_UPDATE = 0, FWD_SWEEP_BAR = 1, FWD_SWEEP_LAM = 2, FWD_UPDATE_REC = 3 };
 // backward: update pass; B sweep at lambda stored; energies at lambda; energies at lambda_bar;
-// min-marginals at lambda_bar; B sweep at lambda_bar stored
-enum BwdMode { BWD_UPDATE = 0, BWD_STORE = 1, BWD_EN_LAM = 2, BWD_EN_BAR = 3, BWD_MM = 4, BWD_STORE_BAR = 5 };
+// min-marginals at lambda_bar; B sweep at lambda_bar stored; update pass recording its argmins
+enum BwdMode {
+    BWD_UPDATE = 0,
+    BWD_STORE = 1,
+    BWD_EN_LAM = 2,
+    BWD_EN_BAR = 3,
+    BWD_MM = 4,
+    BWD_STORE_BAR = 5,
+    BWD_UPDATE_REC = 6
+};
 
 struct DevTables {
     // tile tables
@@ -48,6 +57,10 @@ struct DevTables {
     float *energies;          // [m] per-row E^j at the flushed multipliers
     float *en_lam;            // [m] per-row E^j at the current multipliers (from backward passes)
     float *out0, *out1;       // [edges] canonical min-marginal outputs
+    // recording update passes of one-wave diagrams, per edge slot: [2 slot] = lowest argmin node of
+    // m^0 | its lo child << 16, [2 slot + 1] = the same for m^1 and the hi child; mdiff = m^1 - m^0
+    int32_t *mrec;
+    float *mdiff;
 };
 
 struct ClassLaunch {
@@ -98,8 +111,9 @@ constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) 
 // one-wave diagrams (P = 64), pull form: staged B and the adjoints of two levels in node buffers
 // of RMAX rows + 64 slots, then the level table
 constexpr int lds_words_adj_B_w(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
-// one-wave diagrams, push form: cost, adjoint and staged B of a level, the list of arcs into
-// nonzero adjoints (key and child, arc value, child adjoint), then the level table
+// one-wave diagrams, push form: cost and adjoint of a level, a spare node buffer (the bids of an
+// overflowing list), the list of arcs into nonzero adjoints (key and child, arc value, child
+// adjoint), then the level table
 constexpr int kAdjListW = 64;
 constexpr int lds_words_adj_F_w(int RMAX, int NL) {
     return 3 * node_buf_w(RMAX) + 3 * kAdjListW + ((2 * NL + 3) & ~3);
@@ -123,6 +137,8 @@ struct AdjTables {
     float *dalpha, *domega; // accumulated over passes
     int32_t *rec_idx;       // [2 * slots] argmin node indices handed from one sweep to the other (-1: none)
     float *rec_val;         // [2 * slots] the adjoint values that go with them
+    const int32_t *mrec;    // the replayed (or stored) pass's argmin records (update sweeps of one-wave
+    const float *mdiff;     // diagrams), layout as in DevTables
 };
 
 enum AdjSweep { ADJ_F_UPDATE = 0, ADJ_F_FIXED = 1, ADJ_B_UPDATE = 2, ADJ_B_FIXED = 3 };
