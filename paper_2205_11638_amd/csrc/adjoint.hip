@@ -697,10 +697,11 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
 // Push-form sweep of one-wave diagrams (P = 64), levels l = L-1 .. 0, in the wide layout.  The
 // adjoint of F also lives on minimizing paths only (a node hands its adjoint to its argmin
 // parent arc), but a node's parents are known only to the level above, so every arc of level l
-// still looks up its child's adjoint; the few arcs into a nonzero one are listed (key 2k + beta,
-// child, arc value, child adjoint) and bid for their child with one lane per entry, in the
-// child's adjoint slot (its value is in the list by then), and the winners add into the level's
-// adjoint.  A list that overflows is bid and collected by the owning lanes instead.  F and its
+// still looks up its child's adjoint; the few nodes with an arc into a nonzero one are listed
+// (node, children, cost, the two child adjoints), and with one lane per entry their arcs bid 2k +
+// beta for their child, in the child's adjoint slot (its value is in the list by then); a node's
+// adjoint is the sum of the children it won.  A list that overflows is bid and collected by the
+// owning lanes instead.  F and its
 // adjoint have one buffer each: level l overwrites level l+1 once every value of level l+1 that
 // the hop needs has been read.  The update sweep takes the hop's argmin nodes, their children and
 // m^1 - m^0 from the records of the replayed (or stored) pass, so it reads no B at all.
@@ -721,8 +722,9 @@ struct AdjInF<false> {  // fixed side: the multiplier swept, dlambda_in so far, 
 };
 
 template <int Q, int RMAX, bool UPD>
-__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, uint32_t *lkw, float *lval, float *lfa,
-                                           const u32x4 (&tp)[RMAX / 4], const f32x4 (&fvi)[RMAX / 4], int lane,
+__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, int *lk, uint32_t *lt, float *lf,
+                                           float *la0, float *la1, const u32x4 (&tp)[RMAX / 4],
+                                           const f32x4 (&fvi)[RMAX / 4], int lane,
                                            const Lev &c0, int Wn, float lam_use, const AdjInF<UPD> &x,
                                            const AdjOut &o, int l, int cap) {
     constexpr int CAP = kAdjListW;
@@ -742,10 +744,10 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, u
             t[Q - 1][j] = dead;
             f[Q - 1][j] = kInf;
         }
-    // arcs into a child with a nonzero adjoint (terminal slots of Fa hold 0), in wave order;
-    // the first CAP go to the list; returns the number of such arcs
-    // (the node values are taken afresh, so nothing derived from them is computed ahead and
-    // held in registers)
+    // nodes with an arc into a child with a nonzero adjoint (terminal slots of Fa hold 0), in wave
+    // order; the first CAP go to the list (node, children, cost, the two child adjoints); returns
+    // how many there are (the node values are taken afresh, so nothing derived from them is
+    // computed ahead and held in registers)
     auto detect = [&]() {
         int n = 0;
         const int k4 = lane16(lane) >> 2;
@@ -756,21 +758,18 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, u
                 uint32_t tt = t[q][j];
                 float ff = f[q][j];
                 __asm__ volatile("" : "+v"(tt), "+v"(ff));
-#pragma unroll
-                for (int beta = 0; beta < 2; ++beta) {
-                    const int w = beta ? (int)(tt >> 16) : (int)(tt & 0xFFFFu);
-                    const float a = Fa[w];
-                    const bool nz = a != 0.f;
-                    const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
-                    const int pos = n + lanes_below(m);
-                    if (nz && pos < CAP) {
-                        const int key = 2 * (q * 256 + k4 + j) + beta;
-                        lkw[pos] = (uint32_t)key | ((uint32_t)w << 16);
-                        lval[pos] = beta ? ff + lam_use : ff;
-                        lfa[pos] = a;
-                    }
-                    n += (int)__builtin_popcountll(m);
+                const float a0 = Fa[(int)(tt & 0xFFFFu)], a1 = Fa[(int)(tt >> 16)];
+                const bool nz = a0 != 0.f || a1 != 0.f;
+                const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
+                const int pos = n + lanes_below(m);
+                if (nz && pos < CAP) {
+                    lk[pos] = q * 256 + k4 + j;
+                    lt[pos] = tt;
+                    lf[pos] = ff;
+                    la0[pos] = a0;
+                    la1[pos] = a1;
                 }
+                n += (int)__builtin_popcountll(m);
             }
         return n;
     };
@@ -780,18 +779,22 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, u
     const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
     int *Fai = (int *)Fa;
     if (n <= min(cap, CAP)) {
-        // the listed arcs whose value equals the child's cost bid for it, in the child's own
-        // adjoint slot (its value is in the list now)
+        // each listed arc whose value equals its child's cost bids 2k + beta for the child, in the
+        // child's own adjoint slot (its value is in the list now)
         const bool mine = lane < n;
-        const uint32_t kw = mine ? lkw[lane] : 0u;
-        const float v = mine ? lval[lane] : 0.f, a = mine ? lfa[lane] : 0.f;
-        const int key = (int)(kw & 0xFFFFu), w = (int)(kw >> 16);
-        const bool tight = mine && v == Fv[w];
-        if (tight) Fai[w] = INT_MAX;
+        const int k = mine ? lk[lane] : 0;
+        const uint32_t tt = mine ? lt[lane] : 0u;
+        const float ff = mine ? lf[lane] : 0.f, a0 = mine ? la0[lane] : 0.f, a1 = mine ? la1[lane] : 0.f;
+        const int lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
+        const bool t0 = mine && a0 != 0.f && ff == Fv[lo];
+        const bool t1 = mine && a1 != 0.f && ff + lam_use == Fv[hi];
+        if (t0) Fai[lo] = INT_MAX;
+        if (t1) Fai[hi] = INT_MAX;
         wave_sync();
-        if (tight) lds_imin(&Fai[w], key);
+        if (t0) lds_imin(&Fai[lo], 2 * k);
+        if (t1) lds_imin(&Fai[hi], 2 * k + 1);
         wave_sync();
-        const bool won = tight && Fai[w] == key;
+        const bool w0 = t0 && Fai[lo] == 2 * k, w1 = t1 && Fai[hi] == 2 * k + 1;
         wave_sync();  // a lane's node of level l may share a slot with another lane's child
         // level l replaces level l+1 (everything read from it is in registers now)
 #pragma unroll
@@ -800,10 +803,9 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, u
             lds4(Fa, l16 + q * 1024) = zero4;
         }
         wave_sync();
-        if (won) {
-            lds_fadd(&Fa[key >> 1], a);
-            if (key & 1) hisum = a;
-        }
+        // a node is listed once: its adjoint is the sum of the children it won
+        if (w0 || w1) Fa[k] = (w0 ? a0 : 0.f) + (w1 ? a1 : 0.f);
+        if (w1) hisum = a1;
     } else {
         // more arcs than the list holds: every lane bids for its own arcs (bids in the spare
         // buffer) and collects its nodes' adjoints
@@ -894,9 +896,10 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
     float *Fv = lds_f + (size_t)wave * lds_words_adj_F_w(RMAX, NL);
     float *Fa = Fv + NB;
     float *spare = Fa + NB;
-    uint32_t *lkw = (uint32_t *)(spare + NB);
-    float *lval = (float *)(lkw + kAdjListW), *lfa = lval + kAdjListW;
-    int *meta = (int *)(lfa + kAdjListW);
+    int *lk = (int *)(spare + NB);
+    uint32_t *lt = (uint32_t *)(lk + kAdjListW);
+    float *lf = (float *)(lt + kAdjListW), *la0 = lf + kAdjListW, *la1 = la0 + kAdjListW;
+    int *meta = (int *)(la1 + kAdjListW);
     int *off = meta + NL;
     const TileCtx tc = tile_ctx(T, tile);
     preload_meta<1>(T, tc, lane, meta, off);
@@ -983,7 +986,7 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         if constexpr (!UPD)
             if (!use_rec) xu.i0 = xu.i1 = -1;
         with_count<1, QM>(groups(c0), [&](auto qc) {
-            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, spare, lkw, lval, lfa, tp, fv, lane, c0, Wn, lam_use,
+            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, spare, lk, lt, lf, la0, la1, tp, fv, lane, c0, Wn, lam_use,
                                                        xu, o, l, cap);
         });
         wave_sync();
