@@ -247,6 +247,48 @@ def test_dense_routing_matches_listed_routing(case):
         close(x, y, name)
 
 
+def test_knapsack_full_reverse_mode():
+    """Reverse mode on the full 2,000,000-variable knapsack program in the benchmark's launch
+    configuration (one-wave diagrams: sparse routing, recorded argmins).  Rows cannot be sampled
+    here (dM_in sums over every row of a variable), so the checks are those that hold at any size:
+    Euler's identity for each pass adjoint, <d_c, c> = LB for the unrolled gradient, and the stored
+    trajectory against checkpoints every iteration, bit for bit."""
+    import torch
+    w = synth.workload("knapsack")
+    p = w["problem"]
+    say(f"knapsack full reverse mode E={p.nnz}: compiling")
+    inst, _, _ = make_instance(p, f32(w["omega"]), f32(w["alpha_hat"]))
+    assert any(s["P"] == 64 for s in inst.launch_shapes())
+    rng = np.random.default_rng(31)
+    dev = lambda a: torch.tensor(np.asarray(a, np.float32), device="cuda")
+    inst.run(2)
+    for direction in (0, 1):
+        lam_in, M_in = inst.get_state()
+        li, mi = host(lam_in), host(M_in)
+        dlo, dmo = f32(rng.normal(size=p.nnz)), f32(rng.normal(size=p.nnz))
+        say(f"  pass vjp dir {direction}")
+        dli, dmi, da, dw = (host(t) for t in inst.pass_vjp(direction, lam_in, M_in, dev(dlo), dev(dmo)))
+        lam_o, M_o = (host(t) for t in inst.get_state())
+        for a in (dli, dmi, da, dw):
+            assert np.isfinite(a).all()
+        terms = np.concatenate([dli * li, dmi * mi])
+        euler_close(terms.sum(), dlo @ lam_o + dmo @ M_o, np.abs(terms).sum(), f"dir {direction}")
+    say("  unrolled T=2, checkpoints every iteration and stored")
+    lb1 = inst.forward_unrolled(2, 1)
+    g1 = [host(t) for t in inst.backward(1.0)]
+    lbs = inst.forward_unrolled(2, -1)
+    gs = [host(t) for t in inst.backward(1.0)]
+    assert lbs == lb1
+    for a, b, name in zip(g1, gs, ("d_omega", "d_alpha", "d_c")):
+        assert np.isfinite(a).all()
+        np.testing.assert_array_equal(a, b, err_msg=name)
+    dc = g1[2]
+    c = f32(p.c)
+    euler_close(dc @ c, lb1, np.abs(dc * c).sum(), "<d_c, c> = LB")
+    del inst
+    torch.cuda.synchronize()
+
+
 def test_gm_mini_unrolled_gradient(orc):
     """The 50-assignment-variable graph-matching instance whose oracle gradient is pinned by
     central differences on every coordinate; T = 20, checkpoints every 5."""
