@@ -1005,16 +1005,14 @@ int save_state(dd_instance *h, std::vector<float *> &L, std::vector<float *> &Mv
         L.push_back(a);
         Mv.push_back(b);
     }
-    int st = copy_slots(h, L[i], h->T.lam, s);
-    if (st) return st;
-    return copy_slots(h, Mv[i], h->T.M, s);
+    HIP_TRY(launch_copy2(h->T.lam, L[i], h->T.M, Mv[i], h->edge_slots, s));
+    return DD_OK;
 }
 
 int load_state(dd_instance *h, const std::vector<float *> &L, const std::vector<float *> &Mv, size_t i,
                hipStream_t s) {
-    int st = copy_slots(h, h->T.lam, L[i], s);
-    if (st) return st;
-    return copy_slots(h, h->T.M, Mv[i], s);
+    HIP_TRY(launch_copy2(L[i], h->T.lam, Mv[i], h->T.M, h->edge_slots, s));
+    return DD_OK;
 }
 
 }  // namespace
@@ -1191,19 +1189,23 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     HIP_TRY(launch_adj_deferred(h->var_ptr, h->var_slots, h->g, h->dMA, (int)h->n, h->var_team, s));
     float *dl = h->dlamA, *dm = h->dMA, *dl2 = h->dlamB, *dm2 = h->dMB;
     if (stored) {
-        // every pass from its stored output state and node costs: no recomputation, no replay
+        // every pass from its stored output state and node costs: no recomputation, no replay, no
+        // copy (the tables point at the stored arrays, which the reverse sweeps only read)
+        float *own_lam = h->T.lam, *own_M = h->T.M;
         for (int t = T - 1; t >= 0 && st == DD_OK; --t) {
             h->T.F = h->trF[t];
             h->T.B = h->trB[t + 1];  // the backward pass of iteration t
-            if ((st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s)) ||
-                (st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1],
+            h->T.lam = h->tr_lam[2 * t + 2];
+            h->T.M = h->tr_M[2 * t + 2];
+            if ((st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1],
                                h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1])))
                 break;
             std::swap(dl, dl2);
             std::swap(dm, dm2);
             h->T.B = h->trB[t];  // its forward pass
-            if ((st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)) ||
-                (st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t], h->tr_mrec[2 * t],
+            h->T.lam = h->tr_lam[2 * t + 1];
+            h->T.M = h->tr_M[2 * t + 1];
+            if ((st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t], h->tr_mrec[2 * t],
                                h->tr_mdiff[2 * t])))
                 break;
             std::swap(dl, dl2);
@@ -1211,6 +1213,8 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
         }
         h->T.F = h->F0;
         h->T.B = h->B0;
+        h->T.lam = own_lam;
+        h->T.M = own_M;
         if (st) return st;
     }
     for (int seg = stored ? -1 : nseg - 1; seg >= 0; --seg) {

@@ -809,6 +809,15 @@ __global__ void k_init_lambda(const int32_t *__restrict__ canon2slot, const int3
     M[s] = 0.f;
 }
 
+// two same-length copies in one launch (a solver state: multipliers and M)
+__global__ void k_copy2(const float *__restrict__ a, float *__restrict__ ad, const float *__restrict__ b,
+                        float *__restrict__ bd, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        ad[i] = a[i];
+        bd[i] = b[i];
+    }
+}
+
 __global__ void k_scatter(const int32_t *__restrict__ canon2slot, const float *__restrict__ src, float *dst,
                           int64_t E) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -993,6 +1002,13 @@ hipError_t launch_init_lambda(const int32_t *canon2slot, const int32_t *evar, co
                               float *lam, float *M, int64_t E, hipStream_t s) {
     if (E <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_init_lambda, dim3(blocks_for(E, 256)), dim3(256), 0, s, canon2slot, evar, var_ptr, c, lam, M, E);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy2(const float *a, float *ad, const float *b, float *bd, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned nb = std::min<unsigned>(blocks_for(n, 256), 8192u);
+    hipLaunchKernelGGL(k_copy2, dim3(nb), dim3(256), 0, s, a, ad, b, bd, n);
     return hipGetLastError();
 }
 

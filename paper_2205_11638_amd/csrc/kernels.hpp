@@ -190,6 +190,8 @@ hipError_t launch_init_lambda(const int32_t *canon2slot, const int32_t *evar, co
                               float *lam, float *M, int64_t E, hipStream_t s);
 // dst[canon2slot[e]] = src[e]
 hipError_t launch_scatter(const int32_t *canon2slot, const float *src, float *dst, int64_t E, hipStream_t s);
+// ad[i] = a[i], bd[i] = b[i] for i < n (one launch)
+hipError_t launch_copy2(const float *a, float *ad, const float *b, float *bd, int64_t n, hipStream_t s);
 // dst[e] = src[canon2slot[e]] (+ add[canon2slot[e]] when add is not NULL)
 hipError_t launch_gather(const int32_t *canon2slot, const float *src, float *dst, int64_t E, const float *add,
                          hipStream_t s);
