@@ -82,7 +82,10 @@ typedef struct {
     int32_t adj_route_dense;/* nonzero: the reverse sweeps of one-wave diagrams route every level node by
                                node instead of through their per-level lists of nonzero adjoints (the
                                path taken by levels whose lists overflow); for checking that path */
-    int32_t reserved[2];
+    int32_t adj_replay;     /* nonzero: the checkpointed backward sweep recomputes each segment's pass
+                               inputs and replays every pass for its adjoint instead of storing the
+                               segment's node costs (no device memory beyond the checkpoints) */
+    int32_t reserved[1];
 } dd_options;
 
 typedef struct {
@@ -181,8 +184,11 @@ int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *l
 /* Gradient of dlb * LB(after the recorded T iterations) with respect to omega, alpha and c:
  * the seed dLB/dlambda_bar is the argmin assignment of every row (Sec. "Loss"), the flush
  * lambda_bar = lambda + alpha*S is differentiated, then every pass in reverse with Alg. 2
- * (each segment between checkpoints is recomputed; every pass is replayed bit for bit to
- * recover its node costs), and finally lambda_0 = c/|J_i|; a variable in no row contributes
+ * (each segment between checkpoints is recomputed, keeping its node costs, its states and its
+ * passes' argmins on the device when 2K + 1 node-cost arrays fit -- they stay allocated with the
+ * instance -- or else, and always with the adj_replay option, replaying every pass bit for bit
+ * to recover them; the results are the same bits), and finally lambda_0 = c/|J_i|; a variable
+ * in no row contributes
  * dlb * [c_i < 0].  Subgradients at ties: lo arcs before hi arcs, lower node indices first.
  * Outputs are device arrays (may be NULL): d_omega, d_alpha [edges] canonical, d_c [n].
  * Leaves the solver at the final state.  DD_E_STATE without a valid record. */

@@ -36,7 +36,7 @@ class dd_problem(C.Structure):
 class dd_options(C.Structure):
     _fields_ = [("nodes_per_lane", C.c_int32), ("waves_per_block", C.c_int32), ("ckpt_every", C.c_int32),
                 ("lds_budget", C.c_int32), ("no_graphs", C.c_int32), ("adj_route_dense", C.c_int32),
-                ("reserved", C.c_int32 * 2)]
+                ("adj_replay", C.c_int32), ("reserved", C.c_int32 * 1)]
 
 
 class dd_stats(C.Structure):
@@ -187,20 +187,21 @@ def compile_row(prob, row):
     return w[:length], arcs[:nodes.value]
 
 
-def _options(nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0, graphs=True, adj_route_dense=False):
+def _options(nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0, graphs=True, adj_route_dense=False,
+             adj_replay=False):
     return dd_options(int(nodes_per_lane), int(waves_per_block), int(ckpt_every), int(lds_budget),
-                      0 if graphs else 1, 1 if adj_route_dense else 0)
+                      0 if graphs else 1, 1 if adj_route_dense else 0, 1 if adj_replay else 0)
 
 
 class Instance:
     """A binary program resident on the current GPU (see include/dd.h for the semantics)."""
 
     def __init__(self, prob, nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0, graphs=True,
-                 adj_route_dense=False):
+                 adj_route_dense=False, adj_replay=False):
         import torch
         L_ = lib()
         pa = _ProblemArgs(prob)
-        opt = _options(nodes_per_lane, waves_per_block, lds_budget, ckpt_every, graphs, adj_route_dense)
+        opt = _options(nodes_per_lane, waves_per_block, lds_budget, ckpt_every, graphs, adj_route_dense, adj_replay)
         h = C.c_void_p()
         # input validation and compilation run on the host before any HIP call
         stream = _stream() if torch.cuda.is_available() else None

@@ -554,6 +554,7 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     if (o.ckpt_every > 0) h->ckpt_default = o.ckpt_every;
     h->use_graphs = o.no_graphs == 0;
     h->adj_dense = o.adj_route_dense != 0;
+    h->adj_replay = o.adj_replay != 0;
     h->lds_budget = lds_budget;
     h->n = prob->n;
     h->m = m;
@@ -1050,42 +1051,112 @@ namespace {
 // into an array of its own and every backward pass B (the tables are pointed at them), and the
 // state before every pass is kept.  Afterwards the instance is back on its own arrays, with B as
 // the last pass left it, so any later call finds it as after an ordinary run.
-int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void *stream) {
-    hipStream_t s = (hipStream_t)stream;
-    const size_t nodes = (size_t)h->node_slots + 64, bytes = nodes * sizeof(float);
-    const size_t rec_bytes = (size_t)h->edge_slots * 12;  // argmin records of one pass
+// Device arrays for a stored run of n iterations: 2n + 1 node-cost arrays and each pass's argmin
+// records (the states before the passes are allocated as they are saved).  Bytes still to allocate:
+size_t stored_need(const dd_instance *h, int n) {
+    const size_t bytes = ((size_t)h->node_slots + 64) * sizeof(float), rec_bytes = (size_t)h->edge_slots * 12;
     size_t need = 0;
-    if ((int)h->trF.size() < T) need += ((size_t)T - h->trF.size()) * bytes;
-    if ((int)h->trB.size() < T + 1) need += ((size_t)T + 1 - h->trB.size()) * bytes;
-    if ((int)h->tr_mrec.size() < 2 * T) need += ((size_t)2 * T - h->tr_mrec.size()) * rec_bytes;
-    if (need) {
-        size_t free_b = 0, total_b = 0;
-        HIP_TRY(hipMemGetInfo(&free_b, &total_b));
-        const size_t margin = (size_t)2 << 30;
-        if (need + margin > free_b)
-            return fail(DD_E_OOM,
-                        "a stored trajectory of %d iterations needs %.1f GB more device memory (%.1f GB free): "
-                        "use checkpoints (ckpt_every >= 1)",
-                        T, (double)need / 1e9, (double)free_b / 1e9);
-    }
+    if ((int)h->trF.size() < n) need += ((size_t)n - h->trF.size()) * bytes;
+    if ((int)h->trB.size() < n + 1) need += ((size_t)n + 1 - h->trB.size()) * bytes;
+    if ((int)h->tr_mrec.size() < 2 * n) need += ((size_t)2 * n - h->tr_mrec.size()) * rec_bytes;
+    if ((int)h->tr_lam.size() < 2 * n + 1) need += ((size_t)2 * n + 1 - h->tr_lam.size()) * 8 * (size_t)h->edge_slots;
+    return need;
+}
+
+// whether they fit in the free device memory with a margin of 2 GiB
+bool stored_fits(const dd_instance *h, int n, size_t *need_out = nullptr, size_t *free_out = nullptr) {
+    const size_t need = stored_need(h, n);
+    size_t free_b = 0, total_b = 0;
+    if (need && hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
+    if (need_out) *need_out = need;
+    if (free_out) *free_out = free_b;
+    return need == 0 || need + ((size_t)2 << 30) <= free_b;
+}
+
+int stored_alloc(dd_instance *h, int n) {
+    const size_t nodes = (size_t)h->node_slots + 64;
     int st;
-    while ((int)h->trF.size() < T) {
+    while ((int)h->trF.size() < n) {
         float *p = nullptr;
         if ((st = h->alloc(&p, nodes))) return st;
         h->trF.push_back(p);
     }
-    while ((int)h->trB.size() < T + 1) {
+    while ((int)h->trB.size() < n + 1) {
         float *p = nullptr;
         if ((st = h->alloc(&p, nodes))) return st;
         h->trB.push_back(p);
     }
-    while ((int)h->tr_mrec.size() < 2 * T) {
+    while ((int)h->tr_mrec.size() < 2 * n) {
         int32_t *p = nullptr;
         float *q = nullptr;
         if ((st = h->alloc(&p, 2 * (size_t)h->edge_slots)) || (st = h->alloc(&q, (size_t)h->edge_slots))) return st;
         h->tr_mrec.push_back(p);
         h->tr_mdiff.push_back(q);
     }
+    return DD_OK;
+}
+
+// n iterations from the current state, with B at that state already in trB[0]: forward pass t
+// writes F into trF[t] and its backward pass B into trB[t + 1] (the tables are re-pointed), every
+// pass records its argmins, and the state before every pass is kept.  The tables are left on the
+// last arrays.
+int stored_passes(dd_instance *h, int n, hipStream_t s) {
+    int st = save_state(h, h->tr_lam, h->tr_M, 0, s);
+    for (int t = 0; t < n && st == DD_OK; ++t) {
+        h->T.F = h->trF[t];
+        h->T.B = h->trB[t];
+        if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t])) ||
+            (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)))
+            break;
+        h->T.B = h->trB[t + 1];
+        if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1]))) break;
+        st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s);
+    }
+    return st;
+}
+
+// The reverse of stored_passes: every pass's adjoint from its stored output state, node costs and
+// records -- no recomputation, no replay, no copy (the tables point at the stored arrays, which the
+// reverse sweeps only read).  The tables' multipliers and M are restored; the node-cost pointers
+// are left to the caller.
+int stored_reverse(dd_instance *h, int n, float *&dl, float *&dm, float *&dl2, float *&dm2, hipStream_t s) {
+    float *own_lam = h->T.lam, *own_M = h->T.M;
+    int st = DD_OK;
+    for (int t = n - 1; t >= 0 && st == DD_OK; --t) {
+        h->T.F = h->trF[t];
+        h->T.B = h->trB[t + 1];  // the backward pass of iteration t
+        h->T.lam = h->tr_lam[2 * t + 2];
+        h->T.M = h->tr_M[2 * t + 2];
+        if ((st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1],
+                           h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1])))
+            break;
+        std::swap(dl, dl2);
+        std::swap(dm, dm2);
+        h->T.B = h->trB[t];  // its forward pass
+        h->T.lam = h->tr_lam[2 * t + 1];
+        h->T.M = h->tr_M[2 * t + 1];
+        if ((st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t], h->tr_mrec[2 * t],
+                           h->tr_mdiff[2 * t])))
+            break;
+        std::swap(dl, dl2);
+        std::swap(dm, dm2);
+    }
+    h->T.lam = own_lam;
+    h->T.M = own_M;
+    return st;
+}
+
+int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void *stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bytes = ((size_t)h->node_slots + 64) * sizeof(float);
+    size_t need = 0, free_b = 0;
+    if (!stored_fits(h, T, &need, &free_b))
+        return fail(DD_E_OOM,
+                    "a stored trajectory of %d iterations needs %.1f GB more device memory (%.1f GB free): "
+                    "use checkpoints (ckpt_every >= 1)",
+                    T, (double)need / 1e9, (double)free_b / 1e9);
+    int st;
+    if ((st = stored_alloc(h, T))) return st;
     h->F0 = h->T.F;
     h->B0 = h->T.B;
     h->fwd_stored = false;
@@ -1097,17 +1168,7 @@ int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void 
         h->T.B = h->B0;
         return st;
     }
-    st = save_state(h, h->tr_lam, h->tr_M, 0, s);
-    for (int t = 0; t < T && st == DD_OK; ++t) {
-        h->T.F = h->trF[t];
-        h->T.B = h->trB[t];
-        if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t])) ||
-            (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)))
-            break;
-        h->T.B = h->trB[t + 1];
-        if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1]))) break;
-        st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s);
-    }
+    st = stored_passes(h, T, s);
     if (st == DD_OK) st = dd_lower_bound(h, lb, nullptr, stream);
     const hipError_t e = hipMemcpyAsync(h->B0, h->trB[T], bytes, hipMemcpyDeviceToDevice, s);
     h->T.F = h->F0;
@@ -1189,37 +1250,29 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     HIP_TRY(launch_adj_deferred(h->var_ptr, h->var_slots, h->g, h->dMA, (int)h->n, h->var_team, s));
     float *dl = h->dlamA, *dm = h->dMA, *dl2 = h->dlamB, *dm2 = h->dMB;
     if (stored) {
-        // every pass from its stored output state and node costs: no recomputation, no replay, no
-        // copy (the tables point at the stored arrays, which the reverse sweeps only read)
-        float *own_lam = h->T.lam, *own_M = h->T.M;
-        for (int t = T - 1; t >= 0 && st == DD_OK; --t) {
-            h->T.F = h->trF[t];
-            h->T.B = h->trB[t + 1];  // the backward pass of iteration t
-            h->T.lam = h->tr_lam[2 * t + 2];
-            h->T.M = h->tr_M[2 * t + 2];
-            if ((st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1],
-                               h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1])))
-                break;
-            std::swap(dl, dl2);
-            std::swap(dm, dm2);
-            h->T.B = h->trB[t];  // its forward pass
-            h->T.lam = h->tr_lam[2 * t + 1];
-            h->T.M = h->tr_M[2 * t + 1];
-            if ((st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t], h->tr_mrec[2 * t],
-                               h->tr_mdiff[2 * t])))
-                break;
-            std::swap(dl, dl2);
-            std::swap(dm, dm2);
-        }
+        st = stored_reverse(h, T, dl, dm, dl2, dm2, s);
         h->T.F = h->F0;
         h->T.B = h->B0;
-        h->T.lam = own_lam;
-        h->T.M = own_M;
         if (st) return st;
     }
+    // checkpoint segments: when the device holds a stored run of K iterations, each segment is
+    // recomputed into the stored-trajectory arrays and reversed like a stored trajectory (no pass
+    // replayed); otherwise the pass inputs are recomputed and each pass is replayed for its adjoint
+    float *own_F = h->T.F, *own_B = h->T.B;
+    const bool seg_store = !stored && !h->adj_replay && nseg > 0 && stored_fits(h, K) && stored_alloc(h, K) == DD_OK;
     for (int seg = stored ? -1 : nseg - 1; seg >= 0; --seg) {
         const int t0 = seg * K, t1 = std::min(T, t0 + K), np = 2 * (t1 - t0);
         if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)seg, s))) return st;
+        if (seg_store) {
+            h->T.B = h->trB[0];  // B at the checkpoint goes to the first stored array
+            st = recompute_B(h, s);
+            if (st == DD_OK) st = stored_passes(h, t1 - t0, s);
+            if (st == DD_OK) st = stored_reverse(h, t1 - t0, dl, dm, dl2, dm2, s);
+            h->T.F = own_F;
+            h->T.B = own_B;
+            if (st) return st;
+            continue;
+        }
         // a forward pass reads B at its input multipliers: the backward pass before it left
         // exactly that, so rebuild it from the checkpoint (same expression, same bits)
         if ((st = recompute_B(h, s))) return st;

@@ -99,6 +99,7 @@ struct dd_instance {
     hipGraphExec_t graph_one = nullptr, graph_chunk = nullptr;
     bool use_graphs = true;
     int adj_dense = 0;  // reverse sweeps of one-wave diagrams route node by node (check of that path)
+    bool adj_replay = false;  // checkpointed backward: replay passes instead of storing segments
 
     ~dd_instance() {
         if (graph_one) (void)hipGraphExecDestroy(graph_one);
