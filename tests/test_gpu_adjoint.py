@@ -68,6 +68,18 @@ def team_size_problem():
     return synth.generators._from_rows(n, -rng.uniform(0, 1, size=n), rows, "team-sizes")
 
 
+def unit_rows_problem():
+    """Rows sum x <= b with unit coefficients: their diagrams' level widths step through every value
+    up to about b, so levels of exactly 255, 256, 257, 511, 512 and 513 nodes occur (the boundaries
+    of the one-wave kernels' 256-node groups, where a level's terminal slots fall just past its
+    groups), next to 2-variable rows."""
+    rng, n = np.random.default_rng(21), 3000
+    rows = [(rng.choice(n, size=k, replace=False), np.ones(k, np.int64), -1, b) for k, b in ((600, 300), (1100, 520))]
+    for _ in range(60):
+        rows.append((rng.choice(n, size=2, replace=False), np.ones(2, np.int64), -1, 1))
+    return synth.generators._from_rows(n, -rng.uniform(0, 1, size=n), rows, "unit-rows")
+
+
 CASES = {
     "mixed0": lambda: mixed_problem(0),
     "mixed3": lambda: mixed_problem(3),
@@ -78,6 +90,7 @@ CASES = {
     "gm-full": lambda: synth.workload("gm")["problem"],
     "wide-24": lambda: wide_class_problem(24)[0],
     "wide-32": lambda: wide_class_problem(32)[0],
+    "unit-rows": unit_rows_problem,
 }
 
 
@@ -192,7 +205,7 @@ def test_stored_trajectory_matches_checkpoints(case, T):
 
 
 @pytest.mark.parametrize("case,T,K", [("gm-small", 5, 2), ("knapsack-small", 3, 2), ("wide-32", 3, 2),
-                                      ("mixed0", 5, 3)])
+                                      ("mixed0", 5, 3), ("unit-rows", 3, 2)])
 def test_segment_storage_matches_replay(case, T, K):
     """The checkpointed backward sweep keeps each recomputed segment's node costs, states and argmin
     records on the device and reverses it like a stored trajectory; with the adj_replay option it
@@ -227,13 +240,15 @@ def test_stored_trajectory_too_large_is_rejected():
     assert inst.lower_bound()[0] == lb  # nothing ran
 
 
-@pytest.mark.parametrize("case", ["knapsack-small", "team-sizes", "wide-24", "wide-32"])
+@pytest.mark.parametrize("case", ["knapsack-small", "team-sizes", "wide-24", "wide-32", "unit-rows"])
 def test_dense_routing_matches_listed_routing(case):
     """The reverse sweeps of one-wave diagrams route a level's nonzero adjoints through a per-level
     list, and a level whose list would overflow node by node from the owning lanes; the option
     adj_route_dense takes the second path on every level.  Both follow the same argmins, so pass
     VJPs and unrolled gradients agree up to the order of float sums (a node reached from several
-    parents or children, the hi-arc sums): 1e-5 relative, norm-wise and entry-wise with a floor."""
+    parents in the pull form, the hi-arc sums), whose rounding accumulates along the paths: a few
+    1e-5 relative on the ~1000-level unit-coefficient rows, so the bar is the gradient tests' 1e-4
+    (norm-wise and entry-wise with a floor).  A misrouted adjoint would be off by O(1)."""
     import torch
     p = CASES[case]()
     rng = np.random.default_rng(5)
@@ -245,11 +260,7 @@ def test_dense_routing_matches_listed_routing(case):
     assert any(s["P"] == 64 for s in a.launch_shapes())
     dev = lambda x: torch.tensor(np.asarray(x, np.float32), device="cuda")
 
-    def close(x, y, what):
-        x, y = np.asarray(x, np.float64), np.asarray(y, np.float64)
-        assert np.linalg.norm(x - y) <= 1e-5 * max(np.linalg.norm(y), 1e-6), (what, np.linalg.norm(x - y))
-        bad = np.abs(x - y) > np.maximum(1e-5 * np.abs(y), 1e-5 * max(np.abs(y).max(), 1e-6))
-        assert not bad.any(), (what, int(bad.sum()))
+    close = lambda x, y, what: close_grad(x, y, what)
 
     for direction in (0, 1):
         for inst in (a, b):
