@@ -438,10 +438,15 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
 
 int deferred(dd_instance *h, hipStream_t s) { return deferred_from(h, h->T.M, s); }
 
-int deferred_from(dd_instance *h, const float *M, hipStream_t s) {
-    int st = recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 12.0 * (double)h->n, s, [&] {
+// S_i of the given M (without alpha * S per edge)
+int deferred_sum(dd_instance *h, const float *M, hipStream_t s) {
+    return recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 12.0 * (double)h->n, s, [&] {
         return launch_deferred_sum(h->var_ptr, h->var_slots, M, h->S, (int)h->n, h->var_team, s);
     });
+}
+
+int deferred_from(dd_instance *h, const float *M, hipStream_t s) {
+    int st = deferred_sum(h, M, s);
     if (st) return st;
     return recorded(h, "k_edge_alpha_s", 16.0 * (double)h->edge_slots, s, [&] {
         return launch_edge_alpha_s(h->T.evar, h->alpha, h->S, h->aS, h->edge_slots, s);
@@ -958,7 +963,9 @@ int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out
              const int32_t *mrec_src = nullptr, const float *mdiff_src = nullptr) {
     const bool fresh = lam_src != nullptr;
     if (fresh && (!mrec_src || !mdiff_src)) return fail(DD_E_ARG, "internal: a pass adjoint needs the pass's records");
-    int st = deferred_from(h, fresh ? M_src : h->T.M, s);  // S and alpha*S of the pass-input M
+    // S of the pass-input M (per edge for the update sweeps) and, for the replayed update pass, alpha*S;
+    // the reverse sweeps read no alpha*S, and every later reader of it recomputes it from its state
+    int st = fresh ? deferred_sum(h, M_src, s) : deferred_from(h, h->T.M, s);
     if (st) return st;
     st = recorded(h, "k_edge_S", 12.0 * (double)h->edge_slots, s,
                   [&] { return launch_edge_S(h->T.evar, h->S, h->Se, h->edge_slots, s); });
