@@ -18,6 +18,8 @@
 // parent arc whose value equals F_{l+1}(w) bids with (node index, lo before hi) in LDS and the
 // lowest bid wins, so each minimum has exactly one argmin).  Argmin tests are exact float
 // equalities: the stored costs and the recomputed candidates come from the same expressions.
+// The argmin nodes of each hop's two min-marginals (lowest index on ties), their children and
+// m^1 - m^0 are recorded by the update pass that the sweeps reverse (its recording variant).
 // Contributions from one sweep to the other side travel as per-edge records
 // (two node indices, two values), not as a dense per-node array.
 #include <hip/hip_runtime.h>
@@ -42,11 +44,13 @@ struct AdjEdge {
     float dl;
     int i0, i1;
     float v0, v1;
+    uint32_t kc0, kc1;  // update sweeps: the pass's argmin node of m^0 | its lo child << 16, same for m^1 / hi
+    float d;            // and m^1 - m^0 as the pass formed it
 };
 
 template <bool UPD>
 __device__ __forceinline__ AdjEdge adj_edge(const DevTables &T, const AdjTables &A, int e, bool bar, bool rec) {
-    AdjEdge x{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, -1, 0.f, 0.f};
+    AdjEdge x{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, -1, 0.f, 0.f, 0u, 0u, 0.f};
     if (UPD) {
         x.lam_use = T.lam[e];
         x.lam_old = A.lam_in[e];
@@ -57,6 +61,9 @@ __device__ __forceinline__ AdjEdge adj_edge(const DevTables &T, const AdjTables 
         x.S = A.Se[e];
         x.da = A.dalpha[e];
         x.dw = A.domega[e];
+        x.kc0 = (uint32_t)A.mrec[2 * e];
+        x.kc1 = (uint32_t)A.mrec[2 * e + 1];
+        x.d = A.mdiff[e];
     } else {
         x.lam_use = A.lam_src[e];
         if (bar) x.lam_use = x.lam_use + T.aS[e];
@@ -73,9 +80,10 @@ __device__ __forceinline__ AdjEdge adj_edge(const DevTables &T, const AdjTables 
 
 // ------------------------------------------------------------------------------------------
 // Push-form sweep (F side), against the level order: l = L-1 .. 0.  Every global operand of
-// hop l-1 (topology, F, B of level l, edge data) is loaded during hop l.
+// hop l-1 (topology, F of level l-1, edge data) is loaded during hop l; the update sweep takes
+// the hop's argmins from the pass's records.
 // LDS per wave: Fv, Fa (cost and adjoint of level l+1, overwritten by level l at the end of
-// the hop), bid (ints), Bst (B of level l+1, update sweeps), then the level table.
+// the hop), bid (ints), then the level table.
 // ------------------------------------------------------------------------------------------
 template <int P, int RMAX, bool UPD>
 // (the fixed-side variant is asked for 3 waves per SIMD: measured faster; the update variant would spill)
@@ -90,8 +98,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!UPD && RMA
     float *Fv = lds_f + (size_t)wave * lds_words_adj_F(P, WB, NL);
     float *Fa = Fv + WB * G;
     int *bid = (int *)(Fa + WB * G);
-    float *Bst = (float *)(bid + WB * G);
-    int *meta = (int *)(Bst + WB * G);
+    int *meta = bid + WB * G;
     int *off = meta + NL * G;
     const TileCtx tc = tile_ctx(T, tile);
     preload_meta<G>(T, tc, lane, meta, off);
@@ -109,12 +116,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!UPD && RMA
     const int mine = p * G + g;
     Lev c0 = level(nlev - 1), c1{0, 0, 0};  // levels l and l+1 (terminals only below the last level)
     uint32_t tpn[RMAX];
-    float fvn[RMAX], bvn[RMAX];
+    float fvn[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
         tpn[r] = r < c0.R ? T.topo[c0.base + r * 64 + lane] : 0u;
         fvn[r] = r < c0.R ? T.F[c0.base + r * 64 + lane] : kInf;
-        bvn[r] = 0.f;
     }
     AdjEdge xn = adj_edge<UPD>(T, A, tc.ebase + (nlev - 1) * G + g, false, true);
     for (int l = nlev - 1; l >= 0; --l) {
@@ -132,11 +138,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!UPD && RMA
                 tp[r] = dead;
                 fv[r] = kInf;
             }
-            if (UPD && r < c1.R) Bst[mine + r * P * G] = bvn[r];  // B of level l+1
-        }
-        if (UPD && p == 0) {
-            Bst[Wn * G + g] = kInf;
-            Bst[(Wn + 1) * G + g] = 0.f;
         }
         // prefetch hop l-1: topology and F of level l-1, B of level l, edge data of level l-1
         const Lev cp = level(l - 1);
@@ -144,7 +145,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!UPD && RMA
         for (int r = 0; r < RMAX; ++r) {
             tpn[r] = r < cp.R ? T.topo[cp.base + r * 64 + lane] : 0u;
             fvn[r] = r < cp.R ? T.F[cp.base + r * 64 + lane] : kInf;
-            if (UPD) bvn[r] = r < c0.R ? T.B[c0.base + r * 64 + lane] : 0.f;
         }
         if (l > 0) xn = adj_edge<UPD>(T, A, e - G, false, true);
         wave_sync();
@@ -175,34 +175,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!UPD && RMA
         }
         hisum = team_sum<P>(hisum);
         if (UPD) {
-            // min-marginals of this hop again (same expressions as the pass), then their argmins
-            float m0 = kInf, m1 = kInf;
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                if (r < c0.R) {
-                    m0 = fminf(m0, fv[r] + Bst[(int)(tp[r] & 0xFFFFu) * G + g]);
-                    m1 = fminf(m1, fv[r] + Bst[(int)(tp[r] >> 16) * G + g]);
-                }
-            }
-            m0 = team_min<P>(m0);
-            m1 = team_min<P>(m1);
-            // lowest argmin node and its child in one key: node << 12 | child code
-            int key0 = INT_MAX, key1 = INT_MAX;
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                if (r < c0.R) {
-                    const int k = r * P + p, lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
-                    if (fv[r] + Bst[lo * G + g] == m0) key0 = min(key0, (k << 12) | lo);
-                    if (fv[r] + Bst[hi * G + g] == m1) key1 = min(key1, (k << 12) | hi);
-                }
-            }
-            key0 = team_min_i<P>(key0);
-            key1 = team_min_i<P>(key1);
+            // the hop's argmin nodes of the two min-marginals and their children: the pass's records
             if (c0.W > 0) {
-                const int k0 = key0 >> 12, k1 = key1 >> 12, ch0 = key0 & 0xFFF, ch1 = key1 & 0xFFF;
+                const int k0 = (int)(x.kc0 & 0xFFFFu), k1 = (int)(x.kc1 & 0xFFFFu);
+                const int ch0 = (int)(x.kc0 >> 16), ch1 = (int)(x.kc1 >> 16);
                 const float dlam_new = x.dlo + hisum;
                 const float dM = x.dMo - dlam_new;
-                const float diff = (m1 + x.lam_old) - m0;  // m^1 - m^0 as the pass formed it
+                const float diff = x.d;  // m^1 - m^0 as the pass formed it
                 const float dm1 = x.om * dM, dm0 = -dm1;
                 if (p == 0) {
                     A.dlam_in[e] = dlam_new + dm1;  // identity path + the hi arc of m^1 itself
@@ -249,7 +228,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!UPD && RMA
 
 // ------------------------------------------------------------------------------------------
 // Pull-form sweep (B side), along the level order: l = 0 .. L-1, with the operands of hop l+1
-// (topology and F of level l+1, B of level l+2, edge data) loaded during hop l.
+// (topology of level l+1, B of level l+2, edge data) loaded during hop l; the update sweep takes
+// the hop's argmins from the pass's records.
 // LDS per wave: Bst (B of level l+1), Ba[2] (adjoints of levels l / l+1), level table.
 // seed != 0: the adjoint of B(root) is `seed` (the lower bound's own gradient).
 // ------------------------------------------------------------------------------------------
@@ -288,11 +268,10 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
     }
     Lev c0 = level(0), c1 = level(1);
     uint32_t tpn[RMAX];
-    float fvn[RMAX], bvn[RMAX];
+    float bvn[RMAX];
 #pragma unroll
     for (int r = 0; r < RMAX; ++r) {
         tpn[r] = r < c0.R ? T.topo[c0.base + r * 64 + lane] : 0u;
-        fvn[r] = (UPD && r < c0.R) ? T.F[c0.base + r * 64 + lane] : 0.f;
         bvn[r] = r < c1.R ? T.B[c1.base + r * 64 + lane] : 0.f;
     }
     AdjEdge xn = adj_edge<UPD>(T, A, tc.ebase + g, bar != 0, false);
@@ -309,16 +288,11 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
             if (pi1 >= 0) ba0[pi1 * G + g] += pv1;
         }
         uint32_t tp[RMAX];
-        float fv[RMAX];
         const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             tp[r] = tpn[r];
-            fv[r] = fvn[r];
-            if (r < c0.R && !in_level<P>(r, c0.R, lane, c0.W)) {
-                tp[r] = dead;
-                fv[r] = kInf;
-            }
+            if (r < c0.R && !in_level<P>(r, c0.R, lane, c0.W)) tp[r] = dead;
             if (r < c1.R) {
                 Bst[mine + r * P * G] = bvn[r];
                 ba1[mine + r * P * G] = 0.f;
@@ -328,12 +302,11 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
             Bst[Wn * G + g] = kInf;
             Bst[(Wn + 1) * G + g] = 0.f;
         }
-        // prefetch hop l+1: topology and F of level l+1, B of level l+2, edge data of level l+1
+        // prefetch hop l+1: topology of level l+1, B of level l+2, edge data of level l+1
         const Lev c2 = level(l + 2);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             tpn[r] = r < c1.R ? T.topo[c1.base + r * 64 + lane] : 0u;
-            if (UPD) fvn[r] = r < c1.R ? T.F[c1.base + r * 64 + lane] : 0.f;
             bvn[r] = r < c2.R ? T.B[c2.base + r * 64 + lane] : 0.f;
         }
         if (l + 1 < nlev) xn = adj_edge<UPD>(T, A, e + G, bar != 0, false);
@@ -362,31 +335,12 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
         }
         hisum = team_sum<P>(hisum);
         if (UPD) {
-            float m0 = kInf, m1 = kInf;
-#pragma unroll
-            for (int r = 0; r < RMAX; ++r) {
-                if (r < c0.R) {
-                    m0 = fminf(m0, fv[r] + Bst[(int)(tp[r] & 0xFFFFu) * G + g]);
-                    m1 = fminf(m1, fv[r] + Bst[(int)(tp[r] >> 16) * G + g]);
-                }
-            }
-            m0 = team_min<P>(m0);
-            m1 = team_min<P>(m1);
-            int k0 = INT_MAX, k1 = INT_MAX;
-#pragma unroll
-            for (int r = RMAX - 1; r >= 0; --r) {
-                if (r < c0.R) {
-                    const int k = r * P + p;
-                    if (fv[r] + Bst[(int)(tp[r] & 0xFFFFu) * G + g] == m0) k0 = k;
-                    if (fv[r] + Bst[(int)(tp[r] >> 16) * G + g] == m1) k1 = k;
-                }
-            }
-            k0 = team_min_i<P>(k0);
-            k1 = team_min_i<P>(k1);
+            // the hop's argmin nodes of the two min-marginals: the pass's records
+            const int k0 = (int)(x.kc0 & 0xFFFFu), k1 = (int)(x.kc1 & 0xFFFFu);
             if (c0.W > 0) {
                 const float dlam_new = x.dlo + hisum;
                 const float dM = x.dMo - dlam_new;
-                const float diff = (m1 + x.lam_old) - m0;
+                const float diff = x.d;  // m^1 - m^0 as the pass formed it
                 const float dm1 = x.om * dM, dm0 = -dm1;
 #pragma unroll
                 for (int r = 0; r < RMAX; ++r) {

@@ -243,5 +243,21 @@ __device__ __forceinline__ rsrc_t mdiff_buf(const DevTables &T, const TileCtx &t
     else return buf(T.lam, 0);
 }
 
+
+// The same for a team of P lanes of a narrower tile (node k = r P + p): the lowest attaining node
+// and its child code are reduced as one key (node << 12 | child; nodes and child codes of these
+// tiles stay below 4096), and the team's first lane stores at its edge slot's offset off (4 bytes
+// per slot; other lanes pass an offset past the ne bytes of the tile's slots).
+template <int P>
+__device__ __forceinline__ void record_argmins_team(const DevTables &T, int ebase, int ne, int off, float lm0,
+                                                    float M0, int k0, int h0, float lm1, float M1, int k1, int h1,
+                                                    float d) {
+    const int key0 = team_min_i<P>(lm0 == M0 && k0 != INT_MAX ? (k0 << 12) | h0 : INT_MAX);
+    const int key1 = team_min_i<P>(lm1 == M1 && k1 != INT_MAX ? (k1 << 12) | h1 : INT_MAX);
+    st2(buf(T.mrec + 2 * (int64_t)ebase, 2 * ne), 2 * off, (uint32_t)(key0 >> 12) | ((uint32_t)(key0 & 0xFFF) << 16),
+        (uint32_t)(key1 >> 12) | ((uint32_t)(key1 & 0xFFF) << 16));
+    st1(buf(T.mdiff + ebase, ne), off, d);
+}
+
 }  // namespace dev
 }  // namespace dd

@@ -28,7 +28,7 @@ using namespace dev;
 template <int P, int RMAX, int MODE, bool LOOP>
 __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
-    constexpr bool UPD = MODE == FWD_UPDATE;
+    constexpr bool REC = MODE == FWD_UPDATE_REC, UPD = MODE == FWD_UPDATE || REC;
     extern __shared__ float lds_f[];
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int g = lane / P, p = lane % P;
@@ -108,25 +108,31 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
                 if (UPD) omn = T.omega[e];
             }
             float m0 = kInf, m1 = kInf;
+            int k0 = INT_MAX, k1 = INT_MAX, h0 = 0, h1 = 0;  // recording: first node attaining the lane's min
             const uint32_t dead = (uint32_t)c1.W | ((uint32_t)c1.W << 16);
     #pragma unroll
             for (int r = 0; r < RMAX; ++r) {
                 if (r < c0.R) {
                     if (!in_level<P>(r, c0.R, lane, c0.W)) tp[r] = dead;
                     if (UPD) {
-                        const float b0 = Bst[(int)(tp[r] & 0xFFFFu) * G + g];
-                        const float b1 = Bst[(int)(tp[r] >> 16) * G + g];
-                        m0 = fminf(m0, fv[r] + b0);
-                        m1 = fminf(m1, fv[r] + b1);
+                        const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
+                        const float v0 = fv[r] + Bst[lo * G + g], v1 = fv[r] + Bst[hi * G + g];
+                        if (REC) argmin_step(v0, m0, r * P + p, lo, k0, h0);
+                        if (REC) argmin_step(v1, m1, r * P + p, hi, k1, h1);
+                        m0 = fminf(m0, v0);
+                        m1 = fminf(m1, v1);
                     }
                 }
             }
             float lam_new;
             if (UPD) {
+                const float lm0 = m0, lm1 = m1;
                 m0 = team_min<P>(m0);
                 m1 = team_min<P>(m1);
+                const float M1 = m1;
                 m1 += lam;
-                const float Mn = om * (m1 - m0);
+                const float d = m1 - m0;
+                const float Mn = om * d;
                 const bool live = c0.W > 0;  // this team's diagram has a node at level l
                 lam_new = live ? lam - Mn + aS : lam;
                 // stored by the team's first lane through a resource over the tile's edges: the
@@ -134,6 +140,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
                 const int ne = nlev * G * 4, off = p == 0 && live ? (l * G + g) * 4 : ne;
                 st1(buf(T.lam + tc.ebase, ne), off, lam_new);
                 st1(buf(T.M + tc.ebase, ne), off, Mn);
+                if (REC) record_argmins_team<P>(T, tc.ebase, ne, off, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
             } else {
                 lam_new = MODE == FWD_SWEEP_BAR ? lam + aS : lam;  // sweep, no update
             }
@@ -165,7 +172,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
 template <int P, int RMAX, int MODE, bool LOOP>
 __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
-    constexpr bool UPD = MODE == BWD_UPDATE, MM = MODE == BWD_MM;
+    constexpr bool REC = MODE == BWD_UPDATE_REC, UPD = MODE == BWD_UPDATE || REC, MM = MODE == BWD_MM;
     constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM || MODE == BWD_STORE_BAR;
     constexpr bool STOREB = UPD || MODE == BWD_STORE || MODE == BWD_STORE_BAR;
     extern __shared__ float lds_f[];
@@ -242,6 +249,7 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                 if (UPD) omn = T.omega[e];
             }
             float m0 = kInf, m1 = kInf;
+            int k0 = INT_MAX, k1 = INT_MAX, h0 = 0, h1 = 0;  // recording: first node attaining the lane's min
             const uint32_t dead = (uint32_t)cn.W | ((uint32_t)cn.W << 16);
     #pragma unroll
             for (int r = 0; r < RMAX; ++r) {
@@ -249,27 +257,33 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                     if (!in_level<P>(r, c0.R, lane, c0.W)) tp[r] = dead;
                     if (NEEDF) {
                         // a lane past the level's end has two 0-terminal children: its cost is +inf
-                        const float b0 = bn[(int)(tp[r] & 0xFFFFu) * G + g];
-                        const float b1 = bn[(int)(tp[r] >> 16) * G + g];
-                        m0 = fminf(m0, fv[r] + b0);
-                        m1 = fminf(m1, fv[r] + b1);
+                        const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
+                        const float v0 = fv[r] + bn[lo * G + g], v1 = fv[r] + bn[hi * G + g];
+                        if (REC) argmin_step(v0, m0, r * P + p, lo, k0, h0);
+                        if (REC) argmin_step(v1, m1, r * P + p, hi, k1, h1);
+                        m0 = fminf(m0, v0);
+                        m1 = fminf(m1, v1);
                     }
                 }
             }
             const float lam_use = BAR ? lam + aS : lam;
             float lam_new = lam_use;
             if (NEEDF) {
+                const float lm0 = m0, lm1 = m1;
                 m0 = team_min<P>(m0);
                 m1 = team_min<P>(m1);
+                const float M1 = m1;
                 m1 += lam_use;
                 const bool live = c0.W > 0;  // this team's diagram has a node at level l
                 if (UPD) {
-                    const float Mn = om * (m1 - m0);
+                    const float d = m1 - m0;
+                    const float Mn = om * d;
                     lam_new = live ? lam - Mn + aS : lam_new;
                     // the team's first lane stores; other offsets fall outside the tile's edges
                     const int ne = nlev * G * 4, off = p == 0 && live ? (l * G + g) * 4 : ne;
                     st1(buf(T.lam + tc.ebase, ne), off, lam_new);
                     st1(buf(T.M + tc.ebase, ne), off, Mn);
+                    if (REC) record_argmins_team<P>(T, tc.ebase, ne, off, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
                 } else if (p == 0 && live) {
                     const int ce = T.slot2canon[tc.ebase + l * G + g];
                     T.out0[ce] = m0;
@@ -717,7 +731,6 @@ hipError_t bwd_dispatch_w(const DevTables &t, const ClassLaunch &c, int mode, hi
 
 template <int P, int RMAX>
 hipError_t fwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
-    if (mode == FWD_UPDATE_REC) mode = FWD_UPDATE;  // narrow reverse sweeps form their argmins themselves
     const unsigned full = full_grid(c.ntiles, c.wpb_f);
     dim3 grid(full), block(64 * c.wpb_f);
     size_t lds = (size_t)c.wpb_f * lds_words_pass(P, c.WB, c.NL) * 4;
@@ -726,6 +739,9 @@ hipError_t fwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hi
                            c.WB, c.NL);
     else if (mode == FWD_UPDATE)
         hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL);
+    else if (mode == FWD_UPDATE_REC)
+        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE_REC, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB,
+                           c.NL);
     else if (mode == FWD_SWEEP_BAR)
         hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_SWEEP_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB,
                            c.NL);
@@ -737,7 +753,6 @@ hipError_t fwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hi
 
 template <int P, int RMAX>
 hipError_t bwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
-    if (mode == BWD_UPDATE_REC) mode = BWD_UPDATE;  // narrow reverse sweeps form their argmins themselves
     const unsigned full = full_grid(c.ntiles, c.wpb_b);
     dim3 grid(full), block(64 * c.wpb_b);
     size_t lds = (size_t)c.wpb_b * lds_words_pass(P, c.WB, c.NL) * 4;
@@ -748,6 +763,7 @@ hipError_t bwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hi
     }
     switch (mode) {
         case BWD_UPDATE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        case BWD_UPDATE_REC: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE_REC, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
         case BWD_STORE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_STORE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
         case BWD_EN_LAM: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_LAM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
         case BWD_EN_BAR: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;

@@ -104,9 +104,9 @@ constexpr int lds_words_pass_c(int P, int RMAX, int WB, int NL) {
 #define DD_CLASSES(X) \
     X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(64, 8) X(64, 12) X(64, 16) X(64, 24) X(64, 32)
 
-// per wave of the adjoint sweeps: push form = cost and adjoint of one level, bids, staged B;
-// pull form = staged B and the adjoints of two levels; both + the level table
-constexpr int lds_words_adj_F(int P, int WB, int NL) { return 4 * WB * (64 / P) + NL * ((64 / P) + 1); }
+// per wave of the adjoint sweeps: push form = cost and adjoint of one level, bids; pull form =
+// staged B and the adjoints of two levels; both + the level table
+constexpr int lds_words_adj_F(int P, int WB, int NL) { return 3 * WB * (64 / P) + NL * ((64 / P) + 1); }
 constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) + NL * ((64 / P) + 1); }
 // one-wave diagrams (P = 64), pull form: staged B and the adjoints of two levels in node buffers
 // of RMAX rows + 64 slots, then the level table
