@@ -34,13 +34,13 @@ namespace {
 
 using namespace dev;
 
-// Per-edge inputs of one hop, loaded one hop ahead.  Update sweeps: the multipliers after
-// (lam_use) and before (lam_old) the replayed pass, the output adjoints, omega, alpha, S of
-// the variable, and the d_alpha / d_omega accumulated so far.  Fixed sweeps: the multiplier
-// the side was computed with, the dlambda_in accumulated by the update sweep, and the record
-// (two node indices and adjoints) handed over by the update sweep.
+// Per-edge inputs of one hop, loaded one hop ahead.  Update sweeps: the multiplier after the
+// pass (lam_use), the output adjoints, omega, alpha, S of the variable, the d_alpha / d_omega
+// accumulated so far, and the pass's argmin records.  Fixed sweeps: the multiplier the side was
+// computed with, the dlambda_in accumulated by the update sweep, and the record (two node
+// indices and adjoints) handed over by the update sweep.
 struct AdjEdge {
-    float lam_use, lam_old, dlo, dMo, om, al, S, da, dw;
+    float lam_use, dlo, dMo, om, al, S, da, dw;
     float dl;
     int i0, i1;
     float v0, v1;
@@ -50,10 +50,9 @@ struct AdjEdge {
 
 template <bool UPD>
 __device__ __forceinline__ AdjEdge adj_edge(const DevTables &T, const AdjTables &A, int e, bool bar, bool rec) {
-    AdjEdge x{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, -1, 0.f, 0.f, 0u, 0u, 0.f};
+    AdjEdge x{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, -1, -1, 0.f, 0.f, 0u, 0u, 0.f};
     if (UPD) {
         x.lam_use = T.lam[e];
-        x.lam_old = A.lam_in[e];
         x.dlo = A.dlam_out[e];
         x.dMo = A.dM_out[e];
         x.om = T.omega[e];

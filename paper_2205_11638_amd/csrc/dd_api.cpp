@@ -412,9 +412,8 @@ int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
         [&](const ClassLaunch &cl) { return algorithmic_bytes(fwd, mode, cl); });
 }
 
-// Reverse sweeps.  Bytes: update sweeps read topology, the swept side's cost and the staged
-// other side (12 B/node) and ~68 B of edge data, or, for one-wave diagrams, topology and the swept
-// side (8 B/node) and ~76 B of edge data with the pass's records; fixed sweeps 8 B/node, ~28 B/edge.
+// Reverse sweeps.  Bytes: topology and the swept side's cost (8 B/node) in both; update sweeps
+// ~76 B of edge data with the pass's argmin records, fixed sweeps ~28 B/edge.
 int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs, float seed, hipStream_t s) {
     const bool upd = which == ADJ_F_UPDATE || which == ADJ_B_UPDATE;
     const char *nm = which == ADJ_F_UPDATE || which == ADJ_F_FIXED ? "k_adj_F" : "k_adj_B";
@@ -430,9 +429,7 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
             return std::string(name);
         },
         [&](const ClassLaunch &cl) {
-            // one-wave update sweeps take the argmins from the pass's records instead of the other side
-            if (upd && cl.P == 64) return 8.0 * cl.nodes + 76.0 * cl.edges;
-            return upd ? 12.0 * cl.nodes + 68.0 * cl.edges : 8.0 * cl.nodes + 28.0 * cl.edges;
+            return upd ? 8.0 * cl.nodes + 76.0 * cl.edges : 8.0 * cl.nodes + 28.0 * cl.edges;
         });
 }
 
@@ -973,8 +970,7 @@ int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out
     // the pass-input multipliers: kept by the caller, or copied before the replay overwrites them
     if (!fresh && (st = copy_slots(h, h->lam_in, h->T.lam, s))) return st;
     AdjTables A{};
-    A.lam_in = fresh ? lam_src : h->lam_in;
-    A.lam_src = A.lam_in;
+    A.lam_src = fresh ? lam_src : h->lam_in;
     A.mrec = fresh ? mrec_src : h->mrec;
     A.mdiff = fresh ? mdiff_src : h->mdiff;
     A.dlam_out = dlam_out;

@@ -127,8 +127,7 @@ constexpr int lds_words_adj_B_c(int P, int RMAX, int WB, int NL) {
 
 // Arrays of the reverse sweeps (edge-slot indexed unless noted).
 struct AdjTables {
-    const float *lam_in;    // pass-input multipliers
-    const float *lam_src;   // multipliers of a fixed-side sweep (plus alpha*S when flushed)
+    const float *lam_src;   // multipliers of a fixed-side sweep: the pass input (plus alpha*S when flushed)
     const float *dlam_out;  // adjoint of the pass-output multipliers
     const float *dM_out;    // adjoint of the pass-output M
     const float *Se;        // S of each edge's variable (update sweeps)
