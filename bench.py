@@ -154,6 +154,32 @@ def features_leg(inst, stream):
     return out
 
 
+def queries_leg(inst, stream, reps=3):
+    """The two read-outs of the state on the main instance, each timed alone: the lower bound at
+    lambda_bar (deferred sums, one B sweep, per-row sums) and the min-marginals at lambda_bar
+    (deferred sums, an F sweep, a B sweep with the per-hop minima)."""
+    import torch
+
+    out = {}
+    for name, fn in (("lower_bound", inst.lower_bound), ("min_marginals", inst.min_marginals)):
+        fn()
+        inst.profile_begin(max_launches=64 * reps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        prof = inst.profile_end()
+        out[name] = {"ms": e0.elapsed_time(e1) / reps, "kernels": {
+            k: {"launches": n, "avg_ms": tot / n, "gbs_algorithmic": b / (tot / n) / 1e6}
+            for k, (n, tot, b) in prof.items()}}
+    log(f"[bench] queries: lower bound {out['lower_bound']['ms']:.2f} ms, "
+        f"min-marginals {out['min_marginals']['ms']:.2f} ms")
+    return out
+
+
 def other_workloads(stream):
     """The smaller configurations at their own iteration counts (graph replays), timed like the
     main step: T iterations + the lower bound, inputs resident."""
@@ -426,6 +452,7 @@ def main():
     value = arcs * T / (ms / 1e3)
     stream_gbs = stream_reference()
     log(f"[bench] stream reference (torch.add, 3 x 1 GiB): {stream_gbs:.1f} GB/s")
+    queries = queries_leg(inst, stream)
     feats = None if args.no_features else features_leg(inst, stream)
     adj = None
     if not args.no_adjoint:
@@ -472,6 +499,7 @@ def main():
                      "stream_reference_gbs": stream_gbs, "frac_of_stream_reference": achieved / stream_gbs},
         "hbm_frac_step": (sum(b * n for n, _, b in prof.values()) / args.steps) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "lower_bound": lb[0],
+        "queries": queries,
         "adjoint": adj,
         "features": feats,
         "batch": bat,

@@ -210,6 +210,7 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         }
         const int et = tc.ebase + (nlev - 1) * G + g;
         float lamn = T.lam[et], aSn = (UPD || BAR) ? T.aS[et] : 0.f, omn = UPD ? T.omega[et] : 0.f;
+        int cen = MM ? T.slot2canon[et] : 0;  // canonical edge of the min-marginals (padding slots: unused)
         int cur = 0;  // buffer holding B of level l+1 (terminals only, below the last level)
         if (p == 0) {
             buf0[g] = kInf;
@@ -218,6 +219,7 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         wave_sync();
         for (int l = nlev - 1; l >= 0; --l) {
             const float lam = lamn, om = omn, aS = aSn;
+            const int ce = cen;
             uint32_t tp[RMAX];
             float fv[RMAX];
     #pragma unroll
@@ -247,6 +249,7 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                 lamn = T.lam[e];
                 if (UPD || BAR) aSn = T.aS[e];
                 if (UPD) omn = T.omega[e];
+                if (MM) cen = T.slot2canon[e];
             }
             float m0 = kInf, m1 = kInf;
             int k0 = INT_MAX, k1 = INT_MAX, h0 = 0, h1 = 0;  // recording: first node attaining the lane's min
@@ -285,7 +288,6 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                     st1(buf(T.M + tc.ebase, ne), off, Mn);
                     if (REC) record_argmins_team<P>(T, tc.ebase, ne, off, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
                 } else if (p == 0 && live) {
-                    const int ce = T.slot2canon[tc.ebase + l * G + g];
                     T.out0[ce] = m0;
                     T.out1[ce] = m1;
                 }
@@ -515,7 +517,7 @@ template <int Q, int RMAX, int MODE>
 __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t lam_r, rsrc_t M_r, rsrc_t rec_r,
                                           rsrc_t md_r, const float *bn, float *bc, const u32x4 (&tp)[RMAX / 4],
                                           const f32x4 (&fn)[RMAX / 4], int lane, int out, const Lev &c0, int Wn,
-                                          float lam, float om, float aS, int e) {
+                                          float lam, float om, float aS, int ce) {
     constexpr bool REC = MODE == BWD_UPDATE_REC, UPD = MODE == BWD_UPDATE || REC, MM = MODE == BWD_MM;
     constexpr bool NEEDF = UPD || MM, BAR = MODE == BWD_EN_BAR || MM || MODE == BWD_STORE_BAR;
     constexpr bool STOREB = UPD || MODE == BWD_STORE || MODE == BWD_STORE_BAR;
@@ -565,7 +567,6 @@ __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t 
             st1(M_r, out, Mn);
             if (REC) record_argmins(rec_r, md_r, out, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
         } else if (lane == 0) {
-            const int ce = T.slot2canon[e];
             T.out0[ce] = m0;
             T.out1[ce] = m1;
         }
@@ -634,6 +635,7 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
         }
         const int et = tc.ebase + nlev - 1;
         float lamn = T.lam[et], aSn = (UPD || BAR) ? T.aS[et] : 0.f, omn = UPD ? T.omega[et] : 0.f;
+        int cen = MM ? T.slot2canon[et] : 0;  // canonical edge of the min-marginals
         int cur = 0;  // buffer holding B of level l+1 (terminals only, below the last level)
         if (lane == 0) {
             buf0[0] = kInf;
@@ -642,6 +644,7 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
         wave_sync();
         for (int l = nlev - 1; l >= 0; --l) {
             const float lam = lamn, om = omn, aS = aSn;
+            const int ce = cen;
             u32x4 tp[QM];
             f32x4 fv[QM];
 #pragma unroll
@@ -664,11 +667,12 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
                 lamn = T.lam[e];
                 if (UPD || BAR) aSn = T.aS[e];
                 if (UPD) omn = T.omega[e];
+                if (MM) cen = T.slot2canon[e];
             }
             const rsrc_t Br = buf(T.B + c0.base, node_bytes(c0));
             with_count<1, QM>(groups(c0), [&](auto qc) {
                 bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, lam_r, M_r, rec_r, md_r, bn, bc, tp, fv, lane,
-                                                           out0 + 4 * l, c0, Wn, lam, om, aS, tc.ebase + l);
+                                                           out0 + 4 * l, c0, Wn, lam, om, aS, ce);
             });
             wave_sync();
             cur ^= 1;
