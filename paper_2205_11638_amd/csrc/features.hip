@@ -35,8 +35,8 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
     const int g = lane / P, p = lane % P;
     const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;
-    float *buf = lds_f + (size_t)wave * lds_words_features(P, WB, NL);  // two node buffers
-    int *meta = (int *)(buf + 2 * WB * G);
+    float *nbuf = lds_f + (size_t)wave * lds_words_features(P, WB, NL);  // three node buffers
+    int *meta = (int *)(nbuf + 3 * WB * G);
     int *off = meta + NL * G;
     const TileCtx tc = tile_ctx(T, tile);
     const int row = T.bdd[tile * 64 + g];
@@ -52,37 +52,56 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
         }
         return v;
     };
-    auto lam_at = [&](int l) {
-        const int e = tc.ebase + l * G + g;
-        float x = T.lam[e];
-        if (bar) x = x + T.aS[e];
-        return x;
+    // a level's rows (and its edge data) are loaded one hop ahead through level-sized resources:
+    // every load is issued unconditionally, rows past a level load 0 and are never used
+    auto rows_u = [&](const uint32_t *a, const Lev &c, uint32_t (&v)[RMAX]) {
+        const rsrc_t r = buf(a + c.base, c.R * 256);
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) v[q] = ld1(r, (q * 64 + lane) * 4);
     };
+    auto rows_f = [&](const float *a, const Lev &c, float (&v)[RMAX]) {
+        const rsrc_t r = buf(a + c.base, c.R * 256);
+#pragma unroll
+        for (int q = 0; q < RMAX; ++q) v[q] = ld1f(r, (q * 64 + lane) * 4);
+    };
+    const int ne = nlev * G * 4;
+    const rsrc_t lam_r = buf(T.lam + tc.ebase, ne), aS_r = buf(T.aS + tc.ebase, ne);
+    auto edge_off = [&](int l) { return (max(min(l, nlev - 1), 0) * G + g) * 4; };
     const int mine = p * G + g;
     // ---- phase 1: bottom-up soft-min costs, stored to Bs
     int cur = 0;  // buffer holding level l+1
     if (p == 0) {
-        buf[g] = kInf;
-        buf[G + g] = 0.f;
+        nbuf[g] = kInf;
+        nbuf[G + g] = 0.f;
     }
+    Lev c0 = level(nlev - 1), cn{0, 0, 0};
+    uint32_t tpn[RMAX];
+    rows_u(T.topo, c0, tpn);
+    float lamn = ld1f(lam_r, edge_off(nlev - 1)), aSn = ld1f(aS_r, edge_off(nlev - 1));
     wave_sync();
-    Lev cn{0, 0, 0};
     for (int l = nlev - 1; l >= 0; --l) {
-        const Lev c0 = level(l);
-        const float lam = lam_at(l);
-        const float *bn = buf + cur * WB * G;
-        float *bc = buf + (cur ^ 1) * WB * G;
+        uint32_t tp[RMAX];
+#pragma unroll
+        for (int r = 0; r < RMAX; ++r) tp[r] = tpn[r];
+        const float lam = bar ? lamn + aSn : lamn;
+        const Lev cp = level(l - 1);
+        rows_u(T.topo, cp, tpn);  // hop l-1
+        lamn = ld1f(lam_r, edge_off(l - 1));
+        aSn = ld1f(aS_r, edge_off(l - 1));
+        const float *bn = nbuf + cur * WB * G;
+        float *bc = nbuf + (cur ^ 1) * WB * G;
         const uint32_t dead = (uint32_t)cn.W | ((uint32_t)cn.W << 16);
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             if (r < c0.R) {
                 const bool ok = in_level<P>(r, c0.R, lane, c0.W);
-                const uint32_t tp = ok ? T.topo[c0.base + r * 64 + lane] : dead;
-                const float v = softmin2(bn[(int)(tp & 0xFFFFu) * G + g], lam + bn[(int)(tp >> 16) * G + g], tau);
+                const uint32_t t = ok ? tp[r] : dead;
+                const float v = softmin2(bn[(int)(t & 0xFFFFu) * G + g], lam + bn[(int)(t >> 16) * G + g], tau);
                 bc[mine + r * P * G] = v;
                 if (ok) Bs[c0.base + r * 64 + lane] = v;
             }
         }
+        wave_sync();  // the terminals' slots may have been written by another lane
         if (p == 0) {
             bc[c0.W * G + g] = kInf;
             bc[(c0.W + 1) * G + g] = 0.f;
@@ -90,26 +109,55 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
         wave_sync();
         cur ^= 1;
         cn = c0;
+        c0 = cp;
     }
-    if (p == 0 && row >= 0 && E_out) E_out[row] = buf[cur * WB * G + g];  // Bs(root)
+    if (p == 0 && row >= 0 && E_out) E_out[row] = nbuf[cur * WB * G + g];  // Bs(root)
     // phase 2 reads back what phase 1 stored: make the stores visible to this wave's loads
     __threadfence();
     wave_sync();
-    // ---- phase 2: top-down probability mass; buffers: mass of level l (pa) and of level l+1 (pb)
-    float *pa = buf, *pb = buf + WB * G;
+    // ---- phase 2: top-down probability mass; buffers: mass of level l (pa) and of level l+1 (pb),
+    // and the smoothed costs of level l+1 with its terminals (bst)
+    float *pa = nbuf, *pb = nbuf + WB * G, *bst = nbuf + 2 * WB * G;
     {
         const int R0 = uni(meta[0] >> 16);
         for (int r = 0; r < R0; ++r) pa[mine + r * P * G] = 0.f;
         if (p == 0) pa[g] = 1.f;
     }
+    c0 = level(0);
+    Lev c1 = level(1);
+    float bcur[RMAX], bnext[RMAX];  // Bs of levels l and l+1
+    rows_u(T.topo, c0, tpn);
+    rows_f(Bs, c0, bcur);
+    rows_f(Bs, c1, bnext);
+    lamn = ld1f(lam_r, edge_off(0));
+    aSn = ld1f(aS_r, edge_off(0));
     wave_sync();
     for (int l = 0; l < nlev; ++l) {
-        const Lev c0 = level(l), c1 = level(l + 1);
         const int Wn = c1.W;
-        const float lam = lam_at(l);
+        uint32_t tp[RMAX];
+        float bv[RMAX];
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r)
-            if (r < c1.R) pb[mine + r * P * G] = 0.f;
+        for (int r = 0; r < RMAX; ++r) {
+            tp[r] = tpn[r];
+            bv[r] = bcur[r];
+            bcur[r] = bnext[r];
+            if (r < c1.R) {
+                bst[mine + r * P * G] = bnext[r];  // children's costs
+                pb[mine + r * P * G] = 0.f;
+            }
+        }
+        const float lam = bar ? lamn + aSn : lamn;
+        // prefetch hop l+1: topology of level l+1, Bs of level l+2, edge data of level l+1
+        const Lev c2 = level(l + 2);
+        rows_u(T.topo, c1, tpn);
+        rows_f(Bs, c2, bnext);
+        lamn = ld1f(lam_r, edge_off(l + 1));
+        aSn = ld1f(aS_r, edge_off(l + 1));
+        wave_sync();  // the terminals' slots may have been staged by another lane
+        if (p == 0) {
+            bst[Wn * G + g] = kInf;
+            bst[(Wn + 1) * G + g] = 0.f;
+        }
         wave_sync();
         float hi_mass = 0.f;
 #pragma unroll
@@ -118,16 +166,10 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
                 const bool ok = in_level<P>(r, c0.R, lane, c0.W);
                 const float m = ok ? pa[mine + r * P * G] : 0.f;
                 if (m > 0.f) {
-                    const uint32_t tp = T.topo[c0.base + r * 64 + lane];
-                    const int lo = (int)(tp & 0xFFFFu), hi = (int)(tp >> 16);
-                    const float bv = Bs[c0.base + r * 64 + lane];
-                    // children's costs: a node of level l+1 from Bs, a terminal by its code
-                    const float b0 = lo < Wn ? Bs[c1.base + (int64_t)((lo / P) * 64 + g * P + lo % P)]
-                                             : (lo == Wn ? kInf : 0.f);
-                    const float b1 = hi < Wn ? Bs[c1.base + (int64_t)((hi / P) * 64 + g * P + hi % P)]
-                                             : (hi == Wn ? kInf : 0.f);
-                    const float q0 = b0 < kInf ? expf(-(b0 - bv) / tau) : 0.f;
-                    const float q1 = b1 < kInf ? expf(-(lam + b1 - bv) / tau) : 0.f;
+                    const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
+                    const float b0 = bst[lo * G + g], b1 = bst[hi * G + g];
+                    const float q0 = b0 < kInf ? expf(-(b0 - bv[r]) / tau) : 0.f;
+                    const float q1 = b1 < kInf ? expf(-(lam + b1 - bv[r]) / tau) : 0.f;
                     if (lo < Wn) lds_fadd(&pb[lo * G + g], m * q0);
                     if (hi < Wn) lds_fadd(&pb[hi * G + g], m * q1);
                     hi_mass += m * q1;
@@ -140,14 +182,17 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
         float *t = pa;
         pa = pb;
         pb = t;
+        c0 = c1;
+        c1 = c2;
     }
 }
 
 template <int P, int RMAX>
 hipError_t smooth_dispatch(const DevTables &t, const ClassLaunch &c, float *Bs, float tau, int bar, float *E_out,
                            float *p_out, hipStream_t s) {
-    const int wpb = c.wpb_b;
+    int wpb = c.wpb_b;
     if (wpb < 1 || wpb > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
+    while (wpb > 1 && (size_t)wpb * lds_words_features(P, c.WB, c.NL) * 4 > 64 * 1024) wpb /= 2;
     dim3 grid((unsigned)((c.ntiles + wpb - 1) / wpb)), block(64 * wpb);
     const size_t lds = (size_t)wpb * lds_words_features(P, c.WB, c.NL) * 4;
     hipLaunchKernelGGL((k_smooth<P, RMAX>), grid, block, lds, s, t, Bs, tau, bar, E_out, p_out, c.tile0, c.ntiles,

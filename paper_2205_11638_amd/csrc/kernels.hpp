@@ -79,7 +79,7 @@ struct ClassLaunch {
 // LDS words (4 bytes) one wavefront of the forward / backward pass kernels uses.
 // per wave: two node buffers (2 * WB * G) and the level table (NL * G + NL)
 // per wave of the smoothed-feature kernel: two node buffers and the level table
-constexpr int lds_words_features(int P, int WB, int NL) { return 2 * WB * (64 / P) + NL * ((64 / P) + 1); }
+constexpr int lds_words_features(int P, int WB, int NL) { return 3 * WB * (64 / P) + NL * ((64 / P) + 1); }
 // Smoothed energies (E_out[row], may be NULL) and Gibbs marginals (p_out, canonical) of one class at
 // temperature tau, at lambda (bar = 0) or lambda + alpha*S (bar = 1); Bs: node array for the costs.
 hipError_t launch_smooth(const DevTables &t, const ClassLaunch &c, float *Bs, float tau, int bar, float *E_out,
