@@ -18,11 +18,12 @@ namespace {
 
 using namespace dev;
 
-__device__ __forceinline__ float softmin2(float a, float b, float tau) {
+// soft-min of two costs at temperature tau (itau = 1 / tau)
+__device__ __forceinline__ float softmin2(float a, float b, float tau, float itau) {
     if (a == kInf) return b;
     if (b == kInf) return a;
     const float m = fminf(a, b), d = fabsf(a - b);
-    return m - tau * log1pf(expf(-d / tau));
+    return m - tau * log1pf(expf(-d * itau));
 }
 
 template <int P, int RMAX>
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
     const rsrc_t lam_r = buf(T.lam + tc.ebase, ne), aS_r = buf(T.aS + tc.ebase, ne);
     auto edge_off = [&](int l) { return (max(min(l, nlev - 1), 0) * G + g) * 4; };
     const int mine = p * G + g;
+    const float itau = 1.f / tau;
     // ---- phase 1: bottom-up soft-min costs, stored to Bs
     int cur = 0;  // buffer holding level l+1
     if (p == 0) {
@@ -96,7 +98,7 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
             if (r < c0.R) {
                 const bool ok = in_level<P>(r, c0.R, lane, c0.W);
                 const uint32_t t = ok ? tp[r] : dead;
-                const float v = softmin2(bn[(int)(t & 0xFFFFu) * G + g], lam + bn[(int)(t >> 16) * G + g], tau);
+                const float v = softmin2(bn[(int)(t & 0xFFFFu) * G + g], lam + bn[(int)(t >> 16) * G + g], tau, itau);
                 bc[mine + r * P * G] = v;
                 if (ok) Bs[c0.base + r * 64 + lane] = v;
             }
@@ -168,8 +170,8 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
                 if (m > 0.f) {
                     const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
                     const float b0 = bst[lo * G + g], b1 = bst[hi * G + g];
-                    const float q0 = b0 < kInf ? expf(-(b0 - bv[r]) / tau) : 0.f;
-                    const float q1 = b1 < kInf ? expf(-(lam + b1 - bv[r]) / tau) : 0.f;
+                    const float q0 = b0 < kInf ? expf(-(b0 - bv[r]) * itau) : 0.f;
+                    const float q1 = b1 < kInf ? expf(-(lam + b1 - bv[r]) * itau) : 0.f;
                     if (lo < Wn) lds_fadd(&pb[lo * G + g], m * q0);
                     if (hi < Wn) lds_fadd(&pb[hi * G + g], m * q1);
                     hi_mass += m * q1;
