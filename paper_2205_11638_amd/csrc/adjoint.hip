@@ -651,15 +651,13 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
 // adjoint of F also lives on minimizing paths only (a node hands its adjoint to its argmin
 // parent arc), but a node's parents are known only to the level above, so every arc of level l
 // still looks up its child's adjoint; the few nodes with an arc into a nonzero one are listed
-// (node, children, cost, the two child adjoints), and with one lane per entry their arcs bid 2k +
-// beta for their child, in the child's adjoint slot (its value is in the list by then); a node's
-// adjoint is the sum of the children it won.  A list that overflows is bid and collected by the
-// owning lanes instead.  F and its
-// adjoint have one buffer each: level l overwrites level l+1 once every value of level l+1 that
-// the hop needs has been read.  The update sweep takes the hop's argmin nodes, their children and
+// (node, children, cost, the two child adjoints), and with one lane per entry their arcs bid
+// 2k + beta for their child; a node's adjoint is the sum of the children it won.  A list that
+// overflows is bid and collected by the owning lanes instead.  F and its adjoint have one buffer
+// each: level l overwrites level l+1 once every value of level l+1 that the hop needs is read.  The update sweep takes the hop's argmin nodes, their children and
 // m^1 - m^0 from the records of the replayed (or stored) pass, so it reads no B at all.
-// LDS per wave: Fv, Fa (cost and adjoint), a spare node buffer (the bids of an overflowing list),
-// the list, the level table.
+// LDS per wave: Fv, Fa (cost and adjoint), the bids (INT_MAX between hops: the bidding lanes clear
+// what they set), the list, the level table.
 // ------------------------------------------------------------------------------------------
 template <bool UPD>
 struct AdjInF;
@@ -675,7 +673,7 @@ struct AdjInF<false> {  // fixed side: the multiplier swept, dlambda_in so far, 
 };
 
 template <int Q, int RMAX, bool UPD>
-__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, int *lk, uint32_t *lt, float *lf,
+__device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, int *lk, uint32_t *lt, float *lf,
                                            float *la0, float *la1, const u32x4 (&tp)[RMAX / 4],
                                            const f32x4 (&fvi)[RMAX / 4], int lane,
                                            const Lev &c0, int Wn, float lam_use, const AdjInF<UPD> &x,
@@ -730,10 +728,8 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, i
     wave_sync();
     float hisum = 0.f;
     const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
-    int *Fai = (int *)Fa;
     if (n <= min(cap, CAP)) {
-        // each listed arc whose value equals its child's cost bids 2k + beta for the child, in the
-        // child's own adjoint slot (its value is in the list now)
+        // each listed arc whose value equals its child's cost bids 2k + beta for the child
         const bool mine = lane < n;
         const int k = mine ? lk[lane] : 0;
         const uint32_t tt = mine ? lt[lane] : 0u;
@@ -741,15 +737,14 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, i
         const int lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
         const bool t0 = mine && a0 != 0.f && ff == Fv[lo];
         const bool t1 = mine && a1 != 0.f && ff + lam_use == Fv[hi];
-        if (t0) Fai[lo] = INT_MAX;
-        if (t1) Fai[hi] = INT_MAX;
+        if (t0) lds_imin(&bid[lo], 2 * k);
+        if (t1) lds_imin(&bid[hi], 2 * k + 1);
         wave_sync();
-        if (t0) lds_imin(&Fai[lo], 2 * k);
-        if (t1) lds_imin(&Fai[hi], 2 * k + 1);
-        wave_sync();
-        const bool w0 = t0 && Fai[lo] == 2 * k, w1 = t1 && Fai[hi] == 2 * k + 1;
-        wave_sync();  // a lane's node of level l may share a slot with another lane's child
-        // level l replaces level l+1 (everything read from it is in registers now)
+        const bool w0 = t0 && bid[lo] == 2 * k, w1 = t1 && bid[hi] == 2 * k + 1;
+        wave_sync();  // every bid is read, every value of level l+1 too
+        if (t0) bid[lo] = INT_MAX;  // the bid buffer is empty again for the next hop
+        if (t1) bid[hi] = INT_MAX;
+        // level l replaces level l+1 (a lane's node of level l may share a slot with another lane's child)
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             lds4(Fv, l16 + q * 1024) = f[q];
@@ -760,13 +755,8 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, i
         if (w0 || w1) Fa[k] = (w0 ? a0 : 0.f) + (w1 ? a1 : 0.f);
         if (w1) hisum = a1;
     } else {
-        // more arcs than the list holds: every lane bids for its own arcs (bids in the spare
-        // buffer) and collects its nodes' adjoints
-        int *obid = (int *)spare;
-        const i32x4 none = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
-#pragma unroll
-        for (int q = 0; q < RMAX / 4; ++q) *(i32x4 *)((char *)obid + l16 + q * 1024) = none;
-        wave_sync();
+        // more arcs than the list holds: every lane bids for its own arcs and collects its nodes'
+        // adjoints
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
@@ -775,8 +765,8 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, i
                 float ff = f[q][j];
                 __asm__ volatile("" : "+v"(tt), "+v"(ff));
                 const int k = q * 256 + (l16 >> 2) + j, lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
-                if (Fa[lo] != 0.f && ff == Fv[lo]) lds_imin(&obid[lo], 2 * k);
-                if (Fa[hi] != 0.f && ff + lam_use == Fv[hi]) lds_imin(&obid[hi], 2 * k + 1);
+                if (Fa[lo] != 0.f && ff == Fv[lo]) lds_imin(&bid[lo], 2 * k);
+                if (Fa[hi] != 0.f && ff + lam_use == Fv[hi]) lds_imin(&bid[hi], 2 * k + 1);
             }
         wave_sync();  // the bids are in: F of level l+1 is not read again, its buffer collects
 #pragma unroll
@@ -788,18 +778,23 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, float *spare, i
                 const int k = q * 256 + (l16 >> 2) + j, lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
                 const float alo = Fa[lo], ahi = Fa[hi];
                 float acc = 0.f;
-                if (alo != 0.f && obid[lo] == 2 * k) acc += alo;
-                if (ahi != 0.f && obid[hi] == 2 * k + 1) {
+                if (alo != 0.f && bid[lo] == 2 * k) acc += alo;
+                if (ahi != 0.f && bid[hi] == 2 * k + 1) {
                     acc += ahi;
                     hisum += ahi;
                 }
                 Fv[k] = acc;
             }
-        wave_sync();  // every adjoint of level l+1 is read
+        wave_sync();  // every adjoint and every bid of level l+1 is read
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             lds4(Fa, l16 + q * 1024) = lds4(Fv, l16 + q * 1024);
             lds4(Fv, l16 + q * 1024) = f[q];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {  // the bid buffer is empty again for the next hop
+                bid[(int)(t[q][j] & 0xFFFFu)] = INT_MAX;
+                bid[(int)(t[q][j] >> 16)] = INT_MAX;
+            }
         }
     }
     wave_sync();
@@ -848,8 +843,8 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
     if (tile >= tile0 + ntiles) return;  // uniform per wave
     float *Fv = lds_f + (size_t)wave * lds_words_adj_F_w(RMAX, NL);
     float *Fa = Fv + NB;
-    float *spare = Fa + NB;
-    int *lk = (int *)(spare + NB);
+    int *bid = (int *)(Fa + NB);  // INT_MAX between hops
+    int *lk = bid + NB;
     uint32_t *lt = (uint32_t *)(lk + kAdjListW);
     float *lf = (float *)(lt + kAdjListW), *la0 = lf + kAdjListW, *la1 = la0 + kAdjListW;
     int *meta = (int *)(la1 + kAdjListW);
@@ -888,12 +883,16 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         return x;
     };
     {
-        // level L: terminals only, no adjoint
+        // level L: terminals only, no adjoint; no bids
         const int l16 = lane16(lane);
         const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+        const i32x4 none = {INT_MAX, INT_MAX, INT_MAX, INT_MAX};
 #pragma unroll
         for (int q = 0; q <= QM; ++q)
-            if (q < QM || lane < 16) lds4(Fa, l16 + q * 1024) = zero4;
+            if (q < QM || lane < 16) {
+                lds4(Fa, l16 + q * 1024) = zero4;
+                *(i32x4 *)((char *)bid + l16 + q * 1024) = none;
+            }
     }
     Lev c0 = level(nlev - 1), c1{0, 0, 0};
     u32x4 tpn[QM];
@@ -939,7 +938,7 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         if constexpr (!UPD)
             if (!use_rec) xu.i0 = xu.i1 = -1;
         with_count<1, QM>(groups(c0), [&](auto qc) {
-            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, spare, lk, lt, lf, la0, la1, tp, fv, lane, c0, Wn, lam_use,
+            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, bid, lk, lt, lf, la0, la1, tp, fv, lane, c0, Wn, lam_use,
                                                        xu, o, l, cap);
         });
         wave_sync();

@@ -111,9 +111,8 @@ constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) 
 // one-wave diagrams (P = 64), pull form: staged B and the adjoints of two levels in node buffers
 // of RMAX rows + 64 slots, then the level table
 constexpr int lds_words_adj_B_w(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
-// one-wave diagrams, push form: cost and adjoint of a level, a spare node buffer (the bids of an
-// overflowing list), the list of nodes with an arc into a nonzero adjoint (node, children, cost,
-// the two child adjoints), then the level table
+// one-wave diagrams, push form: cost, adjoint and bids of a level, the list of nodes with an arc
+// into a nonzero adjoint (node, children, cost, the two child adjoints), then the level table
 constexpr int kAdjListW = 64;
 constexpr int lds_words_adj_F_w(int RMAX, int NL) {
     return 3 * node_buf_w(RMAX) + 5 * kAdjListW + ((2 * NL + 3) & ~3);
