@@ -674,7 +674,7 @@ struct AdjInF<false> {  // fixed side: the multiplier swept, dlambda_in so far, 
 
 template <int Q, int RMAX, bool UPD>
 __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, int *lk, uint32_t *lt, float *lf,
-                                           float *la0, float *la1, const u32x4 (&tp)[RMAX / 4],
+                                           const u32x4 (&tp)[RMAX / 4],
                                            const f32x4 (&fvi)[RMAX / 4], int lane,
                                            const Lev &c0, int Wn, float lam_use, const AdjInF<UPD> &x,
                                            const AdjOut &o, int l, int cap) {
@@ -696,29 +696,43 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, int *
             f[Q - 1][j] = kInf;
         }
     // nodes with an arc into a child with a nonzero adjoint (terminal slots of Fa hold 0), in wave
-    // order; the first CAP go to the list (node, children, cost, the two child adjoints); returns
-    // how many there are (the node values are taken afresh, so nothing derived from them is
-    // computed ahead and held in registers)
+    // order; the first CAP go to the list (node, children, cost); returns how many there are. Every
+    // child adjoint is read first, in one straight run of LDS reads, and the list is built from the
+    // flags after (a list write per node between the reads would make each read wait for the last).
+    // The node values are taken afresh, so nothing derived from them is computed ahead and held in
+    // registers.
     auto detect = [&]() {
+        u32x4 tv[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            tv[q] = t[q];
+            __asm__ volatile("" : "+v"(tv[q]));
+        }
+        uint32_t nzb = 0;
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t tt = tv[q][j];
+                const float a0 = Fa[(int)(tt & 0xFFFFu)], a1 = Fa[(int)(tt >> 16)];
+                nzb |= (uint32_t)((a0 != 0.f) | (a1 != 0.f)) << (4 * q + j);
+            }
         int n = 0;
         const int k4 = lane16(lane) >> 2;
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                uint32_t tt = t[q][j];
-                float ff = f[q][j];
-                __asm__ volatile("" : "+v"(tt), "+v"(ff));
-                const float a0 = Fa[(int)(tt & 0xFFFFu)], a1 = Fa[(int)(tt >> 16)];
-                const bool nz = a0 != 0.f || a1 != 0.f;
+                const bool nz = (nzb >> (4 * q + j)) & 1u;
                 const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
                 const int pos = n + lanes_below(m);
                 if (nz && pos < CAP) {
+                    uint32_t tt = t[q][j];
+                    float ff = f[q][j];
+                    __asm__ volatile("" : "+v"(tt), "+v"(ff));
                     lk[pos] = q * 256 + k4 + j;
                     lt[pos] = tt;
                     lf[pos] = ff;
-                    la0[pos] = a0;
-                    la1[pos] = a1;
                 }
                 n += (int)__builtin_popcountll(m);
             }
@@ -733,8 +747,9 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, int *
         const bool mine = lane < n;
         const int k = mine ? lk[lane] : 0;
         const uint32_t tt = mine ? lt[lane] : 0u;
-        const float ff = mine ? lf[lane] : 0.f, a0 = mine ? la0[lane] : 0.f, a1 = mine ? la1[lane] : 0.f;
+        const float ff = mine ? lf[lane] : 0.f;
         const int lo = (int)(tt & 0xFFFFu), hi = (int)(tt >> 16);
+        const float a0 = mine ? Fa[lo] : 0.f, a1 = mine ? Fa[hi] : 0.f;  // level l+1 is unchanged until below
         const bool t0 = mine && a0 != 0.f && ff == Fv[lo];
         const bool t1 = mine && a1 != 0.f && ff + lam_use == Fv[hi];
         if (t0) lds_imin(&bid[lo], 2 * k);
@@ -846,8 +861,8 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
     int *bid = (int *)(Fa + NB);  // INT_MAX between hops
     int *lk = bid + NB;
     uint32_t *lt = (uint32_t *)(lk + kAdjListW);
-    float *lf = (float *)(lt + kAdjListW), *la0 = lf + kAdjListW, *la1 = la0 + kAdjListW;
-    int *meta = (int *)(la1 + kAdjListW);
+    float *lf = (float *)(lt + kAdjListW);
+    int *meta = (int *)(lf + kAdjListW);
     int *off = meta + NL;
     const TileCtx tc = tile_ctx(T, tile);
     preload_meta<1>(T, tc, lane, meta, off);
@@ -938,7 +953,7 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
         if constexpr (!UPD)
             if (!use_rec) xu.i0 = xu.i1 = -1;
         with_count<1, QM>(groups(c0), [&](auto qc) {
-            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, bid, lk, lt, lf, la0, la1, tp, fv, lane, c0, Wn, lam_use,
+            adjF_hop_w<decltype(qc)::value, RMAX, UPD>(Fv, Fa, bid, lk, lt, lf, tp, fv, lane, c0, Wn, lam_use,
                                                        xu, o, l, cap);
         });
         wave_sync();

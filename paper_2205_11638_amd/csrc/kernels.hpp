@@ -112,10 +112,10 @@ constexpr int lds_words_adj_B(int P, int WB, int NL) { return 3 * WB * (64 / P) 
 // of RMAX rows + 64 slots, then the level table
 constexpr int lds_words_adj_B_w(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
 // one-wave diagrams, push form: cost, adjoint and bids of a level, the list of nodes with an arc
-// into a nonzero adjoint (node, children, cost, the two child adjoints), then the level table
+// into a nonzero adjoint (node, children, cost), then the level table
 constexpr int kAdjListW = 64;
 constexpr int lds_words_adj_F_w(int RMAX, int NL) {
-    return 3 * node_buf_w(RMAX) + 5 * kAdjListW + ((2 * NL + 3) & ~3);
+    return 3 * node_buf_w(RMAX) + 3 * kAdjListW + ((2 * NL + 3) & ~3);
 }
 constexpr int lds_words_adj_F_c(int P, int RMAX, int WB, int NL) {
     return P == 64 ? lds_words_adj_F_w(RMAX, NL) : lds_words_adj_F(P, WB, NL);
