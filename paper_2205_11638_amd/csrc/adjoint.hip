@@ -972,8 +972,7 @@ __global__ void k_adj_deferred(const int32_t *__restrict__ var_ptr, const int32_
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int i = (int)(t / TS), u = (int)(t % TS);
     const int a = i < n ? var_ptr[i] : 0, b = i < n ? var_ptr[i + 1] : 0;
-    float s = 0.f;
-    for (int q = a + u; q < b; q += TS) s += g[var_slots[q]];
+    float s = strided_gather_sum<TS>(var_slots, g, a, b, u);
     for (int w = TS / 2; w > 0; w >>= 1) s += __shfl_xor(s, w, TS);  // every lane takes part
     for (int q = a + u; q < b; q += TS) dM[var_slots[q]] = s;
 }

@@ -259,5 +259,33 @@ __device__ __forceinline__ void record_argmins_team(const DevTables &T, int ebas
     st1(buf(T.mdiff + ebase, ne), off, d);
 }
 
+// The sum of x[idx[q]] over q = a + u, a + u + TS, ... below b, added in that order from 0 (lane u of
+// a team of TS lanes summing one CSR list).  Up to four indices are loaded, then their four values,
+// before any is added: a long list waits for a quarter of the dependent load round trips of the plain
+// loop, and the adds (so the bits) are the plain loop's.
+template <int TS>
+__device__ __forceinline__ float strided_gather_sum(const int32_t *__restrict__ idx, const float *__restrict__ x,
+                                                    int a, int b, int u) {
+    float s = 0.f;
+    int q = a + u;
+    for (; q + 3 * TS < b; q += 4 * TS) {
+        const int e0 = idx[q], e1 = idx[q + TS], e2 = idx[q + 2 * TS], e3 = idx[q + 3 * TS];
+        const float x0 = x[e0], x1 = x[e1], x2 = x[e2], x3 = x[e3];
+        s += x0;
+        s += x1;
+        s += x2;
+        s += x3;
+    }
+    if (q < b) {  // at most three left
+        const bool h1 = q + TS < b, h2 = q + 2 * TS < b;
+        const int e0 = idx[q], e1 = h1 ? idx[q + TS] : 0, e2 = h2 ? idx[q + 2 * TS] : 0;
+        const float x0 = x[e0], x1 = h1 ? x[e1] : 0.f, x2 = h2 ? x[e2] : 0.f;
+        s += x0;
+        if (h1) s += x1;
+        if (h2) s += x2;
+    }
+    return s;
+}
+
 }  // namespace dev
 }  // namespace dd

@@ -802,9 +802,8 @@ __global__ void k_deferred_sum(const int32_t *__restrict__ var_ptr, const int32_
                                const float *__restrict__ M, float *__restrict__ S, int n) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int i = (int)(t / TS), u = (int)(t % TS);
-    float s = 0.f;
-    if (i < n)
-        for (int q = var_ptr[i] + u; q < var_ptr[i + 1]; q += TS) s += M[var_slots[q]];
+    const int a = i < n ? var_ptr[i] : 0, b = i < n ? var_ptr[i + 1] : 0;
+    float s = strided_gather_sum<TS>(var_slots, M, a, b, u);
     for (int w = TS / 2; w > 0; w >>= 1) s += __shfl_xor(s, w, TS);  // every lane takes part
     if (i < n && u == 0) S[i] = s;
 }
