@@ -138,14 +138,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(!UPD && RMA
                 fv[r] = kInf;
             }
         }
-        // prefetch hop l-1: topology and F of level l-1, B of level l, edge data of level l-1
+        // prefetch hop l-1: topology and F of level l-1, edge data of level l-1. Rows past the level
+        // load 0 without a memory access (no row past a level is read) and the last hop reloads its
+        // own edge data: no branch, so no prefetched register is merged with its old value (a merge
+        // would wait for the load right after issuing it).
         const Lev cp = level(l - 1);
+        {
+            const rsrc_t tr = buf(T.topo + cp.base, cp.R * 256), fr = buf(T.F + cp.base, cp.R * 256);
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-            tpn[r] = r < cp.R ? T.topo[cp.base + r * 64 + lane] : 0u;
-            fvn[r] = r < cp.R ? T.F[cp.base + r * 64 + lane] : kInf;
+            for (int r = 0; r < RMAX; ++r) {
+                tpn[r] = ld1(tr, (r * 64 + lane) * 4);
+                fvn[r] = ld1f(fr, (r * 64 + lane) * 4);
+            }
         }
-        if (l > 0) xn = adj_edge<UPD>(T, A, e - G, false, true);
+        xn = adj_edge<UPD>(T, A, tc.ebase + max(l - 1, 0) * G + g, false, true);
         wave_sync();
         // bids for the argmin parent arc of every node of level l+1
 #pragma unroll
@@ -274,7 +280,13 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
         bvn[r] = r < c1.R ? T.B[c1.base + r * 64 + lane] : 0.f;
     }
     AdjEdge xn = adj_edge<UPD>(T, A, tc.ebase + g, bar != 0, false);
-    int pi0 = -1, pi1 = -1;  // record of the previous hop's edge (fixed sweeps)
+    // record of the previous hop's edge (fixed sweeps): read through a resource over the tile's
+    // edges, past it for teams with no node at that level; prec says whether there is one
+    const int ne8 = recs ? nlev * G * 8 : 0;
+    const rsrc_t ri = buf(recs ? (const void *)(A.rec_idx + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in, ne8);
+    const rsrc_t rv = buf(recs ? (const void *)(A.rec_val + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in, ne8);
+    bool prec = false;
+    int pi0 = -1, pi1 = -1;
     float pv0 = 0.f, pv1 = 0.f;
     for (int l = 0; l < nlev; ++l) {
         const int Wn = c1.W;
@@ -282,7 +294,7 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
         const AdjEdge x = xn;
         float *ba0 = Ba + cur * WB * G, *ba1 = Ba + (cur ^ 1) * WB * G;
         // fixed side: argmin contributions of the update sweep to B_l (record of edge l-1)
-        if (!UPD && p == 0) {
+        if (!UPD && p == 0 && prec) {
             if (pi0 >= 0) ba0[pi0 * G + g] += pv0;
             if (pi1 >= 0) ba0[pi1 * G + g] += pv1;
         }
@@ -301,22 +313,26 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
             Bst[Wn * G + g] = kInf;
             Bst[(Wn + 1) * G + g] = 0.f;
         }
-        // prefetch hop l+1: topology of level l+1, B of level l+2, edge data of level l+1
+        // prefetch hop l+1: topology of level l+1, B of level l+2, edge data of level l+1, the record
+        // of edge l. Rows past a level load 0 without a memory access and the last hop reloads its
+        // own edge data: no branch, so no prefetched register is merged with its old value.
         const Lev c2 = level(l + 2);
+        {
+            const rsrc_t tr = buf(T.topo + c1.base, c1.R * 256), br = buf(T.B + c2.base, c2.R * 256);
 #pragma unroll
-        for (int r = 0; r < RMAX; ++r) {
-            tpn[r] = r < c1.R ? T.topo[c1.base + r * 64 + lane] : 0u;
-            bvn[r] = r < c2.R ? T.B[c2.base + r * 64 + lane] : 0.f;
-        }
-        if (l + 1 < nlev) xn = adj_edge<UPD>(T, A, e + G, bar != 0, false);
-        if (!UPD) {
-            pi0 = pi1 = -1;
-            if (recs && c0.W > 0) {
-                pi0 = A.rec_idx[2 * e];
-                pi1 = A.rec_idx[2 * e + 1];
-                pv0 = A.rec_val[2 * e];
-                pv1 = A.rec_val[2 * e + 1];
+            for (int r = 0; r < RMAX; ++r) {
+                tpn[r] = ld1(tr, (r * 64 + lane) * 4);
+                bvn[r] = ld1f(br, (r * 64 + lane) * 4);
             }
+        }
+        xn = adj_edge<UPD>(T, A, tc.ebase + min(l + 1, nlev - 1) * G + g, bar != 0, false);
+        if (!UPD) {
+            prec = recs && c0.W > 0;
+            const int o8 = c0.W > 0 ? (l * G + g) * 8 : ne8;
+            pi0 = (int)ld1(ri, o8);
+            pi1 = (int)ld1(ri, o8 + 4);
+            pv0 = ld1f(rv, o8);
+            pv1 = ld1f(rv, o8 + 4);
         }
         wave_sync();
         float hisum = 0.f;
@@ -1119,23 +1135,29 @@ hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunc
     const int cap = dense ? 0 : INT_MAX;  // list entries the one-wave sweeps may use
     if (c.wpb_af < 1 || c.wpb_af > kMaxWavesPerBlock || c.wpb_ab < 1 || c.wpb_ab > kMaxWavesPerBlock)
         return hipErrorInvalidConfiguration;
-    if ((which == ADJ_F_UPDATE || which == ADJ_F_FIXED) && P == 64) {
-        dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
-        const size_t lds = (size_t)c.wpb_af * lds_words_adj_F_w(RMAX, c.NL) * 4;
-        if (which == ADJ_F_UPDATE)
-            hipLaunchKernelGGL((k_adj_F_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs,
-                               cap);
-        else
-            hipLaunchKernelGGL((k_adj_F_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs,
-                               cap);
-    } else if (which == ADJ_F_UPDATE || which == ADJ_F_FIXED) {
+    const bool push = which == ADJ_F_UPDATE || which == ADJ_F_FIXED;
+    if constexpr (P == 64) {  // one-wave diagrams: the wide sweeps only
+        if (push) {
+            dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
+            const size_t lds = (size_t)c.wpb_af * lds_words_adj_F_w(RMAX, c.NL) * 4;
+            if (which == ADJ_F_UPDATE)
+                hipLaunchKernelGGL((k_adj_F_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL, recs,
+                                   cap);
+            else
+                hipLaunchKernelGGL((k_adj_F_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL,
+                                   recs, cap);
+            return hipGetLastError();
+        }
+    } else if (push) {
         dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
         const size_t lds = (size_t)c.wpb_af * lds_words_adj_F(P, c.WB, c.NL) * 4;
         if (which == ADJ_F_UPDATE)
             hipLaunchKernelGGL((k_adj_F<P, RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.WB, c.NL);
         else
             hipLaunchKernelGGL((k_adj_F<P, RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.WB, c.NL);
-    } else if constexpr (P == 64) {
+        return hipGetLastError();
+    }
+    if constexpr (P == 64) {
         dim3 grid((unsigned)((c.ntiles + c.wpb_ab - 1) / c.wpb_ab)), block(64 * c.wpb_ab);
         const size_t lds = (size_t)c.wpb_ab * lds_words_adj_B_w(RMAX, c.NL) * 4;
         if (which == ADJ_B_UPDATE)
