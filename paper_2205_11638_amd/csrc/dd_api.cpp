@@ -457,7 +457,8 @@ int recompute_B(dd_instance *h, hipStream_t s) {
 }
 
 int pass_launches(dd_instance *h, int dir, hipStream_t s) {
-    int st = deferred(h, s);
+    // with form_as the update passes form and store alpha * S themselves
+    int st = h->T.form_as ? deferred_sum(h, h->T.M, s) : deferred(h, s);
     if (st) return st;
     return all_classes(h, dir == 0, dir == 0 ? (int)FWD_UPDATE : (int)BWD_UPDATE, s);
 }
@@ -636,6 +637,11 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     TRY(upload(h, &h->cdev, c32, s));
     TRY(h->alloc(&h->S, (size_t)prob->n));
     T.S = h->S;
+    {
+        bool wide = false;
+        for (const ClassLaunch &c : h->classes) wide = wide || c.P == 64;
+        T.form_as = !wide && (int64_t)prob->n * 4 <= dd::kFormAsMaxBytes;
+    }
     TRY(h->alloc(&T.energies, (size_t)m));
     TRY(h->alloc(&T.en_lam, (size_t)m));
     TRY(h->alloc(&h->partial, (size_t)kSumBlocks));

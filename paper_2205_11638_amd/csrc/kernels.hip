@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -22,10 +23,34 @@ namespace {
 
 using namespace dev;
 
+// alpha * S_i of the edges an update pass visits, formed in the pass (the deferred sums S are
+// complete when it starts). The variable of the next hop's edge is loaded a hop earlier, so the load
+// of its S waits for nothing issued in the current hop. Padding slots (variable -1) give 0, as the
+// stored alpha * S has; the pass stores the value beside the multipliers, so the stored array holds
+// what the separate per-edge launch would have written. Used when the instance's form_as is set.
+struct EdgeAlphaS {
+    float al = 0.f, s = 0.f;  // alpha and S of the next hop's edge
+    int v = -1;               // its variable
+    int vn = -1;              // the variable of the edge after it
+    // the value for the next hop: a rounded product, as a stored one is (no multiply-add with its use)
+    __device__ __forceinline__ float value() const {
+        float r = v >= 0 ? al * s : 0.f;
+        __asm__("" : "+v"(r));
+        return r;
+    }
+    // loads for edge e, whose variable is vn, and the variable of edge e2
+    __device__ __forceinline__ void prefetch(const DevTables &T, int64_t e, int64_t e2) {
+        al = T.alpha[e];
+        s = T.S[vn >= 0 ? vn : 0];
+        v = vn;
+        vn = T.evar[e2];
+    }
+};
+
 // LOOP = false: one wave per tile.  LOOP = true (update passes on a resident grid): each wave
 // takes tiles w, w + stride, ... (stride = waves in the grid); tiles are sorted by decreasing
 // length within a class, so striding mixes long and short ones.
-template <int P, int RMAX, int MODE, bool LOOP>
+template <int P, int RMAX, int MODE, bool LOOP, bool FAS>
 __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
     constexpr bool REC = MODE == FWD_UPDATE_REC, UPD = MODE == FWD_UPDATE || REC;
@@ -40,6 +65,9 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
         int *meta = (int *)(Bst + WB * G);
         int *off = meta + NL * G;
         const TileCtx tc = tile_ctx(T, tile);
+        constexpr bool fas = UPD && FAS;  // this pass forms alpha * S (the instance's form_as)
+        EdgeAlphaS eas;
+        if (fas) eas.vn = T.evar[tc.ebase + g];  // issued first: the level table's load covers its wait
         preload_meta<G>(T, tc, lane, meta, off);
         const int nlev = tc.nlev;
         auto level = [&](int l) {
@@ -62,11 +90,12 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
             tpn[r] = r < c0.R ? T.topo[c0.base + r * 64 + lane] : 0u;
             bvn[r] = (UPD && r < c1.R) ? T.B[c1.base + r * 64 + lane] : 0.f;
         }
-        float lamn = T.lam[tc.ebase + g], aSn = T.aS[tc.ebase + g], omn = UPD ? T.omega[tc.ebase + g] : 0.f;
+        float lamn = T.lam[tc.ebase + g], aSn = fas ? 0.f : T.aS[tc.ebase + g], omn = UPD ? T.omega[tc.ebase + g] : 0.f;
+        if (fas) eas.prefetch(T, tc.ebase + g, tc.ebase + min(1, nlev - 1) * G + g);
         if (p == 0) Fb[g] = 0.f;  // F(root) = 0
         wave_sync();
         for (int l = 0; l < nlev; ++l) {
-            const float lam = lamn, om = omn, aS = aSn;
+            const float lam = lamn, om = omn, aS = fas ? eas.value() : aSn;
             uint32_t tp[RMAX];
             float fv[RMAX];
             // B of level l+1 (prefetched last hop) into LDS, with the terminals after it
@@ -104,8 +133,9 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
                 }
                 const int e = tc.ebase + min(l + 1, nlev - 1) * G + g;
                 lamn = T.lam[e];
-                aSn = T.aS[e];
                 if (UPD) omn = T.omega[e];
+                if (fas) eas.prefetch(T, e, tc.ebase + min(l + 2, nlev - 1) * G + g);
+                else aSn = T.aS[e];
             }
             float m0 = kInf, m1 = kInf;
             int k0 = INT_MAX, k1 = INT_MAX, h0 = 0, h1 = 0;  // recording: first node attaining the lane's min
@@ -140,6 +170,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
                 const int ne = nlev * G * 4, off = p == 0 && live ? (l * G + g) * 4 : ne;
                 st1(buf(T.lam + tc.ebase, ne), off, lam_new);
                 st1(buf(T.M + tc.ebase, ne), off, Mn);
+                if (fas) st1(buf(T.aS + tc.ebase, ne), off, aS);
                 if (REC) record_argmins_team<P>(T, tc.ebase, ne, off, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
             } else {
                 lam_new = MODE == FWD_SWEEP_BAR ? lam + aS : lam;  // sweep, no update
@@ -169,7 +200,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
 // level l (written); B of a level goes to global memory at the start of the next hop, before
 // that hop's prefetch, so waiting for prefetched data never waits for a fresh store.
 // ------------------------------------------------------------------------------------------
-template <int P, int RMAX, int MODE, bool LOOP>
+template <int P, int RMAX, int MODE, bool LOOP, bool FAS>
 __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
     constexpr bool REC = MODE == BWD_UPDATE_REC, UPD = MODE == BWD_UPDATE || REC, MM = MODE == BWD_MM;
@@ -185,6 +216,9 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         int *meta = (int *)(buf0 + 2 * WB * G);
         int *off = meta + NL * G;
         const TileCtx tc = tile_ctx(T, tile);
+        constexpr bool fas = UPD && FAS;  // this pass forms alpha * S (the instance's form_as)
+        EdgeAlphaS eas;
+        if (fas) eas.vn = T.evar[tc.ebase + (tc.nlev - 1) * G + g];  // issued first, as in the forward pass
         const int row = T.bdd[tile * 64 + g];
         preload_meta<G>(T, tc, lane, meta, off);
         const int nlev = tc.nlev;
@@ -209,7 +243,8 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
             fn[r] = (NEEDF && r < c0.R) ? T.F[c0.base + r * 64 + lane] : 0.f;
         }
         const int et = tc.ebase + (nlev - 1) * G + g;
-        float lamn = T.lam[et], aSn = (UPD || BAR) ? T.aS[et] : 0.f, omn = UPD ? T.omega[et] : 0.f;
+        float lamn = T.lam[et], aSn = (BAR || (UPD && !fas)) ? T.aS[et] : 0.f, omn = UPD ? T.omega[et] : 0.f;
+        if (fas) eas.prefetch(T, et, tc.ebase + max(nlev - 2, 0) * G + g);
         int cen = MM ? T.slot2canon[et] : 0;  // canonical edge of the min-marginals (padding slots: unused)
         int cur = 0;  // buffer holding B of level l+1 (terminals only, below the last level)
         if (p == 0) {
@@ -218,7 +253,7 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         }
         wave_sync();
         for (int l = nlev - 1; l >= 0; --l) {
-            const float lam = lamn, om = omn, aS = aSn;
+            const float lam = lamn, om = omn, aS = fas ? eas.value() : aSn;
             const int ce = cen;
             uint32_t tp[RMAX];
             float fv[RMAX];
@@ -247,8 +282,9 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                 }
                 const int e = tc.ebase + max(l - 1, 0) * G + g;
                 lamn = T.lam[e];
-                if (UPD || BAR) aSn = T.aS[e];
                 if (UPD) omn = T.omega[e];
+                if (fas) eas.prefetch(T, e, tc.ebase + max(l - 2, 0) * G + g);
+                else if (UPD || BAR) aSn = T.aS[e];
                 if (MM) cen = T.slot2canon[e];
             }
             float m0 = kInf, m1 = kInf;
@@ -286,6 +322,7 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                     const int ne = nlev * G * 4, off = p == 0 && live ? (l * G + g) * 4 : ne;
                     st1(buf(T.lam + tc.ebase, ne), off, lam_new);
                     st1(buf(T.M + tc.ebase, ne), off, Mn);
+                    if (fas) st1(buf(T.aS + tc.ebase, ne), off, aS);
                     if (REC) record_argmins_team<P>(T, tc.ebase, ne, off, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
                 } else if (p == 0 && live) {
                     T.out0[ce] = m0;
@@ -738,20 +775,28 @@ hipError_t fwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hi
     const unsigned full = full_grid(c.ntiles, c.wpb_f);
     dim3 grid(full), block(64 * c.wpb_f);
     size_t lds = (size_t)c.wpb_f * lds_words_pass(P, c.WB, c.NL) * 4;
-    if (mode == FWD_UPDATE && c.grid_f > 0 && (unsigned)c.grid_f < full)
-        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE, true>), dim3(c.grid_f), block, lds, s, t, c.tile0, c.ntiles,
+    auto update = [&](auto fas) {
+        constexpr bool F = decltype(fas)::value;
+        if (mode == FWD_UPDATE && c.grid_f > 0 && (unsigned)c.grid_f < full)
+            hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE, true, F>), dim3(c.grid_f), block, lds, s, t, c.tile0,
+                               c.ntiles, c.WB, c.NL);
+        else if (mode == FWD_UPDATE)
+            hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE, false, F>), grid, block, lds, s, t, c.tile0, c.ntiles,
+                               c.WB, c.NL);
+        else
+            hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE_REC, false, F>), grid, block, lds, s, t, c.tile0, c.ntiles,
+                               c.WB, c.NL);
+    };
+    if (mode == FWD_UPDATE || mode == FWD_UPDATE_REC) {
+        if (t.form_as) update(std::true_type{});
+        else update(std::false_type{});
+    } else if (mode == FWD_SWEEP_BAR) {
+        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_SWEEP_BAR, false, false>), grid, block, lds, s, t, c.tile0, c.ntiles,
                            c.WB, c.NL);
-    else if (mode == FWD_UPDATE)
-        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL);
-    else if (mode == FWD_UPDATE_REC)
-        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_UPDATE_REC, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB,
-                           c.NL);
-    else if (mode == FWD_SWEEP_BAR)
-        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_SWEEP_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB,
-                           c.NL);
-    else
-        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_SWEEP_LAM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB,
-                           c.NL);
+    } else {
+        hipLaunchKernelGGL((k_fwd<P, RMAX, FWD_SWEEP_LAM, false, false>), grid, block, lds, s, t, c.tile0, c.ntiles,
+                           c.WB, c.NL);
+    }
     return hipGetLastError();
 }
 
@@ -760,19 +805,29 @@ hipError_t bwd_dispatch_g(const DevTables &t, const ClassLaunch &c, int mode, hi
     const unsigned full = full_grid(c.ntiles, c.wpb_b);
     dim3 grid(full), block(64 * c.wpb_b);
     size_t lds = (size_t)c.wpb_b * lds_words_pass(P, c.WB, c.NL) * 4;
-    if (mode == BWD_UPDATE && c.grid_b > 0 && (unsigned)c.grid_b < full) {
-        hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE, true>), dim3(c.grid_b), block, lds, s, t, c.tile0, c.ntiles,
-                           c.WB, c.NL);
-        return hipGetLastError();
-    }
+    auto update = [&](auto fas) {
+        constexpr bool F = decltype(fas)::value;
+        if (mode == BWD_UPDATE && c.grid_b > 0 && (unsigned)c.grid_b < full)
+            hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE, true, F>), dim3(c.grid_b), block, lds, s, t, c.tile0,
+                               c.ntiles, c.WB, c.NL);
+        else if (mode == BWD_UPDATE)
+            hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE, false, F>), grid, block, lds, s, t, c.tile0, c.ntiles,
+                               c.WB, c.NL);
+        else
+            hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE_REC, false, F>), grid, block, lds, s, t, c.tile0, c.ntiles,
+                               c.WB, c.NL);
+    };
     switch (mode) {
-        case BWD_UPDATE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
-        case BWD_UPDATE_REC: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_UPDATE_REC, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
-        case BWD_STORE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_STORE, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
-        case BWD_EN_LAM: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_LAM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
-        case BWD_EN_BAR: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
-        case BWD_STORE_BAR: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_STORE_BAR, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
-        default: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_MM, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        case BWD_UPDATE:
+        case BWD_UPDATE_REC:
+            if (t.form_as) update(std::true_type{});
+            else update(std::false_type{});
+            break;
+        case BWD_STORE: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_STORE, false, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        case BWD_EN_LAM: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_LAM, false, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        case BWD_EN_BAR: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_EN_BAR, false, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        case BWD_STORE_BAR: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_STORE_BAR, false, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
+        default: hipLaunchKernelGGL((k_bwd<P, RMAX, BWD_MM, false, false>), grid, block, lds, s, t, c.tile0, c.ntiles, c.WB, c.NL); break;
     }
     return hipGetLastError();
 }
@@ -950,9 +1005,9 @@ int pass_blocks_per_cu_t(const ClassLaunch &c, bool fwd) {
     } else {
         const hipError_t e =
             fwd ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &nb, reinterpret_cast<const void *>(&k_fwd<P, RMAX, FWD_UPDATE, true>), 64 * wpb, lds)
+                      &nb, reinterpret_cast<const void *>(&k_fwd<P, RMAX, FWD_UPDATE, true, true>), 64 * wpb, lds)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &nb, reinterpret_cast<const void *>(&k_bwd<P, RMAX, BWD_UPDATE, true>), 64 * wpb, lds);
+                      &nb, reinterpret_cast<const void *>(&k_bwd<P, RMAX, BWD_UPDATE, true, true>), 64 * wpb, lds);
         return e == hipSuccess ? nb : 0;
     }
 }

@@ -53,7 +53,8 @@ struct DevTables {
     const int32_t *evar;      // variable of each edge slot (-1: padding)
     const int32_t *slot2canon;
     const float *S;           // [n] deferred sums
-    const float *aS;          // [edge slots] alpha * S of the edge's variable
+    float *aS;                // [edge slots] alpha * S of the edge's variable
+    int form_as;              // narrow update passes form alpha * S from S and store it (no separate launch)
     float *energies;          // [m] per-row E^j at the flushed multipliers
     float *en_lam;            // [m] per-row E^j at the current multipliers (from backward passes)
     float *out0, *out1;       // [edges] canonical min-marginal outputs
@@ -114,6 +115,10 @@ constexpr int lds_words_adj_B_w(int RMAX, int NL) { return 3 * node_buf_w(RMAX) 
 // one-wave diagrams, push form: cost, adjoint and bids of a level, the list of nodes with an arc
 // into a nonzero adjoint (node, children, cost), then the level table
 constexpr int kAdjListW = 64;
+// The narrow update passes form alpha * S themselves when the instance has no one-wave class and S
+// fits one XCD's L2: they gather S_i per edge inside their hop chain, which pays while that gather
+// hits L2; otherwise a separate launch, which gathers at full occupancy, is faster.
+constexpr int64_t kFormAsMaxBytes = 4 << 20;
 constexpr int lds_words_adj_F_w(int RMAX, int NL) {
     return 3 * node_buf_w(RMAX) + 3 * kAdjListW + ((2 * NL + 3) & ~3);
 }
