@@ -189,3 +189,40 @@ def test_batch_gradients_equal_separate_instances():
         np.testing.assert_array_equal(dw[e0:e1], g1[0], err_msg=f"program {q}")
         np.testing.assert_array_equal(da[e0:e1], g1[1], err_msg=f"program {q}")
         np.testing.assert_array_equal(dc[v0:v1], g1[2], err_msg=f"program {q}")
+
+
+def test_alpha_s_formed_in_the_pass_gives_the_separate_launchs_bits():
+    """The narrow update passes form alpha * S themselves while S fits in 4 MB (one XCD's L2); a
+    larger instance forms it with a separate launch before each pass. Two independent-set programs
+    of 540,000 variables each: alone, each forms it in its passes; packed (1,080,000 variables), the
+    batch uses the separate launch. The states must agree bit for bit."""
+    import torch
+
+    import paper_2205_11638_amd as dd
+    ps = [synth.independent_set(n=540_000, M=540_000, seed=31 + q) for q in range(2)]
+    params = [learned(p, 40 + q) for q, p in enumerate(ps)]
+    say(f"[alpha*S] packed n={sum(p.n for p in ps)}, edges={sum(p.nnz for p in ps)}")
+    bt = dd.Batch(ps)
+    inst = bt.instance
+    om = torch.tensor(np.concatenate([q[0] for q in params]), device="cuda")
+    ah = torch.tensor(np.concatenate([q[1] for q in params]), device="cuda")
+    inst.set_params(om, inst.seg_softmax(ah))
+    inst.reset()
+    inst.profile_begin()
+    inst.run_pass(0)
+    assert "k_edge_alpha_s" in inst.profile_end()
+    inst.run_pass(1)
+    T = 5
+    bt.run(T)
+    lam, M = state(inst)
+    for q, p in enumerate(ps):
+        e0, e1 = bt.edge_off[q], bt.edge_off[q + 1]
+        one, _, _ = make_instance(p, *params[q])
+        one.profile_begin()
+        one.run_pass(0)
+        assert "k_edge_alpha_s" not in one.profile_end()
+        one.run_pass(1)
+        one.run(T)
+        l1, M1 = state(one)
+        np.testing.assert_array_equal(lam[e0:e1], l1, err_msg=f"program {q}")
+        np.testing.assert_array_equal(M[e0:e1], M1, err_msg=f"program {q}")
