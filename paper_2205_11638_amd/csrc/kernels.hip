@@ -49,7 +49,8 @@ struct EdgeAlphaS {
 
 // LOOP = false: one wave per tile.  LOOP = true (update passes on a resident grid): each wave
 // takes tiles w, w + stride, ... (stride = waves in the grid); tiles are sorted by decreasing
-// length within a class, so striding mixes long and short ones.
+// length within a class, so striding mixes long and short ones.  FAS (update modes): the pass forms
+// alpha * S itself (the instance's form_as) instead of reading the stored array.
 template <int P, int RMAX, int MODE, bool LOOP, bool FAS>
 __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
