@@ -1,10 +1,10 @@
 """The deferred sums S_i = sum over the subproblems k of M_ik (the coupling term of the multiplier
 update, Alg. 1) are formed in one fixed order, so a program gets the same bits alone and packed into a
-batch. Four lanes per variable take the variable's edges (rows ascending) in strided order. Each lane
-loads up to four terms ahead, then adds them in list order, and a fixed butterfly (partner lane 2,
-then lane 1) adds the four partial sums. The flushed multipliers lambda + alpha * S, read back
-through the C ABI, must equal a float32 host model of that order bit for bit, for variables in 1 to
-45 rows (every tail of the strided loads)."""
+batch. A team of lanes per variable takes the variable's edges (rows ascending) in strided order.
+Each lane loads up to four terms ahead, then adds them in list order, and a fixed butterfly (partner
+lane half the team away first, lane 1 last) adds the partial sums. The flushed multipliers
+lambda + alpha * S, read back through the C ABI, must equal a float32 host model of that order bit
+for bit, for variables in 1 to 45 rows (every tail of the strided loads)."""
 from __future__ import annotations
 
 import numpy as np
@@ -30,15 +30,19 @@ def degree_problem():
 
 
 def team_sum(vals):
-    """float32 model of one variable's sum: strided lane sums from 0, then the butterfly."""
+    """float32 model of one variable's sum: strided lane sums from 0, then the butterfly (partner
+    lane TEAM/2 first, lane 1 last)."""
     part = []
     for u in range(TEAM):
         s = np.float32(0.0)
         for v in vals[u::TEAM]:
             s = np.float32(s + v)
         part.append(s)
-    p2 = [np.float32(part[u] + part[u ^ 2]) for u in range(TEAM)]
-    return np.float32(p2[0] + p2[1])
+    w = TEAM // 2
+    while w:
+        part = [np.float32(part[u] + part[u ^ w]) for u in range(TEAM)]
+        w //= 2
+    return part[0]
 
 
 def test_flushed_multipliers_follow_the_fixed_sum_order():
