@@ -667,7 +667,7 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
 // adjoint of F also lives on minimizing paths only (a node hands its adjoint to its argmin
 // parent arc), but a node's parents are known only to the level above, so every arc of level l
 // still looks up its child's adjoint; the few nodes with an arc into a nonzero one are listed
-// (node, children, cost, the two child adjoints), and with one lane per entry their arcs bid
+// (node, children, cost), and with one lane per entry, which reads its two child adjoints, their arcs bid
 // 2k + beta for their child; a node's adjoint is the sum of the children it won.  A list that
 // overflows is bid and collected by the owning lanes instead.  F and its adjoint have one buffer
 // each: level l overwrites level l+1 once every value of level l+1 that the hop needs is read.  The update sweep takes the hop's argmin nodes, their children and
