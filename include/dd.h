@@ -151,7 +151,12 @@ int dd_get_state(dd_instance *h, float *lambda_out, float *M_out, int32_t flushe
  * profiling; the launches, and so the results, are the same either way. */
 int dd_run(dd_instance *h, int32_t T, void *stream);
 
-/* One pass: direction 0 = forward, 1 = backward. */
+/* One pass of Alg. 1: direction 0 = forward, 1 = backward.  A pass reads the other side's
+ * shortest-path costs at its input multipliers (eq. 8 for the hops it has not visited yet): B for a
+ * forward pass, F for a backward pass.  A pass of the other direction leaves them in place; when the
+ * previous call did not (two passes of one direction in a row, or a call that moved the multipliers
+ * or reused the node arrays: dd_set_state, dd_reset, dd_min_marginals, dd_pass_vjp, dd_backward, ...)
+ * they are recomputed first, with one more sweep. */
 int dd_run_pass(dd_instance *h, int32_t direction, void *stream);
 
 /* Lower bound (D) at lambda_bar plus the uncovered-variable constant (into *lb), and
@@ -193,6 +198,13 @@ int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *l
  * Outputs are device arrays (may be NULL): d_omega, d_alpha [edges] canonical, d_c [n].
  * Leaves the solver at the final state.  DD_E_STATE without a valid record. */
 int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream);
+
+/* Serial number of the recorded unrolled forward, for callers that hold several records of one
+ * instance (each autograd node of a graph): every successful dd_forward_unrolled* takes the next
+ * serial; *serial = -1 when no record is valid (none made, or the state changed since).  A caller
+ * that kept the serial of its forward and finds another one here knows that dd_backward would
+ * differentiate a later forward, not its own.  Host only. */
+int dd_record_serial(const dd_instance *h, int64_t *serial);
 
 /* Alg. 2 applied to one whole pass (direction 0 forward, 1 backward): given the pass input
  * (lam_in, M_in) and the adjoints of its outputs (dlam_out, dM_out), write the adjoints of the

@@ -142,18 +142,24 @@ static double energy(const row_t *r, const double *lam, double *Q) {
     return Q[-r->smin];
 }
 
-/* Smallest relative gap between the two options of any decision taken so far (a diagnostic:
- * where it is tiny the minimizer is not unique up to rounding, so any subgradient is valid). */
-static void note_gap(double *gap, double a, double b) {
+/* Smallest gap between the two options of any decision taken so far, relative (|a - b| divided by
+ * the larger of |a|, |b|) and absolute (|a - b|).  A diagnostic: where it is below the rounding
+ * error of the values compared, the minimizer is not unique up to rounding, so any of the
+ * candidates gives a valid subgradient. */
+typedef struct {
+    double rel, abs;
+} gap_t;
+static void note_gap(gap_t *gap, double a, double b) {
     if (!gap || a == INF || b == INF) return;
     double d = fabs(a - b), s = fmax(fmax(fabs(a), fabs(b)), 1e-300);
-    if (d / s < *gap) *gap = d / s;
+    if (d / s < gap->rel) gap->rel = d / s;
+    if (d < gap->abs) gap->abs = d;
 }
 
 /* Minimizer of <lam, x> over X_j with x_l = beta (l = -1: unconstrained), written to x[0..L).
  * Ties: lowest partial sum, then x_p = 0 before x_p = 1.  gap (may be NULL): see note_gap. */
 static void minimizer(const row_t *r, const double *lam, const double *P, const double *Q, int l, int beta,
-                      int8_t *x, double *gap) {
+                      int8_t *x, gap_t *gap) {
     int64_t s;
     if (l < 0) {
         s = 0;
@@ -189,6 +195,109 @@ static void minimizer(const row_t *r, const double *lam, const double *P, const 
         if (x[p]) s += r->a[p];
     }
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Near-ties: how far the adjoint can move when another engine takes other decisions.          */
+/* The adjoint routes through minimizers, so it is a function of the decisions taken while     */
+/* tracing them.  Another engine whose arithmetic differs (fp32 instead of fp64) may take the   */
+/* other option of a decision whose two options lie within its rounding error of each other,   */
+/* and both choices give valid subgradients.  The functions below bound, per output, how much  */
+/* such flips can change it ("flip bound"; 0: the output is determined and must agree).  tol   */
+/* is the caller's bound on how far the compared values can lie from this oracle's.  The bound */
+/* is first order: decisions are flipped one at a time, and the changes they cause are carried */
+/* through the adjoint recurrences with absolute values.                                        */
+/* ------------------------------------------------------------------------------------------ */
+
+/* Greedy trace back through the prefix table from state s at level p: xv[q] for q < p
+ * (the rules of minimizer()). */
+static void trace_back(const row_t *r, const double *lam, const double *P, int p, int64_t s, int8_t *xv) {
+    for (int q = p - 1; q >= 0; --q) {
+        double x0 = at(r, P, q, s), x1 = at(r, P, q, s - r->a[q]) + lam[q];
+        xv[q] = x0 <= x1 ? 0 : 1;
+        if (xv[q]) s -= r->a[q];
+    }
+}
+
+/* Greedy trace forward through the suffix table from state s at level p: xv[q] for q >= p. */
+static void trace_fwd(const row_t *r, const double *lam, const double *Q, int p, int64_t s, int8_t *xv) {
+    for (int q = p; q < r->L; ++q) {
+        double x0 = at(r, Q, q + 1, s), x1 = lam[q] + at(r, Q, q + 1, s + r->a[q]);
+        xv[q] = x0 <= x1 ? 0 : 1;
+        if (xv[q]) s += r->a[q];
+    }
+}
+
+static int near(double a, double b, double tol) { return a != INF && b != INF && fabs(a - b) <= tol; }
+
+/* amb[q] = 1 for every position q where the minimizer x traced by minimizer() for (l, beta) changes
+ * when one of its decisions whose two options lie within tol goes the other way: that option is
+ * traced to the end by the same rules and compared with x.  Decisions are flipped one at a time. */
+static void near_ties(const row_t *r, const double *lam, const double *P, const double *Q, int l, int beta,
+                      const int8_t *x, double tol, int8_t *amb, int8_t *alt) {
+    const int L = r->L;
+    int64_t s;
+    if (l < 0) {
+        s = 0;
+        for (int p = 0; p < L; ++p) {
+            double x0 = at(r, Q, p + 1, s), x1 = lam[p] + at(r, Q, p + 1, s + r->a[p]);
+            if (near(x0, x1, tol)) {
+                alt[p] = (int8_t)(1 - x[p]);
+                trace_fwd(r, lam, Q, p + 1, s + (alt[p] ? r->a[p] : 0), alt);
+                for (int q = p; q < L; ++q) if (alt[q] != x[q]) amb[q] = 1;
+            }
+            if (x[p]) s += r->a[p];
+        }
+        return;
+    }
+    const int64_t shift = beta ? r->a[l] : 0;
+    double best = INF; int64_t sb = 0;
+    for (int k = 0; k < r->W; ++k) {
+        int64_t ss = r->smin + k;
+        double v = at(r, P, l, ss) + (beta ? lam[l] : 0.0) + at(r, Q, l + 1, ss + shift);
+        if (v < best) { best = v; sb = ss; }
+    }
+    for (int k = 0; k < r->W; ++k) {            /* another state of level l within tol */
+        int64_t ss = r->smin + k;
+        double v = at(r, P, l, ss) + (beta ? lam[l] : 0.0) + at(r, Q, l + 1, ss + shift);
+        if (ss == sb || !near(v, best, tol)) continue;
+        alt[l] = (int8_t)beta;
+        trace_back(r, lam, P, l, ss, alt);
+        trace_fwd(r, lam, Q, l + 1, ss + shift, alt);
+        for (int q = 0; q < L; ++q) if (alt[q] != x[q]) amb[q] = 1;
+    }
+    s = sb;
+    for (int p = l - 1; p >= 0; --p) {           /* decisions back through the prefix table */
+        double x0 = at(r, P, p, s), x1 = at(r, P, p, s - r->a[p]) + lam[p];
+        if (near(x0, x1, tol)) {
+            alt[p] = (int8_t)(1 - x[p]);
+            trace_back(r, lam, P, p, s - (alt[p] ? r->a[p] : 0), alt);
+            for (int q = 0; q <= p; ++q) if (alt[q] != x[q]) amb[q] = 1;
+        }
+        if (x[p]) s -= r->a[p];
+    }
+    s = sb + shift;
+    for (int p = l + 1; p < L; ++p) {            /* decisions forward through the suffix table */
+        double x0 = at(r, Q, p + 1, s), x1 = lam[p] + at(r, Q, p + 1, s + r->a[p]);
+        if (near(x0, x1, tol)) {
+            alt[p] = (int8_t)(1 - x[p]);
+            trace_fwd(r, lam, Q, p + 1, s + (alt[p] ? r->a[p] : 0), alt);
+            for (int q = p; q < L; ++q) if (alt[q] != x[q]) amb[q] = 1;
+        }
+        if (x[p]) s += r->a[p];
+    }
+}
+
+/* Flip bounds of one row's pass adjoint (all arrays indexed by the row's positions). */
+typedef struct {
+    double tol;                          /* decision tolerance of this row */
+    const double *dlo, *dmo;             /* bounds of the adjoints of the pass outputs (NULL: 0) */
+    double *dli, *gS, *dalpha, *domega;  /* outputs: dli, gS set; dalpha, domega accumulated */
+    double *wscale;                      /* output, accumulated: |Mt| s_j, the size of d_omega's rounding
+                                            (d_omega = Mt (m1 - m0), a difference of path costs of size
+                                            s_j = sum_p |lambda_p| of the row) */
+    double *ad;                          /* scratch: bound of ad_new */
+    int8_t *amb0, *amb1, *alt;           /* scratch */
+} taint_t;
 
 /* ------------------------------------------------------------------------------------------ */
 /* One pass of Alg. 1 on one row: BlockUpdate for each hop in pass order.                      */
@@ -482,6 +591,7 @@ int orc_min_marginals(int m, const int64_t *row_ptr, const int32_t *col, const i
 /* Minimizing assignment of every row at lam (the supergradient of (D), Sec. "Loss"). */
 int orc_argmin(int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
                const int64_t *rhs, const double *lam, int8_t *x, double *gap, int nthreads) {
+    /* gap (may be NULL): [2 m], per row the smallest relative and absolute gap (note_gap) */
     size_t tab;
     max_table(m, row_ptr, coef, &tab);
     set_threads(nthreads);
@@ -494,9 +604,11 @@ int orc_argmin(int m, const int64_t *row_ptr, const int32_t *col, const int32_t 
             row_t r;
             int64_t b = row_ptr[j];
             int st = row_init(&r, (int)(row_ptr[j + 1] - b), col + b, coef + b, sense[j], rhs[j]);
+            gap_t g = {INF, INF};
             if (st == ORC_OK) {
                 suffix_table(&r, lam + b, Q);
-                minimizer(&r, lam + b, NULL, Q, -1, 0, x + b, gap ? gap + j : NULL);
+                minimizer(&r, lam + b, NULL, Q, -1, 0, x + b, &g);
+                if (gap) { gap[2 * j] = g.rel; gap[2 * j + 1] = g.abs; }
             } else {
 #pragma omp critical
                 status = st;
@@ -517,9 +629,11 @@ int orc_argmin(int m, const int64_t *row_ptr, const int32_t *col, const int32_t 
 static int row_pass_vjp(const row_t *r, int dir, const double *omega, const double *alpha, const double *S,
                         const double *lam_in, const double *lam_out, const double *dlam_out, const double *dM_out,
                         double *dlam_in, double *gS, double *d_alpha, double *d_omega, double *P, double *Q,
-                        double *lam_h, double *ad_new, int8_t *x0, int8_t *x1, double *gap) {
+                        double *lam_h, double *ad_new, int8_t *x0, int8_t *x1, gap_t *gap, taint_t *tt) {
     const int L = r->L;
     for (int p = 0; p < L; ++p) { ad_new[p] = dlam_out[p]; dlam_in[p] = 0.0; }
+    if (tt)
+        for (int p = 0; p < L; ++p) { tt->ad[p] = tt->dlo ? tt->dlo[p] : 0.0; tt->dli[p] = 0.0; }
     for (int h = L - 1; h >= 0; --h) {
         int l = dir == 0 ? h : L - 1 - h;
         /* position p was visited before hop h iff its pass order is < h */
@@ -532,12 +646,26 @@ static int row_pass_vjp(const row_t *r, int dir, const double *omega, const doub
         double Mt = dM_out[l] - g;     /* Alg. 2: dM_new <- dM_new - dlambda_new */
         d_alpha[l] += g * S[l];        /* Alg. 2: d_alpha += dlambda * sum_k M_ik */
         gS[l] = g * alpha[l];          /* this edge's share of d S_i = sum_k dlambda_ik alpha_ik */
+        double eg = 0.0, eM = 0.0;     /* flip bounds of g and of Mt */
+        if (tt) {
+            eg = tt->ad[l];
+            eM = eg + (tt->dmo ? tt->dmo[l] : 0.0);
+            tt->dli[l] += eg;
+            tt->gS[l] = eg * alpha[l];
+            tt->dalpha[l] += eg * fabs(S[l]);
+        }
         prefix_table(r, lam_h, P);
         suffix_table(r, lam_h, Q);
         double m0, m1;
         marginals(r, P, Q, lam_h, l, &m0, &m1);
         if (m0 == INF || m1 == INF) return ORC_E_FORCED;
         d_omega[l] += Mt * (m1 - m0);  /* dM_new * M_new / omega, written without the division */
+        if (tt) {
+            double sj = 0.0;
+            for (int p = 0; p < L; ++p) sj += fabs(lam_h[p]);
+            tt->domega[l] += eM * fabs(m1 - m0);
+            tt->wscale[l] += fabs(Mt) * sj;
+        }
         minimizer(r, lam_h, P, Q, l, 0, x0, gap);
         minimizer(r, lam_h, P, Q, l, 1, x1, gap);
         double k = omega[l] * Mt;
@@ -548,27 +676,49 @@ static int row_pass_vjp(const row_t *r, int dir, const double *omega, const doub
             if (order < h) ad_new[p] += d;  /* the block saw the updated multiplier */
             else dlam_in[p] += d;           /* the block saw the pass input */
         }
+        if (tt && (k != 0.0 || eM != 0.0)) {
+            /* k = omega Mt moves by at most ek on every position it reaches; a flip of either
+             * minimizer's value at p moves x1[p] - x0[p] by 1, and so the contribution by |k| + ek */
+            const double ek = omega[l] * eM, ef = fabs(k) + ek;
+            memset(tt->amb0, 0, (size_t)L);
+            memset(tt->amb1, 0, (size_t)L);
+            near_ties(r, lam_h, P, Q, l, 0, x0, tt->tol, tt->amb0, tt->alt);
+            near_ties(r, lam_h, P, Q, l, 1, x1, tt->tol, tt->amb1, tt->alt);
+            for (int p = 0; p < L; ++p) {
+                double e = (x1[p] != x0[p] ? ek : 0.0) + (tt->amb0[p] + tt->amb1[p]) * ef;
+                if (e == 0.0) continue;
+                int order = dir == 0 ? p : L - 1 - p;
+                if (order < h) tt->ad[p] += e;
+                else tt->dli[p] += e;
+            }
+        }
     }
     return ORC_OK;
 }
 
-/* VJP of one full pass.  lam_in/M_in: pass input; the pass is re-run here to get lam_out.
- * Outputs dlam_in[E], dM_in[E]; d_alpha[E], d_omega[E] are accumulated (+=).
- * row_gap (may be NULL): per row, the smallest relative gap of its minimizer decisions. */
-int orc_pass_vjp(int n, int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
-                 const int64_t *rhs, const double *omega, const double *alpha, int dir, const double *lam_in,
-                 const double *M_in, const double *dlam_out, const double *dM_out, double *dlam_in, double *dM_in,
-                 double *d_alpha, double *d_omega, double *row_gap, int nthreads) {
+/* Alg. 2 over one pass of the given rows, with the deferred sums S supplied per edge (given S the
+ * rows are independent, so a subset of rows can be differentiated on its own: the adjoints of the
+ * other rows' outputs only reach these rows through dM_in).  lam_in: pass input; the pass is re-run
+ * here to get lam_out.  Per edge: dlam_in (set); gS = dlambda_new * alpha, the edge's share of
+ * dS_i = d M_in_ik (Alg. 2, first line), set; d_alpha, d_omega accumulated (+=).
+ * row_gap (may be NULL): [2 m], per row the smallest relative and absolute gap of its decisions.
+ * row_tol (may be NULL: no tracking): [m] decision tolerance per row; then t_dlo, t_dmo (may be NULL)
+ * are flip bounds of the adjoints of the pass outputs per edge, and t_out [5 E] receives the flip
+ * bounds of dlam_in, gS (set), d_alpha and d_omega (accumulated) -- see near_ties() -- and the
+ * rounding scale of d_omega (accumulated, see taint_t). */
+int orc_rows_pass_vjp(int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
+                      const int64_t *rhs, const double *omega, const double *alpha, const double *S_edge, int dir,
+                      const double *lam_in, const double *dlam_out, const double *dM_out, double *dlam_in,
+                      double *gS, double *d_alpha, double *d_omega, double *row_gap, const double *row_tol,
+                      const double *t_dlo, const double *t_dmo, double *t_out, int nthreads) {
+    if (m < 0 || (dir != 0 && dir != 1)) return ORC_E_ARG;
     int64_t E = row_ptr[m];
     size_t nE = (size_t)(E > 0 ? E : 1);
-    double *Sv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    double *Se = (double *)malloc(sizeof(double) * nE);
     double *lam_out = (double *)malloc(sizeof(double) * nE);
     double *M_out = (double *)malloc(sizeof(double) * nE);
-    double *gS = (double *)calloc(nE, sizeof(double));
-    deferred_sums(n, E, col, M_in, Sv, Se);
     memcpy(lam_out, lam_in, sizeof(double) * (size_t)E);
-    int status = orc_rows_pass(m, row_ptr, col, coef, sense, rhs, omega, alpha, Se, dir, 0, lam_out, M_out, nthreads);
+    int status = orc_rows_pass(m, row_ptr, col, coef, sense, rhs, omega, alpha, S_edge, dir, 0, lam_out, M_out,
+                               nthreads);
     if (status) goto done;
     size_t tab;
     max_table(m, row_ptr, coef, &tab);
@@ -583,47 +733,129 @@ int orc_pass_vjp(int n, int m, const int64_t *row_ptr, const int32_t *col, const
         double *ad_new = (double *)malloc(sizeof(double) * (size_t)(maxL + 1));
         int8_t *x0 = (int8_t *)malloc((size_t)(maxL + 1));
         int8_t *x1 = (int8_t *)malloc((size_t)(maxL + 1));
-#pragma omp for schedule(dynamic, 16)
+        int8_t *scr = (int8_t *)malloc(3 * (size_t)(maxL + 1));
+        double *ad_t = (double *)malloc(sizeof(double) * (size_t)(maxL + 1));
+#pragma omp for schedule(dynamic, 4)
         for (int j = 0; j < m; ++j) {
             row_t r;
             int64_t b = row_ptr[j];
+            gap_t g = {INF, INF};
+            taint_t tt;
+            if (row_tol) {
+                tt.tol = row_tol[j];
+                tt.dlo = t_dlo ? t_dlo + b : NULL;
+                tt.dmo = t_dmo ? t_dmo + b : NULL;
+                tt.dli = t_out + b;
+                tt.gS = t_out + E + b;
+                tt.dalpha = t_out + 2 * E + b;
+                tt.domega = t_out + 3 * E + b;
+                tt.wscale = t_out + 4 * E + b;
+                tt.ad = ad_t;
+                tt.amb0 = scr;
+                tt.amb1 = scr + maxL + 1;
+                tt.alt = scr + 2 * (maxL + 1);
+            }
             int st = row_init(&r, (int)(row_ptr[j + 1] - b), col + b, coef + b, sense[j], rhs[j]);
-            if (row_gap) row_gap[j] = INF;
             if (st == ORC_OK)
-                st = row_pass_vjp(&r, dir, omega + b, alpha + b, Se + b, lam_in + b, lam_out + b, dlam_out + b,
+                st = row_pass_vjp(&r, dir, omega + b, alpha + b, S_edge + b, lam_in + b, lam_out + b, dlam_out + b,
                                   dM_out + b, dlam_in + b, gS + b, d_alpha + b, d_omega + b, P, Q, lam_h, ad_new, x0,
-                                  x1, row_gap ? row_gap + j : NULL);
+                                  x1, &g, row_tol ? &tt : NULL);
+            if (row_gap) { row_gap[2 * j] = g.rel; row_gap[2 * j + 1] = g.abs; }
             if (st) {
 #pragma omp critical
                 status = st;
             }
         }
-        free(P); free(Q); free(lam_h); free(ad_new); free(x0); free(x1);
+        free(P); free(Q); free(lam_h); free(ad_new); free(x0); free(x1); free(scr); free(ad_t);
     }
-    if (status) goto done;
-    /* d M_in_ik = d S_i = sum_j dlambda_new_ij alpha_ij (Alg. 2, first line) */
-    memset(Sv, 0, sizeof(double) * (size_t)n);
-    for (int64_t e = 0; e < E; ++e) Sv[col[e]] += gS[e];
-    for (int64_t e = 0; e < E; ++e) dM_in[e] = Sv[col[e]];
 done:
-    free(Sv); free(Se); free(lam_out); free(M_out); free(gS);
+    free(lam_out); free(M_out);
     return status;
 }
 
-/* Gradient of the final lower bound after T iterations (from lambda = c/|J|, M = 0) with
- * respect to omega, alpha and c: forward run keeping every pass's state, seed
- * dLB/dlambda_bar = argmin assignment (Sec. "Loss"), the flush lambda_bar = lambda + alpha S,
- * then orc_pass_vjp on every pass in reverse, then lambda_0 = c / |J_i|.
- * Variables in no row contribute min(0, c_i) to LB, so dLB/dc_i = [c_i < 0] for them. */
-/* T iterations from (lam0, M0) -- or, when lam0 is NULL, from lambda = c/|J_i|, M = 0 -- then the
- * lower bound and its gradient by Alg. 2 pass by pass in reverse.  d_c is the gradient through
- * lambda_0 = c/|J_i| and the uncovered-variable constant (reset start only; may be NULL);
- * d_lam0 / d_M0 (may be NULL) are the adjoints of the start state. */
+/* VJP of one full pass: S from M_in, orc_rows_pass_vjp over every row, then
+ * d M_in_ik = d S_i = sum_j dlambda_new_ij alpha_ij (Alg. 2, first line).
+ * Outputs dlam_in[E], dM_in[E]; d_alpha[E], d_omega[E] are accumulated (+=); row_gap, row_tol, t_dlo,
+ * t_dmo as there; t_out [5 E] receives the flip bounds of dlam_in and dM_in (set) and of d_alpha and
+ * d_omega (accumulated) -- dM_in's is the sum of its variable's gS bounds -- and d_omega's rounding
+ * scale (accumulated). */
+int orc_pass_vjp(int n, int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
+                 const int64_t *rhs, const double *omega, const double *alpha, int dir, const double *lam_in,
+                 const double *M_in, const double *dlam_out, const double *dM_out, double *dlam_in, double *dM_in,
+                 double *d_alpha, double *d_omega, double *row_gap, const double *row_tol, const double *t_dlo,
+                 const double *t_dmo, double *t_out, int nthreads) {
+    int64_t E = row_ptr[m];
+    size_t nE = (size_t)(E > 0 ? E : 1);
+    double *Sv = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *Se = (double *)malloc(sizeof(double) * nE);
+    double *gS = (double *)calloc(nE, sizeof(double));
+    deferred_sums(n, E, col, M_in, Sv, Se);
+    int status = orc_rows_pass_vjp(m, row_ptr, col, coef, sense, rhs, omega, alpha, Se, dir, lam_in, dlam_out, dM_out,
+                                   dlam_in, gS, d_alpha, d_omega, row_gap, row_tol, t_dlo, t_dmo, t_out, nthreads);
+    if (status == ORC_OK) {
+        memset(Sv, 0, sizeof(double) * (size_t)(n > 0 ? n : 1));
+        for (int64_t e = 0; e < E; ++e) Sv[col[e]] += gS[e];
+        for (int64_t e = 0; e < E; ++e) dM_in[e] = Sv[col[e]];
+        if (row_tol) {  /* bound of dM_in: the bounds of the variable's shares, summed */
+            memset(Sv, 0, sizeof(double) * (size_t)(n > 0 ? n : 1));
+            for (int64_t e = 0; e < E; ++e) Sv[col[e]] += t_out[E + e];
+            for (int64_t e = 0; e < E; ++e) t_out[E + e] = Sv[col[e]];
+        }
+    }
+    free(Sv); free(Se); free(gS);
+    return status;
+}
+
+/* Gradient of the final lower bound after T iterations with respect to omega, alpha and c (or the
+ * start state): T iterations from (lam0, M0) -- or, when lam0 is NULL, from lambda = c/|J_i|, M = 0 --
+ * keeping every pass's state, then the seed dLB/dlambda_bar = argmin assignment (Sec. "Loss"), the
+ * flush lambda_bar = lambda + alpha S, orc_pass_vjp on every pass in reverse, and finally
+ * lambda_0 = c / |J_i|.  d_c (reset start only; may be NULL) is the gradient through lambda_0 and the
+ * uncovered-variable constant: variables in no row contribute min(0, c_i) to LB, so dLB/dc_i = [c_i < 0]
+ * for them.  d_lam0 / d_M0 (may be NULL) are the adjoints of the start state.
+ * row_gap (may be NULL): [2 m], per row the smallest relative and absolute gap (note_gap) of any
+ * decision taken on the way (the seed and every pass).
+ * pass_tol (may be NULL: no tracking): [(2T + 1) m], the decision tolerance of every row in pass
+ * p = 0 .. 2T-1 (at p m) and in the seed (at 2T m); then taint [5 E + n] receives the flip bounds
+ * (near_ties()) of d_omega, d_alpha, d_lam0 and d_M0, the rounding scale of d_omega summed over the
+ * passes (taint_t), and the flip bounds of d_c. */
+static int seed_taint(int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef, const int8_t *sense,
+                      const int64_t *rhs, const double *lam, const int8_t *x, const double *row_tol, int8_t *amb,
+                      int nthreads) {
+    size_t tab;
+    max_table(m, row_ptr, coef, &tab);
+    int maxL = 0;
+    for (int j = 0; j < m; ++j) if (row_ptr[j + 1] - row_ptr[j] > maxL) maxL = (int)(row_ptr[j + 1] - row_ptr[j]);
+    set_threads(nthreads);
+    int status = ORC_OK;
+#pragma omp parallel
+    {
+        double *Q = (double *)malloc(sizeof(double) * tab);
+        int8_t *alt = (int8_t *)malloc((size_t)(maxL + 1));
+#pragma omp for schedule(dynamic, 16)
+        for (int j = 0; j < m; ++j) {
+            row_t r;
+            int64_t b = row_ptr[j];
+            int st = row_init(&r, (int)(row_ptr[j + 1] - b), col + b, coef + b, sense[j], rhs[j]);
+            if (st == ORC_OK) {
+                memset(amb + b, 0, (size_t)r.L);
+                suffix_table(&r, lam + b, Q);
+                near_ties(&r, lam + b, NULL, Q, -1, 0, x + b, row_tol[j], amb + b, alt);
+            } else {
+#pragma omp critical
+                status = st;
+            }
+        }
+        free(Q); free(alt);
+    }
+    return status;
+}
+
 int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, const int32_t *coef,
                       const int8_t *sense, const int64_t *rhs, const double *c, const double *omega,
                       const double *alpha, int T, const double *lam0, const double *M0, double *lb_out,
                       double *d_omega, double *d_alpha, double *d_c, double *d_lam0, double *d_M0,
-                      double *min_gap, int nthreads) {
+                      double *row_gap, const double *pass_tol, double *taint, int nthreads) {
     int64_t E = row_ptr[m];
     size_t nE = (size_t)(E > 0 ? E : 1);
     int npass = 2 * T;
@@ -638,8 +870,21 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
     double *Se = (double *)malloc(sizeof(double) * nE);
     int8_t *x = (int8_t *)malloc(nE);
     int64_t *deg = (int64_t *)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
-    double *gaps = (double *)malloc(sizeof(double) * (size_t)(m > 0 ? m : 1));
-    if (min_gap) *min_gap = INF;
+    double *gaps = (double *)malloc(sizeof(double) * 2 * (size_t)(m > 0 ? m : 1));
+    /* flip bounds: t_dl, t_dM, the pass outputs [4 E] (dl, dM, alpha, omega), per variable [n] */
+    double *t_dl = NULL, *t_dM = NULL, *t_pass = NULL, *t_var = NULL, *t_alpha = NULL, *t_omega = NULL;
+    int8_t *amb = NULL;
+    if (pass_tol) {
+        t_dl = (double *)calloc(nE, sizeof(double));
+        t_dM = (double *)calloc(nE, sizeof(double));
+        t_pass = (double *)calloc(5 * nE, sizeof(double));
+        t_var = (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double));
+        amb = (int8_t *)calloc(nE, 1);
+        t_alpha = taint + E;
+        t_omega = taint;
+        for (size_t q = 0; q < 5 * (size_t)E + (size_t)n; ++q) taint[q] = 0.0;
+    }
+    for (int j = 0; j < 2 * m && row_gap; ++j) row_gap[j] = INF;
     int st = ORC_OK;
     if (lam0) {
         memcpy(lam, lam0, sizeof(double) * (size_t)E);
@@ -658,10 +903,9 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
     st = orc_lower_bound(n, m, row_ptr, col, coef, sense, rhs, c, alpha, lam + nE * npass, M + nE * npass, lb_out,
                          &dlv, lam_bar, nthreads);
     if (st) goto done;
-    for (int j = 0; j < m; ++j) gaps[j] = INF;
     st = orc_argmin(m, row_ptr, col, coef, sense, rhs, lam_bar, x, gaps, nthreads);
     if (st) goto done;
-    for (int j = 0; j < m && min_gap; ++j) *min_gap = fmin(*min_gap, gaps[j]);
+    for (int j = 0; j < 2 * m && row_gap; ++j) row_gap[j] = fmin(row_gap[j], gaps[j]);
     for (int64_t e = 0; e < E; ++e) { d_alpha[e] = 0.0; d_omega[e] = 0.0; }
     /* flush adjoint: lambda_bar_e = lambda_e + alpha_e S_i */
     deferred_sums(n, E, col, M + nE * npass, Sv, Se);
@@ -672,15 +916,44 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
         Sv[col[e]] += (double)x[e] * alpha[e];
     }
     for (int64_t e = 0; e < E; ++e) dM[e] = Sv[col[e]];
+    if (pass_tol) {  /* the seed: a near-tie of the argmin can flip x_e, which moves its terms by 1 * factor */
+        st = seed_taint(m, row_ptr, col, coef, sense, rhs, lam_bar, x, pass_tol + (size_t)npass * m, amb, nthreads);
+        if (st) goto done;
+        for (int64_t e = 0; e < E; ++e) {
+            t_dl[e] = amb[e];
+            t_alpha[e] += amb[e] * fabs(Se[e]);
+            t_var[col[e]] += amb[e] * alpha[e];
+        }
+        for (int64_t e = 0; e < E; ++e) t_dM[e] = t_var[col[e]];
+    }
     for (int p = npass - 1; p >= 0 && st == ORC_OK; --p) {
+        if (pass_tol) memset(t_pass, 0, 5 * nE * sizeof(double));
         st = orc_pass_vjp(n, m, row_ptr, col, coef, sense, rhs, omega, alpha, p % 2, lam + nE * p, M + nE * p, dl, dM,
-                          dl2, dM2, d_alpha, d_omega, gaps, nthreads);
-        for (int j = 0; j < m && min_gap; ++j) *min_gap = fmin(*min_gap, gaps[j]);
+                          dl2, dM2, d_alpha, d_omega, gaps, pass_tol ? pass_tol + (size_t)p * m : NULL, t_dl, t_dM,
+                          t_pass, nthreads);
+        for (int j = 0; j < 2 * m && row_gap; ++j) row_gap[j] = fmin(row_gap[j], gaps[j]);
+        if (pass_tol) {
+            memcpy(t_dl, t_pass, sizeof(double) * (size_t)E);
+            memcpy(t_dM, t_pass + E, sizeof(double) * (size_t)E);
+            for (int64_t e = 0; e < E; ++e) {
+                t_alpha[e] += t_pass[2 * E + e];
+                t_omega[e] += t_pass[3 * E + e];
+                taint[4 * E + e] += t_pass[4 * E + e];
+            }
+        }
         double *t;
         t = dl; dl = dl2; dl2 = t;
         t = dM; dM = dM2; dM2 = t;
     }
     if (st) goto done;
+    if (pass_tol) {
+        memcpy(taint + 2 * E, t_dl, sizeof(double) * (size_t)E);
+        memcpy(taint + 3 * E, t_dM, sizeof(double) * (size_t)E);
+        double *tc = taint + 5 * E;
+        for (int64_t e = 0; e < E; ++e) deg[col[e]]++;
+        for (int64_t e = 0; e < E; ++e) tc[col[e]] += t_dl[e] / (double)deg[col[e]];
+        for (int64_t e = 0; e < E; ++e) deg[col[e]] = 0;
+    }
     if (d_lam0) memcpy(d_lam0, dl, sizeof(double) * (size_t)E);
     if (d_M0) memcpy(d_M0, dM, sizeof(double) * (size_t)E);
     if (d_c) {
@@ -690,7 +963,7 @@ int orc_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col, 
     }
 done:
     free(lam); free(M); free(lam_bar); free(dl); free(dM); free(dl2); free(dM2); free(Sv); free(Se); free(x);
-    free(deg); free(gaps);
+    free(deg); free(gaps); free(t_dl); free(t_dM); free(t_pass); free(t_var); free(amb);
     return st;
 }
 

@@ -13,6 +13,18 @@ from __future__ import annotations
 
 import torch
 
+from .binding import DD_E_STATE, DDError
+
+
+def _check_record(ctx):
+    """The instance's recorded forward must still be this node's: a later forward on the same
+    instance (another node of the graph) replaces it, and its backward would differentiate that one."""
+    now = ctx.inst.record_serial()
+    if now != ctx.serial:
+        raise DDError(DD_E_STATE, f"this node's unrolled forward (record {ctx.serial}) is no longer the "
+                                  f"instance's record ({now}): run its backward before another forward "
+                                  "on the same instance, or use one instance per node")
+
 
 class DualLowerBound(torch.autograd.Function):
     @staticmethod
@@ -25,6 +37,7 @@ class DualLowerBound(torch.autograd.Function):
         inst.set_params(om, alpha)
         lb = inst.forward_unrolled(int(T), int(ckpt_every))
         ctx.inst = inst
+        ctx.serial = inst.record_serial()
         ctx.save_for_backward(alpha)
         ctx.dtypes = (c.dtype, omega.dtype, alpha_hat.dtype)
         return torch.tensor(lb, dtype=torch.float64, device=c.device)
@@ -33,6 +46,7 @@ class DualLowerBound(torch.autograd.Function):
     def backward(ctx, grad):
         (alpha,) = ctx.saved_tensors
         inst = ctx.inst
+        _check_record(ctx)
         d_omega, d_alpha, d_c = inst.backward(float(grad.item()))
         d_alpha_hat = inst.seg_softmax_vjp(alpha, d_alpha)
         tc, tw, ta = ctx.dtypes
@@ -59,6 +73,7 @@ class DualRound(torch.autograd.Function):
         inst.nonparam_update(th)
         lb = inst.forward_unrolled_from_state(int(T), int(ckpt_every))
         ctx.inst = inst
+        ctx.serial = inst.record_serial()
         ctx.save_for_backward(omega, alpha)
         ctx.dtypes = (omega_hat.dtype, alpha_hat.dtype, theta_hat.dtype)
         return torch.tensor(lb, dtype=torch.float64, device=omega_hat.device)
@@ -67,6 +82,7 @@ class DualRound(torch.autograd.Function):
     def backward(ctx, grad):
         omega, alpha = ctx.saved_tensors
         inst = ctx.inst
+        _check_record(ctx)
         d_omega, d_alpha, d_lam0, _ = inst.backward_state(float(grad.item()))
         # lambda_0 = lambda_prev + theta_hat - mean over J_i: its adjoint is the centring of d_lam0
         dwh, dah, dth = inst.param_transform_vjp(omega, alpha, d_omega, d_alpha, d_lam0)

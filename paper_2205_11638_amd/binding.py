@@ -78,6 +78,7 @@ SIGNATURES = {
     "dd_set_costs": ([_VP, _VP, _VP], C.c_int),
     "dd_forward_unrolled": ([_VP, C.c_int32, C.c_int32, C.POINTER(C.c_double), _VP], C.c_int),
     "dd_backward": ([_VP, C.c_double, _VP, _VP, _VP, _VP], C.c_int),
+    "dd_record_serial": ([_VP, C.POINTER(C.c_int64)], C.c_int),
     "dd_pass_vjp": ([_VP, C.c_int32, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
     "dd_seg_softmax_vjp": ([_VP, _VP, _VP, _VP, _VP], C.c_int),
     "dd_profile_begin": ([_VP, C.c_int32], C.c_int),
@@ -320,6 +321,12 @@ class Instance:
         dw, da, dc = self._f32(self.E), self._f32(self.E), self._f32(self.n)
         _check(self._L.dd_backward(self._h, float(dlb), _dptr(dw), _dptr(da), _dptr(dc), _stream()))
         return dw, da, dc
+
+    def record_serial(self):
+        """Serial of the recorded unrolled forward (-1: none valid)."""
+        v = C.c_int64()
+        _check(self._L.dd_record_serial(self._h, C.byref(v)))
+        return v.value
 
     def forward_unrolled_from_state(self, T, ckpt_every=0):
         lb = C.c_double()

@@ -196,6 +196,7 @@ int dd_autotune(dd_instance *h, const char *cache_path, int32_t *from_cache, voi
         HIP_TRY(hipMemcpyAsync(h->T.lam, lam0, bytes, hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(h->T.M, M0, bytes, hipMemcpyDeviceToDevice, s));
         h->version++;
+        h->f_valid = false;  // the timed passes left F at other multipliers
         if ((st = recompute_B(h, s))) return st;
         HIP_TRY(hipStreamSynchronize(s));
         return DD_OK;

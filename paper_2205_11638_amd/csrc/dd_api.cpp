@@ -388,7 +388,28 @@ std::string kname(const char *k, const ClassLaunch &cl) {
     return name;
 }
 
+int all_classes_launch(dd_instance *h, bool fwd, int mode, hipStream_t s);
+
+// Which node-cost array holds the costs at the current multipliers after a sweep of this mode.
+void note_sweep(dd_instance *h, bool fwd, int mode) {
+    if (fwd) {
+        h->f_valid = mode != FWD_SWEEP_BAR;  // every forward sweep writes F; at lambda_bar it is not F(lambda)
+        if (mode == FWD_UPDATE || mode == FWD_UPDATE_REC) h->b_valid = false;
+    } else if (mode == BWD_UPDATE || mode == BWD_UPDATE_REC || mode == BWD_STORE) {
+        h->b_valid = true;
+        if (mode != BWD_STORE) h->f_valid = false;
+    } else if (mode == BWD_STORE_BAR) {
+        h->b_valid = false;
+    }
+}
+
 int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s) {
+    const int st = all_classes_launch(h, fwd, mode, s);
+    if (st == DD_OK) note_sweep(h, fwd, mode);
+    return st;
+}
+
+int all_classes_launch(dd_instance *h, bool fwd, int mode, hipStream_t s) {
     return per_class(
         h, s,
         [&](const ClassLaunch &cl, hipStream_t cs) {
@@ -748,6 +769,7 @@ int dd_reset(dd_instance *h, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_init_lambda(h->canon2slot, h->T.evar, h->var_ptr, h->cdev, h->T.lam, h->T.M, h->E, s));
     h->version++;
+    h->f_valid = h->b_valid = false;
     return recompute_B(h, s);
 }
 
@@ -757,6 +779,7 @@ int dd_set_state(dd_instance *h, const float *lambda, const float *M, void *stre
     HIP_TRY(launch_scatter(h->canon2slot, lambda, h->T.lam, h->E, s));
     HIP_TRY(launch_scatter(h->canon2slot, M, h->T.M, h->E, s));
     h->version++;
+    h->f_valid = h->b_valid = false;
     return recompute_B(h, s);
 }
 
@@ -774,11 +797,19 @@ int dd_get_state(dd_instance *h, float *lambda_out, float *M_out, int32_t flushe
 
 int dd_run_pass(dd_instance *h, int32_t direction, void *stream) {
     if (!h || (direction != 0 && direction != 1)) return fail(DD_E_ARG, "bad instance or direction");
+    hipStream_t s = (hipStream_t)stream;
+    // the pass reads the other side's node costs at its input multipliers (eq. 8 for hops not yet
+    // visited): rebuild them when the last call left them stale (two passes of one direction in a
+    // row, or a call that changed the multipliers or the arrays without a sweep)
+    int st = DD_OK;
+    if (direction == 0 && !h->b_valid) st = recompute_B(h, s);
+    if (direction == 1 && !h->f_valid) st = all_classes(h, true, FWD_SWEEP_LAM, s);
+    if (st) return st;
     // a backward pass ends with B(root) = E^j at the updated multipliers; a forward pass
     // changes the multipliers without computing it
     h->en_lam_valid = false;
     h->version++;
-    int st = pass_launches(h, direction, (hipStream_t)stream);
+    st = pass_launches(h, direction, s);
     h->en_lam_valid = st == DD_OK && direction == 1;
     return st;
 }
@@ -837,6 +868,7 @@ int dd_run(dd_instance *h, int32_t T, void *stream) {
         return DD_OK;
     }
     int st;
+    if (!h->b_valid && (st = recompute_B(h, s))) return st;  // what the first forward pass reads
     if (!h->graph_one && (st = capture_iterations(h, 1, &h->graph_one))) return st;
     if (T >= kGraphChunk && !h->graph_chunk && (st = capture_iterations(h, kGraphChunk, &h->graph_chunk)))
         return st;
@@ -846,6 +878,8 @@ int dd_run(dd_instance *h, int32_t T, void *stream) {
     for (; t < T; ++t) HIP_TRY(hipGraphLaunch(h->graph_one, s));
     h->version += 2 * (int64_t)T;
     h->en_lam_valid = true;
+    h->b_valid = true;  // the last pass replayed was a backward pass (capture ran no sweep)
+    h->f_valid = false;
     return DD_OK;
 }
 
@@ -1022,6 +1056,7 @@ int save_state(dd_instance *h, std::vector<float *> &L, std::vector<float *> &Mv
 int load_state(dd_instance *h, const std::vector<float *> &L, const std::vector<float *> &Mv, size_t i,
                hipStream_t s) {
     HIP_TRY(launch_copy2(L[i], h->T.lam, Mv[i], h->T.M, h->edge_slots, s));
+    h->f_valid = h->b_valid = false;
     return DD_OK;
 }
 
@@ -1039,6 +1074,7 @@ int dd_pass_vjp(dd_instance *h, int32_t direction, const float *lam_in, const fl
     if (st) return st;
     HIP_TRY(launch_scatter(h->canon2slot, lam_in, h->T.lam, h->E, s));
     HIP_TRY(launch_scatter(h->canon2slot, M_in, h->T.M, h->E, s));
+    h->f_valid = h->b_valid = false;
     HIP_TRY(launch_scatter(h->canon2slot, dlam_out, h->dlamA, h->E, s));
     HIP_TRY(launch_scatter(h->canon2slot, dM_out, h->dMA, h->E, s));
     HIP_TRY(launch_fill(h->dalpha, 0.f, h->edge_slots, s));
@@ -1182,6 +1218,8 @@ int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void 
     const hipError_t e = hipMemcpyAsync(h->B0, h->trB[T], bytes, hipMemcpyDeviceToDevice, s);
     h->T.F = h->F0;
     h->T.B = h->B0;
+    h->b_valid = true;   // B of the final state, copied back
+    h->f_valid = false;  // the instance's own F was not written
     if (st) return st;
     if (e != hipSuccess) return fail(DD_E_HIP, "copy of the final B: %s", hipGetErrorString(e));
     h->fwd_T = T;
@@ -1189,6 +1227,7 @@ int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void 
     h->fwd_stored = true;
     h->fwd_from_state = from_state;
     h->fwd_version = h->version;
+    h->fwd_serial++;
     return DD_OK;
 }
 
@@ -1219,6 +1258,7 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
     h->fwd_K = K;
     h->fwd_from_state = from_state;
     h->fwd_version = h->version;
+    h->fwd_serial++;
     return DD_OK;
 }
 
@@ -1313,6 +1353,7 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     // final B in B0, which the backward sweep did not touch)
     if (stored) {
         if ((st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)T, s))) return st;
+        h->b_valid = true;  // B0 still holds the final B
     } else {
         if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;
         if ((st = recompute_B(h, s))) return st;
@@ -1331,6 +1372,12 @@ int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *l
 
 int dd_forward_unrolled_from_state(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream) {
     return forward_unrolled(h, T, ckpt_every, lb, true, stream);
+}
+
+int dd_record_serial(const dd_instance *h, int64_t *serial) {
+    if (!h || !serial) return fail(DD_E_ARG, "NULL argument");
+    *serial = h->fwd_T >= 0 && h->fwd_version == h->version ? h->fwd_serial : -1;
+    return DD_OK;
 }
 
 int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream) {
@@ -1367,6 +1414,7 @@ int dd_nonparam_update(dd_instance *h, const float *theta_hat, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     HIP_TRY(launch_nonparam_update(h->var_ptr, h->var_canon, h->canon2slot, theta_hat, h->T.lam, (int)h->n, s));
     h->version++;
+    h->f_valid = h->b_valid = false;
     return recompute_B(h, s);
 }
 

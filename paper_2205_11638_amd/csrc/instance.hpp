@@ -64,6 +64,10 @@ struct dd_instance {
     double *red = nullptr;   // device reduction output [4]
     double *partial = nullptr;  // [kSumBlocks] reduction scratch
     bool en_lam_valid = false;  // T.en_lam holds E^j at the current multipliers
+    // T.B / T.F hold the node costs at the current multipliers: what a forward / backward update
+    // pass reads (a forward pass leaves F valid and B stale, a backward pass the opposite)
+    bool b_valid = false, f_valid = false;
+    int64_t fwd_serial = 0;  // serial of the recorded unrolled forward (incremented by every one)
     // reverse mode (buffers allocated on first use)
     bool adj_ready = false;
     float *lam_in = nullptr, *dlamA = nullptr, *dlamB = nullptr, *dMA = nullptr, *dMB = nullptr, *g = nullptr;

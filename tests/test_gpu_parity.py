@@ -295,6 +295,50 @@ def test_knapsack_full_sampled_rows(orc):
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("wl", ["gm-small", "knapsack-small"])
+def test_passes_after_calls_that_leave_a_side_stale(orc, wl):
+    """A pass reads the other side's shortest-path costs at its input multipliers (B for a forward
+    pass, F for a backward pass).  After set_state, after a pass of the same direction and after a
+    min-marginal query (whose sweep reuses the F array at lambda_bar) the library rebuilds that side:
+    each pass equals one oracle pass from the same input."""
+    import torch
+    if wl == "gm-small":
+        w = synth.workload("gm", small=True)
+        p, omega, ah = w["problem"], w["omega"], w["alpha_hat"]
+    else:
+        p = synth.knapsack(n=3000, m=30, seed=9)
+        rng = np.random.default_rng(2)
+        omega, ah = synth.sigmoid(rng.normal(size=p.nnz)), rng.normal(0, 0.3, size=p.nnz)
+    inst, om, al = make_instance(p, f32(omega), f32(ah))
+    om64, al64 = host(om), host(al)
+
+    def check(direction, what):
+        lam_in, M_in = (host(t) for t in inst.get_state())
+        inst.run_pass(direction)
+        lam_g, M_g = (host(t) for t in inst.get_state())
+        lo, Mo = lam_in.copy(), M_in.copy()
+        orc.run_pass(p, om64, al64, lo, Mo, direction)
+        sc = row_scale(p, lo)
+        assert_close_scaled(lam_g, lo, sc, RTOL, f"{wl} {what} lambda")
+        assert_close_scaled(M_g, Mo, sc, RTOL, f"{wl} {what} M")
+
+    inst.run(2)
+    lam, M = (t.clone() for t in inst.get_state())
+    inst.run(1)
+    inst.set_state(lam, M)
+    check(1, "backward after set_state")
+    check(1, "backward after backward")
+    check(0, "forward after backward")
+    check(0, "forward after forward")
+    inst.min_marginals()
+    check(1, "backward after min-marginals")
+    inst.set_state(lam, M)
+    check(0, "forward after set_state")
+    inst.min_marginals()
+    check(1, "backward after forward and min-marginals")
+    torch.cuda.synchronize()
+
+
 def test_bad_parameters_rejected():
     import torch
 

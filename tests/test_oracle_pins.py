@@ -447,6 +447,175 @@ def test_argmin_gap_reports_ties(orc):
     assert g[0] == 0.0
     _, g = orc.argmin(q, np.array([-1.0, -1.25, 0.5]), with_gap=True)
     assert g[0] > 0.1
+    # absolute gaps: first decision takes var 1 (-1.25) over var 0 (-1): |(-1) - (-1.25)| = 0.25
+    _, rel, ab = orc.argmin(q, np.array([-1.0, -1.25, 0.5]), row_gaps=True)
+    assert ab[0] == 0.25 and rel[0] == pytest.approx(0.25 / 1.25)
+
+
+# ------------------------------------------------------------------------------------------
+# Alg. 2 on a subset of rows with S given per edge, and the trajectory helpers
+# ------------------------------------------------------------------------------------------
+
+def _torch_rows_pass(p, W, A, lam, Se, direction):
+    """A pass over every row with the deferred sums given per edge, by enumeration (torch f64)."""
+    sets = [torch.tensor(X, dtype=torch.float64) for X in brute.row_sets(p)]
+    lo_parts, M_parts = [], []
+    for j, X in enumerate(sets):
+        a, b = int(p.row_ptr[j]), int(p.row_ptr[j + 1])
+        lj = [lam[a + l] for l in range(b - a)]
+        Mj = [None] * (b - a)
+        for l in (range(b - a) if direction == 0 else range(b - a - 1, -1, -1)):
+            cost = X @ torch.stack(lj)
+            Mn = W[a + l] * (cost[X[:, l] == 1].min(dim=0).values - cost[X[:, l] == 0].min(dim=0).values)
+            lj[l] = lj[l] - Mn + A[a + l] * Se[a + l]
+            Mj[l] = Mn
+        lo_parts += lj
+        M_parts += Mj
+    return torch.stack(lo_parts), torch.stack(M_parts)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_rows_pass_vjp_matches_autograd(orc, seed):
+    """Alg. 2 with S given per edge: the adjoint of S_edge is exactly the edge's share gS = dlambda' alpha."""
+    p = tiny(seed + 700, n=9, m=6, kmax=6)
+    om, ah = learned_params(p, seed + 1)
+    al = orc.softmax_alpha(p, ah)
+    rng = np.random.default_rng(seed + 2)
+    lam, Se = rng.normal(size=p.nnz), rng.normal(0.0, 0.3, size=p.nnz)
+    for direction in (0, 1):
+        dlo, dmo = rng.normal(size=p.nnz), rng.normal(size=p.nnz)
+        dli, gS, da, dw, _, _ = orc.rows_pass_vjp(p, om, al, Se, direction, lam, dlo, dmo)
+        L = torch.tensor(lam, requires_grad=True)
+        S = torch.tensor(Se, requires_grad=True)
+        A = torch.tensor(al, requires_grad=True)
+        W = torch.tensor(om, requires_grad=True)
+        lo, Mo = _torch_rows_pass(p, W, A, L, S, direction)
+        (lo @ torch.tensor(dlo) + Mo @ torch.tensor(dmo)).backward()
+        np.testing.assert_allclose(dli, L.grad.numpy(), atol=1e-10)
+        np.testing.assert_allclose(gS, S.grad.numpy(), atol=1e-10)
+        np.testing.assert_allclose(da, A.grad.numpy(), atol=1e-10)
+        np.testing.assert_allclose(dw, W.grad.numpy(), atol=1e-10)
+        lo_o, Mo_o = orc.rows_pass(p, om, al, Se, lam, direction)
+        np.testing.assert_allclose(lo_o, lo.detach().numpy(), atol=1e-12)
+
+
+def test_rows_pass_vjp_on_a_subset_equals_the_whole_pass(orc):
+    """Given S, rows are independent: the adjoint of a row subset (S from the whole program's M) equals
+    the whole pass's adjoint when the other rows' output adjoints are zero; those rows then get
+    exactly zero, and dM_in is the per-variable sum of the subset's shares."""
+    w = synth.workload("gm", small=True)
+    p = w["problem"]
+    om, ah = learned_params(p, 21)
+    al = orc.softmax_alpha(p, ah)
+    lam, M = orc.run(p, om, al, 2)
+    rng = np.random.default_rng(22)
+    rows = np.sort(rng.choice(p.m, size=p.m // 5, replace=False))
+    sub = p.subset_rows(rows)
+    eidx = np.concatenate([np.arange(p.row_ptr[r], p.row_ptr[r + 1]) for r in rows])
+    on = np.zeros(p.nnz, bool)
+    on[eidx] = True
+    var = p.col.astype(np.int64)
+    S = np.zeros(p.n)
+    np.add.at(S, var, M)
+    for direction in (0, 1):
+        dlo, dmo = rng.normal(size=p.nnz) * on, rng.normal(size=p.nnz) * on
+        dli, dmi, da, dw = orc.pass_vjp(p, om, al, direction, lam, M, dlo, dmo)
+        dli_s, gS_s, da_s, dw_s, _, _ = orc.rows_pass_vjp(sub, om[eidx], al[eidx], S[var[eidx]], direction, lam[eidx],
+                                                          dlo[eidx], dmo[eidx])
+        np.testing.assert_allclose(dli[eidx], dli_s, atol=1e-12)
+        np.testing.assert_allclose(da[eidx], da_s, atol=1e-12)
+        np.testing.assert_allclose(dw[eidx], dw_s, atol=1e-12)
+        assert not dli[~on].any() and not da[~on].any() and not dw[~on].any()
+        gv = np.zeros(p.n)
+        np.add.at(gv, var[eidx], gS_s)
+        np.testing.assert_allclose(dmi, gv[var], atol=1e-12)
+
+
+def test_unrolled_grad_along_its_own_trajectory(orc):
+    """The chain over supplied states reproduces unrolled_grad on the oracle's own trajectory."""
+    p = synth.workload("gm", small=True)["problem"]
+    om, ah = learned_params(p, 31)
+    al = orc.softmax_alpha(p, ah)
+    lb, dw, da, dc = orc.unrolled_grad(p, om, al, 4)
+    states = orc.trajectory(p, om, al, 4)
+    lb2, dw2, da2, dc2 = orc.unrolled_grad_along(p, om, al, states)
+    assert lb2 == lb
+    for a, b in ((dw, dw2), (da, da2), (dc, dc2)):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12 * np.abs(a).max())
+    lam, M = orc.run(p, om, al, 4)
+    np.testing.assert_array_equal(states[-1][0], lam)
+    r = orc.trajectory(p, om, al, 4, round_f32=True)
+    assert all((s[0] == s[0].astype(np.float32)).all() for s in r[1:])
+
+
+# ------------------------------------------------------------------------------------------
+# Flip bounds: how far near-tie decisions can move the adjoint (the oracle's account of which
+# outputs are determined).  Pinned by resolving exact ties both ways with tiny perturbations.
+# ------------------------------------------------------------------------------------------
+
+def _tied_rows(seed):
+    """Unit-coefficient rows (sum x <= b and sum x >= b) with continuous costs, in which two
+    variables of every row get the same multiplier: one exact tie per row."""
+    rng = np.random.default_rng(seed)
+    n, rows = 14, []
+    for j in range(5):
+        k = int(rng.integers(4, 7))
+        cols = rng.choice(n, size=k, replace=False)
+        rows.append((cols, np.ones(k, np.int64), int(rng.choice([-1, 1])), int(rng.integers(1, k))))
+    p = synth.generators._from_rows(n, rng.normal(size=n), rows, "tied")
+    lam = rng.normal(size=p.nnz)
+    for j in range(p.m):
+        a, b = int(p.row_ptr[j]), int(p.row_ptr[j + 1])
+        i1, i2 = rng.choice(np.arange(a, b), size=2, replace=False)
+        lam[i2] = lam[i1]
+    return p, lam, rng
+
+
+def test_flip_bounds_zero_without_ties(orc):
+    """A tolerance below every row's smallest decision gap flags nothing; one above it does."""
+    p = tiny(801, n=10, m=6, kmax=6)
+    om, ah = learned_params(p, 2)
+    al = orc.softmax_alpha(p, ah)
+    lam, M = orc.run(p, om, al, 1)
+    rng = np.random.default_rng(3)
+    dlo, dmo = rng.normal(size=p.nnz), rng.normal(size=p.nnz)
+    *r, rel, ab = orc.pass_vjp(p, om, al, 0, lam, M, dlo, dmo, row_gaps=True)
+    ab = np.where(np.isfinite(ab), ab, 1.0)  # rows with no two-way decision
+    assert (ab > 0).all()
+    *r2, bnd = orc.pass_vjp(p, om, al, 0, lam, M, dlo, dmo, row_tol=0.5 * ab)
+    assert not bnd[:4].any()
+    for a, b in zip(r, r2):
+        np.testing.assert_array_equal(a, b)
+    *_, bnd = orc.pass_vjp(p, om, al, 0, lam, M, dlo, dmo, row_tol=2.0 * ab)
+    assert bnd[:4].any()
+
+
+def test_flip_bounds_cover_tie_resolutions(orc):
+    """At a point with exact ties, nudging a tied multiplier by +-eps resolves each tie one way or the
+    other (and moves no other decision): every resolved adjoint must lie within the flip bounds
+    computed at the tied point, and the ties must matter (the pin is not vacuous)."""
+    eps, tol = 1e-9, 1e-7
+    seeds_moved = 0
+    for seed in range(8):
+        p, lam, rng = _tied_rows(900 + seed)
+        om = synth.sigmoid(rng.normal(size=p.nnz))
+        al = orc.softmax_alpha(p, rng.normal(0.0, 0.5, size=p.nnz))
+        M = rng.normal(0.0, 0.2, size=p.nnz)
+        moved = 0
+        for direction in (0, 1):
+            dlo, dmo = rng.normal(size=p.nnz), rng.normal(size=p.nnz)
+            *base, bnd = orc.pass_vjp(p, om, al, direction, lam, M, dlo, dmo, row_tol=np.full(p.m, tol))
+            for e in range(p.nnz):
+                for sgn in (1.0, -1.0):
+                    lp = lam.copy()
+                    lp[e] += sgn * eps
+                    pert = orc.pass_vjp(p, om, al, direction, lp, M, dlo, dmo)
+                    for q, (x, y) in enumerate(zip(pert, base)):
+                        slack = 1e-6 * max(1.0, np.abs(y).max())  # continuous parts move by O(eps)
+                        assert (np.abs(x - y) <= bnd[q] + slack).all(), (seed, direction, e, q)
+                        moved += int((np.abs(x - y) > slack).any())
+        seeds_moved += moved > 0
+    assert seeds_moved >= 5
 
 
 # ------------------------------------------------------------------------------------------
