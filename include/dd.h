@@ -259,6 +259,16 @@ int dd_seg_softmax_vjp(dd_instance *h, const float *alpha, const float *d_alpha,
  * allocates a node-sized scratch array kept until dd_destroy. */
 int dd_smoothed(dd_instance *h, float tau, int32_t flushed, float *E_out, float *p_out, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): dd_smoothed, with the node scratch of its sweeps taken
+ * from a 16 MiB array per GPU that the library reserves when it is loaded and holds until the
+ * process ends, instead of an array allocated on first use.  Allocates nothing; same kernels and
+ * results as dd_smoothed.  Limit: instances of at most 4,194,240 node slots (dd_stats.node_slots);
+ * larger ones get DD_E_ARG.  The current device must be the instance's (DD_E_ARG otherwise).  Every
+ * call on one GPU uses that GPU's one array: calls that overlap on a GPU (other streams or threads)
+ * race on it and must be serialized by the caller. */
+int dd_smoothed_noalloc(dd_instance *h, float tau, int32_t flushed, float *E_out, float *p_out, void *stream);
+
 /* Minimizing assignment of every row (a subgradient of the dual objective, Sec. "Loss"), 0/1 per
  * edge into x_out [edges] (f32, canonical order), at lambda or lambda_bar; ties: lo arcs first. */
 int dd_argmin_assignment(dd_instance *h, int32_t flushed, float *x_out, void *stream);

@@ -90,6 +90,7 @@ SIGNATURES = {
     "dd_param_transform_vjp": ([_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP], C.c_int),
     "dd_nonparam_update": ([_VP, _VP, _VP], C.c_int),
     "dd_smoothed": ([_VP, C.c_float, C.c_int32, _VP, _VP, _VP], C.c_int),
+    "dd_smoothed_noalloc": ([_VP, C.c_float, C.c_int32, _VP, _VP, _VP], C.c_int),
     "dd_argmin_assignment": ([_VP, C.c_int32, _VP, _VP], C.c_int),
     "dd_solve": ([_VP, C.c_int32, C.c_int32, C.c_double, _VP, _VP, C.POINTER(C.c_int32), _VP], C.c_int),
     "dd_gap_integral": ([_VP, _VP, C.c_int32, C.c_double, _VP, C.POINTER(C.c_double)], C.c_int),
@@ -374,6 +375,14 @@ class Instance:
         E, pm = self._f32(self.m), self._f32(self.E)
         _check(self._L.dd_smoothed(self._h, float(tau), int(bool(flushed)), _dptr(E), _dptr(pm), _stream()))
         return E, pm
+
+    def smoothed_noalloc(self, tau, E_out, p_out, flushed=False):
+        """As smoothed, into caller-allocated device tensors (E_out [m], p_out [E]), with the library's
+        static per-GPU scratch: the call itself allocates nothing."""
+        import torch
+        _check(self._L.dd_smoothed_noalloc(self._h, float(tau), int(bool(flushed)),
+                                           _dptr(E_out, torch.float32, self.m), _dptr(p_out, torch.float32, self.E),
+                                           _stream()))
 
     def argmin_assignment(self, flushed=False):
         x = self._f32(self.E)

@@ -19,7 +19,7 @@ ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
 HOST_SRC = ["bdd.cpp", "dd_api.cpp", "batch.cpp", "autotune.cpp"]
-DEVICE_SRC = ["kernels.hip", "adjoint.hip", "features.hip"]
+DEVICE_SRC = ["kernels.hip", "adjoint.hip", "features.hip", "noalloc.hip"]
 # packed-fp32 instructions are disabled for all device code
 # -fno-honor-nans: the solver never forms NaN (infinite costs only mark 0-terminal arcs and
 # are never subtracted), so min/max need no NaN-quieting; parameter checks use bit tests.

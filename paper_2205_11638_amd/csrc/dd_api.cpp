@@ -456,6 +456,20 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
 
 int deferred(dd_instance *h, hipStream_t s) { return deferred_from(h, h->T.M, s); }
 
+int smoothed_sweeps(dd_instance *h, float *Bs, float tau, int flushed, float *E_out, float *p_out, hipStream_t s) {
+    int st;
+    if (flushed && (st = deferred(h, s))) return st;
+    if (E_out) HIP_TRY(launch_fill(E_out, 0.f, h->m, s));  // rows with no variable: E = 0
+    return per_class(
+        h, s, [&](const ClassLaunch &cl, hipStream_t cs) {
+            return launch_smooth(h->T, cl, Bs, tau, flushed ? 1 : 0, E_out, p_out, cs);
+        },
+        [&](const ClassLaunch &cl) { return kname("k_smooth", cl); },
+        // per node: topology twice, the soft-min cost written, read back and gathered for two
+        // children (24 B); per edge: multipliers (and alpha*S) twice, the marginal and its index
+        [&](const ClassLaunch &cl) { return 24.0 * cl.nodes + 24.0 * cl.edges; });
+}
+
 // S_i of the given M (without alpha * S per edge)
 int deferred_sum(dd_instance *h, const float *M, hipStream_t s) {
     return recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 12.0 * (double)h->n, s, [&] {
@@ -1420,19 +1434,9 @@ int dd_nonparam_update(dd_instance *h, const float *theta_hat, void *stream) {
 
 int dd_smoothed(dd_instance *h, float tau, int32_t flushed, float *E_out, float *p_out, void *stream) {
     if (!h || !(tau > 0.f) || !std::isfinite(tau) || (h->E && !p_out)) return fail(DD_E_ARG, "bad argument");
-    hipStream_t s = (hipStream_t)stream;
     int st;
     if (!h->Bs && (st = h->alloc(&h->Bs, (size_t)(h->node_slots + 64)))) return st;
-    if (flushed && (st = deferred(h, s))) return st;
-    if (E_out) HIP_TRY(launch_fill(E_out, 0.f, h->m, s));  // rows with no variable: E = 0
-    return per_class(
-        h, s, [&](const ClassLaunch &cl, hipStream_t cs) {
-            return launch_smooth(h->T, cl, h->Bs, tau, flushed ? 1 : 0, E_out, p_out, cs);
-        },
-        [&](const ClassLaunch &cl) { return kname("k_smooth", cl); },
-        // per node: topology twice, the soft-min cost written, read back and gathered for two
-        // children (24 B); per edge: multipliers (and alpha*S) twice, the marginal and its index
-        [&](const ClassLaunch &cl) { return 24.0 * cl.nodes + 24.0 * cl.edges; });
+    return smoothed_sweeps(h, h->Bs, tau, flushed, E_out, p_out, (hipStream_t)stream);
 }
 
 int dd_argmin_assignment(dd_instance *h, int32_t flushed, float *x_out, void *stream) {

@@ -159,6 +159,9 @@ int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s);
 int recompute_B(dd_instance *h, hipStream_t s);
 // The launches of one pass (deferred sums, then the update sweep of every class); host flags untouched.
 int pass_launches(dd_instance *h, int dir, hipStream_t s);
+// The smoothed-subproblem sweeps of every class (soft-min costs into Bs, a node array of at least
+// node_slots + 64 floats whose prior contents are never read), E_out / p_out as dd_smoothed.
+int smoothed_sweeps(dd_instance *h, float *Bs, float tau, int flushed, float *E_out, float *p_out, hipStream_t s);
 // Forget captured iteration graphs (after a change of launch shapes).
 void drop_graphs(dd_instance *h);
 
