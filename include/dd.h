@@ -55,7 +55,9 @@ enum {
     DD_E_UNSUPPORTED = -6, /* a row's decision diagram is wider than the kernels support */
     DD_E_OOM = -7,         /* device or host allocation failed */
     DD_E_NONFINITE = -8,   /* a reduced bound is not finite */
-    DD_E_STATE = -9        /* call out of order (e.g. backward without a recorded forward) */
+    DD_E_STATE = -9,       /* call out of order (e.g. backward without a recorded forward) */
+    DD_E_CHECKPOINT = -10  /* a checkpoint of the unrolled forward changed, or recomputing from it did not
+                              reproduce the next one (dd_backward) */
 };
 
 /* Binary program (Def. 1): min <c, x> s.t. each row  sum_p coef[p] x[col[p]]  (sense)  rhs,
@@ -85,8 +87,16 @@ typedef struct {
     int32_t adj_replay;     /* nonzero: the checkpointed backward sweep recomputes each segment's pass
                                inputs and replays every pass for its adjoint instead of storing the
                                segment's node costs (no device memory beyond the checkpoints) */
-    int32_t reserved[1];
+    int32_t lb_every;       /* default iterations between the bounds dd_run_trace records, default 1 */
+    int64_t max_device_bytes; /* cap on the device memory the instance may hold, 0 = none: an allocation
+                                 that would pass it fails with DD_E_OOM (at create, or later when reverse
+                                 mode, a stored trajectory or a feature first needs memory) */
 } dd_options;
+/* Tile and launch shapes have no option of their own: one wavefront processes one tile of 64 / P
+ * diagrams (P, the lanes per diagram, follows from nodes_per_lane), waves_per_block sets the
+ * workgroup size, passes are hop-synchronous inside a wave (no hop blocking), and every result is
+ * deterministic (fixed reduction orders, no floating-point atomics in device memory), so there is no
+ * non-deterministic mode to choose. */
 
 typedef struct {
     int64_t n, m, edges;    /* variables, rows, edges (Lagrange multipliers) */
@@ -121,7 +131,12 @@ int dd_destroy(dd_instance *h);
 /* Sizes of the instance (host struct). */
 int dd_get_stats(const dd_instance *h, dd_stats *out);
 
-/* Canonical edge e -> (variable, row); host arrays of length edges. */
+/* Number of edges (Lagrange multipliers lambda_ij, one per variable i of row j: the coupling of the
+ * decomposition, Sec. "Lagrange decomposition").  Host. */
+int dd_num_edges(const dd_instance *h, int64_t *E);
+
+/* Canonical edge e -> (variable, row): the pairs (i, j), i in I_j, that index the Lagrange
+ * multipliers (Sec. "Lagrange decomposition"); host arrays of length edges. */
 int dd_edge_map(const dd_instance *h, int32_t *var_out, int32_t *row_out);
 
 /* Set the damping factors omega_ij (in [0,1], Prop. 1) and averaging weights alpha_ij
@@ -133,15 +148,18 @@ int dd_set_params(dd_instance *h, const float *omega, const float *alpha, void *
  * alpha a convex combination).  Device arrays [edges], canonical order. */
 int dd_seg_softmax(dd_instance *h, const float *alpha_hat, float *alpha_out, void *stream);
 
-/* Back to the start state: lambda = c_i/|J_i|, M = 0, shortest-path costs recomputed. */
+/* Back to the start state of Alg. 1: lambda = c_i/|J_i| (a feasible start; the paper leaves the
+ * initialization to the caller), M = 0 (Alg. 1, initialization), shortest-path costs recomputed. */
 int dd_reset(dd_instance *h, void *stream);
 
-/* Replace the solver state (device arrays [edges], canonical order); shortest-path
- * costs are recomputed. */
+/* Replace the solver state (lambda, M) of Alg. 1 (device arrays [edges], canonical order): a test hook
+ * and the resume point of a round that starts elsewhere (Sec. "Overall pipeline"); shortest-path
+ * costs are recomputed.  Feasibility (Prop. 1) is the caller's: sum_j (lambda_ij + M_ij) = c_i. */
 int dd_set_state(dd_instance *h, const float *lambda, const float *M, void *stream);
 
-/* Read the state into device arrays [edges] (canonical order).  flushed != 0 returns
- * lambda_bar = lambda + alpha * S instead of lambda.  M_out may be NULL. */
+/* Read the state (lambda, M) that Alg. 1 returns into device arrays [edges] (canonical order).
+ * flushed != 0 returns lambda_bar = lambda + alpha * S instead of lambda: the deferred term applied,
+ * the dual-feasible multipliers at which the bound (D) is evaluated.  M_out may be NULL. */
 int dd_get_state(dd_instance *h, float *lambda_out, float *M_out, int32_t flushed, void *stream);
 
 /* T iterations of Alg. 1: each a forward pass (hops in ascending variable order)
@@ -164,6 +182,13 @@ int dd_run_pass(dd_instance *h, int32_t direction, void *stream);
  * D_L = sum_j E^j(lambda) + sum_e min(0, M_e) + the same constant (into *dl, may be NULL).
  * Synchronizes the stream.  DD_E_NONFINITE if a bound is not finite. */
 int dd_lower_bound(dd_instance *h, double *lb, double *dl, void *stream);
+
+/* T iterations of Alg. 1 (as dd_run) recording the lower bound (as dd_lower_bound, the constant of
+ * variables in no row included) after every lb_every iterations (0: the instance's lb_every option):
+ * lb_dev[i] (device, fp64, caller-allocated, floor(T / lb_every) entries) is the bound after
+ * (i + 1) lb_every iterations.  Asynchronous: nothing is copied to the host and the stream is not
+ * synchronized, so a caller reads the whole trajectory once at the end. */
+int dd_run_trace(dd_instance *h, int32_t T, int32_t lb_every, double *lb_dev, void *stream);
 
 /* Per-row energies E^j(lambda_bar) (eq. 1) into a device array [m]. */
 int dd_row_energies(dd_instance *h, float *E_out, void *stream);
@@ -198,6 +223,11 @@ int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *l
  * Outputs are device arrays (may be NULL): d_omega, d_alpha [edges] canonical, d_c [n].
  * Leaves the solver at the final state.  DD_E_STATE without a valid record. */
 int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream);
+
+/* Test hook for the checkpoint verification: adds 1 to the first multiplier slot of checkpoint
+ * `index` (0 .. ceil(T / K)) of the recorded checkpointed forward, so that the next dd_backward returns
+ * DD_E_CHECKPOINT.  DD_E_STATE without such a record.  Synchronizes the device. */
+int dd_corrupt_checkpoint(dd_instance *h, int32_t index);
 
 /* Serial number of the recorded unrolled forward, for callers that hold several records of one
  * instance (each autograd node of a graph): every successful dd_forward_unrolled* takes the next
@@ -334,20 +364,23 @@ int dd_autotune(dd_instance *h, const char *cache_path, int32_t *from_cache, voi
 /* ---- Batches: many programs packed into one instance ---------------------------------------- */
 
 /* A batch is the disjoint union of k programs (variables and rows of program q follow those
- * of q-1): every pass over the batch is one launch per kernel class over all programs, and
- * rows of different programs share tiles.  Since the programs share no variable, each one's
- * iterates are those it would have alone.  dd_batch_instance returns the packed instance
- * (owned by the batch) for every per-instance call; its edge, variable and row arrays are the
- * programs' canonical arrays concatenated in batch order. */
+ * of q-1): the mini-batches of the training loop (Sec. "Loss": the loss is averaged over a
+ * mini-batch of instances; Table 5 gives the batch sizes).  Every pass over the batch is one launch
+ * per kernel class over all programs, and rows of different programs share tiles.  Since the
+ * programs share no variable, each one's iterates are those it would have alone (Alg. 1 couples
+ * rows only through shared variables).  dd_batch_instance returns the packed instance (owned by the
+ * batch) for every per-instance call; its edge, variable and row arrays are the programs' canonical
+ * arrays concatenated in batch order.  The batch is built from the programs (rows are compiled into
+ * shared tiles), not from existing instances, which keep no copy of their rows. */
 typedef struct dd_batch dd_batch;
 int dd_batch_create(const dd_problem *probs, int32_t k, const dd_options *opt, void *stream, dd_batch **out);
 int dd_batch_destroy(dd_batch *b);
 dd_instance *dd_batch_instance(dd_batch *b);
 /* Offsets of program q's variables, rows and edges: host arrays [k+1] each (may be NULL). */
 int dd_batch_offsets(const dd_batch *b, int64_t *var_off, int64_t *row_off, int64_t *edge_off);
-/* T iterations over every program (graph replays as in dd_run). */
+/* T iterations of Alg. 1 over every program (graph replays as in dd_run). */
 int dd_batch_run(dd_batch *b, int32_t T, void *stream);
-/* Per-program lower bounds (as dd_lower_bound, each with its own uncovered-variable
+/* Per-program lower bounds (D) (as dd_lower_bound, each with its own uncovered-variable
  * constant): lbs[k] and, if not NULL, dls[k] (D_L).  Host arrays; synchronizes the stream. */
 int dd_batch_lower_bounds(dd_batch *b, double *lbs, double *dls, void *stream);
 

@@ -15,10 +15,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdd.so")
 
 DD_OK, DD_E_ARG, DD_E_INFEASIBLE, DD_E_FORCED, DD_E_PARAM, DD_E_HIP, DD_E_UNSUPPORTED, DD_E_OOM, DD_E_NONFINITE, \
-    DD_E_STATE = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+    DD_E_STATE, DD_E_CHECKPOINT = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10
 
 _NAMES = {0: "DD_OK", -1: "DD_E_ARG", -2: "DD_E_INFEASIBLE", -3: "DD_E_FORCED", -4: "DD_E_PARAM", -5: "DD_E_HIP",
-          -6: "DD_E_UNSUPPORTED", -7: "DD_E_OOM", -8: "DD_E_NONFINITE", -9: "DD_E_STATE"}
+          -6: "DD_E_UNSUPPORTED", -7: "DD_E_OOM", -8: "DD_E_NONFINITE", -9: "DD_E_STATE", -10: "DD_E_CHECKPOINT"}
 
 
 class DDError(RuntimeError):
@@ -36,7 +36,7 @@ class dd_problem(C.Structure):
 class dd_options(C.Structure):
     _fields_ = [("nodes_per_lane", C.c_int32), ("waves_per_block", C.c_int32), ("ckpt_every", C.c_int32),
                 ("lds_budget", C.c_int32), ("no_graphs", C.c_int32), ("adj_route_dense", C.c_int32),
-                ("adj_replay", C.c_int32), ("reserved", C.c_int32 * 1)]
+                ("adj_replay", C.c_int32), ("lb_every", C.c_int32), ("max_device_bytes", C.c_int64)]
 
 
 class dd_stats(C.Structure):
@@ -71,6 +71,9 @@ SIGNATURES = {
     "dd_get_state": ([_VP, _VP, _VP, C.c_int32, _VP], C.c_int),
     "dd_run": ([_VP, C.c_int32, _VP], C.c_int),
     "dd_run_pass": ([_VP, C.c_int32, _VP], C.c_int),
+    "dd_run_trace": ([_VP, C.c_int32, C.c_int32, _VP, _VP], C.c_int),
+    "dd_num_edges": ([_VP, C.POINTER(C.c_int64)], C.c_int),
+    "dd_corrupt_checkpoint": ([_VP, C.c_int32], C.c_int),
     "dd_lower_bound": ([_VP, C.POINTER(C.c_double), C.POINTER(C.c_double), _VP], C.c_int),
     "dd_row_energies": ([_VP, _VP, _VP], C.c_int),
     "dd_min_marginals": ([_VP, _VP, _VP, _VP], C.c_int),
@@ -190,20 +193,23 @@ def compile_row(prob, row):
 
 
 def _options(nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0, graphs=True, adj_route_dense=False,
-             adj_replay=False):
+             adj_replay=False, lb_every=0, max_device_bytes=0):
     return dd_options(int(nodes_per_lane), int(waves_per_block), int(ckpt_every), int(lds_budget),
-                      0 if graphs else 1, 1 if adj_route_dense else 0, 1 if adj_replay else 0)
+                      0 if graphs else 1, 1 if adj_route_dense else 0, 1 if adj_replay else 0, int(lb_every),
+                      int(max_device_bytes))
 
 
 class Instance:
     """A binary program resident on the current GPU (see include/dd.h for the semantics)."""
 
     def __init__(self, prob, nodes_per_lane=0, waves_per_block=0, lds_budget=0, ckpt_every=0, graphs=True,
-                 adj_route_dense=False, adj_replay=False):
+                 adj_route_dense=False, adj_replay=False, lb_every=0, max_device_bytes=0):
         import torch
         L_ = lib()
         pa = _ProblemArgs(prob)
-        opt = _options(nodes_per_lane, waves_per_block, lds_budget, ckpt_every, graphs, adj_route_dense, adj_replay)
+        opt = _options(nodes_per_lane, waves_per_block, lds_budget, ckpt_every, graphs, adj_route_dense, adj_replay,
+                       lb_every, max_device_bytes)
+        self._lb_every = int(lb_every) if lb_every else 1
         h = C.c_void_p()
         # input validation and compilation run on the host before any HIP call
         stream = _stream() if torch.cuda.is_available() else None
@@ -272,6 +278,24 @@ class Instance:
 
     def run(self, T):
         _check(self._L.dd_run(self._h, int(T), _stream()))
+
+    def run_trace(self, T, lb_every=0):
+        """T iterations with the bound after every lb_every of them, recorded on the device: float64 [T // k]."""
+        import torch
+        k = int(lb_every) if lb_every else getattr(self, "_lb_every", 1)
+        n = int(T) // k
+        out = torch.empty(max(n, 1), dtype=torch.float64, device=self.device)
+        _check(self._L.dd_run_trace(self._h, int(T), k, _dptr(out), _stream()))
+        return out[:n]
+
+    def num_edges(self):
+        v = C.c_int64()
+        _check(self._L.dd_num_edges(self._h, C.byref(v)))
+        return v.value
+
+    def corrupt_checkpoint(self, index):
+        """Test hook: perturb stored checkpoint `index` so that the next backward fails (DD_E_CHECKPOINT)."""
+        _check(self._L.dd_corrupt_checkpoint(self._h, int(index)))
 
     def run_pass(self, direction):
         _check(self._L.dd_run_pass(self._h, int(direction), _stream()))

@@ -543,6 +543,8 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     const int wpb = o.waves_per_block > 0 ? o.waves_per_block : kMaxWavesPerBlock;
     const int lds_budget = o.lds_budget > 0 ? o.lds_budget : 64 * 1024;
     if (o.ckpt_every < 0) return fail(DD_E_ARG, "ckpt_every must be >= 0");
+    if (o.lb_every < 0) return fail(DD_E_ARG, "lb_every must be >= 0");
+    if (o.max_device_bytes < 0) return fail(DD_E_ARG, "max_device_bytes must be >= 0");
     SortedRows sr;
     int st = validate_and_sort(prob, sr);
     if (st) return st;
@@ -590,6 +592,8 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     dd_instance *h = new dd_instance();
     h->device = device;
     if (o.ckpt_every > 0) h->ckpt_default = o.ckpt_every;
+    if (o.lb_every > 0) h->lb_every = o.lb_every;
+    h->max_device_bytes = o.max_device_bytes;
     h->use_graphs = o.no_graphs == 0;
     h->adj_dense = o.adj_route_dense != 0;
     h->adj_replay = o.adj_replay != 0;
@@ -923,6 +927,32 @@ int dd_lower_bound(dd_instance *h, double *lb, double *dl, void *stream) {
     return DD_OK;
 }
 
+int dd_run_trace(dd_instance *h, int32_t T, int32_t lb_every, double *lb_dev, void *stream) {
+    if (!h || T < 0) return fail(DD_E_ARG, "bad instance or T");
+    const int every = lb_every > 0 ? lb_every : h->lb_every;
+    if (T >= every && !lb_dev) return fail(DD_E_ARG, "lb_dev is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int st;
+    for (int t = 0, i = 0; t < T; t += every) {
+        const int n = std::min(every, T - t);
+        if ((st = dd_run(h, n, stream))) return st;
+        if (n < every) break;
+        // the bound as dd_lower_bound computes it, with the constant added on the device
+        if ((st = deferred(h, s)) || (st = all_classes(h, false, BWD_EN_BAR, s))) return st;
+        double *out = lb_dev + i++;
+        st = recorded(h, "k_sum", 4.0 * (double)h->m, s,
+                      [&] { return launch_sum(h->T.energies, h->m, 0, h->partial, out, s, h->unc_const); });
+        if (st) return st;
+    }
+    return DD_OK;
+}
+
+int dd_num_edges(const dd_instance *h, int64_t *E) {
+    if (!h || !E) return fail(DD_E_ARG, "NULL argument");
+    *E = h->E;
+    return DD_OK;
+}
+
 int dd_row_energies(dd_instance *h, float *E_out, void *stream) {
     if (!h || (h->m && !E_out)) return fail(DD_E_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
@@ -964,6 +994,7 @@ int adj_alloc(dd_instance *h) {
     HIP_TRY(hipMemset(h->mrec, 0, sizeof(int32_t) * 2 * S));
     HIP_TRY(hipMemset(h->mdiff, 0, sizeof(float) * S));
     if ((st = h->alloc(&h->scratch_n, (size_t)std::max<int64_t>(h->n, 1)))) return st;
+    if ((st = h->alloc(&h->hash_tmp, 1)) || (st = h->alloc(&h->ck_flag, 1))) return st;
     for (float *b : {h->lam_in, h->dlamA, h->dlamB, h->dMA, h->dMB, h->g, h->dalpha, h->domega, h->Se})
         HIP_TRY(hipMemset(b, 0, sizeof(float) * S));
     HIP_TRY(hipMemset(h->rec_val, 0, sizeof(float) * 2 * S));
@@ -1067,6 +1098,21 @@ int save_state(dd_instance *h, std::vector<float *> &L, std::vector<float *> &Mv
     return DD_OK;
 }
 
+// Fingerprint of a state (slot-ordered lambda, M) into *out (device).
+int state_hash(dd_instance *h, const float *lam, const float *M, uint64_t *out, hipStream_t s) {
+    return recorded(h, "k_hash", 8.0 * (double)h->edge_slots, s, [&] {
+        return launch_state_hash(lam, M, h->edge_slots, (uint64_t *)h->partial, out, s);
+    });
+}
+
+// Flag (ck_flag) when the state (lam, M) does not have checkpoint i's fingerprint.
+int verify_state(dd_instance *h, const float *lam, const float *M, size_t i, hipStream_t s) {
+    int st = state_hash(h, lam, M, h->hash_tmp, s);
+    if (st) return st;
+    HIP_TRY(launch_hash_check(h->hash_tmp, h->ck_hash + i, h->ck_flag, s));
+    return DD_OK;
+}
+
 int load_state(dd_instance *h, const std::vector<float *> &L, const std::vector<float *> &Mv, size_t i,
                hipStream_t s) {
     HIP_TRY(launch_copy2(L[i], h->T.lam, Mv[i], h->T.M, h->edge_slots, s));
@@ -1129,6 +1175,7 @@ bool stored_fits(const dd_instance *h, int n, size_t *need_out = nullptr, size_t
     if (need && hipMemGetInfo(&free_b, &total_b) != hipSuccess) return false;
     if (need_out) *need_out = need;
     if (free_out) *free_out = free_b;
+    if (need && h->max_device_bytes > 0 && h->device_bytes + (int64_t)need > h->max_device_bytes) return false;
     return need == 0 || need + ((size_t)2 << 30) <= free_b;
 }
 
@@ -1261,12 +1308,21 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
     } else if ((st = dd_reset(h, stream))) {
         return st;
     }
+    const int nseg = (T + K - 1) / K;
+    if (h->ck_hash_cap < (size_t)nseg + 1) {  // fingerprints of the checkpoints (the old array stays with the instance)
+        const size_t cap = std::max<size_t>(64, (size_t)nseg + 1);
+        if ((st = h->alloc(&h->ck_hash, cap))) return st;
+        h->ck_hash_cap = cap;
+    }
+    auto checkpoint = [&](size_t i) {
+        int r = save_state(h, h->ck_lam, h->ck_M, i, s);
+        return r ? r : state_hash(h, h->ck_lam[i], h->ck_M[i], h->ck_hash + i, s);
+    };
     for (int t = 0; t < T; ++t) {
-        if (t % K == 0 && (st = save_state(h, h->ck_lam, h->ck_M, (size_t)(t / K), s))) return st;
+        if (t % K == 0 && (st = checkpoint((size_t)(t / K)))) return st;
         if ((st = dd_run(h, 1, stream))) return st;
     }
-    const int nseg = (T + K - 1) / K;
-    if ((st = save_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;  // the final state
+    if ((st = checkpoint((size_t)nseg))) return st;  // the final state
     if ((st = dd_lower_bound(h, lb, nullptr, stream))) return st;
     h->fwd_T = T;
     h->fwd_K = K;
@@ -1288,9 +1344,13 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     const int T = h->fwd_T, K = stored ? 1 : h->fwd_K, nseg = (T + K - 1) / K;
     const float seed = (float)dlb;
     int st;
+    // checkpoints are verified against the fingerprints taken when they were saved: when loaded, and
+    // at the end of each recomputed segment (the recomputation must reproduce the next checkpoint)
+    if (!stored) HIP_TRY(launch_fill((float *)h->ck_flag, 0.f, 1, s));
     // adjoint of the lower bound at the final state: dLB / dlambda_bar_j = argmin assignment of row j
     if (stored) st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)T, s);
     else st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s);
+    if (st == DD_OK && !stored) st = verify_state(h, h->T.lam, h->T.M, (size_t)nseg, s);
     if (st) return st;
     if ((st = deferred(h, s))) return st;
     if (stored) h->T.B = h->F0;  // a stored trajectory keeps the final B in B0: the bound's B goes to the spare array
@@ -1326,10 +1386,12 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     for (int seg = stored ? -1 : nseg - 1; seg >= 0; --seg) {
         const int t0 = seg * K, t1 = std::min(T, t0 + K), np = 2 * (t1 - t0);
         if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)seg, s))) return st;
+        if ((st = verify_state(h, h->T.lam, h->T.M, (size_t)seg, s))) return st;
         if (seg_store) {
             h->T.B = h->trB[0];  // B at the checkpoint goes to the first stored array
             st = recompute_B(h, s);
             if (st == DD_OK) st = stored_passes(h, t1 - t0, s);
+            if (st == DD_OK) st = verify_state(h, h->tr_lam[np], h->tr_M[np], (size_t)seg + 1, s);
             if (st == DD_OK) st = stored_reverse(h, t1 - t0, dl, dm, dl2, dm2, s);
             h->T.F = own_F;
             h->T.B = own_B;
@@ -1343,6 +1405,7 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
             if ((st = save_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
             if ((st = q == np - 1 ? run_pass_rec(h, q % 2, s) : dd_run_pass(h, q % 2, stream))) return st;
         }
+        if ((st = verify_state(h, h->T.lam, h->T.M, (size_t)seg + 1, s))) return st;
         for (int q = np - 1; q >= 0; --q) {
             if (q == np - 1) {
                 // the recomputation just ran this pass: its outputs and both node sides are in place
@@ -1371,6 +1434,13 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     } else {
         if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s))) return st;
         if ((st = recompute_B(h, s))) return st;
+        int32_t *flag = (int32_t *)h->red_host;
+        HIP_TRY(hipMemcpyAsync(flag, h->ck_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (*flag)
+            return fail(DD_E_CHECKPOINT,
+                        "a checkpoint of the unrolled forward no longer has the fingerprint taken when it was "
+                        "saved, or recomputing a segment from it did not reproduce the next one");
     }
     h->fwd_version = h->version;
     return DD_OK;
@@ -1386,6 +1456,20 @@ int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *l
 
 int dd_forward_unrolled_from_state(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream) {
     return forward_unrolled(h, T, ckpt_every, lb, true, stream);
+}
+
+int dd_corrupt_checkpoint(dd_instance *h, int32_t index) {
+    if (!h) return fail(DD_E_ARG, "NULL instance");
+    if (h->fwd_T < 0 || h->fwd_version != h->version || h->fwd_stored)
+        return fail(DD_E_STATE, "no checkpointed unrolled forward is recorded");
+    const int nseg = (h->fwd_T + h->fwd_K - 1) / h->fwd_K;
+    if (index < 0 || index > nseg) return fail(DD_E_ARG, "checkpoint %d out of range [0, %d]", index, nseg);
+    float v = 0.f;
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipMemcpy(&v, h->ck_lam[index], sizeof v, hipMemcpyDeviceToHost));
+    v += 1.f;
+    HIP_TRY(hipMemcpy(h->ck_lam[index], &v, sizeof v, hipMemcpyHostToDevice));
+    return DD_OK;
 }
 
 int dd_record_serial(const dd_instance *h, int64_t *serial) {

@@ -34,6 +34,8 @@ struct dd_instance {
     int var_team = 1;  // lanes per variable in the per-variable sums (deferred S and its adjoint)
     static constexpr int kVarTeam = 4;
     int lds_budget = 64 * 1024;  // max LDS bytes per workgroup
+    int64_t max_device_bytes = 0;  // cap on the device memory the instance may hold (0: none)
+    int lb_every = 1;              // default iterations between the bounds of dd_run_trace
     std::vector<ClassLaunch> classes;
     int64_t ntiles = 0, node_slots = 0, edge_slots = 0, device_bytes = 0;
     std::vector<int32_t> edge_var, edge_row;  // canonical edge map (host)
@@ -77,6 +79,10 @@ struct dd_instance {
     int32_t *mrec = nullptr;  // argmin records of the last recording update pass (one-wave diagrams)
     float *mdiff = nullptr;
     std::vector<float *> ck_lam, ck_M;    // checkpoints of the unrolled forward (state at iterations 0, K, 2K, ..., T)
+    uint64_t *ck_hash = nullptr;          // fingerprint of every checkpoint, taken when it is saved
+    size_t ck_hash_cap = 0;
+    uint64_t *hash_tmp = nullptr;         // [1] fingerprint of a loaded or recomputed state
+    int32_t *ck_flag = nullptr;           // [1] set when a checkpoint or its recomputation does not match
     std::vector<float *> seg_lam, seg_M;  // pass-input states inside one checkpoint segment
     // stored trajectory of the unrolled forward (ckpt_every = -1): the node costs every pass read or
     // wrote and the state before every pass, so the backward sweep recomputes nothing
@@ -120,6 +126,11 @@ struct dd_instance {
     int alloc(T_ **p, size_t count) {
         void *q = nullptr;
         size_t bytes = std::max<size_t>(count, 1) * sizeof(T_);
+        if (max_device_bytes > 0 && device_bytes + (int64_t)bytes > max_device_bytes)
+            return ddi::fail(DD_E_OOM,
+                             "allocating %zu bytes would exceed the instance's device-memory cap "
+                             "(%lld of %lld bytes held)",
+                             bytes, (long long)device_bytes, (long long)max_device_bytes);
         hipError_t e = hipMalloc(&q, bytes);
         if (e != hipSuccess) return ddi::fail(DD_E_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
         allocs.push_back(q);

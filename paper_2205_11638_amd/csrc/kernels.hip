@@ -943,7 +943,8 @@ __global__ __launch_bounds__(256) void k_sum_partial(const float *__restrict__ x
     if (t == 0) partial[blockIdx.x] = sh[0];
 }
 
-__global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ partial, int nb, double *out) {
+__global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ partial, int nb, double add,
+                                                   double *out) {
     __shared__ double sh[256];
     const int t = threadIdx.x;
     double acc = 0.0;
@@ -954,7 +955,54 @@ __global__ __launch_bounds__(256) void k_sum_final(const double *__restrict__ pa
         if (t < w) sh[t] += sh[t + w];
         __syncthreads();
     }
+    if (t == 0) *out = sh[0] + add;
+}
+
+// Order-independent 64-bit fingerprint of a state (two float arrays a, b of n entries): the 32-bit
+// pattern of word w (a[i] is word 2i, b[i] word 2i + 1) is keyed with w and mixed by the splitmix64
+// finalizer (Steele, Lea and Flood, 2014), and the results are added modulo 2^64 -- the same sum in
+// any order, so blocks may add their chunks separately and one block add the partial sums.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void k_hash_partial(const float *__restrict__ a, const float *__restrict__ b,
+                                                      int64_t n, int64_t chunk, uint64_t *partial) {
+    __shared__ uint64_t sh[256];
+    const int t = threadIdx.x;
+    const int64_t lo = (int64_t)blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
+    uint64_t acc = 0;
+    for (int64_t i = lo + t; i < hi; i += 256) {
+        acc += mix64(((uint64_t)(2 * i) << 32 | __float_as_uint(a[i])) + 0x9E3779B97F4A7C15ull);
+        acc += mix64(((uint64_t)(2 * i + 1) << 32 | __float_as_uint(b[i])) + 0x9E3779B97F4A7C15ull);
+    }
+    sh[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
+    if (t == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(256) void k_hash_final(const uint64_t *__restrict__ partial, int nb, uint64_t *out) {
+    __shared__ uint64_t sh[256];
+    const int t = threadIdx.x;
+    uint64_t acc = 0;
+    for (int j = t; j < nb; j += 256) acc += partial[j];
+    sh[t] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) sh[t] += sh[t + w];
+        __syncthreads();
+    }
     if (t == 0) *out = sh[0];
+}
+
+__global__ void k_hash_check(const uint64_t *__restrict__ x, const uint64_t *__restrict__ y, int32_t *flag) {
+    if (threadIdx.x == 0 && *x != *y) *flag = 1;
 }
 
 __global__ void k_check_params(const float *__restrict__ om, const float *__restrict__ al, int64_t E, int32_t *flags) {
@@ -1107,11 +1155,26 @@ hipError_t launch_seg_softmax(const int32_t *var_ptr, const int32_t *var_canon, 
     return hipGetLastError();
 }
 
-hipError_t launch_sum(const float *x, int64_t n, int neg_part, double *partial, double *out, hipStream_t s) {
+hipError_t launch_sum(const float *x, int64_t n, int neg_part, double *partial, double *out, hipStream_t s,
+                      double add) {
     const int nb = (int)std::min<int64_t>(kSumBlocks, std::max<int64_t>(1, (n + 4095) / 4096));
     const int64_t chunk = (std::max<int64_t>(n, 1) + nb - 1) / nb;
     hipLaunchKernelGGL(k_sum_partial, dim3(nb), dim3(256), 0, s, x, n, chunk, neg_part, partial);
-    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, out);
+    hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(256), 0, s, partial, nb, add, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_hash(const float *a, const float *b, int64_t n, uint64_t *partial, uint64_t *out,
+                             hipStream_t s) {
+    const int nb = (int)std::min<int64_t>(kSumBlocks, std::max<int64_t>(1, (n + 4095) / 4096));
+    const int64_t chunk = (std::max<int64_t>(n, 1) + nb - 1) / nb;
+    hipLaunchKernelGGL(k_hash_partial, dim3(nb), dim3(256), 0, s, a, b, n, chunk, partial);
+    hipLaunchKernelGGL(k_hash_final, dim3(1), dim3(256), 0, s, partial, nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_check(const uint64_t *x, const uint64_t *y, int32_t *flag, hipStream_t s) {
+    hipLaunchKernelGGL(k_hash_check, dim3(1), dim3(64), 0, s, x, y, flag);
     return hipGetLastError();
 }
 

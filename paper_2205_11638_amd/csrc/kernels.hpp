@@ -201,10 +201,16 @@ hipError_t launch_gather(const int32_t *canon2slot, const float *src, float *dst
 // softmax over each variable's edges; inputs/outputs canonical, var_canon is the CSR of canonical edge ids
 hipError_t launch_seg_softmax(const int32_t *var_ptr, const int32_t *var_canon, const float *x, float *y, int n,
                               hipStream_t s);
-// *out = sum of x[0..n) (or of min(0, x) when neg_part), fp64, fixed order; partial holds
+// *out = add + sum of x[0..n) (or of min(0, x) when neg_part), fp64, fixed order; partial holds
 // kSumBlocks doubles of scratch.
 constexpr int kSumBlocks = 1024;
-hipError_t launch_sum(const float *x, int64_t n, int neg_part, double *partial, double *out, hipStream_t s);
+hipError_t launch_sum(const float *x, int64_t n, int neg_part, double *partial, double *out, hipStream_t s,
+                      double add = 0.0);
+// *out = order-independent 64-bit fingerprint of the state (a[0..n), b[0..n)); partial holds kSumBlocks
+// words of scratch.  launch_hash_check sets *flag = 1 when *x != *y (and leaves it otherwise).
+hipError_t launch_state_hash(const float *a, const float *b, int64_t n, uint64_t *partial, uint64_t *out,
+                             hipStream_t s);
+hipError_t launch_hash_check(const uint64_t *x, const uint64_t *y, int32_t *flag, hipStream_t s);
 // validity check of parameters: flags[0] |= omega outside [0,1] or non-finite, flags[1] |= alpha < 0 or non-finite
 hipError_t launch_check_params(const float *omega, const float *alpha, int64_t E, int32_t *flags, hipStream_t s);
 

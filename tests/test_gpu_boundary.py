@@ -1,0 +1,108 @@
+"""GPU: boundary behaviour of the C ABI -- the device-memory cap (DD_E_OOM), checkpoint
+verification (DD_E_CHECKPOINT, forced from the host through the test hook), the device-side bound
+trace, and sizes."""
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import host, make_instance, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+
+
+def _gm():
+    w = synth.workload("gm", small=True)
+    return w["problem"], w["omega"], w["alpha_hat"]
+
+
+def test_device_memory_cap():
+    """An allocation that would pass max_device_bytes fails with DD_E_OOM: at create when the cap is
+    below what the instance needs, and later when reverse mode first needs its buffers; the instance
+    stays usable after such a refusal."""
+    import paper_2205_11638_amd as dd
+    p, om, ah = _gm()
+    need = make_instance(p)[0].stats["device_bytes"]
+    with pytest.raises(dd.DDError) as e:
+        make_instance(p, max_device_bytes=need - 1)
+    assert e.value.code == dd.binding.DD_E_OOM and "cap" in str(e.value)
+    inst, _, _ = make_instance(p, om, ah, max_device_bytes=need)
+    assert inst.stats["device_bytes"] == need
+    with pytest.raises(dd.DDError) as e:
+        inst.forward_unrolled(3, 1)
+    assert e.value.code == dd.binding.DD_E_OOM
+    inst.run(2)  # still usable
+    lb = inst.lower_bound()[0]
+    ref, _, _ = make_instance(p, om, ah)
+    ref.run(2)
+    assert lb == ref.lower_bound()[0]
+    # a cap with room for reverse mode but not for a stored trajectory
+    big, _, _ = make_instance(p, om, ah, max_device_bytes=need * 4)
+    big.forward_unrolled(3, 1)
+    big.backward(1.0)
+    with pytest.raises(dd.DDError) as e:
+        big.forward_unrolled(200, -1)
+    assert e.value.code == dd.binding.DD_E_OOM
+
+
+@pytest.mark.parametrize("replay", [False, True])
+def test_checkpoint_verification(replay):
+    """The backward sweep checks every checkpoint against the fingerprint taken when it was saved,
+    and the state each recomputed segment ends in against the next checkpoint's: a checkpoint changed
+    after the forward (the test hook adds 1 to one slot) fails with DD_E_CHECKPOINT; an intact record
+    passes and gives the gradients of a fresh instance."""
+    import paper_2205_11638_amd as dd
+    p, om, ah = _gm()
+    inst, _, _ = make_instance(p, om, ah, adj_replay=replay)
+    ref, _, _ = make_instance(p, om, ah, adj_replay=replay)
+    ref.forward_unrolled(6, 2)
+    g_ref = [host(t) for t in ref.backward(1.0)]
+    for index in (0, 1, 3):  # the start state, an inner checkpoint, the final state
+        inst.forward_unrolled(6, 2)
+        inst.corrupt_checkpoint(index)
+        with pytest.raises(dd.DDError) as e:
+            inst.backward(1.0)
+        assert e.value.code == dd.binding.DD_E_CHECKPOINT, index
+    inst.forward_unrolled(6, 2)
+    g = [host(t) for t in inst.backward(1.0)]
+    for a, b in zip(g, g_ref):
+        np.testing.assert_array_equal(a, b)
+    with pytest.raises(dd.DDError) as e:
+        inst.corrupt_checkpoint(4)
+    assert e.value.code == dd.binding.DD_E_ARG
+    inst.forward_unrolled(2, -1)  # a stored trajectory has no checkpoints
+    with pytest.raises(dd.DDError) as e:
+        inst.corrupt_checkpoint(0)
+    assert e.value.code == dd.binding.DD_E_STATE
+
+
+def test_run_trace_equals_bounds_between_runs():
+    p, om, ah = _gm()
+    a, _, _ = make_instance(p, om, ah, lb_every=3)
+    b, _, _ = make_instance(p, om, ah)
+    tr = host(a.run_trace(20))  # 6 bounds; the last 2 iterations run without one
+    assert tr.shape == (6,)
+    ref = []
+    for _ in range(6):
+        b.run(3)
+        ref.append(b.lower_bound()[0])
+    np.testing.assert_array_equal(tr, np.array(ref))
+    b.run(2)
+    assert a.lower_bound()[0] == b.lower_bound()[0]
+    tr7 = host(a.run_trace(7, lb_every=7))
+    b.run(7)
+    assert tr7[0] == b.lower_bound()[0]
+    say("trace", tr)
+
+
+def test_sizes():
+    p, _, _ = _gm()
+    inst, _, _ = make_instance(p)
+    assert inst.num_edges() == p.nnz == inst.E

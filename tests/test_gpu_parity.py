@@ -203,6 +203,12 @@ def test_lb_trajectory_setcover(orc):
 def test_lb_trajectory_indset_full(orc):
     inst, p, lam_o, M_o, tr = _trajectory(orc, "indset", 1000, 10)
     say("indset LB", tr[0], tr[-1])
+    # the same trajectory recorded on the device by dd_run_trace (bound every 10 iterations, no host
+    # synchronization in between): the same kernels and the same fp64 additions, so the same bits
+    w = synth.workload("indset")
+    inst2, _, _ = make_instance(w["problem"], f32(w["omega"]), f32(w["alpha_hat"]), lb_every=10)
+    trace = host(inst2.run_trace(1000))
+    np.testing.assert_array_equal(trace, np.array([t[1] for t in tr]))
 
 
 def test_gm_full_short_horizon(orc):
