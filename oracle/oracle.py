@@ -15,7 +15,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dd_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1: the AddressSanitizer / UndefinedBehaviorSanitizer build (CPU checks)
+_SAN = os.environ.get("ORACLE_SANITIZE") == "1"
+_LIB = os.path.join(_HERE, "liboracle_san.so" if _SAN else "liboracle.so")
+_SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-g"]
 _lib = None
 
 OK, E_ARG, E_INFEASIBLE, E_FORCED = 0, -1, -2, -3
@@ -31,7 +34,7 @@ def build(force=True):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-Wall", "-Wno-unused-function",
-                           "-o", tmp, _SRC, "-lm"])
+                           *(_SAN_FLAGS if _SAN else []), "-o", tmp, _SRC, "-lm"])
     os.replace(tmp, _LIB)
     return _LIB
 

@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdd.so")
+# DD_SANITIZE=1 loads the host-sanitized build (CPU checks only; see build.py)
+LIB_PATH = os.path.join(HERE, "libdd_san.so" if os.environ.get("DD_SANITIZE") == "1" else "libdd.so")
 
 DD_OK, DD_E_ARG, DD_E_INFEASIBLE, DD_E_FORCED, DD_E_PARAM, DD_E_HIP, DD_E_UNSUPPORTED, DD_E_OOM, DD_E_NONFINITE, \
     DD_E_STATE, DD_E_CHECKPOINT = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9, -10

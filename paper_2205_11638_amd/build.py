@@ -15,6 +15,10 @@ import tempfile
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdd.so")
+# host-side AddressSanitizer / UndefinedBehaviorSanitizer build (CPU checks of the diagram compiler and
+# the host logic; device code is built as usual)
+LIB_SAN = os.path.join(HERE, "libdd_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-O1", "-g"]
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
@@ -36,14 +40,17 @@ def _run(cmd):
     return r
 
 
-def build(verbose=False) -> str:
-    """Compile every source (always) and link libdd.so; returns the library path."""
+def build(verbose=False, sanitize=False) -> str:
+    """Compile every source (always) and link libdd.so (libdd_san.so with sanitize: host objects built
+    with ASan/UBSan, for CPU-only checks); returns the library path."""
+    out_lib = LIB_SAN if sanitize else LIB
+    host_flags = HOST_FLAGS + (SAN_FLAGS if sanitize else [])
     with tempfile.TemporaryDirectory(prefix="ddbuild") as tmp:
         objs = []
         procs = []
         for f in HOST_SRC:
             o = os.path.join(tmp, f + ".o")
-            procs.append((["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, f), "-o", o]))
+            procs.append((["g++", *host_flags, "-c", os.path.join(CSRC, f), "-o", o]))
             objs.append(o)
         for f in DEVICE_SRC:
             o = os.path.join(tmp, f + ".o")
@@ -58,11 +65,13 @@ def build(verbose=False) -> str:
             if p.returncode != 0:
                 sys.stderr.write(" ".join(c) + "\n" + (out or ""))
                 raise RuntimeError("compile failed: " + c[-3])
-        tmp_lib = LIB + ".tmp%d" % os.getpid()
+        tmp_lib = out_lib + ".tmp%d" % os.getpid()
+        # with sanitize the runtimes of the g++-built host objects are left unresolved here: the checking
+        # process preloads gcc's libasan and libubsan
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_lib, *objs, "-lpthread"])
-        os.replace(tmp_lib, LIB)
-    return LIB
+        os.replace(tmp_lib, out_lib)
+    return out_lib
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, sanitize="--sanitize" in sys.argv))
