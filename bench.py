@@ -349,10 +349,32 @@ def batch_leg(T, stream):
         for inst in singles:
             inst.run(iters)
 
+    ms_default = timed(packed)
+    shapes_default = bt.instance.launch_shapes()
+    # the launch shapes of the packed instance chosen by the library's autotuner (timed here, or read
+    # back from the cache file of an earlier run with the same signature)
+    import tempfile
+    cache = os.path.join(tempfile.gettempdir(), "dd_autotune_cache.txt")
+    t1 = time.time()
+    hit = bt.instance.autotune(cache)
+    tune_s = time.time() - t1
+    shapes = bt.instance.launch_shapes()
     ms_packed = timed(packed)
+    log(f"[bench] batch autotune ({'cache' if hit else 'timed'}, {tune_s:.1f}s): {ms_default:.1f} -> "
+        f"{ms_packed:.1f} ms; shapes {shapes}")
+    # per-kernel times of the packed iterations (eager launches while the library profiles)
+    bt.instance.profile_begin(4096)
+    bt.run(20)
+    prof = bt.instance.profile_end()
+    kernels = {k: {"launches": n, "avg_ms": tot / n, "gbs_algorithmic": b / (tot / n) / 1e6, "ms_per_iter": tot / 20}
+               for k, (n, tot, b) in prof.items()}
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["ms_per_iter"]):
+        log(f"[bench] batch kernel {k:40s} {v['ms_per_iter']:.4f} ms/iter {v['gbs_algorithmic']:8.1f} GB/s")
     ms_seq = timed(one_by_one)
     lbs, _ = bt.lower_bounds()
     out = {"programs": len(ps), "iterations": T, "arcs": arcs, "packed_ms": ms_packed, "sequential_ms": ms_seq,
+           "packed_default_shapes_ms": ms_default, "default_shapes": shapes_default, "tuned_shapes": shapes,
+           "autotune": {"from_cache": bool(hit), "seconds": tune_s}, "kernels": kernels,
            "packed_instances_per_s": len(ps) / (ms_packed / 1e3),
            "sequential_instances_per_s": len(ps) / (ms_seq / 1e3),
            "packed_arcs_per_s": arcs * T / (ms_packed / 1e3), "sequential_arcs_per_s": arcs * T / (ms_seq / 1e3),

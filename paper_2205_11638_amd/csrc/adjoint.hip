@@ -1129,6 +1129,299 @@ __global__ void k_uncovered(const int32_t *__restrict__ var_ptr, const float *__
 
 inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// ------------------------------------------------------------------------------------------
+// Reverse sweeps of one-wave diagrams that route along the argmin codes the sweeps they reverse
+// recorded (DevTables::Fpar, Bch): every node's argmin parent arc (F side) or child arc (B side) is
+// read from a 2-byte code row, so a hop needs neither topology nor node costs nor bids, only the
+// codes of one level and the adjoint buffer in LDS.
+//  * pull (B side, levels 0 .. L-1): node v hands its adjoint to its recorded child and, through a
+//    hi arc, to the hi-arc sum;
+//  * push (F side, levels L-1 .. 0): node w of level l+1 hands its adjoint to its recorded parent
+//    arc (k, beta) of level l.  An arc has one child, so a parent receives at most one adjoint per
+//    arc kind: lo arcs are written first, then hi arcs added, with no conflict and in the order
+//    lo + hi of the bidding sweeps.
+// The BlockUpdate adjoint, the argmin records of the pass and the hand-over records are those of
+// the bidding sweeps above.
+// ------------------------------------------------------------------------------------------
+constexpr int lds_words_adjc_F_w(int RMAX, int NL) { return node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+constexpr int lds_words_adjc_B_w(int RMAX, int NL) { return 2 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+
+template <int Q, int RMAX, bool UPD>
+__device__ __forceinline__ void adjcB_hop_w(float *ba0, float *ba1, const u32x2 (&cc)[RMAX / 4], int lane, int Wn,
+                                            const AdjIn<UPD> &x, const AdjOut &o, int l) {
+    const int l16 = lane16(lane);
+    float hisum = 0.f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const f32x4 d = lds4(ba0, l16 + q * 1024);  // slots past the level's width hold 0
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t code = code_at(cc[q], j);
+            const int ch = (int)(code & 0x7FFFu);
+            if (d[j] != 0.f) {
+                if (ch < Wn) lds_fadd(&ba1[ch], d[j]);
+                if (code & 0x8000u) hisum += d[j];
+            }
+        }
+    }
+    hisum = team_sum<64>(hisum);
+    if constexpr (UPD) {
+        // the pass's argmin nodes of the two min-marginals and their children (recorded)
+        const int K0 = (int)(x.kc0 & 0xFFFFu), K1 = (int)(x.kc1 & 0xFFFFu);
+        const int r0 = (int)(x.kc0 >> 16), r1 = (int)(x.kc1 >> 16);
+        const float dlam_new = x.dlo + hisum;
+        const float dM = x.dMo - dlam_new;
+        const float dm1 = x.om * dM, dm0 = -dm1;
+        wave_sync();  // after the routed adjoints (a fixed order of the float adds)
+        if (lane == 0 && r0 < Wn) lds_fadd(&ba1[r0], dm0);
+        if (lane == 0 && r1 < Wn) lds_fadd(&ba1[r1], dm1);
+        st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
+        st1(o.g, o.o4 + 4 * l, dlam_new * x.al);
+        st1(o.dalpha, o.o4 + 4 * l, x.da + dlam_new * x.S);
+        st1(o.domega, o.o4 + 4 * l, x.dw + dM * x.d);
+        st2(o.rec_idx, o.o8 + 8 * l, (uint32_t)K0, (uint32_t)K1);  // argmin nodes of level l: F_l side
+        st2(o.rec_val, o.o8 + 8 * l, __float_as_uint(dm0), __float_as_uint(dm1));
+    } else {
+        st1(o.dlam_in, o.o4 + 4 * l, x.dl + hisum);
+    }
+}
+
+template <int RMAX, bool UPD>
+__global__ __launch_bounds__(256) void k_adjc_B_w(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int NL,
+                                                  int recs, float seed) {
+    constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;  // uniform per wave
+    float *Ba = lds_f + (size_t)wave * lds_words_adjc_B_w(RMAX, NL);
+    int *meta = (int *)(Ba + 2 * NB);
+    int *off = meta + NL;
+    const TileCtx tc = tile_ctx(T, tile);
+    preload_meta<1>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l < nlev) {
+            v.W = uni(meta[l] & 0xFFFF);
+            v.R = uni(meta[l] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
+    };
+    const AdjOut o = adj_out<UPD>(A, tc, nlev, lane);
+    const bool use_rec = !UPD && recs;
+    const rsrc_t ri = buf(use_rec ? (const void *)(A.rec_idx + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
+                          use_rec ? nlev * 8 : 0);
+    const rsrc_t rv = buf(use_rec ? (const void *)(A.rec_val + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
+                          use_rec ? nlev * 8 : 0);
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+    int cur = 0;  // Ba + cur * NB: adjoints of level l
+    {
+        const int l16 = lane16(lane);
+#pragma unroll
+        for (int q = 0; q < QM; ++q) lds4(Ba, l16 + q * 1024) = zero4;
+        if (lane == 0) Ba[0] = seed;  // the root is node 0 of level 0
+    }
+    Lev c0 = level(0), c1 = level(1);
+    u32x2 ccn[QM];
+    {
+        const int l8 = lane8(lane);
+        const rsrc_t cr = buf(T.Bch + c0.base, code_bytes(c0));
+#pragma unroll
+        for (int q = 0; q < QM; ++q) ccn[q] = ld2(cr, l8 + q * 512);
+    }
+    AdjIn<UPD> xn = adj_in<UPD>(T, A, tc.ebase);
+    int pi0 = -1, pi1 = -1;  // record of the previous hop's edge (children at this level, or -1)
+    float pv0 = 0.f, pv1 = 0.f;
+    for (int l = 0; l < nlev; ++l) {
+        const int Wn = c1.W;
+        const AdjIn<UPD> x = xn;
+        float *ba0 = Ba + cur * NB, *ba1 = Ba + (cur ^ 1) * NB;
+        // fixed side: argmin contributions of the update sweep to B_l (record of edge l-1)
+        if (use_rec && l > 0 && lane == 0) {
+            if (pi0 >= 0) ba0[pi0] += pv0;
+            if (pi1 >= 0) ba0[pi1] += pv1;
+        }
+        u32x2 cc[QM];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) cc[q] = ccn[q];
+        {
+            const int l16 = lane16(lane);
+#pragma unroll
+            for (int q = 0; q < QM; ++q) lds4(ba1, l16 + q * 1024) = zero4;  // adjoints of level l+1 start at 0
+        }
+        // prefetch hop l+1: codes of level l+1, edge data of level l+1 (the last hop reloads its own),
+        // the record of edge l
+        {
+            const int l8 = lane8(lane);
+            const rsrc_t cr = buf(T.Bch + c1.base, code_bytes(c1));
+#pragma unroll
+            for (int q = 0; q < QM; ++q) ccn[q] = ld2(cr, l8 + q * 512);
+            xn = adj_in<UPD>(T, A, tc.ebase + min(l + 1, nlev - 1));
+            if (!UPD) {
+                pi0 = (int)ld1(ri, 8 * l);
+                pi1 = (int)ld1(ri, 8 * l + 4);
+                pv0 = ld1f(rv, 8 * l);
+                pv1 = ld1f(rv, 8 * l + 4);
+            }
+        }
+        wave_sync();
+        with_count<1, QM>(groups(c0), [&](auto qc) {
+            adjcB_hop_w<decltype(qc)::value, RMAX, UPD>(ba0, ba1, cc, lane, Wn, x, o, l);
+        });
+        wave_sync();
+        cur ^= 1;
+        c0 = c1;
+        c1 = level(l + 2);
+    }
+}
+
+template <int Q, int RMAX, bool UPD>
+__device__ __forceinline__ void adjcF_hop_w(float *Fa, const u32x2 (&cc)[RMAX / 4], int lane, const Lev &c0, int Wn,
+                                            const AdjInF<UPD> &x, const AdjOut &o, int l) {
+    constexpr int QM = RMAX / 4;
+    const int l16 = lane16(lane);
+    f32x4 a[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) a[q] = lds4(Fa, l16 + q * 1024);  // adjoints of level l+1 (0 past its width)
+    wave_sync();  // every adjoint of level l+1 is read: the buffer collects level l
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < QM; ++q) lds4(Fa, l16 + q * 1024) = zero4;
+    wave_sync();
+    float hisum = 0.f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t code = code_at(cc[q], j);
+            const int k = (int)(code >> 1);
+            if (a[q][j] != 0.f && !(code & 1u) && k < c0.W) Fa[k] = a[q][j];  // lo arcs: one per parent
+        }
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t code = code_at(cc[q], j);
+            const int k = (int)(code >> 1);
+            if (a[q][j] != 0.f && (code & 1u) && k < c0.W) {  // hi arcs: one per parent, added to its lo share
+                Fa[k] += a[q][j];
+                hisum += a[q][j];
+            }
+        }
+    hisum = team_sum<64>(hisum);
+    if constexpr (UPD) {
+        // the pass's argmin nodes of the two min-marginals and their children (recorded)
+        const AdjIn<true> &y = x.a;
+        const int K0 = (int)(y.kc0 & 0xFFFFu), K1 = (int)(y.kc1 & 0xFFFFu);
+        const int r0 = (int)(y.kc0 >> 16), r1 = (int)(y.kc1 >> 16);
+        const float dlam_new = y.dlo + hisum;
+        const float dM = y.dMo - dlam_new;
+        const float diff = y.d;
+        const float dm1 = y.om * dM, dm0 = -dm1;
+        wave_sync();  // after the routed adds (a fixed order of the float adds)
+        if (lane == 0) lds_fadd(&Fa[K0], dm0);
+        if (lane == 0) lds_fadd(&Fa[K1], dm1);
+        st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
+        st1(o.g, o.o4 + 4 * l, dlam_new * y.al);
+        st1(o.dalpha, o.o4 + 4 * l, y.da + dlam_new * y.S);
+        st1(o.domega, o.o4 + 4 * l, y.dw + dM * diff);
+        // children of the argmin nodes: B_{l+1} side contributions (-1 for a terminal)
+        st2(o.rec_idx, o.o8 + 8 * l, (uint32_t)(r0 < Wn ? r0 : -1), (uint32_t)(r1 < Wn ? r1 : -1));
+        st2(o.rec_val, o.o8 + 8 * l, __float_as_uint(dm0), __float_as_uint(dm1));
+    } else {
+        wave_sync();
+        // argmin contributions of the update sweep to F_l (record of edge l)
+        if (lane == 0) {
+            if (x.i0 >= 0 && x.i0 < c0.W) Fa[x.i0] += x.v0;
+            if (x.i1 >= 0 && x.i1 < c0.W) Fa[x.i1] += x.v1;
+        }
+        st1(o.dlam_in, o.o4 + 4 * l, x.dl + hisum);
+    }
+}
+
+template <int RMAX, bool UPD>
+__global__ __launch_bounds__(256) void k_adjc_F_w(DevTables T, AdjTables A, int64_t tile0, int64_t ntiles, int NL,
+                                                  int recs) {
+    constexpr int QM = RMAX / 4;
+    extern __shared__ float lds_f[];
+    const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+    if (tile >= tile0 + ntiles) return;  // uniform per wave
+    float *Fa = lds_f + (size_t)wave * lds_words_adjc_F_w(RMAX, NL);
+    int *meta = (int *)(Fa + node_buf_w(RMAX));
+    int *off = meta + NL;
+    const TileCtx tc = tile_ctx(T, tile);
+    preload_meta<1>(T, tc, lane, meta, off);
+    const int nlev = tc.nlev;
+    auto level = [&](int l) {
+        Lev v{0, 0, 0};
+        if (l >= 0 && l < nlev) {
+            v.W = uni(meta[l] & 0xFFFF);
+            v.R = uni(meta[l] >> 16);
+            v.base = tc.nbase + (int64_t)uni(off[l]);
+        }
+        return v;
+    };
+    const AdjOut o = adj_out<UPD>(A, tc, nlev, lane);
+    const bool use_rec = !UPD && recs;
+    const rsrc_t ri = buf(use_rec ? (const void *)(A.rec_idx + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
+                          use_rec ? nlev * 8 : 0);
+    const rsrc_t rv = buf(use_rec ? (const void *)(A.rec_val + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
+                          use_rec ? nlev * 8 : 0);
+    auto edge = [&](int l) {
+        AdjInF<UPD> x;
+        const int e = tc.ebase + l;
+        if constexpr (UPD) {
+            x.a = adj_in<true>(T, A, e);
+        } else {
+            x.lam_src = 0.f;
+            x.dl = A.dlam_in[e];
+            x.i0 = use_rec ? (int)ld1(ri, 8 * l) : -1;
+            x.i1 = use_rec ? (int)ld1(ri, 8 * l + 4) : -1;
+            x.v0 = ld1f(rv, 8 * l);
+            x.v1 = ld1f(rv, 8 * l + 4);
+        }
+        return x;
+    };
+    {
+        // level L: terminals only, no adjoint
+        const int l16 = lane16(lane);
+        const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < QM; ++q) lds4(Fa, l16 + q * 1024) = zero4;
+    }
+    Lev c0 = level(nlev - 1), c1{0, 0, 0};
+    u32x2 ccn[QM];  // codes of level l+1 (none below the last level)
+#pragma unroll
+    for (int q = 0; q < QM; ++q) ccn[q] = u32x2{0u, 0u};
+    AdjInF<UPD> xn = edge(nlev - 1);
+    for (int l = nlev - 1; l >= 0; --l) {
+        const int Wn = c1.W;
+        const AdjInF<UPD> x = xn;
+        u32x2 cc[QM];
+#pragma unroll
+        for (int q = 0; q < QM; ++q) cc[q] = ccn[q];
+        // prefetch hop l-1: the codes of level l, edge data of level l-1 (the last hop reloads its own)
+        {
+            const int l8 = lane8(lane);
+            const rsrc_t cr = buf(T.Fpar + c0.base, code_bytes(c0));
+#pragma unroll
+            for (int q = 0; q < QM; ++q) ccn[q] = ld2(cr, l8 + q * 512);
+            xn = edge(max(l - 1, 0));
+        }
+        wave_sync();
+        with_count<1, QM>(max(groups(c1), 1), [&](auto qc) {
+            adjcF_hop_w<decltype(qc)::value, RMAX, UPD>(Fa, cc, lane, c0, Wn, x, o, l);
+        });
+        wave_sync();
+        c1 = c0;
+        c0 = level(l - 1);
+    }
+}
+
 template <int P, int RMAX>
 hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunch &c, int which, int bar, int recs,
                         float seed, int dense, hipStream_t s) {
@@ -1137,6 +1430,29 @@ hipError_t adj_dispatch(const DevTables &t, const AdjTables &a, const ClassLaunc
         return hipErrorInvalidConfiguration;
     const bool push = which == ADJ_F_UPDATE || which == ADJ_F_FIXED;
     if constexpr (P == 64) {  // one-wave diagrams: the wide sweeps only
+        // along the recorded argmin codes (unless asked for the bidding sweeps' node-by-node routing)
+        if (!dense && (push ? t.Fpar != nullptr : t.Bch != nullptr)) {
+            if (push) {
+                dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
+                const size_t lds = (size_t)c.wpb_af * lds_words_adjc_F_w(RMAX, c.NL) * 4;
+                if (which == ADJ_F_UPDATE)
+                    hipLaunchKernelGGL((k_adjc_F_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL,
+                                       recs);
+                else
+                    hipLaunchKernelGGL((k_adjc_F_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL,
+                                       recs);
+            } else {
+                dim3 grid((unsigned)((c.ntiles + c.wpb_ab - 1) / c.wpb_ab)), block(64 * c.wpb_ab);
+                const size_t lds = (size_t)c.wpb_ab * lds_words_adjc_B_w(RMAX, c.NL) * 4;
+                if (which == ADJ_B_UPDATE)
+                    hipLaunchKernelGGL((k_adjc_B_w<RMAX, true>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL,
+                                       recs, seed);
+                else
+                    hipLaunchKernelGGL((k_adjc_B_w<RMAX, false>), grid, block, lds, s, t, a, c.tile0, c.ntiles, c.NL,
+                                       recs, seed);
+            }
+            return hipGetLastError();
+        }
         if (push) {
             dim3 grid((unsigned)((c.ntiles + c.wpb_af - 1) / c.wpb_af)), block(64 * c.wpb_af);
             const size_t lds = (size_t)c.wpb_af * lds_words_adj_F_w(RMAX, c.NL) * 4;

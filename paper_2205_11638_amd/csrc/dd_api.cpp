@@ -343,17 +343,23 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
     return DD_OK;
 }
 
-// Bytes one launch must move by the method's own accounting (per node / per edge / per row).
-double algorithmic_bytes(bool fwd, int mode, const ClassLaunch &c) {
+// Bytes one launch must move by the method's own accounting (per node / per edge / per row); codes:
+// the sweep also writes the argmin codes of the nodes it computes (2 bytes per node of a one-wave class).
+double algorithmic_bytes(bool fwd, int mode, const ClassLaunch &c, bool codes) {
     const double N = (double)c.nodes, E = (double)c.edges, R = (double)c.rows;
-    if (fwd) return mode == FWD_UPDATE ? 12 * N + 28 * E : mode == FWD_UPDATE_REC ? 12 * N + 40 * E : 8 * N + 16 * E;
+    const bool writes_codes = codes && c.P == 64 &&
+                              (fwd ? mode == FWD_UPDATE_REC || mode == FWD_SWEEP_LAM
+                                   : mode == BWD_UPDATE_REC || mode == BWD_STORE || mode == BWD_STORE_BAR);
+    const double cb = writes_codes ? 2 * N : 0.0;
+    if (fwd)
+        return cb + (mode == FWD_UPDATE ? 12 * N + 28 * E : mode == FWD_UPDATE_REC ? 12 * N + 40 * E : 8 * N + 16 * E);
     switch (mode) {
         case BWD_UPDATE: return 12 * N + 28 * E + 4 * R;
-        case BWD_UPDATE_REC: return 12 * N + 40 * E + 4 * R;
-        case BWD_STORE: return 8 * N + 8 * E + 4 * R;
+        case BWD_UPDATE_REC: return cb + 12 * N + 40 * E + 4 * R;
+        case BWD_STORE: return cb + 8 * N + 8 * E + 4 * R;
         case BWD_EN_LAM: return 4 * N + 4 * E + 4 * R;
         case BWD_EN_BAR: return 4 * N + 16 * E + 4 * R;
-        default: return 8 * N + 24 * E;
+        default: return cb + 8 * N + 24 * E;
     }
 }
 
@@ -430,11 +436,14 @@ int all_classes_launch(dd_instance *h, bool fwd, int mode, hipStream_t s) {
                          loop ? "true" : "false");
             return std::string(name);
         },
-        [&](const ClassLaunch &cl) { return algorithmic_bytes(fwd, mode, cl); });
+        [&](const ClassLaunch &cl) {
+            return algorithmic_bytes(fwd, mode, cl, fwd ? h->T.Fpar != nullptr : h->T.Bch != nullptr);
+        });
 }
 
-// Reverse sweeps.  Bytes: topology and the swept side's cost (8 B/node) in both; update sweeps
-// ~76 B of edge data with the pass's argmin records, fixed sweeps ~28 B/edge.
+// Reverse sweeps.  Bytes: topology and the swept side's cost (8 B/node), or for one-wave classes the
+// argmin codes alone (2 B/node); update sweeps ~76 B of edge data with the pass's argmin records, fixed
+// sweeps ~28 B/edge.
 int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs, float seed, hipStream_t s) {
     const bool upd = which == ADJ_F_UPDATE || which == ADJ_B_UPDATE;
     const char *nm = which == ADJ_F_UPDATE || which == ADJ_F_FIXED ? "k_adj_F" : "k_adj_B";
@@ -450,7 +459,10 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
             return std::string(name);
         },
         [&](const ClassLaunch &cl) {
-            return upd ? 8.0 * cl.nodes + 76.0 * cl.edges : 8.0 * cl.nodes + 28.0 * cl.edges;
+            const bool push = which == ADJ_F_UPDATE || which == ADJ_F_FIXED;
+            const bool coded = cl.P == 64 && !h->adj_dense && (push ? h->T.Fpar != nullptr : h->T.Bch != nullptr);
+            const double per_node = coded ? 2.0 : 8.0;
+            return upd ? per_node * cl.nodes + 76.0 * cl.edges : per_node * cl.nodes + 28.0 * cl.edges;
         });
 }
 
@@ -981,6 +993,16 @@ int dd_min_marginals(dd_instance *h, float *m0_out, float *m1_out, void *stream)
 
 namespace {
 
+// Point the tables at node-cost arrays together with their argmin codes.
+void use_F(dd_instance *h, float *F, uint16_t *Fp) {
+    h->T.F = F;
+    h->T.Fpar = Fp;
+}
+void use_B(dd_instance *h, float *B, uint16_t *Bc) {
+    h->T.B = B;
+    h->T.Bch = Bc;
+}
+
 int adj_alloc(dd_instance *h) {
     if (h->adj_ready) return DD_OK;
     const size_t S = (size_t)h->edge_slots;
@@ -995,6 +1017,13 @@ int adj_alloc(dd_instance *h) {
     HIP_TRY(hipMemset(h->mdiff, 0, sizeof(float) * S));
     if ((st = h->alloc(&h->scratch_n, (size_t)std::max<int64_t>(h->n, 1)))) return st;
     if ((st = h->alloc(&h->hash_tmp, 1)) || (st = h->alloc(&h->ck_flag, 1))) return st;
+    // argmin codes of the instance's own node-cost arrays: recorded by the sweeps reverse mode reads
+    const size_t nodes = (size_t)h->node_slots + 64;
+    if ((st = h->alloc(&h->Fpar0, nodes)) || (st = h->alloc(&h->Bch0, nodes))) return st;
+    HIP_TRY(hipMemset(h->Fpar0, 0, sizeof(uint16_t) * nodes));
+    HIP_TRY(hipMemset(h->Bch0, 0, sizeof(uint16_t) * nodes));
+    h->T.Fpar = h->Fpar0;
+    h->T.Bch = h->Bch0;
     for (float *b : {h->lam_in, h->dlamA, h->dlamB, h->dMA, h->dMB, h->g, h->dalpha, h->domega, h->Se})
         HIP_TRY(hipMemset(b, 0, sizeof(float) * S));
     HIP_TRY(hipMemset(h->rec_val, 0, sizeof(float) * 2 * S));
@@ -1159,7 +1188,9 @@ namespace {
 // Device arrays for a stored run of n iterations: 2n + 1 node-cost arrays and each pass's argmin
 // records (the states before the passes are allocated as they are saved).  Bytes still to allocate:
 size_t stored_need(const dd_instance *h, int n) {
-    const size_t bytes = ((size_t)h->node_slots + 64) * sizeof(float), rec_bytes = (size_t)h->edge_slots * 12;
+    // a node-cost array and its argmin codes
+    const size_t bytes = ((size_t)h->node_slots + 64) * (sizeof(float) + sizeof(uint16_t)),
+                 rec_bytes = (size_t)h->edge_slots * 12;
     size_t need = 0;
     if ((int)h->trF.size() < n) need += ((size_t)n - h->trF.size()) * bytes;
     if ((int)h->trB.size() < n + 1) need += ((size_t)n + 1 - h->trB.size()) * bytes;
@@ -1184,13 +1215,17 @@ int stored_alloc(dd_instance *h, int n) {
     int st;
     while ((int)h->trF.size() < n) {
         float *p = nullptr;
-        if ((st = h->alloc(&p, nodes))) return st;
+        uint16_t *c = nullptr;
+        if ((st = h->alloc(&p, nodes)) || (st = h->alloc(&c, nodes))) return st;
         h->trF.push_back(p);
+        h->trFp.push_back(c);
     }
     while ((int)h->trB.size() < n + 1) {
         float *p = nullptr;
-        if ((st = h->alloc(&p, nodes))) return st;
+        uint16_t *c = nullptr;
+        if ((st = h->alloc(&p, nodes)) || (st = h->alloc(&c, nodes))) return st;
         h->trB.push_back(p);
+        h->trBc.push_back(c);
     }
     while ((int)h->tr_mrec.size() < 2 * n) {
         int32_t *p = nullptr;
@@ -1209,12 +1244,12 @@ int stored_alloc(dd_instance *h, int n) {
 int stored_passes(dd_instance *h, int n, hipStream_t s) {
     int st = save_state(h, h->tr_lam, h->tr_M, 0, s);
     for (int t = 0; t < n && st == DD_OK; ++t) {
-        h->T.F = h->trF[t];
-        h->T.B = h->trB[t];
+        use_F(h, h->trF[t], h->trFp[t]);
+        use_B(h, h->trB[t], h->trBc[t]);
         if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t])) ||
             (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)))
             break;
-        h->T.B = h->trB[t + 1];
+        use_B(h, h->trB[t + 1], h->trBc[t + 1]);
         if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1]))) break;
         st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s);
     }
@@ -1229,8 +1264,8 @@ int stored_reverse(dd_instance *h, int n, float *&dl, float *&dm, float *&dl2, f
     float *own_lam = h->T.lam, *own_M = h->T.M;
     int st = DD_OK;
     for (int t = n - 1; t >= 0 && st == DD_OK; --t) {
-        h->T.F = h->trF[t];
-        h->T.B = h->trB[t + 1];  // the backward pass of iteration t
+        use_F(h, h->trF[t], h->trFp[t]);
+        use_B(h, h->trB[t + 1], h->trBc[t + 1]);  // the backward pass of iteration t
         h->T.lam = h->tr_lam[2 * t + 2];
         h->T.M = h->tr_M[2 * t + 2];
         if ((st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1],
@@ -1238,7 +1273,7 @@ int stored_reverse(dd_instance *h, int n, float *&dl, float *&dm, float *&dl2, f
             break;
         std::swap(dl, dl2);
         std::swap(dm, dm2);
-        h->T.B = h->trB[t];  // its forward pass
+        use_B(h, h->trB[t], h->trBc[t]);  // its forward pass
         h->T.lam = h->tr_lam[2 * t + 1];
         h->T.M = h->tr_M[2 * t + 1];
         if ((st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t], h->tr_mrec[2 * t],
@@ -1266,19 +1301,19 @@ int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void 
     h->F0 = h->T.F;
     h->B0 = h->T.B;
     h->fwd_stored = false;
-    h->T.B = h->trB[0];  // B at the start state goes to the first stored array
+    use_B(h, h->trB[0], h->trBc[0]);  // B at the start state goes to the first stored array
     if (from_state) {
         if ((st = recompute_B(h, s))) return st;
         h->version++;
     } else if ((st = dd_reset(h, stream))) {
-        h->T.B = h->B0;
+        use_B(h, h->B0, h->Bch0);
         return st;
     }
     st = stored_passes(h, T, s);
     if (st == DD_OK) st = dd_lower_bound(h, lb, nullptr, stream);
     const hipError_t e = hipMemcpyAsync(h->B0, h->trB[T], bytes, hipMemcpyDeviceToDevice, s);
-    h->T.F = h->F0;
-    h->T.B = h->B0;
+    use_F(h, h->F0, h->Fpar0);
+    use_B(h, h->B0, h->Bch0);
     h->b_valid = true;   // B of the final state, copied back
     h->f_valid = false;  // the instance's own F was not written
     if (st) return st;
@@ -1353,10 +1388,11 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     if (st == DD_OK && !stored) st = verify_state(h, h->T.lam, h->T.M, (size_t)nseg, s);
     if (st) return st;
     if ((st = deferred(h, s))) return st;
-    if (stored) h->T.B = h->F0;  // a stored trajectory keeps the final B in B0: the bound's B goes to the spare array
+    // a stored trajectory keeps the final B in B0: the bound's B goes to the spare array (with its codes)
+    if (stored) use_B(h, h->F0, h->Fpar0);
     st = all_classes(h, false, BWD_STORE_BAR, s);
     if (st) {
-        h->T.B = h->B0;
+        use_B(h, h->B0, h->Bch0);
         return st;
     }
     HIP_TRY(launch_fill(h->dalpha, 0.f, h->edge_slots, s));
@@ -1374,36 +1410,39 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     float *dl = h->dlamA, *dm = h->dMA, *dl2 = h->dlamB, *dm2 = h->dMB;
     if (stored) {
         st = stored_reverse(h, T, dl, dm, dl2, dm2, s);
-        h->T.F = h->F0;
-        h->T.B = h->B0;
+        use_F(h, h->F0, h->Fpar0);
+        use_B(h, h->B0, h->Bch0);
         if (st) return st;
     }
     // checkpoint segments: when the device holds a stored run of K iterations, each segment is
     // recomputed into the stored-trajectory arrays and reversed like a stored trajectory (no pass
     // replayed); otherwise the pass inputs are recomputed and each pass is replayed for its adjoint
     float *own_F = h->T.F, *own_B = h->T.B;
+    uint16_t *own_Fp = h->T.Fpar, *own_Bc = h->T.Bch;
     const bool seg_store = !stored && !h->adj_replay && nseg > 0 && stored_fits(h, K) && stored_alloc(h, K) == DD_OK;
     for (int seg = stored ? -1 : nseg - 1; seg >= 0; --seg) {
         const int t0 = seg * K, t1 = std::min(T, t0 + K), np = 2 * (t1 - t0);
         if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)seg, s))) return st;
         if ((st = verify_state(h, h->T.lam, h->T.M, (size_t)seg, s))) return st;
         if (seg_store) {
-            h->T.B = h->trB[0];  // B at the checkpoint goes to the first stored array
+            use_B(h, h->trB[0], h->trBc[0]);  // B at the checkpoint goes to the first stored array
             st = recompute_B(h, s);
             if (st == DD_OK) st = stored_passes(h, t1 - t0, s);
             if (st == DD_OK) st = verify_state(h, h->tr_lam[np], h->tr_M[np], (size_t)seg + 1, s);
             if (st == DD_OK) st = stored_reverse(h, t1 - t0, dl, dm, dl2, dm2, s);
-            h->T.F = own_F;
-            h->T.B = own_B;
+            use_F(h, own_F, own_Fp);
+            use_B(h, own_B, own_Bc);
             if (st) return st;
             continue;
         }
         // a forward pass reads B at its input multipliers: the backward pass before it left
         // exactly that, so rebuild it from the checkpoint (same expression, same bits)
         if ((st = recompute_B(h, s))) return st;
-        for (int q = 0; q < np; ++q) {  // recompute the pass inputs of the segment (the last records)
+        // recompute the pass inputs of the segment; the last two passes record (the last one's argmins,
+        // and the argmin codes of both: the last pass's reverse sweeps read the F its forward pass left)
+        for (int q = 0; q < np; ++q) {
             if ((st = save_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
-            if ((st = q == np - 1 ? run_pass_rec(h, q % 2, s) : dd_run_pass(h, q % 2, stream))) return st;
+            if ((st = q >= np - 2 ? run_pass_rec(h, q % 2, s) : dd_run_pass(h, q % 2, stream))) return st;
         }
         if ((st = verify_state(h, h->T.lam, h->T.M, (size_t)seg + 1, s))) return st;
         for (int q = np - 1; q >= 0; --q) {

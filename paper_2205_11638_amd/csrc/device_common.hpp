@@ -202,10 +202,23 @@ __device__ __forceinline__ int node_bytes(const Lev &c) { return ((c.W + 3) & ~3
 __device__ __forceinline__ int groups(const Lev &c) { return (c.R + 3) >> 2; }
 
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st2(rsrc_t r, int off, uint32_t a, uint32_t b) {
-    typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
     const u32x2 v = {a, b};
     __builtin_amdgcn_raw_buffer_store_b64(v, r, off, 0, 0);
+}
+__device__ __forceinline__ u32x2 ld2(rsrc_t r, int off) { return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0); }
+// Argmin codes (2 bytes per node) of one-wave diagrams: a lane's four nodes 4 lane + j of group q
+// are the 8 bytes at 512 q + 8 lane of the level's code row; code j is half j & 1 of word j >> 1.
+__device__ __forceinline__ int lane8(int lane) {
+    int v = lane * 8;
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ int code_bytes(const Lev &c) { return ((c.W + 3) & ~3) * 2; }
+__device__ __forceinline__ uint32_t code_at(const u32x2 &w, int j) { return (w[j >> 1] >> (16 * (j & 1))) & 0xFFFFu; }
+__device__ __forceinline__ void lds_umin(uint32_t *a, uint32_t v) {
+    __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 
 // Recording update passes (one-wave diagrams): each lane visits its nodes in increasing index and

@@ -91,6 +91,10 @@ struct dd_instance {
     std::vector<int32_t *> tr_mrec;     // argmin records of pass q = 0 .. 2T-1
     std::vector<float *> tr_mdiff;
     float *F0 = nullptr, *B0 = nullptr; // the instance's own node-cost arrays
+    // argmin codes of the node costs (DevTables::Fpar / Bch): the instance's own, paired with F0 / B0,
+    // and those of the stored trajectory's arrays (trFp[t] with trF[t], trBc[t] with trB[t])
+    uint16_t *Fpar0 = nullptr, *Bch0 = nullptr;
+    std::vector<uint16_t *> trFp, trBc;
     bool fwd_stored = false;
     int fwd_T = -1, fwd_K = 0;
     bool fwd_from_state = false;  // the recorded forward started from a given state (no reset)

@@ -390,11 +390,13 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
 // empty-level case.  The arithmetic is that of the general kernels above; the min over a
 // level's arcs is exact, so the order in which a lane visits its nodes does not matter.
 template <int Q, int RMAX, int MODE, typename Prefetch>
-__device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, rsrc_t rec_r, rsrc_t md_r, float *Fb,
-                                          const float *Bst, const u32x4 (&tp)[RMAX / 4], int lane, int out,
+__device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, rsrc_t rec_r, rsrc_t md_r, rsrc_t Pr,
+                                          float *Fb, float *Bst, const u32x4 (&tp)[RMAX / 4], int lane, int out,
                                           const Lev &c0, const Lev &c1, float lam, float om, float aS,
                                           Prefetch &&prefetch) {
     constexpr bool REC = MODE == FWD_UPDATE_REC, UPD = MODE == FWD_UPDATE || REC;
+    // the sweeps that reverse mode reads record each next-level node's argmin parent arc
+    constexpr bool PAR = REC || MODE == FWD_SWEEP_LAM;
     constexpr int QM = RMAX / 4, SINK = RMAX * 64;
     const int l16 = lane16(lane);
     f32x4 fv[Q];
@@ -451,6 +453,33 @@ __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, r
             lds_fmin(&Fb[hi < c1.W ? hi : SINK + lane], fv[q][j] + lam_new);
         }
     wave_sync();
+    if constexpr (PAR) {
+        // argmin parent arcs of level l+1: every arc whose value is its child's cost bids 2 k + beta
+        // (an integer min in the staged-B buffer, free once the min-marginals are formed), the lowest
+        // bid wins (lo before hi, lowest node), and the owners of level l+1 store the winners
+        uint32_t *bid = (uint32_t *)Bst;
+        const u32x4 none = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
+#pragma unroll
+        for (int q = 0; q < QM; ++q) *(u32x4 *)((char *)bid + l16 + q * 1024) = none;
+        wave_sync();
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
+                const uint32_t k2 = 2u * (uint32_t)(q * 256 + (l16 >> 2) + j);
+                if (lo < c1.W && fv[q][j] == Fb[lo]) lds_umin(&bid[lo], k2);
+                if (hi < c1.W && fv[q][j] + lam_new == Fb[hi]) lds_umin(&bid[hi], k2 + 1u);
+            }
+        wave_sync();
+        const int l8 = lane8(lane);
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const u32x4 b = *(const u32x4 *)((const char *)bid + l16 + q * 1024);
+            st2(Pr, l8 + q * 512, (b[0] & 0xFFFFu) | (b[1] << 16), (b[2] & 0xFFFFu) | (b[3] << 16));
+        }
+        wave_sync();  // the bids are read: the next hop stages B here
+    }
 }
 
 template <int RMAX, int MODE, bool LOOP>
@@ -534,8 +563,10 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
                 if (UPD) omn = T.omega[e];
             };
             const rsrc_t Fr = buf(T.F + c0.base, node_bytes(c0));
+            const rsrc_t Pr = buf(T.Fpar ? (const void *)(T.Fpar + c1.base) : (const void *)T.F,
+                                  T.Fpar ? code_bytes(c1) : 0);  // no codes recorded: every store dropped
             with_count<1, QM>(groups(c0), [&](auto qc) {
-                fwd_hop_w<decltype(qc)::value, RMAX, MODE>(Fr, lam_r, M_r, rec_r, md_r, Fb, Bst, tp, lane,
+                fwd_hop_w<decltype(qc)::value, RMAX, MODE>(Fr, lam_r, M_r, rec_r, md_r, Pr, Fb, Bst, tp, lane,
                                                            out0 + 4 * l, c0, c1, lam, om, aS, prefetch);
             });
             c0 = c1;
@@ -552,8 +583,9 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
 // Backward hop of level l: bn = B of level l+1 (Wn its width: terminals at Wn, Wn+1), bc
 // receives B of level l, which also goes to global memory here, from registers.
 template <int Q, int RMAX, int MODE>
-__device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t lam_r, rsrc_t M_r, rsrc_t rec_r,
-                                          rsrc_t md_r, const float *bn, float *bc, const u32x4 (&tp)[RMAX / 4],
+__device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t Cr, rsrc_t lam_r, rsrc_t M_r,
+                                          rsrc_t rec_r, rsrc_t md_r, const float *bn, float *bc,
+                                          const u32x4 (&tp)[RMAX / 4],
                                           const f32x4 (&fn)[RMAX / 4], int lane, int out, const Lev &c0, int Wn,
                                           float lam, float om, float aS, int ce) {
     constexpr bool REC = MODE == BWD_UPDATE_REC, UPD = MODE == BWD_UPDATE || REC, MM = MODE == BWD_MM;
@@ -625,6 +657,23 @@ __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t 
         const f32x4 z = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int q = 0; q < QM; ++q) st4(Br, l16 + q * 1024, q < Q ? bv[q < Q ? q : 0] : z);
+    }
+    if constexpr (REC || MODE == BWD_STORE || MODE == BWD_STORE_BAR) {
+        // the arc each node's B went through (the pull sweeps' argmin child: lo on ties), as
+        // child code | beta << 15; dropped when the codes are not recorded (Cr of no size)
+        const int l8 = lane8(lane);
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            uint32_t c[4] = {0u, 0u, 0u, 0u};
+            if (q < Q)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int qq = q < Q ? q : 0;
+                    const bool hi = lam_new + b1[qq][j] < b0[qq][j];
+                    c[j] = hi ? ((t[qq][j] >> 16) | 0x8000u) : (t[qq][j] & 0xFFFFu);
+                }
+            st2(Cr, l8 + q * 512, c[0] | (c[1] << 16), c[2] | (c[3] << 16));
+        }
     }
 }
 
@@ -708,8 +757,10 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
                 if (MM) cen = T.slot2canon[e];
             }
             const rsrc_t Br = buf(T.B + c0.base, node_bytes(c0));
+            const rsrc_t Cr = buf(T.Bch ? (const void *)(T.Bch + c0.base) : (const void *)T.B,
+                                  T.Bch ? code_bytes(c0) : 0);  // no codes recorded: every store dropped
             with_count<1, QM>(groups(c0), [&](auto qc) {
-                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, lam_r, M_r, rec_r, md_r, bn, bc, tp, fv, lane,
+                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, Cr, lam_r, M_r, rec_r, md_r, bn, bc, tp, fv, lane,
                                                            out0 + 4 * l, c0, Wn, lam, om, aS, ce);
             });
             wave_sync();

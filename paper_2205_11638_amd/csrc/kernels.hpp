@@ -62,6 +62,13 @@ struct DevTables {
     // m^0 | its lo child << 16, [2 slot + 1] = the same for m^1 and the hi child; mdiff = m^1 - m^0
     int32_t *mrec;
     float *mdiff;
+    // argmin codes of the node costs in F and B (one-wave diagrams, node-slot indexed like F and B; NULL:
+    // not recorded).  Fpar[w] = 2 k + beta: the arc (node k of the level above, beta) whose value is
+    // F(w) (lowest code on ties), written by the forward sweeps that the reverse sweeps read
+    // (FWD_UPDATE_REC, FWD_SWEEP_LAM).  Bch[v] = child code | beta << 15: the arc that attains B(v) (lo
+    // on ties), written by BWD_UPDATE_REC, BWD_STORE and BWD_STORE_BAR.
+    uint16_t *Fpar;
+    uint16_t *Bch;
 };
 
 struct ClassLaunch {
