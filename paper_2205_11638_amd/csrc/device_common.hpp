@@ -220,6 +220,30 @@ __device__ __forceinline__ uint32_t code_at(const u32x2 &w, int j) { return (w[j
 __device__ __forceinline__ void lds_umin(uint32_t *a, uint32_t v) {
     __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
+// A cost and a 16-bit code as one 64-bit key whose unsigned order is (cost, code): the cost's bits
+// are mapped to an unsigned integer of the same order (sign bit set for non-negative values, all
+// bits flipped for negative ones), so one integer min gives the least cost and, among equal costs,
+// the lowest code.
+__device__ __forceinline__ uint64_t cost_key(float v, uint32_t code) {
+    uint32_t u = __float_as_uint(v);
+    if (u == 0x80000000u) u = 0u;  // -0 and +0 are one cost
+    const uint32_t o = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return ((uint64_t)o << 32) | code;
+}
+__device__ __forceinline__ float key_cost(uint64_t k) {
+    const uint32_t o = (uint32_t)(k >> 32);
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o);
+}
+__device__ __forceinline__ void lds_umin64(uint64_t *a, uint64_t v) {
+    __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+// 32 * lane (a lane's four 64-bit keys of a 256-node group), made anew like lane16
+__device__ __forceinline__ int lane32(int lane) {
+    int v = lane * 32;
+    __asm__ volatile("" : "+v"(v));
+    return v;
+}
 
 // Recording update passes (one-wave diagrams): each lane visits its nodes in increasing index and
 // keeps the first one attaining its running minimum m of a min-marginal (call before m takes v),

@@ -389,22 +389,40 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
 // the tile.  Every level of a built diagram holds at least one node, so the update needs no
 // empty-level case.  The arithmetic is that of the general kernels above; the min over a
 // level's arcs is exact, so the order in which a lane visits its nodes does not matter.
+// The sweeps that reverse mode reads also record each node's argmin parent arc 2 k + beta: their
+// next-level buffer holds 64-bit keys (cost, code) (cost_key), so one integer min per arc forms the
+// cost and, among arcs of equal cost, the lowest code (lo before hi, lowest node); the next hop
+// splits the keys of its level into the F row and the code row.
 template <int Q, int RMAX, int MODE, typename Prefetch>
 __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, rsrc_t rec_r, rsrc_t md_r, rsrc_t Pr,
-                                          float *Fb, float *Bst, const u32x4 (&tp)[RMAX / 4], int lane, int out,
-                                          const Lev &c0, const Lev &c1, float lam, float om, float aS,
+                                          float *Fb, const float *Bst, const u32x4 (&tp)[RMAX / 4], int lane,
+                                          int out, const Lev &c0, const Lev &c1, float lam, float om, float aS,
                                           Prefetch &&prefetch) {
     constexpr bool REC = MODE == FWD_UPDATE_REC, UPD = MODE == FWD_UPDATE || REC;
-    // the sweeps that reverse mode reads record each next-level node's argmin parent arc
     constexpr bool PAR = REC || MODE == FWD_SWEEP_LAM;
     constexpr int QM = RMAX / 4, SINK = RMAX * 64;
     const int l16 = lane16(lane);
+    uint64_t *Kb = (uint64_t *)Fb;  // PAR: the keys of this level, then of level l+1
     f32x4 fv[Q];
     u32x4 t[Q];
+    if constexpr (PAR) {
+        const int l32 = lane32(lane), l8 = lane8(lane);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        fv[q] = lds4(Fb, l16 + q * 1024);  // slots past the level's width hold +inf
-        t[q] = tp[q];
+        for (int q = 0; q < Q; ++q) {
+            const u64x2 a = *(const u64x2 *)((const char *)Kb + l32 + q * 2048);
+            const u64x2 b = *(const u64x2 *)((const char *)Kb + l32 + q * 2048 + 16);
+            fv[q] = f32x4{key_cost(a[0]), key_cost(a[1]), key_cost(b[0]), key_cost(b[1])};
+            // codes of this level's nodes (every slot past the width holds 0xFFFF)
+            st2(Pr, l8 + q * 512, ((uint32_t)a[0] & 0xFFFFu) | ((uint32_t)a[1] << 16),
+                ((uint32_t)b[0] & 0xFFFFu) | ((uint32_t)b[1] << 16));
+            t[q] = tp[q];
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            fv[q] = lds4(Fb, l16 + q * 1024);  // slots past the level's width hold +inf
+            t[q] = tp[q];
+        }
     }
     // last group: this lane's slots past the level's width get two 0-terminal arcs
     const int rem = c0.W - (Q - 1) * 256 - lane * 4;
@@ -415,9 +433,20 @@ __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, r
 #pragma unroll
     for (int q = 0; q < Q; ++q) st4(Fr, l16 + q * 1024, fv[q]);  // F for the backward pass
     prefetch(l16);  // after the stores: waiting for the prefetched rows then waits for no fresh store
-    const f32x4 inf4 = {kInf, kInf, kInf, kInf};
+    if constexpr (PAR) {
+        const int l32 = lane32(lane);
+        const uint64_t none = cost_key(kInf, 0xFFFFu);
+        const u64x2 none2 = {none, none};
 #pragma unroll
-    for (int q = 0; q < QM; ++q) lds4(Fb, l16 + q * 1024) = inf4;  // F of level l+1 accumulates here
+        for (int q = 0; q < QM; ++q) {
+            *(u64x2 *)((char *)Kb + l32 + q * 2048) = none2;  // level l+1 accumulates here
+            *(u64x2 *)((char *)Kb + l32 + q * 2048 + 16) = none2;
+        }
+    } else {
+        const f32x4 inf4 = {kInf, kInf, kInf, kInf};
+#pragma unroll
+        for (int q = 0; q < QM; ++q) lds4(Fb, l16 + q * 1024) = inf4;  // F of level l+1 accumulates here
+    }
     wave_sync();
     float lam_new;
     if (UPD) {
@@ -449,49 +478,29 @@ __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, r
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
-            lds_fmin(&Fb[lo < c1.W ? lo : SINK + lane], fv[q][j]);
-            lds_fmin(&Fb[hi < c1.W ? hi : SINK + lane], fv[q][j] + lam_new);
+            if constexpr (PAR) {
+                const uint32_t k2 = 2u * (uint32_t)(q * 256 + (l16 >> 2) + j);
+                lds_umin64(&Kb[lo < c1.W ? lo : SINK + lane], cost_key(fv[q][j], k2));
+                lds_umin64(&Kb[hi < c1.W ? hi : SINK + lane], cost_key(fv[q][j] + lam_new, k2 + 1u));
+            } else {
+                lds_fmin(&Fb[lo < c1.W ? lo : SINK + lane], fv[q][j]);
+                lds_fmin(&Fb[hi < c1.W ? hi : SINK + lane], fv[q][j] + lam_new);
+            }
         }
     wave_sync();
-    if constexpr (PAR) {
-        // argmin parent arcs of level l+1: every arc whose value is its child's cost bids 2 k + beta
-        // (an integer min in the staged-B buffer, free once the min-marginals are formed), the lowest
-        // bid wins (lo before hi, lowest node), and the owners of level l+1 store the winners
-        uint32_t *bid = (uint32_t *)Bst;
-        const u32x4 none = {0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};
-#pragma unroll
-        for (int q = 0; q < QM; ++q) *(u32x4 *)((char *)bid + l16 + q * 1024) = none;
-        wave_sync();
-#pragma unroll
-        for (int q = 0; q < Q; ++q)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int lo = (int)(t[q][j] & 0xFFFFu), hi = (int)(t[q][j] >> 16);
-                const uint32_t k2 = 2u * (uint32_t)(q * 256 + (l16 >> 2) + j);
-                if (lo < c1.W && fv[q][j] == Fb[lo]) lds_umin(&bid[lo], k2);
-                if (hi < c1.W && fv[q][j] + lam_new == Fb[hi]) lds_umin(&bid[hi], k2 + 1u);
-            }
-        wave_sync();
-        const int l8 = lane8(lane);
-#pragma unroll
-        for (int q = 0; q < QM; ++q) {
-            const u32x4 b = *(const u32x4 *)((const char *)bid + l16 + q * 1024);
-            st2(Pr, l8 + q * 512, (b[0] & 0xFFFFu) | (b[1] << 16), (b[2] & 0xFFFFu) | (b[3] << 16));
-        }
-        wave_sync();  // the bids are read: the next hop stages B here
-    }
 }
 
 template <int RMAX, int MODE, bool LOOP>
 __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64_t ntiles, int NL) {
     constexpr bool REC = MODE == FWD_UPDATE_REC, UPD = MODE == FWD_UPDATE || REC;
+    constexpr bool PAR = REC || MODE == FWD_SWEEP_LAM;
     constexpr int NB = node_buf_w(RMAX), QM = RMAX / 4;
     extern __shared__ float lds_f[];
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;  // uniform per wave
-    float *Fb = lds_f + (size_t)wave * lds_words_pass_w(RMAX, NL);
-    float *Bst = Fb + NB;
+    float *Fb = lds_f + (size_t)wave * (PAR ? lds_words_pass_w_par(RMAX, NL) : lds_words_pass_w(RMAX, NL));
+    float *Bst = Fb + (PAR ? 2 * NB : NB);  // PAR: Fb holds NB 64-bit keys
     int *meta = (int *)(Bst + NB);
     int *off = meta + NL;
     const f32x4 inf4 = {kInf, kInf, kInf, kInf};
@@ -524,7 +533,18 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
             }
         }
         float lamn = T.lam[tc.ebase], aSn = T.aS[tc.ebase], omn = UPD ? T.omega[tc.ebase] : 0.f;
-        {
+        if constexpr (PAR) {
+            const int l32 = lane32(lane);
+            const uint64_t none = cost_key(kInf, 0xFFFFu);
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                u64x2 a = {none, none};
+                const u64x2 b = {none, none};
+                if (q == 0 && lane == 0) a[0] = cost_key(0.f, 0xFFFFu);  // F(root) = 0
+                *(u64x2 *)((char *)Fb + l32 + q * 2048) = a;
+                *(u64x2 *)((char *)Fb + l32 + q * 2048 + 16) = b;
+            }
+        } else {
             const int l16 = lane16(lane);
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
@@ -563,8 +583,10 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
                 if (UPD) omn = T.omega[e];
             };
             const rsrc_t Fr = buf(T.F + c0.base, node_bytes(c0));
-            const rsrc_t Pr = buf(T.Fpar ? (const void *)(T.Fpar + c1.base) : (const void *)T.F,
-                                  T.Fpar ? code_bytes(c1) : 0);  // no codes recorded: every store dropped
+            // codes of this level (the root has no parent; no codes recorded: every store dropped)
+            const bool codes = PAR && T.Fpar && l > 0;
+            const rsrc_t Pr = buf(codes ? (const void *)(T.Fpar + c0.base) : (const void *)T.F,
+                                  codes ? code_bytes(c0) : 0);
             with_count<1, QM>(groups(c0), [&](auto qc) {
                 fwd_hop_w<decltype(qc)::value, RMAX, MODE>(Fr, lam_r, M_r, rec_r, md_r, Pr, Fb, Bst, tp, lane,
                                                            out0 + 4 * l, c0, c1, lam, om, aS, prefetch);
@@ -785,9 +807,13 @@ inline unsigned full_grid(int64_t ntiles, int wpb) { return (unsigned)((ntiles +
 
 template <int RMAX>
 hipError_t fwd_dispatch_w(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
-    const unsigned full = full_grid(c.ntiles, c.wpb_f);
-    dim3 grid(full), block(64 * c.wpb_f);
-    size_t lds = (size_t)c.wpb_f * lds_words_pass_w(RMAX, c.NL) * 4;
+    // the recording sweeps need a node buffer more per wave: at most the waves per workgroup of the
+    // push-form adjoint sweep, whose LDS per wave is larger still
+    const bool par = mode == FWD_UPDATE_REC || mode == FWD_SWEEP_LAM;
+    const int wpb = par ? std::min(c.wpb_f, c.wpb_af) : c.wpb_f;
+    const unsigned full = full_grid(c.ntiles, wpb);
+    dim3 grid(full), block(64 * wpb);
+    size_t lds = (size_t)wpb * (par ? lds_words_pass_w_par(RMAX, c.NL) : lds_words_pass_w(RMAX, c.NL)) * 4;
     if (mode == FWD_UPDATE && c.grid_f > 0 && (unsigned)c.grid_f < full)
         hipLaunchKernelGGL((k_fwd_w<RMAX, FWD_UPDATE, true>), dim3(c.grid_f), block, lds, s, t, c.tile0, c.ntiles, c.NL);
     else if (mode == FWD_UPDATE)

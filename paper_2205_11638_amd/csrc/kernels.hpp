@@ -104,6 +104,9 @@ constexpr int lds_words_pass(int P, int WB, int NL) {  // constexpr: usable in d
 // wave's share is a multiple of 4 words, so 16-byte LDS accesses stay aligned.
 constexpr int node_buf_w(int RMAX) { return RMAX * 64 + 64; }
 constexpr int lds_words_pass_w(int RMAX, int NL) { return 2 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+// The forward sweeps that record argmin parent codes keep the next level's costs as 64-bit keys
+// (cost, code): one node buffer more.
+constexpr int lds_words_pass_w_par(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
 // LDS words per wave of the pass kernels of a class
 constexpr int lds_words_pass_c(int P, int RMAX, int WB, int NL) {
     return P == 64 ? lds_words_pass_w(RMAX, NL) : lds_words_pass(P, WB, NL);
@@ -129,6 +132,8 @@ constexpr int64_t kFormAsMaxBytes = 4 << 20;
 constexpr int lds_words_adj_F_w(int RMAX, int NL) {
     return 3 * node_buf_w(RMAX) + 3 * kAdjListW + ((2 * NL + 3) & ~3);
 }
+// the recording forward sweeps launch with the push-form sweep's waves per workgroup
+static_assert(lds_words_pass_w_par(32, 1024) <= lds_words_adj_F_w(32, 1024), "recording sweep LDS");
 constexpr int lds_words_adj_F_c(int P, int RMAX, int WB, int NL) {
     return P == 64 ? lds_words_adj_F_w(RMAX, NL) : lds_words_adj_F(P, WB, NL);
 }
