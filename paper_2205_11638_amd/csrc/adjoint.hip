@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_adj_B(DevTables T, AdjTables A, int64_t
     {
         const int R0 = uni(meta[0] >> 16);
         for (int r = 0; r < R0; ++r) Ba[mine + r * P * G] = 0.f;
-        if (p == 0) Ba[g] = seed;  // the root is node 0 of level 0
+        if (p == 0) Ba[g] = A.seed ? *A.seed : seed;  // the root is node 0 of level 0
     }
     Lev c0 = level(0), c1 = level(1);
     uint32_t tpn[RMAX];
@@ -586,7 +586,7 @@ __global__ __launch_bounds__(256) void k_adj_B_w(DevTables T, AdjTables A, int64
         const int l16 = lane16(lane);
 #pragma unroll
         for (int q = 0; q < QM; ++q) lds4(Ba, l16 + q * 1024) = zero4;
-        if (lane == 0) Ba[0] = seed;  // the root is node 0 of level 0
+        if (lane == 0) Ba[0] = A.seed ? *A.seed : seed;  // the root is node 0 of level 0
     }
     Lev c0 = level(0), c1 = level(1);
     u32x4 tpn[QM];
@@ -1221,7 +1221,7 @@ __global__ __launch_bounds__(256) void k_adjc_B_w(DevTables T, AdjTables A, int6
         const int l16 = lane16(lane);
 #pragma unroll
         for (int q = 0; q < QM; ++q) lds4(Ba, l16 + q * 1024) = zero4;
-        if (lane == 0) Ba[0] = seed;  // the root is node 0 of level 0
+        if (lane == 0) Ba[0] = A.seed ? *A.seed : seed;  // the root is node 0 of level 0
     }
     Lev c0 = level(0), c1 = level(1);
     u32x2 ccn[QM];

@@ -879,6 +879,8 @@ void drop_graphs(dd_instance *h) {
     if (h->graph_one) (void)hipGraphExecDestroy(h->graph_one);
     if (h->graph_chunk) (void)hipGraphExecDestroy(h->graph_chunk);
     h->graph_one = h->graph_chunk = nullptr;
+    for (dd_instance::SeqGraph &g : h->seq_graphs) (void)hipGraphExecDestroy(g.exec);
+    h->seq_graphs.clear();
 }
 
 }  // namespace ddi
@@ -1181,6 +1183,75 @@ int dd_pass_vjp(dd_instance *h, int32_t direction, const float *lam_in, const fl
 
 namespace {
 
+constexpr size_t kMaxSeqGraphs = 8;  // captured sequences kept per instance (the oldest goes first)
+
+// Runs `seq(q)` -- the launches of a sequence fixed by `key` on stream q, with their host-side
+// bookkeeping -- eagerly while profiling or without graphs.  Otherwise the first run with a key
+// captures the sequence on the instance's own stream and replays the graph on s; later runs only
+// replay it and apply the host-side effects the capture recorded (state version, side flags, table
+// pointers).  The key also holds everything host code reads to choose the launches: the side flags
+// and table pointers on entry and the allocation count, so a sequence that would see other buffers
+// is captured anew.  A sequence must not allocate (its buffers are allocated beforehand), read device
+// memory on the host or wait for the device.
+template <typename Seq>
+int replayed(dd_instance *h, std::vector<int64_t> key, hipStream_t s, Seq &&seq) {
+    if (h->prof || !h->use_graphs) return seq(s);
+    key.insert(key.end(), {h->alloc_epoch, (int64_t)h->en_lam_valid, (int64_t)h->b_valid, (int64_t)h->f_valid,
+                           (int64_t)h->adj_dense, (int64_t)h->adj_replay, (int64_t)(intptr_t)h->T.F,
+                           (int64_t)(intptr_t)h->T.B, (int64_t)(intptr_t)h->T.lam, (int64_t)(intptr_t)h->T.M});
+    for (const dd_instance::SeqGraph &g : h->seq_graphs)
+        if (g.key == key) {
+            HIP_TRY(hipGraphLaunch(g.exec, s));
+            h->version += g.dversion;
+            h->en_lam_valid = g.en_lam_valid;
+            h->b_valid = g.b_valid;
+            h->f_valid = g.f_valid;
+            h->T.F = g.F;
+            h->T.B = g.B;
+            h->T.Fpar = g.Fpar;
+            h->T.Bch = g.Bch;
+            h->T.lam = g.lam;
+            h->T.M = g.M;
+            return DD_OK;
+        }
+    if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    const int64_t v0 = h->version;
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    h->capturing = true;
+    const int st = seq(h->cap_stream);
+    h->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+    if (st != DD_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return st != DD_OK ? st : fail(DD_E_HIP, "sequence capture: %s", hipGetErrorString(e));
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(DD_E_HIP, "sequence graph instantiate: %s", hipGetErrorString(ei));
+    if (h->seq_graphs.size() >= kMaxSeqGraphs) {
+        (void)hipGraphExecDestroy(h->seq_graphs.front().exec);
+        h->seq_graphs.erase(h->seq_graphs.begin());
+    }
+    h->seq_graphs.push_back({std::move(key), x, h->version - v0, h->en_lam_valid, h->b_valid, h->f_valid, h->T.F,
+                             h->T.B, h->T.lam, h->T.M, h->T.Fpar, h->T.Bch});
+    HIP_TRY(hipGraphLaunch(x, s));
+    return DD_OK;
+}
+
+// State arrays L[0 .. n-1], Mv[0 .. n-1] allocated (save_state fills them).
+int reserve_states(dd_instance *h, std::vector<float *> &L, std::vector<float *> &Mv, size_t n) {
+    while (L.size() < n) {
+        float *a = nullptr, *b = nullptr;
+        int st = h->alloc(&a, (size_t)h->edge_slots);
+        if (st || (st = h->alloc(&b, (size_t)h->edge_slots))) return st;
+        L.push_back(a);
+        Mv.push_back(b);
+    }
+    return DD_OK;
+}
+
 // The unrolled forward with its whole trajectory kept on the device: every forward pass writes F
 // into an array of its own and every backward pass B (the tables are pointed at them), and the
 // state before every pass is kept.  Afterwards the instance is back on its own arrays, with B as
@@ -1309,7 +1380,8 @@ int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void 
         use_B(h, h->B0, h->Bch0);
         return st;
     }
-    st = stored_passes(h, T, s);
+    if (st == DD_OK) st = reserve_states(h, h->tr_lam, h->tr_M, 2 * (size_t)T + 1);
+    if (st == DD_OK) st = replayed(h, {1, T}, s, [&](hipStream_t q) { return stored_passes(h, T, q); });
     if (st == DD_OK) st = dd_lower_bound(h, lb, nullptr, stream);
     const hipError_t e = hipMemcpyAsync(h->B0, h->trB[T], bytes, hipMemcpyDeviceToDevice, s);
     use_F(h, h->F0, h->Fpar0);
@@ -1349,15 +1421,21 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
         if ((st = h->alloc(&h->ck_hash, cap))) return st;
         h->ck_hash_cap = cap;
     }
-    auto checkpoint = [&](size_t i) {
-        int r = save_state(h, h->ck_lam, h->ck_M, i, s);
-        return r ? r : state_hash(h, h->ck_lam[i], h->ck_M[i], h->ck_hash + i, s);
-    };
-    for (int t = 0; t < T; ++t) {
-        if (t % K == 0 && (st = checkpoint((size_t)(t / K)))) return st;
-        if ((st = dd_run(h, 1, stream))) return st;
-    }
-    if ((st = checkpoint((size_t)nseg))) return st;  // the final state
+    if ((st = reserve_states(h, h->ck_lam, h->ck_M, (size_t)nseg + 1))) return st;
+    // T iterations with a checkpoint (state and fingerprint) every K and one of the final state
+    st = replayed(h, {2, T, K}, s, [&](hipStream_t q) {
+        auto checkpoint = [&](size_t i) {
+            int r = save_state(h, h->ck_lam, h->ck_M, i, q);
+            return r ? r : state_hash(h, h->ck_lam[i], h->ck_M[i], h->ck_hash + i, q);
+        };
+        int r = DD_OK;
+        for (int t = 0; t < T && r == DD_OK; ++t) {
+            if (t % K == 0 && (r = checkpoint((size_t)(t / K)))) break;
+            for (int d = 0; d < 2 && r == DD_OK; ++d) r = dd_run_pass(h, d, q);
+        }
+        return r ? r : checkpoint((size_t)nseg);
+    });
+    if (st) return st;
     if ((st = dd_lower_bound(h, lb, nullptr, stream))) return st;
     h->fwd_T = T;
     h->fwd_K = K;
@@ -1367,21 +1445,12 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
     return DD_OK;
 }
 
-int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, float *d_lam0, float *d_M0,
-             void *stream) {
-    if (!h) return fail(DD_E_ARG, "NULL instance");
-    if (h->fwd_T < 0 || h->fwd_version != h->version)
-        return fail(DD_E_STATE, "the backward sweep needs the state left by an unrolled forward");
-    if (d_c && h->fwd_from_state)
-        return fail(DD_E_ARG, "d_c needs an unrolled forward from the reset state (lambda = c/|J_i|)");
-    hipStream_t s = (hipStream_t)stream;
-    const bool stored = h->fwd_stored;
-    const int T = h->fwd_T, K = stored ? 1 : h->fwd_K, nseg = (T + K - 1) / K;
-    const float seed = (float)dlb;
+// The launches of the backward sweep up to the adjoints of the start state (in dlamA / dMA: every pass
+// adjoint swaps the buffer pairs, and there are 2T of them); d_alpha and d_omega accumulate in the
+// slot-ordered dalpha / domega.  The seed is read from seed_dev.
+int backward_core(dd_instance *h, int T, int K, bool stored, bool seg_store, hipStream_t s) {
+    const int nseg = (T + K - 1) / K;
     int st;
-    // checkpoints are verified against the fingerprints taken when they were saved: when loaded, and
-    // at the end of each recomputed segment (the recomputation must reproduce the next checkpoint)
-    if (!stored) HIP_TRY(launch_fill((float *)h->ck_flag, 0.f, 1, s));
     // adjoint of the lower bound at the final state: dLB / dlambda_bar_j = argmin assignment of row j
     if (stored) st = load_state(h, h->tr_lam, h->tr_M, 2 * (size_t)T, s);
     else st = load_state(h, h->ck_lam, h->ck_M, (size_t)nseg, s);
@@ -1402,7 +1471,8 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
         AdjTables A{};
         A.lam_src = h->T.lam;
         A.dlam_in = h->dlamA;
-        if ((st = adj_classes(h, A, ADJ_B_FIXED, 1, 0, seed, s))) return st;
+        A.seed = h->seed_dev;
+        if ((st = adj_classes(h, A, ADJ_B_FIXED, 1, 0, 0.f, s))) return st;
     }
     // lambda_bar = lambda + alpha S(M): dlambda = dlambda_bar, d_alpha += dlambda_bar S, dM = dS
     HIP_TRY(launch_flush_adj(h->T.evar, h->S, h->alpha, h->dlamA, h->dalpha, h->g, h->edge_slots, s));
@@ -1416,10 +1486,11 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     }
     // checkpoint segments: when the device holds a stored run of K iterations, each segment is
     // recomputed into the stored-trajectory arrays and reversed like a stored trajectory (no pass
-    // replayed); otherwise the pass inputs are recomputed and each pass is replayed for its adjoint
+    // replayed); otherwise the pass inputs are recomputed and each pass is replayed for its adjoint.
+    // Checkpoints are verified against the fingerprints taken when they were saved: when loaded, and
+    // at the end of each recomputed segment (the recomputation must reproduce the next checkpoint).
     float *own_F = h->T.F, *own_B = h->T.B;
     uint16_t *own_Fp = h->T.Fpar, *own_Bc = h->T.Bch;
-    const bool seg_store = !stored && !h->adj_replay && nseg > 0 && stored_fits(h, K) && stored_alloc(h, K) == DD_OK;
     for (int seg = stored ? -1 : nseg - 1; seg >= 0; --seg) {
         const int t0 = seg * K, t1 = std::min(T, t0 + K), np = 2 * (t1 - t0);
         if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)seg, s))) return st;
@@ -1442,7 +1513,7 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
         // and the argmin codes of both: the last pass's reverse sweeps read the F its forward pass left)
         for (int q = 0; q < np; ++q) {
             if ((st = save_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
-            if ((st = q >= np - 2 ? run_pass_rec(h, q % 2, s) : dd_run_pass(h, q % 2, stream))) return st;
+            if ((st = q >= np - 2 ? run_pass_rec(h, q % 2, s) : dd_run_pass(h, q % 2, s))) return st;
         }
         if ((st = verify_state(h, h->T.lam, h->T.M, (size_t)seg + 1, s))) return st;
         for (int q = np - 1; q >= 0; --q) {
@@ -1459,6 +1530,33 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
             std::swap(dm, dm2);
         }
     }
+    if (dl != h->dlamA || dm != h->dMA) return fail(DD_E_STATE, "internal: pass adjoints out of step");
+    return DD_OK;
+}
+
+int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, float *d_lam0, float *d_M0,
+             void *stream) {
+    if (!h) return fail(DD_E_ARG, "NULL instance");
+    if (h->fwd_T < 0 || h->fwd_version != h->version)
+        return fail(DD_E_STATE, "the backward sweep needs the state left by an unrolled forward");
+    if (d_c && h->fwd_from_state)
+        return fail(DD_E_ARG, "d_c needs an unrolled forward from the reset state (lambda = c/|J_i|)");
+    hipStream_t s = (hipStream_t)stream;
+    const bool stored = h->fwd_stored;
+    const int T = h->fwd_T, K = stored ? 1 : h->fwd_K, nseg = (T + K - 1) / K;
+    const float seed = (float)dlb;
+    int st;
+    // the buffers of the launch sequence, allocated beforehand
+    if (!h->seed_dev && (st = h->alloc(&h->seed_dev, 1))) return st;
+    const bool seg_store = !stored && !h->adj_replay && nseg > 0 && stored_fits(h, K) && stored_alloc(h, K) == DD_OK;
+    if (!stored && !seg_store && (st = reserve_states(h, h->seg_lam, h->seg_M, 2 * (size_t)K))) return st;
+    if (seg_store && (st = reserve_states(h, h->tr_lam, h->tr_M, 2 * (size_t)K + 1))) return st;
+    HIP_TRY(launch_fill(h->seed_dev, seed, 1, s));
+    if (!stored) HIP_TRY(launch_fill((float *)h->ck_flag, 0.f, 1, s));
+    st = replayed(h, {3, T, K, stored, seg_store}, s,
+                  [&](hipStream_t q) { return backward_core(h, T, K, stored, seg_store, q); });
+    if (st) return st;
+    float *dl = h->dlamA, *dm = h->dMA;
     // lambda_0 = c / |J_i|
     if (d_c) HIP_TRY(launch_dc(h->var_ptr, h->var_slots, dl, h->cdev, seed, d_c, (int)h->n, s));
     if (d_lam0) HIP_TRY(launch_gather(h->canon2slot, dl, d_lam0, h->E, nullptr, s));

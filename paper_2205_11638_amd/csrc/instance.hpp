@@ -112,12 +112,27 @@ struct dd_instance {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t graph_one = nullptr, graph_chunk = nullptr;
     bool use_graphs = true;
+    // launch sequences of the unrolled forward and backward, replayed from graphs captured the first
+    // time their key is seen, with the host-side effects the sequence had when it was captured
+    struct SeqGraph {
+        std::vector<int64_t> key;
+        hipGraphExec_t exec;
+        int64_t dversion;
+        bool en_lam_valid, b_valid, f_valid;
+        float *F, *B, *lam, *M;  // table pointers the sequence leaves
+        uint16_t *Fpar, *Bch;
+    };
+    std::vector<SeqGraph> seq_graphs;
+    bool capturing = false;   // a sequence is being captured: allocation is an internal error
+    int64_t alloc_epoch = 0;  // counts allocations (a captured sequence keeps the buffers it saw)
+    float *seed_dev = nullptr;  // [1] adjoint of the lower bound in the captured backward
     int adj_dense = 0;  // reverse sweeps of one-wave diagrams route node by node (check of that path)
     bool adj_replay = false;  // checkpointed backward: replay passes instead of storing segments
 
     ~dd_instance() {
         if (graph_one) (void)hipGraphExecDestroy(graph_one);
         if (graph_chunk) (void)hipGraphExecDestroy(graph_chunk);
+        for (SeqGraph &g : seq_graphs) (void)hipGraphExecDestroy(g.exec);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : join) (void)hipEventDestroy(e);
         if (fork) (void)hipEventDestroy(fork);
@@ -130,6 +145,7 @@ struct dd_instance {
     int alloc(T_ **p, size_t count) {
         void *q = nullptr;
         size_t bytes = std::max<size_t>(count, 1) * sizeof(T_);
+        if (capturing) return ddi::fail(DD_E_HIP, "internal: device allocation inside a captured launch sequence");
         if (max_device_bytes > 0 && device_bytes + (int64_t)bytes > max_device_bytes)
             return ddi::fail(DD_E_OOM,
                              "allocating %zu bytes would exceed the instance's device-memory cap "
@@ -139,6 +155,7 @@ struct dd_instance {
         if (e != hipSuccess) return ddi::fail(DD_E_OOM, "hipMalloc(%zu bytes): %s", bytes, hipGetErrorString(e));
         allocs.push_back(q);
         device_bytes += (int64_t)bytes;
+        ++alloc_epoch;
         *p = (T_ *)q;
         return DD_OK;
     }
@@ -177,7 +194,7 @@ int pass_launches(dd_instance *h, int dir, hipStream_t s);
 // The smoothed-subproblem sweeps of every class (soft-min costs into Bs, a node array of at least
 // node_slots + 64 floats whose prior contents are never read), E_out / p_out as dd_smoothed.
 int smoothed_sweeps(dd_instance *h, float *Bs, float tau, int flushed, float *E_out, float *p_out, hipStream_t s);
-// Forget captured iteration graphs (after a change of launch shapes).
+// Forget captured iteration and sequence graphs (after a change of launch shapes).
 void drop_graphs(dd_instance *h);
 
 }  // namespace ddi

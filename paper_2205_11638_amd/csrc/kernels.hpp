@@ -154,6 +154,8 @@ struct AdjTables {
     float *rec_val;         // [2 * slots] the adjoint values that go with them
     const int32_t *mrec;    // the replayed (or stored) pass's argmin records (update sweeps of one-wave
     const float *mdiff;     // diagrams), layout as in DevTables
+    const float *seed;      // when set, the adjoint of B(root) is read here instead of the seed argument
+                            // (a launch replayed from a graph then takes the value of the moment)
 };
 
 enum AdjSweep { ADJ_F_UPDATE = 0, ADJ_F_FIXED = 1, ADJ_B_UPDATE = 2, ADJ_B_FIXED = 3 };

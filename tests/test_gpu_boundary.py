@@ -106,3 +106,42 @@ def test_sizes():
     p, _, _ = _gm()
     inst, _, _ = make_instance(p)
     assert inst.num_edges() == p.nnz == inst.E
+
+
+@pytest.mark.parametrize("case,T,K,replay", [("gm", 6, 2, False), ("gm", 5, 2, True), ("gm", 4, -1, False),
+                                             ("knapsack", 3, 2, False), ("knapsack", 3, -1, False)])
+def test_captured_sequences_equal_eager_launches(case, T, K, replay):
+    """The unrolled forward and the backward sweep run as launch sequences captured into graphs the
+    first time (T, K, mode) is seen and replayed afterwards; an instance created without graphs
+    launches every kernel itself.  Replays take the seed of the moment (it is read from device
+    memory), so over several rounds with different seeds, with eager work in between, bound,
+    gradients and the state left behind agree bit for bit; a checkpoint changed before a replayed
+    backward is still caught."""
+    import paper_2205_11638_amd as dd
+    if case == "gm":
+        p, om, ah = _gm()
+    else:
+        w = synth.workload("knapsack", small=True)
+        p, om, ah = w["problem"], w["omega"], w["alpha_hat"]
+    say(f"captured vs eager {case} T={T} K={K} replay={replay}")
+    g, _, _ = make_instance(p, om, ah, adj_replay=replay)
+    e, _, _ = make_instance(p, om, ah, adj_replay=replay, graphs=False)
+    for rnd, seed in enumerate((1.0, -2.5, 0.75)):
+        lbg, lbe = g.forward_unrolled(T, K), e.forward_unrolled(T, K)
+        assert lbg == lbe, rnd
+        gg = [host(t) for t in g.backward(seed)]
+        ge = [host(t) for t in e.backward(seed)]
+        for a, b, name in zip(gg, ge, ("d_omega", "d_alpha", "d_c")):
+            assert np.isfinite(a).all()
+            np.testing.assert_array_equal(a, b, err_msg=f"{name} round {rnd}")
+        for a, b in zip(g.get_state(), e.get_state()):
+            np.testing.assert_array_equal(host(a), host(b))
+        g.run(1)  # eager work between the replays
+        e.run(1)
+        assert g.lower_bound()[0] == e.lower_bound()[0]
+    if K > 0:
+        g.forward_unrolled(T, K)
+        g.corrupt_checkpoint(1)
+        with pytest.raises(dd.DDError) as err:
+            g.backward(1.0)
+        assert err.value.code == dd.binding.DD_E_CHECKPOINT
