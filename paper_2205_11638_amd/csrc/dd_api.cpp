@@ -489,11 +489,11 @@ int deferred_sum(dd_instance *h, const float *M, hipStream_t s) {
     });
 }
 
-int deferred_from(dd_instance *h, const float *M, hipStream_t s) {
+int deferred_from(dd_instance *h, const float *M, hipStream_t s, float *Se) {
     int st = deferred_sum(h, M, s);
     if (st) return st;
-    return recorded(h, "k_edge_alpha_s", 16.0 * (double)h->edge_slots, s, [&] {
-        return launch_edge_alpha_s(h->T.evar, h->alpha, h->S, h->aS, h->edge_slots, s);
+    return recorded(h, "k_edge_alpha_s", (Se ? 20.0 : 16.0) * (double)h->edge_slots, s, [&] {
+        return launch_edge_alpha_s(h->T.evar, h->alpha, h->S, h->aS, Se, h->edge_slots, s);
     });
 }
 
@@ -1051,11 +1051,13 @@ int recording(dd_instance *h, Fn &&fn, int32_t *mrec = nullptr, float *mdiff = n
     return st;
 }
 
-// An update pass that records its argmins (as dd_run_pass otherwise).
-int run_pass_rec(dd_instance *h, int dir, hipStream_t s, int32_t *mrec = nullptr, float *mdiff = nullptr) {
+// An update pass that records its argmins (as dd_run_pass otherwise); with Se, it keeps the S per
+// edge of its input M there.
+int run_pass_rec(dd_instance *h, int dir, hipStream_t s, int32_t *mrec = nullptr, float *mdiff = nullptr,
+                 float *Se = nullptr) {
     h->en_lam_valid = false;
     h->version++;
-    int st = deferred(h, s);
+    int st = deferred_from(h, h->T.M, s, Se);
     if (st == DD_OK)
         st = recording(h, [&] { return all_classes(h, dir == 0, dir == 0 ? (int)FWD_UPDATE_REC : (int)BWD_UPDATE_REC, s); },
                        mrec, mdiff);
@@ -1069,19 +1071,24 @@ int run_pass_rec(dd_instance *h, int dir, hipStream_t s, int32_t *mrec = nullptr
 // With lam_src/M_src (slot order): the instance already holds this pass's outputs -- its
 // multipliers, M and both node sides exactly as the pass left them (the side it read, computed
 // from the input multipliers, and the side it rebuilt) -- and lam_src/M_src are its inputs and
-// mrec_src/mdiff_src its argmin records; the fixed-side sweep and the replay are then skipped.
-// Otherwise the replay records them.
+// mrec_src/mdiff_src its argmin records (and Se_src, when kept, the S per edge of M_src); the
+// fixed-side sweep and the replay are then skipped.  Otherwise the replay records them.
 int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out, float *dlam_in, float *dM_in,
              hipStream_t s, const float *lam_src = nullptr, const float *M_src = nullptr,
-             const int32_t *mrec_src = nullptr, const float *mdiff_src = nullptr) {
+             const int32_t *mrec_src = nullptr, const float *mdiff_src = nullptr, const float *Se_src = nullptr) {
     const bool fresh = lam_src != nullptr;
     if (fresh && (!mrec_src || !mdiff_src)) return fail(DD_E_ARG, "internal: a pass adjoint needs the pass's records");
-    // S of the pass-input M (per edge for the update sweeps) and, for the replayed update pass, alpha*S;
+    // S of the pass-input M per edge for the update sweeps and, for the replayed update pass, alpha*S;
     // the reverse sweeps read no alpha*S, and every later reader of it recomputes it from its state
-    int st = fresh ? deferred_sum(h, M_src, s) : deferred_from(h, h->T.M, s);
-    if (st) return st;
-    st = recorded(h, "k_edge_S", 12.0 * (double)h->edge_slots, s,
-                  [&] { return launch_edge_S(h->T.evar, h->S, h->Se, h->edge_slots, s); });
+    int st = DD_OK;
+    if (!fresh) {
+        st = deferred_from(h, h->T.M, s, h->Se);
+    } else if (!Se_src) {
+        st = deferred_sum(h, M_src, s);
+        if (st == DD_OK)
+            st = recorded(h, "k_edge_S", 12.0 * (double)h->edge_slots, s,
+                          [&] { return launch_edge_S(h->T.evar, h->S, h->Se, h->edge_slots, s); });
+    }
     if (st) return st;
     // the pass-input multipliers: kept by the caller, or copied before the replay overwrites them
     if (!fresh && (st = copy_slots(h, h->lam_in, h->T.lam, s))) return st;
@@ -1091,7 +1098,7 @@ int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out
     A.mdiff = fresh ? mdiff_src : h->mdiff;
     A.dlam_out = dlam_out;
     A.dM_out = dM_out;
-    A.Se = h->Se;
+    A.Se = Se_src ? Se_src : h->Se;
     A.dlam_in = dlam_in;
     A.g = h->g;
     A.dalpha = h->dalpha;
@@ -1266,6 +1273,7 @@ size_t stored_need(const dd_instance *h, int n) {
     if ((int)h->trF.size() < n) need += ((size_t)n - h->trF.size()) * bytes;
     if ((int)h->trB.size() < n + 1) need += ((size_t)n + 1 - h->trB.size()) * bytes;
     if ((int)h->tr_mrec.size() < 2 * n) need += ((size_t)2 * n - h->tr_mrec.size()) * rec_bytes;
+    if ((int)h->tr_Se.size() < 2 * n) need += ((size_t)2 * n - h->tr_Se.size()) * 4 * (size_t)h->edge_slots;
     if ((int)h->tr_lam.size() < 2 * n + 1) need += ((size_t)2 * n + 1 - h->tr_lam.size()) * 8 * (size_t)h->edge_slots;
     return need;
 }
@@ -1305,6 +1313,11 @@ int stored_alloc(dd_instance *h, int n) {
         h->tr_mrec.push_back(p);
         h->tr_mdiff.push_back(q);
     }
+    while ((int)h->tr_Se.size() < 2 * n) {
+        float *p = nullptr;
+        if ((st = h->alloc(&p, (size_t)h->edge_slots))) return st;
+        h->tr_Se.push_back(p);
+    }
     return DD_OK;
 }
 
@@ -1317,11 +1330,11 @@ int stored_passes(dd_instance *h, int n, hipStream_t s) {
     for (int t = 0; t < n && st == DD_OK; ++t) {
         use_F(h, h->trF[t], h->trFp[t]);
         use_B(h, h->trB[t], h->trBc[t]);
-        if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t])) ||
+        if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t], h->tr_Se[2 * t])) ||
             (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)))
             break;
         use_B(h, h->trB[t + 1], h->trBc[t + 1]);
-        if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1]))) break;
+        if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1], h->tr_Se[2 * t + 1]))) break;
         st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s);
     }
     return st;
@@ -1340,7 +1353,7 @@ int stored_reverse(dd_instance *h, int n, float *&dl, float *&dm, float *&dl2, f
         h->T.lam = h->tr_lam[2 * t + 2];
         h->T.M = h->tr_M[2 * t + 2];
         if ((st = pass_vjp(h, 1, dl, dm, dl2, dm2, s, h->tr_lam[2 * t + 1], h->tr_M[2 * t + 1],
-                           h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1])))
+                           h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1], h->tr_Se[2 * t + 1])))
             break;
         std::swap(dl, dl2);
         std::swap(dm, dm2);
@@ -1348,7 +1361,7 @@ int stored_reverse(dd_instance *h, int n, float *&dl, float *&dm, float *&dl2, f
         h->T.lam = h->tr_lam[2 * t + 1];
         h->T.M = h->tr_M[2 * t + 1];
         if ((st = pass_vjp(h, 0, dl, dm, dl2, dm2, s, h->tr_lam[2 * t], h->tr_M[2 * t], h->tr_mrec[2 * t],
-                           h->tr_mdiff[2 * t])))
+                           h->tr_mdiff[2 * t], h->tr_Se[2 * t])))
             break;
         std::swap(dl, dl2);
         std::swap(dm, dm2);
@@ -1513,14 +1526,18 @@ int backward_core(dd_instance *h, int T, int K, bool stored, bool seg_store, hip
         // and the argmin codes of both: the last pass's reverse sweeps read the F its forward pass left)
         for (int q = 0; q < np; ++q) {
             if ((st = save_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;
-            if ((st = q >= np - 2 ? run_pass_rec(h, q % 2, s) : dd_run_pass(h, q % 2, s))) return st;
+            // (the last also keeps its input's S per edge for its adjoint)
+            if ((st = q >= np - 2 ? run_pass_rec(h, q % 2, s, nullptr, nullptr, q == np - 1 ? h->Se : nullptr)
+                                  : dd_run_pass(h, q % 2, s)))
+                return st;
         }
         if ((st = verify_state(h, h->T.lam, h->T.M, (size_t)seg + 1, s))) return st;
         for (int q = np - 1; q >= 0; --q) {
             if (q == np - 1) {
                 // the recomputation just ran this pass: its outputs and both node sides are in place
                 // (a segment ends with a backward pass, whose fixed side is the F its forward pass left)
-                if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s, h->seg_lam[q], h->seg_M[q], h->mrec, h->mdiff)))
+                if ((st = pass_vjp(h, q % 2, dl, dm, dl2, dm2, s, h->seg_lam[q], h->seg_M[q], h->mrec, h->mdiff,
+                                   h->Se)))
                     return st;
             } else {
                 if ((st = load_state(h, h->seg_lam, h->seg_M, (size_t)q, s))) return st;

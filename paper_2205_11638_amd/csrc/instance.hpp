@@ -90,6 +90,7 @@ struct dd_instance {
     std::vector<float *> tr_lam, tr_M;  // state before pass q = 0 .. 2T (the last one: the final state)
     std::vector<int32_t *> tr_mrec;     // argmin records of pass q = 0 .. 2T-1
     std::vector<float *> tr_mdiff;
+    std::vector<float *> tr_Se;         // S per edge slot of pass q's input M (q = 0 .. 2T-1)
     float *F0 = nullptr, *B0 = nullptr; // the instance's own node-cost arrays
     // argmin codes of the node costs (DevTables::Fpar / Bch): the instance's own, paired with F0 / B0,
     // and those of the stored trajectory's arrays (trFp[t] with trF[t], trBc[t] with trB[t])
@@ -182,9 +183,10 @@ inline int recorded(dd_instance *h, const char *name, double bytes, hipStream_t 
     return DD_OK;
 }
 
-// S and alpha*S of the current M (start of a pass), or of a given M (slot order).
+// S and alpha*S of the current M (start of a pass), or of a given M (slot order); with Se, S per
+// edge slot too.
 int deferred(dd_instance *h, hipStream_t s);
-int deferred_from(dd_instance *h, const float *M, hipStream_t s);
+int deferred_from(dd_instance *h, const float *M, hipStream_t s, float *Se = nullptr);
 // One sweep (pass-kernel mode) over every class, classes concurrently on side streams.
 int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s);
 // B at the current multipliers, stored (what a forward pass reads).

@@ -943,11 +943,14 @@ __global__ void k_deferred_sum(const int32_t *__restrict__ var_ptr, const int32_
 
 // aS[slot] = alpha[slot] * S[var(slot)] over all edge slots (padding slots have var -1).
 __global__ void k_edge_alpha_s(const int32_t *__restrict__ evar, const float *__restrict__ alpha,
-                               const float *__restrict__ S, float *__restrict__ aS, int64_t slots) {
+                               const float *__restrict__ S, float *__restrict__ aS, float *__restrict__ Se,
+                               int64_t slots) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= slots) return;
     const int v = evar[e];
-    aS[e] = v >= 0 ? alpha[e] * S[v] : 0.f;
+    const float Sv = v >= 0 ? S[v] : 0.f;
+    aS[e] = v >= 0 ? alpha[e] * Sv : 0.f;
+    if (Se) Se[e] = Sv;
 }
 
 __global__ void k_init_lambda(const int32_t *__restrict__ canon2slot, const int32_t *__restrict__ evar,
@@ -1191,10 +1194,10 @@ hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots,
     return hipGetLastError();
 }
 
-hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, int64_t slots,
-                               hipStream_t s) {
+hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, float *Se,
+                               int64_t slots, hipStream_t s) {
     if (slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_alpha_s, dim3(blocks_for(slots, 256)), dim3(256), 0, s, evar, alpha, S, aS, slots);
+    hipLaunchKernelGGL(k_edge_alpha_s, dim3(blocks_for(slots, 256)), dim3(256), 0, s, evar, alpha, S, aS, Se, slots);
     return hipGetLastError();
 }
 

@@ -199,9 +199,10 @@ bool class_supported(int P, int RMAX);
 // 4, 8 or 16), strided partial sums in list order, then a fixed butterfly (same bits on every call).
 hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots, const float *M, float *S, int n,
                                int team, hipStream_t s);
-// aS[slot] = alpha[slot] * S[evar[slot]] for every edge slot (0 on padding).
-hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, int64_t slots,
-                               hipStream_t s);
+// aS[slot] = alpha[slot] * S[evar[slot]] for every edge slot (0 on padding); with Se, also
+// Se[slot] = S[evar[slot]] (the S per edge that the reverse sweeps read).
+hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, float *Se,
+                               int64_t slots, hipStream_t s);
 // lambda[slot] = c_i / |J_i|, M[slot] = 0 for every canonical edge.
 hipError_t launch_init_lambda(const int32_t *canon2slot, const int32_t *evar, const int32_t *var_ptr, const float *c,
                               float *lam, float *M, int64_t E, hipStream_t s);
