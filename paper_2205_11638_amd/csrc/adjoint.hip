@@ -978,31 +978,16 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
     }
 }
 
-// dS_i = sum over the edges of variable i of g (= dlambda' alpha), then dM_in[slot] = dS_i
-// (first line of Alg. 2, with alpha_ik per the derivative of the lambda update).
-// TS lanes per variable, summed as S is in the forward direction (strided partial sums, then a fixed
-// butterfly), the total written to every edge of the variable.
-template <int TS>
-__global__ void k_adj_deferred(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_slots,
-                               const float *__restrict__ g, float *__restrict__ dM, int n) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int i = (int)(t / TS), u = (int)(t % TS);
-    const int a = i < n ? var_ptr[i] : 0, b = i < n ? var_ptr[i + 1] : 0;
-    float s = strided_gather_sum<TS>(var_slots, g, a, b, u);
-    for (int w = TS / 2; w > 0; w >>= 1) s += __shfl_xor(s, w, TS);  // every lane takes part
-    for (int q = a + u; q < b; q += TS) dM[var_slots[q]] = s;
-}
-
 __global__ void k_edge_S(const int32_t *__restrict__ evar, const float *__restrict__ S, float *__restrict__ Se,
                          int64_t slots) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (e >= slots) return;
     const int v = evar[e];
     Se[e] = v >= 0 ? S[v] : 0.f;
 }
 
 // Adjoint of lambda_bar = lambda + alpha * S: dlambda stays, d_alpha += dlambda_bar * S_i,
-// g = dlambda_bar * alpha (dS then dM as in k_adj_deferred).
+// g = dlambda_bar * alpha (then dS per variable and dM per edge, as after a pass adjoint).
 __global__ void k_flush_adj(const int32_t *__restrict__ evar, const float *__restrict__ S,
                             const float *__restrict__ alpha, const float *__restrict__ dlam, float *__restrict__ dalpha,
                             float *__restrict__ g, int64_t slots) {
@@ -1507,24 +1492,9 @@ hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch 
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots, const float *g, float *dM, int n,
-                               int team, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const unsigned nb = blocks_for((int64_t)n * team, 256);
-    switch (team) {
-        case 1: hipLaunchKernelGGL(k_adj_deferred<1>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
-        case 2: hipLaunchKernelGGL(k_adj_deferred<2>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
-        case 4: hipLaunchKernelGGL(k_adj_deferred<4>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
-        case 8: hipLaunchKernelGGL(k_adj_deferred<8>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
-        case 16: hipLaunchKernelGGL(k_adj_deferred<16>, dim3(nb), dim3(256), 0, s, var_ptr, var_slots, g, dM, n); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
 hipError_t launch_edge_S(const int32_t *evar, const float *S, float *Se, int64_t slots, hipStream_t s) {
     if (slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_S, dim3(blocks_for(slots, 256)), dim3(256), 0, s, evar, S, Se, slots);
+    hipLaunchKernelGGL(k_edge_S, dim3(xcd_grid(blocks_for(slots, 256))), dim3(256), 0, s, evar, S, Se, slots);
     return hipGetLastError();
 }
 

@@ -96,7 +96,17 @@ int dd_batch_create(const dd_problem *probs, int32_t k, const dd_options *opt, v
         }
     }
     dd_problem u{(int32_t)n, c.data(), (int32_t)m, row_ptr.data(), col.data(), coef.data(), sense.data(), rhs.data()};
-    int st = dd_create(&u, opt, stream, &b->h);
+    // locality: the programs in eight buckets of about equal edge count (by the middle of each
+    // program's edge range), whose rows keep to consecutive tiles.  The per-slot kernels hand each of
+    // the chip's 8 L2 slices one eighth of the slot range, so each slice mostly gathers the S of its
+    // own bucket's programs.
+    std::vector<int32_t> group((size_t)m);
+    for (int q = 0; q < k; ++q) {
+        const int64_t mid2 = b->edge_off[q] + b->edge_off[q + 1];  // twice the middle
+        const int g = E > 0 ? (int)std::min<int64_t>(7, (8 * mid2) / (2 * E)) : 0;
+        for (int64_t j = b->row_off[q]; j < b->row_off[q + 1]; ++j) group[(size_t)j] = g;
+    }
+    int st = create_grouped(&u, opt, stream, group.data(), &b->h);
     if (st) {
         delete b;
         return st;

@@ -163,7 +163,7 @@ int upload(dd_instance *h, T_ **dst, const std::vector<T_> &src, hipStream_t s) 
 }
 
 int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowBdd> &bdds, int npl, int wpb,
-               int lds_budget, HostPlan &hp, std::vector<uint32_t> &topo) {
+               int lds_budget, const int32_t *row_group, HostPlan &hp, std::vector<uint32_t> &topo) {
     const int m = p->m;
     // class of every row
     std::vector<int> rP(m, 0), rR(m, 0);
@@ -195,9 +195,12 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
     std::vector<int> order;
     for (int j = 0; j < m; ++j)
         if (bdds[j].L > 0) order.push_back(j);
+    // within a class, rows of one locality group (a batch's programs, bucketed) stay together, so the
+    // edge slots of a group are one stretch of the slot range; then longest diagrams first
     std::sort(order.begin(), order.end(), [&](int x, int y) {
         if (rP[x] != rP[y]) return rP[x] < rP[y];
         if (rR[x] != rR[y]) return rR[x] < rR[y];
+        if (row_group && row_group[x] != row_group[y]) return row_group[x] < row_group[y];
         if (bdds[x].L != bdds[y].L) return bdds[x].L > bdds[y].L;
         if (bdds[x].max_width != bdds[y].max_width) return bdds[x].max_width > bdds[y].max_width;
         return x < y;
@@ -543,6 +546,15 @@ int dd_compile_row(const dd_problem *prob, int32_t row, int32_t *width, uint32_t
 }
 
 int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_instance **out) {
+    return ddi::create_grouped(prob, opt, stream, nullptr, out);
+}
+
+}  // extern "C"
+
+namespace ddi {
+
+int create_grouped(const dd_problem *prob, const dd_options *opt, void *stream, const int32_t *row_group,
+                   dd_instance **out) {
     if (!out) return fail(DD_E_ARG, "out is NULL");
     *out = nullptr;
     hipStream_t s = (hipStream_t)stream;
@@ -596,7 +608,7 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     }
     HostPlan hp;
     std::vector<uint32_t> topo;
-    st = build_plan(prob, sr, bdds, npl, wpb, lds_budget, hp, topo);
+    st = build_plan(prob, sr, bdds, npl, wpb, lds_budget, row_group, hp, topo);
     if (st) return st;
 
     int device = 0;
@@ -741,6 +753,10 @@ int dd_create(const dd_problem *prob, const dd_options *opt, void *stream, dd_in
     *out = h;
     return DD_OK;
 }
+
+}  // namespace ddi
+
+extern "C" {
 
 int dd_destroy(dd_instance *h) {
     delete h;
@@ -1051,6 +1067,19 @@ int recording(dd_instance *h, Fn &&fn, int32_t *mrec = nullptr, float *mdiff = n
     return st;
 }
 
+// First line of Alg. 2 with the multiplier update's alpha: dS_i = sum of g (= dlambda' alpha) over the
+// edges of variable i, summed as S is in the forward direction (the deferred-sum kernel on g, into the
+// per-variable scratch), then dM[slot] = dS_i for every edge slot of i (0 on padding) in slot order,
+// which writes coalesced where writing each variable's total to its own slots would scatter.
+int adj_deferred(dd_instance *h, float *dM, hipStream_t s) {
+    int st = recorded(h, "k_deferred_sum", 8.0 * (double)h->E + 12.0 * (double)h->n, s, [&] {
+        return launch_deferred_sum(h->var_ptr, h->var_slots, h->g, h->scratch_n, (int)h->n, h->var_team, s);
+    });
+    if (st) return st;
+    return recorded(h, "k_edge_S", 12.0 * (double)h->edge_slots, s,
+                    [&] { return launch_edge_S(h->T.evar, h->scratch_n, dM, h->edge_slots, s); });
+}
+
 // An update pass that records its argmins (as dd_run_pass otherwise); with Se, it keeps the S per
 // edge of its input M there.
 int run_pass_rec(dd_instance *h, int dir, hipStream_t s, int32_t *mrec = nullptr, float *mdiff = nullptr,
@@ -1118,9 +1147,7 @@ int pass_vjp(dd_instance *h, int dir, const float *dlam_out, const float *dM_out
         if ((st = adj_classes(h, A, ADJ_B_UPDATE, 0, 0, 0.f, s))) return st;
         if ((st = adj_classes(h, A, ADJ_F_FIXED, 0, 1, 0.f, s))) return st;
     }
-    return recorded(h, "k_adj_deferred", 12.0 * (double)h->E + 8.0 * (double)h->n, s, [&] {
-        return launch_adj_deferred(h->var_ptr, h->var_slots, h->g, dM_in, (int)h->n, h->var_team, s);
-    });
+    return adj_deferred(h, dM_in, s);
 }
 
 int save_state(dd_instance *h, std::vector<float *> &L, std::vector<float *> &Mv, size_t i, hipStream_t s) {
@@ -1489,7 +1516,7 @@ int backward_core(dd_instance *h, int T, int K, bool stored, bool seg_store, hip
     }
     // lambda_bar = lambda + alpha S(M): dlambda = dlambda_bar, d_alpha += dlambda_bar S, dM = dS
     HIP_TRY(launch_flush_adj(h->T.evar, h->S, h->alpha, h->dlamA, h->dalpha, h->g, h->edge_slots, s));
-    HIP_TRY(launch_adj_deferred(h->var_ptr, h->var_slots, h->g, h->dMA, (int)h->n, h->var_team, s));
+    if ((st = adj_deferred(h, h->dMA, s))) return st;
     float *dl = h->dlamA, *dm = h->dMA, *dl2 = h->dlamB, *dm2 = h->dMB;
     if (stored) {
         st = stored_reverse(h, T, dl, dm, dl2, dm2, s);

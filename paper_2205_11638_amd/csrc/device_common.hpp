@@ -238,6 +238,12 @@ __device__ __forceinline__ void lds_umin64(uint64_t *a, uint64_t v) {
     __hip_atomic_fetch_min(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
 }
 typedef uint64_t u64x2 __attribute__((ext_vector_type(2)));
+// Workgroups go to the chip's 8 XCDs round-robin (workgroup b to XCD b mod 8), each XCD with an L2
+// of its own.  xcd_block gives the workgroups on XCD x the x-th contiguous eighth of the index range
+// (a bijection on [0, nb) for nb a multiple of 8), so gathers from items that are near each other in
+// that range share one L2.  Launches pad the grid to a multiple of 8; the items past the range exit.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb) { return (b & 7) * (nb >> 3) + (b >> 3); }
+inline unsigned xcd_grid(int64_t blocks) { return (unsigned)((blocks + 7) & ~(int64_t)7); }
 // 32 * lane (a lane's four 64-bit keys of a 256-node group), made anew like lane16
 __device__ __forceinline__ int lane32(int lane) {
     int v = lane * 32;
@@ -303,10 +309,11 @@ __device__ __forceinline__ void record_argmins_team(const DevTables &T, int ebas
 template <int TS>
 __device__ __forceinline__ float strided_gather_sum(const int32_t *__restrict__ idx, const float *__restrict__ x,
                                                     int a, int b, int u) {
+    auto ix = [&](int q) { return idx[q]; };
     float s = 0.f;
     int q = a + u;
     for (; q + 3 * TS < b; q += 4 * TS) {
-        const int e0 = idx[q], e1 = idx[q + TS], e2 = idx[q + 2 * TS], e3 = idx[q + 3 * TS];
+        const int e0 = ix(q), e1 = ix(q + TS), e2 = ix(q + 2 * TS), e3 = ix(q + 3 * TS);
         const float x0 = x[e0], x1 = x[e1], x2 = x[e2], x3 = x[e3];
         s += x0;
         s += x1;
@@ -315,7 +322,7 @@ __device__ __forceinline__ float strided_gather_sum(const int32_t *__restrict__ 
     }
     if (q < b) {  // at most three left
         const bool h1 = q + TS < b, h2 = q + 2 * TS < b;
-        const int e0 = idx[q], e1 = h1 ? idx[q + TS] : 0, e2 = h2 ? idx[q + 2 * TS] : 0;
+        const int e0 = ix(q), e1 = h1 ? ix(q + TS) : 0, e2 = h2 ? ix(q + 2 * TS) : 0;
         const float x0 = x[e0], x1 = h1 ? x[e1] : 0.f, x2 = h2 ? x[e2] : 0.f;
         s += x0;
         if (h1) s += x1;

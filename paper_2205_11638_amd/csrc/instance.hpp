@@ -196,6 +196,10 @@ int pass_launches(dd_instance *h, int dir, hipStream_t s);
 // The smoothed-subproblem sweeps of every class (soft-min costs into Bs, a node array of at least
 // node_slots + 64 floats whose prior contents are never read), E_out / p_out as dd_smoothed.
 int smoothed_sweeps(dd_instance *h, float *Bs, float tau, int flushed, float *E_out, float *p_out, hipStream_t s);
+// dd_create with a locality group per row (row_group[j] for row j, or nullptr): within a kernel
+// class the rows of one group get consecutive tiles, so their edge slots form one stretch.
+int create_grouped(const dd_problem *prob, const dd_options *opt, void *stream, const int32_t *row_group,
+                   dd_instance **out);
 // Forget captured iteration and sequence graphs (after a change of launch shapes).
 void drop_graphs(dd_instance *h);
 

@@ -929,7 +929,9 @@ hipError_t bwd_dispatch(const DevTables &t, const ClassLaunch &c, int mode, hipS
 // S_i = sum of M over the edges of variable i.  TS lanes per variable (a power of two, fixed for an
 // instance): lane u adds edges u, u + TS, ... of the variable in CSR order, then a fixed butterfly
 // adds the TS partial sums, so S has the same bits on every call (TS = 1: one serial sum).  Teams
-// keep the chain of dependent loads short for variables in many rows.
+// keep the chain of dependent loads short for variables in many rows.  Blocks take the variables in
+// plain order: the work per variable is skewed, and ranges per XCD (by count or by edges) piled an
+// instance's long variables onto a few XCDs.
 template <int TS>
 __global__ void k_deferred_sum(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_slots,
                                const float *__restrict__ M, float *__restrict__ S, int n) {
@@ -945,7 +947,7 @@ __global__ void k_deferred_sum(const int32_t *__restrict__ var_ptr, const int32_
 __global__ void k_edge_alpha_s(const int32_t *__restrict__ evar, const float *__restrict__ alpha,
                                const float *__restrict__ S, float *__restrict__ aS, float *__restrict__ Se,
                                int64_t slots) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (e >= slots) return;
     const int v = evar[e];
     const float Sv = v >= 0 ? S[v] : 0.f;
@@ -1197,7 +1199,8 @@ hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots,
 hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, float *Se,
                                int64_t slots, hipStream_t s) {
     if (slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_alpha_s, dim3(blocks_for(slots, 256)), dim3(256), 0, s, evar, alpha, S, aS, Se, slots);
+    hipLaunchKernelGGL(k_edge_alpha_s, dim3(xcd_grid(blocks_for(slots, 256))), dim3(256), 0, s, evar, alpha, S, aS, Se,
+                       slots);
     return hipGetLastError();
 }
 

@@ -167,8 +167,6 @@ hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch 
                       float seed, int dense, hipStream_t s);
 // Se[slot] = S[evar[slot]] (0 on padding)
 hipError_t launch_edge_S(const int32_t *evar, const float *S, float *Se, int64_t slots, hipStream_t s);
-hipError_t launch_adj_deferred(const int32_t *var_ptr, const int32_t *var_slots, const float *g, float *dM, int n,
-                               int team, hipStream_t s);
 hipError_t launch_flush_adj(const int32_t *evar, const float *S, const float *alpha, const float *dlam, float *dalpha,
                             float *g, int64_t slots, hipStream_t s);
 hipError_t launch_dc(const int32_t *var_ptr, const int32_t *var_slots, const float *dlam, const float *c, float seed,
