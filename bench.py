@@ -21,20 +21,73 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def counted_traffic(kernel, workload):
-    """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
-    against a plain copy), or None when a kernel source changed since the counters were taken."""
+TRAFFIC_JSON = os.path.join(HERE, "profiles", "traffic_knapsack_2M_vars.json")
+
+
+def kernel_sources_sha256():
     import hashlib
-    path = os.path.join(HERE, "profiles", "traffic_knapsack_2M_vars.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
     h = hashlib.sha256()
     for f in ("kernels.hip", "adjoint.hip"):
         h.update(open(os.path.join(HERE, "paper_2205_11638_amd", "csrc", f), "rb").read())
-    if rec.get("workload") != workload or h.hexdigest() != rec.get("sources_sha256"):
+    return h.hexdigest()
+
+
+def counted_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE / WRITE_SIZE (calibrated
+    against a plain copy), or None when a kernel source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_JSON):
+        return None
+    rec = json.load(open(TRAFFIC_JSON))
+    if rec.get("workload") != workload or kernel_sources_sha256() != rec.get("sources_sha256"):
         return None
     return rec["per_launch_bytes"].get(kernel)
+
+
+def short_kernel_name(name):
+    """'void dd::(anonymous namespace)::k_bwd_w<16, 0, false>(dd::DevTables, ...)' -> 'k_bwd_w<16, 0, false>'."""
+    name = name.replace("void ", "").replace("dd::(anonymous namespace)::", "").replace("dd::", "")
+    depth = 0
+    for i, ch in enumerate(name):  # cut the argument list: the first '(' outside template brackets
+        if ch == "<":
+            depth += 1
+        elif ch == ">":
+            depth -= 1
+        elif ch == "(" and depth == 0:
+            return name[:i].strip()
+    return name.strip()
+
+
+def counter_means(csv_path, counter):
+    """Mean value per dispatch of one counter, per kernel, from a rocprofv3 --pmc CSV."""
+    import csv
+    acc = {}
+    for r in csv.DictReader(open(csv_path)):
+        if r["Counter_Name"] != counter:
+            continue
+        k = short_kernel_name(r["Kernel_Name"])
+        s, n = acc.get(k, (0.0, 0))
+        acc[k] = (s + float(r["Counter_Value"]), n + 1)
+    return {k: s / n for k, (s, n) in acc.items()}
+
+
+def write_traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_gib, workload):
+    """profiles/traffic_knapsack_2M_vars.json from two counter runs of the workload (FETCH_SIZE, then
+    WRITE_SIZE) and two of the copy probe: the copy kernel moves copy_gib GiB each way, which fixes
+    the bytes per counted unit; every kernel's mean per dispatch is scaled by it."""
+    copy_bytes = int(copy_gib * (1 << 30)) // 4 * 4
+    cf = max(v for k, v in counter_means(copy_fetch_csv, "FETCH_SIZE").items() if "copyBuffer" in k or "copy" in k)
+    cw = max(v for k, v in counter_means(copy_write_csv, "WRITE_SIZE").items() if "copyBuffer" in k or "copy" in k)
+    bf, bw = copy_bytes / cf, copy_bytes / cw
+    fetch, wr = counter_means(fetch_csv, "FETCH_SIZE"), counter_means(write_csv, "WRITE_SIZE")
+    per = {k: fetch[k] * bf + wr[k] * bw for k in fetch if k in wr and k.startswith("k_")}
+    rec = {"workload": workload, "sources_sha256": kernel_sources_sha256(),
+           "calibration": {"copy_bytes": copy_bytes, "fetch_units": cf, "write_units": cw,
+                           "bytes_per_fetch_unit": bf, "bytes_per_write_unit": bw},
+           "per_launch_bytes": dict(sorted(per.items(), key=lambda kv: -kv[1])),
+           "summary": "pass_kernels_knapsack_2M_vars.md, adjoint_kernels_knapsack_2M_vars.md"}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+    log(f"[bench] wrote {TRAFFIC_JSON}: {len(per)} kernels, {bf:.0f} B per fetch unit, {bw:.0f} B per write unit")
 
 
 def log(*a):
@@ -310,6 +363,17 @@ def round_leg(stream, reps=3):
     log(f"[bench] GM round (T={T}, K={K}): fwd+bwd {out['round_fwd_bwd_ms']:.2f} ms, plain forward "
         f"{out['plain_fwd_ms']:.2f} ms, ratio {out['ratio']:.2f}; stored trajectory "
         f"{out['round_stored_fwd_bwd_ms']:.2f} ms, ratio {out['ratio_stored']:.2f}")
+    # where the solver's part of a round goes: one unrolled forward + backward sweep, every launch
+    # bracketed by events (eager launches while profiling), per kernel in ms per round
+    inst.set_state(lam, M)
+    inst.profile_begin(8192)
+    inst.forward_unrolled_from_state(T, K)
+    inst.backward_state(1.0)
+    prof = inst.profile_end()
+    out["kernels_per_round"] = {k: {"launches": n, "ms": tot} for k, (n, tot, _) in
+                                sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    for k, v in list(out["kernels_per_round"].items())[:12]:
+        log(f"[bench] GM round kernel {k:32s} {v['launches']:5d} launches {v['ms']:7.3f} ms")
     inst.close()
     return out
 
@@ -405,7 +469,15 @@ def main():
     ap.add_argument("--no-driver", action="store_true", help="skip the test-time driver / relative-gap leg")
     ap.add_argument("--copy-probe", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device-to-device copy of GIB GiB (HBM counter calibration) and exit")
+    ap.add_argument("--write-traffic", nargs=4, default=None,
+                    metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="write the counted-traffic record from rocprofv3 --pmc CSVs of this workload and of "
+                         "--copy-probe 2, then exit (no GPU use)")
     args = ap.parse_args()
+    if args.write_traffic:
+        import synth
+        write_traffic(*args.write_traffic, 2.0, synth.workload(args.workload)["problem"].name)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on exactly one GPU: this solver has no multi-GPU path "
               "(sharding is described in the design notes only)", file=sys.stderr)

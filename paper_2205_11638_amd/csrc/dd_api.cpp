@@ -453,10 +453,14 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
     return per_class(
         h, s, [&](const ClassLaunch &cl, hipStream_t cs) { return launch_adj(h->T, A, cl, which, bar, recs, seed, h->adj_dense, cs); },
         [&](const ClassLaunch &cl) {
-            // the kernel and template arguments as the profiler prints them
+            // the kernel and template arguments as the profiler prints them (one-wave sweeps that
+            // route along recorded argmin codes run the k_adjc_ kernels)
+            const bool push = which == ADJ_F_UPDATE || which == ADJ_F_FIXED;
+            const bool coded = cl.P == 64 && !h->adj_dense && (push ? h->T.Fpar != nullptr : h->T.Bch != nullptr);
             char name[96];
             if (cl.P == 64)
-                snprintf(name, sizeof name, "%s_w<%d, %s>", nm, cl.RMAX, upd ? "true" : "false");
+                snprintf(name, sizeof name, "%s_w<%d, %s>", coded ? (push ? "k_adjc_F" : "k_adjc_B") : nm, cl.RMAX,
+                         upd ? "true" : "false");
             else
                 snprintf(name, sizeof name, "%s<%d, %d, %s>", nm, cl.P, cl.RMAX, upd ? "true" : "false");
             return std::string(name);
