@@ -999,57 +999,77 @@ __global__ void k_flush_adj(const int32_t *__restrict__ evar, const float *__res
     g[e] = d * alpha[e];
 }
 
+// The per-variable transforms below run kVarLanes lanes per variable: lane u of a team visits the
+// variable's edges u, u + kVarLanes, ... (var_canon order), and a fixed butterfly combines the lanes'
+// partial sums or maxima, so every result has the same bits on every call.  A variable in many rows
+// (a graph-matching assignment variable sits in ~42) then waits for a quarter of the dependent loads
+// of a single thread.  Every lane of a wave takes part in the butterflies; lanes past n have no edges.
+constexpr int kVarLanes = 4;
+
+__device__ __forceinline__ float team_sum_v(float s) {
+    for (int w = kVarLanes / 2; w > 0; w >>= 1) s += __shfl_xor(s, w, kVarLanes);
+    return s;
+}
+__device__ __forceinline__ float team_max_v(float s) {
+    for (int w = kVarLanes / 2; w > 0; w >>= 1) s = fmaxf(s, __shfl_xor(s, w, kVarLanes));
+    return s;
+}
+struct VarTeam {
+    int a, b, u;  // the variable's edge range in var_canon; this lane's offset in it
+};
+__device__ __forceinline__ VarTeam var_team(const int32_t *__restrict__ var_ptr, int n) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = (int)(t / kVarLanes), u = (int)(t % kVarLanes);
+    return {i < n ? var_ptr[i] : 0, i < n ? var_ptr[i + 1] : 0, u};
+}
+
 // d c_i = sum_{e of i} dlambda_e / |J_i|  (lambda_0 = c / |J|); variables in no row: seed * [c_i < 0].
 __global__ void k_dc(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_slots,
                      const float *__restrict__ dlam, const float *__restrict__ c, float seed, float *__restrict__ dc,
                      int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a = var_ptr[i], b = var_ptr[i + 1];
-    if (a == b) {
-        dc[i] = c[i] < 0.f ? seed : 0.f;
-        return;
-    }
+    const VarTeam v = var_team(var_ptr, n);
+    const int i = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kVarLanes);
     float s = 0.f;
-    for (int q = a; q < b; ++q) s += dlam[var_slots[q]];
-    dc[i] = s / (float)(b - a);
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) s += dlam[var_slots[q]];
+    s = team_sum_v(s);
+    if (i < n && v.u == 0) dc[i] = v.a == v.b ? (c[i] < 0.f ? seed : 0.f) : s / (float)(v.b - v.a);
 }
 
 // d alpha_hat_e = alpha_e (d alpha_e - sum_{k in J_i} alpha_k d alpha_k), canonical arrays.
 __global__ void k_softmax_vjp(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_canon,
                               const float *__restrict__ alpha, const float *__restrict__ dalpha, float *__restrict__ out,
                               int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a = var_ptr[i], b = var_ptr[i + 1];
+    const VarTeam v = var_team(var_ptr, n);
     float s = 0.f;
-    for (int q = a; q < b; ++q) s += alpha[var_canon[q]] * dalpha[var_canon[q]];
-    for (int q = a; q < b; ++q) {
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) s += alpha[var_canon[q]] * dalpha[var_canon[q]];
+    s = team_sum_v(s);
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) {
         const int e = var_canon[q];
         out[e] = alpha[e] * (dalpha[e] - s);
     }
 }
 
 // Output transforms of the parameter predictor (Alg. 3): omega = sigmoid(omega_hat) per edge,
-// alpha = softmax over J_i of alpha_hat, theta = theta_hat minus its mean over J_i.  One thread per
-// variable; canonical edge arrays, var_canon = CSR of each variable's canonical edges.
+// alpha = softmax over J_i of alpha_hat, theta = theta_hat minus its mean over J_i.  Canonical edge
+// arrays; var_canon = CSR of each variable's canonical edges.
 __global__ void k_param_transform(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_canon,
                                   const float *__restrict__ wh, const float *__restrict__ ah,
                                   const float *__restrict__ th, float *__restrict__ w, float *__restrict__ al,
                                   float *__restrict__ t, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a = var_ptr[i], b = var_ptr[i + 1];
+    const VarTeam v = var_team(var_ptr, n);
     float mx = -kInf, tsum = 0.f;
-    for (int q = a; q < b; ++q) {
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) {
         const int e = var_canon[q];
         mx = fmaxf(mx, ah[e]);
         if (th) tsum += th[e];
     }
+    mx = team_max_v(mx);
+    tsum = team_sum_v(tsum);
     float den = 0.f;
-    for (int q = a; q < b; ++q) den += expf(ah[var_canon[q]] - mx);
-    const float tmean = tsum / (float)(b > a ? b - a : 1);
-    for (int q = a; q < b; ++q) {
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) den += expf(ah[var_canon[q]] - mx);
+    den = team_sum_v(den);
+    const float tmean = tsum / (float)(v.b > v.a ? v.b - v.a : 1);
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) {
         const int e = var_canon[q];
         w[e] = 1.f / (1.f + expf(-wh[e]));
         al[e] = expf(ah[e] - mx) / den;
@@ -1064,17 +1084,17 @@ __global__ void k_param_transform_vjp(const int32_t *__restrict__ var_ptr, const
                                       const float *__restrict__ dw, const float *__restrict__ da,
                                       const float *__restrict__ dt, float *__restrict__ dwh,
                                       float *__restrict__ dah, float *__restrict__ dth, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a = var_ptr[i], b = var_ptr[i + 1];
+    const VarTeam v = var_team(var_ptr, n);
     float s = 0.f, tsum = 0.f;
-    for (int q = a; q < b; ++q) {
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) {
         const int e = var_canon[q];
         s += al[e] * da[e];
         if (dt) tsum += dt[e];
     }
-    const float tmean = tsum / (float)(b > a ? b - a : 1);
-    for (int q = a; q < b; ++q) {
+    s = team_sum_v(s);
+    tsum = team_sum_v(tsum);
+    const float tmean = tsum / (float)(v.b > v.a ? v.b - v.a : 1);
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) {
         const int e = var_canon[q];
         dwh[e] = dw[e] * w[e] * (1.f - w[e]);
         dah[e] = al[e] * (da[e] - s);
@@ -1086,13 +1106,12 @@ __global__ void k_param_transform_vjp(const int32_t *__restrict__ var_ptr, const
 __global__ void k_nonparam_update(const int32_t *__restrict__ var_ptr, const int32_t *__restrict__ var_canon,
                                   const int32_t *__restrict__ canon2slot, const float *__restrict__ th,
                                   float *__restrict__ lam, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int a = var_ptr[i], b = var_ptr[i + 1];
+    const VarTeam v = var_team(var_ptr, n);
     float tsum = 0.f;
-    for (int q = a; q < b; ++q) tsum += th[var_canon[q]];
-    const float tmean = tsum / (float)(b > a ? b - a : 1);
-    for (int q = a; q < b; ++q) {
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) tsum += th[var_canon[q]];
+    tsum = team_sum_v(tsum);
+    const float tmean = tsum / (float)(v.b > v.a ? v.b - v.a : 1);
+    for (int q = v.a + v.u; q < v.b; q += kVarLanes) {
         const int e = var_canon[q];
         const int sl = canon2slot[e];
         lam[sl] = lam[sl] + (th[e] - tmean);
@@ -1509,14 +1528,14 @@ hipError_t launch_flush_adj(const int32_t *evar, const float *S, const float *al
 hipError_t launch_dc(const int32_t *var_ptr, const int32_t *var_slots, const float *dlam, const float *c, float seed,
                      float *dc, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_dc, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_slots, dlam, c, seed, dc, n);
+    hipLaunchKernelGGL(k_dc, dim3(blocks_for((int64_t)n * kVarLanes, 256)), dim3(256), 0, s, var_ptr, var_slots, dlam, c, seed, dc, n);
     return hipGetLastError();
 }
 
 hipError_t launch_softmax_vjp(const int32_t *var_ptr, const int32_t *var_canon, const float *alpha,
                               const float *dalpha, float *out, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_softmax_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, alpha, dalpha, out,
+    hipLaunchKernelGGL(k_softmax_vjp, dim3(blocks_for((int64_t)n * kVarLanes, 256)), dim3(256), 0, s, var_ptr, var_canon, alpha, dalpha, out,
                        n);
     return hipGetLastError();
 }
@@ -1524,7 +1543,7 @@ hipError_t launch_softmax_vjp(const int32_t *var_ptr, const int32_t *var_canon, 
 hipError_t launch_param_transform(const int32_t *var_ptr, const int32_t *var_canon, const float *wh, const float *ah,
                                   const float *th, float *w, float *al, float *t, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_param_transform, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, wh, ah, th, w,
+    hipLaunchKernelGGL(k_param_transform, dim3(blocks_for((int64_t)n * kVarLanes, 256)), dim3(256), 0, s, var_ptr, var_canon, wh, ah, th, w,
                        al, t, n);
     return hipGetLastError();
 }
@@ -1533,7 +1552,7 @@ hipError_t launch_param_transform_vjp(const int32_t *var_ptr, const int32_t *var
                                       const float *al, const float *dw, const float *da, const float *dt, float *dwh,
                                       float *dah, float *dth, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_param_transform_vjp, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, w, al, dw,
+    hipLaunchKernelGGL(k_param_transform_vjp, dim3(blocks_for((int64_t)n * kVarLanes, 256)), dim3(256), 0, s, var_ptr, var_canon, w, al, dw,
                        da, dt, dwh, dah, dth, n);
     return hipGetLastError();
 }
@@ -1541,7 +1560,7 @@ hipError_t launch_param_transform_vjp(const int32_t *var_ptr, const int32_t *var
 hipError_t launch_nonparam_update(const int32_t *var_ptr, const int32_t *var_canon, const int32_t *canon2slot,
                                   const float *th, float *lam, int n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_nonparam_update, dim3(blocks_for(n, 256)), dim3(256), 0, s, var_ptr, var_canon, canon2slot,
+    hipLaunchKernelGGL(k_nonparam_update, dim3(blocks_for((int64_t)n * kVarLanes, 256)), dim3(256), 0, s, var_ptr, var_canon, canon2slot,
                        th, lam, n);
     return hipGetLastError();
 }
