@@ -1090,10 +1090,16 @@ int run_pass_rec(dd_instance *h, int dir, hipStream_t s, int32_t *mrec = nullptr
                  float *Se = nullptr) {
     h->en_lam_valid = false;
     h->version++;
-    int st = deferred_from(h, h->T.M, s, Se);
-    if (st == DD_OK)
+    // passes that form alpha*S themselves also write S per edge (every slot of a diagram level;
+    // padding slots keep the 0 they were allocated with): only S per variable is needed first
+    const bool fas = h->T.form_as != 0;
+    int st = fas ? deferred_sum(h, h->T.M, s) : deferred_from(h, h->T.M, s, Se);
+    if (st == DD_OK) {
+        if (fas) h->T.Se_rec = Se;
         st = recording(h, [&] { return all_classes(h, dir == 0, dir == 0 ? (int)FWD_UPDATE_REC : (int)BWD_UPDATE_REC, s); },
                        mrec, mdiff);
+        h->T.Se_rec = nullptr;
+    }
     h->en_lam_valid = st == DD_OK && dir == 1;
     return st;
 }
@@ -1347,6 +1353,7 @@ int stored_alloc(dd_instance *h, int n) {
     while ((int)h->tr_Se.size() < 2 * n) {
         float *p = nullptr;
         if ((st = h->alloc(&p, (size_t)h->edge_slots))) return st;
+        HIP_TRY(hipMemset(p, 0, sizeof(float) * (size_t)h->edge_slots));  // padding slots hold S = 0
         h->tr_Se.push_back(p);
     }
     return DD_OK;

@@ -38,6 +38,8 @@ struct EdgeAlphaS {
         __asm__("" : "+v"(r));
         return r;
     }
+    // S of the next hop's edge (0 on padding), as the S-per-edge array holds it
+    __device__ __forceinline__ float s_edge() const { return v >= 0 ? s : 0.f; }
     // loads for edge e, whose variable is vn, and the variable of edge e2
     __device__ __forceinline__ void prefetch(const DevTables &T, int64_t e, int64_t e2) {
         al = T.alpha[e];
@@ -97,6 +99,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
         wave_sync();
         for (int l = 0; l < nlev; ++l) {
             const float lam = lamn, om = omn, aS = fas ? eas.value() : aSn;
+            const float Se_now = fas && REC ? eas.s_edge() : 0.f;  // kept for the reverse sweeps
             uint32_t tp[RMAX];
             float fv[RMAX];
             // B of level l+1 (prefetched last hop) into LDS, with the terminals after it
@@ -172,6 +175,7 @@ __global__ __launch_bounds__(256) void k_fwd(DevTables T, int64_t tile0, int64_t
                 st1(buf(T.lam + tc.ebase, ne), off, lam_new);
                 st1(buf(T.M + tc.ebase, ne), off, Mn);
                 if (fas) st1(buf(T.aS + tc.ebase, ne), off, aS);
+                if (fas && REC) st1(buf(T.Se_rec ? T.Se_rec + tc.ebase : T.lam, T.Se_rec ? ne : 0), off, Se_now);
                 if (REC) record_argmins_team<P>(T, tc.ebase, ne, off, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
             } else {
                 lam_new = MODE == FWD_SWEEP_BAR ? lam + aS : lam;  // sweep, no update
@@ -255,6 +259,7 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
         wave_sync();
         for (int l = nlev - 1; l >= 0; --l) {
             const float lam = lamn, om = omn, aS = fas ? eas.value() : aSn;
+            const float Se_now = fas && REC ? eas.s_edge() : 0.f;  // kept for the reverse sweeps
             const int ce = cen;
             uint32_t tp[RMAX];
             float fv[RMAX];
@@ -324,6 +329,8 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
                     st1(buf(T.lam + tc.ebase, ne), off, lam_new);
                     st1(buf(T.M + tc.ebase, ne), off, Mn);
                     if (fas) st1(buf(T.aS + tc.ebase, ne), off, aS);
+                    if (fas && REC)
+                        st1(buf(T.Se_rec ? T.Se_rec + tc.ebase : T.lam, T.Se_rec ? ne : 0), off, Se_now);
                     if (REC) record_argmins_team<P>(T, tc.ebase, ne, off, lm0, m0, k0, h0, lm1, M1, k1, h1, d);
                 } else if (p == 0 && live) {
                     T.out0[ce] = m0;

@@ -55,6 +55,8 @@ struct DevTables {
     const float *S;           // [n] deferred sums
     float *aS;                // [edge slots] alpha * S of the edge's variable
     int form_as;              // narrow update passes form alpha * S from S and store it (no separate launch)
+    float *Se_rec;            // [edge slots] S of each edge's variable, written by the recording narrow passes
+                              // that form alpha * S (NULL: not kept; padding slots are left as they are)
     float *energies;          // [m] per-row E^j at the flushed multipliers
     float *en_lam;            // [m] per-row E^j at the current multipliers (from backward passes)
     float *out0, *out1;       // [edges] canonical min-marginal outputs
