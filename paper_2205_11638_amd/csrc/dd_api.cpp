@@ -1086,20 +1086,35 @@ int adj_deferred(dd_instance *h, float *dM, hipStream_t s) {
 
 // An update pass that records its argmins (as dd_run_pass otherwise); with Se, it keeps the S per
 // edge of its input M there.
+// With S_given (S of the pass-input M, kept by the forward that first ran this pass), the deferred
+// sum is not formed again.
 int run_pass_rec(dd_instance *h, int dir, hipStream_t s, int32_t *mrec = nullptr, float *mdiff = nullptr,
-                 float *Se = nullptr) {
+                 float *Se = nullptr, float *S_given = nullptr) {
     h->en_lam_valid = false;
     h->version++;
+    float *own_S = h->S;
+    if (S_given) {
+        h->S = S_given;
+        h->T.S = S_given;
+    }
     // passes that form alpha*S themselves also write S per edge (every slot of a diagram level;
     // padding slots keep the 0 they were allocated with): only S per variable is needed first
     const bool fas = h->T.form_as != 0;
-    int st = fas ? deferred_sum(h, h->T.M, s) : deferred_from(h, h->T.M, s, Se);
+    int st = DD_OK;
+    if (fas) st = S_given ? DD_OK : deferred_sum(h, h->T.M, s);
+    else if (S_given)
+        st = recorded(h, "k_edge_alpha_s", (Se ? 20.0 : 16.0) * (double)h->edge_slots, s, [&] {
+            return launch_edge_alpha_s(h->T.evar, h->alpha, h->S, h->aS, Se, h->edge_slots, s);
+        });
+    else st = deferred_from(h, h->T.M, s, Se);
     if (st == DD_OK) {
         if (fas) h->T.Se_rec = Se;
         st = recording(h, [&] { return all_classes(h, dir == 0, dir == 0 ? (int)FWD_UPDATE_REC : (int)BWD_UPDATE_REC, s); },
                        mrec, mdiff);
         h->T.Se_rec = nullptr;
     }
+    h->S = own_S;
+    h->T.S = own_S;
     h->en_lam_valid = st == DD_OK && dir == 1;
     return st;
 }
@@ -1362,17 +1377,20 @@ int stored_alloc(dd_instance *h, int n) {
 // n iterations from the current state, with B at that state already in trB[0]: forward pass t
 // writes F into trF[t] and its backward pass B into trB[t + 1] (the tables are re-pointed), every
 // pass records its argmins, and the state before every pass is kept.  The tables are left on the
-// last arrays.
-int stored_passes(dd_instance *h, int n, hipStream_t s) {
+// last arrays.  Sp (or NULL): the S of each of the 2n passes, when a forward already formed them.
+int stored_passes(dd_instance *h, int n, hipStream_t s, float *const *Sp = nullptr) {
     int st = save_state(h, h->tr_lam, h->tr_M, 0, s);
     for (int t = 0; t < n && st == DD_OK; ++t) {
         use_F(h, h->trF[t], h->trFp[t]);
         use_B(h, h->trB[t], h->trBc[t]);
-        if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t], h->tr_Se[2 * t])) ||
+        if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t], h->tr_Se[2 * t],
+                               Sp ? Sp[2 * t] : nullptr)) ||
             (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)))
             break;
         use_B(h, h->trB[t + 1], h->trBc[t + 1]);
-        if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1], h->tr_Se[2 * t + 1]))) break;
+        if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1], h->tr_Se[2 * t + 1],
+                               Sp ? Sp[2 * t + 1] : nullptr)))
+            break;
         st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s);
     }
     return st;
@@ -1473,17 +1491,30 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
         h->ck_hash_cap = cap;
     }
     if ((st = reserve_states(h, h->ck_lam, h->ck_M, (size_t)nseg + 1))) return st;
+    // the S of every pass, kept for the backward sweep's recomputed segments
+    while (h->fwd_S.size() < 2 * (size_t)T) {
+        float *p = nullptr;
+        if ((st = h->alloc(&p, (size_t)std::max<int64_t>(h->n, 1)))) return st;
+        h->fwd_S.push_back(p);
+    }
     // T iterations with a checkpoint (state and fingerprint) every K and one of the final state
     st = replayed(h, {2, T, K}, s, [&](hipStream_t q) {
         auto checkpoint = [&](size_t i) {
             int r = save_state(h, h->ck_lam, h->ck_M, i, q);
             return r ? r : state_hash(h, h->ck_lam[i], h->ck_M[i], h->ck_hash + i, q);
         };
+        float *own_S = h->S;
         int r = DD_OK;
         for (int t = 0; t < T && r == DD_OK; ++t) {
             if (t % K == 0 && (r = checkpoint((size_t)(t / K)))) break;
-            for (int d = 0; d < 2 && r == DD_OK; ++d) r = dd_run_pass(h, d, q);
+            for (int d = 0; d < 2 && r == DD_OK; ++d) {
+                h->S = h->fwd_S[2 * (size_t)t + d];  // the pass's deferred sums go here
+                h->T.S = h->S;
+                r = dd_run_pass(h, d, q);
+            }
         }
+        h->S = own_S;
+        h->T.S = own_S;
         return r ? r : checkpoint((size_t)nseg);
     });
     if (st) return st;
@@ -1549,7 +1580,7 @@ int backward_core(dd_instance *h, int T, int K, bool stored, bool seg_store, hip
         if (seg_store) {
             use_B(h, h->trB[0], h->trBc[0]);  // B at the checkpoint goes to the first stored array
             st = recompute_B(h, s);
-            if (st == DD_OK) st = stored_passes(h, t1 - t0, s);
+            if (st == DD_OK) st = stored_passes(h, t1 - t0, s, h->fwd_S.data() + 2 * (size_t)t0);
             if (st == DD_OK) st = verify_state(h, h->tr_lam[np], h->tr_M[np], (size_t)seg + 1, s);
             if (st == DD_OK) st = stored_reverse(h, t1 - t0, dl, dm, dl2, dm2, s);
             use_F(h, own_F, own_Fp);

@@ -84,6 +84,8 @@ struct dd_instance {
     uint64_t *hash_tmp = nullptr;         // [1] fingerprint of a loaded or recomputed state
     int32_t *ck_flag = nullptr;           // [1] set when a checkpoint or its recomputation does not match
     std::vector<float *> seg_lam, seg_M;  // pass-input states inside one checkpoint segment
+    std::vector<float *> fwd_S;           // S of every pass of the checkpointed forward (2T arrays of n),
+                                          // which a recomputed segment reproduces bit for bit
     // stored trajectory of the unrolled forward (ckpt_every = -1): the node costs every pass read or
     // wrote and the state before every pass, so the backward sweep recomputes nothing
     std::vector<float *> trF, trB;      // trF[t]: F left by forward pass t; trB[t]: B forward pass t read (t <= T)
