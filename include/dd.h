@@ -80,7 +80,8 @@ typedef struct {
     int32_t waves_per_block;/* max waves (tiles) per workgroup, 1..4, default 4 (DD_E_ARG otherwise) */
     int32_t ckpt_every;     /* iterations between adjoint checkpoints, default 5 */
     int32_t lds_budget;     /* max LDS bytes per workgroup, default 64 KiB */
-    int32_t no_graphs;      /* nonzero: dd_run launches every kernel itself instead of replaying graphs */
+    int32_t no_graphs;      /* nonzero: dd_run, the unrolled forward and the backward sweep launch every
+                               kernel themselves instead of replaying captured graphs */
     int32_t adj_route_dense;/* nonzero: the reverse sweeps of one-wave diagrams route every level node by
                                node instead of through their per-level lists of nonzero adjoints (the
                                path taken by levels whose lists overflow); for checking that path */
@@ -208,7 +209,11 @@ int dd_set_costs(dd_instance *h, const float *c, void *stream);
  * pass, so dd_backward recomputes no pass (DD_E_OOM, with nothing run, when the free device
  * memory is short; the arrays stay allocated with the instance for later calls).
  * Records what dd_backward needs; any later call that changes the state (a pass, reset,
- * set_state, set_params, set_costs) invalidates the record. */
+ * set_state, set_params, set_costs) invalidates the record.  With checkpoints, the deferred sums
+ * S of every pass are kept too (2T arrays of n floats) for the recomputed segments.  The launches
+ * after the reset are captured into a HIP graph the first time (T, ckpt_every) is seen with the
+ * same buffers and replayed afterwards (not while profiling or with no_graphs); results are the
+ * same bits either way. */
 int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, void *stream);
 
 /* Gradient of dlb * LB(after the recorded T iterations) with respect to omega, alpha and c:
@@ -221,7 +226,10 @@ int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *l
  * in no row contributes
  * dlb * [c_i < 0].  Subgradients at ties: lo arcs before hi arcs, lower node indices first.
  * Outputs are device arrays (may be NULL): d_omega, d_alpha [edges] canonical, d_c [n].
- * Leaves the solver at the final state.  DD_E_STATE without a valid record. */
+ * Leaves the solver at the final state.  DD_E_STATE without a valid record.  The launches up to
+ * the start-state adjoints replay a captured graph as dd_forward_unrolled's do (dlb is read from
+ * device memory, so one graph serves every seed); the call ends with a host wait for the
+ * checkpoint verification flag. */
 int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream);
 
 /* Test hook for the checkpoint verification: adds 1 to the first multiplier slot of checkpoint
