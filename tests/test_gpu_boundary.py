@@ -145,3 +145,38 @@ def test_captured_sequences_equal_eager_launches(case, T, K, replay):
         with pytest.raises(dd.DDError) as err:
             g.backward(1.0)
         assert err.value.code == dd.binding.DD_E_CHECKPOINT
+
+
+@pytest.mark.parametrize("K,dense", [(5, False), (-1, False), (2, True)])
+def test_captured_sequences_from_a_state(K, dense):
+    """The same equality for rounds that start from a given state (the training round's form: the
+    start state is set, the unrolled forward runs from it, the backward returns the start state's
+    adjoints too), alternating with eager calls that move the state; and with the reverse sweeps of
+    one-wave diagrams routed node by node (adj_route_dense)."""
+    import torch
+    if dense:
+        w = synth.workload("knapsack", small=True)
+        p, om, ah = w["problem"], w["omega"], w["alpha_hat"]
+    else:
+        p, om, ah = _gm()
+    say(f"captured vs eager from a state K={K} dense={dense}")
+    g, _, _ = make_instance(p, om, ah, adj_route_dense=dense)
+    e, _, _ = make_instance(p, om, ah, adj_route_dense=dense, graphs=False)
+    g.run(3)
+    lam, M = g.get_state()
+    for rnd, (T, seed) in enumerate(((6, 1.0), (6, -0.5), (4, 2.0), (6, 1.0))):
+        for inst in (g, e):
+            inst.set_state(lam, M)
+        lbg, lbe = g.forward_unrolled_from_state(T, K), e.forward_unrolled_from_state(T, K)
+        assert lbg == lbe, rnd
+        og = [host(t) for t in g.backward_state(seed)]
+        oe = [host(t) for t in e.backward_state(seed)]
+        for a, b, name in zip(og, oe, ("d_omega", "d_alpha", "d_lam0", "d_M0")):
+            assert np.isfinite(a).all()
+            np.testing.assert_array_equal(a, b, err_msg=f"{name} round {rnd}")
+        g.run(2)
+        e.run(2)
+        lam, M = (t.clone() for t in g.get_state())
+        for a, b in zip(g.get_state(), e.get_state()):
+            np.testing.assert_array_equal(host(a), host(b))
+        torch.cuda.synchronize()
