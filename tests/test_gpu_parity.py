@@ -301,6 +301,28 @@ def test_knapsack_full_sampled_rows(orc):
     torch.cuda.synchronize()
 
 
+def test_knapsack_full_lower_bound_trajectory(orc):
+    """The bound (D) of the whole 2,000,000-variable knapsack program after each of the first three
+    iterations, GPU against the oracle's fp64 iterations of all 40,000 rows from the same reset
+    state, at the bound's tolerance of 1e-5 relative."""
+    import torch
+    w = synth.workload("knapsack")
+    p = w["problem"]
+    say(f"knapsack full bound trajectory E={p.nnz}")
+    inst, om, al = make_instance(p, f32(w["omega"]), f32(w["alpha_hat"]))
+    om64, al64 = host(om), host(al)
+    lam, M = None, None
+    for t in range(1, 4):
+        inst.run(1)
+        lb_g = inst.lower_bound()[0]
+        lam, M = orc.run(p, om64, al64, 1, lam=lam, M=M)
+        lb_o = orc.lower_bound(p, al64, lam, M)[0]
+        say(f"  T={t}: gpu {lb_g:.6f} oracle {lb_o:.6f} rel {abs(lb_g - lb_o) / abs(lb_o):.2e}")
+        assert abs(lb_g - lb_o) <= 1e-5 * abs(lb_o), (t, lb_g, lb_o)
+    del inst
+    torch.cuda.synchronize()
+
+
 @pytest.mark.parametrize("wl", ["gm-small", "knapsack-small"])
 def test_passes_after_calls_that_leave_a_side_stale(orc, wl):
     """A pass reads the other side's shortest-path costs at its input multipliers (B for a forward
