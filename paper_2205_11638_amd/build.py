@@ -7,7 +7,9 @@ objects are linked by hipcc into paper_2205_11638_amd/libdd.so.
 """
 from __future__ import annotations
 
+import hashlib
 import os
+import shutil
 import subprocess
 import sys
 import tempfile
@@ -30,6 +32,19 @@ DEVICE_SRC = ["kernels.hip", "adjoint.hip", "features.hip", "noalloc.hip"]
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang",
              "-packed-fp32-ops", "-fno-honor-nans", "-Wall", "-Wno-unused-result"]
 HOST_FLAGS = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__", f"-I{ROCM}/include"]
+# device objects of the last build, keyed by the sources and flags they came from: the sanitized
+# build (host objects only differ) links them instead of compiling the device code again
+OBJ_CACHE = os.path.join(HERE, "_objcache")
+
+
+def _device_key():
+    h = hashlib.sha256(" ".join(HIP_FLAGS).encode())
+    for d, names in ((CSRC, sorted(os.listdir(CSRC))), (os.path.join(HERE, "..", "include"), ["dd.h"])):
+        for f in names:
+            if f.endswith((".hip", ".hpp", ".cpp", ".h")):
+                h.update(f.encode())
+                h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:24]
 
 
 def _run(cmd):
@@ -45,6 +60,9 @@ def build(verbose=False, sanitize=False) -> str:
     with ASan/UBSan, for CPU-only checks); returns the library path."""
     out_lib = LIB_SAN if sanitize else LIB
     host_flags = HOST_FLAGS + (SAN_FLAGS if sanitize else [])
+    key = _device_key()
+    cached = os.path.join(OBJ_CACHE, key)
+    reuse = sanitize and all(os.path.exists(os.path.join(cached, f + ".o")) for f in DEVICE_SRC)
     with tempfile.TemporaryDirectory(prefix="ddbuild") as tmp:
         objs = []
         procs = []
@@ -53,6 +71,9 @@ def build(verbose=False, sanitize=False) -> str:
             procs.append((["g++", *host_flags, "-c", os.path.join(CSRC, f), "-o", o]))
             objs.append(o)
         for f in DEVICE_SRC:
+            if reuse:
+                objs.append(os.path.join(cached, f + ".o"))
+                continue
             o = os.path.join(tmp, f + ".o")
             procs.append(([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, f), "-o", o]))
             objs.append(o)
@@ -70,6 +91,11 @@ def build(verbose=False, sanitize=False) -> str:
         # process preloads gcc's libasan and libubsan
         _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp_lib, *objs, "-lpthread"])
         os.replace(tmp_lib, out_lib)
+        if not reuse:  # keep this build's device objects (only the latest key)
+            shutil.rmtree(OBJ_CACHE, ignore_errors=True)
+            os.makedirs(cached, exist_ok=True)
+            for f in DEVICE_SRC:
+                shutil.copy(os.path.join(tmp, f + ".o"), os.path.join(cached, f + ".o"))
     return out_lib
 
 

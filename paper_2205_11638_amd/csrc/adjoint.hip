@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <type_traits>
 
 #include "device_common.hpp"
 #include "kernels.hpp"
@@ -724,14 +725,16 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, int *
             tv[q] = t[q];
             __asm__ volatile("" : "+v"(tv[q]));
         }
-        uint32_t nzb = 0;
+        // one flag per node of the lane: 4 Q bits (64-bit words for levels of more than 8 groups)
+        using flags_t = std::conditional_t<(4 * Q > 32), uint64_t, uint32_t>;
+        flags_t nzb = 0;
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const uint32_t tt = tv[q][j];
                 const float a0 = Fa[(int)(tt & 0xFFFFu)], a1 = Fa[(int)(tt >> 16)];
-                nzb |= (uint32_t)((a0 != 0.f) | (a1 != 0.f)) << (4 * q + j);
+                nzb |= (flags_t)((a0 != 0.f) | (a1 != 0.f)) << (4 * q + j);
             }
         int n = 0;
         const int k4 = lane16(lane) >> 2;
@@ -739,7 +742,7 @@ __device__ __forceinline__ void adjF_hop_w(float *Fv, float *Fa, int *bid, int *
         for (int q = 0; q < Q; ++q)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const bool nz = (nzb >> (4 * q + j)) & 1u;
+                const bool nz = (nzb >> (4 * q + j)) & 1;
                 const uint64_t m = __builtin_amdgcn_ballot_w64(nz);
                 const int pos = n + lanes_below(m);
                 if (nz && pos < CAP) {

@@ -174,13 +174,13 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
         int R = (b.max_width + P - 1) / P;
         int RMAX = 4;
         if (P == 64)
-            for (int cand : {4, 8, 12, 16, 24, 32, 1 << 30})
+            for (int cand : {4, 8, 12, 16, 24, 32, 64, 1 << 30})
                 if (cand >= R) {
                     RMAX = cand;
                     break;
                 }
         if (!class_supported(P, RMAX))
-            return fail(DD_E_UNSUPPORTED, "row %d: diagram width %d is wider than the kernels support (2048)", j,
+            return fail(DD_E_UNSUPPORTED, "row %d: diagram width %d is wider than the kernels support (4096)", j,
                         b.max_width);
         rP[j] = P;
         rR[j] = RMAX;

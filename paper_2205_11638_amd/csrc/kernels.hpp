@@ -115,7 +115,8 @@ constexpr int lds_words_pass_c(int P, int RMAX, int WB, int NL) {
 }
 
 #define DD_CLASSES(X) \
-    X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(64, 8) X(64, 12) X(64, 16) X(64, 24) X(64, 32)
+    X(1, 4) X(2, 4) X(4, 4) X(8, 4) X(16, 4) X(32, 4) X(64, 4) X(64, 8) X(64, 12) X(64, 16) X(64, 24) X(64, 32) \
+    X(64, 64)
 
 // per wave of the adjoint sweeps: push form = cost and adjoint of one level, bids; pull form =
 // staged B and the adjoints of two levels; both + the level table

@@ -70,10 +70,11 @@ def wide_class_problem(rmax):
     class of all of them): one row of width in that class's range, narrower knapsack rows, and
     2-variable rows (another tile class).  Returns (problem, width of the widest row)."""
     import synth
-    lo = {4: 128, 8: 256, 12: 512, 16: 768, 24: 1024, 32: 1536}[rmax]
+    lo = {4: 128, 8: 256, 12: 512, 16: 768, 24: 1024, 32: 1536, 64: 3072}[rmax]
     rng = np.random.default_rng(100 + rmax)
     n = 3000
-    wide, w = _row_of_width(rng, n, lo, rmax * 64, *((200, 40) if rmax > 16 else (140, 24)))
+    shape = (320, 60) if rmax > 32 else (200, 40) if rmax > 16 else (140, 24)
+    wide, w = _row_of_width(rng, n, lo, rmax * 64, *shape)
     rows = [wide]
     k = synth.knapsack(n=n, m=6, kmin=20, kmax=60, amax=10, frac=0.3, seed=200 + rmax)
     rows += [k.row(j) for j in range(k.m)]

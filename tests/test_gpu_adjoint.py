@@ -180,6 +180,7 @@ CASES = {
     "gm-full": lambda: synth.workload("gm")["problem"],
     "wide-24": lambda: wide_class_problem(24)[0],
     "wide-32": lambda: wide_class_problem(32)[0],
+    "wide-64": lambda: wide_class_problem(64)[0],
     "unit-rows": unit_rows_problem,
 }
 
@@ -339,7 +340,7 @@ def test_stored_trajectory_too_large_is_rejected():
     assert inst.lower_bound()[0] == lb  # nothing ran
 
 
-@pytest.mark.parametrize("case", ["knapsack-small", "team-sizes", "wide-24", "wide-32", "unit-rows"])
+@pytest.mark.parametrize("case", ["knapsack-small", "team-sizes", "wide-24", "wide-32", "wide-64", "unit-rows"])
 def test_dense_routing_matches_listed_routing(case):
     """The reverse sweeps of one-wave diagrams route a level's nonzero adjoints through a per-level
     list, and a level whose list would overflow node by node from the owning lanes; the option

@@ -116,7 +116,7 @@ def test_single_pass_parity_wide_and_narrow(orc):
     assert inst.stats["classes"] >= 2          # one-wave diagrams share a launch; 2-variable rows use another
 
 
-@pytest.mark.parametrize("rmax", [4, 8, 12, 16, 24, 32])
+@pytest.mark.parametrize("rmax", [4, 8, 12, 16, 24, 32, 64])
 def test_single_pass_parity_every_wide_class(orc, rmax):
     """One-wave diagrams in each register-tile class (the widest row sets the class of all of them):
     partial last groups and levels whose widths are not multiples of 4 occur along every row."""

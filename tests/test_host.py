@@ -171,3 +171,19 @@ def test_gap_integral(dd):
     g, gi = dd.gap_integral([1.0, 2.0], [0.0, 10.0], 1.0)
     np.testing.assert_allclose(g, [0.0, 0.0])
     assert gi == 0.0
+
+
+def test_diagram_wider_than_the_kernels_is_rejected_at_create():
+    """The widest one-wave class holds 64 rows of 64 nodes per level: a row whose diagram is wider
+    fails at create with DD_E_UNSUPPORTED naming the row, before any device memory is touched."""
+    import paper_2205_11638_amd as dd
+    rng = np.random.default_rng(0)
+    n = 2000
+    cols = rng.choice(n, size=600, replace=False)
+    a = rng.integers(1, 40, size=600)
+    p = synth.generators._from_rows(n, -np.ones(n), [(cols, a, -1, int(0.4 * a.sum()))], "too-wide")
+    w, _ = dd.binding.compile_row(p, 0)
+    assert w.max() > 4096
+    with pytest.raises(dd.DDError) as e:
+        dd.Instance(p)
+    assert e.value.code == dd.binding.DD_E_UNSUPPORTED and "row 0" in str(e.value) and "4096" in str(e.value)
