@@ -111,6 +111,10 @@ typedef struct {
     int32_t classes;        /* kernel specialisations used */
     int32_t uncovered;      /* variables in no row */
     int64_t device_bytes;   /* bytes the instance holds on the device */
+    int64_t coded_levels;   /* levels of one-wave diagrams whose passes read the topology in one byte
+                               per node (child-code steps; see DevTables::tcode) */
+    int64_t raw_levels;     /* levels of one-wave diagrams read in four bytes per node (steps that do
+                               not fit a nibble) */
 } dd_stats;
 
 typedef struct dd_instance dd_instance;

@@ -44,7 +44,7 @@ class dd_stats(C.Structure):
     _fields_ = [("n", C.c_int64), ("m", C.c_int64), ("edges", C.c_int64), ("nodes", C.c_int64), ("arcs", C.c_int64),
                 ("node_slots", C.c_int64), ("edge_slots", C.c_int64), ("tiles", C.c_int64),
                 ("max_width", C.c_int32), ("max_len", C.c_int32), ("classes", C.c_int32), ("uncovered", C.c_int32),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("coded_levels", C.c_int64), ("raw_levels", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

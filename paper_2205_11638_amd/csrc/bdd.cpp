@@ -8,6 +8,11 @@
 // both reach the 0-terminal is itself dropped.  No level is ever skipped, so every
 // root-to-1 path crosses exactly one node per variable, as the paper's node sets P_i
 // require.
+//
+// Nodes of a level are numbered in increasing partial sum: a node's children are the
+// classes of s and s + a_l one level below, so both child numbers are non-decreasing in the
+// node number, up to the point where they reach the 0-terminal.  The always-true node stands
+// for the smallest sums of a <= row (numbered first) and the largest of a >= row (last).
 #include "bdd.hpp"
 
 #include <algorithm>
@@ -119,9 +124,11 @@ int compile_row(int L, const int32_t *a, int sense, int64_t rhs, RowBdd &out, Co
             return W++;
         };
         ids.resize(st.size());
-        for (size_t t = 0; t < st.size(); ++t) ids[t] = node_for(child(st[t]), child(st[t] + al));
         int true_here = kBot;
-        if (scr.has_true[l]) true_here = node_for(true_next, true_next);
+        const bool true_first = sense < 0;
+        if (scr.has_true[l] && true_first) true_here = node_for(true_next, true_next);
+        for (size_t t = 0; t < st.size(); ++t) ids[t] = node_for(child(st[t]), child(st[t] + al));
+        if (scr.has_true[l] && !true_first) true_here = node_for(true_next, true_next);
         if (W > kMaxWidth) return E_UNSUPPORTED;
         // the dense index now describes this level
         for (int64_t s : scr.states[l + 1]) scr.index[(size_t)(s - smin)] = kBot;

@@ -141,7 +141,10 @@ struct HostPlan {
     std::vector<int64_t> node_base;
     std::vector<int32_t> edge_base, nlev, lev_base, w_base, bdd;
     std::vector<int32_t> lev_off, lev_rows;
+    std::vector<uint32_t> lev_code;  // codes of each level's first node, or kRawLevel
     std::vector<uint16_t> widths;
+    std::vector<uint8_t> tcode;      // byte codes of one-wave levels (node-slot indexed)
+    int64_t coded_levels = 0, raw_levels = 0;
     std::vector<int32_t> tile_P;
     int64_t node_slots = 0, edge_slots = 0, node_alloc = 0;
     // edges
@@ -160,6 +163,54 @@ int upload(dd_instance *h, T_ **dst, const std::vector<T_> &src, hipStream_t s) 
     if (st) return st;
     if (!src.empty()) HIP_TRY(hipMemcpyAsync(*dst, src.data(), src.size() * sizeof(T_), hipMemcpyHostToDevice, s));
     return DD_OK;
+}
+
+// Byte codes of the one-wave levels (DevTables::tcode, lev_code): nodes are numbered in increasing
+// partial sum, so a level's lo and hi child codes are non-decreasing in the node number, with the
+// 0-terminal (code Wn) after every node of the level below, and they mostly step by 0 or 1.  Each
+// node gets the two steps from the node before as nibbles; the first node's codes go to lev_code.
+// The last level (codes 0 = 0-terminal, 1 = 1-terminal) is coded as 1 - code, which is
+// non-decreasing there too.  A level whose steps fall outside 0..15 keeps kRawLevel and is read
+// from the 4-byte codes.
+void encode_topology(HostPlan &hp, const std::vector<uint32_t> &topo) {
+    hp.lev_code.assign(hp.lev_off.size(), kRawLevel);
+    hp.tcode.assign((size_t)hp.node_alloc, 0);
+    const int64_t ntiles = (int64_t)hp.nlev.size();
+    std::vector<int64_t> coded(ntiles, 0), raw(ntiles, 0);
+    parallel_for(ntiles, 64, [&](int64_t t, int) {
+        if (hp.tile_P[t] != 64) return;
+        const int nl = hp.nlev[t];
+        for (int l = 0; l < nl; ++l) {
+            const int li = hp.lev_base[t] + l;
+            const int64_t base = hp.node_base[t] + hp.lev_off[li];
+            const int W = hp.widths[hp.w_base[t] + l];
+            const bool last = l + 1 == nl;
+            auto code = [&](int k) {
+                const uint32_t c = topo[(size_t)(base + k)];
+                return last ? 0x00010001u - c : c;
+            };
+            bool ok = W > 0;
+            for (int k = 1; k < W && ok; ++k) {
+                const uint32_t a = code(k - 1), b = code(k);
+                const int dl = (int)(b & 0xFFFFu) - (int)(a & 0xFFFFu), dh = (int)(b >> 16) - (int)(a >> 16);
+                ok = dl >= 0 && dl <= 15 && dh >= 0 && dh <= 15;
+            }
+            if (!ok) {
+                ++raw[t];
+                continue;
+            }
+            hp.lev_code[li] = code(0);
+            for (int k = 1; k < W; ++k) {
+                const uint32_t a = code(k - 1), b = code(k);
+                hp.tcode[(size_t)(base + k)] = (uint8_t)(((b & 0xFFFFu) - (a & 0xFFFFu)) | (((b >> 16) - (a >> 16)) << 4));
+            }
+            ++coded[t];
+        }
+    });
+    for (int64_t t = 0; t < ntiles; ++t) {
+        hp.coded_levels += coded[t];
+        hp.raw_levels += raw[t];
+    }
 }
 
 int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowBdd> &bdds, int npl, int wpb,
@@ -312,6 +363,7 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
             }
         }
     });
+    encode_topology(hp, topo);
     // edges
     const int64_t E = sr.ptr[m];
     hp.canon2slot.assign((size_t)E, -1);
@@ -475,18 +527,18 @@ int adj_classes(dd_instance *h, const AdjTables &A, int which, int bar, int recs
 
 int deferred(dd_instance *h, hipStream_t s) { return deferred_from(h, h->T.M, s); }
 
-int smoothed_sweeps(dd_instance *h, float *Bs, float tau, int flushed, float *E_out, float *p_out, hipStream_t s) {
+int smoothed_sweeps(dd_instance *h, float *Qs, float tau, int flushed, float *E_out, float *p_out, hipStream_t s) {
     int st;
     if (flushed && (st = deferred(h, s))) return st;
     if (E_out) HIP_TRY(launch_fill(E_out, 0.f, h->m, s));  // rows with no variable: E = 0
     return per_class(
         h, s, [&](const ClassLaunch &cl, hipStream_t cs) {
-            return launch_smooth(h->T, cl, Bs, tau, flushed ? 1 : 0, E_out, p_out, cs);
+            return launch_smooth(h->T, cl, Qs, tau, flushed ? 1 : 0, E_out, p_out, cs);
         },
         [&](const ClassLaunch &cl) { return kname("k_smooth", cl); },
-        // per node: topology twice, the soft-min cost written, read back and gathered for two
-        // children (24 B); per edge: multipliers (and alpha*S) twice, the marginal and its index
-        [&](const ClassLaunch &cl) { return 24.0 * cl.nodes + 24.0 * cl.edges; });
+        // per node: topology twice, the arc probability written and read back (16 B); per edge:
+        // the multipliers and alpha*S, the marginal and its index (16 B)
+        [&](const ClassLaunch &cl) { return 16.0 * cl.nodes + 16.0 * cl.edges; });
 }
 
 // S_i of the given M (without alpha * S per edge)
@@ -634,6 +686,8 @@ int create_grouped(const dd_problem *prob, const dd_options *opt, void *stream, 
                      [](const ClassLaunch &x, const ClassLaunch &y) { return x.nodes > y.nodes; });
     h->ntiles = (int64_t)hp.nlev.size();
     h->node_slots = hp.node_slots;
+    h->coded_levels = hp.coded_levels;
+    h->raw_levels = hp.raw_levels;
     h->edge_slots = hp.edge_slots;
     h->row_nodes.resize((size_t)m);
     for (int j = 0; j < m; ++j) h->row_nodes[j] = (int64_t)bdds[j].arcs.size();
@@ -682,6 +736,8 @@ int create_grouped(const dd_problem *prob, const dd_options *opt, void *stream, 
     TRY(upload(h, (int32_t **)&T.lev_rows, hp.lev_rows, s));
     TRY(upload(h, (uint16_t **)&T.widths, hp.widths, s));
     TRY(upload(h, (uint32_t **)&T.topo, topo, s));
+    TRY(upload(h, (uint8_t **)&T.tcode, hp.tcode, s));
+    TRY(upload(h, (uint32_t **)&T.lev_code, hp.lev_code, s));
     TRY(h->alloc(&T.F, (size_t)hp.node_alloc));
     TRY(h->alloc(&T.B, (size_t)hp.node_alloc));
     TRY(h->alloc(&T.lam, (size_t)hp.edge_slots));
@@ -782,6 +838,8 @@ int dd_get_stats(const dd_instance *h, dd_stats *o) {
     o->classes = (int32_t)h->classes.size();
     o->uncovered = h->uncovered;
     o->device_bytes = h->device_bytes;
+    o->coded_levels = h->coded_levels;
+    o->raw_levels = h->raw_levels;
     return DD_OK;
 }
 
@@ -1742,8 +1800,8 @@ int dd_nonparam_update(dd_instance *h, const float *theta_hat, void *stream) {
 int dd_smoothed(dd_instance *h, float tau, int32_t flushed, float *E_out, float *p_out, void *stream) {
     if (!h || !(tau > 0.f) || !std::isfinite(tau) || (h->E && !p_out)) return fail(DD_E_ARG, "bad argument");
     int st;
-    if (!h->Bs && (st = h->alloc(&h->Bs, (size_t)(h->node_slots + 64)))) return st;
-    return smoothed_sweeps(h, h->Bs, tau, flushed, E_out, p_out, (hipStream_t)stream);
+    if (!h->Qs && (st = h->alloc(&h->Qs, (size_t)(h->node_slots + 64)))) return st;
+    return smoothed_sweeps(h, h->Qs, tau, flushed, E_out, p_out, (hipStream_t)stream);
 }
 
 int dd_argmin_assignment(dd_instance *h, int32_t flushed, float *x_out, void *stream) {

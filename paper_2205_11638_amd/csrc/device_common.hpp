@@ -196,10 +196,69 @@ __device__ __forceinline__ int lane16(int lane) {
     return v;
 }
 
+// Inclusive sum over the lanes of the wave, in lane order (unsigned, wrapping): shifts by 1, 2, 4
+// and 8 within each row of 16 lanes, then the row broadcasts of the wave64 DPP forms (lane 15 of
+// each row into the next row for rows 1 and 3, then lane 31 into rows 2 and 3).  Lanes whose
+// source falls outside take the first operand, 0.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);
+    return v;
+}
+
+// Child codes (lo | hi << 16) of a lane's four nodes in each of the first Q groups of a one-wave
+// level, from the level's byte codes (DevTables::tcode, one 32-bit word per lane and group, as
+// loaded at byte 256 q + 4 lane of the level) and the codes of its first node (cb).  The nibbles
+// are steps from the node before, so a node's codes are cb plus the steps of every node up to it:
+// the lane's own steps by byte-wise prefix sums, the lanes before it by a scan of the packed lane
+// totals (lo and hi in separate halves: sums stay far below 2^16), the groups before it by the scan
+// totals.  Lanes past the level's width decode the bytes that follow it; their codes are replaced
+// by the callers, and they only feed lanes after them.  last: the next level is empty, so the bytes
+// describe 1 - code.  A level of kRawLevel reads its 4-byte codes from traw instead.
+template <int Q, int QM>
+__device__ __forceinline__ void child_codes(const uint32_t (&cw)[QM], uint32_t cb, bool last, rsrc_t traw, int lane,
+                                            u32x4 (&t)[Q]) {
+    if (cb == 0xFFFFFFFFu) {
+        const int l16 = lane16(lane);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) t[q] = ld4(traw, l16 + q * 1024);
+        return;
+    }
+    uint32_t base = cb;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const uint32_t w = cw[q];
+        uint32_t wl = w & 0x0F0F0F0Fu, wh = (w >> 4) & 0x0F0F0F0Fu;
+        wl += wl << 8;
+        wl += wl << 16;
+        wh += wh << 8;
+        wh += wh << 16;
+        const uint32_t tot = (wl >> 24) | ((wh >> 24) << 16);
+        const uint32_t inc = wave_incl_sum(tot);
+        const uint32_t x = base + inc - tot;
+        if (q + 1 < Q) base += (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+        // node j: byte j of the lo sums into bits 0-7, byte j of the hi sums into bits 16-23
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            t[q][j] = x + __builtin_amdgcn_perm(wh, wl, (uint32_t)j | 0x0C00u | (uint32_t)(4 + j) << 16 | 0x0C000000u);
+    }
+    if (last)
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) t[q][j] = 0x00010001u - t[q][j];
+}
+
 // bytes of a level's node rows (loads) and of its nodes rounded up to whole lane chunks (stores)
 __device__ __forceinline__ int row_bytes(const Lev &c) { return c.R * 256; }
 __device__ __forceinline__ int node_bytes(const Lev &c) { return ((c.W + 3) & ~3) * 4; }
 __device__ __forceinline__ int groups(const Lev &c) { return (c.R + 3) >> 2; }
+// bytes of a level's rows of byte codes (DevTables::tcode)
+__device__ __forceinline__ int code_row_bytes(const Lev &c) { return c.R * 64; }
 
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));

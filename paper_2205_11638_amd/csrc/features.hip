@@ -4,10 +4,13 @@
 //
 // One wavefront per tile, as in the pass kernels.  Phase 1 sweeps the levels bottom-up in the
 // (soft-min, +) semiring: Bs(v) = softmin(Bs(lo v), lambda_l + Bs(hi v)) is the smoothed cost from
-// v to the 1-terminal, stored to a node array, and Bs(root) = E_tau^j.  Phase 2 sweeps top-down
-// pushing probability mass: the root holds 1, and node v passes p(v) exp(-(beta lambda_l +
-// Bs(child_beta v) - Bs(v)) / tau) along its beta arc (the two shares sum to 1); the mass that
-// takes hi arcs at level l is P(x_l = 1).  Mass is accumulated in LDS with native float adds.
+// v to the 1-terminal, and Bs(root) = E_tau^j.  The Gibbs distribution conditioned on reaching v
+// takes v's beta arc with probability exp(-(beta lambda_l + Bs(child_beta v) - Bs(v)) / tau); the
+// two probabilities sum to 1 and are fixed by the same exponential the soft-min evaluates, so
+// phase 1 stores, per node, the smaller of the two with its sign bit naming the arc it belongs to
+// (clear: lo, set: hi).  Phase 2 sweeps top-down pushing probability mass from the root (mass 1)
+// along both arcs, the larger share taken as 1 minus the smaller; the mass that takes hi arcs at
+// level l is P(x_l = 1).  Mass is accumulated in LDS with native float adds.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
@@ -18,16 +21,26 @@ namespace {
 
 using namespace dev;
 
-// soft-min of two costs at temperature tau (itau = 1 / tau)
-__device__ __forceinline__ float softmin2(float a, float b, float tau, float itau) {
-    if (a == kInf) return b;
-    if (b == kInf) return a;
-    const float m = fminf(a, b), d = fabsf(a - b);
-    return m - tau * log1pf(expf(-d * itau));
+// soft-min of the lo-arc cost a and the hi-arc cost b at temperature tau (itau = 1 / tau); q gets
+// the smaller of the two arc probabilities, signed as above (an arc into an infinite cost has
+// probability 0, a tie splits evenly)
+__device__ __forceinline__ float softmin2(float a, float b, float tau, float itau, float &q) {
+    if (a == kInf) {
+        q = 0.f;
+        return b;
+    }
+    if (b == kInf) {
+        q = -0.f;
+        return a;
+    }
+    const float m = fminf(a, b), e = expf(-fabsf(a - b) * itau);
+    const float small = e * __builtin_amdgcn_rcpf(1.f + e);  // 1 + e lies in [1, 2]
+    q = a <= b ? -small : small;
+    return m - tau * log1pf(e);
 }
 
 template <int P, int RMAX>
-__global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__ Bs, float tau, int bar,
+__global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__ Q, float tau, int bar,
                                                 float *__restrict__ E_out, float *__restrict__ p_out, int64_t tile0,
                                                 int64_t ntiles, int WB, int NL) {
     constexpr int G = 64 / P;
@@ -36,8 +49,8 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
     const int g = lane / P, p = lane % P;
     const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;
-    float *nbuf = lds_f + (size_t)wave * lds_words_features(P, WB, NL);  // three node buffers
-    int *meta = (int *)(nbuf + 3 * WB * G);
+    float *nbuf = lds_f + (size_t)wave * lds_words_features(P, WB, NL);  // two node buffers
+    int *meta = (int *)(nbuf + 2 * WB * G);
     int *off = meta + NL * G;
     const TileCtx tc = tile_ctx(T, tile);
     const int row = T.bdd[tile * 64 + g];
@@ -70,7 +83,7 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
     auto edge_off = [&](int l) { return (max(min(l, nlev - 1), 0) * G + g) * 4; };
     const int mine = p * G + g;
     const float itau = 1.f / tau;
-    // ---- phase 1: bottom-up soft-min costs, stored to Bs
+    // ---- phase 1: bottom-up soft-min costs (in LDS), arc probabilities stored to Q
     int cur = 0;  // buffer holding level l+1
     if (p == 0) {
         nbuf[g] = kInf;
@@ -98,9 +111,11 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
             if (r < c0.R) {
                 const bool ok = in_level<P>(r, c0.R, lane, c0.W);
                 const uint32_t t = ok ? tp[r] : dead;
-                const float v = softmin2(bn[(int)(t & 0xFFFFu) * G + g], lam + bn[(int)(t >> 16) * G + g], tau, itau);
+                float q;
+                const float v =
+                    softmin2(bn[(int)(t & 0xFFFFu) * G + g], lam + bn[(int)(t >> 16) * G + g], tau, itau, q);
                 bc[mine + r * P * G] = v;
-                if (ok) Bs[c0.base + r * 64 + lane] = v;
+                if (ok) Q[c0.base + r * 64 + lane] = q;
             }
         }
         wave_sync();  // the terminals' slots may have been written by another lane
@@ -117,9 +132,8 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
     // phase 2 reads back what phase 1 stored: make the stores visible to this wave's loads
     __threadfence();
     wave_sync();
-    // ---- phase 2: top-down probability mass; buffers: mass of level l (pa) and of level l+1 (pb),
-    // and the smoothed costs of level l+1 with its terminals (bst)
-    float *pa = nbuf, *pb = nbuf + WB * G, *bst = nbuf + 2 * WB * G;
+    // ---- phase 2: top-down probability mass; buffers: mass of level l (pa) and of level l+1 (pb)
+    float *pa = nbuf, *pb = nbuf + WB * G;
     {
         const int R0 = uni(meta[0] >> 16);
         for (int r = 0; r < R0; ++r) pa[mine + r * P * G] = 0.f;
@@ -127,40 +141,24 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
     }
     c0 = level(0);
     Lev c1 = level(1);
-    float bcur[RMAX], bnext[RMAX];  // Bs of levels l and l+1
+    float qn[RMAX];  // arc probabilities of the next level
     rows_u(T.topo, c0, tpn);
-    rows_f(Bs, c0, bcur);
-    rows_f(Bs, c1, bnext);
-    lamn = ld1f(lam_r, edge_off(0));
-    aSn = ld1f(aS_r, edge_off(0));
+    rows_f(Q, c0, qn);
     wave_sync();
     for (int l = 0; l < nlev; ++l) {
         const int Wn = c1.W;
         uint32_t tp[RMAX];
-        float bv[RMAX];
+        float qv[RMAX];
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
             tp[r] = tpn[r];
-            bv[r] = bcur[r];
-            bcur[r] = bnext[r];
-            if (r < c1.R) {
-                bst[mine + r * P * G] = bnext[r];  // children's costs
-                pb[mine + r * P * G] = 0.f;
-            }
+            qv[r] = qn[r];
+            if (r < c1.R) pb[mine + r * P * G] = 0.f;
         }
-        const float lam = bar ? lamn + aSn : lamn;
-        // prefetch hop l+1: topology of level l+1, Bs of level l+2, edge data of level l+1
-        const Lev c2 = level(l + 2);
+        // prefetch hop l+1
         rows_u(T.topo, c1, tpn);
-        rows_f(Bs, c2, bnext);
-        lamn = ld1f(lam_r, edge_off(l + 1));
-        aSn = ld1f(aS_r, edge_off(l + 1));
-        wave_sync();  // the terminals' slots may have been staged by another lane
-        if (p == 0) {
-            bst[Wn * G + g] = kInf;
-            bst[(Wn + 1) * G + g] = 0.f;
-        }
-        wave_sync();
+        rows_f(Q, c1, qn);
+        wave_sync();  // the next level's mass is cleared before any lane adds to it
         float hi_mass = 0.f;
 #pragma unroll
         for (int r = 0; r < RMAX; ++r) {
@@ -169,10 +167,10 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
                 const float m = ok ? pa[mine + r * P * G] : 0.f;
                 if (m > 0.f) {
                     const int lo = (int)(tp[r] & 0xFFFFu), hi = (int)(tp[r] >> 16);
-                    const float b0 = bst[lo * G + g], b1 = bst[hi * G + g];
-                    const float q0 = b0 < kInf ? expf(-(b0 - bv[r]) * itau) : 0.f;
-                    const float q1 = b1 < kInf ? expf(-(lam + b1 - bv[r]) * itau) : 0.f;
-                    if (lo < Wn) lds_fadd(&pb[lo * G + g], m * q0);
+                    const float small = fabsf(qv[r]), large = 1.f - small;
+                    const bool hi_small = signbit(qv[r]);
+                    const float q1 = hi_small ? small : large;
+                    if (lo < Wn) lds_fadd(&pb[lo * G + g], m * (hi_small ? large : small));
                     if (hi < Wn) lds_fadd(&pb[hi * G + g], m * q1);
                     hi_mass += m * q1;
                 }
@@ -185,30 +183,30 @@ __global__ __launch_bounds__(256) void k_smooth(DevTables T, float *__restrict__
         pa = pb;
         pb = t;
         c0 = c1;
-        c1 = c2;
+        c1 = level(l + 2);
     }
 }
 
 template <int P, int RMAX>
-hipError_t smooth_dispatch(const DevTables &t, const ClassLaunch &c, float *Bs, float tau, int bar, float *E_out,
+hipError_t smooth_dispatch(const DevTables &t, const ClassLaunch &c, float *Q, float tau, int bar, float *E_out,
                            float *p_out, hipStream_t s) {
     int wpb = c.wpb_b;
     if (wpb < 1 || wpb > kMaxWavesPerBlock) return hipErrorInvalidConfiguration;
     while (wpb > 1 && (size_t)wpb * lds_words_features(P, c.WB, c.NL) * 4 > 64 * 1024) wpb /= 2;
     dim3 grid((unsigned)((c.ntiles + wpb - 1) / wpb)), block(64 * wpb);
     const size_t lds = (size_t)wpb * lds_words_features(P, c.WB, c.NL) * 4;
-    hipLaunchKernelGGL((k_smooth<P, RMAX>), grid, block, lds, s, t, Bs, tau, bar, E_out, p_out, c.tile0, c.ntiles,
+    hipLaunchKernelGGL((k_smooth<P, RMAX>), grid, block, lds, s, t, Q, tau, bar, E_out, p_out, c.tile0, c.ntiles,
                        c.WB, c.NL);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_smooth(const DevTables &t, const ClassLaunch &c, float *Bs, float tau, int bar, float *E_out,
+hipError_t launch_smooth(const DevTables &t, const ClassLaunch &c, float *Q, float tau, int bar, float *E_out,
                          float *p_out, hipStream_t s) {
     if (c.ntiles <= 0) return hipSuccess;
 #define DD_SMOOTH(PP, RR) \
-    if (c.P == PP && c.RMAX == RR) return smooth_dispatch<PP, RR>(t, c, Bs, tau, bar, E_out, p_out, s);
+    if (c.P == PP && c.RMAX == RR) return smooth_dispatch<PP, RR>(t, c, Q, tau, bar, E_out, p_out, s);
     DD_CLASSES(DD_SMOOTH)
 #undef DD_SMOOTH
     return hipErrorInvalidValue;

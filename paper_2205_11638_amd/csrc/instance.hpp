@@ -38,6 +38,7 @@ struct dd_instance {
     int lb_every = 1;              // default iterations between the bounds of dd_run_trace
     std::vector<ClassLaunch> classes;
     int64_t ntiles = 0, node_slots = 0, edge_slots = 0, device_bytes = 0;
+    int64_t coded_levels = 0, raw_levels = 0;  // one-wave levels with and without byte codes
     std::vector<int32_t> edge_var, edge_row;  // canonical edge map (host)
     std::vector<int64_t> row_nodes;
     // profiling: event pairs recorded around launches while enabled
@@ -74,7 +75,7 @@ struct dd_instance {
     bool adj_ready = false;
     float *lam_in = nullptr, *dlamA = nullptr, *dlamB = nullptr, *dMA = nullptr, *dMB = nullptr, *g = nullptr;
     float *dalpha = nullptr, *domega = nullptr, *rec_val = nullptr, *scratch_n = nullptr, *Se = nullptr;
-    float *Bs = nullptr;  // smoothed node costs (allocated on first use)
+    float *Qs = nullptr;  // per-node arc probabilities of the smoothed sweeps (allocated on first use)
     int32_t *rec_idx = nullptr;
     int32_t *mrec = nullptr;  // argmin records of the last recording update pass (one-wave diagrams)
     float *mdiff = nullptr;
@@ -195,9 +196,9 @@ int all_classes(dd_instance *h, bool fwd, int mode, hipStream_t s);
 int recompute_B(dd_instance *h, hipStream_t s);
 // The launches of one pass (deferred sums, then the update sweep of every class); host flags untouched.
 int pass_launches(dd_instance *h, int dir, hipStream_t s);
-// The smoothed-subproblem sweeps of every class (soft-min costs into Bs, a node array of at least
+// The smoothed-subproblem sweeps of every class (arc probabilities into Qs, a node array of at least
 // node_slots + 64 floats whose prior contents are never read), E_out / p_out as dd_smoothed.
-int smoothed_sweeps(dd_instance *h, float *Bs, float tau, int flushed, float *E_out, float *p_out, hipStream_t s);
+int smoothed_sweeps(dd_instance *h, float *Qs, float tau, int flushed, float *E_out, float *p_out, hipStream_t s);
 // dd_create with a locality group per row (row_group[j] for row j, or nullptr): within a kernel
 // class the rows of one group get consecutive tiles, so their edge slots form one stretch.
 int create_grouped(const dd_problem *prob, const dd_options *opt, void *stream, const int32_t *row_group,

@@ -402,9 +402,9 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
 // splits the keys of its level into the F row and the code row.
 template <int Q, int RMAX, int MODE, typename Prefetch>
 __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, rsrc_t rec_r, rsrc_t md_r, rsrc_t Pr,
-                                          float *Fb, const float *Bst, const u32x4 (&tp)[RMAX / 4], int lane,
-                                          int out, const Lev &c0, const Lev &c1, float lam, float om, float aS,
-                                          Prefetch &&prefetch) {
+                                          float *Fb, const float *Bst, const uint32_t (&cw)[RMAX / 4], uint32_t cb,
+                                          rsrc_t traw, int lane, int out, const Lev &c0, const Lev &c1, float lam,
+                                          float om, float aS, Prefetch &&prefetch) {
     constexpr bool REC = MODE == FWD_UPDATE_REC, UPD = MODE == FWD_UPDATE || REC;
     constexpr bool PAR = REC || MODE == FWD_SWEEP_LAM;
     constexpr int QM = RMAX / 4, SINK = RMAX * 64;
@@ -412,6 +412,7 @@ __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, r
     uint64_t *Kb = (uint64_t *)Fb;  // PAR: the keys of this level, then of level l+1
     f32x4 fv[Q];
     u32x4 t[Q];
+    child_codes<Q>(cw, cb, c1.W == 0, traw, lane, t);
     if constexpr (PAR) {
         const int l32 = lane32(lane), l8 = lane8(lane);
 #pragma unroll
@@ -422,14 +423,10 @@ __device__ __forceinline__ void fwd_hop_w(rsrc_t Fr, rsrc_t lam_r, rsrc_t M_r, r
             // codes of this level's nodes (every slot past the width holds 0xFFFF)
             st2(Pr, l8 + q * 512, ((uint32_t)a[0] & 0xFFFFu) | ((uint32_t)a[1] << 16),
                 ((uint32_t)b[0] & 0xFFFFu) | ((uint32_t)b[1] << 16));
-            t[q] = tp[q];
         }
     } else {
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-            fv[q] = lds4(Fb, l16 + q * 1024);  // slots past the level's width hold +inf
-            t[q] = tp[q];
-        }
+        for (int q = 0; q < Q; ++q) fv[q] = lds4(Fb, l16 + q * 1024);  // slots past the level's width hold +inf
     }
     // last group: this lane's slots past the level's width get two 0-terminal arcs
     const int rem = c0.W - (Q - 1) * 256 - lane * 4;
@@ -528,14 +525,14 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
         const rsrc_t rec_r = rec_buf<REC>(T, tc, nlev), md_r = mdiff_buf<REC>(T, tc, nlev);
         const int out0 = lane * nlev * 4;  // hop l stores at out0 + 4 l: in range for lane 0 only
         Lev c0 = level(0), c1 = level(1), c2 = level(2);
-        u32x4 tpn[QM];
+        uint32_t cwn[QM], cbn = T.lev_code[tc.lbase];  // byte codes of the level's topology
         f32x4 bvn[QM];
         {
             const int l16 = lane16(lane);
-            const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), br = buf(T.B + c1.base, row_bytes(c1));
+            const rsrc_t cr = buf(T.tcode + c0.base, code_row_bytes(c0)), br = buf(T.B + c1.base, row_bytes(c1));
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
-                tpn[q] = ld4(tr, l16 + q * 1024);
+                cwn[q] = ld1(cr, lane * 4 + q * 256);
                 bvn[q] = UPD ? ld4f(br, l16 + q * 1024) : inf4;
             }
         }
@@ -563,9 +560,10 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
         wave_sync();
         for (int l = 0; l < nlev; ++l) {
             const float lam = lamn, om = omn, aS = aSn;
-            u32x4 tp[QM];
+            uint32_t cw[QM];
+            const uint32_t cb = uni((int)cbn);
 #pragma unroll
-            for (int q = 0; q < QM; ++q) tp[q] = tpn[q];
+            for (int q = 0; q < QM; ++q) cw[q] = cwn[q];
             if (UPD) {
                 // B of level l+1, then its terminals
                 const int l16 = lane16(lane);
@@ -578,12 +576,13 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
             }
             // prefetch: topology of l+1, B of l+2, edge data of l+1 (the last hop reloads its own)
             auto prefetch = [&](int l16) {
-                const rsrc_t tr = buf(T.topo + c1.base, row_bytes(c1)), br = buf(T.B + c2.base, row_bytes(c2));
+                const rsrc_t cr = buf(T.tcode + c1.base, code_row_bytes(c1)), br = buf(T.B + c2.base, row_bytes(c2));
 #pragma unroll
                 for (int q = 0; q < QM; ++q) {
-                    tpn[q] = ld4(tr, l16 + q * 1024);
+                    cwn[q] = ld1(cr, lane * 4 + q * 256);
                     if (UPD) bvn[q] = ld4f(br, l16 + q * 1024);
                 }
+                cbn = T.lev_code[tc.lbase + min(l + 1, nlev - 1)];
                 const int e = tc.ebase + min(l + 1, nlev - 1);
                 lamn = T.lam[e];
                 aSn = T.aS[e];
@@ -594,9 +593,10 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
             const bool codes = PAR && T.Fpar && l > 0;
             const rsrc_t Pr = buf(codes ? (const void *)(T.Fpar + c0.base) : (const void *)T.F,
                                   codes ? code_bytes(c0) : 0);
+            const rsrc_t traw = buf(T.topo + c0.base, row_bytes(c0));
             with_count<1, QM>(groups(c0), [&](auto qc) {
-                fwd_hop_w<decltype(qc)::value, RMAX, MODE>(Fr, lam_r, M_r, rec_r, md_r, Pr, Fb, Bst, tp, lane,
-                                                           out0 + 4 * l, c0, c1, lam, om, aS, prefetch);
+                fwd_hop_w<decltype(qc)::value, RMAX, MODE>(Fr, lam_r, M_r, rec_r, md_r, Pr, Fb, Bst, cw, cb, traw,
+                                                           lane, out0 + 4 * l, c0, c1, lam, om, aS, prefetch);
             });
             c0 = c1;
             c1 = c2;
@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
 template <int Q, int RMAX, int MODE>
 __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t Cr, rsrc_t lam_r, rsrc_t M_r,
                                           rsrc_t rec_r, rsrc_t md_r, const float *bn, float *bc,
-                                          const u32x4 (&tp)[RMAX / 4],
+                                          const uint32_t (&cw)[RMAX / 4], uint32_t cb, rsrc_t traw,
                                           const f32x4 (&fn)[RMAX / 4], int lane, int out, const Lev &c0, int Wn,
                                           float lam, float om, float aS, int ce) {
     constexpr bool REC = MODE == BWD_UPDATE_REC, UPD = MODE == BWD_UPDATE || REC, MM = MODE == BWD_MM;
@@ -624,8 +624,7 @@ __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t 
     const int l16 = lane16(lane);
     u32x4 t[Q];
     f32x4 b0[Q], b1[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) t[q] = tp[q];
+    child_codes<Q>(cw, cb, Wn == 0, traw, lane, t);
     const int rem = c0.W - (Q - 1) * 256 - lane * 4;
     const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
 #pragma unroll
@@ -738,14 +737,14 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
         const int out0 = lane * nlev * 4;  // hop l stores at out0 + 4 l: in range for lane 0 only
         Lev c0 = level(nlev - 1), cp = level(nlev - 2);  // levels l, l-1
         int Wn = 0;                                       // width of level l+1 (none below the last)
-        u32x4 tpn[QM];
+        uint32_t cwn[QM], cbn = T.lev_code[tc.lbase + nlev - 1];  // byte codes of the level's topology
         f32x4 fn[QM];
         {
             const int l16 = lane16(lane);
-            const rsrc_t tr = buf(T.topo + c0.base, row_bytes(c0)), fr = buf(T.F + c0.base, row_bytes(c0));
+            const rsrc_t cr = buf(T.tcode + c0.base, code_row_bytes(c0)), fr = buf(T.F + c0.base, row_bytes(c0));
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
-                tpn[q] = ld4(tr, l16 + q * 1024);
+                cwn[q] = ld1(cr, lane * 4 + q * 256);
                 fn[q] = NEEDF ? ld4f(fr, l16 + q * 1024) : zero4;
             }
         }
@@ -761,11 +760,12 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
         for (int l = nlev - 1; l >= 0; --l) {
             const float lam = lamn, om = omn, aS = aSn;
             const int ce = cen;
-            u32x4 tp[QM];
+            uint32_t cw[QM];
+            const uint32_t cb = uni((int)cbn);
             f32x4 fv[QM];
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
-                tp[q] = tpn[q];
+                cw[q] = cwn[q];
                 fv[q] = fn[q];
             }
             const float *bn = buf0 + cur * NB;
@@ -773,12 +773,13 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
             // prefetch level l-1 (the first level reloads its own edge data)
             {
                 const int l16 = lane16(lane);
-                const rsrc_t tr = buf(T.topo + cp.base, row_bytes(cp)), fr = buf(T.F + cp.base, row_bytes(cp));
+                const rsrc_t cr = buf(T.tcode + cp.base, code_row_bytes(cp)), fr = buf(T.F + cp.base, row_bytes(cp));
 #pragma unroll
                 for (int q = 0; q < QM; ++q) {
-                    tpn[q] = ld4(tr, l16 + q * 1024);
+                    cwn[q] = ld1(cr, lane * 4 + q * 256);
                     if (NEEDF) fn[q] = ld4f(fr, l16 + q * 1024);
                 }
+                cbn = T.lev_code[tc.lbase + max(l - 1, 0)];
                 const int e = tc.ebase + max(l - 1, 0);
                 lamn = T.lam[e];
                 if (UPD || BAR) aSn = T.aS[e];
@@ -788,9 +789,10 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
             const rsrc_t Br = buf(T.B + c0.base, node_bytes(c0));
             const rsrc_t Cr = buf(T.Bch ? (const void *)(T.Bch + c0.base) : (const void *)T.B,
                                   T.Bch ? code_bytes(c0) : 0);  // no codes recorded: every store dropped
+            const rsrc_t traw = buf(T.topo + c0.base, row_bytes(c0));
             with_count<1, QM>(groups(c0), [&](auto qc) {
-                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, Cr, lam_r, M_r, rec_r, md_r, bn, bc, tp, fv, lane,
-                                                           out0 + 4 * l, c0, Wn, lam, om, aS, ce);
+                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, Cr, lam_r, M_r, rec_r, md_r, bn, bc, cw, cb, traw,
+                                                           fv, lane, out0 + 4 * l, c0, Wn, lam, om, aS, ce);
             });
             wave_sync();
             cur ^= 1;

@@ -30,6 +30,8 @@ enum BwdMode {
     BWD_UPDATE_REC = 6
 };
 
+constexpr uint32_t kRawLevel = 0xFFFFFFFFu;  // lev_code of a level without byte codes
+
 struct DevTables {
     // tile tables
     const int64_t *node_base;
@@ -43,6 +45,14 @@ struct DevTables {
     const uint16_t *widths;
     // nodes
     const uint32_t *topo;     // lo | hi << 16 child codes
+    // the same codes of one-wave diagrams in one byte per node (node-slot indexed like topo): the
+    // step of the lo child code in the low nibble and of the hi child code in the high nibble, from
+    // the node before in the level; lev_code[level] (indexed like lev_off) holds the codes of the
+    // level's first node, lo | hi << 16, or kRawLevel when the steps of a level do not fit (its
+    // passes read topo).  On a level whose next one is empty (codes 0 and 1, the two terminals)
+    // the bytes describe 1 - code, so that those codes are non-decreasing too.
+    const uint8_t *tcode;
+    const uint32_t *lev_code;
     float *F;                 // shortest path root -> node (forward pass output)
     float *B;                 // shortest path node -> 1-terminal (backward pass output)
     // edges (slot indexed)
@@ -89,10 +99,11 @@ struct ClassLaunch {
 // LDS words (4 bytes) one wavefront of the forward / backward pass kernels uses.
 // per wave: two node buffers (2 * WB * G) and the level table (NL * G + NL)
 // per wave of the smoothed-feature kernel: two node buffers and the level table
-constexpr int lds_words_features(int P, int WB, int NL) { return 3 * WB * (64 / P) + NL * ((64 / P) + 1); }
+constexpr int lds_words_features(int P, int WB, int NL) { return 2 * WB * (64 / P) + NL * ((64 / P) + 1); }
 // Smoothed energies (E_out[row], may be NULL) and Gibbs marginals (p_out, canonical) of one class at
-// temperature tau, at lambda (bar = 0) or lambda + alpha*S (bar = 1); Bs: node array for the costs.
-hipError_t launch_smooth(const DevTables &t, const ClassLaunch &c, float *Bs, float tau, int bar, float *E_out,
+// temperature tau, at lambda (bar = 0) or lambda + alpha*S (bar = 1); Q: node array for the
+// per-node arc probabilities that the up sweep hands to the down sweep.
+hipError_t launch_smooth(const DevTables &t, const ClassLaunch &c, float *Q, float tau, int bar, float *E_out,
                          float *p_out, hipStream_t s);
 
 // Every kernel of the solver is compiled for workgroups of at most 256 threads (4 waves).

@@ -18,8 +18,8 @@
 
 namespace {
 
-// 16 MiB of fp32 scratch per GPU: the node costs of the smoothed-subproblem sweeps of instances up
-// to kScratchFloats - 64 node slots (the graph-matching workload needs 2.3M).
+// 16 MiB of fp32 scratch per GPU: the per-node arc probabilities of the smoothed-subproblem sweeps of
+// instances up to kScratchFloats - 64 node slots (the graph-matching workload needs 2.3M).
 constexpr size_t kScratchFloats = size_t(1) << 22;
 
 static __device__ __align__(256) float scratch[kScratchFloats];
@@ -60,10 +60,10 @@ int dd_smoothed_noalloc(dd_instance *h, float tau, int32_t flushed, float *E_out
     if (device != h->device)
         return ddi::fail(DD_E_ARG, "dd_smoothed_noalloc: the current device %d is not the instance's (%d)", device,
                          h->device);
-    float *Bs = nullptr;
-    const int st = scratch_on(device, &Bs);
+    float *Qs = nullptr;
+    const int st = scratch_on(device, &Qs);
     if (st) return st;
-    return ddi::smoothed_sweeps(h, Bs, tau, flushed, E_out, p_out, (hipStream_t)stream);
+    return ddi::smoothed_sweeps(h, Qs, tau, flushed, E_out, p_out, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -81,3 +81,34 @@ def wide_class_problem(rmax):
     s = synth.independent_set(n=n, M=50, seed=300 + rmax)
     rows += [s.row(j) for j in range(s.m)]
     return synth.generators._from_rows(n, -rng.uniform(0, 1, size=n), rows, f"class-{rmax}"), w
+
+
+def coded_and_raw_problem(seed=31):
+    """One-wave diagrams whose passes read some levels in byte codes (child-code steps of 0..15) and
+    some in 4-byte codes: >= rows (their small partial sums lead to the 0-terminal first, so child
+    codes are not monotone), <= rows with coefficients up to 400 (steps beyond a nibble), knapsack
+    rows (every level coded), next to = rows and 2-variable rows of narrower classes."""
+    import synth
+    rng = np.random.default_rng(seed)
+    n = 3000
+    rows = []
+    for _ in range(3):
+        cols = rng.choice(n, 60, replace=False)
+        a = rng.integers(1, 21, 60)
+        rows.append((cols, a, 1, int(0.6 * a.sum())))
+    for _ in range(3):
+        cols = rng.choice(n, 40, replace=False)
+        a = rng.integers(1, 9, 40)
+        rows.append((cols, a, 0, int(0.5 * a.sum())))
+    for _ in range(2):
+        cols = rng.choice(n, 24, replace=False)
+        a = rng.integers(1, 400, 24)
+        rows.append((cols, a, -1, int(0.4 * a.sum())))
+    k = synth.knapsack(n=n, m=4, kmin=40, kmax=80, amax=20, frac=0.4, seed=seed)
+    rows += [k.row(j) for j in range(k.m)]
+    s = synth.independent_set(n=n, M=40, seed=seed + 1)
+    rows += [s.row(j) for j in range(s.m)]
+    # normal costs (of both signs) from a stream of their own: the dual is still moving after a few
+    # iterations, so the gradients with respect to omega are not rounding residue
+    c = np.random.default_rng(seed + 68).normal(size=n)
+    return synth.generators._from_rows(n, c, rows, "coded-and-raw")

@@ -29,7 +29,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import host, make_instance, say, wide_class_problem
+from tests.gpu_util import coded_and_raw_problem, host, make_instance, say, wide_class_problem
 
 pytestmark = pytest.mark.gpu
 GRAD_RTOL = 1e-4
@@ -182,6 +182,7 @@ CASES = {
     "wide-32": lambda: wide_class_problem(32)[0],
     "wide-64": lambda: wide_class_problem(64)[0],
     "unit-rows": unit_rows_problem,
+    "coded-raw": coded_and_raw_problem,
 }
 
 
@@ -263,7 +264,8 @@ def unrolled_against_oracle(orc, p, om, ah, T, K, what, min_det=MIN_DETERMINED):
 
 
 @pytest.mark.parametrize("case,T,K,seed", [("mixed0", 3, 2, 23), ("setcover", 4, 3, 3), ("gm-small", 5, 2, 1),
-                                           ("team-sizes", 3, 1, 0), ("knapsack-small", 3, 5, 0)])
+                                           ("team-sizes", 3, 1, 0), ("knapsack-small", 3, 5, 0),
+                                           ("coded-raw", 2, 1, 4)])
 def test_unrolled_gradient_matches_oracle(orc, case, T, K, seed):
     p = CASES[case]()
     rng = np.random.default_rng(seed)
@@ -340,7 +342,8 @@ def test_stored_trajectory_too_large_is_rejected():
     assert inst.lower_bound()[0] == lb  # nothing ran
 
 
-@pytest.mark.parametrize("case", ["knapsack-small", "team-sizes", "wide-24", "wide-32", "wide-64", "unit-rows"])
+@pytest.mark.parametrize("case", ["knapsack-small", "team-sizes", "wide-24", "wide-32", "wide-64", "unit-rows",
+                                  "coded-raw"])
 def test_dense_routing_matches_listed_routing(case):
     """The reverse sweeps of one-wave diagrams route a level's nonzero adjoints through a per-level
     list, and a level whose list would overflow node by node from the owning lanes; the option

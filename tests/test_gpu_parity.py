@@ -12,7 +12,8 @@ import numpy as np
 import pytest
 
 import synth
-from tests.gpu_util import assert_close_scaled, host, make_instance, row_scale, say, wide_class_problem
+from tests.gpu_util import (assert_close_scaled, coded_and_raw_problem, host, make_instance, row_scale, say,
+                            wide_class_problem)
 
 pytestmark = pytest.mark.gpu
 
@@ -137,6 +138,28 @@ def test_single_pass_parity_every_wide_class(orc, rmax):
     sc = row_scale(p, lbar)
     assert_close_scaled(m0g, m0o, sc, RTOL, f"class{rmax} m0")
     assert_close_scaled(m1g, m1o, sc, RTOL, f"class{rmax} m1")
+
+
+def test_single_pass_parity_byte_coded_and_raw_levels(orc):
+    """One-wave levels read in byte codes next to levels read in 4-byte codes, in one launch: passes,
+    the bound sweep and the min-marginal query against the oracle."""
+    p = coded_and_raw_problem()
+    rng = np.random.default_rng(41)
+    ah = rng.normal(0, 0.2, size=p.nnz)
+    say(f"byte-coded and raw levels E={p.nnz}")
+    inst = check_passes(orc, p, synth.sigmoid(rng.normal(size=p.nnz)), ah, 6, "coded-raw")
+    st = inst.stats
+    assert st["coded_levels"] > 0 and st["raw_levels"] > 0, st
+    lam, M = (host(t) for t in inst.get_state())
+    lb_g, dl_g = inst.lower_bound()
+    assert lb_g == pytest.approx(orc.lower_bound(p, orc.softmax_alpha(p, f32(ah)), lam, M)[0], rel=LB_RTOL)
+    assert dl_g <= lb_g + 1e-6 * abs(lb_g)
+    lbar = host(inst.get_state(flushed=True)[0])
+    m0g, m1g = (host(t) for t in inst.min_marginals())
+    m0o, m1o = orc.min_marginals(p, lbar)
+    sc = row_scale(p, lbar)
+    assert_close_scaled(m0g, m0o, sc, RTOL, "coded-raw m0")
+    assert_close_scaled(m1g, m1o, sc, RTOL, "coded-raw m1")
 
 
 def test_single_pass_parity_every_team_size(orc):
