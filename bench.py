@@ -27,7 +27,7 @@ TRAFFIC_JSON = os.path.join(HERE, "profiles", "traffic_knapsack_2M_vars.json")
 def kernel_sources_sha256():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "adjoint.hip"):
+    for f in ("kernels.hip", "adjoint.hip", "device_common.hpp", "kernels.hpp"):
         h.update(open(os.path.join(HERE, "paper_2205_11638_amd", "csrc", f), "rb").read())
     return h.hexdigest()
 

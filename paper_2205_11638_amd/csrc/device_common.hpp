@@ -228,15 +228,18 @@ __device__ __forceinline__ void child_codes(const uint32_t (&cw)[QM], uint32_t c
         for (int q = 0; q < Q; ++q) t[q] = ld4(traw, l16 + q * 1024);
         return;
     }
-    uint32_t base = cb;
+    uint32_t base = cb, k8 = 8, k16 = 16;
+    // shift counts the compiler cannot see: it would fold the shifts and adds into a multiply by
+    // 0x01010101, a quarter-rate instruction, instead of two shift-and-adds
+    __asm__ volatile("" : "+s"(k8), "+s"(k16));
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
         const uint32_t w = cw[q];
         uint32_t wl = w & 0x0F0F0F0Fu, wh = (w >> 4) & 0x0F0F0F0Fu;
-        wl += wl << 8;
-        wl += wl << 16;
-        wh += wh << 8;
-        wh += wh << 16;
+        wl += wl << k8;
+        wl += wl << k16;
+        wh += wh << k8;
+        wh += wh << k16;
         const uint32_t tot = (wl >> 24) | ((wh >> 24) << 16);
         const uint32_t inc = wave_incl_sum(tot);
         const uint32_t x = base + inc - tot;
