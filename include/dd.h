@@ -214,7 +214,10 @@ int dd_set_costs(dd_instance *h, const float *c, void *stream);
  * memory is short; the arrays stay allocated with the instance for later calls).
  * Records what dd_backward needs; any later call that changes the state (a pass, reset,
  * set_state, set_params, set_costs) invalidates the record.  With checkpoints, the deferred sums
- * S of every pass are kept too (2T arrays of n floats) for the recomputed segments.  The launches
+ * S of every pass are kept too (2T arrays of n floats) for the recomputed segments, and when the
+ * 2K + 1 node-cost arrays that dd_backward recomputes a segment into fit on the device, the last
+ * segment runs with the recording passes straight into them (same bits), so that dd_backward
+ * does not recompute it; the final B is then copied back to the instance.  The launches
  * after the reset are captured into a HIP graph the first time (T, ckpt_every) is seen with the
  * same buffers and replayed afterwards (not while profiling or with no_graphs); results are the
  * same bits either way. */
@@ -237,8 +240,10 @@ int dd_forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *l
 int dd_backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *d_c, void *stream);
 
 /* Test hook for the checkpoint verification: adds 1 to the first multiplier slot of checkpoint
- * `index` (0 .. ceil(T / K)) of the recorded checkpointed forward, so that the next dd_backward returns
- * DD_E_CHECKPOINT.  DD_E_STATE without such a record.  Synchronizes the device. */
+ * `index` (0 .. ceil(T / K)) of the recorded checkpointed forward, so that the next dd_backward that
+ * reads it returns DD_E_CHECKPOINT (every checkpoint is verified when it is read; the start of a
+ * last segment that the forward kept is read only by a second dd_backward of the same record).
+ * DD_E_STATE without such a record.  Synchronizes the device. */
 int dd_corrupt_checkpoint(dd_instance *h, int32_t index);
 
 /* Serial number of the recorded unrolled forward, for callers that hold several records of one

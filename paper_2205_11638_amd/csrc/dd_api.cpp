@@ -1435,20 +1435,27 @@ int stored_alloc(dd_instance *h, int n) {
 // n iterations from the current state, with B at that state already in trB[0]: forward pass t
 // writes F into trF[t] and its backward pass B into trB[t + 1] (the tables are re-pointed), every
 // pass records its argmins, and the state before every pass is kept.  The tables are left on the
-// last arrays.  Sp (or NULL): the S of each of the 2n passes, when a forward already formed them.
-int stored_passes(dd_instance *h, int n, hipStream_t s, float *const *Sp = nullptr) {
+// last arrays.  Sp (or NULL): the S of each of the 2n passes, when a forward already formed them;
+// S_out (or NULL): where the passes put the S they form, for a later recomputation.
+int stored_passes(dd_instance *h, int n, hipStream_t s, float *const *Sp = nullptr, float *const *S_out = nullptr) {
+    float *own_S = h->S;
+    auto pass = [&](int dir, int p) {
+        if (S_out) {
+            h->S = S_out[p];
+            h->T.S = S_out[p];
+        }
+        const int r = run_pass_rec(h, dir, s, h->tr_mrec[p], h->tr_mdiff[p], h->tr_Se[p], Sp ? Sp[p] : nullptr);
+        h->S = own_S;
+        h->T.S = own_S;
+        return r;
+    };
     int st = save_state(h, h->tr_lam, h->tr_M, 0, s);
     for (int t = 0; t < n && st == DD_OK; ++t) {
         use_F(h, h->trF[t], h->trFp[t]);
         use_B(h, h->trB[t], h->trBc[t]);
-        if ((st = run_pass_rec(h, 0, s, h->tr_mrec[2 * t], h->tr_mdiff[2 * t], h->tr_Se[2 * t],
-                               Sp ? Sp[2 * t] : nullptr)) ||
-            (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s)))
-            break;
+        if ((st = pass(0, 2 * t)) || (st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 1, s))) break;
         use_B(h, h->trB[t + 1], h->trBc[t + 1]);
-        if ((st = run_pass_rec(h, 1, s, h->tr_mrec[2 * t + 1], h->tr_mdiff[2 * t + 1], h->tr_Se[2 * t + 1],
-                               Sp ? Sp[2 * t + 1] : nullptr)))
-            break;
+        if ((st = pass(1, 2 * t + 1))) break;
         st = save_state(h, h->tr_lam, h->tr_M, 2 * (size_t)t + 2, s);
     }
     return st;
@@ -1520,6 +1527,7 @@ int forward_stored(dd_instance *h, int32_t T, double *lb, bool from_state, void 
     h->fwd_T = T;
     h->fwd_K = -1;
     h->fwd_stored = true;
+    h->fwd_last_stored = false;
     h->fwd_from_state = from_state;
     h->fwd_version = h->version;
     h->fwd_serial++;
@@ -1555,8 +1563,14 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
         if ((st = h->alloc(&p, (size_t)std::max<int64_t>(h->n, 1)))) return st;
         h->fwd_S.push_back(p);
     }
+    // When the device holds a stored run of K iterations (the arrays the backward sweep recomputes
+    // each segment into), the last segment runs with the recording passes straight into them: the
+    // backward sweep then reverses it without recomputing it.  Same arithmetic, same bits.
+    const int t_last = (nseg - 1) * K;
+    const bool pre = nseg > 0 && !h->adj_replay && stored_fits(h, K) && stored_alloc(h, K) == DD_OK &&
+                     reserve_states(h, h->tr_lam, h->tr_M, 2 * (size_t)K + 1) == DD_OK;
     // T iterations with a checkpoint (state and fingerprint) every K and one of the final state
-    st = replayed(h, {2, T, K}, s, [&](hipStream_t q) {
+    st = replayed(h, {2, T, K, (int64_t)pre}, s, [&](hipStream_t q) {
         auto checkpoint = [&](size_t i) {
             int r = save_state(h, h->ck_lam, h->ck_M, i, q);
             return r ? r : state_hash(h, h->ck_lam[i], h->ck_M[i], h->ck_hash + i, q);
@@ -1565,6 +1579,18 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
         int r = DD_OK;
         for (int t = 0; t < T && r == DD_OK; ++t) {
             if (t % K == 0 && (r = checkpoint((size_t)(t / K)))) break;
+            if (pre && t == t_last) {
+                float *own_F = h->T.F, *own_B = h->T.B;
+                uint16_t *own_Fp = h->T.Fpar, *own_Bc = h->T.Bch;
+                h->S = own_S;
+                h->T.S = own_S;
+                use_B(h, h->trB[0], h->trBc[0]);  // B at the checkpoint, with its argmin codes
+                r = recompute_B(h, q);
+                if (r == DD_OK) r = stored_passes(h, T - t_last, q, nullptr, h->fwd_S.data() + 2 * (size_t)t_last);
+                use_F(h, own_F, own_Fp);
+                use_B(h, own_B, own_Bc);
+                break;
+            }
             for (int d = 0; d < 2 && r == DD_OK; ++d) {
                 h->S = h->fwd_S[2 * (size_t)t + d];  // the pass's deferred sums go here
                 h->T.S = h->S;
@@ -1576,9 +1602,17 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
         return r ? r : checkpoint((size_t)nseg);
     });
     if (st) return st;
+    if (pre) {
+        // the instance's own B takes the final B (its own F was not written by the recorded passes)
+        const size_t bytes = ((size_t)h->node_slots + 64) * sizeof(float);
+        HIP_TRY(hipMemcpyAsync(h->T.B, h->trB[T - t_last], bytes, hipMemcpyDeviceToDevice, s));
+        h->b_valid = true;
+        h->f_valid = false;
+    }
     if ((st = dd_lower_bound(h, lb, nullptr, stream))) return st;
     h->fwd_T = T;
     h->fwd_K = K;
+    h->fwd_last_stored = pre;
     h->fwd_from_state = from_state;
     h->fwd_version = h->version;
     h->fwd_serial++;
@@ -1588,7 +1622,7 @@ int forward_unrolled(dd_instance *h, int32_t T, int32_t ckpt_every, double *lb, 
 // The launches of the backward sweep up to the adjoints of the start state (in dlamA / dMA: every pass
 // adjoint swaps the buffer pairs, and there are 2T of them); d_alpha and d_omega accumulate in the
 // slot-ordered dalpha / domega.  The seed is read from seed_dev.
-int backward_core(dd_instance *h, int T, int K, bool stored, bool seg_store, hipStream_t s) {
+int backward_core(dd_instance *h, int T, int K, bool stored, bool seg_store, bool last_stored, hipStream_t s) {
     const int nseg = (T + K - 1) / K;
     int st;
     // adjoint of the lower bound at the final state: dLB / dlambda_bar_j = argmin assignment of row j
@@ -1633,6 +1667,14 @@ int backward_core(dd_instance *h, int T, int K, bool stored, bool seg_store, hip
     uint16_t *own_Fp = h->T.Fpar, *own_Bc = h->T.Bch;
     for (int seg = stored ? -1 : nseg - 1; seg >= 0; --seg) {
         const int t0 = seg * K, t1 = std::min(T, t0 + K), np = 2 * (t1 - t0);
+        if (last_stored && seg == nseg - 1) {
+            // the unrolled forward ran this segment into the stored arrays
+            st = stored_reverse(h, t1 - t0, dl, dm, dl2, dm2, s);
+            use_F(h, own_F, own_Fp);
+            use_B(h, own_B, own_Bc);
+            if (st) return st;
+            continue;
+        }
         if ((st = load_state(h, h->ck_lam, h->ck_M, (size_t)seg, s))) return st;
         if ((st = verify_state(h, h->T.lam, h->T.M, (size_t)seg, s))) return st;
         if (seg_store) {
@@ -1692,13 +1734,18 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     int st;
     // the buffers of the launch sequence, allocated beforehand
     if (!h->seed_dev && (st = h->alloc(&h->seed_dev, 1))) return st;
-    const bool seg_store = !stored && !h->adj_replay && nseg > 0 && stored_fits(h, K) && stored_alloc(h, K) == DD_OK;
+    const bool last_stored = !stored && h->fwd_last_stored;
+    const bool seg_store =
+        last_stored || (!stored && !h->adj_replay && nseg > 0 && stored_fits(h, K) && stored_alloc(h, K) == DD_OK);
     if (!stored && !seg_store && (st = reserve_states(h, h->seg_lam, h->seg_M, 2 * (size_t)K))) return st;
     if (seg_store && (st = reserve_states(h, h->tr_lam, h->tr_M, 2 * (size_t)K + 1))) return st;
     HIP_TRY(launch_fill(h->seed_dev, seed, 1, s));
     if (!stored) HIP_TRY(launch_fill((float *)h->ck_flag, 0.f, 1, s));
-    st = replayed(h, {3, T, K, stored, seg_store}, s,
-                  [&](hipStream_t q) { return backward_core(h, T, K, stored, seg_store, q); });
+    st = replayed(h, {3, T, K, stored, seg_store, last_stored}, s,
+                  [&](hipStream_t q) { return backward_core(h, T, K, stored, seg_store, last_stored, q); });
+    // the other segments were recomputed into the same arrays: a later backward sweep of this forward
+    // recomputes the last one too
+    if (nseg > 1) h->fwd_last_stored = false;
     if (st) return st;
     float *dl = h->dlamA, *dm = h->dMA;
     // lambda_0 = c / |J_i|

@@ -100,6 +100,7 @@ struct dd_instance {
     uint16_t *Fpar0 = nullptr, *Bch0 = nullptr;
     std::vector<uint16_t *> trFp, trBc;
     bool fwd_stored = false;
+    bool fwd_last_stored = false;  // the checkpointed forward ran its last segment into the stored arrays
     int fwd_T = -1, fwd_K = 0;
     bool fwd_from_state = false;  // the recorded forward started from a given state (no reset)
     int64_t version = 0, fwd_version = -1;  // the recorded forward is valid while the state is unchanged

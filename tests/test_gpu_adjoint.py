@@ -612,6 +612,9 @@ def test_backward_is_linear_in_the_seed_and_checkpoint_free():
     g3 = [host(t) for t in inst.backward(1.0)]
     for a, b in zip(g1, g3):
         np.testing.assert_array_equal(a, b)
+    g4 = [host(t) for t in inst.backward(1.0)]  # one segment kept by the forward: read again
+    for a, b in zip(g1, g4):
+        np.testing.assert_array_equal(a, b)
 
 
 def test_backward_needs_a_recorded_forward():

@@ -54,10 +54,10 @@ def test_device_memory_cap():
 
 @pytest.mark.parametrize("replay", [False, True])
 def test_checkpoint_verification(replay):
-    """The backward sweep checks every checkpoint against the fingerprint taken when it was saved,
-    and the state each recomputed segment ends in against the next checkpoint's: a checkpoint changed
-    after the forward (the test hook adds 1 to one slot) fails with DD_E_CHECKPOINT; an intact record
-    passes and gives the gradients of a fresh instance."""
+    """The backward sweep checks every checkpoint it reads against the fingerprint taken when it was
+    saved, and the state each recomputed segment ends in against the next checkpoint's: a checkpoint
+    changed after the forward (the test hook adds 1 to one slot) fails with DD_E_CHECKPOINT; an intact
+    record passes and gives the gradients of a fresh instance."""
     import paper_2205_11638_amd as dd
     p, om, ah = _gm()
     inst, _, _ = make_instance(p, om, ah, adj_replay=replay)
@@ -70,6 +70,17 @@ def test_checkpoint_verification(replay):
         with pytest.raises(dd.DDError) as e:
             inst.backward(1.0)
         assert e.value.code == dd.binding.DD_E_CHECKPOINT, index
+    # the last segment's start: without replays the forward keeps that segment's records, so the
+    # first backward sweep does not read the checkpoint and the second one (which recomputes it) does
+    inst.forward_unrolled(6, 2)
+    inst.corrupt_checkpoint(2)
+    if not replay:
+        g = [host(t) for t in inst.backward(1.0)]
+        for a, b in zip(g, g_ref):
+            np.testing.assert_array_equal(a, b)
+    with pytest.raises(dd.DDError) as e:
+        inst.backward(1.0)
+    assert e.value.code == dd.binding.DD_E_CHECKPOINT
     inst.forward_unrolled(6, 2)
     g = [host(t) for t in inst.backward(1.0)]
     for a, b in zip(g, g_ref):
@@ -140,8 +151,10 @@ def test_captured_sequences_equal_eager_launches(case, T, K, replay):
         e.run(1)
         assert g.lower_bound()[0] == e.lower_bound()[0]
     if K > 0:
+        # the first segment's start (the last segment's start is read only when that segment is
+        # recomputed, which the forward's kept records make unnecessary the first time)
         g.forward_unrolled(T, K)
-        g.corrupt_checkpoint(1)
+        g.corrupt_checkpoint(0)
         with pytest.raises(dd.DDError) as err:
             g.backward(1.0)
         assert err.value.code == dd.binding.DD_E_CHECKPOINT
