@@ -614,7 +614,7 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
 template <int Q, int RMAX, int MODE>
 __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t Cr, rsrc_t lam_r, rsrc_t M_r,
                                           rsrc_t rec_r, rsrc_t md_r, const float *bn, float *bc,
-                                          const uint32_t (&cw)[RMAX / 4], uint32_t cb, rsrc_t traw,
+                                          const u32x4 (&tp)[RMAX / 4],
                                           const f32x4 (&fn)[RMAX / 4], int lane, int out, const Lev &c0, int Wn,
                                           float lam, float om, float aS, int ce) {
     constexpr bool REC = MODE == BWD_UPDATE_REC, UPD = MODE == BWD_UPDATE || REC, MM = MODE == BWD_MM;
@@ -624,7 +624,8 @@ __device__ __forceinline__ void bwd_hop_w(const DevTables &T, rsrc_t Br, rsrc_t 
     const int l16 = lane16(lane);
     u32x4 t[Q];
     f32x4 b0[Q], b1[Q];
-    child_codes<Q>(cw, cb, Wn == 0, traw, lane, t);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) t[q] = tp[q];
     const int rem = c0.W - (Q - 1) * 256 - lane * 4;
     const uint32_t dead = (uint32_t)Wn | ((uint32_t)Wn << 16);
 #pragma unroll
@@ -737,8 +738,23 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
         const int out0 = lane * nlev * 4;  // hop l stores at out0 + 4 l: in range for lane 0 only
         Lev c0 = level(nlev - 1), cp = level(nlev - 2);  // levels l, l-1
         int Wn = 0;                                       // width of level l+1 (none below the last)
-        uint32_t cwn[QM], cbn = T.lev_code[tc.lbase + nlev - 1];  // byte codes of the level's topology
+        // byte codes of the level's topology (prefetched one hop ahead) and the child codes they
+        // decode to (decoded at the end of the hop before, while its LDS stores complete)
+        uint32_t cwn[QM], cbn = T.lev_code[tc.lbase + nlev - 1];
+        u32x4 tpn[QM];
         f32x4 fn[QM];
+        // decode the prefetched codes of level c (whose next level has Wc nodes) into tpn
+        auto decode = [&](const Lev &c, int Wc) {
+            const rsrc_t traw = buf(T.topo + c.base, row_bytes(c));
+            const uint32_t cb = uni((int)cbn);
+            with_count<1, QM>(groups(c), [&](auto qc) {
+                constexpr int QQ = decltype(qc)::value;
+                u32x4 t[QQ];
+                child_codes<QQ>(cwn, cb, Wc == 0, traw, lane, t);
+#pragma unroll
+                for (int q = 0; q < QQ; ++q) tpn[q] = t[q];
+            });
+        };
         {
             const int l16 = lane16(lane);
             const rsrc_t cr = buf(T.tcode + c0.base, code_row_bytes(c0)), fr = buf(T.F + c0.base, row_bytes(c0));
@@ -748,6 +764,7 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
                 fn[q] = NEEDF ? ld4f(fr, l16 + q * 1024) : zero4;
             }
         }
+        decode(c0, 0);
         const int et = tc.ebase + nlev - 1;
         float lamn = T.lam[et], aSn = (UPD || BAR) ? T.aS[et] : 0.f, omn = UPD ? T.omega[et] : 0.f;
         int cen = MM ? T.slot2canon[et] : 0;  // canonical edge of the min-marginals
@@ -760,12 +777,11 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
         for (int l = nlev - 1; l >= 0; --l) {
             const float lam = lamn, om = omn, aS = aSn;
             const int ce = cen;
-            uint32_t cw[QM];
-            const uint32_t cb = uni((int)cbn);
+            u32x4 tp[QM];
             f32x4 fv[QM];
 #pragma unroll
             for (int q = 0; q < QM; ++q) {
-                cw[q] = cwn[q];
+                tp[q] = tpn[q];
                 fv[q] = fn[q];
             }
             const float *bn = buf0 + cur * NB;
@@ -789,11 +805,11 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
             const rsrc_t Br = buf(T.B + c0.base, node_bytes(c0));
             const rsrc_t Cr = buf(T.Bch ? (const void *)(T.Bch + c0.base) : (const void *)T.B,
                                   T.Bch ? code_bytes(c0) : 0);  // no codes recorded: every store dropped
-            const rsrc_t traw = buf(T.topo + c0.base, row_bytes(c0));
             with_count<1, QM>(groups(c0), [&](auto qc) {
-                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, Cr, lam_r, M_r, rec_r, md_r, bn, bc, cw, cb, traw,
-                                                           fv, lane, out0 + 4 * l, c0, Wn, lam, om, aS, ce);
+                bwd_hop_w<decltype(qc)::value, RMAX, MODE>(T, Br, Cr, lam_r, M_r, rec_r, md_r, bn, bc, tp, fv, lane,
+                                                           out0 + 4 * l, c0, Wn, lam, om, aS, ce);
             });
+            if (l > 0) decode(cp, c0.W);
             wave_sync();
             cur ^= 1;
             Wn = c0.W;
