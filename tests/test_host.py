@@ -92,6 +92,40 @@ def test_known_shapes(dd):
         assert max(w) <= rhs + 2                      # states are partial sums 0..b plus "always feasible"
 
 
+@pytest.mark.parametrize("seed", range(12))
+def test_child_codes_are_monotone_in_partial_sum_order(dd, seed):
+    """Nodes of a level are numbered in increasing partial sum (the always-true node of a <= row
+    first), so on <= rows -- with coefficients of both signs -- each level's lo and hi child codes are
+    non-decreasing in the node number, the 0-terminal (code = next width) after every node; on the
+    last level the codes (0 = 0-terminal, 1 = 1-terminal) are non-increasing.  The one-wave passes
+    read the steps of these codes in one nibble each (4-byte codes where a step does not fit)."""
+    rng = np.random.default_rng(seed)
+    rows, n = [], 60
+    for _ in range(6):
+        k = int(rng.integers(3, 40))
+        a = rng.integers(-8 if seed % 3 == 0 else 1, 21, size=k)
+        a[a == 0] = 1
+        lo, hi = int(np.minimum(a, 0).sum()), int(np.maximum(a, 0).sum())
+        rows.append((rng.choice(n, size=k, replace=False), a, -1, int(rng.integers(lo + (hi - lo) // 4, hi - (hi - lo) // 4 + 1))))
+    p = synth.generators._from_rows(n, np.zeros(n), rows, "le-rows")
+    steps = 0
+    for j in range(p.m):
+        try:
+            width, arcs = dd.compile_row(p, j)
+        except Exception:
+            continue  # a forcing or infeasible draw
+        start = 0
+        for l, w in enumerate(width):
+            lvl = arcs[start:start + w].astype(np.int64)
+            start += w
+            last = l + 1 == len(width)
+            for c in (lvl & 0xFFFF, lvl >> 16):
+                d = np.diff(-c if last else c)
+                assert np.all(d >= 0), (j, l)
+                steps += d.size
+    assert steps > 0
+
+
 def _one_row(coefs, sense, rhs, n=None):
     n = n or len(coefs)
     return synth.generators._from_rows(n, np.zeros(n), [(np.arange(len(coefs)), np.array(coefs), sense, rhs)], "r")
