@@ -378,9 +378,11 @@ __global__ __launch_bounds__(256) void k_bwd(DevTables T, int64_t tile0, int64_t
 // One-wave diagrams (P = 64): the same passes, laid out for wide memory operations.
 // ------------------------------------------------------------------------------------------
 // Each lane owns 4 consecutive nodes of a group of 256 (node k = 256 q + 4 lane + j), so
-// every row of topology, F or B moves with one 16-byte access per lane: a quarter of the
-// memory instructions of one node per lane, whose address processing, not HBM, would
-// otherwise bound the pass.  Levels of these tiles start at multiples of 4 nodes.
+// every row of F or B moves with one 16-byte access per lane and a row of byte-coded child
+// codes with one 4-byte access (decoded by child_codes; the 4-byte codes of a level without
+// byte codes with one 16-byte access): a quarter of the memory instructions of one node per
+// lane, whose address processing, not HBM, would otherwise bound the pass.  Levels of these
+// tiles start at multiples of 4 nodes.
 // A hop branches once on its level's group count Q (a binary tree of scalar compares) into a
 // body unrolled over exactly Q groups, so no group carries a predicate of its own.  Node
 // buffers hold RMAX rows of 64 and 64 more slots: clears and staged groups cover all RMAX
@@ -574,7 +576,7 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
                     Bst[c1.W + 1] = 0.f;
                 }
             }
-            // prefetch: topology of l+1, B of l+2, edge data of l+1 (the last hop reloads its own)
+            // prefetch: byte codes of l+1, B of l+2, edge data of l+1 (the last hop reloads its own)
             auto prefetch = [&](int l16) {
                 const rsrc_t cr = buf(T.tcode + c1.base, code_row_bytes(c1)), br = buf(T.B + c2.base, row_bytes(c2));
 #pragma unroll
