@@ -571,6 +571,7 @@ def main():
         log("[bench] CPU oracle baseline ...")
         cpu = cpu_baseline(prob, w, inst.row_nodes())
         log(f"[bench] cpu baseline {cpu}")
+    traffic = counted_traffic(dom, prob.name)
     out = {
         "metric": "BDD arcs/s per dual iteration (% HBM peak); fwd+bwd unroll vs plain fwd time",
         "value": value,
@@ -588,8 +589,12 @@ def main():
                    "arcs": arcs, "iterations_per_step": T, "step": "T dual iterations + lower bound",
                    "launch_shapes": inst.launch_shapes()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counted_traffic(dom, prob.name),
-                     "algorithmic_bytes_per_launch": b_dom, "avg_launch_ms": tot_dom / n_dom,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "algorithmic_bytes_per_launch": b_dom,
+                     "bytes_model": "update pass: 12 B/node (4-byte child codes, F or B read and written) + "
+                                    "28 B/edge; the passes read byte-coded child codes, so they move less",
+                     "traffic_gbs": traffic / (tot_dom / n_dom) / 1e6 if traffic else None,
+                     "avg_launch_ms": tot_dom / n_dom,
                      "stream_reference_gbs": stream_gbs, "frac_of_stream_reference": achieved / stream_gbs},
         "hbm_frac_step": (sum(b * n for n, _, b in prof.values()) / args.steps) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS,
         "lower_bound": lb[0],
