@@ -150,6 +150,7 @@ struct HostPlan {
     // edges
     std::vector<int32_t> canon2slot, slot2canon, evar;
     std::vector<int32_t> var_ptr, var_slots, var_canon;
+    std::vector<int32_t> var_perm;  // the library's number of each variable (see build_plan)
 };
 
 }  // namespace
@@ -383,15 +384,30 @@ int build_plan(const dd_problem *p, const SortedRows &sr, const std::vector<RowB
             }
         }
     }
+    // The library numbers the variables in the order they first appear in the edge slots (variables in
+    // no row last): the per-variable sums handle consecutive numbers side by side, and a variable's
+    // first edge then lies near those of its neighbours in the slot range, as do the S values that
+    // the per-slot gathers read.  Per-variable arrays at the boundary (c, d_c) are mapped through
+    // var_perm; every sum over a variable's edges keeps the canonical order.
+    hp.var_perm.assign((size_t)p->n, -1);
+    int32_t next = 0;
+    for (int64_t slot = 0; slot < edge_slots; ++slot) {
+        const int32_t v = hp.evar[slot];
+        if (v >= 0 && hp.var_perm[v] < 0) hp.var_perm[v] = next++;
+    }
+    for (int v = 0; v < p->n; ++v)
+        if (hp.var_perm[v] < 0) hp.var_perm[v] = next++;
+    for (int64_t slot = 0; slot < edge_slots; ++slot)
+        if (hp.evar[slot] >= 0) hp.evar[slot] = hp.var_perm[hp.evar[slot]];
     // variable -> edges (canonical order within a variable: rows ascending)
     hp.var_ptr.assign((size_t)p->n + 1, 0);
-    for (int64_t e = 0; e < E; ++e) hp.var_ptr[sr.col[e] + 1]++;
+    for (int64_t e = 0; e < E; ++e) hp.var_ptr[hp.var_perm[sr.col[e]] + 1]++;
     for (int v = 0; v < p->n; ++v) hp.var_ptr[v + 1] += hp.var_ptr[v];
     hp.var_slots.assign((size_t)E, 0);
     hp.var_canon.assign((size_t)E, 0);
     std::vector<int32_t> fill(hp.var_ptr.begin(), hp.var_ptr.end() - 1);
     for (int64_t e = 0; e < E; ++e) {
-        const int v = sr.col[e];
+        const int v = hp.var_perm[sr.col[e]];
         hp.var_canon[fill[v]] = (int32_t)e;
         hp.var_slots[fill[v]++] = hp.canon2slot[e];
     }
@@ -704,14 +720,15 @@ int create_grouped(const dd_problem *prob, const dd_options *opt, void *stream, 
         for (int64_t e = sr.ptr[j]; e < sr.ptr[j + 1]; ++e) h->edge_row[e] = j;
     std::vector<float> c32((size_t)prob->n), om((size_t)h->E), al((size_t)h->E);
     for (int i = 0; i < prob->n; ++i) {
-        c32[i] = (float)prob->c[i];
-        if (hp.var_ptr[i + 1] == hp.var_ptr[i]) {
+        const int v = hp.var_perm[i];
+        c32[v] = (float)prob->c[i];
+        if (hp.var_ptr[v + 1] == hp.var_ptr[v]) {
             h->uncovered++;
             if (prob->c[i] < 0) h->unc_const += prob->c[i];
         }
     }
     for (int64_t e = 0; e < h->E; ++e) {
-        const int v = sr.col[e];
+        const int v = hp.var_perm[sr.col[e]];
         om[e] = 0.5f;
         al[e] = 1.0f / (float)(hp.var_ptr[v + 1] - hp.var_ptr[v]);
     }
@@ -752,6 +769,7 @@ int create_grouped(const dd_problem *prob, const dd_options *opt, void *stream, 
     TRY(upload(h, (int32_t **)&T.slot2canon, hp.slot2canon, s));
     TRY(upload(h, &h->canon2slot, hp.canon2slot, s));
     TRY(upload(h, &h->var_ptr, hp.var_ptr, s));
+    TRY(upload(h, &h->var_perm, hp.var_perm, s));
     // lanes per variable in the per-variable sums: one constant, so that a program gets the same bits
     // alone and packed into a batch with programs of other degrees
     h->var_team = dd_instance::kVarTeam;
@@ -1749,7 +1767,10 @@ int backward(dd_instance *h, double dlb, float *d_omega, float *d_alpha, float *
     if (st) return st;
     float *dl = h->dlamA, *dm = h->dMA;
     // lambda_0 = c / |J_i|
-    if (d_c) HIP_TRY(launch_dc(h->var_ptr, h->var_slots, dl, h->cdev, seed, d_c, (int)h->n, s));
+    if (d_c) {  // per variable in the library's order, then in the caller's
+        HIP_TRY(launch_dc(h->var_ptr, h->var_slots, dl, h->cdev, seed, h->scratch_n, (int)h->n, s));
+        HIP_TRY(launch_gather(h->var_perm, h->scratch_n, d_c, h->n, nullptr, s));
+    }
     if (d_lam0) HIP_TRY(launch_gather(h->canon2slot, dl, d_lam0, h->E, nullptr, s));
     if (d_M0) HIP_TRY(launch_gather(h->canon2slot, dm, d_M0, h->E, nullptr, s));
     if (d_omega) HIP_TRY(launch_gather(h->canon2slot, h->domega, d_omega, h->E, nullptr, s));
@@ -1917,7 +1938,7 @@ int dd_set_costs(dd_instance *h, const float *c, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     int st = adj_alloc(h);
     if (st) return st;
-    HIP_TRY(hipMemcpyAsync(h->cdev, c, sizeof(float) * h->n, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(launch_scatter(h->var_perm, c, h->cdev, h->n, s));  // the library's variable order
     HIP_TRY(launch_uncovered(h->var_ptr, h->cdev, h->scratch_n, (int)h->n, s));
     HIP_TRY(launch_sum(h->scratch_n, h->n, 0, h->partial, h->red, s));
     HIP_TRY(hipMemcpyAsync(h->red_host, h->red, sizeof(double), hipMemcpyDeviceToHost, s));

@@ -63,6 +63,7 @@ struct dd_instance {
     std::vector<void *> allocs;
     DevTables T{};
     int32_t *var_ptr = nullptr, *var_slots = nullptr, *var_canon = nullptr, *canon2slot = nullptr;
+    int32_t *var_perm = nullptr;  // [n] the library's number of each variable (first appearance in slot order)
     float *cdev = nullptr, *S = nullptr, *aS = nullptr, *omega = nullptr, *alpha = nullptr, *tmp = nullptr;
     double *red = nullptr;   // device reduction output [4]
     double *partial = nullptr;  // [kSumBlocks] reduction scratch
