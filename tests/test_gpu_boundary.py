@@ -113,6 +113,34 @@ def test_run_trace_equals_bounds_between_runs():
     say("trace", tr)
 
 
+def test_set_costs_equals_a_fresh_instance():
+    """Replacing the costs (device array in the caller's variable order; the library keeps its own
+    order) gives the state and cost gradient of an instance created with those costs bit for bit, and
+    its bound -- uncovered variables included (the independent-set workload leaves some in no row)."""
+    import torch
+    for name in ("gm", "indset"):
+        w = synth.workload(name, small=True) if name == "gm" else {"problem": synth.independent_set(n=3000, M=4000, seed=5)}
+        p = w["problem"]
+        rng = np.random.default_rng(3)
+        c2 = rng.normal(size=p.n)
+        p2 = synth.Problem(p.n, c2, p.row_ptr, p.col, p.coef, p.sense, p.rhs)
+        a, _, _ = make_instance(p)
+        b, _, _ = make_instance(p2)
+        a.set_costs(torch.tensor(c2, dtype=torch.float32, device="cuda"))
+        a.run(3)
+        b.run(3)
+        for x, y in zip(a.get_state(), b.get_state()):
+            np.testing.assert_array_equal(host(x), host(y))
+        # the constant of the uncovered variables: a device sum of the f32 costs against a host sum of
+        # the f64 ones at create
+        assert a.lower_bound()[0] == pytest.approx(b.lower_bound()[0], rel=1e-9, abs=1e-9)
+        a.forward_unrolled(2, 1)
+        b.forward_unrolled(2, 1)
+        ga, gb = a.backward(1.0)[2], b.backward(1.0)[2]
+        np.testing.assert_array_equal(host(ga), host(gb))
+        say(f"set_costs {name}: n={p.n}, uncovered {a.stats['uncovered']}")
+
+
 def test_sizes():
     p, _, _ = _gm()
     inst, _, _ = make_instance(p)
