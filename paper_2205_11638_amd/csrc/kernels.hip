@@ -717,8 +717,10 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;
-    float *buf0 = lds_f + (size_t)wave * lds_words_pass_w(RMAX, NL);
-    int *meta = (int *)(buf0 + 2 * NB);
+    // one node buffer: a hop reads every child's B before it writes its own level's, in order, so
+    // B of level l replaces B of level l+1 in place (the terminals go after the level's width)
+    float *buf0 = lds_f + (size_t)wave * lds_words_bwd_w(RMAX, NL);
+    int *meta = (int *)(buf0 + NB);
     int *off = meta + NL;
     const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
     for (;;) {
@@ -770,8 +772,7 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
         const int et = tc.ebase + nlev - 1;
         float lamn = T.lam[et], aSn = (UPD || BAR) ? T.aS[et] : 0.f, omn = UPD ? T.omega[et] : 0.f;
         int cen = MM ? T.slot2canon[et] : 0;  // canonical edge of the min-marginals
-        int cur = 0;  // buffer holding B of level l+1 (terminals only, below the last level)
-        if (lane == 0) {
+        if (lane == 0) {  // below the last level: the terminals alone
             buf0[0] = kInf;
             buf0[1] = 0.f;
         }
@@ -786,8 +787,8 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
                 tp[q] = tpn[q];
                 fv[q] = fn[q];
             }
-            const float *bn = buf0 + cur * NB;
-            float *bc = buf0 + (cur ^ 1) * NB;
+            const float *bn = buf0;
+            float *bc = buf0;
             // prefetch level l-1 (the first level reloads its own edge data)
             {
                 const int l16 = lane16(lane);
@@ -813,13 +814,13 @@ __global__ __launch_bounds__(256) void k_bwd_w(DevTables T, int64_t tile0, int64
             });
             if (l > 0) decode(cp, c0.W);
             wave_sync();
-            cur ^= 1;
+            
             Wn = c0.W;
             c0 = cp;
             cp = level(l - 2);
         }
         if (!MM && lane == 0 && row >= 0) {
-            const float e0 = buf0[cur * NB];  // B(root) = E^j at the multipliers swept
+            const float e0 = buf0[0];  // B(root) = E^j at the multipliers swept
             if (BAR) T.energies[row] = e0;
             else T.en_lam[row] = e0;
         }
@@ -858,7 +859,7 @@ template <int RMAX>
 hipError_t bwd_dispatch_w(const DevTables &t, const ClassLaunch &c, int mode, hipStream_t s) {
     const unsigned full = full_grid(c.ntiles, c.wpb_b);
     dim3 grid(full), block(64 * c.wpb_b);
-    size_t lds = (size_t)c.wpb_b * lds_words_pass_w(RMAX, c.NL) * 4;
+    size_t lds = (size_t)c.wpb_b * lds_words_bwd_w(RMAX, c.NL) * 4;
     if (mode == BWD_UPDATE && c.grid_b > 0 && (unsigned)c.grid_b < full) {
         hipLaunchKernelGGL((k_bwd_w<RMAX, BWD_UPDATE, true>), dim3(c.grid_b), block, lds, s, t, c.tile0, c.ntiles, c.NL);
         return hipGetLastError();

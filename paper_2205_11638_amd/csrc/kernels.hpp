@@ -117,6 +117,8 @@ constexpr int lds_words_pass(int P, int WB, int NL) {  // constexpr: usable in d
 // wave's share is a multiple of 4 words, so 16-byte LDS accesses stay aligned.
 constexpr int node_buf_w(int RMAX) { return RMAX * 64 + 64; }
 constexpr int lds_words_pass_w(int RMAX, int NL) { return 2 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+// the one-wave backward kernels: one node buffer (updated in place) and the level table
+constexpr int lds_words_bwd_w(int RMAX, int NL) { return node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
 // The forward sweeps that record argmin parent codes keep the next level's costs as 64-bit keys
 // (cost, code): one node buffer more.
 constexpr int lds_words_pass_w_par(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
