@@ -981,12 +981,20 @@ __global__ __launch_bounds__(256) void k_adj_F_w(DevTables T, AdjTables A, int64
     }
 }
 
-__global__ void k_edge_S(const int32_t *__restrict__ evar, const float *__restrict__ S, float *__restrict__ Se,
-                         int64_t slots) {
-    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (e >= slots) return;
-    const int v = evar[e];
-    Se[e] = v >= 0 ? S[v] : 0.f;
+// Se[slot] = S[var(slot)], four slots per thread with the loads of a thread issued together, as in
+// k_edge_alpha_s.
+__global__ __launch_bounds__(256) void k_edge_S(const int32_t *__restrict__ evar, const float *__restrict__ S,
+                                                float *__restrict__ Se, int64_t slots) {
+    constexpr int K = kSlotsPerThread;
+    const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * (256 * K) + threadIdx.x;
+    int v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] = e0 + 256 * k < slots ? evar[e0 + 256 * k] : -1;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const float sv = v[k] >= 0 ? S[v[k]] : 0.f;
+        if (e0 + 256 * k < slots) Se[e0 + 256 * k] = sv;
+    }
 }
 
 // Adjoint of lambda_bar = lambda + alpha * S: dlambda stays, d_alpha += dlambda_bar * S_i,
@@ -1516,7 +1524,8 @@ hipError_t launch_adj(const DevTables &t, const AdjTables &a, const ClassLaunch 
 
 hipError_t launch_edge_S(const int32_t *evar, const float *S, float *Se, int64_t slots, hipStream_t s) {
     if (slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_S, dim3(xcd_grid(blocks_for(slots, 256))), dim3(256), 0, s, evar, S, Se, slots);
+    hipLaunchKernelGGL(k_edge_S, dim3(xcd_grid(blocks_for(slots, 256 * kSlotsPerThread))), dim3(256), 0, s, evar, S,
+                       Se, slots);
     return hipGetLastError();
 }
 

@@ -971,16 +971,34 @@ __global__ void k_deferred_sum(const int32_t *__restrict__ var_ptr, const int32_
     if (i < n && u == 0) S[i] = s;
 }
 
-// aS[slot] = alpha[slot] * S[var(slot)] over all edge slots (padding slots have var -1).
-__global__ void k_edge_alpha_s(const int32_t *__restrict__ evar, const float *__restrict__ alpha,
-                               const float *__restrict__ S, float *__restrict__ aS, float *__restrict__ Se,
-                               int64_t slots) {
-    const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-    if (e >= slots) return;
-    const int v = evar[e];
-    const float Sv = v >= 0 ? S[v] : 0.f;
-    aS[e] = v >= 0 ? alpha[e] * Sv : 0.f;
-    if (Se) Se[e] = Sv;
+// aS[slot] = alpha[slot] * S[var(slot)] over all edge slots (padding slots have var -1).  A
+// workgroup takes kSlotsPerThread * 256 consecutive slots, a thread every 256th of them: it issues
+// all of its variable loads, then all of its S gathers, so one round trip of each serves four slots
+// (a gather per thread left every wave waiting for two dependent round trips per slot).
+__global__ __launch_bounds__(256) void k_edge_alpha_s(const int32_t *__restrict__ evar,
+                                                      const float *__restrict__ alpha,
+                                                      const float *__restrict__ S, float *__restrict__ aS,
+                                                      float *__restrict__ Se, int64_t slots) {
+    constexpr int K = kSlotsPerThread;
+    const int64_t e0 = xcd_block(blockIdx.x, gridDim.x) * (256 * K) + threadIdx.x;
+    int v[K];
+    float a[K], sv[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t e = e0 + 256 * k;
+        v[k] = e < slots ? evar[e] : -1;
+        a[k] = e < slots ? alpha[e] : 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) sv[k] = v[k] >= 0 ? S[v[k]] : 0.f;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int64_t e = e0 + 256 * k;
+        if (e < slots) {
+            aS[e] = v[k] >= 0 ? a[k] * sv[k] : 0.f;
+            if (Se) Se[e] = sv[k];
+        }
+    }
 }
 
 __global__ void k_init_lambda(const int32_t *__restrict__ canon2slot, const int32_t *__restrict__ evar,
@@ -1227,7 +1245,8 @@ hipError_t launch_deferred_sum(const int32_t *var_ptr, const int32_t *var_slots,
 hipError_t launch_edge_alpha_s(const int32_t *evar, const float *alpha, const float *S, float *aS, float *Se,
                                int64_t slots, hipStream_t s) {
     if (slots <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_edge_alpha_s, dim3(xcd_grid(blocks_for(slots, 256))), dim3(256), 0, s, evar, alpha, S, aS, Se,
+    hipLaunchKernelGGL(k_edge_alpha_s, dim3(xcd_grid(blocks_for(slots, 256 * kSlotsPerThread))), dim3(256), 0, s, evar,
+                       alpha, S, aS, Se,
                        slots);
     return hipGetLastError();
 }

@@ -108,6 +108,8 @@ hipError_t launch_smooth(const DevTables &t, const ClassLaunch &c, float *Q, flo
 
 // Every kernel of the solver is compiled for workgroups of at most 256 threads (4 waves).
 constexpr int kMaxWavesPerBlock = 4;
+// edge slots per thread of the per-slot gathers of S (alpha * S, S per edge)
+constexpr int kSlotsPerThread = 4;
 
 constexpr int lds_words_pass(int P, int WB, int NL) {  // constexpr: usable in device code too
     return 2 * WB * (64 / P) + NL * ((64 / P) + 1);
