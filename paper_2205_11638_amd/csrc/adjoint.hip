@@ -1159,23 +1159,33 @@ inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b
 // the bidding sweeps above.
 // ------------------------------------------------------------------------------------------
 constexpr int lds_words_adjc_F_w(int RMAX, int NL) { return node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
-constexpr int lds_words_adjc_B_w(int RMAX, int NL) { return 2 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+// the pull sweep keeps one adjoint buffer: a hop reads its level's adjoints into registers before it
+// clears the buffer and routes them into the next level there, as the push sweep does
+constexpr int lds_words_adjc_B_w(int RMAX, int NL) { return node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
 
 template <int Q, int RMAX, bool UPD>
-__device__ __forceinline__ void adjcB_hop_w(float *ba0, float *ba1, const u32x2 (&cc)[RMAX / 4], int lane, int Wn,
+__device__ __forceinline__ void adjcB_hop_w(float *Ba, const u32x2 (&cc)[RMAX / 4], int lane, int Wn,
                                             const AdjIn<UPD> &x, const AdjOut &o, int l) {
+    constexpr int QM = RMAX / 4;
     const int l16 = lane16(lane);
+    f32x4 d[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) d[q] = lds4(Ba, l16 + q * 1024);  // adjoints of level l (0 past its width)
+    wave_sync();  // every adjoint of level l is read: the buffer collects level l+1
+    const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < QM; ++q) lds4(Ba, l16 + q * 1024) = zero4;
+    wave_sync();
     float hisum = 0.f;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const f32x4 d = lds4(ba0, l16 + q * 1024);  // slots past the level's width hold 0
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t code = code_at(cc[q], j);
             const int ch = (int)(code & 0x7FFFu);
-            if (d[j] != 0.f) {
-                if (ch < Wn) lds_fadd(&ba1[ch], d[j]);
-                if (code & 0x8000u) hisum += d[j];
+            if (d[q][j] != 0.f) {
+                if (ch < Wn) lds_fadd(&Ba[ch], d[q][j]);
+                if (code & 0x8000u) hisum += d[q][j];
             }
         }
     }
@@ -1188,8 +1198,8 @@ __device__ __forceinline__ void adjcB_hop_w(float *ba0, float *ba1, const u32x2 
         const float dM = x.dMo - dlam_new;
         const float dm1 = x.om * dM, dm0 = -dm1;
         wave_sync();  // after the routed adjoints (a fixed order of the float adds)
-        if (lane == 0 && r0 < Wn) lds_fadd(&ba1[r0], dm0);
-        if (lane == 0 && r1 < Wn) lds_fadd(&ba1[r1], dm1);
+        if (lane == 0 && r0 < Wn) lds_fadd(&Ba[r0], dm0);
+        if (lane == 0 && r1 < Wn) lds_fadd(&Ba[r1], dm1);
         st1(o.dlam_in, o.o4 + 4 * l, dlam_new + dm1);  // identity path + the hi arc of m^1 itself
         st1(o.g, o.o4 + 4 * l, dlam_new * x.al);
         st1(o.dalpha, o.o4 + 4 * l, x.da + dlam_new * x.S);
@@ -1209,8 +1219,8 @@ __global__ __launch_bounds__(256) void k_adjc_B_w(DevTables T, AdjTables A, int6
     const int wave = uni(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int64_t tile = tile0 + (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
     if (tile >= tile0 + ntiles) return;  // uniform per wave
-    float *Ba = lds_f + (size_t)wave * lds_words_adjc_B_w(RMAX, NL);
-    int *meta = (int *)(Ba + 2 * NB);
+    float *Ba = lds_f + (size_t)wave * lds_words_adjc_B_w(RMAX, NL);  // adjoints of level l, in place
+    int *meta = (int *)(Ba + NB);
     int *off = meta + NL;
     const TileCtx tc = tile_ctx(T, tile);
     preload_meta<1>(T, tc, lane, meta, off);
@@ -1231,7 +1241,6 @@ __global__ __launch_bounds__(256) void k_adjc_B_w(DevTables T, AdjTables A, int6
     const rsrc_t rv = buf(use_rec ? (const void *)(A.rec_val + 2 * (int64_t)tc.ebase) : (const void *)A.dlam_in,
                           use_rec ? nlev * 8 : 0);
     const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
-    int cur = 0;  // Ba + cur * NB: adjoints of level l
     {
         const int l16 = lane16(lane);
 #pragma unroll
@@ -1252,20 +1261,14 @@ __global__ __launch_bounds__(256) void k_adjc_B_w(DevTables T, AdjTables A, int6
     for (int l = 0; l < nlev; ++l) {
         const int Wn = c1.W;
         const AdjIn<UPD> x = xn;
-        float *ba0 = Ba + cur * NB, *ba1 = Ba + (cur ^ 1) * NB;
         // fixed side: argmin contributions of the update sweep to B_l (record of edge l-1)
         if (use_rec && l > 0 && lane == 0) {
-            if (pi0 >= 0) ba0[pi0] += pv0;
-            if (pi1 >= 0) ba0[pi1] += pv1;
+            if (pi0 >= 0) Ba[pi0] += pv0;
+            if (pi1 >= 0) Ba[pi1] += pv1;
         }
         u32x2 cc[QM];
 #pragma unroll
         for (int q = 0; q < QM; ++q) cc[q] = ccn[q];
-        {
-            const int l16 = lane16(lane);
-#pragma unroll
-            for (int q = 0; q < QM; ++q) lds4(ba1, l16 + q * 1024) = zero4;  // adjoints of level l+1 start at 0
-        }
         // prefetch hop l+1: codes of level l+1, edge data of level l+1 (the last hop reloads its own),
         // the record of edge l
         {
@@ -1283,10 +1286,9 @@ __global__ __launch_bounds__(256) void k_adjc_B_w(DevTables T, AdjTables A, int6
         }
         wave_sync();
         with_count<1, QM>(groups(c0), [&](auto qc) {
-            adjcB_hop_w<decltype(qc)::value, RMAX, UPD>(ba0, ba1, cc, lane, Wn, x, o, l);
+            adjcB_hop_w<decltype(qc)::value, RMAX, UPD>(Ba, cc, lane, Wn, x, o, l);
         });
         wave_sync();
-        cur ^= 1;
         c0 = c1;
         c1 = level(l + 2);
     }
