@@ -510,16 +510,42 @@ __global__ __launch_bounds__(256) void k_fwd_w(DevTables T, int64_t tile0, int64
     int *meta = (int *)(Bst + NB);
     int *off = meta + NL;
     const f32x4 inf4 = {kInf, kInf, kInf, kInf};
+    // the recording sweeps keep the level table in registers when it fits (their LDS then holds the
+    // node buffers alone, and more waves fit a CU): lane k holds levels k, k + 64, k + 128, k + 192
+    constexpr int NR = kParRegLevels / 64;
+    static_assert(NR == 4, "the register level table is read through a four-way choice");
+    const bool regs = PAR && NL <= kParRegLevels;
+    int mr[NR], orr[NR];
     for (;;) {
         const TileCtx tc = tile_ctx(T, tile);
-        preload_meta<1>(T, tc, lane, meta, off);
         const int nlev = tc.nlev;
+        if (regs) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) {
+                const int l = lane + 64 * r;
+                mr[r] = l < nlev ? (int)T.widths[tc.wbase + l] | (T.lev_rows[tc.lbase + l] << 16) : 0;
+                orr[r] = l < nlev ? T.lev_off[tc.lbase + l] : 0;
+            }
+        } else {
+            preload_meta<1>(T, tc, lane, meta, off);
+        }
         auto level = [&](int l) {
             Lev v{0, 0, 0};
             if (l < nlev) {
-                v.W = uni(meta[l] & 0xFFFF);
-                v.R = uni(meta[l] >> 16);
-                v.base = tc.nbase + (int64_t)uni(off[l]);
+                int mw, ow;
+                if (regs) {
+                    const int r = l >> 6;  // uniform: a choice among the lane's registers, then one lane's
+                    const int ms = r == 0 ? mr[0] : r == 1 ? mr[1] : r == 2 ? mr[2] : mr[3];
+                    const int os = r == 0 ? orr[0] : r == 1 ? orr[1] : r == 2 ? orr[2] : orr[3];
+                    mw = __builtin_amdgcn_readlane(ms, l & 63);
+                    ow = __builtin_amdgcn_readlane(os, l & 63);
+                } else {
+                    mw = meta[l];
+                    ow = off[l];
+                }
+                v.W = uni(mw & 0xFFFF);
+                v.R = uni(mw >> 16);
+                v.base = tc.nbase + (int64_t)uni(ow);
             }
             return v;
         };

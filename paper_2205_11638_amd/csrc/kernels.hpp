@@ -123,7 +123,12 @@ constexpr int lds_words_pass_w(int RMAX, int NL) { return 2 * node_buf_w(RMAX) +
 constexpr int lds_words_bwd_w(int RMAX, int NL) { return node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
 // The forward sweeps that record argmin parent codes keep the next level's costs as 64-bit keys
 // (cost, code): one node buffer more.
-constexpr int lds_words_pass_w_par(int RMAX, int NL) { return 3 * node_buf_w(RMAX) + ((2 * NL + 3) & ~3); }
+// Their level table (two words per level) stays in registers when the tile has at most
+// kParRegLevels levels (lane k holds levels k, k + 64, ...), and takes LDS only beyond.
+constexpr int kParRegLevels = 256;
+constexpr int lds_words_pass_w_par(int RMAX, int NL) {
+    return 3 * node_buf_w(RMAX) + (NL <= kParRegLevels ? 0 : ((2 * NL + 3) & ~3));
+}
 // LDS words per wave of the pass kernels of a class
 constexpr int lds_words_pass_c(int P, int RMAX, int WB, int NL) {
     return P == 64 ? lds_words_pass_w(RMAX, NL) : lds_words_pass(P, WB, NL);
